@@ -1,0 +1,174 @@
+"""Oracle-side model construction in FP64 numpy (test infrastructure only).
+
+Everything here is the oracle's own reading of the paper's definitions; the
+HIP library builds the same quantities with separate C++ code.
+
+* Sine-DVR (particle-in-a-box DVR; the DVR family of Sec. II.A): box walls
+  lo, hi and n interior points q_i = lo + i*dx, dx = (hi-lo)/(n+1), i = 1..n,
+  DVR weight dx (Eq. pvN_def's omega_j).  The kinetic matrix is written in
+  the closed form of the sine DVR (Colbert & Miller's box result), not via
+  its spectral decomposition; its eigenvalues (k pi/L)^2/(2m) are a pin.
+* Diagonal potential factors: q^p and Morse (1-exp(-a(q-q0)))^2 sampled on
+  the grid (DVR potential is diagonal, Sec. II.A).
+* Initial packet: product Gaussian exp(-(q-c)^2/(2 w^2) + i p (q-c)) sampled
+  on the grid and normalised per dimension in the discrete 2-norm.
+* Projected von Neumann basis (Sec. II.B, Eqs. pvN_def, psi_exp_pvb):
+  lattice Gaussians g_{sl}(x) = (2a/pi)^{1/4} exp(-a(x-x_s)^2 + i p_l (x-x_s)),
+  a = dp/(2dx), dx*dp = 2 pi, projected G_{j,(s,l)} = sqrt(w_j) g_{sl}(q_j).
+  Coefficients a = G^dagger c; the operator acting on them is the similarity
+  transform G^dagger h G^{-dagger} of every 1D DVR factor (the full-basis
+  form of S^{-1} H, Sec. II.B.2 last paragraph).
+"""
+import numpy as np
+
+
+def sine_dvr_grid(n, lo, hi):
+    dx = (hi - lo) / (n + 1)
+    return lo + dx * np.arange(1, n + 1), dx
+
+
+def sine_dvr_kinetic(n, lo, hi, mass):
+    """Closed-form sine-DVR kinetic matrix (hbar = 1)."""
+    L = hi - lo
+    K = n + 1
+    pref = np.pi ** 2 / (4.0 * mass * L ** 2)
+    T = np.empty((n, n))
+    for i in range(1, n + 1):
+        for j in range(1, n + 1):
+            if i == j:
+                T[i - 1, j - 1] = pref * ((2.0 * K * K + 1.0) / 3.0 - 1.0 / np.sin(np.pi * i / K) ** 2)
+            else:
+                T[i - 1, j - 1] = pref * (-1.0) ** (i - j) * (
+                    1.0 / np.sin(np.pi * (i - j) / (2.0 * K)) ** 2
+                    - 1.0 / np.sin(np.pi * (i + j) / (2.0 * K)) ** 2)
+    return T
+
+
+def factor_values(f, q):
+    if f["kind"] == "power":
+        return q ** f["p"]
+    if f["kind"] == "morse":
+        return (1.0 - np.exp(-f["a"] * (q - f["q0"]))) ** 2
+    raise ValueError(f"unknown factor kind {f['kind']!r}")
+
+
+def gaussian_1d(q, c, p, w):
+    g = np.exp(-((q - c) ** 2) / (2.0 * w * w)) * np.exp(1j * p * (q - c))
+    return g / np.sqrt(np.sum(np.abs(g) ** 2))
+
+
+def pvb_projection(q, dx_grid, lo, hi, ns, nl):
+    """G[j, s*nl+l] = sqrt(dx_grid) * g_{sl}(q_j)."""
+    dX = (hi - lo) / ns
+    dP = 2.0 * np.pi / dX
+    alpha = dP / (2.0 * dX)
+    xs = lo + (np.arange(ns) + 0.5) * dX
+    pl = (np.arange(nl) - 0.5 * (nl - 1)) * dP
+    G = np.empty((q.size, ns * nl), dtype=np.complex128)
+    for s in range(ns):
+        for l in range(nl):
+            G[:, s * nl + l] = np.sqrt(dx_grid) * (2.0 * alpha / np.pi) ** 0.25 * np.exp(
+                -alpha * (q - xs[s]) ** 2 + 1j * pl[l] * (q - xs[s]))
+    return G
+
+
+class Model:
+    """All 1D ingredients of a card, in the oracle's own FP64 construction."""
+
+    def __init__(self, card):
+        self.card = card
+        D = card["D"]
+        self.D = D
+        self.n = [int(v) for v in card["n"]]
+        self.q, self.dx, self.T = [], [], []
+        for k in range(D):
+            qk, dxk = sine_dvr_grid(self.n[k], card["lo"][k], card["hi"][k])
+            self.q.append(qk)
+            self.dx.append(dxk)
+            self.T.append(sine_dvr_kinetic(self.n[k], card["lo"][k], card["hi"][k], card["mass"]))
+        ps = card["psi0"]
+        self.g0 = [gaussian_1d(self.q[k], ps["centre"][k], ps["momentum"][k], ps["width"][k])
+                   for k in range(D)]
+        self.pvb = card.get("basis", "dvr") == "pvb"
+        if self.pvb:
+            ns, nl = card["lattice"]
+            self.lattice = (ns, nl)
+            self.G = [pvb_projection(self.q[k], self.dx[k], card["lo"][k], card["hi"][k], ns, nl)
+                      for k in range(D)]
+            self.Ginv = [np.linalg.inv(G) for G in self.G]
+            self.GinvH = [np.linalg.inv(G.conj().T) for G in self.G]
+
+    # --- operator pieces -------------------------------------------------
+    def transform(self, k, h):
+        """Matrix acting on dim-k coefficients: h itself (DVR) or G^+ h G^-+ (lattice)."""
+        if not self.pvb:
+            return np.asarray(h, dtype=np.complex128)
+        return self.G[k].conj().T @ h @ self.GinvH[k]
+
+    def single_dim_ops(self):
+        """Per dim: kinetic plus every one-factor potential term (dense in the lattice)."""
+        ops = [self.transform(k, self.T[k]) for k in range(self.D)]
+        if self.pvb:
+            for t in self.card["terms"]:
+                if len(t["factors"]) == 1:
+                    f = t["factors"][0]
+                    k = f["dim"]
+                    ops[k] = ops[k] + t["coef"] * self.transform(k, np.diag(factor_values(f, self.q[k])))
+        return ops
+
+    def diag_terms(self):
+        """Diagonal potential terms (DVR): list of (coef, {dim: values})."""
+        out = []
+        if self.pvb:
+            return out
+        for t in self.card["terms"]:
+            tabs = {}
+            coef = t["coef"]
+            for f in t["factors"]:
+                k = f["dim"]
+                v = factor_values(f, self.q[k])
+                tabs[k] = tabs[k] * v if k in tabs else v
+            out.append((coef, tabs))
+        return out
+
+    def pair_terms(self):
+        """Lattice only: two-factor potential terms as (coef, k1, h1, k2, h2), k1 < k2."""
+        out = []
+        if not self.pvb:
+            return out
+        for t in self.card["terms"]:
+            if len(t["factors"]) == 1:
+                continue
+            if len(t["factors"]) != 2:
+                raise ValueError("lattice cards support one- and two-factor terms")
+            f1, f2 = sorted(t["factors"], key=lambda f: f["dim"])
+            k1, k2 = f1["dim"], f2["dim"]
+            h1 = self.transform(k1, np.diag(factor_values(f1, self.q[k1])))
+            h2 = self.transform(k2, np.diag(factor_values(f2, self.q[k2])))
+            out.append((t["coef"], k1, h1, k2, h2))
+        return out
+
+    def potential_full(self):
+        """V on the full grid (DVR cards; tiny grids only)."""
+        V = np.zeros(self.n)
+        for coef, tabs in self.diag_terms():
+            term = np.full(self.n, coef)
+            for k, v in tabs.items():
+                shape = [1] * self.D
+                shape[k] = self.n[k]
+                term = term * v.reshape(shape)
+            V = V + term
+        return V
+
+    # --- packet tables -----------------------------------------------------
+    def init_tables(self):
+        """1D factors of the initial coefficients (DVR values or lattice a = G^+ c)."""
+        if not self.pvb:
+            return [g.copy() for g in self.g0]
+        return [self.G[k].conj().T @ self.g0[k] for k in range(self.D)]
+
+    def bra_tables(self):
+        """1D factors of the bra that gives C(t) = <psi0|psi(t)> from the coefficients."""
+        if not self.pvb:
+            return [g.copy() for g in self.g0]
+        return [self.Ginv[k] @ self.g0[k] for k in range(self.D)]

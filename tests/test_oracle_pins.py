@@ -1,0 +1,527 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these compare the oracle with itself: every expected value comes from
+a closed form, a textbook/library routine applied to the plain dense problem
+(Kronecker products, scipy's expm / eigh), brute force on tiny inputs, or a
+worked example printed in the paper (tests/golden).
+"""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import oracle as orc
+from oracle.model import Model, sine_dvr_grid, sine_dvr_kinetic, pvb_projection
+from workloads import card, random_active_set, random_complex, random_dense_factor
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# dense references
+# ---------------------------------------------------------------------------
+def kron_dim(n, k, h):
+    """I x ... x h (at k) x ... x I as a dense matrix."""
+    out = np.ones((1, 1), dtype=np.complex128)
+    for j, nj in enumerate(n):
+        out = np.kron(out, h if j == k else np.eye(nj))
+    return out
+
+
+def dense_h(model):
+    n = model.n
+    N = int(np.prod(n))
+    H = np.zeros((N, N), dtype=np.complex128)
+    for k, h in enumerate(model.single_dim_ops()):
+        H += kron_dim(n, k, h)
+    if not model.pvb:
+        H += np.diag(model.potential_full().ravel())
+    return H
+
+
+class RandomOp:
+    """Random non-Hermitian SoP operator made directly in the C oracle."""
+
+    def __init__(self, n, seed, nv=3, npair=2):
+        L = orc.lib()
+        rng = np.random.default_rng(seed)
+        self.n = list(n)
+        D = len(n)
+        nmax = max(n)
+        self.m = L.orc_new(D, orc._ip(np.array(n, dtype=np.int32)))
+        self.h = []
+        for k in range(D):
+            h = random_dense_factor(n[k], seed + 10 + k)
+            self.h.append(h)
+            L.orc_add_h(self.m, k, orc._dp(np.ascontiguousarray(h).view(np.float64)))
+        self.v = []
+        for t in range(nv):
+            use = (rng.random(D) < 0.6).astype(np.int32)
+            tab = rng.standard_normal((D, nmax))
+            coef = float(rng.standard_normal())
+            self.v.append((coef, use.copy(), tab.copy()))
+            L.orc_add_vterm(self.m, coef, orc._ip(use), orc._dp(tab))
+        self.pairs = []
+        for t in range(npair if D > 1 else 0):
+            k1, k2 = sorted(rng.choice(D, size=2, replace=False))
+            h1 = random_dense_factor(n[k1], seed + 100 + t)
+            h2 = random_dense_factor(n[k2], seed + 200 + t)
+            c = complex(rng.standard_normal(), rng.standard_normal())
+            self.pairs.append((c, k1, h1, k2, h2))
+            L.orc_add_pair(self.m, c.real, c.imag, int(k1), int(k2),
+                           orc._dp(np.ascontiguousarray(h1).view(np.float64)),
+                           orc._dp(np.ascontiguousarray(h2).view(np.float64)))
+
+    def __del__(self):
+        orc.lib().orc_free(self.m)
+
+    def dense_pruned(self, keys):
+        """Dense P H P with sequential truncated products, restricted to keys."""
+        n = self.n
+        N = int(np.prod(n))
+        idx = np.asarray(keys, dtype=np.int64)
+        H = np.zeros((N, N), dtype=np.complex128)
+        for k, h in enumerate(self.h):
+            H += kron_dim(n, k, h)
+        V = np.zeros(N)
+        digits = np.unravel_index(np.arange(N), n)
+        for coef, use, tab in self.v:
+            term = np.full(N, coef)
+            for k in range(len(n)):
+                if use[k]:
+                    term = term * tab[k][digits[k]]
+            V += term
+        H += np.diag(V)
+        Hr = H[np.ix_(idx, idx)]
+        for c, k1, h1, k2, h2 in self.pairs:
+            A = kron_dim(n, k1, h1)[np.ix_(idx, idx)]
+            B = kron_dim(n, k2, h2)[np.ix_(idx, idx)]
+            Hr = Hr + c * (A @ B)
+        return Hr
+
+    def apply_def(self, keys, x):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.zeros_like(x)
+        orc.lib().orc_apply_def(self.m, keys.size, orc._up(keys), orc._dp(x.view(np.float64)),
+                                orc._dp(y.view(np.float64)))
+        return y
+
+    def apply_fib(self, keys, x):
+        L = orc.lib()
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        x = np.ascontiguousarray(x, dtype=np.complex128)
+        y = np.zeros_like(x)
+        f = L.orc_fib_build(self.m, keys.size, orc._up(keys))
+        L.orc_apply_fib(self.m, f, orc._dp(x.view(np.float64)), orc._dp(y.view(np.float64)))
+        L.orc_fib_free(f)
+        return y
+
+
+# ---------------------------------------------------------------------------
+# 1D builders
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,lo,hi,mass", [(48, -8.0, 8.0, 1.0), (24, -6.5, 6.5, 1.0), (7, -2.0, 3.0, 1.3)])
+def test_sine_dvr_kinetic_eigenvalues(n, lo, hi, mass):
+    """Particle in a box: the sine-DVR kinetic matrix has eigenvalues (k pi/L)^2/(2m) exactly."""
+    T = sine_dvr_kinetic(n, lo, hi, mass)
+    ev = np.linalg.eigvalsh(T)
+    exact = (np.arange(1, n + 1) * np.pi / (hi - lo)) ** 2 / (2.0 * mass)
+    assert np.allclose(T, T.T, atol=0, rtol=0)
+    assert np.max(np.abs(ev - exact) / exact) < 1e-12
+
+
+def test_harmonic_oscillator_eigenvalues_on_hh2d_grid():
+    """H = (-d^2 + x^2)/2 (Fig. 1's oscillator) on the 48-point grid: E_k = k + 1/2 for low k."""
+    q, _ = sine_dvr_grid(48, -8.0, 8.0)
+    H = sine_dvr_kinetic(48, -8.0, 8.0, 1.0) + np.diag(0.5 * q * q)
+    ev = np.linalg.eigvalsh(H)[:10]
+    assert np.max(np.abs(ev - (np.arange(10) + 0.5))) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# pruned operator
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,seed", [((5,), 1), ((4, 6), 2), ((3, 5, 4), 3), ((3, 2, 4, 3), 4)])
+def test_apply_def_full_fill_equals_kronecker(n, seed):
+    op = RandomOp(n, seed)
+    keys = np.arange(int(np.prod(n)), dtype=np.uint64)
+    x = random_complex(keys.size, seed)
+    y = op.apply_def(keys, x)
+    ref = op.dense_pruned(keys) @ x
+    assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,seed,fill", [((6, 7), 5, 0.4), ((5, 4, 6), 6, 0.3), ((4, 5, 3, 4), 7, 0.25),
+                                         ((9, 8), 8, 0.05)])
+def test_apply_def_pruned_equals_restricted_kronecker(n, seed, fill):
+    op = RandomOp(n, seed)
+    for blob in (True, False):
+        keys = random_active_set(n, fill, seed, blob=blob)
+        x = random_complex(keys.size, seed + 1)
+        y = op.apply_def(keys, x)
+        ref = op.dense_pruned(keys) @ x
+        assert np.max(np.abs(y - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n,seed", [((6, 7), 11), ((5, 4, 6), 12), ((4, 5, 3, 4), 13), ((3, 3, 3, 3, 3, 3), 14)])
+def test_apply_fib_equals_def(n, seed):
+    op = RandomOp(n, seed)
+    for fill, blob in ((0.5, True), (0.2, False), (1.0, False)):
+        keys = random_active_set(n, fill, seed, blob=blob)
+        x = random_complex(keys.size, seed + 2)
+        yd = op.apply_def(keys, x)
+        yf = op.apply_fib(keys, x)
+        assert np.max(np.abs(yd - yf)) <= 1e-12 * max(1.0, np.max(np.abs(yd)))
+
+
+def test_apply_single_point_and_empty():
+    op = RandomOp((4, 5), 21)
+    keys = np.array([7], dtype=np.uint64)
+    x = np.array([1.5 - 0.5j])
+    ref = op.dense_pruned(keys) @ x
+    assert np.allclose(op.apply_def(keys, x), ref, rtol=1e-14, atol=0)
+    assert np.allclose(op.apply_fib(keys, x), ref, rtol=1e-14, atol=0)
+    empty = np.zeros(0, dtype=np.uint64)
+    assert op.apply_def(empty, np.zeros(0, complex)).size == 0
+    assert op.apply_fib(empty, np.zeros(0, complex)).size == 0
+
+
+def test_card_operator_is_hermitian_and_matches_kronecker():
+    o = orc.Oracle(card("small_3d"))
+    H = dense_h(o.model)
+    assert np.allclose(H, H.conj().T, atol=1e-13)
+    keys = random_active_set(o.n, 0.4, 31)
+    x = random_complex(keys.size, 32)
+    idx = keys.astype(np.int64)
+    ref = H[np.ix_(idx, idx)] @ x
+    for y in (o.apply_def(keys, x), o.apply_fib(keys, x)):
+        assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_appendix_range_example():
+    """Ranges of a fiber's index set follow the appendix's worked example."""
+    g = json.load(open(os.path.join(GOLDEN, "appendix_ranges.json")))
+    o = orc.Oracle(card("small_2d"))
+    n1 = o.n[1]
+    # a fiber of dimension 1 at i_0 = 3 holding exactly the example digits
+    keys = np.array([3 * n1 + d for d in g["digits"]], dtype=np.uint64)
+    ranges = o.fiber_ranges(keys, 1)
+    assert ranges == [[tuple(r) for r in g["ranges"]]]
+    # and in the permuted (dimension 0) direction as well
+    n0 = o.n[0]
+    keys0 = np.array(sorted(d * n1 + 5 for d in g["digits"] if d < n0), dtype=np.uint64)
+    r0 = o.fiber_ranges(keys0, 0)
+    expect = [[(a, min(b, n0 - 1)) for a, b in g["ranges"] if a < n0]]
+    assert r0 == expect
+
+
+# ---------------------------------------------------------------------------
+# small exponentials
+# ---------------------------------------------------------------------------
+def test_tridiag_expv_matches_expm():
+    rng = np.random.default_rng(3)
+    for m in (1, 2, 5, 10, 16):
+        a = rng.standard_normal(m) * 3
+        b = np.abs(rng.standard_normal(m - 1))
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        dt = 0.37
+        ref = sla.expm(-1j * dt * T)[:, 0]
+        y = orc.tridiag_expv(a, b, dt)
+        assert np.max(np.abs(y - ref)) < 1e-13
+
+
+def test_complex_expm_matches_scipy():
+    rng = np.random.default_rng(4)
+    for m in (1, 3, 10):
+        A = (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))) * 2.0
+        assert np.max(np.abs(orc.cexpm(A) - sla.expm(A))) < 1e-12 * np.max(np.abs(sla.expm(A)))
+
+
+# ---------------------------------------------------------------------------
+# propagation
+# ---------------------------------------------------------------------------
+def _full_state(o):
+    keys = o.full_keys()
+    return keys, o.psi0_on(keys)
+
+
+def test_sil_step_matches_dense_exponential():
+    """Lanczos m=16 on a full tiny grid equals exp(-iH dt) psi (dense expm)."""
+    o = orc.Oracle(card("small_2d"))
+    keys, c0 = _full_state(o)
+    o.set_state(keys, c0)
+    H = dense_h(o.model)
+    U = sla.expm(-1j * 0.05 * H)
+    c = c0.copy()
+    for _ in range(10):
+        o.sil_step(dt=0.05, m=16)
+        c = U @ c
+    _, cg = o.state()
+    assert np.max(np.abs(cg - c)) < 1e-12
+
+
+def test_arnoldi_step_matches_dense_exponential():
+    """Arnoldi on a non-Hermitian operator: matches expm of the dense restricted operator."""
+    n = (4, 5)
+    op = RandomOp(n, 41, nv=2, npair=1)
+    keys = random_active_set(n, 0.6, 42)
+    x = random_complex(keys.size, 43)
+    x /= np.linalg.norm(x)
+    A = op.dense_pruned(keys)
+    A = A / np.max(np.abs(np.linalg.eigvals(A)))   # scale to unit spectral radius
+    # rebuild the same operator scaled: easier to scale dt instead
+    s = orc.lib().orc_state_new()
+    orc.lib().orc_state_set(s, keys.size, orc._up(np.ascontiguousarray(keys)), orc._dp(x.view(np.float64)))
+    f = orc.lib().orc_fib_build(op.m, keys.size, orc._up(np.ascontiguousarray(keys)))
+    B = op.dense_pruned(keys)
+    dt = 0.02
+    used = orc.lib().orc_sil_step(op.m, f, s, dt, keys.size, 1, None)
+    y = np.zeros_like(x)
+    kk = np.zeros(keys.size, dtype=np.uint64)
+    orc.lib().orc_state_get(s, orc._up(kk), orc._dp(y.view(np.float64)))
+    orc.lib().orc_fib_free(f)
+    orc.lib().orc_state_free(s)
+    ref = sla.expm(-1j * dt * B) @ x
+    assert used >= 1
+    assert np.max(np.abs(y - ref)) < 1e-10
+
+
+def _coherent_card():
+    c = card("hh2d")
+    c["terms"] = [t for t in c["terms"] if len(t["factors"]) == 1 and t["factors"][0]["p"] == 2]
+    return c
+
+
+def test_coherent_state_closed_form():
+    """Uncoupled 2D oscillator: C(t) = prod_k exp(-it/2) exp(-|a_k|^2 (1 - exp(-it)))."""
+    cd = _coherent_card()
+    o = orc.Oracle(cd)
+    keys, c0 = _full_state(o)
+    o.set_state(keys, c0)
+    tr, _ = o.propagate(nsteps=60, dt=0.05, m=16, prune=False)
+    t = tr[:, 0]
+    C = tr[:, 3] + 1j * tr[:, 4]
+    ref = np.ones_like(C)
+    for k in range(2):
+        a = (cd["psi0"]["centre"][k] + 1j * cd["psi0"]["momentum"][k]) / np.sqrt(2.0)
+        ref = ref * np.exp(-0.5j * t) * np.exp(-abs(a) ** 2 * (1.0 - np.exp(-1j * t)))
+    assert np.max(np.abs(C - ref)) < 1e-10
+    assert np.max(np.abs(tr[:, 2] - tr[0, 2])) < 1e-10        # energy conserved
+    E = sum(0.5 + 0.5 * (cd["psi0"]["centre"][k] ** 2 + cd["psi0"]["momentum"][k] ** 2) for k in range(2))
+    assert abs(tr[0, 2] - E) < 1e-10
+
+
+def test_unpruned_norm_and_energy_conserved():
+    o = orc.Oracle(card("small_3d"))
+    keys, c0 = _full_state(o)
+    o.set_state(keys, c0)
+    tr, h = o.propagate(nsteps=40, prune=False)
+    assert np.max(np.abs(tr[:, 1] - tr[0, 1])) < 1e-13
+    assert np.max(np.abs(tr[:, 2] - tr[0, 2])) < 1e-9
+    assert len(set(h.tolist())) == 1
+
+
+def test_pruned_norm_accounting():
+    """SIL conserves the norm; adaption removes exactly the dropped |c|^2."""
+    o = orc.Oracle(card("small_3d"))
+    o.init_state()
+    for _ in range(15):
+        o.sil_step()
+        k_before, c_before = o.state()
+        n_before = np.sum(np.abs(c_before) ** 2)
+        o.prune()
+        k_after, c_after = o.state()
+        kept = np.isin(k_before, k_after)
+        dropped = np.sum(np.abs(c_before[~kept]) ** 2)
+        assert abs(np.sum(np.abs(c_after) ** 2) - (n_before - dropped)) < 1e-14
+        # retained coefficients are carried over untouched, new ones are zero
+        pos = np.searchsorted(k_before, k_after)
+        pos = np.minimum(pos, k_before.size - 1)
+        old = k_before[pos] == k_after
+        assert np.array_equal(c_after[old], c_before[pos[old]])
+        assert np.all(c_after[~old] == 0)
+
+
+def test_eps_zero_reproduces_unpruned():
+    cd = card("small_3d")
+    a = orc.Oracle(cd)
+    b = orc.Oracle(cd)
+    keys, c0 = _full_state(a)
+    a.set_state(keys, c0)
+    b.set_state(keys, c0)
+    ta, _ = a.propagate(nsteps=20, eps=0.0)
+    tb, _ = b.propagate(nsteps=20, prune=False)
+    assert np.max(np.abs(ta[:, 1:5] - tb[:, 1:5])) < 1e-13
+    assert np.all(ta[:, 5] == keys.size)
+
+
+def test_reversibility():
+    o = orc.Oracle(card("small_2d"))
+    keys, c0 = _full_state(o)
+    o.set_state(keys, c0)
+    for _ in range(20):
+        o.sil_step(dt=0.05)
+    for _ in range(20):
+        o.sil_step(dt=-0.05)
+    _, c = o.state()
+    assert np.max(np.abs(c - c0)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# adaption
+# ---------------------------------------------------------------------------
+def brute_adapt(n, keys, c, eps, lattice=None):
+    n = list(n)
+    total = int(np.prod(n))
+    out = set()
+    for key, v in zip(keys.tolist(), c):
+        if v.real * v.real + v.imag * v.imag >= eps * eps:
+            d = list(np.unravel_index(key, n))
+            out.add(key)
+            for k in range(len(n)):
+                moves = []
+                if lattice is None:
+                    moves = [-1, 1]
+                    ok = [0 <= d[k] + s < n[k] for s in moves]
+                else:
+                    ns, nl = lattice
+                    s_, l_ = divmod(d[k], nl)
+                    moves, ok = [], []
+                    for ds, dl in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                        moves.append(ds * nl + dl)
+                        ok.append(0 <= s_ + ds < ns and 0 <= l_ + dl < nl)
+                for s, good in zip(moves, ok):
+                    if good:
+                        e = d.copy()
+                        e[k] += s
+                        out.add(int(np.ravel_multi_index(e, n)))
+    assert all(0 <= k < total for k in out)
+    return np.array(sorted(out), dtype=np.uint64)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_prune_matches_bruteforce(seed):
+    cd = card("small_3d")
+    o = orc.Oracle(cd)
+    keys = random_active_set(o.n, 0.35, seed)
+    rng = np.random.default_rng(seed)
+    c = random_complex(keys.size, seed) * np.exp(rng.uniform(-12, 0, keys.size))
+    eps = 1e-3
+    # exact ties at |c| = eps (representable: re = eps, im = 0) and zeros
+    c[::17] = eps
+    c[5::23] = 0.0
+    o.set_state(keys, c)
+    nab = o.prune(eps=eps)
+    k2, c2 = o.state()
+    ref = brute_adapt(o.n, keys, c, eps)
+    assert np.array_equal(k2, ref)
+    assert nab == int(np.sum(c.real * c.real + c.imag * c.imag >= eps * eps))
+    lookup = dict(zip(keys.tolist(), c))
+    assert np.array_equal(c2, np.array([lookup.get(k, 0j) for k in k2.tolist()]))
+
+
+def test_prune_lattice_stencil_matches_bruteforce():
+    cd = card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0])
+    o = orc.Oracle(cd)
+    keys = random_active_set(o.n, 0.3, 9)
+    c = random_complex(keys.size, 9) * 1e-3
+    o.set_state(keys, c)
+    o.prune(eps=1e-3)
+    k2, _ = o.state()
+    assert np.array_equal(k2, brute_adapt(o.n, keys, c, 1e-3, lattice=(3, 4)))
+
+
+def test_prune_edge_cases():
+    o = orc.Oracle(card("small_2d"))
+    total = int(np.prod(o.n))
+    # empty S: everything below threshold -> empty set
+    keys = np.arange(0, total, 3, dtype=np.uint64)
+    o.set_state(keys, np.full(keys.size, 1e-9 + 0j))
+    assert o.prune(eps=1e-3) == 0
+    assert o.state()[0].size == 0
+    # S = full grid -> full grid
+    keys = np.arange(total, dtype=np.uint64)
+    o.set_state(keys, np.ones(total, complex))
+    o.prune(eps=0.5)
+    assert o.state()[0].size == total
+    # grid corners: neighbours outside the box are dropped, no wrap-around
+    o.set_state(np.array([0, total - 1], dtype=np.uint64), np.ones(2, complex))
+    o.prune(eps=0.5)
+    n0, n1 = o.n
+    expect = sorted({0, 1, n1, total - 1, total - 2, total - 1 - n1})
+    assert o.state()[0].tolist() == expect
+
+
+def test_neighbour_counts_golden():
+    """One function above threshold in a 16-function mode adds 2 (line) or 4 (4x4 lattice) neighbours."""
+    g = json.load(open(os.path.join(GOLDEN, "neighbour_counts.json")))
+    m = g["mode_size"]
+    line = orc.Oracle(card("small_2d", n=[m, 3], lo=[-4.0, -1.0], hi=[4.0, 1.0]))
+    lat = orc.Oracle(card("small_2d", n=[m, m], basis="pvb", lattice=g["lattice"], lo=[-4.0, -4.0],
+                          hi=[4.0, 4.0]))
+    # interior function of mode 0 (digit 5 = lattice cell (1,1)); second dim at the box edge
+    for o, added, frac in ((line, g["added_line"], g["fraction_line"]),
+                           (lat, g["added_lattice"], g["fraction_lattice"])):
+        n1 = o.n[1]
+        key = 5 * n1 + 0
+        o.set_state(np.array([key], dtype=np.uint64), np.array([1.0 + 0j]))
+        o.prune(eps=0.5)
+        k2, _ = o.state()
+        d = np.array(np.unravel_index(k2.astype(np.int64), o.n))
+        along0 = int(np.sum(d[1] == 0)) - 1
+        assert along0 == added
+        assert along0 / m == frac
+
+
+def test_initial_set_matches_bruteforce():
+    cd = card("small_3d")
+    o = orc.Oracle(cd)
+    nab = o.init_state()
+    keys, c = o.state()
+    full = o.full_keys()
+    psi0 = o.psi0_on(full)
+    ref = brute_adapt(o.n, full, psi0, cd["eps"])
+    assert np.array_equal(keys, ref)
+    assert nab == int(np.sum(psi0.real ** 2 + psi0.imag ** 2 >= cd["eps"] ** 2))
+    assert np.allclose(c, o.psi0_on(keys), rtol=1e-14, atol=0)
+    assert abs(np.sum(np.abs(psi0) ** 2) - 1.0) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# phase-space lattice (projected von Neumann, biorthogonal)
+# ---------------------------------------------------------------------------
+def test_pvb_unpruned_dynamics_is_similarity_of_dvr():
+    """a = G^+ c: unpruned lattice dynamics maps back to the DVR dynamics exactly."""
+    base = card("small_4d", n=[12, 12, 12, 12])
+    base["terms"] = base["terms"][:2] + base["terms"][4:6]     # two Morse + two couplings
+    lat = dict(base, basis="pvb", lattice=[3, 4])
+    od = orc.Oracle(base)
+    ol = orc.Oracle(lat)
+    kd, cd0 = _full_state(od)
+    kl, cl0 = _full_state(ol)
+    od.set_state(kd, cd0)
+    ol.set_state(kl, cl0)
+    td, _ = od.propagate(nsteps=8, dt=0.05, m=12, prune=False)
+    tl, _ = ol.propagate(nsteps=8, dt=0.05, m=12, prune=False)
+    # autocorrelation through the dual bra tables equals the DVR one
+    assert np.max(np.abs((td[:, 3] + 1j * td[:, 4]) - (tl[:, 3] + 1j * tl[:, 4]))) < 1e-9
+    _, cdv = od.state()
+    _, clat = ol.state()
+    c_back = clat.reshape(ol.n)
+    for k in range(4):
+        c_back = np.moveaxis(np.tensordot(ol.model.GinvH[k], c_back, axes=([1], [k])), 0, k)
+    assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
+
+
+def test_pvb_coefficients_are_overlaps():
+    """Eq. psi_exp_pvb: lattice coefficients are G^+ c_chi; G's columns are the projected Gaussians."""
+    q, dx = sine_dvr_grid(16, -6.0, 6.0)
+    G = pvb_projection(q, dx, -6.0, 6.0, 4, 4)
+    # each projected Gaussian is (almost) normalised on the grid: sum_j w_j |g(x_j)|^2 ~ 1
+    norms = np.sum(np.abs(G) ** 2, axis=0)
+    assert np.all(np.abs(norms[4:12] - 1.0) < 0.05)     # interior cells; edges leak out of the box
+    assert np.linalg.cond(G) < 10.0
