@@ -1,0 +1,171 @@
+"""Benchmark: pruned H*psi active-point updates/s and steps/s on one MI355X.
+
+Workload: the 6D SoP quartic model (sine-DVR 24^6 = 191,102,976-function
+grid, eps = 1e-6, dt = 0.05, Lanczos order 10), started from its Gaussian
+packet and propagated to a mid-trajectory snapshot (step 250) before timing.
+A step is one pass of the whole hot path: one short-iterative Lanczos step
+(10 pruned H*psi products with the fused diagonal potential, full
+reorthogonalisation, the small exponential, the linear combination), the
+adaption (flag, dilate, compact, remap), the rebuild of the fiber tables and
+the potential cache, and the observables.
+
+value = total H*psi point updates in the K timed steps (sum over steps of
+m * |A|) / wall time of those K steps.  The isolated H*psi rate, the
+roofline of the H*psi kernels and the FP32 form are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SNAPSHOT_STEP = 250
+
+
+def bytes_per_point(D, precision):
+    """Algorithmic bytes of one pruned H*psi per active point: read x once,
+    write y once, one 32-bit fiber/permutation entry per dimension."""
+    sc = 16 if precision == 0 else 8
+    return 2 * sc + 4 * D
+
+
+def cpu_baseline(cd, reps=3):
+    """The FP64 oracle (one thread) applying H on its own initial set of the card."""
+    from oracle.oracle import Oracle
+    o = Oracle(cd)
+    o.init_state()
+    keys, c = o.state()
+    o.apply_current(c)  # builds the stored permutations (not timed)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        o.apply_current(c)
+    dt = time.perf_counter() - t0
+    return {"value": keys.size * reps / dt, "unit": "active-point updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} O-fib H*psi products on the oracle's initial set of the 6D quartic card "
+                      f"(|A0| = {keys.size}), single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--snapshot", type=int, default=SNAPSHOT_STEP)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--workload", default="quartic6d")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1606_04004_amd as ppq
+    from workloads import card
+
+    cd = card(args.workload)
+    D, m, dt, eps = cd["D"], cd["krylov"], cd["dt"], cd["eps"]
+    print(f"[bench] workload {cd['name']} D={D} n={cd['n'][0]} eps={eps}", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    g = ppq.Propagator(cd, precision=ppq.PPQ_FP64, device=0, stream=stream)
+    g.reserve(16_000_000)
+    n0 = g.init_state()
+    t0 = time.perf_counter()
+    g.propagate(nsteps=args.snapshot)
+    torch.cuda.synchronize()
+    print(f"[bench] |A0|={n0}; reached step {args.snapshot} in {time.perf_counter() - t0:.2f} s",
+          file=sys.stderr, flush=True)
+
+    # snapshot (kept for the FP32 leg)
+    snap_keys, snap_c = g.state()
+    # isolated H*psi timing on the snapshot (HIP events on the context stream)
+    n_snap = snap_keys.size
+    ms_h = g.time_apply(50)
+    hpsi_rate = n_snap / (ms_h * 1e-3)
+    bpp = bytes_per_point(D, 0)
+    achieved = bpp * n_snap / (ms_h * 1e-3) / 1e9
+
+    # whole-path steps
+    for _ in range(args.warmup):
+        g.step()
+        g.prune()
+    torch.cuda.synchronize()
+    updates = 0
+    na = g.active_count()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        updates += m * na          # the step's m products act on the current set
+        g.step()
+        na, _ = g.prune()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    value = updates / wall
+
+    out = {
+        "metric": "pruned H*psi active-point updates/s (whole step) + steps/s",
+        "value": value,
+        "unit": "active-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "steps_per_s": 1e3 / ms_step,
+        "hpsi_updates_per_s": hpsi_rate,
+        "hpsi_ms": ms_h,
+        "active_points_at_snapshot": int(n_snap),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "quartic6d: 6D SoP quartic, sine-DVR 24^6 on [-6.5,6.5]^6, eps=1e-6, dt=0.05, "
+                               f"Lanczos m=10, timed from the step-{args.snapshot} snapshot",
+                   "grid": 24 ** 6, "D": D, "krylov": m, "eps": eps, "dt": dt},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "pruned H*psi (D fiber passes, potential fused in the first)",
+                     "bytes_per_point": bpp},
+    }
+
+    if not args.no_fp32:
+        g32 = ppq.Propagator(cd, precision=ppq.PPQ_FP32, device=0, stream=stream)
+        g32.reserve(16_000_000)
+        g32.init_state()
+        g32.set_state(snap_keys, snap_c)
+        ms32 = g32.time_apply(50)
+        for _ in range(args.warmup):
+            g32.step()
+            g32.prune()
+        torch.cuda.synchronize()
+        upd32 = 0
+        na = g32.active_count()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            upd32 += m * na
+            g32.step()
+            na, _ = g32.prune()
+        torch.cuda.synchronize()
+        wall32 = time.perf_counter() - t0
+        bpp32 = bytes_per_point(D, 1)
+        out["fp32"] = {"value": upd32 / wall32, "ms_per_step": wall32 * 1e3 / args.steps,
+                       "hpsi_updates_per_s": n_snap / (ms32 * 1e-3), "hpsi_ms": ms32,
+                       "roofline_frac": bpp32 * n_snap / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "bytes_per_point": bpp32}
+
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cd)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * ppq.h -- C ABI of the MI355X (gfx950) library for dynamically pruned
+ * wavepacket propagation in a direct-product basis (Larsson, Hartke & Tannor,
+ * J. Chem. Phys. 2016, arXiv:1606.04004).
+ *
+ * The state is a coefficient vector held only on an active set A of
+ * multi-indices I = (i_0, ..., i_{D-1}) of a direct-product basis (Sec. II.A,
+ * Eq. wavepacket_form).  Each time step applies a sum-of-products operator
+ * (Sec. II.B.2): one dense 1D matrix per dimension (sine-DVR kinetic energy,
+ * or the similarity-transformed factors of a phase-space lattice basis,
+ * Sec. II.B.1 and II.D) plus a diagonal sum-of-products potential (Sec. II.A,
+ * II.E), restricted to A (the pruned transformation of Sec. II.B.2 and the
+ * appendix), propagates with a short-iterative Lanczos / Arnoldi step
+ * (Sec. III.A), and then adapts A with the amplitude threshold theta
+ * (Sec. II.E): keep |c| >= theta, add the nearest neighbours of every kept
+ * function (ball radius 1, Sec. III.A), drop the rest, compact.
+ *
+ * Conventions for every call
+ *   - Return value: PPQ_OK (0) or a negative ppq_status.  On an error the
+ *     context's state is unchanged unless stated otherwise; ppq_last_error()
+ *     gives a message.  PPQ_E_HIP means a HIP runtime call failed: the context
+ *     is then unusable and must be destroyed.
+ *   - Keys: a multi-index is linearised row-major, last dimension fastest,
+ *     key = sum_k i_k * prod_{k' > k} n_k'  (the layout of the appendix).
+ *     Keys cross the ABI as uint64_t; the grid size prod n_k must be < 2^32.
+ *   - Coefficients cross the ABI as interleaved complex FP64 (re, im) on the
+ *     host, whatever the context precision.  ppq_apply_h takes device vectors
+ *     of the context precision (see there).
+ *   - Matrices are row-major, complex interleaved.
+ *   - Host pointers are read during the call only (inputs copied in); device
+ *     pointers are used in stream order on the context stream and must stay
+ *     valid until that work has run.  The library never frees caller memory.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef PPQ_H
+#define PPQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ppq_ctx ppq_ctx;
+
+typedef enum {
+    PPQ_OK = 0,
+    PPQ_E_ARG = -1,          /* invalid argument (state unchanged) */
+    PPQ_E_STATE = -2,        /* call not valid in the current state (no grid / no set) */
+    PPQ_E_OOM = -3,          /* device allocation failed */
+    PPQ_E_CAPACITY = -4,     /* a size limit of this build was exceeded */
+    PPQ_E_HIP = -5,          /* HIP runtime error; context poisoned */
+    PPQ_E_NUMERIC = -6,      /* non-finite norm or coefficients */
+    PPQ_E_UNSUPPORTED = -7   /* valid request this build does not implement */
+} ppq_status;
+
+typedef enum {
+    PPQ_FP64 = 0,            /* all arithmetic in FP64 */
+    PPQ_FP32 = 1             /* operator products and Krylov vectors in complex FP32
+                                (matrix cores where fibers form dense tiles); inner
+                                products, norms, the small exponential and the
+                                coefficient master copy in FP64 */
+} ppq_precision;
+
+typedef enum {
+    PPQ_FAC_POWER = 0,       /* q_k^p on the grid points;           params = {p, unused} */
+    PPQ_FAC_MORSE = 1,       /* (1 - exp(-a (q_k - q0)))^2;          params = {a, q0}   */
+    PPQ_FAC_TABLE = 2        /* caller-supplied values at the n_k grid points          */
+} ppq_factor_kind;
+
+/* Fields of one observable record (ppq_observables, ppq_propagate). */
+enum {
+    PPQ_OBS_T = 0,           /* time */
+    PPQ_OBS_NORM2 = 1,       /* sum |c_I|^2 over A */
+    PPQ_OBS_ENERGY = 2,      /* <psi|H_A|psi> / <psi|psi> */
+    PPQ_OBS_ACF_RE = 3,      /* autocorrelation C(t) = <psi(0)|psi(t)> (Eq. acorr), real */
+    PPQ_OBS_ACF_IM = 4,      /* imaginary part */
+    PPQ_OBS_NACTIVE = 5,     /* |A| */
+    PPQ_OBS_NABOVE = 6,      /* |{I in A : |c_I| >= theta}| (1 - this/|A| is the wasted fraction, Sec. III.A) */
+    PPQ_OBS_KRYLOV = 7,      /* Krylov dimension used by the step that produced the record */
+    PPQ_OBS_N = 8
+};
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+   run on (NULL: the library creates its own).  `precision` is a ppq_precision. */
+int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision);
+void ppq_destroy(ppq_ctx *ctx);
+/* Message of the last error on this context; valid until the next call. */
+const char *ppq_last_error(const ppq_ctx *ctx);
+
+/* Direct-product sine-DVR grid (particle-in-a-box DVR of the DVR family,
+   Sec. II.A): per dimension n[k] interior points of the box (lo[k], hi[k]),
+   q_i = lo + i (hi-lo)/(n+1), i = 1..n.  Sets the kinetic operator
+   -1/(2 mass) d^2/dq^2 on every dimension.  1 <= D <= 8, 2 <= n[k] <= 64,
+   prod n < 2^32.  Clears any operator and state. */
+int ppq_set_grid(ppq_ctx *ctx, int D, const int32_t *n, const double *lo, const double *hi, double mass);
+
+/* Grid points of dimension k (n[k] doubles, host). */
+int ppq_get_grid(const ppq_ctx *ctx, int k, double *q);
+
+/* Makes dimension k a phase-space lattice basis: n_s x n_l von Neumann
+   Gaussians projected on the DVR grid and used biorthogonally (Sec. II.B.1,
+   Eqs. pvN_def, pvb_def, psi_exp_pvb), n_s * n_l == n[k].  Cells are centred
+   at x_s = lo + (s + 1/2) dx, dx = (hi-lo)/n_s, with momenta
+   p_l = (l - (n_l-1)/2) dp, dp = 2 pi / dx.  Coefficients on this dimension
+   are the overlaps a = G^+ c; every 1D factor on it acts as G^+ h G^{-+}
+   (non-Hermitian, so steps use Arnoldi); its neighbours in adaption are the
+   lattice cells (s+-1, l), (s, l+-1).  Must be called before adding terms. */
+int ppq_set_lattice(ppq_ctx *ctx, int k, int n_s, int n_l);
+
+/* Adds the potential term coef * prod_f factor_f(q_{dims[f]}) (a product of
+   diagonal 1D factors: Sec. II.E, potential as a sum of products of diagonal
+   matrices).  kinds[f] is a ppq_factor_kind, params holds 2 doubles per
+   factor, tables holds n[dims[f]] doubles per PPQ_FAC_TABLE factor (in factor
+   order; may be NULL otherwise).  On DVR dimensions the term stays diagonal;
+   a term touching lattice dimensions becomes a product of dense factors, of
+   which at most two are supported (PPQ_E_UNSUPPORTED otherwise). */
+int ppq_add_potential_term(ppq_ctx *ctx, double coef, int nfac, const int32_t *dims, const int32_t *kinds,
+                           const double *params, const double *tables);
+
+/* Capacity of the active set (number of functions).  Grows automatically when
+   adaption needs more; reserving ahead avoids reallocation inside a run. */
+int ppq_reserve(ppq_ctx *ctx, int64_t max_active);
+
+/* Initial state: product Gaussian psi0(q) = prod_k g_k(q_k),
+   g_k = exp(-(q-centre_k)^2/(2 width_k^2) + i momentum_k (q-centre_k)),
+   sampled on the grid and normalised per dimension; on lattice dimensions
+   taken to coefficients a = G^+ g.  The active set is every function with
+   |psi0_I| >= eps plus its nearest neighbours (the adaption rule applied to
+   the full-grid packet).  psi0 also becomes the reference of C(t).
+   n_active (may be NULL) receives |A|. */
+int ppq_init_gaussian(ppq_ctx *ctx, const double *centre, const double *momentum, const double *width,
+                      double eps, int64_t *n_active);
+
+/* Replaces the state: `count` strictly ascending keys in range, coefficients
+   interleaved complex FP64 (host).  PPQ_E_ARG if keys are unsorted, repeated
+   or out of range. */
+int ppq_set_state(ppq_ctx *ctx, int64_t count, const uint64_t *keys, const double *coeff);
+
+/* Number of functions in the active set (no synchronisation needed). */
+int ppq_active_count(const ppq_ctx *ctx, int64_t *count);
+
+/* Copies the state to the host: *count = |A|; keys and coeff (2*|A| doubles)
+   are written when cap >= |A| (else PPQ_E_ARG with *count set). */
+int ppq_get_state(ppq_ctx *ctx, int64_t cap, int64_t *count, uint64_t *keys, double *coeff);
+
+/* y = P_A H P_A x on the current active set (the pruned product of Sec. II.B.2
+   computed fiber by fiber as in the appendix).  x, y: device arrays of |A|
+   complex values in key order -- interleaved FP64 for PPQ_FP64 contexts,
+   interleaved FP32 for PPQ_FP32 contexts; x and y must not overlap.
+   Enqueued on the context stream; no synchronisation. */
+int ppq_apply_h(ppq_ctx *ctx, const void *x, void *y);
+
+/* One short-iterative Lanczos (Arnoldi if any lattice dimension) step of
+   length dt with Krylov order m (m H-applications, full reorthogonalisation
+   by classical Gram-Schmidt applied twice), on the current set; no
+   adaption.  1 <= m <= 16. */
+int ppq_step(ppq_ctx *ctx, double dt, int m);
+
+/* Adaption with threshold eps (Sec. II.E, radius-1 stencil of Sec. III.A):
+   A' = {I in A : |c_I| >= eps} plus their nearest neighbours inside the grid;
+   coefficients carried over on A cap A', zero on new functions.  |c|^2 is
+   compared as fl(fl(re^2) + fl(im^2)) >= fl(eps^2) (no fused multiply-add).
+   n_active / n_above (may be NULL) receive |A'| and the kept count. */
+int ppq_prune(ppq_ctx *ctx, double eps, int64_t *n_active, int64_t *n_above);
+
+/* nsteps x {ppq_step(dt, m); ppq_prune(eps)} (eps < 0: no adaption), recording
+   an observable record (PPQ_OBS_N doubles) before the first step and after
+   every adaption into trace ((nsteps+1) * PPQ_OBS_N doubles, host; may be
+   NULL).  Synchronises once at the end. */
+int ppq_propagate(ppq_ctx *ctx, int nsteps, double dt, int m, double eps, double *trace);
+
+/* Observable record of the current state (synchronises).  eps is the
+   threshold used for PPQ_OBS_NABOVE. */
+int ppq_observables(ppq_ctx *ctx, double eps, double *out);
+
+/* Measurement helper: applies H to the current state `nrep` times (after
+   one untimed application), bracketed by HIP events recorded on the context
+   stream, and returns the mean time per application in ms (all fiber passes
+   of one P_A H P_A product).  The input is the state (FP64 contexts) or its
+   normalised FP32 copy (FP32 contexts); the output goes to an internal work
+   vector.  Synchronises. */
+int ppq_time_apply(ppq_ctx *ctx, int nrep, double *ms_per_apply);
+
+/* Fiber counts of the current set: nf[k] = number of dimension-k fibers
+   (lines of the set along dimension k), k < D.  Synchronises. */
+int ppq_fiber_counts(ppq_ctx *ctx, int64_t *nf);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

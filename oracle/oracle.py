@@ -65,6 +65,8 @@ def lib():
         L.orc_fib_count.restype = ctypes.c_int64
         L.orc_fib_count.argtypes = [vp, ctypes.c_int]
         L.orc_fib_ranges.argtypes = [vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _c_i32_p, _c_i32_p]
+        L.orc_apply_def_at.argtypes = [vp, ctypes.c_int64, _c_u64_p, _c_double_p, ctypes.c_int64, _c_int64_p,
+                                       _c_double_p]
         _LIB = L
     return _LIB
 
@@ -200,6 +202,17 @@ class Oracle:
         x = _cplx(x)
         y = np.zeros_like(x)
         lib().orc_apply_def(self._m, keys.size, _up(keys), _dp(x.view(np.float64)), _dp(y.view(np.float64)))
+        return y
+
+    def apply_def_at(self, keys, x, idx):
+        """(P H P x) at the positions idx only (plain definition)."""
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        x = _cplx(x)
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        y = np.zeros(idx.size, dtype=np.complex128)
+        if lib().orc_apply_def_at(self._m, keys.size, _up(keys), _dp(x.view(np.float64)), idx.size,
+                                  idx.ctypes.data_as(_c_int64_p), _dp(y.view(np.float64))) != 0:
+            raise ValueError("sampled application needs a model without product terms")
         return y
 
     def apply_fib(self, keys, x):

@@ -869,3 +869,30 @@ int orc_fib_ranges(const orc_fib *f, int k, int64_t fi, int cap, int32_t *lo, in
         if (nr < cap) { lo[nr] = f->rlo[k][r]; hi[nr] = f->rhi[k][r]; }
     return nr;
 }
+
+/* O-def at selected output positions only: out[s] = (P H P x)[idx[s]].
+   Used to check very large sets on a sample of outputs. */
+int orc_apply_def_at(const orc_model *m, int64_t n, const uint64_t *keys, const double *xin, int64_t ns,
+                     const int64_t *idx, double *yout)
+{
+    const zd *x = (const zd *)xin;
+    zd *y = (zd *)yout;
+    if (m->np) return -1;  /* product terms need the full intermediate */
+    for (int64_t s = 0; s < ns; ++s) {
+        int64_t p = idx[s];
+        uint64_t key = keys[p];
+        zd acc = potential_at(m, key) * x[p];
+        for (int k = 0; k < m->D; ++k) {
+            if (!m->h[k]) continue;
+            int nk = m->n[k];
+            int dk = digit(m, key, k);
+            uint64_t base = key - (uint64_t)dk * m->stride[k];
+            for (int j = 0; j < nk; ++j) {
+                int64_t q = find_key(keys, n, base + (uint64_t)j * m->stride[k]);
+                if (q >= 0) acc += m->h[k][(size_t)dk * nk + j] * x[q];
+            }
+        }
+        y[s] = acc;
+    }
+    return 0;
+}

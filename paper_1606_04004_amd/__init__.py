@@ -1,0 +1,181 @@
+"""Dynamically pruned wavepacket propagation on AMD MI355X (gfx950).
+
+Thin Python front end of libppq.so (include/ppq.h).  It only marshals
+arguments: every step of the propagation runs in the library's HIP kernels.
+PyTorch is used for device memory and streams when the caller passes tensors.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _ppq
+from ._ppq import OBS_FIELDS, OBS_N, PPQ_FP32, PPQ_FP64, PPQError  # noqa: F401
+
+__all__ = ["Propagator", "PPQError", "PPQ_FP64", "PPQ_FP32", "OBS_FIELDS"]
+
+_KIND = {"power": _ppq.PPQ_FAC_POWER, "morse": _ppq.PPQ_FAC_MORSE, "table": _ppq.PPQ_FAC_TABLE}
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Propagator:
+    """One library context holding a model card's operator and a state.
+
+    precision: PPQ_FP64 or PPQ_FP32; device: HIP device index; stream: a
+    torch.cuda.Stream (or raw hipStream_t int) to run on, None for the
+    library's own stream.
+    """
+
+    def __init__(self, card, precision=PPQ_FP64, device=0, stream=None):
+        self.lib = _ppq.load()
+        self.card = card
+        self.precision = precision
+        self.D = int(card["D"])
+        self.n = [int(v) for v in card["n"]]
+        handle = None
+        if stream is not None:
+            handle = getattr(stream, "cuda_stream", stream)
+        ctx = ctypes.c_void_p()
+        _ppq.check(None, self.lib.ppq_create(ctypes.byref(ctx), int(device),
+                                             ctypes.c_void_p(handle) if handle else None, int(precision)))
+        self.ctx = ctx
+        n, pn = _i32(self.n)
+        lo, plo = _d(card["lo"])
+        hi, phi = _d(card["hi"])
+        self._call("ppq_set_grid", self.D, pn, plo, phi, float(card["mass"]))
+        if card.get("basis", "dvr") == "pvb":
+            ns, nl = card["lattice"]
+            for k in range(self.D):
+                self._call("ppq_set_lattice", k, int(ns), int(nl))
+        for t in card["terms"]:
+            self.add_term(t["coef"], t["factors"])
+
+    # ---- plumbing -----------------------------------------------------------
+    def _call(self, name, *args):
+        return _ppq.check(self.ctx, getattr(self.lib, name)(self.ctx, *args))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ppq_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- model --------------------------------------------------------------
+    def add_term(self, coef, factors):
+        dims, kinds, params, tables = [], [], [], []
+        for f in factors:
+            dims.append(int(f["dim"]))
+            kinds.append(_KIND[f["kind"]])
+            if f["kind"] == "power":
+                params += [float(f["p"]), 0.0]
+            elif f["kind"] == "morse":
+                params += [float(f["a"]), float(f["q0"])]
+            else:
+                params += [0.0, 0.0]
+                tables += list(f["values"])
+        d, pd = _i32(dims or [0])
+        k, pk = _i32(kinds or [0])
+        p, pp = _d(params or [0.0])
+        tb, ptb = _d(tables or [0.0])
+        self._call("ppq_add_potential_term", float(coef), len(factors), pd, pk, pp, ptb if tables else None)
+
+    def grid(self, k):
+        q = np.zeros(self.n[k])
+        _ppq.check(self.ctx, self.lib.ppq_get_grid(self.ctx, k, q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return q
+
+    def reserve(self, cap):
+        self._call("ppq_reserve", int(cap))
+
+    # ---- state --------------------------------------------------------------
+    def init_state(self, eps=None):
+        ps = self.card["psi0"]
+        eps = self.card["eps"] if eps is None else eps
+        c, pc = _d(ps["centre"])
+        m, pm = _d(ps["momentum"])
+        w, pw = _d(ps["width"])
+        na = ctypes.c_int64(0)
+        self._call("ppq_init_gaussian", pc, pm, pw, float(eps), ctypes.byref(na))
+        return na.value
+
+    def set_state(self, keys, coeff):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        c = np.ascontiguousarray(coeff, dtype=np.complex128)
+        self._call("ppq_set_state", keys.size, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                   c.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+    def active_count(self):
+        n = ctypes.c_int64(0)
+        self._call("ppq_active_count", ctypes.byref(n))
+        return n.value
+
+    def state(self):
+        cnt = ctypes.c_int64(0)
+        code = self.lib.ppq_get_state(self.ctx, 0, ctypes.byref(cnt), None, None)
+        if code not in (0, -1):
+            _ppq.check(self.ctx, code)
+        n = cnt.value
+        keys = np.zeros(n, dtype=np.uint64)
+        c = np.zeros(n, dtype=np.complex128)
+        self._call("ppq_get_state", n, ctypes.byref(cnt), keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                   c.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return keys, c
+
+    # ---- operator and propagation ---------------------------------------------
+    def apply_h(self, x, y):
+        """y = P H P x for device tensors/pointers of the context precision (complex interleaved)."""
+        px = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+        py = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
+        self._call("ppq_apply_h", ctypes.c_void_p(px), ctypes.c_void_p(py))
+
+    def step(self, dt=None, m=None):
+        dt = self.card["dt"] if dt is None else dt
+        m = self.card["krylov"] if m is None else m
+        self._call("ppq_step", float(dt), int(m))
+
+    def prune(self, eps=None):
+        eps = self.card["eps"] if eps is None else eps
+        na, nb = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._call("ppq_prune", float(eps), ctypes.byref(na), ctypes.byref(nb))
+        return na.value, nb.value
+
+    def propagate(self, nsteps=None, dt=None, m=None, eps=None, prune=True):
+        nsteps = self.card["nsteps"] if nsteps is None else nsteps
+        dt = self.card["dt"] if dt is None else dt
+        m = self.card["krylov"] if m is None else m
+        eps = self.card["eps"] if eps is None else eps
+        if not prune:
+            eps = -1.0
+        trace = np.zeros((nsteps + 1, OBS_N))
+        self._call("ppq_propagate", int(nsteps), float(dt), int(m), float(eps),
+                   trace.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return trace
+
+    def observables(self, eps=None):
+        eps = self.card["eps"] if eps is None else eps
+        out = np.zeros(OBS_N)
+        self._call("ppq_observables", float(eps), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return dict(zip(OBS_FIELDS[1:7], out[1:7]))
+
+    def time_apply(self, nrep):
+        ms = ctypes.c_double(0.0)
+        self._call("ppq_time_apply", int(nrep), ctypes.byref(ms))
+        return ms.value
+
+    def fiber_counts(self):
+        nf = np.zeros(self.D, dtype=np.int64)
+        self._call("ppq_fiber_counts", nf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        return nf

@@ -1,0 +1,1253 @@
+// C ABI (include/ppq.h): context, operator assembly, state, and the
+// orchestration of one propagation step on one HIP stream.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ppq_internal.hpp"
+#include "ppq_model.hpp"
+
+using namespace ppq;
+
+namespace {
+
+struct Factor {
+    int dim;
+    int kind;
+    double p0, p1;
+    std::vector<double> table;
+};
+struct Term {
+    double coef;
+    std::vector<Factor> f;
+};
+
+// a product term with two dense (lattice) factors, grouped for evaluation
+struct PairTerm {
+    double coef;
+    int k1, f1;  // outer factor (lower dimension), index into dense factor list
+    int k2, f2;  // inner factor (applied first)
+};
+
+int bucket(int n)
+{
+    if (n <= 8) return 8;
+    if (n <= 16) return 16;
+    if (n <= 24) return 24;
+    if (n <= 32) return 32;
+    if (n <= 48) return 48;
+    return 64;
+}
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+inline void ck(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw HipError{e, what};
+}
+
+template <class T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+template <class T>
+T *dalloc(int64_t count)
+{
+    void *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc(&p, (size_t)count * sizeof(T));
+    if (e != hipSuccess) throw std::bad_alloc();
+    return (T *)p;
+}
+
+}  // namespace
+
+struct ppq_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int precision = PPQ_FP64;
+    std::string err;
+    bool poisoned = false;
+
+    // grid
+    bool has_grid = false;
+    GridDesc g{};
+    double lo[MAXD]{}, hi[MAXD]{}, mass = 1.0;
+    int nb[MAXD]{};  // padded 1D size per dimension
+    bool lattice[MAXD]{};
+    bool any_lattice = false;
+    int64_t nwords = 0;
+
+    // operator (host description)
+    std::vector<Term> terms;
+    bool op_dirty = true;
+    // built operator (device)
+    double *T64[MAXD]{};   // real factor per DVR dimension (kinetic), nb x nb
+    float *T32[MAXD]{};
+    double2 *H64[MAXD]{};  // complex factor per lattice dimension
+    float2 *H32[MAXD]{};
+    std::vector<double2 *> F64;  // distinct dense factors of product terms
+    std::vector<float2 *> F32;
+    std::vector<int> Fdim;
+    std::vector<PairTerm> pairs;
+    double *pot_coef = nullptr;
+    int *pot_tab = nullptr;
+    double *pot_tabs = nullptr;
+    int pot_nterm = 0;
+    int pot_nmax = 0;
+
+    // state
+    int64_t cap = 0;
+    int64_t nact = 0;
+    bool has_state = false;
+    int cur = 0;
+    uint32_t *keys[2]{};
+    double2 *psi[2]{};
+    double2 *psi_tmp = nullptr;
+    double *V64 = nullptr;
+    float *V32 = nullptr;
+    bool derived_valid = false;  // fibers + potential cache match the set
+
+    // fiber tables
+    uint32_t *pi[MAXD]{};
+    uint32_t *off[MAXD]{};
+    uint64_t *mask[MAXD]{};
+    int64_t nf[MAXD]{};
+
+    // work
+    uint32_t *flags = nullptr, *fidx = nullptr;
+    uint64_t *tmpmask = nullptr;
+    uint32_t *scan_tmp = nullptr;
+    int64_t scan_tmp_n = 0;
+    uint64_t *bm = nullptr;
+    uint32_t *prefix = nullptr;
+    uint32_t *small = nullptr;            // device counters
+    unsigned long long *count = nullptr;  // device counter
+    uint32_t *h_small = nullptr;          // pinned mirrors
+    unsigned long long *h_count = nullptr;
+
+    // Krylov
+    int kv_m = 0;
+    int64_t kv_cap = 0;
+    void *Vk = nullptr;
+    void *wk = nullptr;
+    std::vector<void *> zbuf;  // intermediates of product terms
+    KState *ks = nullptr;
+    double2 *partial = nullptr;
+
+    // reference packet
+    bool has_ref = false;
+    double2 *init_tabs = nullptr;
+    double2 *bra_tabs = nullptr;
+    int tab_nmax = 0;
+
+    // records
+    double *rec = nullptr;
+    int64_t rec_cap = 0;
+
+    // measurement
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+int fail(ppq_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(ppq_ctx *c, const HipError &e)
+{
+    c->poisoned = true;
+    c->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+    return PPQ_E_HIP;
+}
+
+void free_state_buffers(ppq_ctx *c)
+{
+    for (int i = 0; i < 2; ++i) {
+        dfree(c->keys[i]);
+        dfree(c->psi[i]);
+    }
+    dfree(c->psi_tmp);
+    dfree(c->V64);
+    dfree(c->V32);
+    for (int k = 0; k < MAXD; ++k) {
+        dfree(c->pi[k]);
+        dfree(c->off[k]);
+        dfree(c->mask[k]);
+    }
+    dfree(c->flags);
+    dfree(c->fidx);
+    dfree(c->tmpmask);
+    dfree(c->scan_tmp);
+    c->cap = 0;
+}
+
+void free_krylov(ppq_ctx *c)
+{
+    dfree(c->Vk);
+    dfree(c->wk);
+    for (auto &z : c->zbuf) dfree(z);
+    c->zbuf.clear();
+    c->kv_m = 0;
+    c->kv_cap = 0;
+}
+
+void free_operator(ppq_ctx *c)
+{
+    for (int k = 0; k < MAXD; ++k) {
+        dfree(c->T64[k]);
+        dfree(c->T32[k]);
+        dfree(c->H64[k]);
+        dfree(c->H32[k]);
+    }
+    for (auto &p : c->F64) dfree(p);
+    for (auto &p : c->F32) dfree(p);
+    c->F64.clear();
+    c->F32.clear();
+    c->Fdim.clear();
+    c->pairs.clear();
+    dfree(c->pot_coef);
+    dfree(c->pot_tab);
+    dfree(c->pot_tabs);
+    c->pot_nterm = 0;
+    c->op_dirty = true;
+}
+
+// (Re)allocates every per-point buffer for at least n points, keeping the
+// current keys and coefficients.
+void ensure_capacity(ppq_ctx *c, int64_t n)
+{
+    if (n <= c->cap) return;
+    int64_t nc = std::max<int64_t>(n, c->cap + c->cap / 4);
+    nc = std::max<int64_t>(nc, 1024);
+    uint32_t *nk = dalloc<uint32_t>(nc);
+    double2 *np = dalloc<double2>(nc);
+    if (c->has_state && c->nact > 0) {
+        ck(hipMemcpyAsync(nk, c->keys[c->cur], c->nact * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream),
+           "copy keys");
+        ck(hipMemcpyAsync(np, c->psi[c->cur], c->nact * sizeof(double2), hipMemcpyDeviceToDevice, c->stream),
+           "copy psi");
+    }
+    ck(hipStreamSynchronize(c->stream), "sync");
+    free_state_buffers(c);
+    c->cap = nc;
+    c->cur = 0;
+    c->keys[0] = nk;
+    c->psi[0] = np;
+    c->keys[1] = dalloc<uint32_t>(nc);
+    c->psi[1] = dalloc<double2>(nc);
+    c->psi_tmp = dalloc<double2>(nc);
+    if (c->precision == PPQ_FP64) c->V64 = dalloc<double>(nc);
+    else c->V32 = dalloc<float>(nc);
+    for (int k = 0; k < c->g.D; ++k) {
+        if (k < c->g.D - 1) c->pi[k] = dalloc<uint32_t>(nc);
+        c->off[k] = dalloc<uint32_t>(nc + 1);
+        c->mask[k] = dalloc<uint64_t>(nc);
+    }
+    c->flags = dalloc<uint32_t>(nc);
+    c->fidx = dalloc<uint32_t>(nc);
+    c->tmpmask = dalloc<uint64_t>(nc);
+    c->scan_tmp_n = std::max(scan_tmp_words(nc), scan_tmp_words(c->nwords));
+    c->scan_tmp = dalloc<uint32_t>(c->scan_tmp_n);
+    c->derived_valid = false;
+    free_krylov(c);
+}
+
+void ensure_krylov(ppq_ctx *c, int m)
+{
+    if (c->Vk && c->kv_m >= m && c->kv_cap == c->cap) return;
+    free_krylov(c);
+    size_t es = c->precision == PPQ_FP64 ? sizeof(double2) : sizeof(float2);
+    void *p = nullptr;
+    if (hipMalloc(&p, es * (size_t)(m + 1) * (size_t)c->cap) != hipSuccess) throw std::bad_alloc();
+    c->Vk = p;
+    if (hipMalloc(&p, es * (size_t)c->cap) != hipSuccess) throw std::bad_alloc();
+    c->wk = p;
+    c->kv_m = m;
+    c->kv_cap = c->cap;
+}
+
+void ensure_zbuf(ppq_ctx *c)
+{
+    size_t need = c->F64.size();
+    if (c->zbuf.size() >= need && c->kv_cap == c->cap && c->Vk) return;
+    size_t es = c->precision == PPQ_FP64 ? sizeof(double2) : sizeof(float2);
+    while (c->zbuf.size() < need) {
+        void *p = nullptr;
+        if (hipMalloc(&p, es * (size_t)c->cap) != hipSuccess) throw std::bad_alloc();
+        c->zbuf.push_back(p);
+    }
+}
+
+// ---- operator assembly -------------------------------------------------------
+std::vector<double> factor_values(const ppq_ctx *c, const Factor &f)
+{
+    int k = f.dim;
+    int n = c->g.n[k];
+    std::vector<double> q = sine_dvr_points(n, c->lo[k], c->hi[k]);
+    std::vector<double> v(n);
+    for (int i = 0; i < n; ++i) {
+        if (f.kind == PPQ_FAC_POWER) {
+            int p = (int)f.p0;
+            double r = 1.0;
+            for (int e = 0; e < p; ++e) r *= q[i];
+            v[i] = r;
+        } else if (f.kind == PPQ_FAC_MORSE) {
+            double e = 1.0 - std::exp(-f.p0 * (q[i] - f.p1));
+            v[i] = e * e;
+        } else {
+            v[i] = f.table[i];
+        }
+    }
+    return v;
+}
+
+template <class T>
+T *upload(const std::vector<T> &h, hipStream_t s)
+{
+    T *d = dalloc<T>((int64_t)h.size());
+    ck(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+    return d;
+}
+
+// Dense factor on a lattice dimension: G^+ h G^{-+} (padded to nb x nb, complex).
+struct LatticeMaps {
+    std::vector<cd> G, Gadj, GinvAdj, Ginv;
+};
+
+LatticeMaps lattice_maps(const ppq_ctx *c, int k)
+{
+    LatticeMaps L;
+    int n = c->g.n[k];
+    L.G = pvb_projection(n, c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k]);
+    L.Gadj = adjoint(L.G, n);
+    L.GinvAdj = L.Gadj;
+    if (!invert(L.GinvAdj, n)) throw std::runtime_error("singular lattice projection");
+    L.Ginv = adjoint(L.GinvAdj, n);
+    return L;
+}
+
+std::vector<cd> similarity(const LatticeMaps &L, const std::vector<cd> &h, int n)
+{
+    return matmul(matmul(L.Gadj, h, n), L.GinvAdj, n);
+}
+
+void build_operator(ppq_ctx *c)
+{
+    if (!c->op_dirty) return;
+    for (int k = 0; k < MAXD; ++k) {
+        dfree(c->T64[k]);
+        dfree(c->T32[k]);
+        dfree(c->H64[k]);
+        dfree(c->H32[k]);
+    }
+    for (auto &p : c->F64) dfree(p);
+    for (auto &p : c->F32) dfree(p);
+    c->F64.clear();
+    c->F32.clear();
+    c->Fdim.clear();
+    c->pairs.clear();
+    dfree(c->pot_coef);
+    dfree(c->pot_tab);
+    dfree(c->pot_tabs);
+    const int D = c->g.D;
+    hipStream_t s = c->stream;
+    if (!c->any_lattice) {
+        for (int k = 0; k < D; ++k) {
+            int n = c->g.n[k], b = c->nb[k];
+            std::vector<double> T = sine_dvr_kinetic(n, c->lo[k], c->hi[k], c->mass);
+            std::vector<double> P((size_t)b * b, 0.0);
+            std::vector<float> Pf((size_t)b * b, 0.0f);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    P[(size_t)i * b + j] = T[(size_t)i * n + j];
+                    Pf[(size_t)i * b + j] = (float)T[(size_t)i * n + j];
+                }
+            c->T64[k] = upload(P, s);
+            c->T32[k] = upload(Pf, s);
+        }
+        // diagonal potential: one table per factor
+        int nmax = 0;
+        for (int k = 0; k < D; ++k) nmax = std::max(nmax, c->g.n[k]);
+        std::vector<double> coef, tabs;
+        std::vector<int> tab;
+        for (const Term &t : c->terms) {
+            std::vector<int> idx(D, -1);
+            std::vector<std::vector<double>> per(D);
+            for (const Factor &f : t.f) {
+                std::vector<double> v = factor_values(c, f);
+                if (per[f.dim].empty()) per[f.dim] = v;
+                else
+                    for (size_t i = 0; i < v.size(); ++i) per[f.dim][i] *= v[i];
+            }
+            for (int k = 0; k < D; ++k) {
+                if (per[k].empty()) continue;
+                idx[k] = (int)(tabs.size() / nmax);
+                per[k].resize(nmax, 0.0);
+                tabs.insert(tabs.end(), per[k].begin(), per[k].end());
+            }
+            coef.push_back(t.coef);
+            tab.insert(tab.end(), idx.begin(), idx.end());
+        }
+        c->pot_nterm = (int)coef.size();
+        c->pot_nmax = nmax;
+        if (coef.empty()) {
+            coef.push_back(0.0);
+            tab.assign(D, -1);
+            tabs.assign(nmax, 0.0);
+        }
+        if (tabs.empty()) tabs.assign(nmax, 0.0);
+        c->pot_coef = upload(coef, s);
+        c->pot_tab = upload(tab, s);
+        c->pot_tabs = upload(tabs, s);
+    } else {
+        std::vector<LatticeMaps> L(D);
+        for (int k = 0; k < D; ++k) L[k] = lattice_maps(c, k);
+        std::vector<std::vector<cd>> Hk(D);
+        for (int k = 0; k < D; ++k) {
+            int n = c->g.n[k];
+            std::vector<double> T = sine_dvr_kinetic(n, c->lo[k], c->hi[k], c->mass);
+            std::vector<cd> h((size_t)n * n);
+            for (size_t i = 0; i < h.size(); ++i) h[i] = T[i];
+            Hk[k] = h;  // DVR-space sum, transformed at the end
+        }
+        // distinct dense factors of product terms keyed by (dim, values)
+        std::vector<std::vector<double>> fvals;
+        auto factor_id = [&](int k, const std::vector<double> &v) {
+            for (size_t i = 0; i < fvals.size(); ++i)
+                if (c->Fdim[i] == k && fvals[i] == v) return (int)i;
+            fvals.push_back(v);
+            c->Fdim.push_back(k);
+            return (int)fvals.size() - 1;
+        };
+        for (const Term &t : c->terms) {
+            std::vector<std::vector<double>> per(D);
+            for (const Factor &f : t.f) {
+                std::vector<double> v = factor_values(c, f);
+                if (per[f.dim].empty()) per[f.dim] = v;
+                else
+                    for (size_t i = 0; i < v.size(); ++i) per[f.dim][i] *= v[i];
+            }
+            std::vector<int> dims;
+            for (int k = 0; k < D; ++k)
+                if (!per[k].empty()) dims.push_back(k);
+            if (dims.size() == 1) {
+                int k = dims[0], n = c->g.n[k];
+                for (int i = 0; i < n; ++i) Hk[k][(size_t)i * n + i] += t.coef * per[k][i];
+            } else if (dims.size() == 2) {
+                PairTerm p;
+                p.coef = t.coef;
+                p.k1 = dims[0];
+                p.k2 = dims[1];
+                p.f1 = factor_id(dims[0], per[dims[0]]);
+                p.f2 = factor_id(dims[1], per[dims[1]]);
+                c->pairs.push_back(p);
+            } else if (!dims.empty()) {
+                throw std::invalid_argument("lattice bases support potential terms on at most two dimensions");
+            }
+        }
+        auto pad_upload = [&](const std::vector<cd> &h, int n, int b, double2 **d64, float2 **d32) {
+            std::vector<double2> P((size_t)b * b, make_double2(0.0, 0.0));
+            std::vector<float2> Pf((size_t)b * b, make_float2(0.f, 0.f));
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    cd v = h[(size_t)i * n + j];
+                    P[(size_t)i * b + j] = make_double2(v.real(), v.imag());
+                    Pf[(size_t)i * b + j] = make_float2((float)v.real(), (float)v.imag());
+                }
+            *d64 = upload(P, s);
+            *d32 = upload(Pf, s);
+        };
+        for (int k = 0; k < D; ++k) {
+            int n = c->g.n[k];
+            std::vector<cd> ht = similarity(L[k], Hk[k], n);
+            pad_upload(ht, n, c->nb[k], &c->H64[k], &c->H32[k]);
+        }
+        for (size_t i = 0; i < fvals.size(); ++i) {
+            int k = c->Fdim[i], n = c->g.n[k];
+            std::vector<cd> h((size_t)n * n, cd(0.0, 0.0));
+            for (int j = 0; j < n; ++j) h[(size_t)j * n + j] = fvals[i][j];
+            std::vector<cd> ht = similarity(L[k], h, n);
+            double2 *d64;
+            float2 *d32;
+            pad_upload(ht, n, c->nb[k], &d64, &d32);
+            c->F64.push_back(d64);
+            c->F32.push_back(d32);
+        }
+    }
+    ck(hipStreamSynchronize(s), "operator upload");
+    c->op_dirty = false;
+}
+
+// ---- derived tables of the current set --------------------------------------
+void build_derived(ppq_ctx *c)
+{
+    if (c->derived_valid) return;
+    build_operator(c);
+    const int D = c->g.D;
+    const int64_t n = c->nact;
+    hipStream_t s = c->stream;
+    const uint32_t *keys = c->keys[c->cur];
+    // last dimension: contiguous runs
+    last_flags(keys, n, c->g.n[D - 1], c->flags, s);
+    scan_u32(c->flags, n, c->fidx, &c->small[D - 1], c->scan_tmp, s);
+    last_fill(keys, n, c->g.n[D - 1], c->flags, c->fidx, &c->small[D - 1], c->off[D - 1], c->mask[D - 1], s);
+    for (int k = 0; k < D - 1; ++k) {
+        fill_u64(c->bm, c->nwords + 2, 0ull, s);
+        rot_set(keys, n, k, c->g, c->bm, s);
+        scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
+        rot_rank(keys, n, k, c->g, c->bm, c->prefix, c->pi[k], c->flags, c->tmpmask, s);
+        scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
+        fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
+    }
+    if (!c->any_lattice) {
+        PotDesc pd{c->pot_nterm, D, c->pot_nmax, c->pot_coef, c->pot_tab, c->pot_tabs};
+        potential(keys, n, c->g, pd, c->V64, c->V32, s);
+    }
+    ck(hipMemcpyAsync(c->h_small, c->small, sizeof(uint32_t) * 2 * MAXD, hipMemcpyDeviceToHost, s), "nf");
+    ck(hipStreamSynchronize(s), "fibers");
+    for (int k = 0; k < D; ++k) c->nf[k] = n > 0 ? c->h_small[k] : 0;
+    c->derived_valid = true;
+}
+
+FiberPass pass_of(const ppq_ctx *c, int k)
+{
+    FiberPass fp;
+    fp.pi = (k == c->g.D - 1) ? nullptr : c->pi[k];
+    fp.off = c->off[k];
+    fp.mask = c->mask[k];
+    fp.nf = c->nf[k];
+    fp.nmax = c->nb[k];
+    return fp;
+}
+
+// y = P H P x on the current set (device vectors of the context precision)
+void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
+{
+    const int D = c->g.D;
+    hipStream_t s = c->stream;
+    if (c->nact == 0) return;
+    if (!c->any_lattice) {
+        if (c->precision == PPQ_FP64) {
+            const double2 *x = (const double2 *)xv;
+            double2 *y = (double2 *)yv;
+            hpsi_real_f64(pass_of(c, D - 1), c->T64[D - 1], x, c->V64, y, true, skip_if, skip_j, s);
+            for (int k = D - 2; k >= 0; --k)
+                hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
+        } else {
+            const float2 *x = (const float2 *)xv;
+            float2 *y = (float2 *)yv;
+            hpsi_real_f32(pass_of(c, D - 1), c->T32[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
+            for (int k = D - 2; k >= 0; --k)
+                hpsi_real_f32(pass_of(c, k), c->T32[k], x, nullptr, y, false, skip_if, skip_j, s);
+        }
+        return;
+    }
+    // lattice: single-dimension factors, then product terms (inner factor first,
+    // truncated to the set, then the outer factor on a combination of inner results)
+    ensure_zbuf(c);
+    std::vector<int> inner_ids;
+    for (const PairTerm &p : c->pairs)
+        if (std::find(inner_ids.begin(), inner_ids.end(), p.f2) == inner_ids.end()) inner_ids.push_back(p.f2);
+    std::vector<int> outer_ids;
+    for (const PairTerm &p : c->pairs)
+        if (std::find(outer_ids.begin(), outer_ids.end(), p.f1) == outer_ids.end()) outer_ids.push_back(p.f1);
+    if (c->precision == PPQ_FP64) {
+        const double2 *x = (const double2 *)xv;
+        double2 *y = (double2 *)yv;
+        CInput in{};
+        in.nin = 1;
+        in.x[0] = x;
+        in.c[0] = make_double2(1.0, 0.0);
+        hpsi_cplx_f64(pass_of(c, D - 1), c->H64[D - 1], in, y, false, nullptr, skip_if, skip_j, s);
+        for (int k = D - 2; k >= 0; --k) hpsi_cplx_f64(pass_of(c, k), c->H64[k], in, y, true, nullptr, skip_if, skip_j, s);
+        for (size_t i = 0; i < inner_ids.size(); ++i) {
+            int f = inner_ids[i];
+            hpsi_cplx_f64(pass_of(c, c->Fdim[f]), c->F64[f], in, (double2 *)c->zbuf[i], false, nullptr, skip_if,
+                          skip_j, s);
+        }
+        for (int f : outer_ids) {
+            CInput acc{};
+            for (const PairTerm &p : c->pairs) {
+                if (p.f1 != f) continue;
+                int zi = (int)(std::find(inner_ids.begin(), inner_ids.end(), p.f2) - inner_ids.begin());
+                acc.x[acc.nin] = (const double2 *)c->zbuf[zi];
+                acc.c[acc.nin] = make_double2(p.coef, 0.0);
+                if (++acc.nin == 4) {
+                    hpsi_cplx_f64(pass_of(c, c->Fdim[f]), c->F64[f], acc, y, true, nullptr, skip_if, skip_j, s);
+                    acc.nin = 0;
+                }
+            }
+            if (acc.nin) hpsi_cplx_f64(pass_of(c, c->Fdim[f]), c->F64[f], acc, y, true, nullptr, skip_if, skip_j, s);
+        }
+    } else {
+        const float2 *x = (const float2 *)xv;
+        float2 *y = (float2 *)yv;
+        CInput32 in{};
+        in.nin = 1;
+        in.x[0] = x;
+        in.c[0] = make_float2(1.f, 0.f);
+        hpsi_cplx_f32(pass_of(c, D - 1), c->H32[D - 1], in, y, false, nullptr, skip_if, skip_j, s);
+        for (int k = D - 2; k >= 0; --k) hpsi_cplx_f32(pass_of(c, k), c->H32[k], in, y, true, nullptr, skip_if, skip_j, s);
+        for (size_t i = 0; i < inner_ids.size(); ++i) {
+            int f = inner_ids[i];
+            hpsi_cplx_f32(pass_of(c, c->Fdim[f]), c->F32[f], in, (float2 *)c->zbuf[i], false, nullptr, skip_if,
+                          skip_j, s);
+        }
+        for (int f : outer_ids) {
+            CInput32 acc{};
+            for (const PairTerm &p : c->pairs) {
+                if (p.f1 != f) continue;
+                int zi = (int)(std::find(inner_ids.begin(), inner_ids.end(), p.f2) - inner_ids.begin());
+                acc.x[acc.nin] = (const float2 *)c->zbuf[zi];
+                acc.c[acc.nin] = make_float2((float)p.coef, 0.f);
+                if (++acc.nin == 4) {
+                    hpsi_cplx_f32(pass_of(c, c->Fdim[f]), c->F32[f], acc, y, true, nullptr, skip_if, skip_j, s);
+                    acc.nin = 0;
+                }
+            }
+            if (acc.nin) hpsi_cplx_f32(pass_of(c, c->Fdim[f]), c->F32[f], acc, y, true, nullptr, skip_if, skip_j, s);
+        }
+    }
+}
+
+template <class C>
+void step_impl(ppq_ctx *c, double dt, int m)
+{
+    hipStream_t s = c->stream;
+    const int64_t n = c->nact;
+    const int64_t ld = c->cap;
+    C *Vb = (C *)c->Vk;
+    C *w = (C *)c->wk;
+    KState *ks = c->ks;
+    const int *meff = &ks->meff;
+    const bool herm = !c->any_lattice;
+    norm2_partial(c->psi[c->cur], n, c->partial, s);
+    reduce_krylov(c->partial, RED_BLOCKS, 1, ks, 0, RED_NORM0, m, s);
+    normalise_from_master<C>(c->psi[c->cur], n, ks, Vb, s);
+    for (int j = 0; j < m; ++j) {
+        const C *vj = Vb + (int64_t)j * ld;
+        apply_internal(c, vj, w, meff, j);
+        const bool last = (j == m - 1);
+        if (last && herm) {
+            cgs_dots<C>(vj, ld, 1, w, n, c->partial, meff, j, s);
+            reduce_krylov(c->partial, RED_BLOCKS, 1, ks, j, RED_H1, m, s, j);
+            break;
+        }
+        cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, meff, j, s);
+        reduce_krylov(c->partial, RED_BLOCKS, j + 1, ks, j, RED_H1, m, s);
+        cgs_update_dots<C>(Vb, ld, j + 1, w, n, ks->h1, c->partial, meff, j, s);
+        reduce_krylov(c->partial, RED_BLOCKS, j + 1, ks, j, RED_H2, m, s);
+        if (last) break;
+        C *vn = Vb + (int64_t)(j + 1) * ld;
+        cgs_update_norm<C>(Vb, ld, j + 1, w, vn, n, ks->h2, c->partial, meff, j, s);
+        reduce_krylov(c->partial, RED_BLOCKS, 1, ks, j, RED_BETA, m, s);
+        scale_vec<C>(vn, n, &ks->inv_beta, meff, j + 1, s);
+    }
+    krylov_expv(ks, m, dt, herm ? 1 : 0, s);
+    lincomb<C>(Vb, ld, m, c->psi[c->cur], n, ks, c->psi_tmp, s);
+    std::swap(c->psi[c->cur], c->psi_tmp);
+}
+
+void do_step(ppq_ctx *c, double dt, int m)
+{
+    build_derived(c);
+    ensure_krylov(c, m);
+    if (c->nact == 0) return;
+    if (c->precision == PPQ_FP64) step_impl<double2>(c, dt, m);
+    else step_impl<float2>(c, dt, m);
+}
+
+// adaption; returns false (state untouched) only on allocation failure
+void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
+{
+    hipStream_t s = c->stream;
+    const int64_t n_old = c->nact;
+    double eps2 = eps * eps;
+    fill_u64(c->bm, c->nwords + 2, 0ull, s);
+    fill_u64((uint64_t *)c->count, 1, 0ull, s);
+    dilate(c->keys[c->cur], c->psi[c->cur], n_old, c->g, eps2, c->bm, c->count, s);
+    scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
+    ck(hipMemcpyAsync(c->h_small + MAXD, c->small + MAXD, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "count");
+    ck(hipMemcpyAsync(c->h_count, c->count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "count");
+    ck(hipStreamSynchronize(s), "prune count");
+    int64_t n_new = c->h_small[MAXD];
+    if (nabove_out) *nabove_out = (int64_t)*c->h_count;
+    if (n_new > c->cap) ensure_capacity(c, n_new);  // keeps keys/psi of the current set
+    int nxt = 1 - c->cur;
+    compact(c->bm, c->prefix, c->nwords, c->keys[nxt], s);
+    fill_zero_bytes(c->psi[nxt], n_new * (int64_t)sizeof(double2), s);
+    remap(c->keys[c->cur], c->psi[c->cur], n_old, c->bm, c->prefix, c->psi[nxt], s);
+    c->cur = nxt;
+    c->nact = n_new;
+    c->derived_valid = false;
+}
+
+void set_record_host(ppq_ctx *c, int64_t r, double t, int krylov)
+{
+    // t, |A| and Krylov dimension are host-known; written via a small H2D copy
+    double vals[3] = {t, (double)c->nact, (double)krylov};
+    double *rec = c->rec + r * PPQ_OBS_N;
+    ck(hipMemcpyAsync(rec + PPQ_OBS_T, &vals[0], sizeof(double), hipMemcpyHostToDevice, c->stream), "rec");
+    ck(hipMemcpyAsync(rec + PPQ_OBS_NACTIVE, &vals[1], sizeof(double), hipMemcpyHostToDevice, c->stream), "rec");
+    ck(hipMemcpyAsync(rec + PPQ_OBS_KRYLOV, &vals[2], sizeof(double), hipMemcpyHostToDevice, c->stream), "rec");
+    ck(hipStreamSynchronize(c->stream), "rec");
+}
+
+void ensure_records(ppq_ctx *c, int64_t nrec)
+{
+    if (c->rec_cap >= nrec) return;
+    dfree(c->rec);
+    c->rec = dalloc<double>(nrec * PPQ_OBS_N);
+    c->rec_cap = nrec;
+    fill_zero_bytes(c->rec, nrec * PPQ_OBS_N * (int64_t)sizeof(double), c->stream);
+}
+
+// observables of the current set into record r (energy left to the caller)
+void observe_into(ppq_ctx *c, int64_t r, double eps)
+{
+    double *rec = c->rec + r * PPQ_OBS_N;
+    // without a reference packet the tables are zero and C(t) reads 0
+    const double2 *bra = c->bra_tabs;
+    obs_partial(c->keys[c->cur], c->psi[c->cur], c->nact, c->g, bra, c->tab_nmax, eps * eps, c->partial,
+                c->stream);
+    obs_final(c->partial, RED_BLOCKS, rec, c->stream);
+}
+
+// energy of the current state by one explicit application (FP64 master in, precision of the context)
+void energy_into(ppq_ctx *c, int64_t r)
+{
+    double *rec = c->rec + r * PPQ_OBS_N;
+    if (c->nact == 0) return;
+    ensure_krylov(c, std::max(c->kv_m, 1));
+    if (c->precision == PPQ_FP64) {
+        apply_internal(c, c->psi[c->cur], c->wk, nullptr, 0);
+        dot_partial(c->psi[c->cur], (const double2 *)c->wk, c->nact, c->partial, c->stream);
+    } else {
+        // FP32 form: H acts on the FP32 copy; the inner product is accumulated in FP64
+        float2 *x32 = (float2 *)c->Vk;
+        KState *ks = c->ks;
+        norm2_partial(c->psi[c->cur], c->nact, c->partial, c->stream);
+        reduce_krylov(c->partial, RED_BLOCKS, 1, ks, 0, RED_NORM0, 1, c->stream);
+        normalise_from_master<float2>(c->psi[c->cur], c->nact, ks, x32, c->stream);
+        apply_internal(c, x32, c->wk, nullptr, 0);
+        cgs_dots<float2>(x32, c->cap, 1, (const float2 *)c->wk, c->nact, c->partial, nullptr, 0, c->stream);
+        reduce_krylov(c->partial, RED_BLOCKS, 1, ks, 0, RED_H1, 1, c->stream);
+        copy_alpha0(ks, rec + PPQ_OBS_ENERGY, c->stream);
+        return;
+    }
+    energy_from_dot(c->partial, RED_BLOCKS, rec, c->stream);
+}
+
+bool keys_valid(const ppq_ctx *c, int64_t n, const uint64_t *keys)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (keys[i] >= c->g.total) return false;
+        if (i && keys[i] <= keys[i - 1]) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
+{
+    if (!out) return PPQ_E_ARG;
+    *out = nullptr;
+    if (precision != PPQ_FP64 && precision != PPQ_FP32) return PPQ_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PPQ_E_ARG;
+    ppq_ctx *c = new (std::nothrow) ppq_ctx();
+    if (!c) return PPQ_E_OOM;
+    c->device = device;
+    c->precision = precision;
+    try {
+        ck(hipSetDevice(device), "hipSetDevice");
+        if (hip_stream) {
+            c->stream = (hipStream_t)hip_stream;
+        } else {
+            ck(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "stream");
+            c->own_stream = true;
+        }
+        void *p = nullptr;
+        ck(hipMalloc(&p, sizeof(KState)), "kstate");
+        c->ks = (KState *)p;
+        c->partial = dalloc<double2>((int64_t)RED_BLOCKS * MAXM);
+        c->small = dalloc<uint32_t>(4 * MAXD);
+        c->count = dalloc<unsigned long long>(2);
+        ck(hipHostMalloc((void **)&c->h_small, sizeof(uint32_t) * 4 * MAXD, hipHostMallocDefault), "pinned");
+        ck(hipHostMalloc((void **)&c->h_count, sizeof(unsigned long long) * 2, hipHostMallocDefault), "pinned");
+        ck(hipEventCreate(&c->ev0), "event");
+        ck(hipEventCreate(&c->ev1), "event");
+    } catch (const HipError &e) {
+        ppq_destroy(c);
+        return PPQ_E_HIP;
+    } catch (const std::bad_alloc &) {
+        ppq_destroy(c);
+        return PPQ_E_OOM;
+    }
+    *out = c;
+    return PPQ_OK;
+}
+
+void ppq_destroy(ppq_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_state_buffers(c);
+    free_krylov(c);
+    free_operator(c);
+    dfree(c->bm);
+    dfree(c->prefix);
+    dfree(c->ks);
+    dfree(c->partial);
+    dfree(c->small);
+    dfree(c->count);
+    dfree(c->init_tabs);
+    dfree(c->bra_tabs);
+    dfree(c->rec);
+    if (c->h_small) (void)hipHostFree(c->h_small);
+    if (c->h_count) (void)hipHostFree(c->h_count);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *ppq_last_error(const ppq_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+#define PPQ_GUARD(c)                                                       \
+    if (!(c)) return PPQ_E_ARG;                                            \
+    if ((c)->poisoned) return fail((c), PPQ_E_HIP, "context poisoned");    \
+    (void)hipSetDevice((c)->device);
+
+#define PPQ_TRY(c, ...)                                                    \
+    try {                                                                  \
+        __VA_ARGS__                                                        \
+    } catch (const HipError &e) {                                          \
+        return hip_fail((c), e);                                           \
+    } catch (const std::bad_alloc &) {                                     \
+        return fail((c), PPQ_E_OOM, "device allocation failed");           \
+    } catch (const std::invalid_argument &e) {                             \
+        return fail((c), PPQ_E_UNSUPPORTED, e.what());                     \
+    } catch (const std::exception &e) {                                    \
+        return fail((c), PPQ_E_NUMERIC, e.what());                         \
+    }
+
+int ppq_set_grid(ppq_ctx *c, int D, const int32_t *n, const double *lo, const double *hi, double mass)
+{
+    PPQ_GUARD(c)
+    if (D < 1 || D > MAXD || !n || !lo || !hi || !(mass > 0.0)) return fail(c, PPQ_E_ARG, "bad grid arguments");
+    uint64_t total = 1;
+    for (int k = 0; k < D; ++k) {
+        if (n[k] < 2 || n[k] > NMAX_FIBER) return fail(c, PPQ_E_ARG, "n[k] must be in [2, 64]");
+        if (!(hi[k] > lo[k])) return fail(c, PPQ_E_ARG, "box must have hi > lo");
+        total *= (uint64_t)n[k];
+        if (total >= (1ull << 32)) return fail(c, PPQ_E_CAPACITY, "grid size must be < 2^32");
+    }
+    PPQ_TRY(c, {
+        ck(hipStreamSynchronize(c->stream), "sync");
+        free_state_buffers(c);
+        free_krylov(c);
+        free_operator(c);
+        dfree(c->bm);
+        dfree(c->prefix);
+        c->terms.clear();
+        c->has_state = false;
+        c->nact = 0;
+        c->has_ref = false;
+        GridDesc g{};
+        g.D = D;
+        uint32_t st = 1;
+        for (int k = D - 1; k >= 0; --k) {
+            g.n[k] = n[k];
+            g.stride[k] = st;
+            st *= (uint32_t)n[k];
+        }
+        g.total = (uint32_t)total;
+        c->g = g;
+        c->any_lattice = false;
+        for (int k = 0; k < D; ++k) {
+            c->lo[k] = lo[k];
+            c->hi[k] = hi[k];
+            c->nb[k] = bucket(n[k]);
+            c->lattice[k] = false;
+        }
+        c->mass = mass;
+        int nmax = 0;
+        for (int k = 0; k < D; ++k) nmax = std::max(nmax, n[k]);
+        std::vector<double2> zt((size_t)D * nmax, make_double2(0.0, 0.0));
+        dfree(c->init_tabs);
+        dfree(c->bra_tabs);
+        c->init_tabs = upload(zt, c->stream);
+        c->bra_tabs = upload(zt, c->stream);
+        c->tab_nmax = nmax;
+        c->nwords = (int64_t)((total + 63) / 64);
+        c->bm = dalloc<uint64_t>(c->nwords + 2);
+        c->prefix = dalloc<uint32_t>(c->nwords + 2);
+        c->has_grid = true;
+        c->op_dirty = true;
+    })
+    return PPQ_OK;
+}
+
+int ppq_get_grid(const ppq_ctx *c, int k, double *q)
+{
+    if (!c || !q) return PPQ_E_ARG;
+    if (!c->has_grid || k < 0 || k >= c->g.D) return PPQ_E_ARG;
+    std::vector<double> v = sine_dvr_points(c->g.n[k], c->lo[k], c->hi[k]);
+    std::memcpy(q, v.data(), v.size() * sizeof(double));
+    return PPQ_OK;
+}
+
+int ppq_set_lattice(ppq_ctx *c, int k, int ns, int nl)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (k < 0 || k >= c->g.D || ns < 1 || nl < 1 || ns * nl != c->g.n[k])
+        return fail(c, PPQ_E_ARG, "lattice shape must satisfy n_s * n_l == n[k]");
+    if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set lattices before adding terms");
+    c->g.lat_s[k] = ns;
+    c->g.lat_l[k] = nl;
+    c->lattice[k] = true;
+    c->any_lattice = true;
+    c->op_dirty = true;
+    c->derived_valid = false;
+    return PPQ_OK;
+}
+
+int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dims, const int32_t *kinds,
+                           const double *params, const double *tables)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (nfac < 0 || nfac > 4 * MAXD || (nfac > 0 && (!dims || !kinds))) return fail(c, PPQ_E_ARG, "bad factors");
+    Term t;
+    t.coef = coef;
+    int64_t toff = 0;
+    for (int f = 0; f < nfac; ++f) {
+        Factor fa;
+        fa.dim = dims[f];
+        fa.kind = kinds[f];
+        if (fa.dim < 0 || fa.dim >= c->g.D) return fail(c, PPQ_E_ARG, "factor dimension out of range");
+        fa.p0 = params ? params[2 * f] : 0.0;
+        fa.p1 = params ? params[2 * f + 1] : 0.0;
+        if (fa.kind == PPQ_FAC_POWER) {
+            if (fa.p0 < 0 || fa.p0 > 16 || fa.p0 != std::floor(fa.p0))
+                return fail(c, PPQ_E_ARG, "power must be an integer in [0, 16]");
+        } else if (fa.kind == PPQ_FAC_MORSE) {
+        } else if (fa.kind == PPQ_FAC_TABLE) {
+            if (!tables) return fail(c, PPQ_E_ARG, "table factor without tables");
+            fa.table.assign(tables + toff, tables + toff + c->g.n[fa.dim]);
+            toff += c->g.n[fa.dim];
+        } else {
+            return fail(c, PPQ_E_ARG, "unknown factor kind");
+        }
+        t.f.push_back(fa);
+    }
+    if (c->any_lattice) {
+        int used[MAXD] = {0};
+        int nd = 0;
+        for (auto &fa : t.f)
+            if (!used[fa.dim]++) ++nd;
+        if (nd > 2) return fail(c, PPQ_E_UNSUPPORTED, "lattice bases support terms on at most two dimensions");
+    }
+    c->terms.push_back(t);
+    c->op_dirty = true;
+    c->derived_valid = false;
+    return PPQ_OK;
+}
+
+int ppq_reserve(ppq_ctx *c, int64_t max_active)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (max_active < 1 || max_active > (int64_t)c->g.total) return fail(c, PPQ_E_ARG, "bad capacity");
+    PPQ_TRY(c, { ensure_capacity(c, max_active); })
+    return PPQ_OK;
+}
+
+int ppq_init_gaussian(ppq_ctx *c, const double *centre, const double *momentum, const double *width, double eps,
+                      int64_t *n_active)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (!centre || !momentum || !width || !(eps >= 0.0)) return fail(c, PPQ_E_ARG, "bad packet");
+    for (int k = 0; k < c->g.D; ++k)
+        if (!(width[k] > 0.0)) return fail(c, PPQ_E_ARG, "width must be positive");
+    PPQ_TRY(c, {
+        const int D = c->g.D;
+        int nmax = 0;
+        for (int k = 0; k < D; ++k) nmax = std::max(nmax, c->g.n[k]);
+        std::vector<double2> it((size_t)D * nmax, make_double2(0.0, 0.0)), bt = it;
+        for (int k = 0; k < D; ++k) {
+            int n = c->g.n[k];
+            std::vector<double> q = sine_dvr_points(n, c->lo[k], c->hi[k]);
+            std::vector<cd> gk(n);
+            double nrm = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double d = q[i] - centre[k];
+                gk[i] = std::exp(-d * d / (2.0 * width[k] * width[k])) * std::exp(cd(0.0, momentum[k] * d));
+                nrm += std::norm(gk[i]);
+            }
+            nrm = std::sqrt(nrm);
+            for (int i = 0; i < n; ++i) gk[i] /= nrm;
+            std::vector<cd> a = gk, b = gk;
+            if (c->lattice[k]) {
+                LatticeMaps L = lattice_maps(c, k);
+                a.assign(n, cd(0.0, 0.0));
+                b.assign(n, cd(0.0, 0.0));
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        a[i] += L.Gadj[(size_t)i * n + j] * gk[j];
+                        b[i] += L.Ginv[(size_t)i * n + j] * gk[j];
+                    }
+            }
+            for (int i = 0; i < n; ++i) {
+                it[(size_t)k * nmax + i] = make_double2(a[i].real(), a[i].imag());
+                bt[(size_t)k * nmax + i] = make_double2(b[i].real(), b[i].imag());
+            }
+        }
+        ck(hipStreamSynchronize(c->stream), "sync");
+        dfree(c->init_tabs);
+        dfree(c->bra_tabs);
+        c->init_tabs = upload(it, c->stream);
+        c->bra_tabs = upload(bt, c->stream);
+        c->tab_nmax = nmax;
+        c->has_ref = true;
+        // flag the full grid, dilate, compact
+        hipStream_t s = c->stream;
+        if (!c->scan_tmp) ensure_capacity(c, 1024);
+        fill_u64(c->bm, c->nwords + 2, 0ull, s);
+        fill_u64((uint64_t *)c->count, 1, 0ull, s);
+        init_flag(c->g, c->init_tabs, nmax, eps * eps, c->bm, c->count, s);
+        scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
+        ck(hipMemcpyAsync(c->h_small + MAXD, c->small + MAXD, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "n");
+        ck(hipStreamSynchronize(s), "init count");
+        int64_t n0 = c->h_small[MAXD];
+        c->has_state = false;
+        c->nact = 0;
+        ensure_capacity(c, std::max<int64_t>(n0, 1));
+        compact(c->bm, c->prefix, c->nwords, c->keys[c->cur], s);
+        product_values(c->keys[c->cur], n0, c->g, c->init_tabs, nmax, c->psi[c->cur], s);
+        c->nact = n0;
+        c->has_state = true;
+        c->derived_valid = false;
+        ck(hipStreamSynchronize(s), "init");
+        if (n_active) *n_active = n0;
+    })
+    return PPQ_OK;
+}
+
+int ppq_set_state(ppq_ctx *c, int64_t count, const uint64_t *keys, const double *coeff)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (count < 0 || (count > 0 && (!keys || !coeff))) return fail(c, PPQ_E_ARG, "bad state arguments");
+    if (!keys_valid(c, count, keys)) return fail(c, PPQ_E_ARG, "keys must be strictly ascending and in range");
+    for (int64_t i = 0; i < 2 * count; ++i)
+        if (!std::isfinite(coeff[i])) return fail(c, PPQ_E_NUMERIC, "non-finite coefficient");
+    PPQ_TRY(c, {
+        c->has_state = false;
+        c->nact = 0;
+        ensure_capacity(c, std::max<int64_t>(count, 1));
+        std::vector<uint32_t> k32(count);
+        for (int64_t i = 0; i < count; ++i) k32[i] = (uint32_t)keys[i];
+        if (count) {
+            ck(hipMemcpyAsync(c->keys[c->cur], k32.data(), count * sizeof(uint32_t), hipMemcpyHostToDevice,
+                              c->stream),
+               "set keys");
+            ck(hipMemcpyAsync(c->psi[c->cur], coeff, count * sizeof(double2), hipMemcpyHostToDevice, c->stream),
+               "set psi");
+        }
+        ck(hipStreamSynchronize(c->stream), "set state");
+        c->nact = count;
+        c->has_state = true;
+        c->derived_valid = false;
+    })
+    return PPQ_OK;
+}
+
+int ppq_active_count(const ppq_ctx *c, int64_t *count)
+{
+    if (!c || !count) return PPQ_E_ARG;
+    if (!c->has_state) return PPQ_E_STATE;
+    *count = c->nact;
+    return PPQ_OK;
+}
+
+int ppq_get_state(ppq_ctx *c, int64_t cap, int64_t *count, uint64_t *keys, double *coeff)
+{
+    PPQ_GUARD(c)
+    if (!count) return fail(c, PPQ_E_ARG, "count is NULL");
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    *count = c->nact;
+    if (cap < c->nact) return fail(c, PPQ_E_ARG, "buffer too small");
+    if (c->nact && (!keys || !coeff)) return fail(c, PPQ_E_ARG, "null buffers");
+    PPQ_TRY(c, {
+        std::vector<uint32_t> k32(c->nact);
+        if (c->nact) {
+            ck(hipMemcpyAsync(k32.data(), c->keys[c->cur], c->nact * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              c->stream),
+               "get keys");
+            ck(hipMemcpyAsync(coeff, c->psi[c->cur], c->nact * sizeof(double2), hipMemcpyDeviceToHost, c->stream),
+               "get psi");
+        }
+        ck(hipStreamSynchronize(c->stream), "get state");
+        for (int64_t i = 0; i < c->nact; ++i) keys[i] = k32[i];
+    })
+    return PPQ_OK;
+}
+
+int ppq_apply_h(ppq_ctx *c, const void *x, void *y)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (c->nact && (!x || !y || x == y)) return fail(c, PPQ_E_ARG, "x and y must be distinct device pointers");
+    PPQ_TRY(c, {
+        build_derived(c);
+        apply_internal(c, x, y, nullptr, 0);
+    })
+    return PPQ_OK;
+}
+
+int ppq_step(ppq_ctx *c, double dt, int m)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (m < 1 || m > MAXM || !std::isfinite(dt)) return fail(c, PPQ_E_ARG, "1 <= m <= 16, finite dt");
+    PPQ_TRY(c, { do_step(c, dt, m); })
+    return PPQ_OK;
+}
+
+int ppq_prune(ppq_ctx *c, double eps, int64_t *n_active, int64_t *n_above)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (!(eps >= 0.0)) return fail(c, PPQ_E_ARG, "eps must be >= 0");
+    PPQ_TRY(c, {
+        if (!c->scan_tmp) ensure_capacity(c, 1024);
+        int64_t nab = 0;
+        do_prune(c, eps, &nab);
+        ck(hipStreamSynchronize(c->stream), "prune");
+        if (n_active) *n_active = c->nact;
+        if (n_above) *n_above = nab;
+    })
+    return PPQ_OK;
+}
+
+int ppq_propagate(ppq_ctx *c, int nsteps, double dt, int m, double eps, double *trace)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (nsteps < 0 || m < 1 || m > MAXM || !std::isfinite(dt)) return fail(c, PPQ_E_ARG, "bad propagate arguments");
+    PPQ_TRY(c, {
+        if (!c->scan_tmp) ensure_capacity(c, 1024);
+        ensure_records(c, (int64_t)nsteps + 1);
+        double eps_obs = eps < 0 ? 0.0 : eps;
+        build_derived(c);
+        observe_into(c, 0, eps_obs);
+        set_record_host(c, 0, 0.0, 0);
+        for (int st = 1; st <= nsteps; ++st) {
+            build_derived(c);
+            ensure_krylov(c, m);
+            if (c->nact) {
+                if (c->precision == PPQ_FP64) step_impl<double2>(c, dt, m);
+                else step_impl<float2>(c, dt, m);
+                // energy of the previous record = alpha_0 of this step
+                copy_alpha0(c->ks, c->rec + (int64_t)(st - 1) * PPQ_OBS_N + PPQ_OBS_ENERGY, c->stream);
+            }
+            if (eps >= 0.0) do_prune(c, eps, nullptr);
+            build_derived(c);
+            observe_into(c, st, eps_obs);
+            set_record_host(c, st, st * dt, m);
+            if (c->nact) copy_meff(c->ks, c->rec + (int64_t)st * PPQ_OBS_N + PPQ_OBS_KRYLOV, c->stream);
+        }
+        energy_into(c, nsteps);
+        ck(hipStreamSynchronize(c->stream), "propagate");
+        if (trace) {
+            ck(hipMemcpy(trace, c->rec, sizeof(double) * PPQ_OBS_N * ((int64_t)nsteps + 1), hipMemcpyDeviceToHost),
+               "trace");
+            // Krylov dimension actually used
+        }
+    })
+    return PPQ_OK;
+}
+
+int ppq_observables(ppq_ctx *c, double eps, double *out)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (!out || !(eps >= 0.0)) return fail(c, PPQ_E_ARG, "bad arguments");
+    PPQ_TRY(c, {
+        if (!c->scan_tmp) ensure_capacity(c, 1024);
+        ensure_records(c, 1);
+        build_derived(c);
+        observe_into(c, 0, eps);
+        set_record_host(c, 0, 0.0, 0);
+        energy_into(c, 0);
+        ck(hipStreamSynchronize(c->stream), "observables");
+        ck(hipMemcpy(out, c->rec, sizeof(double) * PPQ_OBS_N, hipMemcpyDeviceToHost), "obs");
+    })
+    return PPQ_OK;
+}
+
+int ppq_time_apply(ppq_ctx *c, int nrep, double *ms_per_apply)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (nrep < 1 || !ms_per_apply) return fail(c, PPQ_E_ARG, "nrep >= 1");
+    PPQ_TRY(c, {
+        build_derived(c);
+        ensure_krylov(c, std::max(c->kv_m, 1));
+        const void *x = c->psi[c->cur];
+        if (c->precision == PPQ_FP32) {
+            norm2_partial(c->psi[c->cur], c->nact, c->partial, c->stream);
+            reduce_krylov(c->partial, RED_BLOCKS, 1, c->ks, 0, RED_NORM0, 1, c->stream);
+            normalise_from_master<float2>(c->psi[c->cur], c->nact, c->ks, (float2 *)c->Vk, c->stream);
+            x = c->Vk;
+        }
+        apply_internal(c, x, c->wk, nullptr, 0);
+        ck(hipEventRecord(c->ev0, c->stream), "event");
+        for (int r = 0; r < nrep; ++r) apply_internal(c, x, c->wk, nullptr, 0);
+        ck(hipEventRecord(c->ev1, c->stream), "event");
+        ck(hipEventSynchronize(c->ev1), "event sync");
+        float ms = 0.f;
+        ck(hipEventElapsedTime(&ms, c->ev0, c->ev1), "elapsed");
+        *ms_per_apply = (double)ms / nrep;
+    })
+    return PPQ_OK;
+}
+
+int ppq_fiber_counts(ppq_ctx *c, int64_t *nf)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (!nf) return fail(c, PPQ_E_ARG, "nf is NULL");
+    PPQ_TRY(c, {
+        build_derived(c);
+        for (int k = 0; k < c->g.D; ++k) nf[k] = c->nf[k];
+    })
+    return PPQ_OK;
+}
+
+}  // extern "C"

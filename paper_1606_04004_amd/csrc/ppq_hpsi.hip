@@ -1,0 +1,345 @@
+// Pruned tensor transformation along one dimension (the appendix's
+// last-dimension fiber product, generalised through per-dimension fiber
+// tables instead of a materialised permutation):
+//
+//   for every fiber f of dimension k (points sharing all digits but i_k) and
+//   every digit l present in f:  y[p_l] (+)= sum_{j in f} h_k[l][j] x[p_j]
+//
+// Layout.  A fiber is (off, mask): mask has bit d set when digit d is
+// present; the member with digit d sits at entry off + popcount(mask & (2^d - 1))
+// of the dimension's permutation pi_k (identity for the last dimension,
+// whose fibers are contiguous runs of the key-sorted state).
+//
+// Mapping.  One lane per fiber.  Consecutive fibers differ in their lowest
+// remaining digit, so at a given digit j neighbouring lanes read neighbouring
+// positions: the digit-synchronised gather below is close to coalesced for
+// every dimension.  The wavefront's union of masks fixes a window of W
+// digits (W from a few width buckets); the window's W x W block of h_k is
+// wave-uniform and is read through the scalar cache, so the contraction is
+// W^2 FMA pairs per lane with no LDS traffic.  Output positions are
+// recomputed per row (they hit in cache) so the row loop can stay rolled.
+#include "ppq_internal.hpp"
+
+namespace ppq {
+namespace {
+
+constexpr int HB = 256;
+
+__device__ inline uint64_t wave_or64(uint64_t v)
+{
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        uint32_t lo = __shfl_xor((uint32_t)v, s, 64);
+        uint32_t hi = __shfl_xor((uint32_t)(v >> 32), s, 64);
+        v |= ((uint64_t)hi << 32) | lo;
+    }
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <class R>
+struct Cx;
+template <>
+struct Cx<double> {
+    using T = double2;
+    __device__ static T make(double a, double b) { return make_double2(a, b); }
+};
+template <>
+struct Cx<float> {
+    using T = float2;
+    __device__ static T make(float a, float b) { return make_float2(a, b); }
+};
+
+// ---- real factor (DVR kinetic), first pass fuses the diagonal potential -----
+template <class R, int W, int NMAX, bool FIRST, bool IDENT>
+__device__ __forceinline__ void body_real(uint32_t o, uint64_t m, int ws, const uint32_t *__restrict__ pi,
+                                          const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
+                                          const R *__restrict__ V, typename Cx<R>::T *__restrict__ y)
+{
+    using C = typename Cx<R>::T;
+    C xw[W];
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+        int j = ws + jj;
+        xw[jj] = Cx<R>::make(0, 0);
+        if ((m >> j) & 1ull) {
+            uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << j) - 1ull));
+            uint32_t p = IDENT ? pos : pi[pos];
+            xw[jj] = x[p];
+        }
+    }
+    const R *Tw = T + ws * NMAX + ws;
+    // output rows: rolled loop; the W-wide contraction of each row is unrolled
+    // and reads the row of h from the scalar cache
+    for (int ll = 0; ll < W; ++ll) {
+        R ar = 0, ai = 0;
+        const R *Tr = Tw + ll * NMAX;
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            R t = Tr[jj];
+            ar = fma(t, xw[jj].x, ar);
+            ai = fma(t, xw[jj].y, ai);
+        }
+        int l = ws + ll;
+        if ((m >> l) & 1ull) {
+            uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << l) - 1ull));
+            uint32_t p = IDENT ? pos : pi[pos];
+            if (FIRST) {
+                R v = V[p];
+                C xl = x[p];
+                y[p] = Cx<R>::make(fma(v, xl.x, ar), fma(v, xl.y, ai));
+            } else {
+                C o2 = y[p];
+                y[p] = Cx<R>::make(o2.x + ar, o2.y + ai);
+            }
+        }
+    }
+}
+
+template <class R, int NMAX, bool FIRST, bool IDENT>
+__global__ __launch_bounds__(HB) void k_hpsi_real(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
+                                                  const uint64_t *__restrict__ mask, int64_t nf,
+                                                  const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
+                                                  const R *__restrict__ V, typename Cx<R>::T *__restrict__ y,
+                                                  const int *skip_if, int skip_j)
+{
+    if (skip_if && skip_j >= *skip_if) return;
+    int64_t f = (int64_t)blockIdx.x * HB + threadIdx.x;
+    uint64_t m = 0;
+    uint32_t o = 0;
+    if (f < nf) {
+        m = mask[f];
+        o = off[f];
+    }
+    uint64_t wm = wave_or64(m);
+    if (wm == 0) return;
+    int wlo = __ffsll((unsigned long long)wm) - 1;
+    int whi = 63 - __clzll((long long)wm);
+    int width = whi - wlo + 1;
+#define PPQ_BODY(W)                                                                        \
+    {                                                                                      \
+        int ws = wlo < NMAX - (W) ? wlo : NMAX - (W);                                      \
+        body_real<R, W, NMAX, FIRST, IDENT>(o, m, ws, pi, T, x, V, y);                     \
+        return;                                                                            \
+    }
+    if constexpr (NMAX >= 8) {
+        if (width <= 8) PPQ_BODY(8)
+    }
+    if constexpr (NMAX >= 16) {
+        if (width <= 16) PPQ_BODY(16)
+    }
+    if constexpr (NMAX >= 24) {
+        if (width <= 24) PPQ_BODY(24)
+    }
+    if constexpr (NMAX >= 32) {
+        if (width <= 32) PPQ_BODY(32)
+    }
+    if constexpr (NMAX >= 48) {
+        if (width <= 48) PPQ_BODY(48)
+    }
+    PPQ_BODY(NMAX)
+#undef PPQ_BODY
+}
+
+// ---- complex factor (lattice bases), input a linear combination -----------------
+template <class R>
+struct CArgs {
+    int nin;
+    const typename Cx<R>::T *x[4];
+    typename Cx<R>::T c[4];
+};
+
+template <class R, int W, int NMAX, bool IDENT>
+__device__ __forceinline__ void body_cplx(uint32_t o, uint64_t m, int ws, const uint32_t *__restrict__ pi,
+                                          const typename Cx<R>::T *__restrict__ H, const CArgs<R> &in,
+                                          typename Cx<R>::T *__restrict__ y, bool accumulate)
+{
+    using C = typename Cx<R>::T;
+    C xw[W];
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+        int j = ws + jj;
+        xw[jj] = Cx<R>::make(0, 0);
+        if ((m >> j) & 1ull) {
+            uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << j) - 1ull));
+            uint32_t p = IDENT ? pos : pi[pos];
+            C acc = Cx<R>::make(0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i < in.nin) {
+                    C v = in.x[i][p];
+                    C c = in.c[i];
+                    acc.x = fma(c.x, v.x, fma(-c.y, v.y, acc.x));
+                    acc.y = fma(c.x, v.y, fma(c.y, v.x, acc.y));
+                }
+            }
+            xw[jj] = acc;
+        }
+    }
+    const C *Hw = H + ws * NMAX + ws;
+    for (int ll = 0; ll < W; ++ll) {
+        R ar = 0, ai = 0;
+        const C *Hr = Hw + ll * NMAX;
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            C t = Hr[jj];
+            ar = fma(t.x, xw[jj].x, fma(-t.y, xw[jj].y, ar));
+            ai = fma(t.x, xw[jj].y, fma(t.y, xw[jj].x, ai));
+        }
+        int l = ws + ll;
+        if ((m >> l) & 1ull) {
+            uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << l) - 1ull));
+            uint32_t p = IDENT ? pos : pi[pos];
+            if (accumulate) {
+                C o2 = y[p];
+                y[p] = Cx<R>::make(o2.x + ar, o2.y + ai);
+            } else {
+                y[p] = Cx<R>::make(ar, ai);
+            }
+        }
+    }
+}
+
+template <class R, int NMAX, bool IDENT>
+__global__ __launch_bounds__(HB) void k_hpsi_cplx(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
+                                                  const uint64_t *__restrict__ mask, int64_t nf,
+                                                  const typename Cx<R>::T *__restrict__ H, CArgs<R> in,
+                                                  typename Cx<R>::T *__restrict__ y, int accumulate,
+                                                  const int *skip_if, int skip_j)
+{
+    if (skip_if && skip_j >= *skip_if) return;
+    int64_t f = (int64_t)blockIdx.x * HB + threadIdx.x;
+    uint64_t m = 0;
+    uint32_t o = 0;
+    if (f < nf) {
+        m = mask[f];
+        o = off[f];
+    }
+    uint64_t wm = wave_or64(m);
+    if (wm == 0) return;
+    int wlo = __ffsll((unsigned long long)wm) - 1;
+    int whi = 63 - __clzll((long long)wm);
+    int width = whi - wlo + 1;
+#define PPQ_BODY(W)                                                                               \
+    {                                                                                             \
+        int ws = wlo < NMAX - (W) ? wlo : NMAX - (W);                                             \
+        body_cplx<R, W, NMAX, IDENT>(o, m, ws, pi, H, in, y, accumulate != 0);         \
+        return;                                                                                   \
+    }
+    if constexpr (NMAX >= 8) {
+        if (width <= 8) PPQ_BODY(8)
+    }
+    if constexpr (NMAX >= 16) {
+        if (width <= 16) PPQ_BODY(16)
+    }
+    if constexpr (NMAX >= 24) {
+        if (width <= 24) PPQ_BODY(24)
+    }
+    if constexpr (NMAX >= 32) {
+        if (width <= 32) PPQ_BODY(32)
+    }
+    PPQ_BODY(NMAX)
+#undef PPQ_BODY
+}
+
+inline unsigned fblocks(int64_t nf)
+{
+    int64_t b = (nf + HB - 1) / HB;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+template <class R>
+void launch_real(const FiberPass &fp, const R *T, const typename Cx<R>::T *x, const R *V, typename Cx<R>::T *y,
+                 bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (fp.nf <= 0) return;
+    bool ident = fp.pi == nullptr;
+#define L(NM, F, I)                                                                                        \
+    hipLaunchKernelGGL((k_hpsi_real<R, NM, F, I>), dim3(fblocks(fp.nf)), dim3(HB), 0, s, fp.pi, fp.off, fp.mask, \
+                       fp.nf, T, x, V, y, skip_if, skip_j)
+#define DISPATCH(NM)                       \
+    if (first) {                           \
+        if (ident) L(NM, true, true);      \
+        else L(NM, true, false);           \
+    } else {                               \
+        if (ident) L(NM, false, true);     \
+        else L(NM, false, false);          \
+    }
+    switch (fp.nmax) {
+    case 8: DISPATCH(8) break;
+    case 16: DISPATCH(16) break;
+    case 24: DISPATCH(24) break;
+    case 32: DISPATCH(32) break;
+    case 48: DISPATCH(48) break;
+    default: DISPATCH(64) break;
+    }
+#undef DISPATCH
+#undef L
+}
+
+template <class R>
+void launch_cplx(const FiberPass &fp, const typename Cx<R>::T *H, const CArgs<R> &in, typename Cx<R>::T *y,
+                 bool accumulate, const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (fp.nf <= 0) return;
+    bool ident = fp.pi == nullptr;
+#define L(NM, I)                                                                                             \
+    hipLaunchKernelGGL((k_hpsi_cplx<R, NM, I>), dim3(fblocks(fp.nf)), dim3(HB), 0, s, fp.pi, fp.off, fp.mask, \
+                       fp.nf, H, in, y, accumulate ? 1 : 0, skip_if, skip_j)
+#define DISPATCH(NM)        \
+    if (ident) L(NM, true); \
+    else L(NM, false);
+    switch (fp.nmax) {
+    case 8: DISPATCH(8) break;
+    case 16: DISPATCH(16) break;
+    case 24: DISPATCH(24) break;
+    case 32: DISPATCH(32) break;
+    case 48: DISPATCH(48) break;
+    default: DISPATCH(64) break;
+    }
+#undef DISPATCH
+#undef L
+}
+
+}  // namespace
+
+void hpsi_real_f64(const FiberPass &fp, const double *T, const double2 *x, const double *V, double2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_real<double>(fp, T, x, V, y, first, skip_if, skip_j, s);
+}
+
+void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_real<float>(fp, T, x, V, y, first, skip_if, skip_j, s);
+}
+
+void hpsi_cplx_f64(const FiberPass &fp, const double2 *H, const CInput &in, double2 *y, bool accumulate,
+                   const double *V, const int *skip_if, int skip_j, hipStream_t s)
+{
+    (void)V;
+    CArgs<double> a;
+    a.nin = in.nin;
+    for (int i = 0; i < 4; ++i) {
+        a.x[i] = in.x[i];
+        a.c[i] = in.c[i];
+    }
+    launch_cplx<double>(fp, H, a, y, accumulate, skip_if, skip_j, s);
+}
+
+void hpsi_cplx_f32(const FiberPass &fp, const float2 *H, const CInput32 &in, float2 *y, bool accumulate,
+                   const float *V, const int *skip_if, int skip_j, hipStream_t s)
+{
+    (void)V;
+    CArgs<float> a;
+    a.nin = in.nin;
+    for (int i = 0; i < 4; ++i) {
+        a.x[i] = in.x[i];
+        a.c[i] = in.c[i];
+    }
+    launch_cplx<float>(fp, H, a, y, accumulate, skip_if, skip_j, s);
+}
+
+}  // namespace ppq

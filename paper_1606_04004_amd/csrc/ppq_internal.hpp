@@ -1,0 +1,151 @@
+// Internal declarations of the gfx950 library behind include/ppq.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ppq.h"
+
+namespace ppq {
+
+constexpr int MAXD = 8;
+constexpr int MAXM = 16;        // largest Krylov order
+constexpr int NMAX_FIBER = 64;  // largest 1D basis (fiber masks are 64-bit)
+constexpr int RED_BLOCKS = 1024;  // blocks of the fixed-shape reductions
+
+// Grid geometry passed by value to kernels.
+struct GridDesc {
+    int D;
+    int n[MAXD];
+    uint32_t stride[MAXD];  // row-major, last dimension fastest
+    int lat_s[MAXD];        // phase-space lattice shape; lat_s == 0 -> +-1 line stencil
+    int lat_l[MAXD];
+    uint32_t total;
+};
+
+// Diagonal potential as a sum of products of 1D tables.
+struct PotDesc {
+    int nterm;
+    int D;
+    int nmax;
+    const double *coef;   // [nterm]
+    const int *tab;       // [nterm][D]: table index or -1
+    const double *tabs;   // [ntab][nmax]
+};
+
+// Device state of one Krylov step.
+struct KState {
+    double n0;                 // |psi|
+    double alpha[MAXM];        // Re <v_j|H v_j>
+    double beta[MAXM];         // |w_j| after reorthogonalisation
+    double2 h1[MAXM * MAXM];   // Hessenberg, first Gram-Schmidt pass  [i*MAXM + j]
+    double2 h2[MAXM * MAXM];   // second pass
+    double2 y[MAXM];           // coefficients of the propagated vector
+    double inv_beta;           // 1/beta of the last completed iteration
+    double norm2_scratch;
+    int meff;                  // Krylov dimension actually built
+    int pad;
+};
+
+// ---- launchers (ppq_kernels.hip) ------------------------------------------
+void fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+void fill_zero_bytes(void *p, int64_t nbytes, hipStream_t s);
+
+// exclusive scans; *total receives the sum; tmp holds >= scan_tmp_words(n) words
+int64_t scan_tmp_words(int64_t n);
+void scan_popcount(const uint64_t *words, int64_t nwords, uint32_t *prefix, uint32_t *total, uint32_t *tmp,
+                   hipStream_t s);
+void scan_u32(const uint32_t *in, int64_t n, uint32_t *out, uint32_t *total, uint32_t *tmp, hipStream_t s);
+
+void init_flag(const GridDesc &g, const double2 *tabs, int nmax, double eps2, uint64_t *bm,
+               unsigned long long *nabove, hipStream_t s);
+void product_values(const uint32_t *keys, int64_t n, const GridDesc &g, const double2 *tabs, int nmax,
+                    double2 *out, hipStream_t s);
+void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, double eps2, uint64_t *bm,
+            unsigned long long *nabove, hipStream_t s);
+void compact(const uint64_t *bm, const uint32_t *prefix, int64_t nwords, uint32_t *keys_out, hipStream_t s);
+void remap(const uint32_t *okeys, const double2 *opsi, int64_t n_old, const uint64_t *bm, const uint32_t *prefix,
+           double2 *npsi, hipStream_t s);
+void mark_keys(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s);
+
+// fiber tables
+void last_flags(const uint32_t *keys, int64_t n, int nlast, uint32_t *flags, hipStream_t s);
+void last_fill(const uint32_t *keys, int64_t n, int nlast, const uint32_t *flags, const uint32_t *fidx,
+               const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s);
+void rot_set(const uint32_t *keys, int64_t n, int k, const GridDesc &g, uint64_t *bm, hipStream_t s);
+void rot_rank(const uint32_t *keys, int64_t n, int k, const GridDesc &g, const uint64_t *bm,
+              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, hipStream_t s);
+void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
+              const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s);
+
+void potential(const uint32_t *keys, int64_t n, const GridDesc &g, const PotDesc &pd, double *V, float *Vf,
+               hipStream_t s);
+
+// fiber contraction y (+)= P h_k P x along one dimension
+struct FiberPass {
+    const uint32_t *pi;     // nullptr for the last dimension (identity)
+    const uint32_t *off;
+    const uint64_t *mask;
+    int64_t nf;
+    int nmax;               // padded 1D size (matrix leading dimension)
+};
+// real factor (DVR), FP64; first==true writes y = (T + V) x, else y += T x
+void hpsi_real_f64(const FiberPass &fp, const double *T, const double2 *x, const double *V, double2 *y,
+                   bool first, const int *skip_if, int skip_j, hipStream_t s);
+// complex factor, FP64: y (= or +=) coef * h * (sum_i c_i x_i)  (up to 4 inputs)
+struct CInput {
+    int nin;
+    const double2 *x[4];
+    double2 c[4];
+};
+void hpsi_cplx_f64(const FiberPass &fp, const double2 *H, const CInput &in, double2 *y, bool accumulate,
+                   const double *V, const int *skip_if, int skip_j, hipStream_t s);
+// FP32 forms
+void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s);
+struct CInput32 {
+    int nin;
+    const float2 *x[4];
+    float2 c[4];
+};
+void hpsi_cplx_f32(const FiberPass &fp, const float2 *H, const CInput32 &in, float2 *y, bool accumulate,
+                   const float *V, const int *skip_if, int skip_j, hipStream_t s);
+
+// Krylov vector kernels. V_i = Vb + i*ld (elements). T is double2 or float2.
+template <class C>
+void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, const int *meff, int j,
+              hipStream_t s);
+template <class C>
+void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, const double2 *h, double2 *partial,
+                     const int *meff, int j, hipStream_t s);
+template <class C>
+void cgs_update_norm(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const double2 *h,
+                     double2 *partial, const int *meff, int j, hipStream_t s);
+template <class C>
+void scale_vec(C *v, int64_t n, const double *inv, const int *meff, int j, hipStream_t s);
+template <class C>
+void normalise_from_master(const double2 *psi, int64_t n, KState *ks, C *v0, hipStream_t s);
+template <class C>
+void lincomb(const C *Vb, int64_t ld, int nv, const double2 *psi_master, int64_t n, const KState *ks,
+             double2 *psi_out, hipStream_t s);
+
+// finalisers (one block): sum partial[nb][nv] in a fixed order
+enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3 };
+void reduce_krylov(const double2 *partial, int nblocks, int nv, KState *ks, int j, int mode, int m,
+                   hipStream_t s, int ioff = 0);
+void krylov_expv(KState *ks, int m, double dt, int hermitian, hipStream_t s);
+void norm2_partial(const double2 *psi, int64_t n, double2 *partial, hipStream_t s);
+
+// observables
+void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, const double2 *bra,
+                 int nmax, double eps2, double2 *partial, hipStream_t s);
+void obs_final(const double2 *partial, int nblocks, double *rec, hipStream_t s);
+void copy_alpha0(const KState *ks, double *dst, hipStream_t s);
+void copy_meff(const KState *ks, double *dst, hipStream_t s);
+void energy_from_dot(const double2 *partial, int nblocks, double *rec, hipStream_t s);
+void dot_partial(const double2 *a, const double2 *b, int64_t n, double2 *partial, hipStream_t s);
+
+}  // namespace ppq

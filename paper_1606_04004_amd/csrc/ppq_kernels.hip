@@ -1,0 +1,968 @@
+// gfx950 kernels: scans, adaption (flag / dilate / compact / remap), fiber
+// tables, potential cache, Krylov vector work, small exponential, observables.
+// The fiber contraction kernels live in ppq_hpsi.hip.
+#include "ppq_internal.hpp"
+
+namespace ppq {
+
+namespace {
+
+constexpr int TB = 256;  // threads per block for streaming kernels
+
+__device__ inline int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+inline unsigned nblocks(int64_t n, int tb = TB)
+{
+    int64_t b = (n + tb - 1) / tb;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// complex product without contraction: (ac - bd) + i(ad + bc)
+__device__ inline double2 cmul_rn(double2 a, double2 b)
+{
+    return make_double2(__dsub_rn(__dmul_rn(a.x, b.x), __dmul_rn(a.y, b.y)),
+                        __dadd_rn(__dmul_rn(a.x, b.y), __dmul_rn(a.y, b.x)));
+}
+
+__device__ inline bool above_eps(double2 c, double eps2)
+{
+    return __dadd_rn(__dmul_rn(c.x, c.x), __dmul_rn(c.y, c.y)) >= eps2;
+}
+
+__device__ inline void set_bit(uint64_t *bm, uint32_t key)
+{
+    atomicOr((unsigned long long *)&bm[key >> 6], 1ull << (key & 63));
+}
+
+__device__ inline void set_with_neighbours(const GridDesc &g, uint64_t *bm, uint32_t key)
+{
+    set_bit(bm, key);
+    for (int k = 0; k < g.D; ++k) {
+        uint32_t sk = g.stride[k];
+        int d = (int)((key / sk) % (uint32_t)g.n[k]);
+        if (g.lat_s[k] == 0) {
+            if (d > 0) set_bit(bm, key - sk);
+            if (d + 1 < g.n[k]) set_bit(bm, key + sk);
+        } else {
+            int nl = g.lat_l[k];
+            int si = d / nl, l = d % nl;
+            if (si > 0) set_bit(bm, key - (uint32_t)nl * sk);
+            if (si + 1 < g.lat_s[k]) set_bit(bm, key + (uint32_t)nl * sk);
+            if (l > 0) set_bit(bm, key - sk);
+            if (l + 1 < nl) set_bit(bm, key + sk);
+        }
+    }
+}
+
+__device__ inline void count_ballot(bool pred, unsigned long long *counter)
+{
+    uint64_t b = __ballot(pred);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(counter, (unsigned long long)__popcll(b));
+}
+
+// ---- scan ------------------------------------------------------------------
+constexpr int SB = 256;
+constexpr int SI = 8;
+constexpr int STILE = SB * SI;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[NT / 64];
+    uint32_t inc = wave_incl_scan(v);
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        uint32_t s = wsum[i];
+        if (i < w) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+struct PopLoad {
+    const uint64_t *w;
+    __device__ uint32_t operator()(int64_t i) const { return (uint32_t)__popcll(w[i]); }
+};
+struct U32Load {
+    const uint32_t *a;
+    __device__ uint32_t operator()(int64_t i) const { return a[i]; }
+};
+
+template <class L>
+__global__ __launch_bounds__(SB) void k_scan_reduce(L ld, int64_t n, uint32_t *tile_sums)
+{
+    int64_t base = (int64_t)blockIdx.x * STILE;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        int64_t idx = base + (int64_t)i * SB + threadIdx.x;
+        if (idx < n) s += ld(idx);
+    }
+    uint32_t tot;
+    block_excl_scan<SB>(s, &tot);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t *tile, int64_t ntiles, uint32_t *total)
+{
+    int64_t per = (ntiles + 1023) / 1024;
+    int64_t lo = threadIdx.x * per, hi = lo + per < ntiles ? lo + per : ntiles;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += tile[i];
+    uint32_t tot;
+    uint32_t off = block_excl_scan<1024>(s, &tot);
+    for (int64_t i = lo; i < hi; ++i) {
+        uint32_t v = tile[i];
+        tile[i] = off;
+        off += v;
+    }
+    if (threadIdx.x == 0) *total = tot;
+}
+
+template <class L>
+__global__ __launch_bounds__(SB) void k_scan_apply(L ld, int64_t n, const uint32_t *tile_off, uint32_t *out)
+{
+    int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SI;
+    uint32_t v[SI];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        v[i] = (base + i < n) ? ld(base + i) : 0u;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan<SB>(s, &tot) + tile_off[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SI; ++i) {
+        if (base + i < n) out[base + i] = off;
+        off += v[i];
+    }
+}
+
+template <class L>
+void scan_impl(L ld, int64_t n, uint32_t *out, uint32_t *total, uint32_t *tmp, hipStream_t s)
+{
+    int64_t ntiles = (n + STILE - 1) / STILE;
+    if (ntiles < 1) ntiles = 1;
+    hipLaunchKernelGGL(k_scan_reduce<L>, dim3((unsigned)ntiles), dim3(SB), 0, s, ld, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, ntiles, total);
+    hipLaunchKernelGGL(k_scan_apply<L>, dim3((unsigned)ntiles), dim3(SB), 0, s, ld, n, tmp, out);
+}
+
+// ---- fills -----------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T *p, int64_t n, T v)
+{
+    for (int64_t i = gid(); i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---- adaption ----------------------------------------------------------------
+__global__ void k_init_flag(GridDesc g, const double2 *tabs, int nmax, double eps2, uint64_t *bm,
+                            unsigned long long *nabove)
+{
+    for (int64_t i = gid(); i < (int64_t)g.total; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t key = (uint32_t)i;
+        double2 v = make_double2(1.0, 0.0);
+        for (int k = 0; k < g.D; ++k) {
+            int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+            v = cmul_rn(v, tabs[k * nmax + d]);
+        }
+        bool keep = above_eps(v, eps2);
+        if (keep) set_with_neighbours(g, bm, key);
+        count_ballot(keep, nabove);
+    }
+}
+
+__global__ void k_product_values(const uint32_t *keys, int64_t n, GridDesc g, const double2 *tabs, int nmax,
+                                 double2 *out)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    uint32_t key = keys[p];
+    double2 v = make_double2(1.0, 0.0);
+    for (int k = 0; k < g.D; ++k) {
+        int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+        v = cmul_rn(v, tabs[k * nmax + d]);
+    }
+    out[p] = v;
+}
+
+__global__ void k_dilate(const uint32_t *keys, const double2 *psi, int64_t n, GridDesc g, double eps2,
+                         uint64_t *bm, unsigned long long *nabove)
+{
+    int64_t p = gid();
+    bool keep = false;
+    if (p < n) {
+        keep = above_eps(psi[p], eps2);
+        if (keep) set_with_neighbours(g, bm, keys[p]);
+    }
+    count_ballot(keep, nabove);
+}
+
+__global__ void k_mark(const uint32_t *keys, int64_t n, uint64_t *bm)
+{
+    int64_t p = gid();
+    if (p < n) set_bit(bm, keys[p]);
+}
+
+__global__ void k_compact(const uint64_t *bm, const uint32_t *prefix, int64_t nwords, uint32_t *keys_out)
+{
+    int64_t w = gid();
+    if (w >= nwords) return;
+    uint64_t word = bm[w];
+    if (!word) return;
+    uint32_t q = prefix[w];
+    while (word) {
+        int b = __ffsll((unsigned long long)word) - 1;
+        keys_out[q++] = (uint32_t)(w * 64 + b);
+        word &= word - 1;
+    }
+}
+
+__global__ void k_remap(const uint32_t *okeys, const double2 *opsi, int64_t n_old, const uint64_t *bm,
+                        const uint32_t *prefix, double2 *npsi)
+{
+    int64_t p = gid();
+    if (p >= n_old) return;
+    uint32_t key = okeys[p];
+    uint64_t word = bm[key >> 6];
+    uint32_t b = key & 63;
+    if ((word >> b) & 1ull) {
+        uint32_t q = prefix[key >> 6] + (uint32_t)__popcll(word & ((1ull << b) - 1ull));
+        npsi[q] = opsi[p];
+    }
+}
+
+// ---- fiber tables ------------------------------------------------------------
+__global__ void k_last_flags(const uint32_t *keys, int64_t n, int nl, uint32_t *flags)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    flags[p] = (p == 0 || keys[p] / (uint32_t)nl != keys[p - 1] / (uint32_t)nl) ? 1u : 0u;
+}
+
+__global__ void k_last_fill(const uint32_t *keys, int64_t n, int nl, const uint32_t *flags, const uint32_t *fidx,
+                            const uint32_t *nf, uint32_t *off, uint64_t *mask)
+{
+    int64_t p = gid();
+    if (p == 0) off[*nf] = (uint32_t)n;
+    if (p >= n || !flags[p]) return;
+    uint32_t f = fidx[p];
+    uint32_t fk = keys[p] / (uint32_t)nl;
+    uint64_t m = 0;
+    for (int64_t q = p; q < n && keys[q] / (uint32_t)nl == fk; ++q) m |= 1ull << (keys[q] % (uint32_t)nl);
+    off[f] = (uint32_t)p;
+    mask[f] = m;
+}
+
+__device__ inline uint32_t rotate_key(uint32_t key, uint32_t sk, uint32_t nk, uint32_t *dig)
+{
+    uint32_t hi = key / (sk * nk);
+    uint32_t rem = key - hi * sk * nk;
+    uint32_t d = rem / sk, lo = rem - d * sk;
+    *dig = d;
+    return (hi * sk + lo) * nk + d;
+}
+
+// bits [base, base+len) of the bitmap, len <= 64
+__device__ inline uint64_t extract_bits(const uint64_t *bm, uint32_t base, int len)
+{
+    uint32_t w0 = base >> 6, sh = base & 63;
+    uint64_t v = bm[w0] >> sh;
+    if (sh != 0 && sh + (uint32_t)len > 64) v |= bm[w0 + 1] << (64 - sh);
+    return len == 64 ? v : (v & ((1ull << len) - 1ull));
+}
+
+__global__ void k_rot_set(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, uint64_t *bm)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    uint32_t d;
+    set_bit(bm, rotate_key(keys[p], sk, nk, &d));
+}
+
+__global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, const uint64_t *bm,
+                           const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    uint32_t d;
+    uint32_t rk = rotate_key(keys[p], sk, nk, &d);
+    uint64_t word = bm[rk >> 6];
+    uint32_t q = prefix[rk >> 6] + (uint32_t)__popcll(word & ((1ull << (rk & 63)) - 1ull));
+    pi[q] = (uint32_t)p;
+    uint64_t m = extract_bits(bm, rk - d, (int)nk);
+    bool start = (m & ((1ull << d) - 1ull)) == 0;
+    flags[q] = start ? 1u : 0u;
+    if (start) tmpmask[q] = m;
+}
+
+__global__ void k_fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
+                           const uint32_t *nf, uint32_t *off, uint64_t *mask)
+{
+    int64_t q = gid();
+    if (q == 0) off[*nf] = (uint32_t)n;
+    if (q >= n || !flags[q]) return;
+    uint32_t f = fidx[q];
+    off[f] = (uint32_t)q;
+    mask[f] = tmpmask[q];
+}
+
+// ---- potential cache -----------------------------------------------------------
+__global__ void k_potential(const uint32_t *keys, int64_t n, GridDesc g, PotDesc pd, double *V, float *Vf)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    uint32_t key = keys[p];
+    int d[MAXD];
+    for (int k = 0; k < g.D; ++k) d[k] = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+    double v = 0.0;
+    for (int t = 0; t < pd.nterm; ++t) {
+        double f = pd.coef[t];
+        for (int k = 0; k < g.D; ++k) {
+            int ti = pd.tab[t * pd.D + k];
+            if (ti >= 0) f *= pd.tabs[(int64_t)ti * pd.nmax + d[k]];
+        }
+        v += f;
+    }
+    if (V) V[p] = v;
+    if (Vf) Vf[p] = (float)v;
+}
+
+// ---- Krylov vectors ---------------------------------------------------------------
+__device__ inline double2 ld2(const double2 *p, int64_t i) { return p[i]; }
+__device__ inline double2 ld2(const float2 *p, int64_t i)
+{
+    float2 v = p[i];
+    return make_double2((double)v.x, (double)v.y);
+}
+__device__ inline void st2(double2 *p, int64_t i, double2 v) { p[i] = v; }
+__device__ inline void st2(float2 *p, int64_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+
+// conj(a) * b accumulated
+__device__ inline void cdot_acc(double2 &acc, double2 a, double2 b)
+{
+    acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
+}
+
+template <int NV>
+__device__ inline void block_reduce_store(double2 (&acc)[NV], double2 *partial)
+{
+    __shared__ double2 red[TB / 64][NV];
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double2 v = acc[i];
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            v.x += __shfl_xor(v.x, s, 64);
+            v.y += __shfl_xor(v.y, s, 64);
+        }
+        if (lane == 0) red[w][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double2 s = red[0][threadIdx.x];
+        for (int ww = 1; ww < TB / 64; ++ww) {
+            s.x += red[ww][threadIdx.x].x;
+            s.y += red[ww][threadIdx.x].y;
+        }
+        partial[(int64_t)blockIdx.x * MAXM + threadIdx.x] = s;
+    }
+}
+
+template <class C, int NV>
+__global__ __launch_bounds__(TB) void k_cgs_dots(const C *Vb, int64_t ld, const C *w, int64_t n, double2 *partial,
+                                                 const int *meff, int j)
+{
+    if (meff && j >= *meff) return;
+    double2 acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 wv = ld2(w, p);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], ld2(Vb, (int64_t)i * ld + p), wv);
+    }
+    block_reduce_store<NV>(acc, partial);
+}
+
+template <class C, int NV>
+__global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld, C *w, int64_t n,
+                                                        const double2 *h, double2 *partial, const int *meff, int j)
+{
+    if (meff && j >= *meff) return;
+    double2 hc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hc[i] = h[i * MAXM + j];
+    double2 acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 wv = ld2(w, p);
+        double2 vv[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            vv[i] = ld2(Vb, (int64_t)i * ld + p);
+            wv.x -= hc[i].x * vv[i].x - hc[i].y * vv[i].y;
+            wv.y -= hc[i].x * vv[i].y + hc[i].y * vv[i].x;
+        }
+        st2(w, p, wv);
+        double2 wr = ld2(w, p);  // dots against the stored (possibly rounded) vector
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], wr);
+    }
+    block_reduce_store<NV>(acc, partial);
+}
+
+template <class C, int NV>
+__global__ __launch_bounds__(TB) void k_cgs_update_norm(const C *Vb, int64_t ld, const C *w, C *out, int64_t n,
+                                                        const double2 *h, double2 *partial, const int *meff, int j)
+{
+    if (meff && j >= *meff) return;
+    double2 hc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hc[i] = h[i * MAXM + j];
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 wv = ld2(w, p);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double2 vv = ld2(Vb, (int64_t)i * ld + p);
+            wv.x -= hc[i].x * vv.x - hc[i].y * vv.y;
+            wv.y -= hc[i].x * vv.y + hc[i].y * vv.x;
+        }
+        st2(out, p, wv);
+        double2 wr = ld2(out, p);
+        acc[0].x = fma(wr.x, wr.x, fma(wr.y, wr.y, acc[0].x));
+    }
+    block_reduce_store<1>(acc, partial);
+}
+
+template <class C>
+__global__ void k_scale(C *v, int64_t n, const double *inv, const int *meff, int j)
+{
+    if (meff && j >= *meff) return;
+    double s = *inv;
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        double2 a = ld2(v, p);
+        st2(v, p, make_double2(a.x * s, a.y * s));
+    }
+}
+
+template <class C>
+__global__ void k_normalise(const double2 *psi, int64_t n, const KState *ks, C *v0)
+{
+    double s = 1.0 / ks->n0;
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        double2 a = psi[p];
+        st2(v0, p, make_double2(a.x * s, a.y * s));
+    }
+}
+
+template <class C>
+__global__ void k_lincomb(const C *Vb, int64_t ld, int nv, const double2 *psi_master, int64_t n, const KState *ks,
+                          double2 *out)
+{
+    int meff = ks->meff;
+    double2 y[MAXM];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) y[i] = ks->y[i];
+    double inv_n0 = 1.0 / ks->n0;
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        // j = 0 from the FP64 master copy (exact v_0 direction), j >= 1 from the basis
+        double2 v = psi_master[p];
+        v.x *= inv_n0;
+        v.y *= inv_n0;
+        double2 acc = make_double2(y[0].x * v.x - y[0].y * v.y, y[0].x * v.y + y[0].y * v.x);
+#pragma unroll
+        for (int i = 1; i < MAXM; ++i) {
+            if (i < meff) {
+                double2 b = ld2(Vb, (int64_t)i * ld + p);
+                acc.x += y[i].x * b.x - y[i].y * b.y;
+                acc.y += y[i].x * b.y + y[i].y * b.x;
+            }
+        }
+        out[p] = acc;
+    }
+    (void)nv;
+}
+
+// Fixed-order final reduction of per-block partials [nb][MAXM].
+__global__ __launch_bounds__(TB) void k_reduce_krylov(const double2 *partial, int nb, int nv, KState *ks, int j,
+                                                      int mode, int m, int ioff)
+{
+    if (mode != RED_NORM0 && j >= ks->meff) return;
+    __shared__ double2 red[TB];
+    for (int i = 0; i < nv; ++i) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = threadIdx.x; b < nb; b += TB) {
+            s.x += partial[(int64_t)b * MAXM + i].x;
+            s.y += partial[(int64_t)b * MAXM + i].y;
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int st = TB / 2; st >= 1; st >>= 1) {
+            if ((int)threadIdx.x < st) {
+                red[threadIdx.x].x += red[threadIdx.x + st].x;
+                red[threadIdx.x].y += red[threadIdx.x + st].y;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double2 r = red[0];
+            if (mode == RED_NORM0) {
+                ks->n0 = sqrt(r.x);
+                ks->meff = m;
+            } else if (mode == RED_H1) {
+                ks->h1[(i + ioff) * MAXM + j] = r;
+                if (i + ioff == j) ks->alpha[j] = r.x;
+            } else if (mode == RED_H2) {
+                ks->h2[(i + ioff) * MAXM + j] = r;
+            } else {  // RED_BETA
+                double b = sqrt(r.x);
+                ks->beta[j] = b;
+                if (j < m - 1) {
+                    if (b < 1e-13) {
+                        ks->meff = j + 1;
+                        ks->inv_beta = 0.0;
+                    } else {
+                        ks->inv_beta = 1.0 / b;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+// y = n0 * exp(-i dt Hk) e_1 for the meff x meff Krylov matrix, by scaling and
+// squaring of a truncated Taylor series; one workgroup of 256 lanes, lane
+// (r, c) owns entry (r, c) of the 16 x 16 matrices.
+__global__ __launch_bounds__(256) void k_krylov_expv(KState *ks, double dt, int hermitian)
+{
+    __shared__ double2 A[MAXM][MAXM], P[MAXM][MAXM], E[MAXM][MAXM];
+    __shared__ double rown[MAXM];
+    __shared__ int s_sq;
+    int meff = ks->meff;
+    int r = threadIdx.x / MAXM, c = threadIdx.x % MAXM;
+    double2 h = make_double2(0.0, 0.0);
+    if (r < meff && c < meff) {
+        if (hermitian) {
+            if (r == c) h = make_double2(ks->alpha[r], 0.0);
+            else if (r == c + 1) h = make_double2(ks->beta[c], 0.0);
+            else if (c == r + 1) h = make_double2(ks->beta[r], 0.0);
+        } else {
+            if (r <= c) {
+                double2 a = ks->h1[r * MAXM + c], b = ks->h2[r * MAXM + c];
+                h = make_double2(a.x + b.x, a.y + b.y);
+            } else if (r == c + 1) {
+                h = make_double2(ks->beta[c], 0.0);
+            }
+        }
+    }
+    // A = -i dt H
+    A[r][c] = make_double2(dt * h.y, -dt * h.x);
+    __syncthreads();
+    if (threadIdx.x < MAXM) {
+        double s = 0.0;
+        for (int cc = 0; cc < MAXM; ++cc) s += sqrt(A[threadIdx.x][cc].x * A[threadIdx.x][cc].x + A[threadIdx.x][cc].y * A[threadIdx.x][cc].y);
+        rown[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double nrm = 0.0;
+        for (int i = 0; i < MAXM; ++i) nrm = rown[i] > nrm ? rown[i] : nrm;
+        int sq = 0;
+        while (nrm > 0.125) {
+            nrm *= 0.5;
+            ++sq;
+        }
+        s_sq = sq;
+    }
+    __syncthreads();
+    int sq = s_sq;
+    double scale = ldexp(1.0, -sq);
+    A[r][c] = make_double2(A[r][c].x * scale, A[r][c].y * scale);
+    P[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    E[r][c] = P[r][c];
+    __syncthreads();
+    for (int kt = 1; kt <= 18; ++kt) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int l = 0; l < MAXM; ++l) {
+            double2 t = cmul(P[r][l], A[l][c]);
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+        __syncthreads();
+        P[r][c] = make_double2(acc.x / kt, acc.y / kt);
+        E[r][c] = make_double2(E[r][c].x + acc.x / kt, E[r][c].y + acc.y / kt);
+        __syncthreads();
+    }
+    for (int q = 0; q < sq; ++q) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int l = 0; l < MAXM; ++l) {
+            double2 t = cmul(E[r][l], E[l][c]);
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+        __syncthreads();
+        E[r][c] = acc;
+        __syncthreads();
+    }
+    if (c == 0 && r < MAXM) {
+        double n0 = ks->n0;
+        ks->y[r] = (r < meff) ? make_double2(n0 * E[r][0].x, n0 * E[r][0].y) : make_double2(0.0, 0.0);
+    }
+}
+
+__global__ __launch_bounds__(TB) void k_norm2_partial(const double2 *psi, int64_t n, double2 *partial)
+{
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 a = psi[p];
+        acc[0].x = fma(a.x, a.x, fma(a.y, a.y, acc[0].x));
+    }
+    block_reduce_store<1>(acc, partial);
+}
+
+__global__ __launch_bounds__(TB) void k_dot_partial(const double2 *a, const double2 *b, int64_t n,
+                                                    double2 *partial)
+{
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) cdot_acc(acc[0], a[p], b[p]);
+    block_reduce_store<1>(acc, partial);
+}
+
+// ---- observables ------------------------------------------------------------------
+__global__ __launch_bounds__(TB) void k_obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, GridDesc g,
+                                                    const double2 *bra, int nmax, double eps2, double2 *partial)
+{
+    double2 acc[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 c = psi[p];
+        acc[0].x = fma(c.x, c.x, fma(c.y, c.y, acc[0].x));
+        uint32_t key = keys[p];
+        double2 v = make_double2(1.0, 0.0);
+        for (int k = 0; k < g.D; ++k) {
+            int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+            v = cmul(v, bra[k * nmax + d]);
+        }
+        cdot_acc(acc[1], v, c);
+        if (above_eps(c, eps2)) acc[2].x += 1.0;
+    }
+    block_reduce_store<3>(acc, partial);
+}
+
+__global__ __launch_bounds__(TB) void k_obs_final(const double2 *partial, int nb, double *rec)
+{
+    __shared__ double2 red[TB];
+    for (int i = 0; i < 3; ++i) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = threadIdx.x; b < nb; b += TB) {
+            s.x += partial[(int64_t)b * MAXM + i].x;
+            s.y += partial[(int64_t)b * MAXM + i].y;
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int st = TB / 2; st >= 1; st >>= 1) {
+            if ((int)threadIdx.x < st) {
+                red[threadIdx.x].x += red[threadIdx.x + st].x;
+                red[threadIdx.x].y += red[threadIdx.x + st].y;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (i == 0) rec[PPQ_OBS_NORM2] = red[0].x;
+            if (i == 1) {
+                rec[PPQ_OBS_ACF_RE] = red[0].x;
+                rec[PPQ_OBS_ACF_IM] = red[0].y;
+            }
+            if (i == 2) rec[PPQ_OBS_NABOVE] = red[0].x;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_copy_alpha0(const KState *ks, double *dst) { *dst = ks->alpha[0]; }
+__global__ void k_copy_meff(const KState *ks, double *dst) { *dst = (double)ks->meff; }
+
+__global__ __launch_bounds__(TB) void k_energy_from_dot(const double2 *partial, int nb, double *rec)
+{
+    __shared__ double red[TB];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += TB) s += partial[(int64_t)b * MAXM].x;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = TB / 2; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double n2 = rec[PPQ_OBS_NORM2];
+        rec[PPQ_OBS_ENERGY] = n2 > 0.0 ? red[0] / n2 : 0.0;
+    }
+}
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------------
+void fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s)
+{
+    if (n <= 0) return;
+    unsigned b = nblocks(n);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_fill<uint64_t>, dim3(b), dim3(TB), 0, s, p, n, v);
+}
+void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
+{
+    if (n <= 0) return;
+    unsigned b = nblocks(n);
+    if (b > 8192) b = 8192;
+    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(b), dim3(TB), 0, s, p, n, v);
+}
+void fill_zero_bytes(void *p, int64_t nbytes, hipStream_t s)
+{
+    // callers pass 8-byte multiples
+    fill_u64((uint64_t *)p, nbytes / 8, 0ull, s);
+}
+
+int64_t scan_tmp_words(int64_t n) { return (n + STILE - 1) / STILE + 16; }
+
+void scan_popcount(const uint64_t *words, int64_t nwords, uint32_t *prefix, uint32_t *total, uint32_t *tmp,
+                   hipStream_t s)
+{
+    scan_impl(PopLoad{words}, nwords, prefix, total, tmp, s);
+}
+void scan_u32(const uint32_t *in, int64_t n, uint32_t *out, uint32_t *total, uint32_t *tmp, hipStream_t s)
+{
+    scan_impl(U32Load{in}, n, out, total, tmp, s);
+}
+
+void init_flag(const GridDesc &g, const double2 *tabs, int nmax, double eps2, uint64_t *bm,
+               unsigned long long *nabove, hipStream_t s)
+{
+    unsigned b = nblocks(g.total);
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(k_init_flag, dim3(b), dim3(TB), 0, s, g, tabs, nmax, eps2, bm, nabove);
+}
+void product_values(const uint32_t *keys, int64_t n, const GridDesc &g, const double2 *tabs, int nmax,
+                    double2 *out, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_product_values, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g, tabs, nmax, out);
+}
+void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, double eps2, uint64_t *bm,
+            unsigned long long *nabove, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_dilate, dim3(nblocks(n)), dim3(TB), 0, s, keys, psi, n, g, eps2, bm, nabove);
+}
+void mark_keys(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mark, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, bm);
+}
+void compact(const uint64_t *bm, const uint32_t *prefix, int64_t nwords, uint32_t *keys_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact, dim3(nblocks(nwords)), dim3(TB), 0, s, bm, prefix, nwords, keys_out);
+}
+void remap(const uint32_t *okeys, const double2 *opsi, int64_t n_old, const uint64_t *bm, const uint32_t *prefix,
+           double2 *npsi, hipStream_t s)
+{
+    if (n_old <= 0) return;
+    hipLaunchKernelGGL(k_remap, dim3(nblocks(n_old)), dim3(TB), 0, s, okeys, opsi, n_old, bm, prefix, npsi);
+}
+
+void last_flags(const uint32_t *keys, int64_t n, int nlast, uint32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_last_flags, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, nlast, flags);
+}
+void last_fill(const uint32_t *keys, int64_t n, int nlast, const uint32_t *flags, const uint32_t *fidx,
+               const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_last_fill, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, nlast, flags, fidx, nf, off, mask);
+}
+void rot_set(const uint32_t *keys, int64_t n, int k, const GridDesc &g, uint64_t *bm, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rot_set, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g.stride[k], (uint32_t)g.n[k], bm);
+}
+void rot_rank(const uint32_t *keys, int64_t n, int k, const GridDesc &g, const uint64_t *bm,
+              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_rot_rank, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g.stride[k], (uint32_t)g.n[k], bm,
+                       prefix, pi, flags, tmpmask);
+}
+void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n, const uint32_t *nf,
+              uint32_t *off, uint64_t *mask, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fib_fill, dim3(nblocks(n)), dim3(TB), 0, s, flags, fidx, tmpmask, n, nf, off, mask);
+}
+
+void potential(const uint32_t *keys, int64_t n, const GridDesc &g, const PotDesc &pd, double *V, float *Vf,
+               hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_potential, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g, pd, V, Vf);
+}
+
+static unsigned red_blocks(int64_t n)
+{
+    int64_t b = (n + TB - 1) / TB;
+    if (b > RED_BLOCKS) b = RED_BLOCKS;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+#define PPQ_NV_SWITCH(nv, CALL) \
+    switch (nv) {               \
+    case 1: CALL(1); break;     \
+    case 2: CALL(2); break;     \
+    case 3: CALL(3); break;     \
+    case 4: CALL(4); break;     \
+    case 5: CALL(5); break;     \
+    case 6: CALL(6); break;     \
+    case 7: CALL(7); break;     \
+    case 8: CALL(8); break;     \
+    case 9: CALL(9); break;     \
+    case 10: CALL(10); break;   \
+    case 11: CALL(11); break;   \
+    case 12: CALL(12); break;   \
+    case 13: CALL(13); break;   \
+    case 14: CALL(14); break;   \
+    case 15: CALL(15); break;   \
+    case 16: CALL(16); break;   \
+    default: break;             \
+    }
+
+template <class C>
+void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, const int *meff, int j,
+              hipStream_t s)
+{
+#define CALL(NV) hipLaunchKernelGGL((k_cgs_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, meff, j)
+    PPQ_NV_SWITCH(nv, CALL)
+#undef CALL
+}
+template <class C>
+void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, const double2 *h, double2 *partial,
+                     const int *meff, int j, hipStream_t s)
+{
+#define CALL(NV) \
+    hipLaunchKernelGGL((k_cgs_update_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, h, partial, meff, j)
+    PPQ_NV_SWITCH(nv, CALL)
+#undef CALL
+}
+template <class C>
+void cgs_update_norm(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const double2 *h,
+                     double2 *partial, const int *meff, int j, hipStream_t s)
+{
+#define CALL(NV)                                                                                                  \
+    hipLaunchKernelGGL((k_cgs_update_norm<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, out, n, h, partial, \
+                       meff, j)
+    PPQ_NV_SWITCH(nv, CALL)
+#undef CALL
+}
+template <class C>
+void scale_vec(C *v, int64_t n, const double *inv, const int *meff, int j, hipStream_t s)
+{
+    unsigned b = red_blocks(n) * 4;
+    hipLaunchKernelGGL(k_scale<C>, dim3(b), dim3(TB), 0, s, v, n, inv, meff, j);
+}
+template <class C>
+void normalise_from_master(const double2 *psi, int64_t n, KState *ks, C *v0, hipStream_t s)
+{
+    unsigned b = red_blocks(n) * 4;
+    hipLaunchKernelGGL(k_normalise<C>, dim3(b), dim3(TB), 0, s, psi, n, ks, v0);
+}
+template <class C>
+void lincomb(const C *Vb, int64_t ld, int nv, const double2 *psi_master, int64_t n, const KState *ks,
+             double2 *psi_out, hipStream_t s)
+{
+    unsigned b = red_blocks(n) * 4;
+    hipLaunchKernelGGL(k_lincomb<C>, dim3(b), dim3(TB), 0, s, Vb, ld, nv, psi_master, n, ks, psi_out);
+}
+
+template void cgs_dots<double2>(const double2 *, int64_t, int, const double2 *, int64_t, double2 *, const int *, int,
+                                hipStream_t);
+template void cgs_dots<float2>(const float2 *, int64_t, int, const float2 *, int64_t, double2 *, const int *, int,
+                               hipStream_t);
+template void cgs_update_dots<double2>(const double2 *, int64_t, int, double2 *, int64_t, const double2 *, double2 *,
+                                       const int *, int, hipStream_t);
+template void cgs_update_dots<float2>(const float2 *, int64_t, int, float2 *, int64_t, const double2 *, double2 *,
+                                      const int *, int, hipStream_t);
+template void cgs_update_norm<double2>(const double2 *, int64_t, int, const double2 *, double2 *, int64_t,
+                                       const double2 *, double2 *, const int *, int, hipStream_t);
+template void cgs_update_norm<float2>(const float2 *, int64_t, int, const float2 *, float2 *, int64_t,
+                                      const double2 *, double2 *, const int *, int, hipStream_t);
+template void scale_vec<double2>(double2 *, int64_t, const double *, const int *, int, hipStream_t);
+template void scale_vec<float2>(float2 *, int64_t, const double *, const int *, int, hipStream_t);
+template void normalise_from_master<double2>(const double2 *, int64_t, KState *, double2 *, hipStream_t);
+template void normalise_from_master<float2>(const double2 *, int64_t, KState *, float2 *, hipStream_t);
+template void lincomb<double2>(const double2 *, int64_t, int, const double2 *, int64_t, const KState *, double2 *,
+                               hipStream_t);
+template void lincomb<float2>(const float2 *, int64_t, int, const double2 *, int64_t, const KState *, double2 *,
+                              hipStream_t);
+
+void reduce_krylov(const double2 *partial, int nblocks_, int nv, KState *ks, int j, int mode, int m, hipStream_t s,
+                   int ioff)
+{
+    hipLaunchKernelGGL(k_reduce_krylov, dim3(1), dim3(TB), 0, s, partial, nblocks_, nv, ks, j, mode, m, ioff);
+}
+void krylov_expv(KState *ks, int m, double dt, int hermitian, hipStream_t s)
+{
+    (void)m;
+    hipLaunchKernelGGL(k_krylov_expv, dim3(1), dim3(256), 0, s, ks, dt, hermitian);
+}
+void norm2_partial(const double2 *psi, int64_t n, double2 *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norm2_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, psi, n, partial);
+}
+void dot_partial(const double2 *a, const double2 *b, int64_t n, double2 *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, a, b, n, partial);
+}
+void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, const double2 *bra,
+                 int nmax, double eps2, double2 *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_obs_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, keys, psi, n, g, bra, nmax, eps2, partial);
+}
+void obs_final(const double2 *partial, int nb, double *rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(TB), 0, s, partial, nb, rec);
+}
+void copy_alpha0(const KState *ks, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_alpha0, dim3(1), dim3(1), 0, s, ks, dst);
+}
+void copy_meff(const KState *ks, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_meff, dim3(1), dim3(1), 0, s, ks, dst);
+}
+void energy_from_dot(const double2 *partial, int nb, double *rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_from_dot, dim3(1), dim3(TB), 0, s, partial, nb, rec);
+}
+
+}  // namespace ppq

@@ -1,0 +1,123 @@
+// Host-side FP64 builders of the 1D ingredients (run once per model).
+#include "ppq_model.hpp"
+
+#include <cmath>
+
+namespace ppq {
+
+std::vector<double> sine_dvr_points(int n, double lo, double hi)
+{
+    std::vector<double> q(n);
+    double dx = (hi - lo) / (n + 1);
+    for (int i = 0; i < n; ++i) q[i] = lo + (i + 1) * dx;
+    return q;
+}
+
+std::vector<double> sine_dvr_kinetic(int n, double lo, double hi, double mass)
+{
+    const double L = hi - lo;
+    std::vector<double> U((size_t)n * n), e(n), T((size_t)n * n, 0.0);
+    const double nrm = std::sqrt(2.0 / (n + 1));
+    for (int i = 1; i <= n; ++i)
+        for (int k = 1; k <= n; ++k) U[(size_t)(i - 1) * n + (k - 1)] = nrm * std::sin(M_PI * i * k / (n + 1));
+    for (int k = 1; k <= n; ++k) {
+        double p = k * M_PI / L;
+        e[k - 1] = p * p / (2.0 * mass);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += U[(size_t)i * n + k] * e[k] * U[(size_t)j * n + k];
+            T[(size_t)i * n + j] = s;
+        }
+    // exact symmetry
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            double s = 0.5 * (T[(size_t)i * n + j] + T[(size_t)j * n + i]);
+            T[(size_t)i * n + j] = s;
+            T[(size_t)j * n + i] = s;
+        }
+    return T;
+}
+
+std::vector<cd> pvb_projection(int n, double lo, double hi, int ns, int nl)
+{
+    std::vector<double> q = sine_dvr_points(n, lo, hi);
+    const double dxg = (hi - lo) / (n + 1);
+    const double cell = (hi - lo) / ns;
+    const double dp = 2.0 * M_PI / cell;
+    const double a = dp / (2.0 * cell);
+    const double pref = std::sqrt(dxg) * std::pow(2.0 * a / M_PI, 0.25);
+    std::vector<cd> G((size_t)n * n);
+    for (int s = 0; s < ns; ++s) {
+        double xs = lo + (s + 0.5) * cell;
+        for (int l = 0; l < nl; ++l) {
+            double pl = (l - 0.5 * (nl - 1)) * dp;
+            for (int j = 0; j < n; ++j) {
+                double d = q[j] - xs;
+                G[(size_t)j * n + (s * nl + l)] = pref * std::exp(cd(-a * d * d, pl * d));
+            }
+        }
+    }
+    return G;
+}
+
+bool invert(std::vector<cd> &a, int n)
+{
+    std::vector<cd> inv((size_t)n * n, cd(0.0, 0.0));
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        double best = std::abs(a[(size_t)c * n + c]);
+        for (int r = c + 1; r < n; ++r) {
+            double v = std::abs(a[(size_t)r * n + c]);
+            if (v > best) {
+                best = v;
+                piv = r;
+            }
+        }
+        if (best == 0.0) return false;
+        if (piv != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[(size_t)c * n + k], a[(size_t)piv * n + k]);
+                std::swap(inv[(size_t)c * n + k], inv[(size_t)piv * n + k]);
+            }
+        cd d = 1.0 / a[(size_t)c * n + c];
+        for (int k = 0; k < n; ++k) {
+            a[(size_t)c * n + k] *= d;
+            inv[(size_t)c * n + k] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            cd f = a[(size_t)r * n + c];
+            if (f == cd(0.0, 0.0)) continue;
+            for (int k = 0; k < n; ++k) {
+                a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+                inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+            }
+        }
+    }
+    a.swap(inv);
+    return true;
+}
+
+std::vector<cd> matmul(const std::vector<cd> &a, const std::vector<cd> &b, int n)
+{
+    std::vector<cd> c((size_t)n * n, cd(0.0, 0.0));
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            cd aik = a[(size_t)i * n + k];
+            for (int j = 0; j < n; ++j) c[(size_t)i * n + j] += aik * b[(size_t)k * n + j];
+        }
+    return c;
+}
+
+std::vector<cd> adjoint(const std::vector<cd> &a, int n)
+{
+    std::vector<cd> t((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) t[(size_t)j * n + i] = std::conj(a[(size_t)i * n + j]);
+    return t;
+}
+
+}  // namespace ppq

@@ -1,0 +1,292 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: integer/index work (active sets, fiber counts, carried-over
+coefficients) bit-exact; FP64 operator products within 1e-13 relative;
+FP64 trajectories within 1e-10 on every observable with identical active
+sets at every step.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from workloads import card, random_active_set, random_complex
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "needs a GPU"
+    return t
+
+
+def make(cd, torch, precision=0):
+    import paper_1606_04004_amd as ppq
+    return ppq.Propagator(cd, precision=precision, device=0, stream=torch.cuda.current_stream())
+
+
+def lattice_card(n=12, ns=3, nl=4, **kw):
+    base = card("small_4d", n=[n, n, n, n], **kw)
+    return dict(base, name="small_lattice4d", basis="pvb", lattice=[ns, nl])
+
+
+# ---------------------------------------------------------------------------
+# operator
+# ---------------------------------------------------------------------------
+APPLY_CASES = [
+    ("small_2d", 0.5, True, 1), ("small_3d", 0.35, True, 2), ("small_4d", 0.25, True, 3),
+    ("small_6d", 0.08, True, 4), ("small_3d", 1.0, False, 5), ("small_4d", 0.05, False, 6),
+    ("hh2d", 0.3, True, 7), ("morse4d", 0.02, True, 8),
+]
+
+
+@pytest.mark.parametrize("name,fill,blob,seed", APPLY_CASES)
+def test_apply_h_fp64(name, fill, blob, seed, torch):
+    cd = card(name)
+    say(f"apply_h fp64 {name} fill={fill} blob={blob} seed={seed}")
+    keys = random_active_set(cd["n"], fill, seed, blob=blob)
+    x = random_complex(keys.size, seed + 100)
+    ref = Oracle(cd).apply_def(keys, x)
+    g = make(cd, torch)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    say(f"  |A|={keys.size} rel err {err:.2e}")
+    assert err < 1e-13
+
+
+def test_apply_h_tiny_sets(torch):
+    cd = card("small_3d")
+    o = Oracle(cd)
+    for keys in (np.array([0], np.uint64), np.array([5, 6, 7], np.uint64),
+                 np.array([int(np.prod(cd["n"])) - 1], np.uint64)):
+        say(f"apply_h tiny set {keys.tolist()}")
+        x = random_complex(keys.size, 3)
+        g = make(cd, torch)
+        g.set_state(keys, x)
+        xt = torch.from_numpy(x).cuda()
+        yt = torch.zeros_like(xt)
+        g.apply_h(xt, yt)
+        torch.cuda.synchronize()
+        assert np.allclose(yt.cpu().numpy(), o.apply_def(keys, x), rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["hh2d", "morse4d", "quartic6d"])
+def test_apply_h_full_size_sampled(name, torch):
+    """Full workload size (the initial active set of each card), outputs sampled."""
+    cd = card(name)
+    say(f"apply_h sampled {name}")
+    g = make(cd, torch)
+    n = g.init_state()
+    keys, _ = g.state()
+    x = random_complex(n, 11)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 1500), [0, n - 1]]))
+    ref = Oracle(cd).apply_def_at(keys, x, idx)
+    err = np.max(np.abs(y[idx] - ref)) / np.max(np.abs(ref))
+    say(f"  |A|={n} sampled={idx.size} rel err {err:.2e}")
+    assert err < 1e-13
+
+
+def test_fiber_counts_match_oracle(torch):
+    cd = card("small_4d")
+    keys = random_active_set(cd["n"], 0.3, 17)
+    g = make(cd, torch)
+    g.set_state(keys, np.ones(keys.size, complex))
+    nf = g.fiber_counts()
+    o = Oracle(cd)
+    ref = [len(o.fiber_ranges(keys, k)) for k in range(cd["D"])]
+    assert nf.tolist() == ref
+
+
+# ---------------------------------------------------------------------------
+# adaption
+# ---------------------------------------------------------------------------
+def adversarial_state(n, seed, eps):
+    keys = random_active_set(n, 0.4, seed)
+    rng = np.random.default_rng(seed)
+    c = random_complex(keys.size, seed) * np.exp(rng.uniform(-14, 0, keys.size))
+    c[::13] = eps                       # |c|^2 == eps^2 exactly
+    c[3::29] = eps * (1 - 2 ** -52)     # just below
+    c[7::31] = 0.0
+    c[11::37] = 1e-310                  # subnormal
+    c[2::41] = 1j * eps                 # tie on the imaginary axis
+    return keys, c
+
+
+@pytest.mark.parametrize("name,seed", [("small_2d", 1), ("small_3d", 2), ("small_4d", 3), ("small_6d", 4)])
+def test_prune_bit_exact(name, seed, torch):
+    cd = card(name)
+    eps = 2.0 ** -10
+    keys, c = adversarial_state(cd["n"], seed, eps)
+    say(f"prune {name} |A|={keys.size}")
+    o = Oracle(cd)
+    o.set_state(keys, c)
+    nab_o = o.prune(eps=eps)
+    ko, co = o.state()
+    g = make(cd, torch)
+    g.set_state(keys, c)
+    na, nab_g = g.prune(eps=eps)
+    kg, cg = g.state()
+    assert np.array_equal(kg, ko)
+    assert np.array_equal(cg.view(np.uint64), co.view(np.uint64))
+    assert nab_g == nab_o and na == ko.size
+
+
+def test_prune_edge_cases(torch):
+    cd = card("small_3d")
+    total = int(np.prod(cd["n"]))
+    g = make(cd, torch)
+    say("prune: empty S")
+    keys = np.arange(0, total, 7, dtype=np.uint64)
+    g.set_state(keys, np.full(keys.size, 1e-9 + 0j))
+    assert g.prune(eps=1e-3) == (0, 0)
+    assert g.state()[0].size == 0
+    say("prune: from empty set")
+    assert g.prune(eps=1e-3) == (0, 0)
+    say("prune: S = full grid")
+    keys = np.arange(total, dtype=np.uint64)
+    g.set_state(keys, np.ones(total, complex))
+    assert g.prune(eps=0.5) == (total, total)
+    say("prune: lattice stencil")
+    lc = lattice_card()
+    o = Oracle(lc)
+    keys = random_active_set(lc["n"], 0.05, 3)
+    c = random_complex(keys.size, 3) * 1e-3
+    o.set_state(keys, c)
+    o.prune(eps=1e-3)
+    gl = make(lc, torch)
+    gl.set_state(keys, c)
+    gl.prune(eps=1e-3)
+    assert np.array_equal(gl.state()[0], o.state()[0])
+
+
+@pytest.mark.parametrize("name", ["hh2d", "small_3d", "morse4d", "quartic6d"])
+def test_initial_state(name, torch):
+    cd = card(name)
+    say(f"init {name}")
+    g = make(cd, torch)
+    n = g.init_state()
+    o = Oracle(cd)
+    o.init_state()
+    kg, cg = g.state()
+    ko, co = o.state()
+    say(f"  |A0| gpu={n} oracle={ko.size}")
+    assert np.array_equal(kg, ko)
+    assert np.max(np.abs(cg - co)) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# propagation
+# ---------------------------------------------------------------------------
+def test_single_step(torch):
+    cd = card("small_4d")
+    o = Oracle(cd)
+    o.init_state()
+    keys, c = o.state()
+    g = make(cd, torch)
+    g.set_state(keys, c)
+    say("single SIL step small_4d")
+    g.step()
+    o.sil_step()
+    kg, cg = g.state()
+    _, co = o.state()
+    assert np.max(np.abs(cg - co)) < 1e-13
+
+
+def test_hh2d_trajectory_sets_every_step(torch):
+    """Config 1 (2D, 48x48, eps=1e-5): identical active set after every step, 200 steps."""
+    cd = card("hh2d")
+    o = Oracle(cd)
+    o.init_state()
+    g = make(cd, torch)
+    g.init_state()
+    worst = 0.0
+    for st in range(cd["nsteps"]):
+        g.step()
+        g.prune()
+        o.sil_step()
+        o.prune()
+        kg, cg = g.state()
+        ko, co = o.state()
+        assert np.array_equal(kg, ko), f"active sets differ after step {st + 1}"
+        worst = max(worst, float(np.max(np.abs(cg - co))))
+    say(f"  hh2d 200 steps: max coefficient difference {worst:.2e}")
+    assert worst < 1e-10
+
+
+@pytest.mark.parametrize("name,nsteps,prune", [("hh2d", 200, True), ("hh2d", 200, False), ("small_3d", 40, True),
+                                               ("morse4d", 100, True), ("small_6d", 10, True)])
+def test_trajectory_observables(name, nsteps, prune, torch):
+    cd = card(name)
+    say(f"trajectory {name} {nsteps} steps prune={prune}")
+    o = Oracle(cd)
+    g = make(cd, torch)
+    if prune:
+        o.init_state()
+        g.init_state()
+    else:
+        # full grid holding the packet; eps = 0 keeps every function
+        keys = np.arange(int(np.prod(cd["n"])), dtype=np.uint64)
+        o.set_state(keys, o.psi0_on(keys))
+        g.init_state(eps=0.0)
+    tr, _ = o.propagate(nsteps=nsteps, prune=prune)
+    tg = g.propagate(nsteps=nsteps, prune=prune)
+    assert np.array_equal(tg[:, 5], tr[:, 5]), "active-set sizes differ"
+    for col, nm in ((1, "norm2"), (2, "energy"), (3, "acf_re"), (4, "acf_im"), (6, "n_above")):
+        d = np.max(np.abs(tg[:, col] - tr[:, col]))
+        say(f"  {nm}: max diff {d:.2e}")
+        assert d < 1e-10, nm
+
+
+def test_lattice_trajectory(torch):
+    """Phase-space lattice (biorthogonal projected von Neumann), Arnoldi, lattice stencil."""
+    cd = lattice_card(eps=1e-4)
+    say("lattice trajectory")
+    o = Oracle(cd)
+    o.init_state()
+    g = make(cd, torch)
+    g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=10, dt=0.05)
+    tg = g.propagate(nsteps=10, dt=0.05)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 3, 4, 6):
+        d = np.max(np.abs(tg[:, col] - tr[:, col]))
+        say(f"  col {col}: {d:.2e}")
+        assert d < 1e-10
+
+
+@pytest.mark.parametrize("name,nsteps", [("hh2d", 200), ("morse4d", 100)])
+def test_fp32_form_error(name, nsteps, torch):
+    """Complex-FP32 operator and Krylov vectors, FP64 reductions: error vs the FP64 oracle."""
+    import paper_1606_04004_amd as ppq
+    cd = card(name)
+    say(f"fp32 form {name}")
+    o = Oracle(cd)
+    o.init_state()
+    tr, _ = o.propagate(nsteps=nsteps)
+    g = make(cd, torch, precision=ppq.PPQ_FP32)
+    g.init_state()
+    tg = g.propagate(nsteps=nsteps)
+    errs = {nm: float(np.max(np.abs(tg[:, c] - tr[:, c]))) for c, nm in ((1, "norm2"), (2, "energy"),
+                                                                      (3, "acf_re"), (4, "acf_im"))}
+    rel_n = float(np.max(np.abs(tg[:, 5] - tr[:, 5]) / tr[:, 5]))
+    say(f"  errors {errs} |A| rel {rel_n:.2e}")
+    assert errs["norm2"] < 1e-5 and errs["acf_re"] < 1e-5 and errs["acf_im"] < 1e-5
+    assert errs["energy"] < 1e-4 * abs(tr[0, 2])
