@@ -230,8 +230,12 @@ def test_hh2d_trajectory_sets_every_step(torch):
     assert worst < 1e-10
 
 
+# The 4D Morse card (dt = 0.1, m = 10) is numerically sensitive: a 1e-15
+# relative perturbation of the oracle's own initial state reaches 1.4e-10 in
+# C(t) after 30 steps, so the free-running comparison stops at 25 steps and
+# test_shadow_steps_morse4d checks the step map itself over a longer run.
 @pytest.mark.parametrize("name,nsteps,prune", [("hh2d", 200, True), ("hh2d", 200, False), ("small_3d", 40, True),
-                                               ("morse4d", 100, True), ("small_6d", 10, True)])
+                                               ("morse4d", 25, True), ("small_6d", 10, True)])
 def test_trajectory_observables(name, nsteps, prune, torch):
     cd = card(name)
     say(f"trajectory {name} {nsteps} steps prune={prune}")
@@ -254,6 +258,29 @@ def test_trajectory_observables(name, nsteps, prune, torch):
         assert d < 1e-10, nm
 
 
+def test_shadow_steps_morse4d(torch):
+    """Each step of the GPU map from the oracle's state equals the oracle's step:
+    identical adapted set, coefficients within 1e-12 (relative to the largest)."""
+    cd = card("morse4d")
+    o = Oracle(cd)
+    o.init_state()
+    g = make(cd, torch)
+    worst = 0.0
+    for st in range(40):
+        keys, c = o.state()
+        g.set_state(keys, c)
+        g.step()
+        g.prune()
+        o.sil_step()
+        o.prune()
+        kg, cg = g.state()
+        ko, co = o.state()
+        assert np.array_equal(kg, ko), f"sets differ at step {st + 1}"
+        worst = max(worst, float(np.max(np.abs(cg - co)) / np.max(np.abs(co))))
+    say(f"  morse4d 40 shadowed steps: |A|={ko.size}, worst rel coefficient diff {worst:.2e}")
+    assert worst < 1e-12
+
+
 def test_lattice_trajectory(torch):
     """Phase-space lattice (biorthogonal projected von Neumann), Arnoldi, lattice stencil."""
     cd = lattice_card(eps=1e-4)
@@ -272,7 +299,7 @@ def test_lattice_trajectory(torch):
         assert d < 1e-10
 
 
-@pytest.mark.parametrize("name,nsteps", [("hh2d", 200), ("morse4d", 100)])
+@pytest.mark.parametrize("name,nsteps", [("hh2d", 200), ("morse4d", 25), ("small_6d", 10)])
 def test_fp32_form_error(name, nsteps, torch):
     """Complex-FP32 operator and Krylov vectors, FP64 reductions: error vs the FP64 oracle."""
     import paper_1606_04004_amd as ppq
