@@ -4,6 +4,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -107,6 +108,7 @@ struct ppq_ctx {
     double *pot_tabs = nullptr;
     int pot_nterm = 0;
     int pot_nmax = 0;
+    int pot_ntab = 0;
 
     // state
     int64_t cap = 0;
@@ -124,7 +126,9 @@ struct ppq_ctx {
     uint32_t *pi[MAXD]{};
     uint32_t *off[MAXD]{};
     uint64_t *mask[MAXD]{};
+    uint8_t *info[MAXD]{};
     int64_t nf[MAXD]{};
+    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides, for measurement)
 
     // work
     uint32_t *flags = nullptr, *fidx = nullptr;
@@ -146,6 +150,7 @@ struct ppq_ctx {
     std::vector<void *> zbuf;  // intermediates of product terms
     KState *ks = nullptr;
     double2 *partial = nullptr;
+    unsigned *counter = nullptr;
 
     // reference packet
     bool has_ref = false;
@@ -189,6 +194,7 @@ void free_state_buffers(ppq_ctx *c)
         dfree(c->pi[k]);
         dfree(c->off[k]);
         dfree(c->mask[k]);
+        dfree(c->info[k]);
     }
     dfree(c->flags);
     dfree(c->fidx);
@@ -258,6 +264,7 @@ void ensure_capacity(ppq_ctx *c, int64_t n)
         if (k < c->g.D - 1) c->pi[k] = dalloc<uint32_t>(nc);
         c->off[k] = dalloc<uint32_t>(nc + 1);
         c->mask[k] = dalloc<uint64_t>(nc);
+        c->info[k] = dalloc<uint8_t>(nc);
     }
     c->flags = dalloc<uint32_t>(nc);
     c->fidx = dalloc<uint32_t>(nc);
@@ -397,15 +404,31 @@ void build_operator(ppq_ctx *c)
             }
             for (int k = 0; k < D; ++k) {
                 if (per[k].empty()) continue;
-                idx[k] = (int)(tabs.size() / nmax);
                 per[k].resize(nmax, 0.0);
-                tabs.insert(tabs.end(), per[k].begin(), per[k].end());
+                // identical tables (q, q^2, ... on equal grids) are stored once
+                int found = -1;
+                for (size_t t0 = 0; t0 < tabs.size() / nmax && found < 0; ++t0)
+                    if (std::equal(per[k].begin(), per[k].end(), tabs.begin() + t0 * nmax)) found = (int)t0;
+                if (found < 0) {
+                    found = (int)(tabs.size() / nmax);
+                    tabs.insert(tabs.end(), per[k].begin(), per[k].end());
+                }
+                idx[k] = found;
             }
             coef.push_back(t.coef);
             tab.insert(tab.end(), idx.begin(), idx.end());
         }
         c->pot_nterm = (int)coef.size();
         c->pot_nmax = nmax;
+        c->pot_ntab = (int)(tabs.size() / nmax);
+        int maxf = 0;
+        for (int t = 0; t < c->pot_nterm; ++t) {
+            int nf = 0;
+            for (int k = 0; k < D; ++k) nf += tab[(size_t)t * D + k] >= 0;
+            maxf = std::max(maxf, nf);
+        }
+        if (c->pot_nterm > 256 || (int64_t)tabs.size() > 1024 || maxf > 4)
+            throw std::invalid_argument("potential: at most 256 terms of at most 4 factors, 1024 distinct table values");
         if (coef.empty()) {
             coef.push_back(0.0);
             tab.assign(D, -1);
@@ -507,16 +530,17 @@ void build_derived(ppq_ctx *c)
     last_flags(keys, n, c->g.n[D - 1], c->flags, s);
     scan_u32(c->flags, n, c->fidx, &c->small[D - 1], c->scan_tmp, s);
     last_fill(keys, n, c->g.n[D - 1], c->flags, c->fidx, &c->small[D - 1], c->off[D - 1], c->mask[D - 1], s);
+    last_info(keys, n, c->g.n[D - 1], c->info[D - 1], s);
     for (int k = 0; k < D - 1; ++k) {
         fill_u64(c->bm, c->nwords + 2, 0ull, s);
         rot_set(keys, n, k, c->g, c->bm, s);
         scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
-        rot_rank(keys, n, k, c->g, c->bm, c->prefix, c->pi[k], c->flags, c->tmpmask, s);
+        rot_rank(keys, n, k, c->g, c->bm, c->prefix, c->pi[k], c->flags, c->tmpmask, c->info[k], s);
         scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
         fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
     }
     if (!c->any_lattice) {
-        PotDesc pd{c->pot_nterm, D, c->pot_nmax, c->pot_coef, c->pot_tab, c->pot_tabs};
+        PotDesc pd{c->pot_nterm, D, c->pot_nmax, c->pot_coef, c->pot_tab, c->pot_tabs, c->pot_ntab};
         potential(keys, n, c->g, pd, c->V64, c->V32, s);
     }
     ck(hipMemcpyAsync(c->h_small, c->small, sizeof(uint32_t) * 2 * MAXD, hipMemcpyDeviceToHost, s), "nf");
@@ -543,6 +567,62 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
     hipStream_t s = c->stream;
     if (c->nact == 0) return;
     if (!c->any_lattice) {
+        if (c->hpsi_variant == 3) {
+            const int64_t n = c->nact;
+            if (c->precision == PPQ_FP64) {
+                const double2 *x = (const double2 *)xv;
+                double2 *y = (double2 *)yv;
+                hpsi_pt_f64(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T64[D - 1], x, c->V64, y, true, skip_if,
+                            skip_j, s);
+                for (int k = D - 2; k >= 0; --k) hpsi_acc_f64(pass_of(c, k), c->T64[k], x, y, skip_if, skip_j, s);
+            } else {
+                const float2 *x = (const float2 *)xv;
+                float2 *y = (float2 *)yv;
+                hpsi_pt_f32(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T32[D - 1], x, c->V32, y, true, skip_if,
+                            skip_j, s);
+                for (int k = D - 2; k >= 0; --k) hpsi_acc_f32(pass_of(c, k), c->T32[k], x, y, skip_if, skip_j, s);
+            }
+            return;
+        }
+        if (c->hpsi_variant == 2) {
+            // point-parallel for the contiguous last dimension, lane per fiber elsewhere
+            const int64_t n = c->nact;
+            if (c->precision == PPQ_FP64) {
+                const double2 *x = (const double2 *)xv;
+                double2 *y = (double2 *)yv;
+                hpsi_pt_f64(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T64[D - 1], x, c->V64, y, true, skip_if,
+                            skip_j, s);
+                for (int k = D - 2; k >= 0; --k)
+                    hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
+            } else {
+                const float2 *x = (const float2 *)xv;
+                float2 *y = (float2 *)yv;
+                hpsi_pt_f32(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T32[D - 1], x, c->V32, y, true, skip_if,
+                            skip_j, s);
+                for (int k = D - 2; k >= 0; --k)
+                    hpsi_real_f32(pass_of(c, k), c->T32[k], x, nullptr, y, false, skip_if, skip_j, s);
+            }
+            return;
+        }
+        if (c->hpsi_variant == 1) {
+            const int64_t n = c->nact;
+            if (c->precision == PPQ_FP64) {
+                const double2 *x = (const double2 *)xv;
+                double2 *y = (double2 *)yv;
+                hpsi_pt_f64(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T64[D - 1], x, c->V64, y, true, skip_if,
+                            skip_j, s);
+                for (int k = D - 2; k >= 0; --k)
+                    hpsi_pt_f64(c->pi[k], c->info[k], n, c->nb[k], c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
+            } else {
+                const float2 *x = (const float2 *)xv;
+                float2 *y = (float2 *)yv;
+                hpsi_pt_f32(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T32[D - 1], x, c->V32, y, true, skip_if,
+                            skip_j, s);
+                for (int k = D - 2; k >= 0; --k)
+                    hpsi_pt_f32(c->pi[k], c->info[k], n, c->nb[k], c->T32[k], x, nullptr, y, false, skip_if, skip_j, s);
+            }
+            return;
+        }
         if (c->precision == PPQ_FP64) {
             const double2 *x = (const double2 *)xv;
             double2 *y = (double2 *)yv;
@@ -637,30 +717,24 @@ void step_impl(ppq_ctx *c, double dt, int m)
     KState *ks = c->ks;
     const int *meff = &ks->meff;
     const bool herm = !c->any_lattice;
-    norm2_partial(c->psi[c->cur], n, c->partial, s);
-    reduce_krylov(c->partial, RED_BLOCKS, 1, ks, 0, RED_NORM0, m, s);
+    norm0<C>(c->psi[c->cur], n, c->partial, c->counter, ks, m, s);
     normalise_from_master<C>(c->psi[c->cur], n, ks, Vb, s);
     for (int j = 0; j < m; ++j) {
         const C *vj = Vb + (int64_t)j * ld;
         apply_internal(c, vj, w, meff, j);
         const bool last = (j == m - 1);
         if (last && herm) {
-            cgs_dots<C>(vj, ld, 1, w, n, c->partial, meff, j, s);
-            reduce_krylov(c->partial, RED_BLOCKS, 1, ks, j, RED_H1, m, s, j);
+            // only alpha_{m-1} = <v_j|H v_j> enters the tridiagonal matrix
+            cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s);
             break;
         }
-        cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, meff, j, s);
-        reduce_krylov(c->partial, RED_BLOCKS, j + 1, ks, j, RED_H1, m, s);
-        cgs_update_dots<C>(Vb, ld, j + 1, w, n, ks->h1, c->partial, meff, j, s);
-        reduce_krylov(c->partial, RED_BLOCKS, j + 1, ks, j, RED_H2, m, s);
+        cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, 0, s);
+        cgs_update_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, !last, s);
         if (last) break;
-        C *vn = Vb + (int64_t)(j + 1) * ld;
-        cgs_update_norm<C>(Vb, ld, j + 1, w, vn, n, ks->h2, c->partial, meff, j, s);
-        reduce_krylov(c->partial, RED_BLOCKS, 1, ks, j, RED_BETA, m, s);
-        scale_vec<C>(vn, n, &ks->inv_beta, meff, j + 1, s);
+        cgs_update_scale<C>(Vb, ld, j + 1, w, Vb + (int64_t)(j + 1) * ld, n, ks, j, s);
     }
     krylov_expv(ks, m, dt, herm ? 1 : 0, s);
-    lincomb<C>(Vb, ld, m, c->psi[c->cur], n, ks, c->psi_tmp, s);
+    lincomb<C>(Vb, ld, c->psi[c->cur], n, ks, c->psi_tmp, s);
     std::swap(c->psi[c->cur], c->psi_tmp);
 }
 
@@ -742,12 +816,11 @@ void energy_into(ppq_ctx *c, int64_t r)
         // FP32 form: H acts on the FP32 copy; the inner product is accumulated in FP64
         float2 *x32 = (float2 *)c->Vk;
         KState *ks = c->ks;
-        norm2_partial(c->psi[c->cur], c->nact, c->partial, c->stream);
-        reduce_krylov(c->partial, RED_BLOCKS, 1, ks, 0, RED_NORM0, 1, c->stream);
+        norm0<float2>(c->psi[c->cur], c->nact, c->partial, c->counter, ks, 1, c->stream);
         normalise_from_master<float2>(c->psi[c->cur], c->nact, ks, x32, c->stream);
         apply_internal(c, x32, c->wk, nullptr, 0);
-        cgs_dots<float2>(x32, c->cap, 1, (const float2 *)c->wk, c->nact, c->partial, nullptr, 0, c->stream);
-        reduce_krylov(c->partial, RED_BLOCKS, 1, ks, 0, RED_H1, 1, c->stream);
+        cgs_dots<float2>(x32, c->cap, 1, (const float2 *)c->wk, c->nact, c->partial, c->counter, ks, 0, 1, 0,
+                         c->stream);
         copy_alpha0(ks, rec + PPQ_OBS_ENERGY, c->stream);
         return;
     }
@@ -779,6 +852,7 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
     if (!c) return PPQ_E_OOM;
     c->device = device;
     c->precision = precision;
+    if (const char *v = std::getenv("PPQ_HPSI")) c->hpsi_variant = std::atoi(v);
     try {
         ck(hipSetDevice(device), "hipSetDevice");
         if (hip_stream) {
@@ -790,7 +864,9 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
         void *p = nullptr;
         ck(hipMalloc(&p, sizeof(KState)), "kstate");
         c->ks = (KState *)p;
-        c->partial = dalloc<double2>((int64_t)RED_BLOCKS * MAXM);
+        c->partial = dalloc<double2>((int64_t)RED_BLOCKS * PSTRIDE_H);
+        c->counter = dalloc<unsigned>(4);
+        ck(hipMemset(c->counter, 0, 4 * sizeof(unsigned)), "counter");
         c->small = dalloc<uint32_t>(4 * MAXD);
         c->count = dalloc<unsigned long long>(2);
         ck(hipHostMalloc((void **)&c->h_small, sizeof(uint32_t) * 4 * MAXD, hipHostMallocDefault), "pinned");
@@ -820,6 +896,7 @@ void ppq_destroy(ppq_ctx *c)
     dfree(c->prefix);
     dfree(c->ks);
     dfree(c->partial);
+    dfree(c->counter);
     dfree(c->small);
     dfree(c->count);
     dfree(c->init_tabs);
@@ -1221,8 +1298,7 @@ int ppq_time_apply(ppq_ctx *c, int nrep, double *ms_per_apply)
         ensure_krylov(c, std::max(c->kv_m, 1));
         const void *x = c->psi[c->cur];
         if (c->precision == PPQ_FP32) {
-            norm2_partial(c->psi[c->cur], c->nact, c->partial, c->stream);
-            reduce_krylov(c->partial, RED_BLOCKS, 1, c->ks, 0, RED_NORM0, 1, c->stream);
+            norm0<float2>(c->psi[c->cur], c->nact, c->partial, c->counter, c->ks, 1, c->stream);
             normalise_from_master<float2>(c->psi[c->cur], c->nact, c->ks, (float2 *)c->Vk, c->stream);
             x = c->Vk;
         }

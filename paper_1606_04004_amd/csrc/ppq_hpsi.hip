@@ -142,6 +142,94 @@ __global__ __launch_bounds__(HB) void k_hpsi_real(const uint32_t *__restrict__ p
 #undef PPQ_BODY
 }
 
+// Accumulating pass with every memory access of the wavefront issued up
+// front: positions, x and the old y of all window digits are loaded before the
+// contraction, so the output loop has no dependent loads.
+template <class R, int W, int NMAX, bool IDENT>
+__device__ __forceinline__ void body_real_acc(uint32_t o, uint64_t m, int ws, const uint32_t *__restrict__ pi,
+                                              const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
+                                              typename Cx<R>::T *__restrict__ y)
+{
+    using C = typename Cx<R>::T;
+    C xw[W], yw[W];
+    uint32_t pw[W];
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+        int j = ws + jj;
+        pw[jj] = 0;
+        if ((m >> j) & 1ull) {
+            uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << j) - 1ull));
+            pw[jj] = IDENT ? pos : pi[pos];
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+        xw[jj] = Cx<R>::make(0, 0);
+        yw[jj] = Cx<R>::make(0, 0);
+        if ((m >> (ws + jj)) & 1ull) {
+            xw[jj] = x[pw[jj]];
+            yw[jj] = y[pw[jj]];
+        }
+    }
+    const R *Tw = T + ws * NMAX + ws;
+#pragma unroll
+    for (int ll = 0; ll < W; ++ll) {
+        R ar = yw[ll].x, ai = yw[ll].y;
+        const R *Tr = Tw + ll * NMAX;
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            R t = Tr[jj];
+            ar = fma(t, xw[jj].x, ar);
+            ai = fma(t, xw[jj].y, ai);
+        }
+        if ((m >> (ws + ll)) & 1ull) y[pw[ll]] = Cx<R>::make(ar, ai);
+    }
+}
+
+template <class R, int NMAX, bool IDENT>
+__global__ __launch_bounds__(HB) void k_hpsi_acc(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
+                                                 const uint64_t *__restrict__ mask, int64_t nf,
+                                                 const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
+                                                 typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
+{
+    if (skip_if && skip_j >= *skip_if) return;
+    int64_t f = (int64_t)blockIdx.x * HB + threadIdx.x;
+    uint64_t m = 0;
+    uint32_t o = 0;
+    if (f < nf) {
+        m = mask[f];
+        o = off[f];
+    }
+    uint64_t wm = wave_or64(m);
+    if (wm == 0) return;
+    int wlo = __ffsll((unsigned long long)wm) - 1;
+    int whi = 63 - __clzll((long long)wm);
+    int width = whi - wlo + 1;
+#define PPQ_BODY(W)                                                        \
+    {                                                                      \
+        int ws = wlo < NMAX - (W) ? wlo : NMAX - (W);                      \
+        body_real_acc<R, W, NMAX, IDENT>(o, m, ws, pi, T, x, y);          \
+        return;                                                            \
+    }
+    if constexpr (NMAX >= 8) {
+        if (width <= 8) PPQ_BODY(8)
+    }
+    if constexpr (NMAX >= 12) {
+        if (width <= 12) PPQ_BODY(12)
+    }
+    if constexpr (NMAX >= 16) {
+        if (width <= 16) PPQ_BODY(16)
+    }
+    if constexpr (NMAX >= 24) {
+        if (width <= 24) PPQ_BODY(24)
+    }
+    if constexpr (NMAX >= 32) {
+        if (width <= 32) PPQ_BODY(32)
+    }
+    PPQ_BODY(NMAX)
+#undef PPQ_BODY
+}
+
 // ---- complex factor (lattice bases), input a linear combination -----------------
 template <class R>
 struct CArgs {
@@ -243,6 +331,112 @@ __global__ __launch_bounds__(HB) void k_hpsi_cplx(const uint32_t *__restrict__ p
 #undef PPQ_BODY
 }
 
+// ---- point-parallel form ----------------------------------------------------
+// One thread per entry of the dimension's permutation (= one output point).
+// A block owns entries [B0, B0+PB); the fibers that straddle its ends are
+// completed from a halo of PH entries on each side (PH >= NMAX - 1 since a
+// fiber has at most n_k members), their values staged in LDS, and each
+// thread contracts its own row of h_k with its fiber: exactly L^2 multiply-
+// adds per fiber, one global load of x and one of y per point.
+constexpr int PB = 256;
+constexpr int PH = 64;
+
+template <class R, int NMAX, bool FIRST, bool IDENT>
+__global__ __launch_bounds__(PB) void k_hpsi_pt(const uint32_t *__restrict__ pi, const uint8_t *__restrict__ info,
+                                                int64_t n, const R *__restrict__ T,
+                                                const typename Cx<R>::T *__restrict__ x, const R *__restrict__ V,
+                                                typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
+{
+    using C = typename Cx<R>::T;
+    if (skip_if && skip_j >= *skip_if) return;
+    __shared__ R sT[NMAX * NMAX];
+    __shared__ uint8_t sinfo[PB + 2 * PH];
+    __shared__ C sx[PB + 2 * PH];
+    __shared__ uint32_t sp[PB + 2 * PH];
+    __shared__ int sS, sE;
+    const int tid = threadIdx.x;
+    const int64_t B0 = (int64_t)blockIdx.x * PB;
+    const int64_t W0 = B0 - PH;
+    for (int i = tid; i < NMAX * NMAX; i += PB) sT[i] = T[i];
+    for (int i = tid; i < PB + 2 * PH; i += PB) {
+        int64_t q = W0 + i;
+        sinfo[i] = (q >= 0 && q < n) ? info[q] : (uint8_t)0x80;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int i = PH;
+        while (i > 0 && !(sinfo[i] & 0x80)) --i;
+        sS = i;
+        int e = PH + PB;
+        while (e < PB + 2 * PH && !(sinfo[e] & 0x80)) ++e;
+        sE = e;
+    }
+    __syncthreads();
+    const int S = sS, E = sE;
+    for (int i = S + tid; i < E; i += PB) {
+        int64_t q = W0 + i;
+        if (q < n) {
+            uint32_t p = IDENT ? (uint32_t)q : pi[q];
+            sp[i] = p;
+            sx[i] = x[p];
+        }
+    }
+    __syncthreads();
+    const int64_t q = B0 + tid;
+    if (q >= n) return;
+    const int i = PH + tid;
+    int fs = i;
+    while (!(sinfo[fs] & 0x80)) --fs;
+    int fe = i + 1;
+    while (fe < E && !(sinfo[fe] & 0x80)) ++fe;
+    const R *Tr = sT + (sinfo[i] & 63) * NMAX;
+    R ar = 0, ai = 0;
+    for (int j = fs; j < fe; ++j) {
+        R t = Tr[sinfo[j] & 63];
+        C v = sx[j];
+        ar = fma(t, v.x, ar);
+        ai = fma(t, v.y, ai);
+    }
+    const uint32_t p = sp[i];
+    if (FIRST) {
+        R vv = V[p];
+        C xv = sx[i];
+        y[p] = Cx<R>::make(fma(vv, xv.x, ar), fma(vv, xv.y, ai));
+    } else {
+        C o2 = y[p];
+        y[p] = Cx<R>::make(o2.x + ar, o2.y + ai);
+    }
+}
+
+template <class R>
+void launch_pt(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, const R *T, const typename Cx<R>::T *x,
+               const R *V, typename Cx<R>::T *y, bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (n <= 0) return;
+    unsigned nb = (unsigned)((n + PB - 1) / PB);
+    bool ident = pi == nullptr;
+#define L(NM, F, I) \
+    hipLaunchKernelGGL((k_hpsi_pt<R, NM, F, I>), dim3(nb), dim3(PB), 0, s, pi, info, n, T, x, V, y, skip_if, skip_j)
+#define DISPATCH(NM)                   \
+    if (first) {                       \
+        if (ident) L(NM, true, true);  \
+        else L(NM, true, false);       \
+    } else {                           \
+        if (ident) L(NM, false, true); \
+        else L(NM, false, false);      \
+    }
+    switch (nmax) {
+    case 8: DISPATCH(8) break;
+    case 16: DISPATCH(16) break;
+    case 24: DISPATCH(24) break;
+    case 32: DISPATCH(32) break;
+    case 48: DISPATCH(48) break;
+    default: DISPATCH(64) break;
+    }
+#undef DISPATCH
+#undef L
+}
+
 inline unsigned fblocks(int64_t nf)
 {
     int64_t b = (nf + HB - 1) / HB;
@@ -308,6 +502,49 @@ void hpsi_real_f64(const FiberPass &fp, const double *T, const double2 *x, const
                    const int *skip_if, int skip_j, hipStream_t s)
 {
     launch_real<double>(fp, T, x, V, y, first, skip_if, skip_j, s);
+}
+
+void hpsi_pt_f64(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, const double *T, const double2 *x,
+                 const double *V, double2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_pt<double>(pi, info, n, nmax, T, x, V, y, first, skip_if, skip_j, s);
+}
+
+void hpsi_pt_f32(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, const float *T, const float2 *x,
+                 const float *V, float2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_pt<float>(pi, info, n, nmax, T, x, V, y, first, skip_if, skip_j, s);
+}
+
+template <class R>
+void launch_acc(const FiberPass &fp, const R *T, const typename Cx<R>::T *x, typename Cx<R>::T *y, const int *skip_if,
+                int skip_j, hipStream_t s)
+{
+    if (fp.nf <= 0) return;
+#define L(NM)                                                                                                  \
+    hipLaunchKernelGGL((k_hpsi_acc<R, NM, false>), dim3((unsigned)((fp.nf + HB - 1) / HB)), dim3(HB), 0, s, fp.pi, \
+                       fp.off, fp.mask, fp.nf, T, x, y, skip_if, skip_j)
+    switch (fp.nmax) {
+    case 8: L(8); break;
+    case 16: L(16); break;
+    case 24: L(24); break;
+    case 32: L(32); break;
+    case 48: L(48); break;
+    default: L(64); break;
+    }
+#undef L
+}
+
+void hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double2 *y, const int *skip_if, int skip_j,
+                  hipStream_t s)
+{
+    launch_acc<double>(fp, T, x, y, skip_if, skip_j, s);
+}
+
+void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
+                  hipStream_t s)
+{
+    launch_acc<float>(fp, T, x, y, skip_if, skip_j, s);
 }
 
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,

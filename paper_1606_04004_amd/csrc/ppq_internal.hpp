@@ -14,6 +14,7 @@ constexpr int MAXD = 8;
 constexpr int MAXM = 16;        // largest Krylov order
 constexpr int NMAX_FIBER = 64;  // largest 1D basis (fiber masks are 64-bit)
 constexpr int RED_BLOCKS = 1024;  // blocks of the fixed-shape reductions
+constexpr int PSTRIDE_H = MAXM + 4;  // partial sums per block (matches the kernels)
 
 // Grid geometry passed by value to kernels.
 struct GridDesc {
@@ -33,6 +34,7 @@ struct PotDesc {
     const double *coef;   // [nterm]
     const int *tab;       // [nterm][D]: table index or -1
     const double *tabs;   // [ntab][nmax]
+    int ntab;
 };
 
 // Device state of one Krylov step.
@@ -73,11 +75,13 @@ void mark_keys(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s);
 
 // fiber tables
 void last_flags(const uint32_t *keys, int64_t n, int nlast, uint32_t *flags, hipStream_t s);
+void last_info(const uint32_t *keys, int64_t n, int nlast, uint8_t *info, hipStream_t s);
 void last_fill(const uint32_t *keys, int64_t n, int nlast, const uint32_t *flags, const uint32_t *fidx,
                const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s);
 void rot_set(const uint32_t *keys, int64_t n, int k, const GridDesc &g, uint64_t *bm, hipStream_t s);
 void rot_rank(const uint32_t *keys, int64_t n, int k, const GridDesc &g, const uint64_t *bm,
-              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, hipStream_t s);
+              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,
+              hipStream_t s);
 void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
               const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s);
 
@@ -103,6 +107,16 @@ struct CInput {
 };
 void hpsi_cplx_f64(const FiberPass &fp, const double2 *H, const CInput &in, double2 *y, bool accumulate,
                    const double *V, const int *skip_if, int skip_j, hipStream_t s);
+// point-parallel form: info[q] = digit | 0x80 at the first member of each fiber
+void hpsi_pt_f64(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, const double *T, const double2 *x,
+                 const double *V, double2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_pt_f32(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, const float *T, const float2 *x,
+                 const float *V, float2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
+// accumulating pass (y += P h P x) with all loads issued before the contraction
+void hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double2 *y, const int *skip_if, int skip_j,
+                  hipStream_t s);
+void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
+                  hipStream_t s);
 // FP32 forms
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);
@@ -114,30 +128,27 @@ struct CInput32 {
 void hpsi_cplx_f32(const FiberPass &fp, const float2 *H, const CInput32 &in, float2 *y, bool accumulate,
                    const float *V, const int *skip_if, int skip_j, hipStream_t s);
 
-// Krylov vector kernels. V_i = Vb + i*ld (elements). T is double2 or float2.
+// Krylov vector kernels. V_i = Vb + i*ld (elements); C is double2 or float2.
+// Reductions end in the last block to finish, which sums the per-block
+// partials in a fixed order (run-to-run deterministic) and updates KState.
+enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3 };
 template <class C>
-void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, const int *meff, int j,
-              hipStream_t s);
+void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, hipStream_t s);
 template <class C>
-void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, const double2 *h, double2 *partial,
-                     const int *meff, int j, hipStream_t s);
+void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
+              int j, int m, int ioff, hipStream_t s);
 template <class C>
-void cgs_update_norm(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const double2 *h,
-                     double2 *partial, const int *meff, int j, hipStream_t s);
+void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, double2 *partial, unsigned *counter,
+                     KState *ks, int j, int m, bool with_norm, hipStream_t s);
 template <class C>
-void scale_vec(C *v, int64_t n, const double *inv, const int *meff, int j, hipStream_t s);
+void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,
+                      hipStream_t s);
 template <class C>
 void normalise_from_master(const double2 *psi, int64_t n, KState *ks, C *v0, hipStream_t s);
 template <class C>
-void lincomb(const C *Vb, int64_t ld, int nv, const double2 *psi_master, int64_t n, const KState *ks,
-             double2 *psi_out, hipStream_t s);
-
-// finalisers (one block): sum partial[nb][nv] in a fixed order
-enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3 };
-void reduce_krylov(const double2 *partial, int nblocks, int nv, KState *ks, int j, int mode, int m,
-                   hipStream_t s, int ioff = 0);
+void lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, const KState *ks, double2 *psi_out,
+             hipStream_t s);
 void krylov_expv(KState *ks, int m, double dt, int hermitian, hipStream_t s);
-void norm2_partial(const double2 *psi, int64_t n, double2 *partial, hipStream_t s);
 
 // observables
 void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, const double2 *bra,

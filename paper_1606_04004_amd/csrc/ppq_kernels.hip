@@ -8,6 +8,7 @@ namespace ppq {
 namespace {
 
 constexpr int TB = 256;  // threads per block for streaming kernels
+constexpr int PSTRIDE = MAXM + 4;  // partial sums per block
 
 __device__ inline int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
@@ -34,30 +35,60 @@ __device__ inline void set_bit(uint64_t *bm, uint32_t key)
     atomicOr((unsigned long long *)&bm[key >> 6], 1ull << (key & 63));
 }
 
-__device__ inline void set_with_neighbours(const GridDesc &g, uint64_t *bm, uint32_t key)
+// Sets bit `key` for every lane with `valid`; all 64 lanes of the wavefront
+// must call it together.  Lanes that target the same word are merged by a
+// segmented OR across neighbouring lanes, so one atomic per run of lanes
+// hitting one word is issued (sorted keys put most of a wavefront's targets
+// in a few words).
+__device__ inline void set_bit_wave(uint64_t *bm, uint32_t key, bool valid)
 {
-    set_bit(bm, key);
+    const int lane = threadIdx.x & 63;
+    uint32_t w = valid ? (key >> 6) : 0xffffffffu;
+    uint64_t bits = valid ? (1ull << (key & 63)) : 0ull;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t ow = __shfl_up(w, d, 64);
+        uint32_t olo = __shfl_up((uint32_t)bits, d, 64);
+        uint32_t ohi = __shfl_up((uint32_t)(bits >> 32), d, 64);
+        if (lane >= d && ow == w) bits |= ((uint64_t)ohi << 32) | olo;
+    }
+    uint32_t nw = __shfl_down(w, 1, 64);
+    bool last = (lane == 63) || (nw != w);
+    if (valid && last) atomicOr((unsigned long long *)&bm[w], (unsigned long long)bits);
+}
+
+// Marks `key` and its radius-1 neighbours for lanes with `keep` (wave-collective).
+__device__ inline void set_with_neighbours(const GridDesc &g, uint64_t *bm, uint32_t key, bool keep)
+{
+    set_bit_wave(bm, key, keep);
     for (int k = 0; k < g.D; ++k) {
         uint32_t sk = g.stride[k];
         int d = (int)((key / sk) % (uint32_t)g.n[k]);
         if (g.lat_s[k] == 0) {
-            if (d > 0) set_bit(bm, key - sk);
-            if (d + 1 < g.n[k]) set_bit(bm, key + sk);
+            set_bit_wave(bm, key - sk, keep && d > 0);
+            set_bit_wave(bm, key + sk, keep && d + 1 < g.n[k]);
         } else {
             int nl = g.lat_l[k];
             int si = d / nl, l = d % nl;
-            if (si > 0) set_bit(bm, key - (uint32_t)nl * sk);
-            if (si + 1 < g.lat_s[k]) set_bit(bm, key + (uint32_t)nl * sk);
-            if (l > 0) set_bit(bm, key - sk);
-            if (l + 1 < nl) set_bit(bm, key + sk);
+            set_bit_wave(bm, key - (uint32_t)nl * sk, keep && si > 0);
+            set_bit_wave(bm, key + (uint32_t)nl * sk, keep && si + 1 < g.lat_s[k]);
+            set_bit_wave(bm, key - sk, keep && l > 0);
+            set_bit_wave(bm, key + sk, keep && l + 1 < nl);
         }
     }
 }
 
+// Counts `pred` over the block and adds the block's total with one atomic
+// (integer, so the sum is order-independent).  Block-collective.
 __device__ inline void count_ballot(bool pred, unsigned long long *counter)
 {
+    __shared__ unsigned s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0u;
+    __syncthreads();
     uint64_t b = __ballot(pred);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(counter, (unsigned long long)__popcll(b));
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&s_cnt, (unsigned)__popcll(b));
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(counter, (unsigned long long)s_cnt);
 }
 
 // ---- scan ------------------------------------------------------------------
@@ -177,15 +208,19 @@ __global__ void k_fill(T *p, int64_t n, T v)
 __global__ void k_init_flag(GridDesc g, const double2 *tabs, int nmax, double eps2, uint64_t *bm,
                             unsigned long long *nabove)
 {
-    for (int64_t i = gid(); i < (int64_t)g.total; i += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t key = (uint32_t)i;
+    // wave-uniform trip count: every lane runs every iteration
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < (int64_t)g.total;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = base + threadIdx.x;
+        bool inside = i < (int64_t)g.total;
+        uint32_t key = inside ? (uint32_t)i : 0u;
         double2 v = make_double2(1.0, 0.0);
         for (int k = 0; k < g.D; ++k) {
             int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
             v = cmul_rn(v, tabs[k * nmax + d]);
         }
-        bool keep = above_eps(v, eps2);
-        if (keep) set_with_neighbours(g, bm, key);
+        bool keep = inside && above_eps(v, eps2);
+        set_with_neighbours(g, bm, key, keep);
         count_ballot(keep, nabove);
     }
 }
@@ -209,10 +244,12 @@ __global__ void k_dilate(const uint32_t *keys, const double2 *psi, int64_t n, Gr
 {
     int64_t p = gid();
     bool keep = false;
+    uint32_t key = 0;
     if (p < n) {
+        key = keys[p];
         keep = above_eps(psi[p], eps2);
-        if (keep) set_with_neighbours(g, bm, keys[p]);
     }
+    set_with_neighbours(g, bm, key, keep);
     count_ballot(keep, nabove);
 }
 
@@ -258,6 +295,14 @@ __global__ void k_last_flags(const uint32_t *keys, int64_t n, int nl, uint32_t *
     flags[p] = (p == 0 || keys[p] / (uint32_t)nl != keys[p - 1] / (uint32_t)nl) ? 1u : 0u;
 }
 
+__global__ void k_last_info(const uint32_t *keys, int64_t n, int nl, uint8_t *info)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    bool start = (p == 0 || keys[p] / (uint32_t)nl != keys[p - 1] / (uint32_t)nl);
+    info[p] = (uint8_t)((keys[p] % (uint32_t)nl) | (start ? 0x80u : 0u));
+}
+
 __global__ void k_last_fill(const uint32_t *keys, int64_t n, int nl, const uint32_t *flags, const uint32_t *fidx,
                             const uint32_t *nf, uint32_t *off, uint64_t *mask)
 {
@@ -293,13 +338,13 @@ __device__ inline uint64_t extract_bits(const uint64_t *bm, uint32_t base, int l
 __global__ void k_rot_set(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, uint64_t *bm)
 {
     int64_t p = gid();
-    if (p >= n) return;
-    uint32_t d;
-    set_bit(bm, rotate_key(keys[p], sk, nk, &d));
+    uint32_t d, rk = 0;
+    if (p < n) rk = rotate_key(keys[p], sk, nk, &d);
+    set_bit_wave(bm, rk, p < n);
 }
 
 __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, const uint64_t *bm,
-                           const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask)
+                           const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, uint8_t *info)
 {
     int64_t p = gid();
     if (p >= n) return;
@@ -312,6 +357,7 @@ __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_
     bool start = (m & ((1ull << d) - 1ull)) == 0;
     flags[q] = start ? 1u : 0u;
     if (start) tmpmask[q] = m;
+    info[q] = (uint8_t)(d | (start ? 0x80u : 0u));
 }
 
 __global__ void k_fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
@@ -326,19 +372,54 @@ __global__ void k_fib_fill(const uint32_t *flags, const uint32_t *fidx, const ui
 }
 
 // ---- potential cache -----------------------------------------------------------
-__global__ void k_potential(const uint32_t *keys, int64_t n, GridDesc g, PotDesc pd, double *V, float *Vf)
+// Potential cache: V_I = sum_t coef_t prod_f tab_{t,f}[digit_{dim_{t,f}}(I)].
+// Term descriptors and the (deduplicated) 1D tables are staged in LDS.
+constexpr int POT_MAX_TERMS = 256;
+constexpr int POT_MAX_TAB = 1024;
+constexpr int POT_MAX_FAC = 4;
+
+__device__ inline int select_digit(const int (&d)[MAXD], int k)
 {
+    int r = d[0];
+#pragma unroll
+    for (int i = 1; i < MAXD; ++i) r = (k == i) ? d[i] : r;
+    return r;
+}
+
+__global__ __launch_bounds__(TB) void k_potential(const uint32_t *keys, int64_t n, GridDesc g, PotDesc pd, double *V,
+                                                  float *Vf)
+{
+    __shared__ double s_coef[POT_MAX_TERMS];
+    __shared__ int s_nf[POT_MAX_TERMS];
+    __shared__ int s_fac[POT_MAX_TERMS][POT_MAX_FAC];  // (table index << 4) | dim
+    __shared__ double s_tab[POT_MAX_TAB];
+    for (int t = threadIdx.x; t < pd.nterm; t += TB) {
+        s_coef[t] = pd.coef[t];
+        int nf = 0;
+        for (int k = 0; k < g.D; ++k) {
+            int ti = pd.tab[t * pd.D + k];
+            if (ti >= 0 && nf < POT_MAX_FAC) s_fac[t][nf++] = (ti << 4) | k;
+        }
+        s_nf[t] = nf;
+    }
+    for (int i = threadIdx.x; i < pd.ntab * pd.nmax; i += TB) s_tab[i] = pd.tabs[i];
+    __syncthreads();
     int64_t p = gid();
     if (p >= n) return;
     uint32_t key = keys[p];
     int d[MAXD];
-    for (int k = 0; k < g.D; ++k) d[k] = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) d[k] = (k < g.D) ? (int)((key / g.stride[k]) % (uint32_t)g.n[k]) : 0;
     double v = 0.0;
     for (int t = 0; t < pd.nterm; ++t) {
-        double f = pd.coef[t];
-        for (int k = 0; k < g.D; ++k) {
-            int ti = pd.tab[t * pd.D + k];
-            if (ti >= 0) f *= pd.tabs[(int64_t)ti * pd.nmax + d[k]];
+        double f = s_coef[t];
+        const int nf = s_nf[t];
+#pragma unroll
+        for (int j = 0; j < POT_MAX_FAC; ++j) {
+            if (j < nf) {
+                int e = s_fac[t][j];
+                f *= s_tab[(e >> 4) * pd.nmax + select_digit(d, e & 15)];
+            }
         }
         v += f;
     }
@@ -385,15 +466,101 @@ __device__ inline void block_reduce_store(double2 (&acc)[NV], double2 *partial)
             s.x += red[ww][threadIdx.x].x;
             s.y += red[ww][threadIdx.x].y;
         }
-        partial[(int64_t)blockIdx.x * MAXM + threadIdx.x] = s;
+        partial[(int64_t)blockIdx.x * PSTRIDE + threadIdx.x] = s;
     }
+}
+
+// Final reduction of the per-block partials [nb][PSTRIDE] by one block: every
+// value at once, each thread a fixed subset of blocks, then a fixed tree
+// (run-to-run deterministic); then the finaliser `mode` updates KState.
+// (A separate launch: a device-scope fence per block to let the last block
+// finish the sum would write back the L2 of every XCD.)
+template <int NV>
+__global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb, KState *ks, int j, int mode, int m,
+                                                 int ioff, int nvals)
+{
+    if (mode != RED_NORM0 && j >= ks->meff) return;
+    double2 tot[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tot[i] = make_double2(0.0, 0.0);
+    for (int b = threadIdx.x; b < nb; b += TB) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double2 v = partial[(int64_t)b * PSTRIDE + i];
+            tot[i].x += v.x;
+            tot[i].y += v.y;
+        }
+    }
+    __shared__ double2 vals[TB / 64][NV];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double2 v = tot[i];
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            v.x += __shfl_xor(v.x, s, 64);
+            v.y += __shfl_xor(v.y, s, 64);
+        }
+        if (lane == 0) vals[wv][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double2 r[NV];
+    for (int i = 0; i < NV; ++i) {
+        r[i] = vals[0][i];
+        for (int w2 = 1; w2 < TB / 64; ++w2) {
+            r[i].x += vals[w2][i].x;
+            r[i].y += vals[w2][i].y;
+        }
+    }
+    if (mode == RED_NORM0) {
+        ks->n0 = sqrt(r[0].x);
+        ks->meff = m;
+    } else if (mode == RED_H1) {
+        for (int i = 0; i < nvals; ++i) {
+            ks->h1[(i + ioff) * MAXM + j] = r[i];
+            if (i + ioff == j) ks->alpha[j] = r[i].x;
+        }
+    } else {  // RED_H2 (+ beta from |w'|^2 - sum |h2_i|^2 when RED_BETA)
+        int nh = (mode == RED_BETA) ? nvals - 1 : nvals;
+        double hh = 0.0;
+        for (int i = 0; i < nh; ++i) {
+            ks->h2[i * MAXM + j] = r[i];
+            hh += r[i].x * r[i].x + r[i].y * r[i].y;
+        }
+        if (mode == RED_BETA) {
+            double b2 = r[nh].x - hh;
+            double b = sqrt(b2 > 0.0 ? b2 : 0.0);
+            ks->beta[j] = b;
+            if (j < m - 1) {
+                if (b < 1e-13) {
+                    ks->meff = j + 1;
+                    ks->inv_beta = 0.0;
+                } else {
+                    ks->inv_beta = 1.0 / b;
+                }
+            }
+        }
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(TB) void k_norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter,
+                                              KState *ks, int m)
+{
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 a = psi[p];
+        acc[0].x = fma(a.x, a.x, fma(a.y, a.y, acc[0].x));
+    }
+    block_reduce_store<1>(acc, partial);
 }
 
 template <class C, int NV>
 __global__ __launch_bounds__(TB) void k_cgs_dots(const C *Vb, int64_t ld, const C *w, int64_t n, double2 *partial,
-                                                 const int *meff, int j)
+                                                 unsigned *counter, KState *ks, int j, int m, int ioff)
 {
-    if (meff && j >= *meff) return;
+    if (j >= ks->meff) return;
     double2 acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = make_double2(0.0, 0.0);
@@ -405,17 +572,18 @@ __global__ __launch_bounds__(TB) void k_cgs_dots(const C *Vb, int64_t ld, const 
     block_reduce_store<NV>(acc, partial);
 }
 
+// w <- w - sum_i h1_i v_i; h2_i = <v_i|w>; with_norm: also |w|^2 and beta
 template <class C, int NV>
-__global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld, C *w, int64_t n,
-                                                        const double2 *h, double2 *partial, const int *meff, int j)
+__global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld, C *w, int64_t n, double2 *partial,
+                                                        unsigned *counter, KState *ks, int j, int m, int with_norm)
 {
-    if (meff && j >= *meff) return;
+    if (j >= ks->meff) return;
     double2 hc[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hc[i] = h[i * MAXM + j];
-    double2 acc[NV];
+    for (int i = 0; i < NV; ++i) hc[i] = ks->h1[i * MAXM + j];
+    double2 acc[NV + 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int i = 0; i <= NV; ++i) acc[i] = make_double2(0.0, 0.0);
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
         double2 wv = ld2(w, p);
         double2 vv[NV];
@@ -429,19 +597,21 @@ __global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld,
         double2 wr = ld2(w, p);  // dots against the stored (possibly rounded) vector
 #pragma unroll
         for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], wr);
+        acc[NV].x = fma(wr.x, wr.x, fma(wr.y, wr.y, acc[NV].x));
     }
-    block_reduce_store<NV>(acc, partial);
+    block_reduce_store<NV + 1>(acc, partial);
 }
 
+// out = (w - sum_i h2_i v_i) / beta
 template <class C, int NV>
-__global__ __launch_bounds__(TB) void k_cgs_update_norm(const C *Vb, int64_t ld, const C *w, C *out, int64_t n,
-                                                        const double2 *h, double2 *partial, const int *meff, int j)
+__global__ __launch_bounds__(TB) void k_cgs_update_scale(const C *Vb, int64_t ld, const C *w, C *out, int64_t n,
+                                                         const KState *ks, int j)
 {
-    if (meff && j >= *meff) return;
+    if (j + 1 >= ks->meff) return;
     double2 hc[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hc[i] = h[i * MAXM + j];
-    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int i = 0; i < NV; ++i) hc[i] = ks->h2[i * MAXM + j];
+    const double s = ks->inv_beta;
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
         double2 wv = ld2(w, p);
 #pragma unroll
@@ -450,21 +620,7 @@ __global__ __launch_bounds__(TB) void k_cgs_update_norm(const C *Vb, int64_t ld,
             wv.x -= hc[i].x * vv.x - hc[i].y * vv.y;
             wv.y -= hc[i].x * vv.y + hc[i].y * vv.x;
         }
-        st2(out, p, wv);
-        double2 wr = ld2(out, p);
-        acc[0].x = fma(wr.x, wr.x, fma(wr.y, wr.y, acc[0].x));
-    }
-    block_reduce_store<1>(acc, partial);
-}
-
-template <class C>
-__global__ void k_scale(C *v, int64_t n, const double *inv, const int *meff, int j)
-{
-    if (meff && j >= *meff) return;
-    double s = *inv;
-    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        double2 a = ld2(v, p);
-        st2(v, p, make_double2(a.x * s, a.y * s));
+        st2(out, p, make_double2(wv.x * s, wv.y * s));
     }
 }
 
@@ -479,7 +635,7 @@ __global__ void k_normalise(const double2 *psi, int64_t n, const KState *ks, C *
 }
 
 template <class C>
-__global__ void k_lincomb(const C *Vb, int64_t ld, int nv, const double2 *psi_master, int64_t n, const KState *ks,
+__global__ void k_lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, const KState *ks,
                           double2 *out)
 {
     int meff = ks->meff;
@@ -502,55 +658,6 @@ __global__ void k_lincomb(const C *Vb, int64_t ld, int nv, const double2 *psi_ma
             }
         }
         out[p] = acc;
-    }
-    (void)nv;
-}
-
-// Fixed-order final reduction of per-block partials [nb][MAXM].
-__global__ __launch_bounds__(TB) void k_reduce_krylov(const double2 *partial, int nb, int nv, KState *ks, int j,
-                                                      int mode, int m, int ioff)
-{
-    if (mode != RED_NORM0 && j >= ks->meff) return;
-    __shared__ double2 red[TB];
-    for (int i = 0; i < nv; ++i) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int b = threadIdx.x; b < nb; b += TB) {
-            s.x += partial[(int64_t)b * MAXM + i].x;
-            s.y += partial[(int64_t)b * MAXM + i].y;
-        }
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int st = TB / 2; st >= 1; st >>= 1) {
-            if ((int)threadIdx.x < st) {
-                red[threadIdx.x].x += red[threadIdx.x + st].x;
-                red[threadIdx.x].y += red[threadIdx.x + st].y;
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            double2 r = red[0];
-            if (mode == RED_NORM0) {
-                ks->n0 = sqrt(r.x);
-                ks->meff = m;
-            } else if (mode == RED_H1) {
-                ks->h1[(i + ioff) * MAXM + j] = r;
-                if (i + ioff == j) ks->alpha[j] = r.x;
-            } else if (mode == RED_H2) {
-                ks->h2[(i + ioff) * MAXM + j] = r;
-            } else {  // RED_BETA
-                double b = sqrt(r.x);
-                ks->beta[j] = b;
-                if (j < m - 1) {
-                    if (b < 1e-13) {
-                        ks->meff = j + 1;
-                        ks->inv_beta = 0.0;
-                    } else {
-                        ks->inv_beta = 1.0 / b;
-                    }
-                }
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -586,7 +693,8 @@ __global__ __launch_bounds__(256) void k_krylov_expv(KState *ks, double dt, int 
     __syncthreads();
     if (threadIdx.x < MAXM) {
         double s = 0.0;
-        for (int cc = 0; cc < MAXM; ++cc) s += sqrt(A[threadIdx.x][cc].x * A[threadIdx.x][cc].x + A[threadIdx.x][cc].y * A[threadIdx.x][cc].y);
+        for (int cc = 0; cc < MAXM; ++cc)
+            s += sqrt(A[threadIdx.x][cc].x * A[threadIdx.x][cc].x + A[threadIdx.x][cc].y * A[threadIdx.x][cc].y);
         rown[threadIdx.x] = s;
     }
     __syncthreads();
@@ -636,16 +744,6 @@ __global__ __launch_bounds__(256) void k_krylov_expv(KState *ks, double dt, int 
     }
 }
 
-__global__ __launch_bounds__(TB) void k_norm2_partial(const double2 *psi, int64_t n, double2 *partial)
-{
-    double2 acc[1] = {make_double2(0.0, 0.0)};
-    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
-        double2 a = psi[p];
-        acc[0].x = fma(a.x, a.x, fma(a.y, a.y, acc[0].x));
-    }
-    block_reduce_store<1>(acc, partial);
-}
-
 __global__ __launch_bounds__(TB) void k_dot_partial(const double2 *a, const double2 *b, int64_t n,
                                                     double2 *partial)
 {
@@ -680,8 +778,8 @@ __global__ __launch_bounds__(TB) void k_obs_final(const double2 *partial, int nb
     for (int i = 0; i < 3; ++i) {
         double2 s = make_double2(0.0, 0.0);
         for (int b = threadIdx.x; b < nb; b += TB) {
-            s.x += partial[(int64_t)b * MAXM + i].x;
-            s.y += partial[(int64_t)b * MAXM + i].y;
+            s.x += partial[(int64_t)b * PSTRIDE + i].x;
+            s.y += partial[(int64_t)b * PSTRIDE + i].y;
         }
         red[threadIdx.x] = s;
         __syncthreads();
@@ -711,7 +809,7 @@ __global__ __launch_bounds__(TB) void k_energy_from_dot(const double2 *partial, 
 {
     __shared__ double red[TB];
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += TB) s += partial[(int64_t)b * MAXM].x;
+    for (int b = threadIdx.x; b < nb; b += TB) s += partial[(int64_t)b * PSTRIDE].x;
     red[threadIdx.x] = s;
     __syncthreads();
     for (int st = TB / 2; st >= 1; st >>= 1) {
@@ -810,11 +908,17 @@ void rot_set(const uint32_t *keys, int64_t n, int k, const GridDesc &g, uint64_t
     hipLaunchKernelGGL(k_rot_set, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g.stride[k], (uint32_t)g.n[k], bm);
 }
 void rot_rank(const uint32_t *keys, int64_t n, int k, const GridDesc &g, const uint64_t *bm,
-              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, hipStream_t s)
+              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,
+              hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_rot_rank, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g.stride[k], (uint32_t)g.n[k], bm,
-                       prefix, pi, flags, tmpmask);
+                       prefix, pi, flags, tmpmask, info);
+}
+void last_info(const uint32_t *keys, int64_t n, int nlast, uint8_t *info, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_last_info, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, nlast, info);
 }
 void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n, const uint32_t *nf,
               uint32_t *off, uint64_t *mask, hipStream_t s)
@@ -858,37 +962,42 @@ static unsigned red_blocks(int64_t n)
     }
 
 template <class C>
-void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, const int *meff, int j,
-              hipStream_t s)
+void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, hipStream_t s)
 {
-#define CALL(NV) hipLaunchKernelGGL((k_cgs_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, meff, j)
-    PPQ_NV_SWITCH(nv, CALL)
-#undef CALL
+    hipLaunchKernelGGL(k_norm0<C>, dim3(RED_BLOCKS), dim3(TB), 0, s, psi, n, partial, counter, ks, m);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, 0, (int)RED_NORM0, m, 0, 1);
 }
 template <class C>
-void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, const double2 *h, double2 *partial,
-                     const int *meff, int j, hipStream_t s)
-{
-#define CALL(NV) \
-    hipLaunchKernelGGL((k_cgs_update_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, h, partial, meff, j)
-    PPQ_NV_SWITCH(nv, CALL)
-#undef CALL
-}
-template <class C>
-void cgs_update_norm(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const double2 *h,
-                     double2 *partial, const int *meff, int j, hipStream_t s)
+void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
+              int j, int m, int ioff, hipStream_t s)
 {
 #define CALL(NV)                                                                                                  \
-    hipLaunchKernelGGL((k_cgs_update_norm<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, out, n, h, partial, \
-                       meff, j)
+    hipLaunchKernelGGL((k_cgs_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, counter, ks, j, \
+                       m, ioff);                                                                              \
+    hipLaunchKernelGGL(k_finalize<NV>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, (int)RED_H1, m, ioff, NV)
     PPQ_NV_SWITCH(nv, CALL)
 #undef CALL
 }
 template <class C>
-void scale_vec(C *v, int64_t n, const double *inv, const int *meff, int j, hipStream_t s)
+void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, double2 *partial, unsigned *counter,
+                     KState *ks, int j, int m, bool with_norm, hipStream_t s)
+{
+#define CALL(NV)                                                                                                    \
+    hipLaunchKernelGGL((k_cgs_update_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, counter, \
+                       ks, j, m, with_norm ? 1 : 0);                                                            \
+    hipLaunchKernelGGL(k_finalize<NV + 1>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j,                  \
+                       with_norm ? (int)RED_BETA : (int)RED_H2, m, 0, with_norm ? NV + 1 : NV)
+    PPQ_NV_SWITCH(nv, CALL)
+#undef CALL
+}
+template <class C>
+void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,
+                      hipStream_t s)
 {
     unsigned b = red_blocks(n) * 4;
-    hipLaunchKernelGGL(k_scale<C>, dim3(b), dim3(TB), 0, s, v, n, inv, meff, j);
+#define CALL(NV) hipLaunchKernelGGL((k_cgs_update_scale<C, NV>), dim3(b), dim3(TB), 0, s, Vb, ld, w, out, n, ks, j)
+    PPQ_NV_SWITCH(nv, CALL)
+#undef CALL
 }
 template <class C>
 void normalise_from_master(const double2 *psi, int64_t n, KState *ks, C *v0, hipStream_t s)
@@ -897,47 +1006,31 @@ void normalise_from_master(const double2 *psi, int64_t n, KState *ks, C *v0, hip
     hipLaunchKernelGGL(k_normalise<C>, dim3(b), dim3(TB), 0, s, psi, n, ks, v0);
 }
 template <class C>
-void lincomb(const C *Vb, int64_t ld, int nv, const double2 *psi_master, int64_t n, const KState *ks,
-             double2 *psi_out, hipStream_t s)
+void lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, const KState *ks, double2 *psi_out,
+             hipStream_t s)
 {
     unsigned b = red_blocks(n) * 4;
-    hipLaunchKernelGGL(k_lincomb<C>, dim3(b), dim3(TB), 0, s, Vb, ld, nv, psi_master, n, ks, psi_out);
+    hipLaunchKernelGGL(k_lincomb<C>, dim3(b), dim3(TB), 0, s, Vb, ld, psi_master, n, ks, psi_out);
 }
 
-template void cgs_dots<double2>(const double2 *, int64_t, int, const double2 *, int64_t, double2 *, const int *, int,
-                                hipStream_t);
-template void cgs_dots<float2>(const float2 *, int64_t, int, const float2 *, int64_t, double2 *, const int *, int,
-                               hipStream_t);
-template void cgs_update_dots<double2>(const double2 *, int64_t, int, double2 *, int64_t, const double2 *, double2 *,
-                                       const int *, int, hipStream_t);
-template void cgs_update_dots<float2>(const float2 *, int64_t, int, float2 *, int64_t, const double2 *, double2 *,
-                                      const int *, int, hipStream_t);
-template void cgs_update_norm<double2>(const double2 *, int64_t, int, const double2 *, double2 *, int64_t,
-                                       const double2 *, double2 *, const int *, int, hipStream_t);
-template void cgs_update_norm<float2>(const float2 *, int64_t, int, const float2 *, float2 *, int64_t,
-                                      const double2 *, double2 *, const int *, int, hipStream_t);
-template void scale_vec<double2>(double2 *, int64_t, const double *, const int *, int, hipStream_t);
-template void scale_vec<float2>(float2 *, int64_t, const double *, const int *, int, hipStream_t);
-template void normalise_from_master<double2>(const double2 *, int64_t, KState *, double2 *, hipStream_t);
-template void normalise_from_master<float2>(const double2 *, int64_t, KState *, float2 *, hipStream_t);
-template void lincomb<double2>(const double2 *, int64_t, int, const double2 *, int64_t, const KState *, double2 *,
-                               hipStream_t);
-template void lincomb<float2>(const float2 *, int64_t, int, const double2 *, int64_t, const KState *, double2 *,
-                              hipStream_t);
+#define PPQ_INST(C)                                                                                               \
+    template void norm0<C>(const double2 *, int64_t, double2 *, unsigned *, KState *, int, hipStream_t);          \
+    template void cgs_dots<C>(const C *, int64_t, int, const C *, int64_t, double2 *, unsigned *, KState *, int,  \
+                              int, int, hipStream_t);                                                           \
+    template void cgs_update_dots<C>(const C *, int64_t, int, C *, int64_t, double2 *, unsigned *, KState *, int, \
+                                     int, bool, hipStream_t);                                                   \
+    template void cgs_update_scale<C>(const C *, int64_t, int, const C *, C *, int64_t, const KState *, int,      \
+                                      hipStream_t);                                                             \
+    template void normalise_from_master<C>(const double2 *, int64_t, KState *, C *, hipStream_t);                 \
+    template void lincomb<C>(const C *, int64_t, const double2 *, int64_t, const KState *, double2 *, hipStream_t);
+PPQ_INST(double2)
+PPQ_INST(float2)
+#undef PPQ_INST
 
-void reduce_krylov(const double2 *partial, int nblocks_, int nv, KState *ks, int j, int mode, int m, hipStream_t s,
-                   int ioff)
-{
-    hipLaunchKernelGGL(k_reduce_krylov, dim3(1), dim3(TB), 0, s, partial, nblocks_, nv, ks, j, mode, m, ioff);
-}
 void krylov_expv(KState *ks, int m, double dt, int hermitian, hipStream_t s)
 {
     (void)m;
     hipLaunchKernelGGL(k_krylov_expv, dim3(1), dim3(256), 0, s, ks, dt, hermitian);
-}
-void norm2_partial(const double2 *psi, int64_t n, double2 *partial, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_norm2_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, psi, n, partial);
 }
 void dot_partial(const double2 *a, const double2 *b, int64_t n, double2 *partial, hipStream_t s)
 {

@@ -299,9 +299,14 @@ def test_lattice_trajectory(torch):
         assert d < 1e-10
 
 
-@pytest.mark.parametrize("name,nsteps", [("hh2d", 200), ("morse4d", 25), ("small_6d", 10)])
+# Stated error of the FP32 form (complex-FP32 operator and Krylov vectors,
+# FP64 reductions, exponential and master copy) against the FP64 oracle, on
+# the cards whose trajectories are well conditioned.
+FP32_BOUNDS = {"norm2": 1e-6, "acf_re": 1e-6, "acf_im": 1e-6, "energy_rel": 1e-6}
+
+
+@pytest.mark.parametrize("name,nsteps", [("hh2d", 200), ("small_3d", 40), ("small_6d", 10)])
 def test_fp32_form_error(name, nsteps, torch):
-    """Complex-FP32 operator and Krylov vectors, FP64 reductions: error vs the FP64 oracle."""
     import paper_1606_04004_amd as ppq
     cd = card(name)
     say(f"fp32 form {name}")
@@ -311,9 +316,31 @@ def test_fp32_form_error(name, nsteps, torch):
     g = make(cd, torch, precision=ppq.PPQ_FP32)
     g.init_state()
     tg = g.propagate(nsteps=nsteps)
-    errs = {nm: float(np.max(np.abs(tg[:, c] - tr[:, c]))) for c, nm in ((1, "norm2"), (2, "energy"),
-                                                                      (3, "acf_re"), (4, "acf_im"))}
+    errs = {nm: float(np.max(np.abs(tg[:, c] - tr[:, c]))) for c, nm in ((1, "norm2"), (3, "acf_re"),
+                                                                      (4, "acf_im"))}
+    errs["energy_rel"] = float(np.max(np.abs(tg[:, 2] - tr[:, 2]) / np.abs(tr[:, 2])))
     rel_n = float(np.max(np.abs(tg[:, 5] - tr[:, 5]) / tr[:, 5]))
     say(f"  errors {errs} |A| rel {rel_n:.2e}")
-    assert errs["norm2"] < 1e-5 and errs["acf_re"] < 1e-5 and errs["acf_im"] < 1e-5
-    assert errs["energy"] < 1e-4 * abs(tr[0, 2])
+    for nm, bound in FP32_BOUNDS.items():
+        assert errs[nm] < bound, nm
+
+
+def test_fp32_shadow_steps_morse4d(torch):
+    """FP32 step map from the oracle's state on the sensitive Morse card: per-step error."""
+    import paper_1606_04004_amd as ppq
+    cd = card("morse4d")
+    o = Oracle(cd)
+    o.init_state()
+    g = make(cd, torch, precision=ppq.PPQ_FP32)
+    worst = 0.0
+    for st in range(15):
+        keys, c = o.state()
+        g.set_state(keys, c)
+        g.step()
+        o.sil_step()
+        _, cg = g.state()
+        _, co = o.state()
+        worst = max(worst, float(np.max(np.abs(cg - co)) / np.max(np.abs(co))))
+        o.prune()
+    say(f"  morse4d fp32 shadowed steps: worst relative coefficient error {worst:.2e}")
+    assert worst < 1e-5
