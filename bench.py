@@ -35,7 +35,7 @@ def bytes_per_point(D, precision):
     return 2 * sc + 4 * D
 
 
-def cpu_baseline(cd, reps=3):
+def cpu_baseline(cd, reps=10):
     """The FP64 oracle (one thread) applying H on its own initial set of the card."""
     from oracle.oracle import Oracle
     o = Oracle(cd)
@@ -108,6 +108,7 @@ def main():
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
     value = updates / wall
+    obs64 = g.observables()
 
     out = {
         "metric": "pruned H*psi active-point updates/s (whole step) + steps/s",
@@ -155,7 +156,12 @@ def main():
         torch.cuda.synchronize()
         wall32 = time.perf_counter() - t0
         bpp32 = bytes_per_point(D, 1)
+        obs32 = g32.observables()
+        err = {k: abs(obs32[k] - obs64[k]) for k in ("norm2", "acf_re", "acf_im")}
+        err["energy_rel"] = abs(obs32["energy"] - obs64["energy"]) / abs(obs64["energy"])
+        err["n_active_rel"] = abs(obs32["n_active"] - obs64["n_active"]) / obs64["n_active"]
         out["fp32"] = {"value": upd32 / wall32, "ms_per_step": wall32 * 1e3 / args.steps,
+                       "error_vs_fp64_after_steps": err,
                        "hpsi_updates_per_s": n_snap / (ms32 * 1e-3), "hpsi_ms": ms32,
                        "roofline_frac": bpp32 * n_snap / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "bytes_per_point": bpp32}

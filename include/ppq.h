@@ -65,7 +65,10 @@ typedef enum {
 typedef enum {
     PPQ_FAC_POWER = 0,       /* q_k^p on the grid points;           params = {p, unused} */
     PPQ_FAC_MORSE = 1,       /* (1 - exp(-a (q_k - q0)))^2;          params = {a, q0}   */
-    PPQ_FAC_TABLE = 2        /* caller-supplied values at the n_k grid points          */
+    PPQ_FAC_TABLE = 2,       /* caller-supplied values at the n_k grid points          */
+    PPQ_FAC_MORSE_DA = 3     /* 2 (1 - e) e (q_k - q0), e = exp(-a (q_k - q0)): the
+                                derivative of the Morse factor with respect to a;
+                                params = {a, q0}                                       */
 } ppq_factor_kind;
 
 /* Fields of one observable record (ppq_observables, ppq_propagate). */
@@ -173,6 +176,45 @@ int ppq_propagate(ppq_ctx *ctx, int nsteps, double dt, int m, double eps, double
 /* Observable record of the current state (synchronises).  eps is the
    threshold used for PPQ_OBS_NABOVE. */
 int ppq_observables(ppq_ctx *ctx, double eps, double *out);
+
+/* ---- adjoint gradient of the survival probability (added form) ----------
+   J(theta) = |<psi0(centre, momentum)|psi(T)>|^2 after nsteps steps of the
+   pruned propagation.  The active-set trajectory {A_n} of the recording run
+   is frozen (adaption is not differentiable); each step map is taken as the
+   exact exponential exp(-i H_{A_n} dt), evaluated in its Krylov space.  The
+   gradient is computed by the adjoint recursion lambda_n = E_n^+ R_n^+
+   lambda_{n+1} from lambda_N = psi0 on A_N, with the step derivative
+   obtained in closed form in the two Krylov spaces (block-triangular
+   exponential), psi recomputed from checkpoints every K steps (each
+   recomputed segment must reproduce the next checkpoint bit for bit).
+   DVR dimensions only (PPQ_E_UNSUPPORTED on lattice dimensions). */
+
+/* Replaces coefficient and factor parameters (2 per factor, layout of
+   ppq_add_potential_term; params may be NULL) of potential term `term`
+   (0-based, in order of addition).  For finite-difference checks. */
+int ppq_set_potential_term(ppq_ctx *ctx, int term, double coef, const double *params);
+
+/* Declares one term of dV/dtheta_param (a trainable potential parameter,
+   0 <= param < 32), a sum-of-products term in the layout of
+   ppq_add_potential_term; a parameter may have several terms. */
+int ppq_add_potential_derivative(ppq_ctx *ctx, int param, double coef, int nfac, const int32_t *dims,
+                                 const int32_t *kinds, const double *params, const double *tables);
+
+/* Recording run: initial packet (as ppq_init_gaussian), nsteps of step +
+   adaption, active sets kept on the device, psi checkpointed every
+   checkpoint_every steps.  J (may be NULL) receives the survival probability. */
+int ppq_adjoint_record(ppq_ctx *ctx, const double *centre, const double *momentum, const double *width,
+                       double eps, int nsteps, double dt, int m, int checkpoint_every, double *J);
+
+/* Forward map on the recorded (frozen) sets from a packet with the given
+   centre and momentum (width of the recording) and the current potential:
+   J for finite differences.  Leaves the recording intact. */
+int ppq_adjoint_frozen(ppq_ctx *ctx, const double *centre, const double *momentum, double *J);
+
+/* Gradient of J at the recording's packet and the current potential:
+   dJ_dparam[nparam] (parameters declared by ppq_add_potential_derivative),
+   dJ_dcentre[D], dJ_dmomentum[D] (any may be NULL).  Synchronises. */
+int ppq_adjoint_gradient(ppq_ctx *ctx, double *dJ_dparam, double *dJ_dcentre, double *dJ_dmomentum);
 
 /* Measurement helper: applies H to the current state `nrep` times (after
    one untimed application), bracketed by HIP events recorded on the context

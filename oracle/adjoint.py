@@ -1,0 +1,71 @@
+"""Finite-difference reference of the adjoint gradient (test infrastructure only).
+
+J(theta) = |<psi0(theta)|psi_N(theta)>|^2 with the active-set trajectory
+frozen at the sets of the pruned run at the reference parameters; psi_N is
+the oracle's forward map (SIL steps, restriction to the next recorded set).
+Central differences with h_p = rel * max(1, |theta_p|).
+"""
+import copy
+
+import numpy as np
+
+from .oracle import Oracle
+
+
+def param_value(card, name):
+    for t in card.get("trainable", []):
+        if t["name"] == name:
+            term = card["terms"][t["term"]]
+            return term["coef"] if t["what"] == "coef" else term["factors"][t["factor"]][t["what"]]
+    if name.startswith("centre"):
+        return card["psi0"]["centre"][int(name[6:])]
+    if name.startswith("momentum"):
+        return card["psi0"]["momentum"][int(name[8:])]
+    raise KeyError(name)
+
+
+def card_with(card, name, value):
+    c = copy.deepcopy(card)
+    for t in c.get("trainable", []):
+        if t["name"] == name:
+            term = c["terms"][t["term"]]
+            if t["what"] == "coef":
+                term["coef"] = value
+            else:
+                term["factors"][t["factor"]][t["what"]] = value
+            return c
+    if name.startswith("centre"):
+        c["psi0"]["centre"][int(name[6:])] = value
+    elif name.startswith("momentum"):
+        c["psi0"]["momentum"][int(name[8:])] = value
+    else:
+        raise KeyError(name)
+    return c
+
+
+def record_sets(card, nsteps=None):
+    o = Oracle(card)
+    o.init_state()
+    nsteps = card["nsteps"] if nsteps is None else nsteps
+    return o.propagate_record(nsteps)
+
+
+def survival_frozen(card, sizes, keys):
+    o = Oracle(card)
+    k0 = keys[: sizes[0]]
+    o.set_state(k0, o.psi0_on(k0))
+    o.propagate_frozen(sizes, keys)
+    kN, cN = o.state()
+    C = np.sum(np.conj(o.psi0_on(kN)) * cN)
+    return float(abs(C) ** 2)
+
+
+def fd_gradient(card, names, sizes, keys, rel=1e-5):
+    g = {}
+    for nm in names:
+        v = param_value(card, nm)
+        h = rel * max(1.0, abs(v))
+        jp = survival_frozen(card_with(card, nm, v + h), sizes, keys)
+        jm = survival_frozen(card_with(card, nm, v - h), sizes, keys)
+        g[nm] = (jp - jm) / (2 * h)
+    return g

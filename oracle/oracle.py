@@ -67,6 +67,11 @@ def lib():
         L.orc_fib_ranges.argtypes = [vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _c_i32_p, _c_i32_p]
         L.orc_apply_def_at.argtypes = [vp, ctypes.c_int64, _c_u64_p, _c_double_p, ctypes.c_int64, _c_int64_p,
                                        _c_double_p]
+        L.orc_propagate_record.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                           _c_int64_p, ctypes.POINTER(_c_u64_p)]
+        L.orc_free_buffer.argtypes = [vp]
+        L.orc_propagate_frozen.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _c_int64_p,
+                                           _c_u64_p]
         _LIB = L
     return _LIB
 
@@ -280,6 +285,31 @@ class Oracle:
         lib().orc_propagate(self._m, self._s, nsteps, dt, m, eps, self.arnoldi,
                             _dp(self._bra_tabs.view(np.float64)), _dp(trace), _up(hashes))
         return trace, hashes
+
+    # --- frozen-set trajectories (adjoint reference) ----------------------------
+    def propagate_record(self, nsteps, dt=None, m=None, eps=None):
+        """Pruned run from the current state; returns (set_sizes, concatenated keys)."""
+        dt = self.card["dt"] if dt is None else dt
+        m = self.card["krylov"] if m is None else m
+        eps = self.card["eps"] if eps is None else eps
+        sizes = np.zeros(nsteps + 1, dtype=np.int64)
+        buf = _c_u64_p()
+        lib().orc_propagate_record(self._m, self._s, nsteps, dt, m, eps, sizes.ctypes.data_as(_c_int64_p),
+                                   ctypes.byref(buf))
+        total = int(sizes.sum())
+        keys = np.ctypeslib.as_array(buf, shape=(total,)).copy() if total else np.zeros(0, np.uint64)
+        lib().orc_free_buffer(ctypes.cast(buf, ctypes.c_void_p))
+        self._drop_fib()
+        return sizes, keys
+
+    def propagate_frozen(self, sizes, keys, dt=None, m=None):
+        dt = self.card["dt"] if dt is None else dt
+        m = self.card["krylov"] if m is None else m
+        sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        lib().orc_propagate_frozen(self._m, self._s, sizes.size - 1, dt, m, sizes.ctypes.data_as(_c_int64_p),
+                                   _up(keys))
+        self._drop_fib()
 
     # --- helpers for tests ---------------------------------------------------
     def full_keys(self):

@@ -896,3 +896,67 @@ int orc_apply_def_at(const orc_model *m, int64_t n, const uint64_t *keys, const 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* frozen active-set trajectories (reference of the adjoint gradient)       */
+/* ------------------------------------------------------------------------ */
+/* Remaps the state onto the given sorted set (coefficients carried over on
+   the intersection, zero elsewhere): the restriction R of one adaption. */
+static void remap_to(orc_state *s, int64_t n, const uint64_t *keys)
+{
+    zd *nc = malloc(sizeof(zd) * (size_t)(n ? n : 1));
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = find_key(s->keys, s->n, keys[q]);
+        nc[q] = (p >= 0) ? s->c[p] : 0.0;
+    }
+    free(s->keys);
+    free(s->c);
+    s->keys = malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    if (n) memcpy(s->keys, keys, sizeof(uint64_t) * (size_t)n);
+    s->c = nc;
+    s->n = n;
+}
+
+/* Pruned forward run that records the active sets: set_sizes[0..nsteps],
+   keys appended to *keys_out (malloc'd; caller frees with orc_free_buffer). */
+int orc_propagate_record(const orc_model *m, orc_state *s, int nsteps, double dt, int mk, double eps,
+                         int64_t *set_sizes, uint64_t **keys_out)
+{
+    int64_t cap = 1024, used = 0;
+    uint64_t *buf = malloc(sizeof(uint64_t) * cap);
+    for (int st = 0; st <= nsteps; ++st) {
+        if (st > 0) {
+            orc_fib *f = orc_fib_build(m, s->n, s->keys);
+            orc_sil_step(m, f, s, dt, mk, 0, NULL);
+            orc_fib_free(f);
+            orc_prune(m, s, eps, 0.0);
+        }
+        set_sizes[st] = s->n;
+        if (used + s->n > cap) {
+            while (used + s->n > cap) cap *= 2;
+            buf = realloc(buf, sizeof(uint64_t) * cap);
+        }
+        memcpy(buf + used, s->keys, sizeof(uint64_t) * (size_t)s->n);
+        used += s->n;
+    }
+    *keys_out = buf;
+    return 0;
+}
+
+void orc_free_buffer(void *p) { free(p); }
+
+/* Forward map with frozen sets: the state (on set 0) takes nsteps SIL steps,
+   each followed by the restriction to the next recorded set. */
+int orc_propagate_frozen(const orc_model *m, orc_state *s, int nsteps, double dt, int mk, const int64_t *set_sizes,
+                         const uint64_t *keys)
+{
+    int64_t off = set_sizes[0];
+    for (int st = 1; st <= nsteps; ++st) {
+        orc_fib *f = orc_fib_build(m, s->n, s->keys);
+        orc_sil_step(m, f, s, dt, mk, 0, NULL);
+        orc_fib_free(f);
+        remap_to(s, set_sizes[st], keys + off);
+        off += set_sizes[st];
+    }
+    return 0;
+}

@@ -13,7 +13,8 @@ from ._ppq import OBS_FIELDS, OBS_N, PPQ_FP32, PPQ_FP64, PPQError  # noqa: F401
 
 __all__ = ["Propagator", "PPQError", "PPQ_FP64", "PPQ_FP32", "OBS_FIELDS"]
 
-_KIND = {"power": _ppq.PPQ_FAC_POWER, "morse": _ppq.PPQ_FAC_MORSE, "table": _ppq.PPQ_FAC_TABLE}
+_KIND = {"power": _ppq.PPQ_FAC_POWER, "morse": _ppq.PPQ_FAC_MORSE, "table": _ppq.PPQ_FAC_TABLE,
+         "morse_da": _ppq.PPQ_FAC_MORSE_DA}
 
 
 def _d(a):
@@ -74,23 +75,73 @@ class Propagator:
             pass
 
     # ---- model --------------------------------------------------------------
-    def add_term(self, coef, factors):
+    @staticmethod
+    def _factors(factors):
         dims, kinds, params, tables = [], [], [], []
         for f in factors:
             dims.append(int(f["dim"]))
             kinds.append(_KIND[f["kind"]])
             if f["kind"] == "power":
                 params += [float(f["p"]), 0.0]
-            elif f["kind"] == "morse":
+            elif f["kind"] in ("morse", "morse_da"):
                 params += [float(f["a"]), float(f["q0"])]
             else:
                 params += [0.0, 0.0]
                 tables += list(f["values"])
+        return dims, kinds, params, tables
+
+    def add_term(self, coef, factors):
+        dims, kinds, params, tables = self._factors(factors)
         d, pd = _i32(dims or [0])
         k, pk = _i32(kinds or [0])
         p, pp = _d(params or [0.0])
         tb, ptb = _d(tables or [0.0])
         self._call("ppq_add_potential_term", float(coef), len(factors), pd, pk, pp, ptb if tables else None)
+
+    def add_derivative(self, param, coef, factors):
+        dims, kinds, params, tables = self._factors(factors)
+        d, pd = _i32(dims or [0])
+        k, pk = _i32(kinds or [0])
+        p, pp = _d(params or [0.0])
+        tb, ptb = _d(tables or [0.0])
+        self._call("ppq_add_potential_derivative", int(param), float(coef), len(factors), pd, pk, pp,
+                   ptb if tables else None)
+
+    def set_term(self, term, coef, params):
+        p, pp = _d(params or [0.0])
+        self._call("ppq_set_potential_term", int(term), float(coef), pp if params else None)
+
+    # ---- adjoint ----------------------------------------------------------------
+    def adjoint_record(self, centre=None, momentum=None, eps=None, nsteps=None, dt=None, m=None, every=None):
+        ps = self.card["psi0"]
+        c, pc = _d(ps["centre"] if centre is None else centre)
+        mo, pm = _d(ps["momentum"] if momentum is None else momentum)
+        w, pw = _d(ps["width"])
+        J = ctypes.c_double(0.0)
+        self._call("ppq_adjoint_record", pc, pm, pw,
+                   float(self.card["eps"] if eps is None else eps),
+                   int(self.card["nsteps"] if nsteps is None else nsteps),
+                   float(self.card["dt"] if dt is None else dt),
+                   int(self.card["krylov"] if m is None else m),
+                   int(self.card.get("checkpoint_every", 50) if every is None else every), ctypes.byref(J))
+        return J.value
+
+    def adjoint_frozen(self, centre, momentum):
+        c, pc = _d(centre)
+        mo, pm = _d(momentum)
+        J = ctypes.c_double(0.0)
+        self._call("ppq_adjoint_frozen", pc, pm, ctypes.byref(J))
+        return J.value
+
+    def adjoint_gradient(self):
+        npar = len(self.card.get("trainable", []))
+        dp = np.zeros(max(npar, 1))
+        dc = np.zeros(self.D)
+        dm = np.zeros(self.D)
+        self._call("ppq_adjoint_gradient", dp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   dc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   dm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return dp[:npar], dc, dm
 
     def grid(self, k):
         q = np.zeros(self.n[k])

@@ -13,7 +13,7 @@ PPQ_OK = 0
 STATUS = {0: "PPQ_OK", -1: "PPQ_E_ARG", -2: "PPQ_E_STATE", -3: "PPQ_E_OOM", -4: "PPQ_E_CAPACITY",
           -5: "PPQ_E_HIP", -6: "PPQ_E_NUMERIC", -7: "PPQ_E_UNSUPPORTED"}
 PPQ_FP64, PPQ_FP32 = 0, 1
-PPQ_FAC_POWER, PPQ_FAC_MORSE, PPQ_FAC_TABLE = 0, 1, 2
+PPQ_FAC_POWER, PPQ_FAC_MORSE, PPQ_FAC_TABLE, PPQ_FAC_MORSE_DA = 0, 1, 2, 3
 OBS_FIELDS = ("t", "norm2", "energy", "acf_re", "acf_im", "n_active", "n_above", "krylov_used")
 OBS_N = 8
 
@@ -41,6 +41,13 @@ SIGNATURES = {
     "ppq_prune": (ctypes.c_int, [_vp, ctypes.c_double, _i64p, _i64p]),
     "ppq_propagate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp]),
     "ppq_observables": (ctypes.c_int, [_vp, ctypes.c_double, _dp]),
+    "ppq_set_potential_term": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp]),
+    "ppq_add_potential_derivative": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _i32p, _i32p,
+                                                    _dp, _dp]),
+    "ppq_adjoint_record": (ctypes.c_int, [_vp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_int, ctypes.c_int, _dp]),
+    "ppq_adjoint_frozen": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "ppq_adjoint_gradient": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "ppq_time_apply": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "ppq_fiber_counts": (ctypes.c_int, [_vp, _i64p]),
 }

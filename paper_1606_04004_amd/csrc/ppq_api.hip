@@ -164,6 +164,32 @@ struct ppq_ctx {
 
     // measurement
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // adjoint: derivative terms dV/dtheta_p, recorded trajectory, work buffers
+    std::vector<Term> dterms;
+    std::vector<int> dparam;
+    int nparam = 0;
+    int *d_param = nullptr, *d_dtab = nullptr;
+    double *d_dcoef = nullptr, *d_dtabs = nullptr;
+    int d_nterm = 0, d_ntab = 0;
+    double2 *dtabs = nullptr;  // [2D][nmax]: d psi0 factor / d centre_k, d momentum_k
+    double pk_centre[MAXD]{}, pk_momentum[MAXD]{}, pk_width[MAXD]{};
+    double rec_centre[MAXD]{}, rec_momentum[MAXD]{};
+    bool recorded = false;
+    int rec_steps = 0, rec_m = 0, rec_every = 0;
+    double rec_dt = 0.0;
+    double2 rec_C = make_double2(0.0, 0.0);
+    uint32_t *rec_keys = nullptr;
+    int64_t rec_keys_cap = 0;
+    std::vector<int64_t> rec_off, rec_n;
+    std::vector<double2 *> ckpt;
+    double2 *seg = nullptr;
+    int64_t seg_cap = 0;
+    void *Wk = nullptr;
+    int64_t wk_cap = 0;
+    KState *ks_b = nullptr;
+    double2 *Qd = nullptr, *dC = nullptr, *lam = nullptr, *mu = nullptr;
+    int64_t adj_cap = 0;
 };
 
 namespace {
@@ -317,6 +343,9 @@ std::vector<double> factor_values(const ppq_ctx *c, const Factor &f)
         } else if (f.kind == PPQ_FAC_MORSE) {
             double e = 1.0 - std::exp(-f.p0 * (q[i] - f.p1));
             v[i] = e * e;
+        } else if (f.kind == PPQ_FAC_MORSE_DA) {
+            double ex = std::exp(-f.p0 * (q[i] - f.p1));
+            v[i] = 2.0 * (1.0 - ex) * ex * (q[i] - f.p1);
         } else {
             v[i] = f.table[i];
         }
@@ -438,6 +467,55 @@ void build_operator(ppq_ctx *c)
         c->pot_coef = upload(coef, s);
         c->pot_tab = upload(tab, s);
         c->pot_tabs = upload(tabs, s);
+        // derivative terms of the trainable parameters, same table layout
+        {
+            std::vector<double> dcoef, dtabsv;
+            std::vector<int> dtab, dpar;
+            for (size_t ti = 0; ti < c->dterms.size(); ++ti) {
+                const Term &t = c->dterms[ti];
+                std::vector<std::vector<double>> per(D);
+                for (const Factor &f : t.f) {
+                    std::vector<double> v = factor_values(c, f);
+                    if (per[f.dim].empty()) per[f.dim] = v;
+                    else
+                        for (size_t i = 0; i < v.size(); ++i) per[f.dim][i] *= v[i];
+                }
+                std::vector<int> idx(D, -1);
+                for (int k = 0; k < D; ++k) {
+                    if (per[k].empty()) continue;
+                    per[k].resize(nmax, 0.0);
+                    int found = -1;
+                    for (size_t t0 = 0; t0 < dtabsv.size() / nmax && found < 0; ++t0)
+                        if (std::equal(per[k].begin(), per[k].end(), dtabsv.begin() + t0 * nmax)) found = (int)t0;
+                    if (found < 0) {
+                        found = (int)(dtabsv.size() / nmax);
+                        dtabsv.insert(dtabsv.end(), per[k].begin(), per[k].end());
+                    }
+                    idx[k] = found;
+                }
+                dcoef.push_back(t.coef);
+                dpar.push_back(c->dparam[ti]);
+                dtab.insert(dtab.end(), idx.begin(), idx.end());
+            }
+            c->d_nterm = (int)dcoef.size();
+            c->d_ntab = (int)(dtabsv.size() / nmax);
+            if (c->d_nterm > 256 || (int64_t)dtabsv.size() > 1024)
+                throw std::invalid_argument("derivative terms: at most 256 terms, 1024 distinct table values");
+            if (dcoef.empty()) {
+                dcoef.push_back(0.0);
+                dpar.push_back(0);
+                dtab.assign(D, -1);
+            }
+            if (dtabsv.empty()) dtabsv.assign(nmax, 0.0);
+            dfree(c->d_dcoef);
+            dfree(c->d_param);
+            dfree(c->d_dtab);
+            dfree(c->d_dtabs);
+            c->d_dcoef = upload(dcoef, s);
+            c->d_param = upload(dpar, s);
+            c->d_dtab = upload(dtab, s);
+            c->d_dtabs = upload(dtabsv, s);
+        }
     } else {
         std::vector<LatticeMaps> L(D);
         for (int k = 0; k < D; ++k) L[k] = lattice_maps(c, k);
@@ -706,19 +784,19 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
     }
 }
 
+// Lanczos/Arnoldi basis of `src` (FP64 master vector on the current set) in
+// Vb with the small matrix and norm in ks; m H-applications, CGS2.
 template <class C>
-void step_impl(ppq_ctx *c, double dt, int m)
+void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
 {
     hipStream_t s = c->stream;
     const int64_t n = c->nact;
     const int64_t ld = c->cap;
-    C *Vb = (C *)c->Vk;
     C *w = (C *)c->wk;
-    KState *ks = c->ks;
     const int *meff = &ks->meff;
     const bool herm = !c->any_lattice;
-    norm0<C>(c->psi[c->cur], n, c->partial, c->counter, ks, m, s);
-    normalise_from_master<C>(c->psi[c->cur], n, ks, Vb, s);
+    norm0<C>(src, n, c->partial, c->counter, ks, m, s);
+    normalise_from_master<C>(src, n, ks, Vb, s);
     for (int j = 0; j < m; ++j) {
         const C *vj = Vb + (int64_t)j * ld;
         apply_internal(c, vj, w, meff, j);
@@ -733,8 +811,15 @@ void step_impl(ppq_ctx *c, double dt, int m)
         if (last) break;
         cgs_update_scale<C>(Vb, ld, j + 1, w, Vb + (int64_t)(j + 1) * ld, n, ks, j, s);
     }
-    krylov_expv(ks, m, dt, herm ? 1 : 0, s);
-    lincomb<C>(Vb, ld, c->psi[c->cur], n, ks, c->psi_tmp, s);
+}
+
+template <class C>
+void step_impl(ppq_ctx *c, double dt, int m)
+{
+    C *Vb = (C *)c->Vk;
+    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m);
+    krylov_expv(c->ks, m, dt, c->any_lattice ? 0 : 1, c->stream);
+    lincomb<C>(Vb, c->cap, c->psi[c->cur], c->nact, c->ks, c->psi_tmp, c->stream);
     std::swap(c->psi[c->cur], c->psi_tmp);
 }
 
@@ -827,6 +912,71 @@ void energy_into(ppq_ctx *c, int64_t r)
     energy_from_dot(c->partial, RED_BLOCKS, rec, c->stream);
 }
 
+// Packet tables: init (coefficients of psi0 per dimension), bra (its dual,
+// giving C(t)) and, for DVR dimensions, the derivatives of the normalised 1D
+// factors with respect to the centre and the momentum.
+void set_packet_tables(ppq_ctx *c, const double *centre, const double *momentum, const double *width)
+{
+    const int D = c->g.D;
+    int nmax = 0;
+    for (int k = 0; k < D; ++k) nmax = std::max(nmax, c->g.n[k]);
+    std::vector<double2> it((size_t)D * nmax, make_double2(0.0, 0.0)), bt = it;
+    std::vector<double2> dt((size_t)2 * D * nmax, make_double2(0.0, 0.0));
+    for (int k = 0; k < D; ++k) {
+        int n = c->g.n[k];
+        std::vector<double> q = sine_dvr_points(n, c->lo[k], c->hi[k]);
+        std::vector<cd> gk(n), dc(n), dp(n);
+        double nrm2 = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double d = q[i] - centre[k];
+            gk[i] = std::exp(-d * d / (2.0 * width[k] * width[k])) * std::exp(cd(0.0, momentum[k] * d));
+            dc[i] = gk[i] * cd(d / (width[k] * width[k]), -momentum[k]);
+            dp[i] = gk[i] * cd(0.0, d);
+            nrm2 += std::norm(gk[i]);
+        }
+        const double nrm = std::sqrt(nrm2);
+        double rc = 0.0, rp = 0.0;  // Re <g|dg>
+        for (int i = 0; i < n; ++i) {
+            rc += (std::conj(gk[i]) * dc[i]).real();
+            rp += (std::conj(gk[i]) * dp[i]).real();
+        }
+        for (int i = 0; i < n; ++i) {
+            cd dci = dc[i] / nrm - gk[i] * (rc / (nrm * nrm2));
+            cd dpi = dp[i] / nrm - gk[i] * (rp / (nrm * nrm2));
+            dt[(size_t)(2 * k) * nmax + i] = make_double2(dci.real(), dci.imag());
+            dt[(size_t)(2 * k + 1) * nmax + i] = make_double2(dpi.real(), dpi.imag());
+        }
+        for (int i = 0; i < n; ++i) gk[i] /= nrm;
+        std::vector<cd> a = gk, b = gk;
+        if (c->lattice[k]) {
+            LatticeMaps L = lattice_maps(c, k);
+            a.assign(n, cd(0.0, 0.0));
+            b.assign(n, cd(0.0, 0.0));
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    a[i] += L.Gadj[(size_t)i * n + j] * gk[j];
+                    b[i] += L.Ginv[(size_t)i * n + j] * gk[j];
+                }
+        }
+        for (int i = 0; i < n; ++i) {
+            it[(size_t)k * nmax + i] = make_double2(a[i].real(), a[i].imag());
+            bt[(size_t)k * nmax + i] = make_double2(b[i].real(), b[i].imag());
+        }
+        c->pk_centre[k] = centre[k];
+        c->pk_momentum[k] = momentum[k];
+        c->pk_width[k] = width[k];
+    }
+    ck(hipStreamSynchronize(c->stream), "sync");
+    dfree(c->init_tabs);
+    dfree(c->bra_tabs);
+    dfree(c->dtabs);
+    c->init_tabs = upload(it, c->stream);
+    c->bra_tabs = upload(bt, c->stream);
+    c->dtabs = upload(dt, c->stream);
+    c->tab_nmax = nmax;
+    c->has_ref = true;
+}
+
 bool keys_valid(const ppq_ctx *c, int64_t n, const uint64_t *keys)
 {
     for (int64_t i = 0; i < n; ++i) {
@@ -834,6 +984,187 @@ bool keys_valid(const ppq_ctx *c, int64_t n, const uint64_t *keys)
         if (i && keys[i] <= keys[i - 1]) return false;
     }
     return true;
+}
+
+
+// ---- adjoint helpers -----------------------------------------------------------
+void set_current_set(ppq_ctx *c, const uint32_t *keys_dev, int64_t n)
+{
+    if (n > c->cap) throw std::runtime_error("set larger than the reserved capacity");
+    if (n) ck(hipMemcpyAsync(c->keys[c->cur], keys_dev, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream),
+              "set keys");
+    c->nact = n;
+    c->has_state = true;
+    c->derived_valid = false;
+}
+
+// restriction of the current state to a recorded set (one frozen adaption)
+void frozen_remap(ppq_ctx *c, const uint32_t *next_keys, int64_t n_next)
+{
+    hipStream_t s = c->stream;
+    if (n_next > c->cap) throw std::runtime_error("set larger than the reserved capacity");
+    fill_u64(c->bm, c->nwords + 2, 0ull, s);
+    mark_keys_wave(next_keys, n_next, c->bm, s);
+    scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
+    const int nxt = 1 - c->cur;
+    if (n_next)
+        ck(hipMemcpyAsync(c->keys[nxt], next_keys, n_next * sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "keys");
+    fill_zero_bytes(c->psi[nxt], n_next * (int64_t)sizeof(double2), s);
+    remap(c->keys[c->cur], c->psi[c->cur], c->nact, c->bm, c->prefix, c->psi[nxt], s);
+    c->cur = nxt;
+    c->nact = n_next;
+    c->derived_valid = false;
+}
+
+void record_append(ppq_ctx *c)
+{
+    int64_t used = c->rec_off.empty() ? 0 : c->rec_off.back() + c->rec_n.back();
+    if (used + c->nact > c->rec_keys_cap) {
+        int64_t nc = std::max<int64_t>(2 * c->rec_keys_cap, used + c->nact + (1 << 20));
+        uint32_t *nb = dalloc<uint32_t>(nc);
+        if (used) ck(hipMemcpyAsync(nb, c->rec_keys, used * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream),
+                     "record grow");
+        ck(hipStreamSynchronize(c->stream), "record grow");
+        dfree(c->rec_keys);
+        c->rec_keys = nb;
+        c->rec_keys_cap = nc;
+    }
+    if (c->nact)
+        ck(hipMemcpyAsync(c->rec_keys + used, c->keys[c->cur], c->nact * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                          c->stream),
+           "record keys");
+    c->rec_off.push_back(used);
+    c->rec_n.push_back(c->nact);
+}
+
+void clear_record(ppq_ctx *c)
+{
+    for (auto &p : c->ckpt) dfree(p);
+    c->ckpt.clear();
+    c->rec_off.clear();
+    c->rec_n.clear();
+    c->recorded = false;
+}
+
+void checkpoint_now(ppq_ctx *c)
+{
+    double2 *b = dalloc<double2>(std::max<int64_t>(c->nact, 1));
+    if (c->nact)
+        ck(hipMemcpyAsync(b, c->psi[c->cur], c->nact * sizeof(double2), hipMemcpyDeviceToDevice, c->stream), "ckpt");
+    c->ckpt.push_back(b);
+}
+
+// C = <psi0|psi> on the current set (the autocorrelation through the bra tables)
+double2 overlap_with_packet(ppq_ctx *c)
+{
+    ensure_records(c, 1);
+    obs_partial(c->keys[c->cur], c->psi[c->cur], c->nact, c->g, c->bra_tabs, c->tab_nmax, 0.0, c->partial, c->stream);
+    obs_final(c->partial, RED_BLOCKS, c->rec, c->stream);
+    double r[PPQ_OBS_N];
+    ck(hipMemcpyAsync(r, c->rec, sizeof(r), hipMemcpyDeviceToHost, c->stream), "C");
+    ck(hipStreamSynchronize(c->stream), "C");
+    return make_double2(r[PPQ_OBS_ACF_RE], r[PPQ_OBS_ACF_IM]);
+}
+
+void ensure_adjoint_buffers(ppq_ctx *c, int m, int K)
+{
+    const size_t es = c->precision == PPQ_FP64 ? sizeof(double2) : sizeof(float2);
+    if (!c->Wk || c->wk_cap != c->cap) {
+        dfree(c->Wk);
+        void *p = nullptr;
+        if (hipMalloc(&p, es * (size_t)(m + 1) * (size_t)c->cap) != hipSuccess) throw std::bad_alloc();
+        c->Wk = p;
+        c->wk_cap = c->cap;
+    }
+    if (!c->ks_b) {
+        void *p = nullptr;
+        ck(hipMalloc(&p, sizeof(KState)), "kstate");
+        c->ks_b = (KState *)p;
+        c->Qd = dalloc<double2>(MAXM * MAXM);
+        c->dC = dalloc<double2>(ADJ_MAXP + 2 * MAXD);
+    }
+    if (c->adj_cap != c->cap || !c->lam) {
+        dfree(c->lam);
+        dfree(c->mu);
+        c->lam = dalloc<double2>(c->cap);
+        c->mu = dalloc<double2>(c->cap);
+        c->adj_cap = c->cap;
+    }
+    if (c->seg_cap < (int64_t)K * c->cap) {
+        dfree(c->seg);
+        c->seg = dalloc<double2>((int64_t)K * c->cap);
+        c->seg_cap = (int64_t)K * c->cap;
+    }
+}
+
+template <class C>
+void adjoint_backward(ppq_ctx *c, double2 C_N)
+{
+    hipStream_t s = c->stream;
+    const int N = c->rec_steps, K = c->rec_every, m = c->rec_m;
+    const double dt = c->rec_dt;
+    const int D = c->g.D;
+    DerivDesc dd{c->nparam, c->d_nterm, c->pot_nmax, c->d_param, c->d_dcoef, c->d_dtab, c->d_dtabs, c->d_ntab};
+    fill_zero_bytes(c->dC, (ADJ_MAXP + 2 * MAXD) * (int64_t)sizeof(double2), s);
+    auto keys_of = [&](int st) { return c->rec_keys + c->rec_off[st]; };
+    // lambda_N = psi0 restricted to A_N
+    product_values(keys_of(N), c->rec_n[N], c->g, c->bra_tabs, c->tab_nmax, c->lam, s);
+    const int nseg = (N + K - 1) / K;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int a = sg * K, e = std::min(a + K, N);
+        set_current_set(c, keys_of(a), c->rec_n[a]);
+        if (c->rec_n[a])
+            ck(hipMemcpyAsync(c->psi[c->cur], c->ckpt[sg], c->rec_n[a] * sizeof(double2), hipMemcpyDeviceToDevice, s),
+               "restore");
+        for (int st = a; st < e; ++st) {
+            if (c->nact)
+                ck(hipMemcpyAsync(c->seg + (int64_t)(st - a) * c->cap, c->psi[c->cur], c->nact * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, s),
+                   "segment");
+            build_derived(c);
+            if (c->nact) step_impl<C>(c, dt, m);
+            frozen_remap(c, keys_of(st + 1), c->rec_n[st + 1]);
+        }
+        if (e == N) {
+            // <d psi0 / d theta | psi_N>
+            adj_packet(keys_of(N), c->rec_n[N], c->g, c->init_tabs, c->dtabs, c->tab_nmax, c->psi[c->cur], 1,
+                       c->partial, s);
+            adj_accumulate(c->partial, 2 * D, 36, make_double2(1.0, 0.0), c->dC + c->nparam, s);
+        } else {
+            // the recomputation must reproduce the stored checkpoint bit for bit
+            unsigned long long nd =
+                count_diff(c->psi[c->cur], c->ckpt[sg + 1], c->nact, c->count, c->h_count, s);
+            if (nd) throw std::runtime_error("recomputed segment differs from the stored checkpoint");
+        }
+        for (int st = e - 1; st >= a; --st) {
+            const int64_t nn = c->rec_n[st];
+            // mu = R^dagger lambda_{st+1}
+            fill_u64(c->bm, c->nwords + 2, 0ull, s);
+            mark_keys_wave(keys_of(st + 1), c->rec_n[st + 1], c->bm, s);
+            scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
+            gather_remap(keys_of(st), nn, c->bm, c->prefix, c->lam, c->mu, s);
+            set_current_set(c, keys_of(st), nn);
+            build_derived(c);
+            if (nn == 0) continue;
+            const double2 *psi_n = c->seg + (int64_t)(st - a) * c->cap;
+            krylov_build<C>(c, psi_n, (C *)c->Vk, c->ks, m);
+            krylov_build<C>(c, c->mu, (C *)c->Wk, c->ks_b, m);
+            adj_q(c->ks, c->ks_b, dt, c->Qd, s);
+            if (c->nparam > 0) {
+                adj_reduce<C>((const C *)c->Vk, (const C *)c->Wk, c->cap, psi_n, c->mu, c->ks, c->ks_b, c->Qd,
+                              keys_of(st), nn, c->g, dd, c->partial, s);
+                adj_accumulate(c->partial, c->nparam, 36, make_double2(0.0, -dt), c->dC, s);
+            }
+            // lambda_st = exp(+i H dt) mu
+            krylov_expv(c->ks_b, m, -dt, 1, s);
+            lincomb<C>((const C *)c->Wk, c->cap, c->mu, nn, c->ks_b, c->lam, s);
+        }
+    }
+    // <lambda_0 | d psi0 / d theta>
+    adj_packet(keys_of(0), c->rec_n[0], c->g, c->init_tabs, c->dtabs, c->tab_nmax, c->lam, 0, c->partial, s);
+    adj_accumulate(c->partial, 2 * D, 36, make_double2(1.0, 0.0), c->dC + c->nparam, s);
+    ck(hipStreamSynchronize(s), "adjoint");
+    (void)C_N;
 }
 
 }  // namespace
@@ -902,6 +1233,20 @@ void ppq_destroy(ppq_ctx *c)
     dfree(c->init_tabs);
     dfree(c->bra_tabs);
     dfree(c->rec);
+    clear_record(c);
+    dfree(c->rec_keys);
+    dfree(c->seg);
+    dfree(c->Wk);
+    dfree(c->ks_b);
+    dfree(c->Qd);
+    dfree(c->dC);
+    dfree(c->lam);
+    dfree(c->mu);
+    dfree(c->dtabs);
+    dfree(c->d_param);
+    dfree(c->d_dcoef);
+    dfree(c->d_dtab);
+    dfree(c->d_dtabs);
     if (c->h_small) (void)hipHostFree(c->h_small);
     if (c->h_count) (void)hipHostFree(c->h_count);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1031,7 +1376,7 @@ int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dim
         if (fa.kind == PPQ_FAC_POWER) {
             if (fa.p0 < 0 || fa.p0 > 16 || fa.p0 != std::floor(fa.p0))
                 return fail(c, PPQ_E_ARG, "power must be an integer in [0, 16]");
-        } else if (fa.kind == PPQ_FAC_MORSE) {
+        } else if (fa.kind == PPQ_FAC_MORSE || fa.kind == PPQ_FAC_MORSE_DA) {
         } else if (fa.kind == PPQ_FAC_TABLE) {
             if (!tables) return fail(c, PPQ_E_ARG, "table factor without tables");
             fa.table.assign(tables + toff, tables + toff + c->g.n[fa.dim]);
@@ -1072,45 +1417,8 @@ int ppq_init_gaussian(ppq_ctx *c, const double *centre, const double *momentum, 
     for (int k = 0; k < c->g.D; ++k)
         if (!(width[k] > 0.0)) return fail(c, PPQ_E_ARG, "width must be positive");
     PPQ_TRY(c, {
-        const int D = c->g.D;
-        int nmax = 0;
-        for (int k = 0; k < D; ++k) nmax = std::max(nmax, c->g.n[k]);
-        std::vector<double2> it((size_t)D * nmax, make_double2(0.0, 0.0)), bt = it;
-        for (int k = 0; k < D; ++k) {
-            int n = c->g.n[k];
-            std::vector<double> q = sine_dvr_points(n, c->lo[k], c->hi[k]);
-            std::vector<cd> gk(n);
-            double nrm = 0.0;
-            for (int i = 0; i < n; ++i) {
-                double d = q[i] - centre[k];
-                gk[i] = std::exp(-d * d / (2.0 * width[k] * width[k])) * std::exp(cd(0.0, momentum[k] * d));
-                nrm += std::norm(gk[i]);
-            }
-            nrm = std::sqrt(nrm);
-            for (int i = 0; i < n; ++i) gk[i] /= nrm;
-            std::vector<cd> a = gk, b = gk;
-            if (c->lattice[k]) {
-                LatticeMaps L = lattice_maps(c, k);
-                a.assign(n, cd(0.0, 0.0));
-                b.assign(n, cd(0.0, 0.0));
-                for (int i = 0; i < n; ++i)
-                    for (int j = 0; j < n; ++j) {
-                        a[i] += L.Gadj[(size_t)i * n + j] * gk[j];
-                        b[i] += L.Ginv[(size_t)i * n + j] * gk[j];
-                    }
-            }
-            for (int i = 0; i < n; ++i) {
-                it[(size_t)k * nmax + i] = make_double2(a[i].real(), a[i].imag());
-                bt[(size_t)k * nmax + i] = make_double2(b[i].real(), b[i].imag());
-            }
-        }
-        ck(hipStreamSynchronize(c->stream), "sync");
-        dfree(c->init_tabs);
-        dfree(c->bra_tabs);
-        c->init_tabs = upload(it, c->stream);
-        c->bra_tabs = upload(bt, c->stream);
-        c->tab_nmax = nmax;
-        c->has_ref = true;
+        set_packet_tables(c, centre, momentum, width);
+        const int nmax = c->tab_nmax;
         // flag the full grid, dilate, compact
         hipStream_t s = c->stream;
         if (!c->scan_tmp) ensure_capacity(c, 1024);
@@ -1284,6 +1592,143 @@ int ppq_observables(ppq_ctx *c, double eps, double *out)
         energy_into(c, 0);
         ck(hipStreamSynchronize(c->stream), "observables");
         ck(hipMemcpy(out, c->rec, sizeof(double) * PPQ_OBS_N, hipMemcpyDeviceToHost), "obs");
+    })
+    return PPQ_OK;
+}
+
+
+int ppq_set_potential_term(ppq_ctx *c, int term, double coef, const double *params)
+{
+    PPQ_GUARD(c)
+    if (term < 0 || term >= (int)c->terms.size()) return fail(c, PPQ_E_ARG, "term index out of range");
+    Term &t = c->terms[term];
+    t.coef = coef;
+    if (params)
+        for (size_t f = 0; f < t.f.size(); ++f) {
+            t.f[f].p0 = params[2 * f];
+            t.f[f].p1 = params[2 * f + 1];
+        }
+    c->op_dirty = true;
+    c->derived_valid = false;
+    return PPQ_OK;
+}
+
+int ppq_add_potential_derivative(ppq_ctx *c, int param, double coef, int nfac, const int32_t *dims,
+                                 const int32_t *kinds, const double *params, const double *tables)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (param < 0 || param >= ADJ_MAXP) return fail(c, PPQ_E_ARG, "parameter index must be in [0, 32)");
+    if (c->any_lattice) return fail(c, PPQ_E_UNSUPPORTED, "adjoint gradients are built for DVR dimensions");
+    size_t before = c->terms.size();
+    int r = ppq_add_potential_term(c, coef, nfac, dims, kinds, params, tables);
+    if (r != PPQ_OK) return r;
+    // move the parsed term from the potential to the derivative list
+    c->dterms.push_back(c->terms.back());
+    c->terms.resize(before);
+    c->dparam.push_back(param);
+    c->nparam = std::max(c->nparam, param + 1);
+    c->op_dirty = true;
+    return PPQ_OK;
+}
+
+int ppq_adjoint_record(ppq_ctx *c, const double *centre, const double *momentum, const double *width, double eps,
+                       int nsteps, double dt, int m, int checkpoint_every, double *J)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (c->any_lattice) return fail(c, PPQ_E_UNSUPPORTED, "adjoint gradients are built for DVR dimensions");
+    if (nsteps < 1 || m < 1 || m > MAXM || checkpoint_every < 1 || !(eps >= 0.0) || !std::isfinite(dt))
+        return fail(c, PPQ_E_ARG, "bad adjoint recording arguments");
+    int r = ppq_init_gaussian(c, centre, momentum, width, eps, nullptr);
+    if (r != PPQ_OK) return r;
+    PPQ_TRY(c, {
+        clear_record(c);
+        record_append(c);
+        checkpoint_now(c);
+        for (int st = 1; st <= nsteps; ++st) {
+            do_step(c, dt, m);
+            do_prune(c, eps, nullptr);
+            record_append(c);
+            if (st % checkpoint_every == 0 && st < nsteps) checkpoint_now(c);
+        }
+        c->rec_C = overlap_with_packet(c);
+        for (int k = 0; k < c->g.D; ++k) {
+            c->rec_centre[k] = centre[k];
+            c->rec_momentum[k] = momentum[k];
+        }
+        c->rec_steps = nsteps;
+        c->rec_m = m;
+        c->rec_dt = dt;
+        c->rec_every = checkpoint_every;
+        c->recorded = true;
+        if (J) *J = c->rec_C.x * c->rec_C.x + c->rec_C.y * c->rec_C.y;
+    })
+    return PPQ_OK;
+}
+
+int ppq_adjoint_frozen(ppq_ctx *c, const double *centre, const double *momentum, double *J)
+{
+    PPQ_GUARD(c)
+    if (!c->recorded) return fail(c, PPQ_E_STATE, "no recorded trajectory");
+    if (!centre || !momentum || !J) return fail(c, PPQ_E_ARG, "null argument");
+    PPQ_TRY(c, {
+        int64_t nmax_set = *std::max_element(c->rec_n.begin(), c->rec_n.end());
+        ensure_capacity(c, std::max<int64_t>(nmax_set, 1));
+        double w[MAXD];
+        for (int k = 0; k < c->g.D; ++k) w[k] = c->pk_width[k];
+        set_packet_tables(c, centre, momentum, w);
+        auto keys_of = [&](int st) { return c->rec_keys + c->rec_off[st]; };
+        set_current_set(c, keys_of(0), c->rec_n[0]);
+        product_values(c->keys[c->cur], c->nact, c->g, c->init_tabs, c->tab_nmax, c->psi[c->cur], c->stream);
+        for (int st = 1; st <= c->rec_steps; ++st) {
+            build_derived(c);
+            ensure_krylov(c, c->rec_m);
+            if (c->nact) {
+                if (c->precision == PPQ_FP64) step_impl<double2>(c, c->rec_dt, c->rec_m);
+                else step_impl<float2>(c, c->rec_dt, c->rec_m);
+            }
+            frozen_remap(c, keys_of(st), c->rec_n[st]);
+        }
+        double2 C = overlap_with_packet(c);
+        *J = C.x * C.x + C.y * C.y;
+    })
+    return PPQ_OK;
+}
+
+int ppq_adjoint_gradient(ppq_ctx *c, double *dJ_dparam, double *dJ_dcentre, double *dJ_dmomentum)
+{
+    PPQ_GUARD(c)
+    if (!c->recorded) return fail(c, PPQ_E_STATE, "no recorded trajectory");
+    PPQ_TRY(c, {
+        const int D = c->g.D;
+        int64_t nmax_set = *std::max_element(c->rec_n.begin(), c->rec_n.end());
+        ensure_capacity(c, std::max<int64_t>(nmax_set, 1));
+        // the packet of the recording (ppq_adjoint_frozen may have changed the tables)
+        double cen[MAXD], mom[MAXD], w[MAXD];
+        for (int k = 0; k < D; ++k) {
+            cen[k] = c->pk_centre[k];
+            mom[k] = c->pk_momentum[k];
+            w[k] = c->pk_width[k];
+        }
+        (void)cen;
+        (void)mom;
+        set_packet_tables(c, c->rec_centre, c->rec_momentum, w);
+        build_operator(c);
+        ensure_krylov(c, c->rec_m);
+        ensure_adjoint_buffers(c, c->rec_m, c->rec_every);
+        if (c->precision == PPQ_FP64) adjoint_backward<double2>(c, c->rec_C);
+        else adjoint_backward<float2>(c, c->rec_C);
+        std::vector<double2> dC(ADJ_MAXP + 2 * MAXD);
+        ck(hipMemcpy(dC.data(), c->dC, dC.size() * sizeof(double2), hipMemcpyDeviceToHost), "dC");
+        const double2 Cn = c->rec_C;
+        auto grad = [&](double2 d) { return 2.0 * (Cn.x * d.x + Cn.y * d.y); };  // 2 Re(conj(C) dC)
+        if (dJ_dparam)
+            for (int p = 0; p < c->nparam; ++p) dJ_dparam[p] = grad(dC[p]);
+        for (int k = 0; k < D; ++k) {
+            if (dJ_dcentre) dJ_dcentre[k] = grad(dC[c->nparam + 2 * k]);
+            if (dJ_dmomentum) dJ_dmomentum[k] = grad(dC[c->nparam + 2 * k + 1]);
+        }
     })
     return PPQ_OK;
 }

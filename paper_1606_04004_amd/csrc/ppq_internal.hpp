@@ -14,7 +14,7 @@ constexpr int MAXD = 8;
 constexpr int MAXM = 16;        // largest Krylov order
 constexpr int NMAX_FIBER = 64;  // largest 1D basis (fiber masks are 64-bit)
 constexpr int RED_BLOCKS = 1024;  // blocks of the fixed-shape reductions
-constexpr int PSTRIDE_H = MAXM + 4;  // partial sums per block (matches the kernels)
+constexpr int PSTRIDE_H = 36;  // partial sums per block (matches the kernels)
 
 // Grid geometry passed by value to kernels.
 struct GridDesc {
@@ -155,6 +155,32 @@ void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const Grid
                  int nmax, double eps2, double2 *partial, hipStream_t s);
 void obs_final(const double2 *partial, int nblocks, double *rec, hipStream_t s);
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s);
+
+// adjoint
+struct DerivDesc {
+    int nparam;
+    int nterm;
+    int nmax;
+    const int *param;     // [nterm]
+    const double *coef;   // [nterm]
+    const int *tab;       // [nterm][D] table index or -1
+    const double *tabs;   // [ntab][nmax]
+    int ntab;
+};
+constexpr int ADJ_MAXP = 32;
+void gather_remap(const uint32_t *keys, int64_t n, const uint64_t *bm, const uint32_t *prefix, const double2 *lam,
+                  double2 *mu, hipStream_t s);
+void mark_keys_wave(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s);
+void adj_q(const KState *kf, const KState *kb, double dt, double2 *Q, hipStream_t s);
+template <class C>
+void adj_reduce(const C *Vb, const C *Wb, int64_t ld, const double2 *psi, const double2 *mu, const KState *kf,
+                const KState *kb, const double2 *Q, const uint32_t *keys, int64_t n, const GridDesc &g,
+                const DerivDesc &dd, double2 *partial, hipStream_t s);
+void adj_accumulate(const double2 *partial, int nparam, int stride, double2 coef, double2 *dC, hipStream_t s);
+void adj_packet(const uint32_t *keys, int64_t n, const GridDesc &g, const double2 *tabs, const double2 *dtabs,
+                int nmax, const double2 *vec, int bra, double2 *partial, hipStream_t s);
+unsigned long long count_diff(const double2 *a, const double2 *b, int64_t n, unsigned long long *dcount,
+                              unsigned long long *hcount, hipStream_t s);
 void copy_meff(const KState *ks, double *dst, hipStream_t s);
 void energy_from_dot(const double2 *partial, int nblocks, double *rec, hipStream_t s);
 void dot_partial(const double2 *a, const double2 *b, int64_t n, double2 *partial, hipStream_t s);

@@ -8,7 +8,7 @@ namespace ppq {
 namespace {
 
 constexpr int TB = 256;  // threads per block for streaming kernels
-constexpr int PSTRIDE = MAXM + 4;  // partial sums per block
+constexpr int PSTRIDE = 36;  // partial sums per block (Krylov values, adjoint parameters)
 
 __device__ inline int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
@@ -822,6 +822,276 @@ __global__ __launch_bounds__(TB) void k_energy_from_dot(const double2 *partial, 
     }
 }
 
+// ---- adjoint ----------------------------------------------------------------------
+// R^dagger of one adaption: mu (on the earlier set) from lambda (on the later
+// set): mu_I = lambda_I for I in both sets, zero otherwise.
+__global__ void k_gather_remap(const uint32_t *keys, int64_t n, const uint64_t *bm, const uint32_t *prefix,
+                               const double2 *lam, double2 *mu)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    uint32_t key = keys[p];
+    uint64_t word = bm[key >> 6];
+    uint32_t b = key & 63;
+    mu[p] = ((word >> b) & 1ull) ? lam[prefix[key >> 6] + (uint32_t)__popcll(word & ((1ull << b) - 1ull))]
+                                 : make_double2(0.0, 0.0);
+}
+
+__global__ void k_count_diff(const double2 *a, const double2 *b, int64_t n, unsigned long long *cnt)
+{
+    int64_t p = gid();
+    bool diff = false;
+    if (p < n) {
+        double2 x = a[p], y = b[p];
+        diff = (__double_as_longlong(x.x) != __double_as_longlong(y.x)) ||
+               (__double_as_longlong(x.y) != __double_as_longlong(y.y));
+    }
+    count_ballot(diff, cnt);
+}
+
+__global__ void k_mark_wave(const uint32_t *keys, int64_t n, uint64_t *bm)
+{
+    int64_t p = gid();
+    uint32_t key = p < n ? keys[p] : 0u;
+    set_bit_wave(bm, key, p < n);
+}
+
+// Time integral of the Krylov-projected Frechet derivative:
+//   Q = m0 n0 [exp([[-i dt T_b, e1 e1^T], [0, -i dt T_f]])]_{12}
+// (the block-triangular exponential gives int_0^1 e^{A(1-s)} X e^{Bs} ds),
+// T_f, T_b the Lanczos matrices of psi_n (forward) and mu (adjoint), both of
+// dimension m; 1024 lanes, one per entry of the 32 x 32 block matrix.
+constexpr int M2 = 2 * MAXM;
+__global__ __launch_bounds__(1024) void k_adj_q(const KState *kf, const KState *kb, double dt, double2 *Q)
+{
+    __shared__ double2 A[M2][M2], P[M2][M2], E[M2][M2];
+    __shared__ double rown[M2];
+    __shared__ int s_sq;
+    const int mf = kf->meff, mb = kb->meff;
+    const int r = threadIdx.x / M2, c = threadIdx.x % M2;
+    double h = 0.0;
+    double2 x = make_double2(0.0, 0.0);
+    // top-left: T_b (mb x mb) at [0, MAXM); bottom-right: T_f at [MAXM, 2 MAXM)
+    auto tri = [](const KState *k, int mm, int i, int j) -> double {
+        if (i >= mm || j >= mm) return 0.0;
+        if (i == j) return k->alpha[i];
+        if (i == j + 1) return k->beta[j];
+        if (j == i + 1) return k->beta[i];
+        return 0.0;
+    };
+    if (r < MAXM && c < MAXM) h = tri(kb, mb, r, c);
+    else if (r >= MAXM && c >= MAXM) h = tri(kf, mf, r - MAXM, c - MAXM);
+    A[r][c] = make_double2(0.0, -dt * h);
+    if (r == 0 && c == MAXM) A[r][c] = make_double2(1.0, 0.0);
+    (void)x;
+    __syncthreads();
+    if (threadIdx.x < M2) {
+        double s = 0.0;
+        for (int cc = 0; cc < M2; ++cc) s += sqrt(A[threadIdx.x][cc].x * A[threadIdx.x][cc].x + A[threadIdx.x][cc].y * A[threadIdx.x][cc].y);
+        rown[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double nrm = 0.0;
+        for (int i = 0; i < M2; ++i) nrm = rown[i] > nrm ? rown[i] : nrm;
+        int sq = 0;
+        while (nrm > 0.125) {
+            nrm *= 0.5;
+            ++sq;
+        }
+        s_sq = sq;
+    }
+    __syncthreads();
+    const int sq = s_sq;
+    const double scale = ldexp(1.0, -sq);
+    A[r][c] = make_double2(A[r][c].x * scale, A[r][c].y * scale);
+    P[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    E[r][c] = P[r][c];
+    __syncthreads();
+    for (int kt = 1; kt <= 18; ++kt) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int l = 0; l < M2; ++l) {
+            double2 a = P[r][l], b = A[l][c];
+            acc.x += a.x * b.x - a.y * b.y;
+            acc.y += a.x * b.y + a.y * b.x;
+        }
+        __syncthreads();
+        P[r][c] = make_double2(acc.x / kt, acc.y / kt);
+        E[r][c] = make_double2(E[r][c].x + acc.x / kt, E[r][c].y + acc.y / kt);
+        __syncthreads();
+    }
+    for (int q = 0; q < sq; ++q) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int l = 0; l < M2; ++l) {
+            double2 a = E[r][l], b = E[l][c];
+            acc.x += a.x * b.x - a.y * b.y;
+            acc.y += a.x * b.y + a.y * b.x;
+        }
+        __syncthreads();
+        E[r][c] = acc;
+        __syncthreads();
+    }
+    if (r < MAXM && c >= MAXM) {
+        const double s2 = kf->n0 * kb->n0;
+        double2 e = E[r][c];
+        Q[r * MAXM + (c - MAXM)] = (r < mb && c - MAXM < mf) ? make_double2(s2 * e.x, s2 * e.y) : make_double2(0.0, 0.0);
+    }
+}
+
+// Per point S = sum_ab Q_ab conj(W_a) V_b, then for every parameter p the
+// partial sums of S * G_p(I), G_p = dV/dtheta_p as a sum of products of 1D
+// tables (staged in LDS).  V_0 / W_0 come from the FP64 master vectors
+// (psi_n / n0 and mu / m0), like the propagated vectors.
+template <class C>
+__global__ __launch_bounds__(TB) void k_adj_reduce(const C *Vb, const C *Wb, int64_t ld, const double2 *psi,
+                                                   const double2 *mu, const KState *kf, const KState *kb,
+                                                   const double2 *Q, const uint32_t *keys, int64_t n, GridDesc g,
+                                                   DerivDesc dd, double2 *partial)
+{
+    __shared__ double2 sQ[MAXM * MAXM];
+    __shared__ double s_coef[POT_MAX_TERMS];
+    __shared__ int s_par[POT_MAX_TERMS];
+    __shared__ int s_nf[POT_MAX_TERMS];
+    __shared__ int s_fac[POT_MAX_TERMS][POT_MAX_FAC];
+    __shared__ double s_tab[POT_MAX_TAB];
+    for (int i = threadIdx.x; i < MAXM * MAXM; i += TB) sQ[i] = Q[i];
+    for (int t = threadIdx.x; t < dd.nterm; t += TB) {
+        s_coef[t] = dd.coef[t];
+        s_par[t] = dd.param[t];
+        int nf = 0;
+        for (int k = 0; k < g.D; ++k) {
+            int ti = dd.tab[t * g.D + k];
+            if (ti >= 0 && nf < POT_MAX_FAC) s_fac[t][nf++] = (ti << 4) | k;
+        }
+        s_nf[t] = nf;
+    }
+    for (int i = threadIdx.x; i < dd.ntab * dd.nmax; i += TB) s_tab[i] = dd.tabs[i];
+    __syncthreads();
+    const int mf = kf->meff, mb = kb->meff;
+    const double inv_n0 = 1.0 / kf->n0, inv_m0 = 1.0 / kb->n0;
+    double2 acc[ADJ_MAXP];
+#pragma unroll
+    for (int i = 0; i < ADJ_MAXP; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 v[MAXM];
+        double2 a0 = psi[p];
+        v[0] = make_double2(a0.x * inv_n0, a0.y * inv_n0);
+#pragma unroll
+        for (int b = 1; b < MAXM; ++b) v[b] = (b < mf) ? ld2(Vb, (int64_t)b * ld + p) : make_double2(0.0, 0.0);
+        double2 S = make_double2(0.0, 0.0);
+        for (int a = 0; a < mb; ++a) {
+            double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < MAXM; ++b) {
+                double2 q = sQ[a * MAXM + b];
+                t.x += q.x * v[b].x - q.y * v[b].y;
+                t.y += q.x * v[b].y + q.y * v[b].x;
+            }
+            double2 wa;
+            if (a == 0) {
+                double2 m0v = mu[p];
+                wa = make_double2(m0v.x * inv_m0, m0v.y * inv_m0);
+            } else {
+                wa = ld2(Wb, (int64_t)a * ld + p);
+            }
+            cdot_acc(S, wa, t);
+        }
+        uint32_t key = keys[p];
+        int d[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) d[k] = (k < g.D) ? (int)((key / g.stride[k]) % (uint32_t)g.n[k]) : 0;
+        for (int t = 0; t < dd.nterm; ++t) {
+            double f = s_coef[t];
+            const int nf = s_nf[t];
+#pragma unroll
+            for (int j = 0; j < POT_MAX_FAC; ++j) {
+                if (j < nf) {
+                    int e = s_fac[t][j];
+                    f *= s_tab[(e >> 4) * dd.nmax + select_digit(d, e & 15)];
+                }
+            }
+            const int pp = s_par[t];
+#pragma unroll
+            for (int i = 0; i < ADJ_MAXP; ++i) {
+                if (i == pp) {
+                    acc[i].x += f * S.x;
+                    acc[i].y += f * S.y;
+                }
+            }
+        }
+    }
+    block_reduce_store<ADJ_MAXP>(acc, partial);
+}
+
+// dC[p] += coef * sum over blocks (fixed order), coef = -i dt
+__global__ __launch_bounds__(TB) void k_adj_accumulate(const double2 *partial, int nb, int nparam, int stride,
+                                                       double2 coef, double2 *dC)
+{
+    __shared__ double2 red[TB];
+    for (int i = 0; i < nparam; ++i) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int b = threadIdx.x; b < nb; b += TB) {
+            s.x += partial[(int64_t)b * stride + i].x;
+            s.y += partial[(int64_t)b * stride + i].y;
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int st = TB / 2; st >= 1; st >>= 1) {
+            if ((int)threadIdx.x < st) {
+                red[threadIdx.x].x += red[threadIdx.x + st].x;
+                red[threadIdx.x].y += red[threadIdx.x + st].y;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double2 r = red[0];
+            dC[i].x += coef.x * r.x - coef.y * r.y;
+            dC[i].y += coef.x * r.y + coef.y * r.x;
+        }
+        __syncthreads();
+    }
+}
+
+// Packet-parameter terms.  For each dimension k and each of the two packet
+// parameters (centre, momentum) the derivative of psi0_I is the product of
+// the 1D tables with factor k replaced by its derivative table.
+//   bra = 1: accumulates conj(dpsi0_I) vec_I      (<d psi0 | psi_N>)
+//   bra = 0: accumulates conj(vec_I) dpsi0_I      (<lambda_0 | d psi0>)
+constexpr int ADJ_MAXQ = 2 * MAXD;
+__global__ __launch_bounds__(TB) void k_adj_packet(const uint32_t *keys, int64_t n, GridDesc g, const double2 *tabs,
+                                                   const double2 *dtabs, int nmax, const double2 *vec, int bra,
+                                                   double2 *partial)
+{
+    double2 acc[ADJ_MAXQ];
+#pragma unroll
+    for (int i = 0; i < ADJ_MAXQ; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        uint32_t key = keys[p];
+        double2 v = vec[p];
+        for (int kd = 0; kd < g.D; ++kd) {
+            for (int which = 0; which < 2; ++which) {
+                double2 prod = make_double2(1.0, 0.0);
+                for (int k = 0; k < g.D; ++k) {
+                    int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+                    double2 f = (k == kd) ? dtabs[(2 * k + which) * nmax + d] : tabs[k * nmax + d];
+                    prod = cmul(prod, f);
+                }
+                double2 r = make_double2(0.0, 0.0);
+                if (bra) cdot_acc(r, prod, v);
+                else cdot_acc(r, v, prod);
+                int slot = 2 * kd + which;
+#pragma unroll
+                for (int i = 0; i < ADJ_MAXQ; ++i)
+                    if (i == slot) {
+                        acc[i].x += r.x;
+                        acc[i].y += r.y;
+                    }
+            }
+        }
+    }
+    block_reduce_store<ADJ_MAXQ>(acc, partial);
+}
+
 }  // namespace
 
 // ---- launchers -------------------------------------------------------------------
@@ -1049,6 +1319,55 @@ void copy_alpha0(const KState *ks, double *dst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy_alpha0, dim3(1), dim3(1), 0, s, ks, dst);
 }
+void gather_remap(const uint32_t *keys, int64_t n, const uint64_t *bm, const uint32_t *prefix, const double2 *lam,
+                  double2 *mu, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_remap, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, bm, prefix, lam, mu);
+}
+unsigned long long count_diff(const double2 *a, const double2 *b, int64_t n, unsigned long long *dcount,
+                              unsigned long long *hcount, hipStream_t s)
+{
+    fill_u64((uint64_t *)dcount, 1, 0ull, s);
+    if (n > 0) hipLaunchKernelGGL(k_count_diff, dim3(nblocks(n)), dim3(TB), 0, s, a, b, n, dcount);
+    (void)hipMemcpyAsync(hcount, dcount, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    return *hcount;
+}
+void mark_keys_wave(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mark_wave, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, bm);
+}
+void adj_q(const KState *kf, const KState *kb, double dt, double2 *Q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_q, dim3(1), dim3(1024), 0, s, kf, kb, dt, Q);
+}
+template <class C>
+void adj_reduce(const C *Vb, const C *Wb, int64_t ld, const double2 *psi, const double2 *mu, const KState *kf,
+                const KState *kb, const double2 *Q, const uint32_t *keys, int64_t n, const GridDesc &g,
+                const DerivDesc &dd, double2 *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_reduce<C>, dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, Wb, ld, psi, mu, kf, kb, Q, keys, n, g,
+                       dd, partial);
+}
+template void adj_reduce<double2>(const double2 *, const double2 *, int64_t, const double2 *, const double2 *,
+                                  const KState *, const KState *, const double2 *, const uint32_t *, int64_t,
+                                  const GridDesc &, const DerivDesc &, double2 *, hipStream_t);
+template void adj_reduce<float2>(const float2 *, const float2 *, int64_t, const double2 *, const double2 *,
+                                 const KState *, const KState *, const double2 *, const uint32_t *, int64_t,
+                                 const GridDesc &, const DerivDesc &, double2 *, hipStream_t);
+void adj_accumulate(const double2 *partial, int nparam, int stride, double2 coef, double2 *dC, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_accumulate, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, nparam, stride, coef, dC);
+}
+void adj_packet(const uint32_t *keys, int64_t n, const GridDesc &g, const double2 *tabs, const double2 *dtabs,
+                int nmax, const double2 *vec, int bra, double2 *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_packet, dim3(RED_BLOCKS), dim3(TB), 0, s, keys, n, g, tabs, dtabs, nmax, vec, bra,
+                       partial);
+}
+
 void copy_meff(const KState *ks, double *dst, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy_meff, dim3(1), dim3(1), 0, s, ks, dst);

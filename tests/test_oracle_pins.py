@@ -525,3 +525,45 @@ def test_pvb_coefficients_are_overlaps():
     norms = np.sum(np.abs(G) ** 2, axis=0)
     assert np.all(np.abs(norms[4:12] - 1.0) < 0.05)     # interior cells; edges leak out of the box
     assert np.linalg.cond(G) < 10.0
+
+
+# ---------------------------------------------------------------------------
+# frozen-set forward map (reference of the adjoint gradient)
+# ---------------------------------------------------------------------------
+def test_frozen_forward_equals_dense_exponentials():
+    """psi_{n+1} = R_{n+1} exp(-i H_{A_n} dt) psi_n with dense restricted H, scipy expm."""
+    from oracle import adjoint as adj
+    cd = card("small_2d", eps=2e-3)
+    o = orc.Oracle(cd)
+    o.init_state()
+    sizes, keys = o.propagate_record(12, m=16)
+    assert len(set(sizes.tolist())) > 1            # the set really changes
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    H = dense_h(o.model)
+    k0 = keys[: sizes[0]].astype(np.int64)
+    psi = o.psi0_on(k0)
+    for st in range(12):
+        ka = keys[offs[st]: offs[st + 1]].astype(np.int64)
+        kb = keys[offs[st + 1]: offs[st + 2]].astype(np.int64)
+        psi = sla.expm(-1j * cd["dt"] * H[np.ix_(ka, ka)]) @ psi
+        pos = {int(k): i for i, k in enumerate(ka)}
+        psi = np.array([psi[pos[int(k)]] if int(k) in pos else 0j for k in kb])
+    f = orc.Oracle(cd)
+    f.set_state(keys[: sizes[0]], f.psi0_on(keys[: sizes[0]]))
+    f.propagate_frozen(sizes, keys, m=16)
+    kf, cf = f.state()
+    assert np.array_equal(kf.astype(np.int64), keys[offs[12]: offs[13]].astype(np.int64))
+    assert np.max(np.abs(cf - psi)) < 1e-11
+
+
+def test_fd_gradient_is_converged():
+    """Central differences at two step sizes agree (the reference is smooth and resolved)."""
+    from oracle import adjoint as adj
+    cd = card("small_adjoint4d", nsteps=6)
+    sizes, keys = adj.record_sets(cd)
+    names = ["D0", "a1", "lam01", "centre0", "momentum2"]
+    g1 = adj.fd_gradient(cd, names, sizes, keys, rel=1e-5)
+    g2 = adj.fd_gradient(cd, names, sizes, keys, rel=1e-4)
+    scale = max(abs(v) for v in g1.values())
+    for nm in names:
+        assert abs(g1[nm] - g2[nm]) < 1e-6 * scale, nm

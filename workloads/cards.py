@@ -130,9 +130,13 @@ def _adjoint4d():
     params = ([f"D{k}" for k in range(4)] + [f"a{k}" for k in range(4)]
               + [f"lam{k}{l}" for (k, l) in ordered]
               + [f"centre{k}" for k in range(4)] + [f"momentum{k}" for k in range(4)])
+    # where each potential parameter sits in the term list
+    trainable = ([{"name": f"D{k}", "term": k, "what": "coef"} for k in range(4)]
+                 + [{"name": f"a{k}", "term": k, "what": "a", "factor": 0} for k in range(4)]
+                 + [{"name": f"lam{k}{l}", "term": 4 + i, "what": "coef"} for i, (k, l) in enumerate(ordered)])
     return {
         "name": "adjoint4d", "D": 4, "n": [32] * 4, "lo": [-3.0] * 4, "hi": [9.0] * 4,
-        "mass": 1.0, "terms": terms, "basis": "dvr", "params": params,
+        "mass": 1.0, "terms": terms, "basis": "dvr", "params": params, "trainable": trainable,
         "psi0": {"centre": [0.5, 0.0, 0.0, 0.0], "momentum": [0.0] * 4, "width": [0.5] * 4},
         "eps": 1e-6, "dt": 0.05, "nsteps": 2000, "krylov": 10, "checkpoint_every": 50,
     }
@@ -153,6 +157,7 @@ def card(name, **overrides):
       small_3d  -> a 3D coupled anharmonic model on 9x11x10 points
       small_4d  -> the 4D Morse model on 10 points per dimension
       small_6d  -> the 6D quartic model on 7 points per dimension
+      small_adjoint4d -> the adjoint card on 10 points per dimension, 20 steps
     """
     if name in _BUILDERS:
         c = _BUILDERS[name]()
@@ -178,6 +183,9 @@ def card(name, **overrides):
     elif name == "small_4d":
         c = _morse4d(n=10)
         c.update({"name": "small_4d", "eps": 1e-4, "nsteps": 30})
+    elif name == "small_adjoint4d":
+        c = _adjoint4d()
+        c.update({"name": "small_adjoint4d", "n": [10] * 4, "eps": 1e-4, "nsteps": 20, "checkpoint_every": 5})
     elif name == "small_6d":
         c = _quartic6d(n=7)
         c.update({"name": "small_6d", "eps": 1e-4, "nsteps": 10})
