@@ -97,6 +97,7 @@ struct ppq_ctx {
     // built operator (device)
     double *T64[MAXD]{};   // real factor per DVR dimension (kinetic), nb x nb
     float *T32[MAXD]{};
+    float *T32p[MAXD]{};  // FP32 factor zero-padded to 64 x 64 (matrix-core tiles)
     double2 *H64[MAXD]{};  // complex factor per lattice dimension
     float2 *H32[MAXD]{};
     std::vector<double2 *> F64;  // distinct dense factors of product terms
@@ -244,6 +245,7 @@ void free_operator(ppq_ctx *c)
     for (int k = 0; k < MAXD; ++k) {
         dfree(c->T64[k]);
         dfree(c->T32[k]);
+        dfree(c->T32p[k]);
         dfree(c->H64[k]);
         dfree(c->H32[k]);
     }
@@ -389,6 +391,7 @@ void build_operator(ppq_ctx *c)
     for (int k = 0; k < MAXD; ++k) {
         dfree(c->T64[k]);
         dfree(c->T32[k]);
+        dfree(c->T32p[k]);
         dfree(c->H64[k]);
         dfree(c->H32[k]);
     }
@@ -416,6 +419,10 @@ void build_operator(ppq_ctx *c)
                 }
             c->T64[k] = upload(P, s);
             c->T32[k] = upload(Pf, s);
+            std::vector<float> P64((size_t)64 * 64, 0.0f);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) P64[(size_t)i * 64 + j] = (float)T[(size_t)i * n + j];
+            c->T32p[k] = upload(P64, s);
         }
         // diagonal potential: one table per factor
         int nmax = 0;
@@ -673,12 +680,12 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
                 for (int k = D - 2; k >= 0; --k)
                     hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
             } else {
+                // complex FP32 on the matrix cores, every dimension
                 const float2 *x = (const float2 *)xv;
                 float2 *y = (float2 *)yv;
-                hpsi_pt_f32(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T32[D - 1], x, c->V32, y, true, skip_if,
-                            skip_j, s);
+                hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
                 for (int k = D - 2; k >= 0; --k)
-                    hpsi_real_f32(pass_of(c, k), c->T32[k], x, nullptr, y, false, skip_if, skip_j, s);
+                    hpsi_mfma_f32(pass_of(c, k), c->T32p[k], x, nullptr, y, false, skip_if, skip_j, s);
             }
             return;
         }

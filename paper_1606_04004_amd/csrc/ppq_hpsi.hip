@@ -437,6 +437,116 @@ void launch_pt(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, con
 #undef L
 }
 
+// ---- complex-FP32 form on the matrix cores ------------------------------------
+// A wavefront takes 16 consecutive fibers.  Their union of digits fixes a
+// window of 16*NT digits; the contraction Y = h_window X is a 16*NT x 16*NT
+// by 16*NT x 16 dense product per real/imaginary part, issued as
+// v_mfma_f32_16x16x4f32 tiles: A = a 16x4 block of h (lane i + 16 k holds
+// h[row i][digit k]), B = the fibers' values at 4 digits (lane j + 16 k holds
+// fiber j at digit k), accumulator D[4 (l/16) + r][l % 16] in register r of
+// lane l.  FP32 accumulation.  h is stored zero-padded to 64 x 64.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int MFB = 256;  // 4 wavefronts, 64 fibers per block
+constexpr int MFP = 64;   // padded size of h
+
+template <int NT, bool FIRST, bool IDENT>
+__device__ __forceinline__ void body_mfma(uint32_t o, uint64_t m, int ws, int lane,
+                                          const uint32_t *__restrict__ pi, const float *__restrict__ T,
+                                          const float2 *__restrict__ x, const float *__restrict__ V,
+                                          float2 *__restrict__ y)
+{
+    const int col = lane & 15, kr = lane >> 4;
+    constexpr int NK = 4 * NT;
+    // The contraction index is taken in the order digit(kb, k) = ws + 16 (kb/4)
+    // + 4 k + kb % 4, so the digits a lane feeds as B over the k-steps are
+    // exactly the digits it holds in the accumulator: one position per digit.
+    uint32_t pp[NK];
+    float2 xin[NK], yold[NK];
+    float vv[NK];
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb) {
+        const int d = ws + 16 * (kb >> 2) + 4 * kr + (kb & 3);
+        pp[kb] = 0xffffffffu;
+        if ((m >> d) & 1ull) {
+            uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << d) - 1ull));
+            pp[kb] = IDENT ? pos : pi[pos];
+        }
+    }
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb) {
+        xin[kb] = make_float2(0.f, 0.f);
+        yold[kb] = make_float2(0.f, 0.f);
+        vv[kb] = 0.f;
+        if (pp[kb] != 0xffffffffu) {
+            xin[kb] = x[pp[kb]];
+            if (FIRST) vv[kb] = V[pp[kb]];
+            else yold[kb] = y[pp[kb]];
+        }
+    }
+    floatx4 accr[NT], acci[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        accr[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb) {
+        const int j = ws + 16 * (kb >> 2) + 4 * kr + (kb & 3);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float a = T[(ws + 16 * t + col) * MFP + j];
+            accr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xin[kb].x, accr[t], 0, 0, 0);
+            acci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xin[kb].y, acci[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int kb = 4 * t + r;  // output digit ws + 16 t + 4 kr + r
+            if (pp[kb] != 0xffffffffu) {
+                float ar = accr[t][r], ai = acci[t][r];
+                if (FIRST) y[pp[kb]] = make_float2(fmaf(vv[kb], xin[kb].x, ar), fmaf(vv[kb], xin[kb].y, ai));
+                else y[pp[kb]] = make_float2(yold[kb].x + ar, yold[kb].y + ai);
+            }
+        }
+    }
+}
+
+template <bool FIRST, bool IDENT>
+__global__ __launch_bounds__(MFB) void k_hpsi_mfma(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
+                                                   const uint64_t *__restrict__ mask, int64_t nf,
+                                                   const float *__restrict__ T, const float2 *__restrict__ x,
+                                                   const float *__restrict__ V, float2 *__restrict__ y,
+                                                   const int *skip_if, int skip_j)
+{
+    if (skip_if && skip_j >= *skip_if) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t f = ((int64_t)blockIdx.x * (MFB / 64) + (threadIdx.x >> 6)) * 16 + (lane & 15);
+    uint64_t m = 0;
+    uint32_t o = 0;
+    if (f < nf) {
+        m = mask[f];
+        o = off[f];
+    }
+    const uint64_t wm = wave_or64(m);
+    if (wm == 0) return;
+    const int wlo = __ffsll((unsigned long long)wm) - 1;
+    const int whi = 63 - __clzll((long long)wm);
+    const int width = whi - wlo + 1;
+#define PPQ_MF(NT)                                                              \
+    {                                                                           \
+        const int ws = wlo < MFP - 16 * (NT) ? wlo : MFP - 16 * (NT);           \
+        body_mfma<NT, FIRST, IDENT>(o, m, ws, lane, pi, T, x, V, y);            \
+        return;                                                                 \
+    }
+    if (width <= 16) PPQ_MF(1)
+    if (width <= 32) PPQ_MF(2)
+    if (width <= 48) PPQ_MF(3)
+    PPQ_MF(4)
+#undef PPQ_MF
+}
+
 inline unsigned fblocks(int64_t nf)
 {
     int64_t b = (nf + HB - 1) / HB;
@@ -545,6 +655,25 @@ void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *
                   hipStream_t s)
 {
     launch_acc<float>(fp, T, x, y, skip_if, skip_j, s);
+}
+
+void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (fp.nf <= 0) return;
+    const unsigned nb = (unsigned)((fp.nf + 63) / 64);
+    const bool ident = fp.pi == nullptr;
+#define L(F, I) \
+    hipLaunchKernelGGL((k_hpsi_mfma<F, I>), dim3(nb), dim3(MFB), 0, s, fp.pi, fp.off, fp.mask, fp.nf, T64, x, V, y, \
+                       skip_if, skip_j)
+    if (first) {
+        if (ident) L(true, true);
+        else L(true, false);
+    } else {
+        if (ident) L(false, true);
+        else L(false, false);
+    }
+#undef L
 }
 
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,

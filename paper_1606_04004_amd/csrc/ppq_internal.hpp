@@ -117,6 +117,9 @@ void hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double
                   hipStream_t s);
 void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
                   hipStream_t s);
+// complex-FP32 form on the matrix cores; T64 is h zero-padded to 64 x 64
+void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s);
 // FP32 forms
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);

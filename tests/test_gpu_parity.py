@@ -281,6 +281,29 @@ def test_shadow_steps_morse4d(torch):
     assert worst < 1e-12
 
 
+def test_lattice_full_card(torch):
+    """4D lattice card at full size (48^4 functions, 6x8 lattice per dimension,
+    dense complex 48x48 factors, Arnoldi): identical sets and observables."""
+    cd = card("pvb4d")
+    say("pvb4d: 3 steps")
+    o = Oracle(cd)
+    o.init_state()
+    g = make(cd, torch)
+    n = g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=3)
+    tg = g.propagate(nsteps=3)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 2, 3, 4, 6):
+        d = np.max(np.abs(tg[:, col] - tr[:, col]))
+        say(f"  col {col}: {d:.2e}")
+        assert d < 1e-10
+    kg, cg = g.state()
+    ko, co = o.state()
+    assert np.array_equal(kg, ko)
+    assert np.max(np.abs(cg - co)) < 1e-11
+
+
 def test_lattice_trajectory(torch):
     """Phase-space lattice (biorthogonal projected von Neumann), Arnoldi, lattice stencil."""
     cd = lattice_card(eps=1e-4)
