@@ -35,7 +35,7 @@ def bytes_per_point(D, precision):
     return 2 * sc + 4 * D
 
 
-def cpu_baseline(cd, reps=10):
+def cpu_baseline(cd, reps=50):
     """The FP64 oracle (one thread) applying H on its own initial set of the card."""
     from oracle.oracle import Oracle
     o = Oracle(cd)
