@@ -129,7 +129,17 @@ struct ppq_ctx {
     uint64_t *mask[MAXD]{};
     uint8_t *info[MAXD]{};
     int64_t nf[MAXD]{};
-    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides, for measurement)
+    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides; 4 = block-fused)
+
+    // block-fused H*psi: outer dimensions [0, split) through the inner-first
+    // frame, inner dimensions [split, D) in the row-major frame
+    int split = 0;
+    bool block_ok = false;    // the operator and grid admit the block form
+    bool block_mode = false;  // the current set's tables are built for it
+    uint32_t *P_R = nullptr, *inv_R = nullptr;
+    uint32_t *chunk[2]{}, *big[2]{};
+    uint32_t *fch[MAXD]{};  // first fiber of each chunk, per dimension
+    uint32_t nch[2]{}, nbig[2]{}, maxch[2]{};
 
     // work
     uint32_t *flags = nullptr, *fidx = nullptr;
@@ -227,6 +237,13 @@ void free_state_buffers(ppq_ctx *c)
     dfree(c->fidx);
     dfree(c->tmpmask);
     dfree(c->scan_tmp);
+    dfree(c->P_R);
+    dfree(c->inv_R);
+    for (int i = 0; i < 2; ++i) {
+        dfree(c->chunk[i]);
+        dfree(c->big[i]);
+    }
+    for (int k = 0; k < MAXD; ++k) dfree(c->fch[k]);
     c->cap = 0;
 }
 
@@ -299,6 +316,13 @@ void ensure_capacity(ppq_ctx *c, int64_t n)
     c->tmpmask = dalloc<uint64_t>(nc);
     c->scan_tmp_n = std::max(scan_tmp_words(nc), scan_tmp_words(c->nwords));
     c->scan_tmp = dalloc<uint32_t>(c->scan_tmp_n);
+    c->P_R = dalloc<uint32_t>(nc);
+    c->inv_R = dalloc<uint32_t>(nc);
+    for (int i = 0; i < 2; ++i) {
+        c->chunk[i] = dalloc<uint32_t>(nc / BLOCK_WINDOW + 2);
+        c->big[i] = dalloc<uint32_t>(nc / BLOCK_WINDOW + 2);
+    }
+    for (int k = 0; k < c->g.D; ++k) c->fch[k] = dalloc<uint32_t>(nc / BLOCK_WINDOW + 2);
     c->derived_valid = false;
     free_krylov(c);
 }
@@ -603,6 +627,50 @@ void build_operator(ppq_ctx *c)
 }
 
 // ---- derived tables of the current set --------------------------------------
+// Row-major fiber tables of dimension k (k < D - 1): pi_k, off_k, mask_k, info_k.
+void build_row_major(ppq_ctx *c, int k)
+{
+    const int64_t n = c->nact;
+    hipStream_t s = c->stream;
+    const uint32_t *keys = c->keys[c->cur];
+    const RotFrame fr = row_major_rot(c->g, k);
+    fill_u64(c->bm, c->nwords + 2, 0ull, s);
+    rot_set(keys, n, fr, c->bm, s);
+    scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
+    rot_rank(keys, n, fr, c->bm, c->prefix, nullptr, c->pi[k], nullptr, c->flags, c->tmpmask, c->info[k], s);
+    scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
+    fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
+}
+
+// Tables of the outer dimensions [0, split) in the inner-first frame (digit
+// order: inner digits, then outer digits): P_R (frame rank -> position) and,
+// per outer dimension, fibers in frame ranks (the last outer dimension is the
+// frame's last digit, so its fibers are contiguous runs of the frame).
+void build_inner_first(ppq_ctx *c)
+{
+    const int64_t n = c->nact;
+    hipStream_t s = c->stream;
+    const uint32_t *keys = c->keys[c->cur];
+    const int sp = c->split;
+    const uint32_t sin = c->g.stride[sp - 1];
+    const uint32_t sout = c->g.total / sin;
+    for (int k = sp - 1; k >= 0; --k) {
+        const RotFrame fr{c->g.stride[k] / sin, (uint32_t)c->g.n[k], sin, sout};
+        const bool frame = (k == sp - 1);
+        fill_u64(c->bm, c->nwords + 2, 0ull, s);
+        rot_set(keys, n, fr, c->bm, s);
+        scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
+        rot_rank(keys, n, fr, c->bm, c->prefix, frame ? nullptr : c->inv_R, frame ? c->P_R : c->pi[k],
+                 frame ? c->inv_R : nullptr, c->flags, c->tmpmask, c->info[k], s);
+        scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
+        fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
+        if (frame)
+            make_chunks(keys, c->P_R, n, sin, true, BLOCK_WINDOW, block_cap_small(c->precision), c->chunk[1],
+                        c->big[1], c->small + 2 * MAXD + 2, s);
+        chunk_fibers(c->chunk[1], n, BLOCK_WINDOW, c->fidx, &c->small[k], c->fch[k], s);
+    }
+}
+
 void build_derived(ppq_ctx *c)
 {
     if (c->derived_valid) return;
@@ -611,27 +679,77 @@ void build_derived(ppq_ctx *c)
     const int64_t n = c->nact;
     hipStream_t s = c->stream;
     const uint32_t *keys = c->keys[c->cur];
+    const bool try_block = c->block_ok && c->hpsi_variant == 4 && n > 0;
+    if (try_block) {
+        fill_u32(c->small + 2 * MAXD, 4, 0u, s);
+        make_chunks(keys, nullptr, n, c->g.stride[c->split - 1], false, BLOCK_WINDOW, block_cap_small(c->precision),
+                    c->chunk[0], c->big[0], c->small + 2 * MAXD, s);
+    }
     // last dimension: contiguous runs
     last_flags(keys, n, c->g.n[D - 1], c->flags, s);
     scan_u32(c->flags, n, c->fidx, &c->small[D - 1], c->scan_tmp, s);
     last_fill(keys, n, c->g.n[D - 1], c->flags, c->fidx, &c->small[D - 1], c->off[D - 1], c->mask[D - 1], s);
     last_info(keys, n, c->g.n[D - 1], c->info[D - 1], s);
-    for (int k = 0; k < D - 1; ++k) {
-        fill_u64(c->bm, c->nwords + 2, 0ull, s);
-        rot_set(keys, n, k, c->g, c->bm, s);
-        scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
-        rot_rank(keys, n, k, c->g, c->bm, c->prefix, c->pi[k], c->flags, c->tmpmask, c->info[k], s);
-        scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
-        fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
+    if (try_block) chunk_fibers(c->chunk[0], n, BLOCK_WINDOW, c->fidx, &c->small[D - 1], c->fch[D - 1], s);
+    for (int k = try_block ? c->split : 0; k < D - 1; ++k) {
+        build_row_major(c, k);
+        if (try_block) chunk_fibers(c->chunk[0], n, BLOCK_WINDOW, c->fidx, &c->small[k], c->fch[k], s);
     }
+    if (try_block) build_inner_first(c);
     if (!c->any_lattice) {
         PotDesc pd{c->pot_nterm, D, c->pot_nmax, c->pot_coef, c->pot_tab, c->pot_tabs, c->pot_ntab};
         potential(keys, n, c->g, pd, c->V64, c->V32, s);
     }
-    ck(hipMemcpyAsync(c->h_small, c->small, sizeof(uint32_t) * 2 * MAXD, hipMemcpyDeviceToHost, s), "nf");
+    ck(hipMemcpyAsync(c->h_small, c->small, sizeof(uint32_t) * (2 * MAXD + 4), hipMemcpyDeviceToHost, s), "nf");
     ck(hipStreamSynchronize(s), "fibers");
     for (int k = 0; k < D; ++k) c->nf[k] = n > 0 ? c->h_small[k] : 0;
+    c->block_mode = false;
+    if (try_block) {
+        const uint32_t *cnt = c->h_small + 2 * MAXD;
+        for (int i = 0; i < 2; ++i) {
+            c->nch[i] = (uint32_t)((n + BLOCK_WINDOW - 1) / BLOCK_WINDOW);
+            c->nbig[i] = cnt[2 * i];
+            c->maxch[i] = cnt[2 * i + 1];
+        }
+        const int npi_inner = D - c->split - 1, npi_outer = c->split - 1;
+        c->block_mode = c->maxch[0] <= block_cap_max(c->precision, npi_inner) &&
+                        c->maxch[1] <= block_cap_max(c->precision, npi_outer);
+        if (std::getenv("PPQ_BLOCK_STATS"))
+            std::fprintf(stderr, "[ppq] block chunks: inner nbig %u max %u, outer nbig %u max %u, mode %d\n",
+                         c->nbig[0], c->maxch[0], c->nbig[1], c->maxch[1], (int)c->block_mode);
+        if (!c->block_mode) {
+            // a chunk too long for LDS: row-major tables for the outer dimensions
+            for (int k = 0; k < c->split; ++k) build_row_major(c, k);
+            ck(hipStreamSynchronize(s), "fibers");
+        }
+    }
     c->derived_valid = true;
+}
+
+BlockPass block_pass(const ppq_ctx *c, int which)
+{
+    BlockPass bp{};
+    const int D = c->g.D, sp = c->split;
+    const int k0 = which == 0 ? sp : 0, k1 = which == 0 ? D : sp;
+    bp.ndim = k1 - k0;
+    for (int i = 0; i < bp.ndim; ++i) {
+        const int k = k0 + i;
+        bp.dim[i] = k;
+        bp.pi[i] = (k == k1 - 1) ? nullptr : c->pi[k];
+        bp.off[i] = c->off[k];
+        bp.mask[i] = c->mask[k];
+        bp.fch[i] = c->fch[k];
+        bp.nf[i] = c->nf[k];
+        bp.nb[i] = c->nb[k];
+    }
+    bp.chunk = c->chunk[which];
+    bp.nch = c->nch[which];
+    bp.P = which == 0 ? nullptr : c->P_R;
+    bp.big = c->big[which];
+    bp.nbig = c->nbig[which];
+    bp.cap_small = block_cap_small(c->precision);
+    bp.cap_big = bp.nbig ? (c->maxch[which] + 63u) / 64u * 64u : 0u;
+    return bp;
 }
 
 FiberPass pass_of(const ppq_ctx *c, int k)
@@ -652,6 +770,25 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
     hipStream_t s = c->stream;
     if (c->nact == 0) return;
     if (!c->any_lattice) {
+        if (c->block_mode) {
+            // inner-first pass over the outer dimensions writes y, the row-major
+            // pass over the inner dimensions adds to it with the potential fused
+            const BlockPass outer = block_pass(c, 1), inner = block_pass(c, 0);
+            if (c->precision == PPQ_FP64) {
+                const double *To[BLOCK_MAXDIM], *Ti[BLOCK_MAXDIM];
+                for (int i = 0; i < outer.ndim; ++i) To[i] = c->T64[outer.dim[i]];
+                for (int i = 0; i < inner.ndim; ++i) Ti[i] = c->T64[inner.dim[i]];
+                hpsi_block_f64(outer, To, (const double2 *)xv, nullptr, (double2 *)yv, false, skip_if, skip_j, s);
+                hpsi_block_f64(inner, Ti, (const double2 *)xv, c->V64, (double2 *)yv, true, skip_if, skip_j, s);
+            } else {
+                const float *To[BLOCK_MAXDIM], *Ti[BLOCK_MAXDIM];
+                for (int i = 0; i < outer.ndim; ++i) To[i] = c->T32[outer.dim[i]];
+                for (int i = 0; i < inner.ndim; ++i) Ti[i] = c->T32[inner.dim[i]];
+                hpsi_block_f32(outer, To, (const float2 *)xv, nullptr, (float2 *)yv, false, skip_if, skip_j, s);
+                hpsi_block_f32(inner, Ti, (const float2 *)xv, c->V32, (float2 *)yv, true, skip_if, skip_j, s);
+            }
+            return;
+        }
         if (c->hpsi_variant == 3) {
             const int64_t n = c->nact;
             if (c->precision == PPQ_FP64) {
@@ -669,14 +806,19 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
             }
             return;
         }
-        if (c->hpsi_variant == 2) {
-            // point-parallel for the contiguous last dimension, lane per fiber elsewhere
+        if (c->hpsi_variant == 2 || c->hpsi_variant == 4) {
+            // last dimension: point-parallel over its contiguous runs while fibers
+            // are short, one lane per fiber once they average more than 16 points;
+            // lane per fiber elsewhere
             const int64_t n = c->nact;
             if (c->precision == PPQ_FP64) {
                 const double2 *x = (const double2 *)xv;
                 double2 *y = (double2 *)yv;
-                hpsi_pt_f64(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T64[D - 1], x, c->V64, y, true, skip_if,
-                            skip_j, s);
+                if (c->nf[D - 1] > 0 && n > 16 * c->nf[D - 1])
+                    hpsi_real_f64(pass_of(c, D - 1), c->T64[D - 1], x, c->V64, y, true, skip_if, skip_j, s);
+                else
+                    hpsi_pt_f64(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T64[D - 1], x, c->V64, y, true,
+                                skip_if, skip_j, s);
                 for (int k = D - 2; k >= 0; --k)
                     hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
             } else {
@@ -1205,7 +1347,7 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
         c->partial = dalloc<double2>((int64_t)RED_BLOCKS * PSTRIDE_H);
         c->counter = dalloc<unsigned>(4);
         ck(hipMemset(c->counter, 0, 4 * sizeof(unsigned)), "counter");
-        c->small = dalloc<uint32_t>(4 * MAXD);
+        c->small = dalloc<uint32_t>(4 * MAXD);  // fiber counts, scan totals, block counters
         c->count = dalloc<unsigned long long>(2);
         ck(hipHostMalloc((void **)&c->h_small, sizeof(uint32_t) * 4 * MAXD, hipHostMallocDefault), "pinned");
         ck(hipHostMalloc((void **)&c->h_count, sizeof(unsigned long long) * 2, hipHostMallocDefault), "pinned");
@@ -1322,6 +1464,9 @@ int ppq_set_grid(ppq_ctx *c, int D, const int32_t *n, const double *lo, const do
             c->lattice[k] = false;
         }
         c->mass = mass;
+        c->split = D / 2;
+        c->block_ok = D >= 2 && D - c->split <= BLOCK_MAXDIM;
+        for (int k = 0; k < D; ++k) c->block_ok = c->block_ok && c->nb[k] <= BLOCK_MAXNB;
         int nmax = 0;
         for (int k = 0; k < D; ++k) nmax = std::max(nmax, n[k]);
         std::vector<double2> zt((size_t)D * nmax, make_double2(0.0, 0.0));
@@ -1359,6 +1504,7 @@ int ppq_set_lattice(ppq_ctx *c, int k, int ns, int nl)
     c->g.lat_l[k] = nl;
     c->lattice[k] = true;
     c->any_lattice = true;
+    c->block_ok = false;
     c->op_dirty = true;
     c->derived_valid = false;
     return PPQ_OK;

@@ -18,6 +18,8 @@
 // wave-uniform and is read through the scalar cache, so the contraction is
 // W^2 FMA pairs per lane with no LDS traffic.  Output positions are
 // recomputed per row (they hit in cache) so the row loop can stay rolled.
+#include <algorithm>
+
 #include "ppq_internal.hpp"
 
 namespace ppq {
@@ -606,6 +608,285 @@ void launch_cplx(const FiberPass &fp, const typename Cx<R>::T *H, const CArgs<R>
 #undef L
 }
 
+
+// ---- block-fused form ----------------------------------------------------------
+// The state is cut into blocks of points that share the digits of the
+// dimensions NOT handled by the pass; a block then holds every fiber of the
+// pass's dimensions through its points.  In the row-major frame the blocks
+// are contiguous runs of the key-sorted state (the pass over the inner
+// dimensions); in the inner-first frame they are reached through the
+// permutation P (the pass over the outer dimensions).  Each dimension's
+// fiber order keeps the block's leading digits first, so a block occupies the
+// same rank range in the frame and in every fiber order of the pass.
+//
+// A workgroup takes a chunk of whole blocks, stages x (and y when
+// accumulating, plus V x when the potential is fused) in LDS, applies the
+// pass's 1D factors one dimension after the other with one lane per fiber
+// (x and y from LDS, the factor's window block through the scalar cache),
+// and writes y back once: x is read once and y written once per pass instead
+// of once per dimension.
+
+template <class R>
+struct BlockArgs {
+    int ndim;
+    const uint32_t *pi[4];
+    const uint32_t *off[4];
+    const uint64_t *mask[4];
+    const uint32_t *fch[4];
+    const R *T[4];
+    int nb[4];
+    const uint32_t *chunk;
+    uint32_t nch;
+    const uint32_t *P;
+    const uint32_t *list;
+    uint32_t cap;
+    int accumulate;
+    const R *V;
+};
+
+// One fiber, one group of 8 output rows: rows ws + 8g .. ws + 8g + 7 of the
+// window [ws, ws + W), summed over the window's columns in blocks of 8
+// inputs (the factor's entries are wave-uniform and come through the scalar
+// cache); the 8 row sums stay in registers and are added to y in LDS once.
+constexpr int RG = 4;  // output rows per wave task
+constexpr int CB = 8;  // window columns per register block
+
+template <class R, int W>
+__device__ __forceinline__ void body_block(uint32_t o, uint64_t m, int ws, int g, uint32_t last, const uint16_t *lp,
+                                           const R *__restrict__ T, int nb, const typename Cx<R>::T *xs,
+                                           typename Cx<R>::T *ys)
+{
+    using C = typename Cx<R>::T;
+    R ar[RG], ai[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+        ar[r] = 0;
+        ai[r] = 0;
+    }
+    // the factor is read-only for the kernel's lifetime: constant address
+    // space, so the wave-uniform entries load through the scalar cache
+    using CR = __attribute__((address_space(4))) const R;
+    CR *Tg = (CR *)(T + (ws + g * RG) * nb + ws);
+    // member loads without branches: absent digits read a valid slot and are
+    // zeroed, so each group of 8 LDS reads is issued back to back
+#pragma unroll 1
+    for (int cb = 0; cb < W / CB; ++cb) {
+        uint32_t q[CB];
+        bool on[CB];
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) {
+            const int j = ws + cb * CB + jj;
+            on[jj] = (m >> j) & 1ull;
+            const uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << j) - 1ull));
+            q[jj] = on[jj] ? pos : (o < last ? o : last);
+        }
+        if (lp) {
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) q[jj] = lp[q[jj]];
+        }
+        C xw[CB];
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) {
+            const C v = xs[q[jj]];
+            xw[jj] = on[jj] ? v : Cx<R>::make(0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            CR *Tr = Tg + r * nb + cb * CB;
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) {
+                const R t = Tr[jj];
+                ar[r] = fma(t, xw[jj].x, ar[r]);
+                ai[r] = fma(t, xw[jj].y, ai[r]);
+            }
+        }
+    }
+    uint32_t q[RG];
+    bool on[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+        const int l = ws + g * RG + r;
+        on[r] = (m >> l) & 1ull;
+        const uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << l) - 1ull));
+        q[r] = on[r] ? pos : (o < last ? o : last);
+    }
+    if (lp) {
+#pragma unroll
+        for (int r = 0; r < RG; ++r) q[r] = lp[q[r]];
+    }
+    C v[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) v[r] = ys[q[r]];
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+        if (on[r]) ys[q[r]] = Cx<R>::make(v[r].x + ar[r], v[r].y + ai[r]);
+}
+
+template <class T4>
+__device__ __forceinline__ T4 pick4(const T4 (&v)[4], int d)
+{
+    return d == 0 ? v[0] : d == 1 ? v[1] : d == 2 ? v[2] : v[3];
+}
+
+// Every global load of a chunk (P, the fiber-order ranks of each dimension,
+// each wave's first fiber batch per dimension, then x, y and V through P) is
+// issued before the first LDS store, so a chunk waits for memory about three
+// times instead of three times per dimension.  NT * SU >= the launch's cap.
+template <class R, int NBMAX, int NT, int SU>
+__global__ __launch_bounds__(NT) void k_hpsi_block(BlockArgs<R> a, const typename Cx<R>::T *__restrict__ x,
+                                                   typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
+{
+    using C = typename Cx<R>::T;
+    if (skip_if && skip_j >= *skip_if) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t ci;
+    if (a.list) {
+        ci = a.list[blockIdx.x];
+    } else {
+        // consecutive chunks on one XCD (workgroups are dealt round-robin over 8)
+        const uint32_t per = (a.nch + 7) / 8, i = blockIdx.x >> 3;
+        ci = (blockIdx.x & 7) * per + i;
+        if (i >= per || ci >= a.nch) return;
+    }
+    const uint32_t c0 = a.chunk[ci], c1 = a.chunk[ci + 1], len = c1 - c0;
+    if (len == 0 || len > a.cap) return;
+    C *xs = reinterpret_cast<C *>(smem);
+    C *ys = xs + a.cap;
+    uint16_t *lpb = reinterpret_cast<uint16_t *>(ys + a.cap);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int nd = a.ndim;
+
+    uint32_t p[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const uint32_t i = u * NT + tid;
+        p[u] = i < len ? (a.P ? a.P[c0 + i] : c0 + i) : 0xffffffffu;
+    }
+    // fiber-order ranks -> local frame ranks, dimensions with a permutation
+    uint32_t q[3][SU];
+    int slot[4];
+    int ns = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        slot[d] = -1;
+        if (d < nd && a.pi[d]) {
+            slot[d] = ns;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const uint32_t i = u * NT + tid;
+                if (ns == 0) q[0][u] = i < len ? a.pi[d][c0 + i] - c0 : 0u;
+                else if (ns == 1) q[1][u] = i < len ? a.pi[d][c0 + i] - c0 : 0u;
+                else q[2][u] = i < len ? a.pi[d][c0 + i] - c0 : 0u;
+            }
+            ++ns;
+        }
+    }
+    // first fiber batch of this wave in every dimension
+    uint32_t fa[4], fb[4], o0[4];
+    uint64_t m0[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        fa[d] = fb[d] = 0;
+        m0[d] = 0;
+        o0[d] = 0;
+        if (d < nd) {
+            fa[d] = a.fch[d][ci];
+            fb[d] = a.fch[d][ci + 1];
+            const uint32_t f = fa[d] + (uint32_t)(wave / (a.nb[d] / RG)) * 64 + (uint32_t)lane;
+            if (f < fb[d]) {
+                m0[d] = a.mask[d][f];
+                o0[d] = a.off[d][f] - c0;
+            }
+        }
+    }
+    {
+        C xv[SU], yv[SU];
+        R vv[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            xv[u] = Cx<R>::make(0, 0);
+            yv[u] = Cx<R>::make(0, 0);
+            vv[u] = 0;
+            if (p[u] != 0xffffffffu) {
+                xv[u] = x[p[u]];
+                if (a.accumulate) yv[u] = y[p[u]];
+                if (a.V) vv[u] = a.V[p[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const uint32_t i = u * NT + tid;
+            if (i < len) {
+                xs[i] = xv[u];
+                ys[i] = a.V ? Cx<R>::make(fma(vv[u], xv[u].x, yv[u].x), fma(vv[u], xv[u].y, yv[u].y)) : yv[u];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < ns) lpb[k * a.cap + i] = (uint16_t)q[k][u];
+            }
+        }
+    }
+    __syncthreads();
+    for (int d = 0; d < nd; ++d) {
+        const uint32_t *off = a.off[d];
+        const int sl = d == 0 ? slot[0] : d == 1 ? slot[1] : d == 2 ? slot[2] : slot[3];
+        const uint16_t *lq = sl >= 0 ? lpb + sl * a.cap : nullptr;
+        const uint32_t f0 = pick4(fa, d), f1 = pick4(fb, d);
+        const R *T = a.T[d];
+        const int nb = a.nb[d];
+        const int G = nb / RG;
+        const uint64_t *mk = a.mask[d];
+        // wave tasks: (batch of 64 consecutive fibers, group of 8 output rows)
+        const uint32_t ntask = (f1 - f0 + 63) / 64 * (uint32_t)G;
+        for (uint32_t task = (uint32_t)wave; task < ntask; task += NT / 64) {
+            const uint32_t batch = task / (uint32_t)G;
+            const int g = (int)(task - batch * (uint32_t)G);
+            uint64_t m;
+            uint32_t o;
+            if (batch == (uint32_t)(wave / G)) {
+                m = pick4(m0, d);
+                o = pick4(o0, d);
+            } else {
+                const uint32_t f = f0 + batch * 64 + (uint32_t)lane;
+                m = 0;
+                o = 0;
+                if (f < f1) {
+                    m = mk[f];
+                    o = off[f] - c0;
+                }
+            }
+            const uint64_t wm = wave_or64(m);
+            const int wlo = __ffsll((unsigned long long)wm) - 1;
+            const int whi = 63 - __clzll((long long)wm);
+            const int width = whi - wlo + 1;
+#define PPQ_BLK(W)                                                          \
+    {                                                                       \
+        if (g * RG >= (W)) continue;                                        \
+        const int ws = wlo < nb - (W) ? wlo : nb - (W);                     \
+        body_block<R, W>(o, m, ws, g, len - 1, lq, T, nb, xs, ys);          \
+        continue;                                                           \
+    }
+            if (width <= 8) PPQ_BLK(8)
+            if constexpr (NBMAX >= 16) {
+                if (width <= 16) PPQ_BLK(16)
+            }
+            if constexpr (NBMAX >= 24) {
+                if (width <= 24) PPQ_BLK(24)
+            }
+            if constexpr (NBMAX >= 32) {
+                if (width <= 32) PPQ_BLK(32)
+            }
+#undef PPQ_BLK
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const uint32_t i = u * NT + tid;
+        if (i < len) y[p[u]] = ys[i];
+    }
+}
+
 }  // namespace
 
 void hpsi_real_f64(const FiberPass &fp, const double *T, const double2 *x, const double *V, double2 *y, bool first,
@@ -706,6 +987,90 @@ void hpsi_cplx_f32(const FiberPass &fp, const float2 *H, const CInput32 &in, flo
         a.c[i] = in.c[i];
     }
     launch_cplx<float>(fp, H, a, y, accumulate, skip_if, skip_j, s);
+}
+
+
+template <class R>
+void launch_block(const BlockPass &bp, const R *const *T, const typename Cx<R>::T *x, const R *V,
+                  typename Cx<R>::T *y, bool accumulate, const int *skip_if, int skip_j, hipStream_t s)
+{
+    using C = typename Cx<R>::T;
+    if (bp.nch == 0) return;
+    BlockArgs<R> a{};
+    a.ndim = bp.ndim;
+    int nbmax = 8;
+    for (int d = 0; d < bp.ndim; ++d) {
+        a.pi[d] = bp.pi[d];
+        a.off[d] = bp.off[d];
+        a.mask[d] = bp.mask[d];
+        a.fch[d] = bp.fch[d];
+        a.T[d] = T[d];
+        a.nb[d] = bp.nb[d];
+        nbmax = std::max(nbmax, bp.nb[d]);
+    }
+    a.chunk = bp.chunk;
+    a.nch = bp.nch;
+    a.P = bp.P;
+    a.accumulate = accumulate ? 1 : 0;
+    a.V = V;
+    int npi = 0;
+    for (int d = 0; d < bp.ndim; ++d) npi += bp.pi[d] ? 1 : 0;
+    const size_t bpp = 2 * sizeof(C) + sizeof(uint16_t) * (size_t)npi;
+    // points per thread of the two launches (NT * SU >= cap)
+    constexpr int SU_S = sizeof(R) == 8 ? 4 : 8, SU_B = sizeof(R) == 8 ? 5 : 8;
+    static bool attr_set = false;
+    if (!attr_set) {
+        const void *fns[] = {
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 8, 512, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 16, 512, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 24, 512, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 32, 512, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 8, 1024, SU_B>),
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 16, 1024, SU_B>),
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 24, 1024, SU_B>),
+            reinterpret_cast<const void *>(&k_hpsi_block<R, 32, 1024, SU_B>),
+        };
+        for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+        attr_set = true;
+    }
+    // main launch: two 512-thread workgroups per CU; long chunks: one
+    // 1024-thread workgroup per CU
+    auto go = [&](dim3 grid, uint32_t cap, bool wide) {
+        a.cap = cap;
+        const size_t lds = (size_t)cap * bpp;
+#define PPQ_GO(NB, NT, SU) \
+    hipLaunchKernelGGL((k_hpsi_block<R, NB, NT, SU>), grid, dim3(NT), lds, s, a, x, y, skip_if, skip_j)
+        if (wide) {
+            if (nbmax <= 8) PPQ_GO(8, 1024, SU_B);
+            else if (nbmax <= 16) PPQ_GO(16, 1024, SU_B);
+            else if (nbmax <= 24) PPQ_GO(24, 1024, SU_B);
+            else PPQ_GO(32, 1024, SU_B);
+        } else {
+            if (nbmax <= 8) PPQ_GO(8, 512, SU_S);
+            else if (nbmax <= 16) PPQ_GO(16, 512, SU_S);
+            else if (nbmax <= 24) PPQ_GO(24, 512, SU_S);
+            else PPQ_GO(32, 512, SU_S);
+        }
+#undef PPQ_GO
+    };
+    a.list = nullptr;
+    go(dim3(8 * ((bp.nch + 7) / 8)), bp.cap_small, false);
+    if (bp.nbig > 0) {
+        a.list = bp.big;
+        go(dim3(bp.nbig), bp.cap_big, true);
+    }
+}
+
+void hpsi_block_f64(const BlockPass &bp, const double *const *T, const double2 *x, const double *V, double2 *y,
+                    bool accumulate, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_block<double>(bp, T, x, V, y, accumulate, skip_if, skip_j, s);
+}
+
+void hpsi_block_f32(const BlockPass &bp, const float *const *T, const float2 *x, const float *V, float2 *y,
+                    bool accumulate, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_block<float>(bp, T, x, V, y, accumulate, skip_if, skip_j, s);
 }
 
 }  // namespace ppq

@@ -78,10 +78,25 @@ void last_flags(const uint32_t *keys, int64_t n, int nlast, uint32_t *flags, hip
 void last_info(const uint32_t *keys, int64_t n, int nlast, uint8_t *info, hipStream_t s);
 void last_fill(const uint32_t *keys, int64_t n, int nlast, const uint32_t *flags, const uint32_t *fidx,
                const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s);
-void rot_set(const uint32_t *keys, int64_t n, int k, const GridDesc &g, uint64_t *bm, hipStream_t s);
-void rot_rank(const uint32_t *keys, int64_t n, int k, const GridDesc &g, const uint64_t *bm,
-              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,
+// Rotated order: the frame key (see RotFrame) with the digit of stride sk and
+// size nk moved to the last place.
+struct RotFrame {
+    uint32_t sk, nk;    // stride and size of the digit moved last, within the frame key
+    uint32_t rin, rout;  // inner-first frame (S_in, total / S_in); rin == 0: row-major frame
+};
+inline RotFrame row_major_rot(const GridDesc &g, int k) { return RotFrame{g.stride[k], (uint32_t)g.n[k], 0u, 0u}; }
+void rot_set(const uint32_t *keys, int64_t n, const RotFrame &f, uint64_t *bm, hipStream_t s);
+void rot_rank(const uint32_t *keys, int64_t n, const RotFrame &f, const uint64_t *bm, const uint32_t *prefix,
+              const uint32_t *map, uint32_t *pi, uint32_t *inv, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,
               hipStream_t s);
+// chunk starts of whole blocks (see the block-fused H*psi); chunk has
+// ceil(n / S) + 1 entries
+void make_chunks(const uint32_t *keys, const uint32_t *P, int64_t n, uint32_t sin, bool inner, uint32_t S,
+                 uint32_t cap, uint32_t *chunk, uint32_t *big, uint32_t *counters, hipStream_t s);
+// out[t] = index of the first fiber of chunk t (fidx: exclusive scan of the
+// fiber start flags in the dimension's fiber order; chunk starts are fiber starts)
+void chunk_fibers(const uint32_t *chunk, int64_t n, uint32_t S, const uint32_t *fidx, const uint32_t *nf,
+                  uint32_t *out, hipStream_t s);
 void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
               const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s);
 
@@ -120,6 +135,48 @@ void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *
 // complex-FP32 form on the matrix cores; T64 is h zero-padded to 64 x 64
 void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);
+// block-fused form: one pass applies the 1D factors of up to 4 dimensions to
+// chunks of whole blocks staged in LDS (see ppq_hpsi.hip)
+constexpr int BLOCK_MAXDIM = 4;
+constexpr int BLOCK_MAXNB = 32;
+constexpr uint32_t BLOCK_WINDOW = 512;  // chunk t starts at the first block start >= t * BLOCK_WINDOW
+constexpr uint32_t LDS_BYTES = 160u * 1024u;
+// LDS per staged point: x and y (complex) and a 16-bit local rank per
+// dimension with a permutation
+inline uint32_t block_point_bytes(int precision, int npi)
+{
+    return (precision == PPQ_FP64 ? 32u : 16u) + 2u * (uint32_t)npi;
+}
+// capacity of the main launch (two 512-thread workgroups per CU: 4 or 8
+// points per thread); chunks above it go to the 1024-thread launch, which
+// holds up to 5 (FP64) or 8 (FP32) points per thread
+inline uint32_t block_cap_small(int precision) { return precision == PPQ_FP64 ? 2048u : 4032u; }
+inline uint32_t block_cap_max(int precision, int npi)
+{
+    const uint32_t lds = LDS_BYTES / block_point_bytes(precision, npi) / 64u * 64u;
+    const uint32_t thr = precision == PPQ_FP64 ? 5u * 1024u : 8u * 1024u;
+    return lds < thr ? lds : thr;
+}
+struct BlockPass {
+    int ndim;
+    int dim[BLOCK_MAXDIM];
+    const uint32_t *pi[BLOCK_MAXDIM];    // fiber-order rank -> frame rank; nullptr = identity
+    const uint32_t *off[BLOCK_MAXDIM];   // fiber starts in fiber-order ranks, off[nf] = n
+    const uint64_t *mask[BLOCK_MAXDIM];
+    const uint32_t *fch[BLOCK_MAXDIM];   // [nch + 1] first fiber of each chunk
+    int64_t nf[BLOCK_MAXDIM];
+    int nb[BLOCK_MAXDIM];                // leading dimension of the factor table
+    const uint32_t *chunk;               // [nch + 1] chunk starts (frame ranks)
+    uint32_t nch;
+    const uint32_t *P;                   // frame rank -> storage position; nullptr = identity
+    const uint32_t *big;                 // chunks longer than cap_small
+    uint32_t nbig;
+    uint32_t cap_small, cap_big;         // LDS capacity (points) of the two launches
+};
+void hpsi_block_f64(const BlockPass &bp, const double *const *T, const double2 *x, const double *V, double2 *y,
+                    bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_block_f32(const BlockPass &bp, const float *const *T, const float2 *x, const float *V, float2 *y,
+                    bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
 // FP32 forms
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);

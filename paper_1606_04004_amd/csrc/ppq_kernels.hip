@@ -335,29 +335,86 @@ __device__ inline uint64_t extract_bits(const uint64_t *bm, uint32_t base, int l
     return len == 64 ? v : (v & ((1ull << len) - 1ull));
 }
 
-__global__ void k_rot_set(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, uint64_t *bm)
+// Key of a point in the frame whose digit order is (inner digits, outer
+// digits): with S_in the product of the inner sizes and N_out = total / S_in,
+// the frame key is (key mod S_in) * N_out + key / S_in.  rin == 0 keeps the
+// row-major frame.
+__device__ inline uint32_t frame_key(uint32_t key, uint32_t rin, uint32_t rout)
+{
+    return rin ? (key % rin) * rout + key / rin : key;
+}
+
+__global__ void k_rot_set(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, uint32_t rin, uint32_t rout,
+                          uint64_t *bm)
 {
     int64_t p = gid();
     uint32_t d, rk = 0;
-    if (p < n) rk = rotate_key(keys[p], sk, nk, &d);
+    if (p < n) rk = rotate_key(frame_key(keys[p], rin, rout), sk, nk, &d);
     set_bit_wave(bm, rk, p < n);
 }
 
-__global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, const uint64_t *bm,
-                           const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, uint8_t *info)
+// q = rank of the point in the rotated order.  pi[q] receives map[p] (p when
+// map is null); inv[p] = q when inv is given.  flags/tmpmask/info describe the
+// fibers along the rotated (last) digit.
+__global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, uint32_t rin, uint32_t rout,
+                           const uint64_t *bm, const uint32_t *prefix, const uint32_t *map, uint32_t *pi,
+                           uint32_t *inv, uint32_t *flags, uint64_t *tmpmask, uint8_t *info)
 {
     int64_t p = gid();
     if (p >= n) return;
     uint32_t d;
-    uint32_t rk = rotate_key(keys[p], sk, nk, &d);
+    uint32_t rk = rotate_key(frame_key(keys[p], rin, rout), sk, nk, &d);
     uint64_t word = bm[rk >> 6];
     uint32_t q = prefix[rk >> 6] + (uint32_t)__popcll(word & ((1ull << (rk & 63)) - 1ull));
-    pi[q] = (uint32_t)p;
+    pi[q] = map ? map[p] : (uint32_t)p;
+    if (inv) inv[p] = q;
     uint64_t m = extract_bits(bm, rk - d, (int)nk);
     bool start = (m & ((1ull << d) - 1ull)) == 0;
     flags[q] = start ? 1u : 0u;
     if (start) tmpmask[q] = m;
     info[q] = (uint8_t)(d | (start ? 0x80u : 0u));
+}
+
+// Chunks of whole blocks for the block-fused H*psi.  A block is a maximal run
+// of frame positions with the same block id (key / S_in in the row-major frame,
+// key mod S_in in the inner-first frame, both non-decreasing along the frame).
+// Chunk t starts at the first block start at or after t * S, so every chunk
+// holds whole blocks; chunk[nch] = n.  counters[0] counts the chunks longer
+// than cap (their indices go to big), counters[1] is the longest chunk.
+__device__ inline uint32_t block_id(const uint32_t *keys, const uint32_t *P, uint32_t r, uint32_t sin, int inner)
+{
+    uint32_t k = keys[P ? P[r] : r];
+    return inner ? k % sin : k / sin;
+}
+
+__device__ uint32_t chunk_start(const uint32_t *keys, const uint32_t *P, uint32_t n, uint32_t sin, int inner,
+                                uint64_t st)
+{
+    if (st >= n) return n;
+    uint32_t r = (uint32_t)st;
+    uint32_t id = block_id(keys, P, r, sin, inner);
+    if (r == 0 || block_id(keys, P, r - 1, sin, inner) != id) return r;
+    uint32_t lo = r + 1, hi = n;
+    while (lo < hi) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (block_id(keys, P, mid, sin, inner) == id) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_chunks(const uint32_t *keys, const uint32_t *P, uint32_t n, uint32_t sin, int inner, uint32_t S,
+                         uint32_t nch, uint32_t cap, uint32_t *chunk, uint32_t *big, uint32_t *counters)
+{
+    int64_t t = gid();
+    if (t > nch) return;
+    uint32_t a = chunk_start(keys, P, n, sin, inner, (uint64_t)t * S);
+    chunk[t] = a;
+    if (t == nch) return;
+    uint32_t b = chunk_start(keys, P, n, sin, inner, (uint64_t)(t + 1) * S);
+    uint32_t len = b - a;
+    if (len > 0) atomicMax(&counters[1], len);
+    if (len > cap) big[atomicAdd(&counters[0], 1u)] = (uint32_t)t;
 }
 
 __global__ void k_fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
@@ -1172,18 +1229,42 @@ void last_fill(const uint32_t *keys, int64_t n, int nlast, const uint32_t *flags
 {
     hipLaunchKernelGGL(k_last_fill, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, nlast, flags, fidx, nf, off, mask);
 }
-void rot_set(const uint32_t *keys, int64_t n, int k, const GridDesc &g, uint64_t *bm, hipStream_t s)
+void rot_set(const uint32_t *keys, int64_t n, const RotFrame &f, uint64_t *bm, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_rot_set, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g.stride[k], (uint32_t)g.n[k], bm);
+    hipLaunchKernelGGL(k_rot_set, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, f.sk, f.nk, f.rin, f.rout, bm);
 }
-void rot_rank(const uint32_t *keys, int64_t n, int k, const GridDesc &g, const uint64_t *bm,
-              const uint32_t *prefix, uint32_t *pi, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,
+void rot_rank(const uint32_t *keys, int64_t n, const RotFrame &f, const uint64_t *bm, const uint32_t *prefix,
+              const uint32_t *map, uint32_t *pi, uint32_t *inv, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,
               hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_rot_rank, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g.stride[k], (uint32_t)g.n[k], bm,
-                       prefix, pi, flags, tmpmask, info);
+    hipLaunchKernelGGL(k_rot_rank, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, f.sk, f.nk, f.rin, f.rout, bm, prefix,
+                       map, pi, inv, flags, tmpmask, info);
+}
+__global__ void k_chunk_fibers(const uint32_t *chunk, uint32_t nch, const uint32_t *fidx, const uint32_t *nf,
+                               uint32_t n, uint32_t *out)
+{
+    int64_t t = gid();
+    if (t > nch) return;
+    const uint32_t c = chunk[t];
+    out[t] = c < n ? fidx[c] : *nf;
+}
+
+void chunk_fibers(const uint32_t *chunk, int64_t n, uint32_t S, const uint32_t *fidx, const uint32_t *nf,
+                  uint32_t *out, hipStream_t s)
+{
+    uint32_t nch = (uint32_t)((n + S - 1) / S);
+    hipLaunchKernelGGL(k_chunk_fibers, dim3(nblocks((int64_t)nch + 1)), dim3(TB), 0, s, chunk, nch, fidx, nf,
+                       (uint32_t)n, out);
+}
+
+void make_chunks(const uint32_t *keys, const uint32_t *P, int64_t n, uint32_t sin, bool inner, uint32_t S,
+                 uint32_t cap, uint32_t *chunk, uint32_t *big, uint32_t *counters, hipStream_t s)
+{
+    uint32_t nch = (uint32_t)((n + S - 1) / S);
+    hipLaunchKernelGGL(k_chunks, dim3(nblocks((int64_t)nch + 1)), dim3(TB), 0, s, keys, P, (uint32_t)n, sin,
+                       inner ? 1 : 0, S, nch, cap, chunk, big, counters);
 }
 void last_info(const uint32_t *keys, int64_t n, int nlast, uint8_t *info, hipStream_t s)
 {

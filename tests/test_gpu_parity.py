@@ -367,3 +367,91 @@ def test_fp32_shadow_steps_morse4d(torch):
         o.prune()
     say(f"  morse4d fp32 shadowed steps: worst relative coefficient error {worst:.2e}")
     assert worst < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# block-fused layout (selected per context with PPQ_HPSI=4): the same
+# products and trajectories as the per-dimension layout
+# ---------------------------------------------------------------------------
+def make_block(cd, torch, precision=0):
+    import os
+    old = os.environ.get("PPQ_HPSI")
+    os.environ["PPQ_HPSI"] = "4"
+    try:
+        return make(cd, torch, precision)
+    finally:
+        if old is None:
+            del os.environ["PPQ_HPSI"]
+        else:
+            os.environ["PPQ_HPSI"] = old
+
+
+@pytest.mark.parametrize("name,fill,blob,seed", APPLY_CASES + [("small_6d", 0.6, True, 9)])
+def test_block_layout_apply_h(name, fill, blob, seed, torch):
+    cd = card(name)
+    say(f"block layout apply_h {name} fill={fill} seed={seed}")
+    keys = random_active_set(cd["n"], fill, seed, blob=blob)
+    x = random_complex(keys.size, seed + 100)
+    ref = Oracle(cd).apply_def(keys, x)
+    g = make_block(cd, torch)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(yt.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    say(f"  |A|={keys.size} rel err {err:.2e}")
+    assert err < 1e-13
+
+
+def test_block_layout_full_size_sampled(torch):
+    """6D quartic initial set (3.5M points): chunks above the main launch's
+    capacity go through the second launch."""
+    cd = card("quartic6d")
+    g = make_block(cd, torch)
+    n = g.init_state()
+    keys, _ = g.state()
+    x = random_complex(n, 12)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy()
+    idx = np.unique(np.concatenate([np.random.default_rng(6).integers(0, n, 1500), [0, n - 1]]))
+    ref = Oracle(cd).apply_def_at(keys, x, idx)
+    err = np.max(np.abs(y[idx] - ref)) / np.max(np.abs(ref))
+    say(f"  block layout |A|={n} rel err {err:.2e}")
+    assert err < 1e-13
+
+
+def test_block_layout_oversized_blocks_fall_back(torch):
+    """A full 2x2x2x20x20x20 grid has 8000-point inner blocks, more than one
+    workgroup's LDS holds: the context uses the per-dimension layout."""
+    cd = card("small_6d", n=[2, 2, 2, 20, 20, 20])
+    keys = np.arange(int(np.prod(cd["n"])), dtype=np.uint64)
+    x = random_complex(keys.size, 13)
+    ref = Oracle(cd).apply_def(keys, x)
+    g = make_block(cd, torch)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(yt.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("name,nsteps", [("small_6d", 10), ("small_4d", 30), ("morse4d", 25)])
+def test_block_layout_trajectory(name, nsteps, torch):
+    cd = card(name)
+    say(f"block layout trajectory {name} {nsteps} steps")
+    o = Oracle(cd)
+    o.init_state()
+    g = make_block(cd, torch)
+    g.init_state()
+    tr, _ = o.propagate(nsteps=nsteps)
+    tg = g.propagate(nsteps=nsteps)
+    assert np.array_equal(tg[:, 5], tr[:, 5]), "active-set sizes differ"
+    for col in (1, 2, 3, 4, 6):
+        assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
