@@ -11,7 +11,10 @@ the potential cache, and the observables.
 
 value = total H*psi point updates in the K timed steps (sum over steps of
 m * |A|) / wall time of those K steps.  The isolated H*psi rate, the
-roofline of the H*psi kernels and the FP32 form are reported beside it.
+roofline of the H*psi kernels and the FP32 form are reported beside it, and
+secondary lines (not the headline) time the other workloads: the 4D coupled
+Morse model (FP64 and FP32), its phase-space lattice form, and the adjoint
+gradient of the survival probability (FP64 and FP32).
 """
 import argparse
 import json
@@ -26,6 +29,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 SNAPSHOT_STEP = 250
+# Measured fabric-side bytes per active point of one FP64 product on this
+# workload's snapshot (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a 1 GiB
+# copy; profiles/hpsi_quartic6d_24pow6_traffic.md).  Valid for the
+# per-dimension layout's kernels as measured there.
+TRAFFIC_BYTES_PER_POINT_FP64 = 323.8
+TRAFFIC_SOURCE = "profiles/hpsi_quartic6d_24pow6_traffic.md"
 
 
 def bytes_per_point(D, precision):
@@ -51,6 +60,85 @@ def cpu_baseline(cd, reps=50):
                       f"(|A0| = {keys.size}), single thread, {dt:.1f} s"}
 
 
+def timed_steps(g, steps, warmup, m):
+    """Whole-path steps (step + adaption); returns (updates/s, ms per step)."""
+    import torch
+    for _ in range(warmup):
+        g.step()
+        g.prune()
+    torch.cuda.synchronize()
+    upd = 0
+    na = g.active_count()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        upd += m * na
+        g.step()
+        na, _ = g.prune()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return upd / wall, wall * 1e3 / steps
+
+
+def secondary(stream, steps, warmup, adjoint_steps):
+    """Other workloads, each from its own seeded start (not the headline)."""
+    import torch
+    import paper_1606_04004_amd as ppq
+    from paper_1606_04004_amd.adjoint import declare_trainable
+    from workloads import card
+    out = {}
+    cd = card("morse4d")
+    for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
+        g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
+        g.init_state()
+        g.propagate(nsteps=20)
+        ms_h = g.time_apply(20)
+        na = g.active_count()
+        rate, ms = timed_steps(g, steps, warmup, cd["krylov"])
+        out[f"morse4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "hpsi_updates_per_s": na / (ms_h * 1e-3),
+                                 "updates_per_s": rate, "ms_per_step": ms,
+                                 "from": "step 20 of the 4D coupled Morse card (32^4, eps 1e-6, dt 0.1, m 10)"}
+        del g
+    cd = card("pvb4d")
+    g = ppq.Propagator(cd, precision=ppq.PPQ_FP64, device=0, stream=stream)
+    g.init_state()
+    ms_h = g.time_apply(10)
+    na = g.active_count()
+    rate, ms = timed_steps(g, steps, warmup, cd["krylov"])
+    out["pvb4d_fp64"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
+                         "from": "initial set of the 4D phase-space lattice card (48^4, 6x8 lattice per dimension)"}
+    del g
+    cd = card("adjoint4d", nsteps=adjoint_steps)
+    for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
+        g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
+        declare_trainable(g, cd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = g.adjoint_record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dp, dc, dm = g.adjoint_gradient()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[f"adjoint4d_{tag}"] = {"steps": adjoint_steps, "J": J, "forward_record_s": t1 - t0,
+                                   "backward_s": t2 - t1, "gradient_components": int(dp.size + dc.size + dm.size),
+                                   "grad_norm": float(np.sqrt(np.sum(dp ** 2) + np.sum(dc ** 2) + np.sum(dm ** 2)))}
+        del g
+    return out
+
+
+def traffic_probe(stream):
+    """A plain device copy of known size, the calibration dispatch for the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes": nbytes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +148,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--workload", default="quartic6d")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -131,7 +223,11 @@ def main():
                                f"Lanczos m=10, timed from the step-{args.snapshot} snapshot",
                    "grid": 24 ** 6, "D": D, "krylov": m, "eps": eps, "dt": dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (TRAFFIC_BYTES_PER_POINT_FP64 * n_snap
+                                 if args.workload == "quartic6d" and args.snapshot == SNAPSHOT_STEP else None),
+                     "traffic_unit": "bytes per product (fabric side, counter-calibrated)",
+                     "traffic_source": TRAFFIC_SOURCE,
                      "kernel": "pruned H*psi (D fiber passes, potential fused in the first)",
                      "bytes_per_point": bpp},
     }
@@ -165,6 +261,12 @@ def main():
                        "hpsi_updates_per_s": n_snap / (ms32 * 1e-3), "hpsi_ms": ms32,
                        "roofline_frac": bpp32 * n_snap / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                        "bytes_per_point": bpp32}
+
+    if not args.no_secondary:
+        print("[bench] secondary workloads ...", file=sys.stderr, flush=True)
+        out["secondary"] = secondary(stream, args.steps, args.warmup, args.adjoint_steps)
+    if args.traffic_probe:
+        out["traffic_probe"] = traffic_probe(stream)
 
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
