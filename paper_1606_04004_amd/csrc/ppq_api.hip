@@ -97,7 +97,12 @@ struct ppq_ctx {
     // built operator (device)
     double *T64[MAXD]{};   // real factor per DVR dimension (kinetic), nb x nb
     float *T32[MAXD]{};
-    float *T32p[MAXD]{};  // FP32 factor zero-padded to 64 x 64 (matrix-core tiles)
+    float *T32p[MAXD]{};   // factors zero-padded to 64 x 64 (matrix-core tiles)
+    double *T64p[MAXD]{};
+    double2 *H64p[MAXD]{};
+    float2 *H32p[MAXD]{};
+    std::vector<double2 *> F64p;
+    std::vector<float2 *> F32p;
     double2 *H64[MAXD]{};  // complex factor per lattice dimension
     float2 *H32[MAXD]{};
     std::vector<double2 *> F64;  // distinct dense factors of product terms
@@ -263,13 +268,20 @@ void free_operator(ppq_ctx *c)
         dfree(c->T64[k]);
         dfree(c->T32[k]);
         dfree(c->T32p[k]);
+        dfree(c->T64p[k]);
+        dfree(c->H64p[k]);
+        dfree(c->H32p[k]);
         dfree(c->H64[k]);
         dfree(c->H32[k]);
     }
     for (auto &p : c->F64) dfree(p);
     for (auto &p : c->F32) dfree(p);
+    for (auto &p : c->F64p) dfree(p);
+    for (auto &p : c->F32p) dfree(p);
     c->F64.clear();
     c->F32.clear();
+    c->F64p.clear();
+    c->F32p.clear();
     c->Fdim.clear();
     c->pairs.clear();
     dfree(c->pot_coef);
@@ -416,13 +428,20 @@ void build_operator(ppq_ctx *c)
         dfree(c->T64[k]);
         dfree(c->T32[k]);
         dfree(c->T32p[k]);
+        dfree(c->T64p[k]);
+        dfree(c->H64p[k]);
+        dfree(c->H32p[k]);
         dfree(c->H64[k]);
         dfree(c->H32[k]);
     }
     for (auto &p : c->F64) dfree(p);
     for (auto &p : c->F32) dfree(p);
+    for (auto &p : c->F64p) dfree(p);
+    for (auto &p : c->F32p) dfree(p);
     c->F64.clear();
     c->F32.clear();
+    c->F64p.clear();
+    c->F32p.clear();
     c->Fdim.clear();
     c->pairs.clear();
     dfree(c->pot_coef);
@@ -444,9 +463,14 @@ void build_operator(ppq_ctx *c)
             c->T64[k] = upload(P, s);
             c->T32[k] = upload(Pf, s);
             std::vector<float> P64((size_t)64 * 64, 0.0f);
+            std::vector<double> D64((size_t)64 * 64, 0.0);
             for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j) P64[(size_t)i * 64 + j] = (float)T[(size_t)i * n + j];
+                for (int j = 0; j < n; ++j) {
+                    P64[(size_t)i * 64 + j] = (float)T[(size_t)i * n + j];
+                    D64[(size_t)i * 64 + j] = T[(size_t)i * n + j];
+                }
             c->T32p[k] = upload(P64, s);
+            c->T64p[k] = upload(D64, s);
         }
         // diagonal potential: one table per factor
         int nmax = 0;
@@ -609,6 +633,7 @@ void build_operator(ppq_ctx *c)
             int n = c->g.n[k];
             std::vector<cd> ht = similarity(L[k], Hk[k], n);
             pad_upload(ht, n, c->nb[k], &c->H64[k], &c->H32[k]);
+            pad_upload(ht, n, 64, &c->H64p[k], &c->H32p[k]);
         }
         for (size_t i = 0; i < fvals.size(); ++i) {
             int k = c->Fdim[i], n = c->g.n[k];
@@ -620,6 +645,9 @@ void build_operator(ppq_ctx *c)
             pad_upload(ht, n, c->nb[k], &d64, &d32);
             c->F64.push_back(d64);
             c->F32.push_back(d32);
+            pad_upload(ht, n, 64, &d64, &d32);
+            c->F64p.push_back(d64);
+            c->F32p.push_back(d32);
         }
     }
     ck(hipStreamSynchronize(s), "operator upload");
@@ -807,20 +835,23 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
             return;
         }
         if (c->hpsi_variant == 2 || c->hpsi_variant == 4) {
-            // last dimension: point-parallel over its contiguous runs while fibers
-            // are short, one lane per fiber once they average more than 16 points;
-            // lane per fiber elsewhere
+            // FP64: point-parallel last dimension and lane-per-fiber passes while
+            // fibers are short; FP32: matrix cores in every pass
             const int64_t n = c->nact;
             if (c->precision == PPQ_FP64) {
                 const double2 *x = (const double2 *)xv;
                 double2 *y = (double2 *)yv;
-                if (c->nf[D - 1] > 0 && n > 16 * c->nf[D - 1])
-                    hpsi_real_f64(pass_of(c, D - 1), c->T64[D - 1], x, c->V64, y, true, skip_if, skip_j, s);
+                // fibers averaging more than 16 points form dense tiles: matrix cores
+                auto longf = [&](int k) { return c->nf[k] > 0 && n > 16 * c->nf[k]; };
+                if (longf(D - 1))
+                    hpsi_mfma_f64(pass_of(c, D - 1), c->T64p[D - 1], x, c->V64, y, true, skip_if, skip_j, s);
                 else
                     hpsi_pt_f64(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T64[D - 1], x, c->V64, y, true,
                                 skip_if, skip_j, s);
-                for (int k = D - 2; k >= 0; --k)
-                    hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
+                for (int k = D - 2; k >= 0; --k) {
+                    if (longf(k)) hpsi_mfma_f64(pass_of(c, k), c->T64p[k], x, nullptr, y, false, skip_if, skip_j, s);
+                    else hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
+                }
             } else {
                 // complex FP32 on the matrix cores, every dimension
                 const float2 *x = (const float2 *)xv;
@@ -874,6 +905,16 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
     std::vector<int> outer_ids;
     for (const PairTerm &p : c->pairs)
         if (std::find(outer_ids.begin(), outer_ids.end(), p.f1) == outer_ids.end()) outer_ids.push_back(p.f1);
+    // complex factors on the matrix cores (PPQ_HPSI=3: vector FMA)
+    const bool mf = c->hpsi_variant != 3;
+    auto cpass64 = [&](int k, const double2 *Hn, const double2 *Hp, const CInput &in, double2 *out, bool acc) {
+        if (mf) hpsi_cmfma_f64(pass_of(c, k), Hp, in, out, acc, skip_if, skip_j, s);
+        else hpsi_cplx_f64(pass_of(c, k), Hn, in, out, acc, nullptr, skip_if, skip_j, s);
+    };
+    auto cpass32 = [&](int k, const float2 *Hn, const float2 *Hp, const CInput32 &in, float2 *out, bool acc) {
+        if (mf) hpsi_cmfma_f32(pass_of(c, k), Hp, in, out, acc, skip_if, skip_j, s);
+        else hpsi_cplx_f32(pass_of(c, k), Hn, in, out, acc, nullptr, skip_if, skip_j, s);
+    };
     if (c->precision == PPQ_FP64) {
         const double2 *x = (const double2 *)xv;
         double2 *y = (double2 *)yv;
@@ -881,12 +922,11 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
         in.nin = 1;
         in.x[0] = x;
         in.c[0] = make_double2(1.0, 0.0);
-        hpsi_cplx_f64(pass_of(c, D - 1), c->H64[D - 1], in, y, false, nullptr, skip_if, skip_j, s);
-        for (int k = D - 2; k >= 0; --k) hpsi_cplx_f64(pass_of(c, k), c->H64[k], in, y, true, nullptr, skip_if, skip_j, s);
+        cpass64(D - 1, c->H64[D - 1], c->H64p[D - 1], in, y, false);
+        for (int k = D - 2; k >= 0; --k) cpass64(k, c->H64[k], c->H64p[k], in, y, true);
         for (size_t i = 0; i < inner_ids.size(); ++i) {
             int f = inner_ids[i];
-            hpsi_cplx_f64(pass_of(c, c->Fdim[f]), c->F64[f], in, (double2 *)c->zbuf[i], false, nullptr, skip_if,
-                          skip_j, s);
+            cpass64(c->Fdim[f], c->F64[f], c->F64p[f], in, (double2 *)c->zbuf[i], false);
         }
         for (int f : outer_ids) {
             CInput acc{};
@@ -896,11 +936,11 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
                 acc.x[acc.nin] = (const double2 *)c->zbuf[zi];
                 acc.c[acc.nin] = make_double2(p.coef, 0.0);
                 if (++acc.nin == 4) {
-                    hpsi_cplx_f64(pass_of(c, c->Fdim[f]), c->F64[f], acc, y, true, nullptr, skip_if, skip_j, s);
+                    cpass64(c->Fdim[f], c->F64[f], c->F64p[f], acc, y, true);
                     acc.nin = 0;
                 }
             }
-            if (acc.nin) hpsi_cplx_f64(pass_of(c, c->Fdim[f]), c->F64[f], acc, y, true, nullptr, skip_if, skip_j, s);
+            if (acc.nin) cpass64(c->Fdim[f], c->F64[f], c->F64p[f], acc, y, true);
         }
     } else {
         const float2 *x = (const float2 *)xv;
@@ -909,12 +949,11 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
         in.nin = 1;
         in.x[0] = x;
         in.c[0] = make_float2(1.f, 0.f);
-        hpsi_cplx_f32(pass_of(c, D - 1), c->H32[D - 1], in, y, false, nullptr, skip_if, skip_j, s);
-        for (int k = D - 2; k >= 0; --k) hpsi_cplx_f32(pass_of(c, k), c->H32[k], in, y, true, nullptr, skip_if, skip_j, s);
+        cpass32(D - 1, c->H32[D - 1], c->H32p[D - 1], in, y, false);
+        for (int k = D - 2; k >= 0; --k) cpass32(k, c->H32[k], c->H32p[k], in, y, true);
         for (size_t i = 0; i < inner_ids.size(); ++i) {
             int f = inner_ids[i];
-            hpsi_cplx_f32(pass_of(c, c->Fdim[f]), c->F32[f], in, (float2 *)c->zbuf[i], false, nullptr, skip_if,
-                          skip_j, s);
+            cpass32(c->Fdim[f], c->F32[f], c->F32p[f], in, (float2 *)c->zbuf[i], false);
         }
         for (int f : outer_ids) {
             CInput32 acc{};
@@ -924,11 +963,11 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
                 acc.x[acc.nin] = (const float2 *)c->zbuf[zi];
                 acc.c[acc.nin] = make_float2((float)p.coef, 0.f);
                 if (++acc.nin == 4) {
-                    hpsi_cplx_f32(pass_of(c, c->Fdim[f]), c->F32[f], acc, y, true, nullptr, skip_if, skip_j, s);
+                    cpass32(c->Fdim[f], c->F32[f], c->F32p[f], acc, y, true);
                     acc.nin = 0;
                 }
             }
-            if (acc.nin) hpsi_cplx_f32(pass_of(c, c->Fdim[f]), c->F32[f], acc, y, true, nullptr, skip_if, skip_j, s);
+            if (acc.nin) cpass32(c->Fdim[f], c->F32[f], c->F32p[f], acc, y, true);
         }
     }
 }

@@ -439,88 +439,140 @@ void launch_pt(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, con
 #undef L
 }
 
-// ---- complex-FP32 form on the matrix cores ------------------------------------
+// ---- matrix-core form -------------------------------------------------------
 // A wavefront takes 16 consecutive fibers.  Their union of digits fixes a
 // window of 16*NT digits; the contraction Y = h_window X is a 16*NT x 16*NT
-// by 16*NT x 16 dense product per real/imaginary part, issued as
-// v_mfma_f32_16x16x4f32 tiles: A = a 16x4 block of h (lane i + 16 k holds
-// h[row i][digit k]), B = the fibers' values at 4 digits (lane j + 16 k holds
-// fiber j at digit k), accumulator D[4 (l/16) + r][l % 16] in register r of
-// lane l.  FP32 accumulation.  h is stored zero-padded to 64 x 64.
+// by 16*NT x 16 dense product, issued as 16x16x4 tiles
+// (v_mfma_f32_16x16x4f32 or v_mfma_f64_16x16x4f64): A = a 16x4 block of h
+// (lane i + 16 k holds h[row i][column k]), B = the fibers' values at 4
+// digits (lane j + 16 k holds fiber j at the k-th digit of the step).  The
+// accumulator holds D[4 (l/16) + r][l % 16] (FP32) or D[l/16 + 4 r][l % 16]
+// (FP64) in element r of lane l.  A real factor takes one product per part
+// (re, im); a complex factor four.  h is stored zero-padded to 64 x 64.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int MFB = 256;  // 4 wavefronts, 64 fibers per block
 constexpr int MFP = 64;   // padded size of h
 
-template <int NT, bool FIRST, bool IDENT>
-__device__ __forceinline__ void body_mfma(uint32_t o, uint64_t m, int ws, int lane,
-                                          const uint32_t *__restrict__ pi, const float *__restrict__ T,
-                                          const float2 *__restrict__ x, const float *__restrict__ V,
-                                          float2 *__restrict__ y)
+template <class R>
+struct Mma;
+template <>
+struct Mma<float> {
+    using V4 = floatx4;
+    __device__ static V4 op(float a, float b, V4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // row of the accumulator's element r in lane group kr, and the digit fed
+    // by lane group k at step kb: the same map, so a lane holds outputs at
+    // exactly the digits it feeds
+    __device__ static int row(int k, int r) { return 4 * k + r; }
+};
+template <>
+struct Mma<double> {
+    using V4 = doublex4;
+    __device__ static V4 op(double a, double b, V4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int k, int r) { return k + 4 * r; }
+};
+
+// Inputs of a matrix-core pass: x = sum_i c_i x_i (one unweighted input for
+// real factors).
+template <class R>
+struct MfIn {
+    int nin;
+    const typename Cx<R>::T *x[4];
+    typename Cx<R>::T c[4];
+};
+
+// MODE 0: y = h x; 1: y += h x; 2: y = h x + V x (first pass, potential fused)
+template <class R, bool CPLX, int NT, int MODE, bool IDENT>
+__device__ __forceinline__ void body_mf(uint32_t o, uint64_t m, int ws, int lane, const uint32_t *__restrict__ pi,
+                                        const void *__restrict__ Hv, const MfIn<R> &in, const R *__restrict__ V,
+                                        typename Cx<R>::T *__restrict__ y)
 {
+    using C = typename Cx<R>::T;
+    using M = Mma<R>;
     const int col = lane & 15, kr = lane >> 4;
     constexpr int NK = 4 * NT;
-    // The contraction index is taken in the order digit(kb, k) = ws + 16 (kb/4)
-    // + 4 k + kb % 4, so the digits a lane feeds as B over the k-steps are
-    // exactly the digits it holds in the accumulator: one position per digit.
     uint32_t pp[NK];
-    float2 xin[NK], yold[NK];
-    float vv[NK];
+    C xin[NK], yold[NK];
+    R vv[NK];
 #pragma unroll
     for (int kb = 0; kb < NK; ++kb) {
-        const int d = ws + 16 * (kb >> 2) + 4 * kr + (kb & 3);
+        const int d = ws + 16 * (kb >> 2) + M::row(kr, kb & 3);
         pp[kb] = 0xffffffffu;
         if ((m >> d) & 1ull) {
-            uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << d) - 1ull));
+            const uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << d) - 1ull));
             pp[kb] = IDENT ? pos : pi[pos];
         }
     }
 #pragma unroll
     for (int kb = 0; kb < NK; ++kb) {
-        xin[kb] = make_float2(0.f, 0.f);
-        yold[kb] = make_float2(0.f, 0.f);
-        vv[kb] = 0.f;
+        xin[kb] = Cx<R>::make(0, 0);
+        yold[kb] = Cx<R>::make(0, 0);
+        vv[kb] = 0;
         if (pp[kb] != 0xffffffffu) {
-            xin[kb] = x[pp[kb]];
-            if (FIRST) vv[kb] = V[pp[kb]];
-            else yold[kb] = y[pp[kb]];
+            if (CPLX) {
+                C acc = Cx<R>::make(0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (i < in.nin) {
+                        const C v = in.x[i][pp[kb]];
+                        const C c = in.c[i];
+                        acc.x = fma(c.x, v.x, fma(-c.y, v.y, acc.x));
+                        acc.y = fma(c.x, v.y, fma(c.y, v.x, acc.y));
+                    }
+                }
+                xin[kb] = acc;
+            } else {
+                xin[kb] = in.x[0][pp[kb]];
+            }
+            if (MODE == 2) vv[kb] = V[pp[kb]];
+            if (MODE == 1) yold[kb] = y[pp[kb]];
         }
     }
-    floatx4 accr[NT], acci[NT];
+    typename M::V4 accr[NT], acci[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        accr[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-        acci[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        accr[t] = typename M::V4{0, 0, 0, 0};
+        acci[t] = typename M::V4{0, 0, 0, 0};
     }
 #pragma unroll
     for (int kb = 0; kb < NK; ++kb) {
-        const int j = ws + 16 * (kb >> 2) + 4 * kr + (kb & 3);
+        const int j = ws + 16 * (kb >> 2) + M::row(kr, kb & 3);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const float a = T[(ws + 16 * t + col) * MFP + j];
-            accr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xin[kb].x, accr[t], 0, 0, 0);
-            acci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xin[kb].y, acci[t], 0, 0, 0);
+            const int hi = (ws + 16 * t + col) * MFP + j;
+            if (CPLX) {
+                const C h = reinterpret_cast<const C *>(Hv)[hi];
+                accr[t] = M::op(h.x, xin[kb].x, accr[t]);
+                accr[t] = M::op(-h.y, xin[kb].y, accr[t]);
+                acci[t] = M::op(h.x, xin[kb].y, acci[t]);
+                acci[t] = M::op(h.y, xin[kb].x, acci[t]);
+            } else {
+                const R a = reinterpret_cast<const R *>(Hv)[hi];
+                accr[t] = M::op(a, xin[kb].x, accr[t]);
+                acci[t] = M::op(a, xin[kb].y, acci[t]);
+            }
         }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int kb = 4 * t + r;  // output digit ws + 16 t + 4 kr + r
+            const int kb = 4 * t + r;  // element r of tile t sits at the digit of step kb
             if (pp[kb] != 0xffffffffu) {
-                float ar = accr[t][r], ai = acci[t][r];
-                if (FIRST) y[pp[kb]] = make_float2(fmaf(vv[kb], xin[kb].x, ar), fmaf(vv[kb], xin[kb].y, ai));
-                else y[pp[kb]] = make_float2(yold[kb].x + ar, yold[kb].y + ai);
+                const R ar = accr[t][r], ai = acci[t][r];
+                if (MODE == 2) y[pp[kb]] = Cx<R>::make(fma(vv[kb], xin[kb].x, ar), fma(vv[kb], xin[kb].y, ai));
+                else if (MODE == 1) y[pp[kb]] = Cx<R>::make(yold[kb].x + ar, yold[kb].y + ai);
+                else y[pp[kb]] = Cx<R>::make(ar, ai);
             }
         }
     }
 }
 
-template <bool FIRST, bool IDENT>
-__global__ __launch_bounds__(MFB) void k_hpsi_mfma(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
-                                                   const uint64_t *__restrict__ mask, int64_t nf,
-                                                   const float *__restrict__ T, const float2 *__restrict__ x,
-                                                   const float *__restrict__ V, float2 *__restrict__ y,
-                                                   const int *skip_if, int skip_j)
+template <class R, bool CPLX, int MODE, bool IDENT>
+__global__ __launch_bounds__(MFB) void k_hpsi_mf(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
+                                                 const uint64_t *__restrict__ mask, int64_t nf,
+                                                 const void *__restrict__ H, MfIn<R> in, const R *__restrict__ V,
+                                                 typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
 {
     if (skip_if && skip_j >= *skip_if) return;
     const int lane = threadIdx.x & 63;
@@ -539,7 +591,7 @@ __global__ __launch_bounds__(MFB) void k_hpsi_mfma(const uint32_t *__restrict__ 
 #define PPQ_MF(NT)                                                              \
     {                                                                           \
         const int ws = wlo < MFP - 16 * (NT) ? wlo : MFP - 16 * (NT);           \
-        body_mfma<NT, FIRST, IDENT>(o, m, ws, lane, pi, T, x, V, y);            \
+        body_mf<R, CPLX, NT, MODE, IDENT>(o, m, ws, lane, pi, H, in, V, y);     \
         return;                                                                 \
     }
     if (width <= 16) PPQ_MF(1)
@@ -938,23 +990,71 @@ void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *
     launch_acc<float>(fp, T, x, y, skip_if, skip_j, s);
 }
 
-void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
-                   const int *skip_if, int skip_j, hipStream_t s)
+template <class R, bool CPLX>
+void launch_mf(const FiberPass &fp, const void *H64, const MfIn<R> &in, const R *V, typename Cx<R>::T *y, int mode,
+               const int *skip_if, int skip_j, hipStream_t s)
 {
     if (fp.nf <= 0) return;
     const unsigned nb = (unsigned)((fp.nf + 63) / 64);
     const bool ident = fp.pi == nullptr;
-#define L(F, I) \
-    hipLaunchKernelGGL((k_hpsi_mfma<F, I>), dim3(nb), dim3(MFB), 0, s, fp.pi, fp.off, fp.mask, fp.nf, T64, x, V, y, \
-                       skip_if, skip_j)
-    if (first) {
-        if (ident) L(true, true);
-        else L(true, false);
+#define L(MD, I)                                                                                                     \
+    hipLaunchKernelGGL((k_hpsi_mf<R, CPLX, MD, I>), dim3(nb), dim3(MFB), 0, s, fp.pi, fp.off, fp.mask, fp.nf, H64, in, \
+                       V, y, skip_if, skip_j)
+    if (mode == 2) {
+        if (ident) L(2, true);
+        else L(2, false);
+    } else if (mode == 1) {
+        if (ident) L(1, true);
+        else L(1, false);
     } else {
-        if (ident) L(false, true);
-        else L(false, false);
+        if (ident) L(0, true);
+        else L(0, false);
     }
 #undef L
+}
+
+void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<float> in{};
+    in.nin = 1;
+    in.x[0] = x;
+    in.c[0] = make_float2(1.f, 0.f);
+    launch_mf<float, false>(fp, T64, in, V, y, first ? 2 : 1, skip_if, skip_j, s);
+}
+
+void hpsi_mfma_f64(const FiberPass &fp, const double *T64, const double2 *x, const double *V, double2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<double> in{};
+    in.nin = 1;
+    in.x[0] = x;
+    in.c[0] = make_double2(1.0, 0.0);
+    launch_mf<double, false>(fp, T64, in, V, y, first ? 2 : 1, skip_if, skip_j, s);
+}
+
+void hpsi_cmfma_f64(const FiberPass &fp, const double2 *H64, const CInput &in, double2 *y, bool accumulate,
+                    const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<double> a{};
+    a.nin = in.nin;
+    for (int i = 0; i < 4; ++i) {
+        a.x[i] = in.x[i];
+        a.c[i] = in.c[i];
+    }
+    launch_mf<double, true>(fp, H64, a, nullptr, y, accumulate ? 1 : 0, skip_if, skip_j, s);
+}
+
+void hpsi_cmfma_f32(const FiberPass &fp, const float2 *H64, const CInput32 &in, float2 *y, bool accumulate,
+                    const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<float> a{};
+    a.nin = in.nin;
+    for (int i = 0; i < 4; ++i) {
+        a.x[i] = in.x[i];
+        a.c[i] = in.c[i];
+    }
+    launch_mf<float, true>(fp, H64, a, nullptr, y, accumulate ? 1 : 0, skip_if, skip_j, s);
 }
 
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,

@@ -132,8 +132,10 @@ void hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double
                   hipStream_t s);
 void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
                   hipStream_t s);
-// complex-FP32 form on the matrix cores; T64 is h zero-padded to 64 x 64
+// matrix-core forms (v_mfma_*_16x16x4); T64 / H64 are h zero-padded to 64 x 64
 void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
+                   const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_mfma_f64(const FiberPass &fp, const double *T64, const double2 *x, const double *V, double2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);
 // block-fused form: one pass applies the 1D factors of up to 4 dimensions to
 // chunks of whole blocks staged in LDS (see ppq_hpsi.hip)
@@ -187,6 +189,11 @@ struct CInput32 {
 };
 void hpsi_cplx_f32(const FiberPass &fp, const float2 *H, const CInput32 &in, float2 *y, bool accumulate,
                    const float *V, const int *skip_if, int skip_j, hipStream_t s);
+// complex factors on the matrix cores: y (= or +=) h (sum_i c_i x_i), h padded to 64 x 64
+void hpsi_cmfma_f64(const FiberPass &fp, const double2 *H64, const CInput &in, double2 *y, bool accumulate,
+                    const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_cmfma_f32(const FiberPass &fp, const float2 *H64, const CInput32 &in, float2 *y, bool accumulate,
+                    const int *skip_if, int skip_j, hipStream_t s);
 
 // Krylov vector kernels. V_i = Vb + i*ld (elements); C is double2 or float2.
 // Reductions end in the last block to finish, which sums the per-block
