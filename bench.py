@@ -44,6 +44,15 @@ def bytes_per_point(D, precision):
     return 2 * sc + 4 * D
 
 
+def describe(cd):
+    names = {"quartic6d": "6D SoP quartic", "morse4d": "4D coupled Morse", "hh2d": "2D Henon-Heiles",
+             "pvb4d": "4D coupled Morse in a 6x8 phase-space lattice basis per dimension",
+             "adjoint4d": "4D coupled Morse (adjoint card)"}
+    n = cd["n"]
+    return (f"{cd['name']}: {names.get(cd['name'], cd['name'])}, sine-DVR {n[0]}^{cd['D']} on "
+            f"[{cd['lo'][0]},{cd['hi'][0]}]^{cd['D']}, eps={cd['eps']}, dt={cd['dt']}, m={cd['krylov']}")
+
+
 def cpu_baseline(cd, reps=50):
     """The FP64 oracle (one thread) applying H on its own initial set of the card."""
     from oracle.oracle import Oracle
@@ -99,14 +108,16 @@ def secondary(stream, steps, warmup, adjoint_steps):
                                  "from": "step 20 of the 4D coupled Morse card (32^4, eps 1e-6, dt 0.1, m 10)"}
         del g
     cd = card("pvb4d")
-    g = ppq.Propagator(cd, precision=ppq.PPQ_FP64, device=0, stream=stream)
-    g.init_state()
-    ms_h = g.time_apply(10)
-    na = g.active_count()
-    rate, ms = timed_steps(g, steps, warmup, cd["krylov"])
-    out["pvb4d_fp64"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
-                         "from": "initial set of the 4D phase-space lattice card (48^4, 6x8 lattice per dimension)"}
-    del g
+    for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
+        g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
+        g.init_state()
+        ms_h = g.time_apply(10)
+        na = g.active_count()
+        rate, ms = timed_steps(g, steps, warmup, cd["krylov"])
+        out[f"pvb4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
+                               "from": "initial set of the 4D phase-space lattice card (48^4, 6x8 lattice per "
+                                       "dimension), complex factors on the matrix cores"}
+        del g
     cd = card("adjoint4d", nsteps=adjoint_steps)
     for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
@@ -166,8 +177,10 @@ def main():
     D, m, dt, eps = cd["D"], cd["krylov"], cd["dt"], cd["eps"]
     print(f"[bench] workload {cd['name']} D={D} n={cd['n'][0]} eps={eps}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
+    total = int(np.prod(cd["n"]))
+    cap = min(16_000_000, total)
     g = ppq.Propagator(cd, precision=ppq.PPQ_FP64, device=0, stream=stream)
-    g.reserve(16_000_000)
+    g.reserve(cap)
     n0 = g.init_state()
     t0 = time.perf_counter()
     g.propagate(nsteps=args.snapshot)
@@ -219,9 +232,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "quartic6d: 6D SoP quartic, sine-DVR 24^6 on [-6.5,6.5]^6, eps=1e-6, dt=0.05, "
-                               f"Lanczos m=10, timed from the step-{args.snapshot} snapshot",
-                   "grid": 24 ** 6, "D": D, "krylov": m, "eps": eps, "dt": dt},
+        "config": {"workload": describe(cd) + f", timed from the step-{args.snapshot} snapshot",
+                   "grid": total, "D": D, "krylov": m, "eps": eps, "dt": dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (TRAFFIC_BYTES_PER_POINT_FP64 * n_snap
@@ -234,7 +246,7 @@ def main():
 
     if not args.no_fp32:
         g32 = ppq.Propagator(cd, precision=ppq.PPQ_FP32, device=0, stream=stream)
-        g32.reserve(16_000_000)
+        g32.reserve(cap)
         g32.init_state()
         g32.set_state(snap_keys, snap_c)
         ms32 = g32.time_apply(50)
