@@ -792,7 +792,7 @@ FiberPass pass_of(const ppq_ctx *c, int k)
 }
 
 // y = P H P x on the current set (device vectors of the context precision)
-void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
+void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
 {
     const int D = c->g.D;
     hipStream_t s = c->stream;
@@ -850,6 +850,7 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
                                 skip_if, skip_j, s);
                 for (int k = D - 2; k >= 0; --k) {
                     if (longf(k)) hpsi_mfma_f64(pass_of(c, k), c->T64p[k], x, nullptr, y, false, skip_if, skip_j, s);
+                    else if (c->nb[k] <= 32) hpsi_acc_f64(pass_of(c, k), c->T64[k], x, y, skip_if, skip_j, s);
                     else hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
                 }
             } else {
@@ -970,6 +971,14 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
             if (acc.nin) cpass32(c->Fdim[f], c->F32[f], c->F32p[f], acc, y, true);
         }
     }
+}
+
+// Launch errors (a configuration the device refuses) surface here rather than
+// as a silently skipped pass.
+void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
+{
+    apply_launches(c, xv, yv, skip_if, skip_j);
+    ck(hipGetLastError(), "H*psi launch");
 }
 
 // Lanczos/Arnoldi basis of `src` (FP64 master vector on the current set) in

@@ -19,6 +19,7 @@
 // W^2 FMA pairs per lane with no LDS traffic.  Output positions are
 // recomputed per row (they hit in cache) so the row loop can stay rolled.
 #include <algorithm>
+#include <mutex>
 
 #include "ppq_internal.hpp"
 
@@ -1118,8 +1119,9 @@ void launch_block(const BlockPass &bp, const R *const *T, const typename Cx<R>::
     const size_t bpp = 2 * sizeof(C) + sizeof(uint16_t) * (size_t)npi;
     // points per thread of the two launches (NT * SU >= cap)
     constexpr int SU_S = sizeof(R) == 8 ? 4 : 8, SU_B = sizeof(R) == 8 ? 5 : 8;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // dynamic LDS above 64 KB: raise each instantiation's limit once per process
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
         const void *fns[] = {
             reinterpret_cast<const void *>(&k_hpsi_block<R, 8, 512, SU_S>),
             reinterpret_cast<const void *>(&k_hpsi_block<R, 16, 512, SU_S>),
@@ -1130,9 +1132,10 @@ void launch_block(const BlockPass &bp, const R *const *T, const typename Cx<R>::
             reinterpret_cast<const void *>(&k_hpsi_block<R, 24, 1024, SU_B>),
             reinterpret_cast<const void *>(&k_hpsi_block<R, 32, 1024, SU_B>),
         };
-        for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
-        attr_set = true;
-    }
+        for (const void *f : fns)
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES) != hipSuccess)
+                (void)hipGetLastError();  // the launch itself then reports the LDS request
+    });
     // main launch: two 512-thread workgroups per CU; long chunks: one
     // 1024-thread workgroup per CU
     auto go = [&](dim3 grid, uint32_t cap, bool wide) {

@@ -455,3 +455,25 @@ def test_block_layout_trajectory(name, nsteps, torch):
     assert np.array_equal(tg[:, 5], tr[:, 5]), "active-set sizes differ"
     for col in (1, 2, 3, 4, 6):
         assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+
+
+@pytest.mark.parametrize("n,prec", [([24, 20, 18], 0), ([24, 20, 18], 1), ([17, 33, 40], 0)])
+def test_apply_h_long_fibers(n, prec, torch):
+    """Full grids: every fiber is longer than 16 points, so FP64 takes the
+    matrix-core passes (windows of 1-3 tiles), as the FP32 form always does."""
+    cd = card("small_3d", n=n)
+    keys = np.arange(int(np.prod(n)), dtype=np.uint64)
+    x = random_complex(keys.size, 21)
+    ref = Oracle(cd).apply_def(keys, x)
+    g = make(cd, torch, precision=prec)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    if prec == 1:
+        xt = xt.to(torch.complex64)
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    y = yt.cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    say(f"  long fibers n={n} prec={prec} rel err {err:.2e}")
+    assert err < (1e-13 if prec == 0 else 1e-6)
