@@ -537,15 +537,34 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
                                                  int ioff, int nvals)
 {
     if (mode != RED_NORM0 && j >= ks->meff) return;
+    // the partials were just written from every XCD: issue all of this
+    // thread's loads before summing them (blocks t, t + TB, ... in order)
     double2 tot[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) tot[i] = make_double2(0.0, 0.0);
-    for (int b = threadIdx.x; b < nb; b += TB) {
+    constexpr int PER = RED_BLOCKS / TB;
+    static_assert(RED_BLOCKS % TB == 0, "partials per thread");
+    if (nb == RED_BLOCKS) {
+        double2 v[PER][NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double2 v = partial[(int64_t)b * PSTRIDE + i];
-            tot[i].x += v.x;
-            tot[i].y += v.y;
+        for (int u = 0; u < PER; ++u)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[u][i] = partial[(int64_t)(threadIdx.x + u * TB) * PSTRIDE + i];
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                tot[i].x += v[u][i].x;
+                tot[i].y += v[u][i].y;
+            }
+    } else {
+        for (int b = threadIdx.x; b < nb; b += TB) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                double2 v = partial[(int64_t)b * PSTRIDE + i];
+                tot[i].x += v.x;
+                tot[i].y += v.y;
+            }
         }
     }
     __shared__ double2 vals[TB / 64][NV];
