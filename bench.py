@@ -165,8 +165,8 @@ def main():
                     help="also run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

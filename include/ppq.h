@@ -31,6 +31,19 @@
  *     pointers are used in stream order on the context stream and must stay
  *     valid until that work has run.  The library never frees caller memory.
  *   - A context is used by one host thread at a time.
+ *
+ * Environment (read at ppq_create; for measurement and comparison only)
+ *   PPQ_HPSI=2  (default) per-dimension fiber passes: matrix cores for the
+ *               FP32 form, for long fibers (mean length > 16) and for complex
+ *               lattice factors; vector FMA for short FP64 fibers.
+ *   PPQ_HPSI=3  vector FMA in every pass (comparison).
+ *   PPQ_HPSI=1  point-parallel in every pass; PPQ_HPSI=0 lane per fiber in
+ *               every pass (earlier layouts, for comparison).
+ *   PPQ_HPSI=4  block-fused layout: two LDS-staged passes over chunks of
+ *               blocks (falls back to 2 when a chunk exceeds LDS).
+ *   PPQ_BLOCK_STATS=1  report the block layout's chunk statistics on stderr.
+ *   Every layout computes the same product; only the summation order of
+ *   the dimensions' contributions differs.
  */
 #ifndef PPQ_H
 #define PPQ_H
