@@ -126,7 +126,11 @@ struct ppq_ctx {
     double2 *psi_tmp = nullptr;
     double *V64 = nullptr;
     float *V32 = nullptr;
+    double *Vt64 = nullptr;  // the previous set's potential while it is carried over
+    float *Vt32 = nullptr;
     bool derived_valid = false;  // fibers + potential cache match the set
+    bool v_valid = false;        // V matches the current set and operator
+    bool v_partial = false;      // V holds the carried-over values, NaN where new
 
     // fiber tables
     uint32_t *pi[MAXD]{};
@@ -232,6 +236,8 @@ void free_state_buffers(ppq_ctx *c)
     dfree(c->psi_tmp);
     dfree(c->V64);
     dfree(c->V32);
+    dfree(c->Vt64);
+    dfree(c->Vt32);
     for (int k = 0; k < MAXD; ++k) {
         dfree(c->pi[k]);
         dfree(c->off[k]);
@@ -315,8 +321,13 @@ void ensure_capacity(ppq_ctx *c, int64_t n)
     c->keys[1] = dalloc<uint32_t>(nc);
     c->psi[1] = dalloc<double2>(nc);
     c->psi_tmp = dalloc<double2>(nc);
-    if (c->precision == PPQ_FP64) c->V64 = dalloc<double>(nc);
-    else c->V32 = dalloc<float>(nc);
+    if (c->precision == PPQ_FP64) {
+        c->V64 = dalloc<double>(nc);
+        c->Vt64 = dalloc<double>(nc);
+    } else {
+        c->V32 = dalloc<float>(nc);
+        c->Vt32 = dalloc<float>(nc);
+    }
     for (int k = 0; k < c->g.D; ++k) {
         if (k < c->g.D - 1) c->pi[k] = dalloc<uint32_t>(nc);
         c->off[k] = dalloc<uint32_t>(nc + 1);
@@ -336,6 +347,8 @@ void ensure_capacity(ppq_ctx *c, int64_t n)
     }
     for (int k = 0; k < c->g.D; ++k) c->fch[k] = dalloc<uint32_t>(nc / BLOCK_WINDOW + 2);
     c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
     free_krylov(c);
 }
 
@@ -652,6 +665,8 @@ void build_operator(ppq_ctx *c)
     }
     ck(hipStreamSynchronize(s), "operator upload");
     c->op_dirty = false;
+    c->v_valid = false;  // a carried potential belongs to the previous operator
+    c->v_partial = false;
 }
 
 // ---- derived tables of the current set --------------------------------------
@@ -726,7 +741,11 @@ void build_derived(ppq_ctx *c)
     if (try_block) build_inner_first(c);
     if (!c->any_lattice) {
         PotDesc pd{c->pot_nterm, D, c->pot_nmax, c->pot_coef, c->pot_tab, c->pot_tabs, c->pot_ntab};
-        potential(keys, n, c->g, pd, c->V64, c->V32, s);
+        // flags is free once the fiber tables are built
+        potential(keys, n, c->g, pd, c->V64, c->V32, c->v_partial ? c->flags : nullptr,
+                  reinterpret_cast<unsigned *>(c->small + 2 * MAXD + 4), s);
+        c->v_valid = true;
+        c->v_partial = false;
     }
     ck(hipMemcpyAsync(c->h_small, c->small, sizeof(uint32_t) * (2 * MAXD + 4), hipMemcpyDeviceToHost, s), "nf");
     ck(hipStreamSynchronize(s), "fibers");
@@ -1049,9 +1068,25 @@ void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
     compact(c->bm, c->prefix, c->nwords, c->keys[nxt], s);
     fill_zero_bytes(c->psi[nxt], n_new * (int64_t)sizeof(double2), s);
     remap(c->keys[c->cur], c->psi[c->cur], n_old, c->bm, c->prefix, c->psi[nxt], s);
+    // The diagonal potential of the functions that stay is carried over;
+    // only the added ones are evaluated again (NaN marks them).
+    const bool carry = c->v_valid && !c->any_lattice;
+    if (carry) {
+        if (c->precision == PPQ_FP64) {
+            std::swap(c->V64, c->Vt64);
+            fill_u64(reinterpret_cast<uint64_t *>(c->V64), n_new, 0x7ff8000000000000ull, s);
+            remap_values(c->keys[c->cur], c->Vt64, n_old, c->bm, c->prefix, c->V64, s);
+        } else {
+            std::swap(c->V32, c->Vt32);
+            fill_u32(reinterpret_cast<uint32_t *>(c->V32), n_new, 0x7fc00000u, s);
+            remap_values(c->keys[c->cur], c->Vt32, n_old, c->bm, c->prefix, c->V32, s);
+        }
+    }
     c->cur = nxt;
     c->nact = n_new;
     c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = carry;
 }
 
 void set_record_host(ppq_ctx *c, int64_t r, double t, int krylov)
@@ -1193,6 +1228,8 @@ void set_current_set(ppq_ctx *c, const uint32_t *keys_dev, int64_t n)
     c->nact = n;
     c->has_state = true;
     c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
 }
 
 // restriction of the current state to a recorded set (one frozen adaption)
@@ -1211,6 +1248,8 @@ void frozen_remap(ppq_ctx *c, const uint32_t *next_keys, int64_t n_next)
     c->cur = nxt;
     c->nact = n_next;
     c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
 }
 
 void record_append(ppq_ctx *c)
@@ -1555,6 +1594,8 @@ int ppq_set_lattice(ppq_ctx *c, int k, int ns, int nl)
     c->block_ok = false;
     c->op_dirty = true;
     c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
     return PPQ_OK;
 }
 
@@ -1597,6 +1638,8 @@ int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dim
     c->terms.push_back(t);
     c->op_dirty = true;
     c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
     return PPQ_OK;
 }
 
@@ -1638,6 +1681,8 @@ int ppq_init_gaussian(ppq_ctx *c, const double *centre, const double *momentum, 
         c->nact = n0;
         c->has_state = true;
         c->derived_valid = false;
+        c->v_valid = false;
+        c->v_partial = false;
         ck(hipStreamSynchronize(s), "init");
         if (n_active) *n_active = n0;
     })
@@ -1669,6 +1714,8 @@ int ppq_set_state(ppq_ctx *c, int64_t count, const uint64_t *keys, const double 
         c->nact = count;
         c->has_state = true;
         c->derived_valid = false;
+        c->v_valid = false;
+        c->v_partial = false;
     })
     return PPQ_OK;
 }
@@ -1811,6 +1858,8 @@ int ppq_set_potential_term(ppq_ctx *c, int term, double coef, const double *para
         }
     c->op_dirty = true;
     c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
     return PPQ_OK;
 }
 

@@ -100,8 +100,14 @@ void chunk_fibers(const uint32_t *chunk, int64_t n, uint32_t S, const uint32_t *
 void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
               const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s);
 
+// V (or Vf) of every point; with `list` (uint32[n] work space) and `count`
+// (one device counter) only where V holds NaN, the rest is kept
 void potential(const uint32_t *keys, int64_t n, const GridDesc &g, const PotDesc &pd, double *V, float *Vf,
-               hipStream_t s);
+               uint32_t *list, unsigned *count, hipStream_t s);
+// nv[rank of okeys[p] in the bitmap] = ov[p] for the keys that stay
+template <class T>
+void remap_values(const uint32_t *okeys, const T *ov, int64_t n_old, const uint64_t *bm, const uint32_t *prefix,
+                  T *nv, hipStream_t s);
 
 // fiber contraction y (+)= P h_k P x along one dimension
 struct FiberPass {

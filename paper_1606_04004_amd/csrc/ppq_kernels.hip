@@ -443,45 +443,93 @@ __device__ inline int select_digit(const int (&d)[MAXD], int k)
     return r;
 }
 
+// Grid-stride over the points (or over a list of them): the term
+// descriptors and tables are staged in LDS once per block.
 __global__ __launch_bounds__(TB) void k_potential(const uint32_t *keys, int64_t n, GridDesc g, PotDesc pd, double *V,
-                                                  float *Vf)
+                                                  float *Vf, const uint32_t *list, const unsigned *count)
 {
     __shared__ double s_coef[POT_MAX_TERMS];
     __shared__ int s_nf[POT_MAX_TERMS];
     __shared__ int s_fac[POT_MAX_TERMS][POT_MAX_FAC];  // (table index << 4) | dim
     __shared__ double s_tab[POT_MAX_TAB];
     for (int t = threadIdx.x; t < pd.nterm; t += TB) {
+        int ti[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) ti[k] = k < g.D ? pd.tab[t * pd.D + k] : -1;
         s_coef[t] = pd.coef[t];
         int nf = 0;
-        for (int k = 0; k < g.D; ++k) {
-            int ti = pd.tab[t * pd.D + k];
-            if (ti >= 0 && nf < POT_MAX_FAC) s_fac[t][nf++] = (ti << 4) | k;
-        }
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k)
+            if (ti[k] >= 0 && nf < POT_MAX_FAC) s_fac[t][nf++] = (ti[k] << 4) | k;
         s_nf[t] = nf;
     }
     for (int i = threadIdx.x; i < pd.ntab * pd.nmax; i += TB) s_tab[i] = pd.tabs[i];
     __syncthreads();
-    int64_t p = gid();
-    if (p >= n) return;
-    uint32_t key = keys[p];
-    int d[MAXD];
+    const int64_t stride = (int64_t)gridDim.x * TB;
+    const int64_t m = list ? (int64_t)*count : n;
+    for (int64_t i = gid(); i < m; i += stride) {
+        const int64_t p = list ? (int64_t)list[i] : i;
+        uint32_t key = keys[p];
+        int d[MAXD];
 #pragma unroll
-    for (int k = 0; k < MAXD; ++k) d[k] = (k < g.D) ? (int)((key / g.stride[k]) % (uint32_t)g.n[k]) : 0;
-    double v = 0.0;
-    for (int t = 0; t < pd.nterm; ++t) {
-        double f = s_coef[t];
-        const int nf = s_nf[t];
+        for (int k = 0; k < MAXD; ++k) d[k] = (k < g.D) ? (int)((key / g.stride[k]) % (uint32_t)g.n[k]) : 0;
+        double v = 0.0;
+        for (int t = 0; t < pd.nterm; ++t) {
+            double f = s_coef[t];
+            const int nf = s_nf[t];
 #pragma unroll
-        for (int j = 0; j < POT_MAX_FAC; ++j) {
-            if (j < nf) {
-                int e = s_fac[t][j];
-                f *= s_tab[(e >> 4) * pd.nmax + select_digit(d, e & 15)];
+            for (int j = 0; j < POT_MAX_FAC; ++j) {
+                if (j < nf) {
+                    int e = s_fac[t][j];
+                    f *= s_tab[(e >> 4) * pd.nmax + select_digit(d, e & 15)];
+                }
             }
+            v += f;
         }
-        v += f;
+        if (V) V[p] = v;
+        if (Vf) Vf[p] = (float)v;
     }
-    if (V) V[p] = v;
-    if (Vf) Vf[p] = (float)v;
+}
+
+// Positions whose potential is missing (NaN) into list.  Each block takes a
+// contiguous range: it counts, reserves its segment with one atomic (block
+// segments in any order), then writes its positions in order.
+template <class T>
+__global__ __launch_bounds__(TB) void k_missing(const T *V, int64_t n, uint32_t *list, unsigned *count)
+{
+    __shared__ unsigned s_w[TB / 64];
+    __shared__ unsigned s_base, s_run;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned c = 0;
+    for (int64_t p = lo + threadIdx.x; p < hi; p += TB) c += (V[p] == V[p]) ? 0u : 1u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane == 0) s_w[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int i = 0; i < TB / 64; ++i) tot += s_w[i];
+        s_base = tot ? atomicAdd(count, tot) : 0u;
+        s_run = 0u;
+    }
+    __syncthreads();
+    for (int64_t p0 = lo; p0 < hi; p0 += TB) {
+        const int64_t p = p0 + threadIdx.x;
+        const bool miss = p < hi && !(V[p] == V[p]);
+        const uint64_t b = __ballot(miss);
+        if (lane == 0) s_w[w] = (unsigned)__popcll(b);
+        __syncthreads();
+        unsigned off = s_base + s_run;
+        for (int i = 0; i < w; ++i) off += s_w[i];
+        if (miss) list[off + (unsigned)__popcll(b & ((1ull << lane) - 1ull))] = (uint32_t)p;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int i = 0; i < TB / 64; ++i) s_run += s_w[i];
+        __syncthreads();
+    }
 }
 
 // ---- Krylov vectors ---------------------------------------------------------------
@@ -1297,11 +1345,45 @@ void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpma
 }
 
 void potential(const uint32_t *keys, int64_t n, const GridDesc &g, const PotDesc &pd, double *V, float *Vf,
-               hipStream_t s)
+               uint32_t *list, unsigned *count, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_potential, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g, pd, V, Vf);
+    const unsigned nb = std::min<unsigned>(nblocks(n), 2048u);
+    if (list) {
+        fill_u32(count, 1, 0u, s);
+        const unsigned mb = std::min<unsigned>(nblocks(n), 1024u);
+        if (V) hipLaunchKernelGGL(k_missing<double>, dim3(mb), dim3(TB), 0, s, V, n, list, count);
+        else hipLaunchKernelGGL(k_missing<float>, dim3(mb), dim3(TB), 0, s, Vf, n, list, count);
+    }
+    hipLaunchKernelGGL(k_potential, dim3(nb), dim3(TB), 0, s, keys, n, g, pd, V, Vf, list, count);
 }
+
+template <class T>
+__global__ void k_remap_values(const uint32_t *okeys, const T *ov, int64_t n_old, const uint64_t *bm,
+                               const uint32_t *prefix, T *nv)
+{
+    int64_t p = gid();
+    if (p >= n_old) return;
+    uint32_t key = okeys[p];
+    uint64_t word = bm[key >> 6];
+    uint32_t b = key & 63;
+    if ((word >> b) & 1ull) {
+        uint32_t q = prefix[key >> 6] + (uint32_t)__popcll(word & ((1ull << b) - 1ull));
+        nv[q] = ov[p];
+    }
+}
+
+template <class T>
+void remap_values(const uint32_t *okeys, const T *ov, int64_t n_old, const uint64_t *bm, const uint32_t *prefix,
+                  T *nv, hipStream_t s)
+{
+    if (n_old <= 0) return;
+    hipLaunchKernelGGL(k_remap_values<T>, dim3(nblocks(n_old)), dim3(TB), 0, s, okeys, ov, n_old, bm, prefix, nv);
+}
+template void remap_values<double>(const uint32_t *, const double *, int64_t, const uint64_t *, const uint32_t *,
+                                   double *, hipStream_t);
+template void remap_values<float>(const uint32_t *, const float *, int64_t, const uint64_t *, const uint32_t *,
+                                  float *, hipStream_t);
 
 static unsigned red_blocks(int64_t n)
 {

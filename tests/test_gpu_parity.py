@@ -477,3 +477,32 @@ def test_apply_h_long_fibers(n, prec, torch):
     err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
     say(f"  long fibers n={n} prec={prec} rel err {err:.2e}")
     assert err < (1e-13 if prec == 0 else 1e-6)
+
+
+def test_apply_h_bench_snapshot_sampled(torch):
+    """The state bench.py times (6D quartic card, step 250, about 3.6M points):
+    sampled rows of the FP64 product and of the FP32 form against the oracle."""
+    cd = card("quartic6d")
+    g = make(cd, torch)
+    g.reserve(16_000_000)
+    g.init_state()
+    g.propagate(nsteps=250)
+    keys, c = g.state()
+    n = keys.size
+    say(f"bench snapshot |A| = {n}")
+    idx = np.unique(np.concatenate([np.random.default_rng(8).integers(0, n, 2000), [0, n - 1]]))
+    ref = Oracle(cd).apply_def_at(keys, c, idx)
+    for prec, tol in ((0, 1e-13), (1, 1e-6)):
+        h = make(cd, torch, precision=prec)
+        h.reserve(16_000_000)
+        h.set_state(keys, c)
+        xt = torch.from_numpy(c).cuda()
+        if prec == 1:
+            xt = xt.to(torch.complex64)
+        yt = torch.zeros_like(xt)
+        h.apply_h(xt, yt)
+        torch.cuda.synchronize()
+        y = yt.cpu().numpy().astype(np.complex128)
+        err = np.max(np.abs(y[idx] - ref)) / np.max(np.abs(ref))
+        say(f"  precision {prec}: sampled rel err {err:.2e}")
+        assert err < tol
