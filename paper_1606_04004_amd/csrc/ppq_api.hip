@@ -1056,7 +1056,7 @@ void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
     double eps2 = eps * eps;
     fill_u64(c->bm, c->nwords + 2, 0ull, s);
     fill_u64((uint64_t *)c->count, 1, 0ull, s);
-    dilate(c->keys[c->cur], c->psi[c->cur], n_old, c->g, eps2, c->bm, c->count, s);
+    dilate(c->keys[c->cur], c->psi[c->cur], n_old, c->g, eps2, c->bm, c->count, c->flags, s);
     scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
     ck(hipMemcpyAsync(c->h_small + MAXD, c->small + MAXD, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "count");
     ck(hipMemcpyAsync(c->h_count, c->count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "count");

@@ -66,8 +66,9 @@ void init_flag(const GridDesc &g, const double2 *tabs, int nmax, double eps2, ui
                unsigned long long *nabove, hipStream_t s);
 void product_values(const uint32_t *keys, int64_t n, const GridDesc &g, const double2 *tabs, int nmax,
                     double2 *out, hipStream_t s);
+// block_counts: work space of at least n / 256 + 1 entries
 void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, double eps2, uint64_t *bm,
-            unsigned long long *nabove, hipStream_t s);
+            unsigned long long *nabove, unsigned *block_counts, hipStream_t s);
 void compact(const uint64_t *bm, const uint32_t *prefix, int64_t nwords, uint32_t *keys_out, hipStream_t s);
 void remap(const uint32_t *okeys, const double2 *opsi, int64_t n_old, const uint64_t *bm, const uint32_t *prefix,
            double2 *npsi, hipStream_t s);

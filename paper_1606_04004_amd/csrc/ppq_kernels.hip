@@ -91,6 +91,36 @@ __device__ inline void count_ballot(bool pred, unsigned long long *counter)
     if (threadIdx.x == 0 && s_cnt) atomicAdd(counter, (unsigned long long)s_cnt);
 }
 
+// Counts `pred` over the block into block_counts[blockIdx.x] (a plain store:
+// thousands of blocks adding to one address serialise).  Block-collective.
+__device__ inline void count_block(bool pred, unsigned *block_counts)
+{
+    __shared__ unsigned s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0u;
+    __syncthreads();
+    uint64_t b = __ballot(pred);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&s_cnt, (unsigned)__popcll(b));
+    __syncthreads();
+    if (threadIdx.x == 0) block_counts[blockIdx.x] = s_cnt;
+}
+
+// *out = sum of nb block counts (one block, fixed order)
+__global__ __launch_bounds__(1024) void k_sum_counts(const unsigned *bc, int64_t nb, unsigned long long *out)
+{
+    __shared__ unsigned long long s_part[16];
+    unsigned long long c = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 1024) c += bc[i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < 16; ++i) t += s_part[i];
+        *out = t;
+    }
+}
+
 // ---- scan ------------------------------------------------------------------
 constexpr int SB = 256;
 constexpr int SI = 8;
@@ -240,7 +270,7 @@ __global__ void k_product_values(const uint32_t *keys, int64_t n, GridDesc g, co
 }
 
 __global__ void k_dilate(const uint32_t *keys, const double2 *psi, int64_t n, GridDesc g, double eps2,
-                         uint64_t *bm, unsigned long long *nabove)
+                         uint64_t *bm, unsigned *block_counts)
 {
     int64_t p = gid();
     bool keep = false;
@@ -250,7 +280,7 @@ __global__ void k_dilate(const uint32_t *keys, const double2 *psi, int64_t n, Gr
         keep = above_eps(psi[p], eps2);
     }
     set_with_neighbours(g, bm, key, keep);
-    count_ballot(keep, nabove);
+    count_block(keep, block_counts);
 }
 
 __global__ void k_mark(const uint32_t *keys, int64_t n, uint64_t *bm)
@@ -1265,10 +1295,12 @@ void product_values(const uint32_t *keys, int64_t n, const GridDesc &g, const do
     hipLaunchKernelGGL(k_product_values, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, g, tabs, nmax, out);
 }
 void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, double eps2, uint64_t *bm,
-            unsigned long long *nabove, hipStream_t s)
+            unsigned long long *nabove, unsigned *block_counts, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_dilate, dim3(nblocks(n)), dim3(TB), 0, s, keys, psi, n, g, eps2, bm, nabove);
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_dilate, dim3(nb), dim3(TB), 0, s, keys, psi, n, g, eps2, bm, block_counts);
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts, (int64_t)nb, nabove);
 }
 void mark_keys(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s)
 {
