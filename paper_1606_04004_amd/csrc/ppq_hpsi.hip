@@ -338,9 +338,9 @@ __global__ __launch_bounds__(HB) void k_hpsi_cplx(const uint32_t *__restrict__ p
 // One thread per entry of the dimension's permutation (= one output point).
 // A block owns entries [B0, B0+PB); the fibers that straddle its ends are
 // completed from a halo of PH entries on each side (PH >= NMAX - 1 since a
-// fiber has at most n_k members), their values staged in LDS, and each
-// thread contracts its own row of h_k with its fiber: exactly L^2 multiply-
-// adds per fiber, one global load of x and one of y per point.
+// fiber has at most n_k members).  The tile and its halos are staged in LDS
+// with all their loads issued together, and each thread contracts its own
+// row of h_k with its fiber: exactly L^2 multiply-adds per fiber.
 constexpr int PB = 256;
 constexpr int PH = 64;
 
@@ -352,41 +352,53 @@ __global__ __launch_bounds__(PB) void k_hpsi_pt(const uint32_t *__restrict__ pi,
 {
     using C = typename Cx<R>::T;
     if (skip_if && skip_j >= *skip_if) return;
+    constexpr int NW = PB + 2 * PH;
     __shared__ R sT[NMAX * NMAX];
-    __shared__ uint8_t sinfo[PB + 2 * PH];
-    __shared__ C sx[PB + 2 * PH];
-    __shared__ uint32_t sp[PB + 2 * PH];
-    __shared__ int sS, sE;
+    __shared__ uint8_t sinfo[NW];
+    __shared__ C sx[NW];
+    __shared__ uint32_t sp[NW];
+    __shared__ int sE;
     const int tid = threadIdx.x;
     const int64_t B0 = (int64_t)blockIdx.x * PB;
     const int64_t W0 = B0 - PH;
+    // every global load of the tile and its halos at once: positions, fiber
+    // info, x, and V for the tile's own points
+    uint32_t pw[2];
+    uint8_t iw[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = tid + u * PB;
+        const int64_t q = W0 + i;
+        const bool in = i < NW && q >= 0 && q < n;
+        iw[u] = in ? info[q] : (uint8_t)0x80;
+        pw[u] = in ? (IDENT ? (uint32_t)q : pi[q]) : 0xffffffffu;
+    }
+    C xw[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) xw[u] = pw[u] != 0xffffffffu ? x[pw[u]] : Cx<R>::make(0, 0);
+    const int64_t qo = B0 + tid;
+    R vv = 0;
+    if (FIRST && qo < n) vv = V[IDENT ? (uint32_t)qo : pi[qo]];
     for (int i = tid; i < NMAX * NMAX; i += PB) sT[i] = T[i];
-    for (int i = tid; i < PB + 2 * PH; i += PB) {
-        int64_t q = W0 + i;
-        sinfo[i] = (q >= 0 && q < n) ? info[q] : (uint8_t)0x80;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int i = PH;
-        while (i > 0 && !(sinfo[i] & 0x80)) --i;
-        sS = i;
-        int e = PH + PB;
-        while (e < PB + 2 * PH && !(sinfo[e] & 0x80)) ++e;
-        sE = e;
-    }
-    __syncthreads();
-    const int S = sS, E = sE;
-    for (int i = S + tid; i < E; i += PB) {
-        int64_t q = W0 + i;
-        if (q < n) {
-            uint32_t p = IDENT ? (uint32_t)q : pi[q];
-            sp[i] = p;
-            sx[i] = x[p];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = tid + u * PB;
+        if (i < NW) {
+            sinfo[i] = iw[u];
+            sp[i] = pw[u];
+            sx[i] = xw[u];
         }
     }
     __syncthreads();
-    const int64_t q = B0 + tid;
-    if (q >= n) return;
+    // end of the tile's last fiber: the first fiber start in the upper halo
+    // (one ballot of the second wavefront)
+    if ((tid >> 6) == 1) {
+        const uint64_t b = __ballot((sinfo[PH + PB + (tid & 63)] & 0x80) != 0);
+        if ((tid & 63) == 0) sE = b ? PH + PB + (__ffsll((unsigned long long)b) - 1) : NW;
+    }
+    __syncthreads();
+    if (qo >= n) return;
+    const int E = sE;
     const int i = PH + tid;
     int fs = i;
     while (!(sinfo[fs] & 0x80)) --fs;
@@ -402,7 +414,6 @@ __global__ __launch_bounds__(PB) void k_hpsi_pt(const uint32_t *__restrict__ pi,
     }
     const uint32_t p = sp[i];
     if (FIRST) {
-        R vv = V[p];
         C xv = sx[i];
         y[p] = Cx<R>::make(fma(vv, xv.x, ar), fma(vv, xv.y, ai));
     } else {
