@@ -680,7 +680,10 @@ void build_row_major(ppq_ctx *c, int k)
     fill_u64(c->bm, c->nwords + 2, 0ull, s);
     rot_set(keys, n, fr, c->bm, s);
     scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
-    rot_rank(keys, n, fr, c->bm, c->prefix, nullptr, c->pi[k], nullptr, c->flags, c->tmpmask, c->info[k], s);
+    // the per-point fiber info of dimensions other than the last is read only
+    // by the point-parallel-everywhere layout
+    rot_rank(keys, n, fr, c->bm, c->prefix, nullptr, c->pi[k], nullptr, c->flags, c->tmpmask,
+             c->hpsi_variant == 1 ? c->info[k] : nullptr, s);
     scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
     fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
 }
@@ -704,7 +707,7 @@ void build_inner_first(ppq_ctx *c)
         rot_set(keys, n, fr, c->bm, s);
         scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
         rot_rank(keys, n, fr, c->bm, c->prefix, frame ? nullptr : c->inv_R, frame ? c->P_R : c->pi[k],
-                 frame ? c->inv_R : nullptr, c->flags, c->tmpmask, c->info[k], s);
+                 frame ? c->inv_R : nullptr, c->flags, c->tmpmask, nullptr, s);
         scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
         fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
         if (frame)

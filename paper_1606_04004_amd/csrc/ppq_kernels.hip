@@ -385,7 +385,7 @@ __global__ void k_rot_set(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t
 
 // q = rank of the point in the rotated order.  pi[q] receives map[p] (p when
 // map is null); inv[p] = q when inv is given.  flags/tmpmask/info describe the
-// fibers along the rotated (last) digit.
+// fibers along the rotated (last) digit (info may be null).
 __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t nk, uint32_t rin, uint32_t rout,
                            const uint64_t *bm, const uint32_t *prefix, const uint32_t *map, uint32_t *pi,
                            uint32_t *inv, uint32_t *flags, uint64_t *tmpmask, uint8_t *info)
@@ -402,7 +402,7 @@ __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_
     bool start = (m & ((1ull << d) - 1ull)) == 0;
     flags[q] = start ? 1u : 0u;
     if (start) tmpmask[q] = m;
-    info[q] = (uint8_t)(d | (start ? 0x80u : 0u));
+    if (info) info[q] = (uint8_t)(d | (start ? 0x80u : 0u));
 }
 
 // Chunks of whole blocks for the block-fused H*psi.  A block is a maximal run
