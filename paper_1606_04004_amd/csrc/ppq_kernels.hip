@@ -342,7 +342,18 @@ __global__ void k_last_fill(const uint32_t *keys, int64_t n, int nl, const uint3
     uint32_t f = fidx[p];
     uint32_t fk = keys[p] / (uint32_t)nl;
     uint64_t m = 0;
-    for (int64_t q = p; q < n && keys[q] / (uint32_t)nl == fk; ++q) m |= 1ull << (keys[q] % (uint32_t)nl);
+    // the fiber's keys are consecutive: read them 8 at a time (independent loads)
+    bool more = true;
+    for (int64_t q0 = p; more && q0 < n; q0 += 8) {
+        uint32_t kv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) kv[u] = q0 + u < n ? keys[q0 + u] : 0xffffffffu;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (more && kv[u] != 0xffffffffu && kv[u] / (uint32_t)nl == fk) m |= 1ull << (kv[u] % (uint32_t)nl);
+            else more = false;
+        }
+    }
     off[f] = (uint32_t)p;
     mask[f] = m;
 }
