@@ -337,7 +337,7 @@ __global__ __launch_bounds__(HB) void k_hpsi_cplx(const uint32_t *__restrict__ p
 // ---- point-parallel form ----------------------------------------------------
 // One thread per entry of the dimension's permutation (= one output point).
 // A block owns entries [B0, B0+PB); the fibers that straddle its ends are
-// completed from a halo of PH entries on each side (PH >= NMAX - 1 since a
+// completed from a halo on each side (at least NMAX - 1 entries, since a
 // fiber has at most n_k members).  The tile and its halos are staged in LDS
 // with all their loads issued together, and each thread contracts its own
 // row of h_k with its fiber: exactly L^2 multiply-adds per fiber.
@@ -352,7 +352,9 @@ __global__ __launch_bounds__(PB) void k_hpsi_pt(const uint32_t *__restrict__ pi,
 {
     using C = typename Cx<R>::T;
     if (skip_if && skip_j >= *skip_if) return;
-    constexpr int NW = PB + 2 * PH;
+    // halo: a fiber has at most NMAX members, so NMAX - 1 entries suffice
+    constexpr int PHN = NMAX <= 32 ? 32 : PH;
+    constexpr int NW = PB + 2 * PHN;
     __shared__ R sT[NMAX * NMAX];
     __shared__ uint8_t sinfo[NW];
     __shared__ C sx[NW];
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(PB) void k_hpsi_pt(const uint32_t *__restrict__ pi,
     __shared__ int sE;
     const int tid = threadIdx.x;
     const int64_t B0 = (int64_t)blockIdx.x * PB;
-    const int64_t W0 = B0 - PH;
+    const int64_t W0 = B0 - PHN;
     // every global load of the tile and its halos at once: positions, fiber
     // info, x, and V for the tile's own points
     uint32_t pw[2];
@@ -393,13 +395,14 @@ __global__ __launch_bounds__(PB) void k_hpsi_pt(const uint32_t *__restrict__ pi,
     // end of the tile's last fiber: the first fiber start in the upper halo
     // (one ballot of the second wavefront)
     if ((tid >> 6) == 1) {
-        const uint64_t b = __ballot((sinfo[PH + PB + (tid & 63)] & 0x80) != 0);
-        if ((tid & 63) == 0) sE = b ? PH + PB + (__ffsll((unsigned long long)b) - 1) : NW;
+        const int e = PHN + PB + (tid & 63);
+        const uint64_t b = __ballot(e >= NW || (sinfo[e] & 0x80) != 0);
+        if ((tid & 63) == 0) sE = b ? PHN + PB + (__ffsll((unsigned long long)b) - 1) : NW;
     }
     __syncthreads();
     if (qo >= n) return;
     const int E = sE;
-    const int i = PH + tid;
+    const int i = PHN + tid;
     int fs = i;
     while (!(sinfo[fs] & 0x80)) --fs;
     int fe = i + 1;
