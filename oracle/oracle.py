@@ -271,6 +271,27 @@ class Oracle:
         lib().orc_observe(self._m, self._fib_now(), self._s, _dp(self._bra_tabs.view(np.float64)), eps, _dp(out))
         return dict(zip(OBS_FIELDS[1:7], out))
 
+    def expect_q(self):
+        """Position expectation per dimension of the current state,
+        <q_k> = sum_I |c_I|^2 q_k(i_k) / sum_I |c_I|^2.
+
+        The DVR position operator is diagonal in the grid index, with the grid
+        point as its eigenvalue (Sec. II.A), so this is the definition written
+        out.  On a phase-space lattice dimension position is not diagonal in
+        the cell index: NaN.  An empty state gives NaN everywhere.
+        """
+        keys, c = self.state()
+        out = np.full(self.D, np.nan)
+        if keys.size == 0:
+            return out
+        w = np.abs(c) ** 2
+        norm2 = np.sum(w)
+        digits = np.unravel_index(keys.astype(np.int64), self.n)
+        for k in range(self.D):
+            if not self.model.pvb:
+                out[k] = np.sum(w * self.model.q[k][digits[k]]) / norm2
+        return out
+
     def propagate(self, nsteps=None, dt=None, m=None, eps=None, prune=True):
         """Returns (trace[nsteps+1, 8], hashes[nsteps+1]); eps<0 or prune=False: no adaption."""
         nsteps = self.card["nsteps"] if nsteps is None else nsteps

@@ -315,6 +315,52 @@ def test_coherent_state_closed_form():
     assert abs(tr[0, 2] - E) < 1e-10
 
 
+def test_expect_q_follows_classical_trajectory():
+    """Uncoupled harmonic oscillator (m = omega = 1): Ehrenfest's theorem is exact,
+    <q_k>(t) = q0_k cos t + p0_k sin t, whatever the packet's shape."""
+    cd = _coherent_card()
+    o = orc.Oracle(cd)
+    keys, c0 = _full_state(o)
+    o.set_state(keys, c0)
+    q0 = np.array(cd["psi0"]["centre"])
+    p0 = np.array(cd["psi0"]["momentum"])
+    dt = 0.05
+    assert np.max(np.abs(o.expect_q() - q0)) < 1e-10
+    for st in range(1, 41):
+        o.sil_step(dt=dt, m=16)
+        t = st * dt
+        assert np.max(np.abs(o.expect_q() - (q0 * np.cos(t) + p0 * np.sin(t)))) < 1e-9
+
+
+def test_expect_q_special_cases():
+    """One grid point: <q_k> is that point's coordinate for any weight; a state
+    mirror-symmetric in dimension k on a symmetric box: <q_k> = 0; lattice
+    dimensions and the empty state: NaN."""
+    cd = card("small_3d")
+    o = orc.Oracle(cd)
+    n = cd["n"]
+    idx = (3, 7, 2)
+    key = np.ravel_multi_index(idx, n)
+    o.set_state(np.array([key], dtype=np.uint64), np.array([3.0 - 4.0j]))
+    want = [sine_dvr_grid(n[k], cd["lo"][k], cd["hi"][k])[0][idx[k]] for k in range(3)]
+    assert np.array_equal(o.expect_q(), np.array(want))
+    # two points mirrored in dimension 0 (box symmetric about 0), equal weight
+    lo, hi = cd["lo"][0], cd["hi"][0]
+    assert lo == -hi
+    a = (1, 4, 5)
+    b = (n[0] - 2, 4, 5)
+    keys = np.array(sorted([np.ravel_multi_index(a, n), np.ravel_multi_index(b, n)]), dtype=np.uint64)
+    o.set_state(keys, np.array([0.6j, -0.6]))
+    q = o.expect_q()
+    assert abs(q[0]) < 1e-15
+    assert q[1] == sine_dvr_grid(n[1], cd["lo"][1], cd["hi"][1])[0][4]
+    o.set_state(np.zeros(0, dtype=np.uint64), np.zeros(0, dtype=np.complex128))
+    assert np.all(np.isnan(o.expect_q()))
+    op = orc.Oracle(card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0]))
+    op.init_state()
+    assert np.all(np.isnan(op.expect_q()))
+
+
 def test_unpruned_norm_and_energy_conserved():
     o = orc.Oracle(card("small_3d"))
     keys, c0 = _full_state(o)
