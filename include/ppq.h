@@ -190,6 +190,15 @@ int ppq_propagate(ppq_ctx *ctx, int nsteps, double dt, int m, double eps, double
    threshold used for PPQ_OBS_NABOVE. */
 int ppq_observables(ppq_ctx *ctx, double eps, double *out);
 
+/* Position expectation per dimension of the current state (synchronises):
+   q[k] = sum_I |c_I|^2 q_k(i_k) / sum_I |c_I|^2 over the active set, with
+   q_k(i) the sine-DVR grid point of index i; the DVR position operator is
+   diagonal with the grid points as eigenvalues (Sec. II.A).  q is a host
+   array of D doubles owned by the caller.  Phase-space lattice dimensions,
+   where position is not diagonal in the cell index, and an empty or zero
+   state give NaN.  PPQ_E_STATE without a state. */
+int ppq_expect_q(ppq_ctx *ctx, double *q);
+
 /* ---- adjoint gradient of the survival probability (added form) ----------
    J(theta) = |<psi0(centre, momentum)|psi(T)>|^2 after nsteps steps of the
    pruned propagation.  The active-set trajectory {A_n} of the recording run

@@ -221,6 +221,12 @@ class Propagator:
         self._call("ppq_observables", float(eps), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return dict(zip(OBS_FIELDS[1:7], out[1:7]))
 
+    def expect_q(self):
+        """<q_k> per dimension of the current state (NaN on lattice dimensions)."""
+        out = np.zeros(self.D)
+        self._call("ppq_expect_q", out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return out
+
     def time_apply(self, nrep):
         ms = ctypes.c_double(0.0)
         self._call("ppq_time_apply", int(nrep), ctypes.byref(ms))

@@ -177,6 +177,7 @@ struct ppq_ctx {
     double2 *init_tabs = nullptr;
     double2 *bra_tabs = nullptr;
     int tab_nmax = 0;
+    double *qtab = nullptr;  // grid points [MAXD][NMAX_FIBER], then MAXD results (position expectations)
 
     // records
     double *rec = nullptr;
@@ -1471,6 +1472,7 @@ void ppq_destroy(ppq_ctx *c)
     dfree(c->count);
     dfree(c->init_tabs);
     dfree(c->bra_tabs);
+    dfree(c->qtab);
     dfree(c->rec);
     clear_record(c);
     dfree(c->rec_keys);
@@ -1847,6 +1849,36 @@ int ppq_observables(ppq_ctx *c, double eps, double *out)
     return PPQ_OK;
 }
 
+
+int ppq_expect_q(ppq_ctx *c, double *q)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (!q) return fail(c, PPQ_E_ARG, "bad arguments");
+    PPQ_TRY(c, {
+        const int D = c->g.D;
+        std::vector<double> tab((size_t)MAXD * NMAX_FIBER + MAXD, 0.0);
+        unsigned nan_mask = 0;
+        for (int k = 0; k < D; ++k) {
+            if (c->lattice[k]) {
+                nan_mask |= 1u << k;
+                continue;
+            }
+            std::vector<double> pts = sine_dvr_points(c->g.n[k], c->lo[k], c->hi[k]);
+            std::copy(pts.begin(), pts.end(), tab.begin() + (size_t)k * NMAX_FIBER);
+        }
+        if (!c->qtab) c->qtab = dalloc<double>((int64_t)tab.size());
+        double *res = c->qtab + (size_t)MAXD * NMAX_FIBER;
+        ck(hipMemcpyAsync(c->qtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream),
+           "grid points");
+        expect_q(c->keys[c->cur], c->psi[c->cur], c->nact, c->g, c->qtab, NMAX_FIBER, nan_mask, c->partial, res,
+                 c->stream);
+        ck(hipGetLastError(), "expect_q launch");
+        ck(hipStreamSynchronize(c->stream), "expect_q");
+        ck(hipMemcpy(q, res, sizeof(double) * D, hipMemcpyDeviceToHost), "expect_q result");
+    })
+    return PPQ_OK;
+}
 
 int ppq_set_potential_term(ppq_ctx *c, int term, double coef, const double *params)
 {

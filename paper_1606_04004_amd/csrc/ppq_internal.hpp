@@ -229,6 +229,9 @@ void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const Grid
                  int nmax, double eps2, double2 *partial, hipStream_t s);
 void obs_final(const double2 *partial, int nblocks, double *rec, hipStream_t s);
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s);
+// position expectations out[D] (device): two launches, partials in `partial`
+void expect_q(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, const double *q, int nmax,
+              unsigned nan_mask, double2 *partial, double *out, hipStream_t s);
 
 // adjoint
 struct DerivDesc {

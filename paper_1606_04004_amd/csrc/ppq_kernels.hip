@@ -967,6 +967,56 @@ __global__ __launch_bounds__(TB) void k_obs_final(const double2 *partial, int nb
     }
 }
 
+// ---- position expectations ---------------------------------------------------------
+// Per block: sum |c|^2 and, per dimension, sum |c|^2 q_k(i_k); the DVR position
+// is diagonal in the grid index with the grid point as eigenvalue (Sec. II.A).
+// q holds the grid points [D][nmax].
+__global__ __launch_bounds__(TB) void k_expq_partial(const uint32_t *keys, const double2 *psi, int64_t n, GridDesc g,
+                                                     const double *q, int nmax, double2 *partial)
+{
+    double2 acc[1 + MAXD];
+#pragma unroll
+    for (int i = 0; i <= MAXD; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 c = psi[p];
+        double w = fma(c.x, c.x, c.y * c.y);
+        acc[0].x += w;
+        uint32_t key = keys[p];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k)
+            if (k < g.D) {
+                int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+                acc[1 + k].x = fma(w, q[k * nmax + d], acc[1 + k].x);
+            }
+    }
+    block_reduce_store<1 + MAXD>(acc, partial);
+}
+
+// Fixed-order sum of the partials; out[k] = sum_k / sum_0, NaN where bit k of
+// `nan_mask` is set (dimensions without a diagonal position) or the sum is 0.
+__global__ __launch_bounds__(TB) void k_expq_final(const double2 *partial, int nb, int D, unsigned nan_mask,
+                                                   double *out)
+{
+    __shared__ double red[TB];
+    __shared__ double norm2;
+    for (int i = 0; i <= D; ++i) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += TB) s += partial[(int64_t)b * PSTRIDE + i].x;
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int st = TB / 2; st >= 1; st >>= 1) {
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (i == 0) norm2 = red[0];
+            else
+                out[i - 1] = ((nan_mask >> (i - 1)) & 1u) || !(norm2 > 0.0) ? __builtin_nan("") : red[0] / norm2;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_copy_alpha0(const KState *ks, double *dst) { *dst = ks->alpha[0]; }
 __global__ void k_copy_meff(const KState *ks, double *dst) { *dst = (double)ks->meff; }
 
@@ -1539,6 +1589,12 @@ void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const Grid
 void obs_final(const double2 *partial, int nb, double *rec, hipStream_t s)
 {
     hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(TB), 0, s, partial, nb, rec);
+}
+void expect_q(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, const double *q, int nmax,
+              unsigned nan_mask, double2 *partial, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_expq_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, keys, psi, n, g, q, nmax, partial);
+    hipLaunchKernelGGL(k_expq_final, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, g.D, nan_mask, out);
 }
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s)
 {

@@ -258,6 +258,76 @@ def test_trajectory_observables(name, nsteps, prune, torch):
         assert d < 1e-10, nm
 
 
+# ---------------------------------------------------------------------------
+# position expectations
+# ---------------------------------------------------------------------------
+def _box_scale(cd):
+    return max(max(abs(v) for v in cd["lo"]), max(abs(v) for v in cd["hi"]))
+
+
+@pytest.mark.parametrize("name,nsteps", [("hh2d", 40), ("small_3d", 20), ("morse4d", 10), ("small_6d", 5)])
+def test_expect_q_trajectory(name, nsteps, torch):
+    """<q_k> of the GPU state equals the oracle's on the same state (1e-13 of the
+    box size) and the oracle's along its own trajectory (1e-10), twice in a row."""
+    cd = card(name)
+    o = Oracle(cd)
+    ref = Oracle(cd)
+    g = make(cd, torch)
+    o.init_state()
+    g.init_state()
+    scale = _box_scale(cd)
+    for rep in range(2):
+        say(f"expect_q {name}: steps {rep * nsteps}..{(rep + 1) * nsteps}")
+        o.propagate(nsteps=nsteps)
+        g.propagate(nsteps=nsteps)
+        qg = g.expect_q()
+        kg, cg = g.state()
+        ref.set_state(kg, cg)
+        d_same = np.max(np.abs(qg - ref.expect_q()))
+        d_traj = np.max(np.abs(qg - o.expect_q()))
+        say(f"  |A|={kg.size} same-state diff {d_same:.2e} trajectory diff {d_traj:.2e}")
+        assert d_same < 1e-13 * scale
+        assert d_traj < 1e-10
+
+
+@pytest.mark.parametrize("fill,seed", [(1.0, 21), (0.7, 22)])
+def test_expect_q_large_sets(fill, seed, torch):
+    """32^4 grid, full and with a ragged random fill: several grid-stride passes."""
+    cd = card("morse4d")
+    keys = random_active_set(cd["n"], fill, seed, blob=False)
+    c = random_complex(keys.size, seed + 1)
+    say(f"expect_q large set |A|={keys.size}")
+    g = make(cd, torch)
+    g.set_state(keys, c)
+    o = Oracle(cd)
+    o.set_state(keys, c)
+    d = np.max(np.abs(g.expect_q() - o.expect_q()))
+    say(f"  diff {d:.2e}")
+    assert d < 1e-13 * _box_scale(cd)
+
+
+def test_expect_q_edge_cases(torch):
+    cd = card("small_3d")
+    n = cd["n"]
+    o = Oracle(cd)
+    g = make(cd, torch)
+    for idx in ((0, 0, 0), (3, 7, 2), (n[0] - 1, n[1] - 1, n[2] - 1)):
+        say(f"expect_q one point {idx}")
+        keys = np.array([np.ravel_multi_index(idx, n)], dtype=np.uint64)
+        c = np.array([3.0 - 4.0j])
+        g.set_state(keys, c)
+        o.set_state(keys, c)
+        assert np.allclose(g.expect_q(), o.expect_q(), rtol=1e-15, atol=1e-15)
+    say("expect_q empty set")
+    g.set_state(np.zeros(0, np.uint64), np.zeros(0, complex))
+    assert np.all(np.isnan(g.expect_q()))
+    say("expect_q lattice dimensions")
+    lc = lattice_card()
+    gl = make(lc, torch)
+    gl.init_state()
+    assert np.all(np.isnan(gl.expect_q()))
+
+
 def test_shadow_steps_morse4d(torch):
     """Each step of the GPU map from the oracle's state equals the oracle's step:
     identical adapted set, coefficients within 1e-12 (relative to the largest)."""
