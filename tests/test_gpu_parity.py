@@ -576,3 +576,106 @@ def test_apply_h_bench_snapshot_sampled(torch):
         err = np.max(np.abs(y[idx] - ref)) / np.max(np.abs(ref))
         say(f"  precision {prec}: sampled rel err {err:.2e}")
         assert err < tol
+
+
+# ---------------------------------------------------------------------------
+# extreme shapes: one dimension, eight dimensions (the most the context takes),
+# two-point and 64-point (largest) bases, a grid near the 2^32 key limit
+# ---------------------------------------------------------------------------
+def shape_card(n, lo=-4.0, hi=4.0):
+    D = len(n)
+    terms = [{"coef": 0.5, "factors": [{"dim": k, "kind": "power", "p": 2}]} for k in range(D)]
+    terms += [{"coef": 0.05, "factors": [{"dim": k, "kind": "power", "p": 1}, {"dim": k + 1, "kind": "power", "p": 1}]}
+              for k in range(D - 1)]
+    return {"name": f"shape_{'x'.join(map(str, n))}", "D": D, "n": list(n), "lo": [lo] * D, "hi": [hi] * D,
+            "mass": 1.0, "terms": terms, "basis": "dvr",
+            "psi0": {"centre": [0.5] * D, "momentum": [0.3] * D, "width": [0.8] * D},
+            "eps": 1e-4, "dt": 0.05, "nsteps": 10, "krylov": 8}
+
+
+SHAPES = [[64], [2] * 6, [4] * 8, [3, 5, 4, 6, 3, 5, 4, 2], [64, 64, 64], [2, 64, 3]]
+
+
+@pytest.mark.parametrize("n", SHAPES, ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_extreme_shapes_apply_h(n, prec, torch):
+    cd = shape_card(n)
+    o = Oracle(cd)
+    for fill, seed in ((1.0, 1), (0.45, 2)):
+        keys = (np.arange(int(np.prod(n)), dtype=np.uint64) if fill == 1.0
+                else random_active_set(n, fill, seed, blob=False))
+        say(f"extreme shape {n} prec {prec} |A|={keys.size}")
+        x = random_complex(keys.size, seed + 10)
+        ref = o.apply_def(keys, x)
+        g = make(cd, torch, precision=prec)
+        g.set_state(keys, x)
+        if prec == 0:
+            xt = torch.from_numpy(x).cuda()
+        else:
+            xt = torch.from_numpy(x.astype(np.complex64)).cuda()
+        yt = torch.zeros_like(xt)
+        g.apply_h(xt, yt)
+        torch.cuda.synchronize()
+        y = yt.cpu().numpy().astype(np.complex128)
+        if prec == 1:
+            ref = o.apply_def(keys, x.astype(np.complex64).astype(np.complex128))
+        err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        say(f"  rel err {err:.2e}")
+        assert err < (1e-13 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("n", SHAPES, ids=lambda n: "x".join(map(str, n)))
+def test_extreme_shapes_trajectory(n, torch):
+    cd = shape_card(n)
+    say(f"extreme shape trajectory {n}")
+    o = Oracle(cd)
+    g = make(cd, torch)
+    o.init_state()
+    g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=10)
+    tg = g.propagate(nsteps=10)
+    assert np.array_equal(tg[:, 5], tr[:, 5]), "active-set sizes differ"
+    for col in (1, 2, 3, 4, 6):
+        assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    assert np.array_equal(g.state()[0], o.state()[0])
+    assert np.max(np.abs(g.expect_q() - o.expect_q())) < 1e-10
+
+
+def test_grid_near_key_limit(torch):
+    """64^5 x 3 = 3.2e9 grid points (keys above 2^31): a blob of ~10^5 functions
+    inside; product, adaption and three steps against the oracle."""
+    n = [64, 64, 64, 64, 64, 3]
+    assert 2 ** 31 < int(np.prod(n)) < 2 ** 32
+    cd = shape_card(n, lo=-8.0, hi=8.0)
+    rng = np.random.default_rng(5)
+    sub = np.stack(np.meshgrid(*[np.arange(40, 48)] * 5, np.arange(3), indexing="ij"), -1).reshape(-1, 6)
+    sub = sub[rng.random(sub.shape[0]) > 0.2]
+    keys = np.sort(np.ravel_multi_index(tuple(sub.T), n)).astype(np.uint64)
+    assert keys[-1] > 2 ** 31
+    x = random_complex(keys.size, 6) / np.sqrt(keys.size)
+    say(f"grid near key limit |A|={keys.size}")
+    o = Oracle(cd)
+    ref = o.apply_def(keys, x)
+    g = make(cd, torch)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(yt.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    say(f"  product rel err {err:.2e}")
+    assert err < 1e-13
+    o.set_state(keys, x)
+    eps = 2e-3
+    assert g.prune(eps=eps)[1] == o.prune(eps=eps)
+    assert np.array_equal(g.state()[0], o.state()[0])
+    say(f"  after adaption |A|={g.state()[0].size}")
+    tr, _ = o.propagate(nsteps=3, eps=eps)
+    tg = g.propagate(nsteps=3, eps=eps)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    # norm, energy and |S| (C(t) needs the reference packet that only the
+    # context's initial-packet call sets, not a state set from the host)
+    for col in (1, 2, 6):
+        assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    assert np.array_equal(g.state()[0], o.state()[0])
