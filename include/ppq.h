@@ -153,6 +153,14 @@ int ppq_init_gaussian(ppq_ctx *ctx, const double *centre, const double *momentum
    or out of range. */
 int ppq_set_state(ppq_ctx *ctx, int64_t count, const uint64_t *keys, const double *coeff);
 
+/* Replaces the reference packet psi0 of C(t) (Eq. acorr) by the normalised
+   product Gaussian of ppq_init_gaussian (same centre/momentum/width layout,
+   D doubles each, host) without touching the state; e.g. for a state given by
+   ppq_set_state.  ppq_init_gaussian and the adjoint calls also set the
+   reference (to their own packet).  PPQ_E_ARG for a non-positive width or
+   non-finite values. */
+int ppq_set_reference(ppq_ctx *ctx, const double *centre, const double *momentum, const double *width);
+
 /* Number of functions in the active set (no synchronisation needed). */
 int ppq_active_count(const ppq_ctx *ctx, int64_t *count);
 
@@ -179,6 +187,14 @@ int ppq_step(ppq_ctx *ctx, double dt, int m);
    compared as fl(fl(re^2) + fl(im^2)) >= fl(eps^2) (no fused multiply-add).
    n_active / n_above (may be NULL) receive |A'| and the kept count. */
 int ppq_prune(ppq_ctx *ctx, double eps, int64_t *n_active, int64_t *n_above);
+
+/* Relative exclusion threshold r >= 0 of every later adaption (ppq_prune,
+   ppq_propagate, the adjoint recording), Sec. II.E: functions are excluded
+   only when more than r * |A| of them would go; otherwise the new set is
+   A' united with A (all current functions stay, with their coefficients).
+   r = 0 (the default) excludes whatever the threshold rule drops.
+   PPQ_E_ARG for negative or non-finite r. */
+int ppq_set_relative_exclusion(ppq_ctx *ctx, double r);
 
 /* nsteps x {ppq_step(dt, m); ppq_prune(eps)} (eps < 0: no adaption), recording
    an observable record (PPQ_OBS_N doubles) before the first step and after

@@ -168,6 +168,14 @@ class Propagator:
         self._call("ppq_set_state", keys.size, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                    c.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
 
+    def set_reference(self, centre=None, momentum=None, width=None):
+        """C(t) reference packet; defaults to the card's psi0."""
+        ps = self.card["psi0"]
+        c, pc = _d(ps["centre"] if centre is None else centre)
+        m, pm = _d(ps["momentum"] if momentum is None else momentum)
+        w, pw = _d(ps["width"] if width is None else width)
+        self._call("ppq_set_reference", pc, pm, pw)
+
     def active_count(self):
         n = ctypes.c_int64(0)
         self._call("ppq_active_count", ctypes.byref(n))
@@ -202,6 +210,9 @@ class Propagator:
         na, nb = ctypes.c_int64(0), ctypes.c_int64(0)
         self._call("ppq_prune", float(eps), ctypes.byref(na), ctypes.byref(nb))
         return na.value, nb.value
+
+    def set_relative_exclusion(self, r):
+        self._call("ppq_set_relative_exclusion", float(r))
 
     def propagate(self, nsteps=None, dt=None, m=None, eps=None, prune=True):
         nsteps = self.card["nsteps"] if nsteps is None else nsteps

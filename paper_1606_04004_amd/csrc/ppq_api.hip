@@ -178,6 +178,7 @@ struct ppq_ctx {
     double2 *bra_tabs = nullptr;
     int tab_nmax = 0;
     double *qtab = nullptr;  // grid points [MAXD][NMAX_FIBER], then MAXD results (position expectations)
+    double rel_excl = 0.0;   // relative exclusion threshold of adaption
 
     // records
     double *rec = nullptr;
@@ -1061,6 +1062,8 @@ void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
     fill_u64(c->bm, c->nwords + 2, 0ull, s);
     fill_u64((uint64_t *)c->count, 1, 0ull, s);
     dilate(c->keys[c->cur], c->psi[c->cur], n_old, c->g, eps2, c->bm, c->count, c->flags, s);
+    if (c->rel_excl > 0.0)
+        keep_all_if_few_dropped(c->keys[c->cur], n_old, c->bm, c->rel_excl, c->flags, c->count + 1, s);
     scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
     ck(hipMemcpyAsync(c->h_small + MAXD, c->small + MAXD, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "count");
     ck(hipMemcpyAsync(c->h_count, c->count, sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "count");
@@ -1151,7 +1154,11 @@ void energy_into(ppq_ctx *c, int64_t r)
 // Packet tables: init (coefficients of psi0 per dimension), bra (its dual,
 // giving C(t)) and, for DVR dimensions, the derivatives of the normalised 1D
 // factors with respect to the centre and the momentum.
-void set_packet_tables(ppq_ctx *c, const double *centre, const double *momentum, const double *width)
+// Packet tables of a product Gaussian: the initial-state tables (and their
+// centre/momentum derivatives, for the adjoint) and the C(t) reference.  With
+// reference_only, only the C(t) reference is replaced.
+void set_packet_tables(ppq_ctx *c, const double *centre, const double *momentum, const double *width,
+                       bool reference_only = false)
 {
     const int D = c->g.D;
     int nmax = 0;
@@ -1198,17 +1205,21 @@ void set_packet_tables(ppq_ctx *c, const double *centre, const double *momentum,
             it[(size_t)k * nmax + i] = make_double2(a[i].real(), a[i].imag());
             bt[(size_t)k * nmax + i] = make_double2(b[i].real(), b[i].imag());
         }
-        c->pk_centre[k] = centre[k];
-        c->pk_momentum[k] = momentum[k];
-        c->pk_width[k] = width[k];
+        if (!reference_only) {
+            c->pk_centre[k] = centre[k];
+            c->pk_momentum[k] = momentum[k];
+            c->pk_width[k] = width[k];
+        }
     }
     ck(hipStreamSynchronize(c->stream), "sync");
-    dfree(c->init_tabs);
     dfree(c->bra_tabs);
-    dfree(c->dtabs);
-    c->init_tabs = upload(it, c->stream);
     c->bra_tabs = upload(bt, c->stream);
-    c->dtabs = upload(dt, c->stream);
+    if (!reference_only) {
+        dfree(c->init_tabs);
+        dfree(c->dtabs);
+        c->init_tabs = upload(it, c->stream);
+        c->dtabs = upload(dt, c->stream);
+    }
     c->tab_nmax = nmax;
     c->has_ref = true;
 }
@@ -1694,6 +1705,21 @@ int ppq_init_gaussian(ppq_ctx *c, const double *centre, const double *momentum, 
     return PPQ_OK;
 }
 
+int ppq_set_reference(ppq_ctx *c, const double *centre, const double *momentum, const double *width)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (!centre || !momentum || !width) return fail(c, PPQ_E_ARG, "bad packet");
+    for (int k = 0; k < c->g.D; ++k)
+        if (!(width[k] > 0.0) || !std::isfinite(centre[k]) || !std::isfinite(momentum[k]))
+            return fail(c, PPQ_E_ARG, "bad packet");
+    PPQ_TRY(c, {
+        set_packet_tables(c, centre, momentum, width, true);
+        ck(hipStreamSynchronize(c->stream), "reference");
+    })
+    return PPQ_OK;
+}
+
 int ppq_set_state(ppq_ctx *c, int64_t count, const uint64_t *keys, const double *coeff)
 {
     PPQ_GUARD(c)
@@ -1790,6 +1816,14 @@ int ppq_prune(ppq_ctx *c, double eps, int64_t *n_active, int64_t *n_above)
         if (n_active) *n_active = c->nact;
         if (n_above) *n_above = nab;
     })
+    return PPQ_OK;
+}
+
+int ppq_set_relative_exclusion(ppq_ctx *c, double r)
+{
+    PPQ_GUARD(c)
+    if (!(r >= 0.0) || !std::isfinite(r)) return fail(c, PPQ_E_ARG, "relative exclusion must be finite and >= 0");
+    c->rel_excl = r;
     return PPQ_OK;
 }
 
@@ -1990,14 +2024,8 @@ int ppq_adjoint_gradient(ppq_ctx *c, double *dJ_dparam, double *dJ_dcentre, doub
         int64_t nmax_set = *std::max_element(c->rec_n.begin(), c->rec_n.end());
         ensure_capacity(c, std::max<int64_t>(nmax_set, 1));
         // the packet of the recording (ppq_adjoint_frozen may have changed the tables)
-        double cen[MAXD], mom[MAXD], w[MAXD];
-        for (int k = 0; k < D; ++k) {
-            cen[k] = c->pk_centre[k];
-            mom[k] = c->pk_momentum[k];
-            w[k] = c->pk_width[k];
-        }
-        (void)cen;
-        (void)mom;
+        double w[MAXD];
+        for (int k = 0; k < D; ++k) w[k] = c->pk_width[k];
         set_packet_tables(c, c->rec_centre, c->rec_momentum, w);
         build_operator(c);
         ensure_krylov(c, c->rec_m);

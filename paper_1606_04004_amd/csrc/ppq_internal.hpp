@@ -72,6 +72,10 @@ void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc 
 void compact(const uint64_t *bm, const uint32_t *prefix, int64_t nwords, uint32_t *keys_out, hipStream_t s);
 void remap(const uint32_t *okeys, const double2 *opsi, int64_t n_old, const uint64_t *bm, const uint32_t *prefix,
            double2 *npsi, hipStream_t s);
+// relative exclusion: sets the bits of all n keys when at most rel * n of them
+// are clear (block_counts: nblocks(n) entries; dropped: one device counter)
+void keep_all_if_few_dropped(const uint32_t *keys, int64_t n, uint64_t *bm, double rel, unsigned *block_counts,
+                             unsigned long long *dropped, hipStream_t s);
 void mark_keys(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s);
 
 // fiber tables

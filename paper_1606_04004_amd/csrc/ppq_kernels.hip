@@ -283,6 +283,30 @@ __global__ void k_dilate(const uint32_t *keys, const double2 *psi, int64_t n, Gr
     count_block(keep, block_counts);
 }
 
+// Relative exclusion (Sec. II.E): counts the current functions whose bit the
+// dilated set leaves clear, i.e. those adaption would drop (block counts).
+__global__ void k_count_dropped(const uint32_t *keys, int64_t n, const uint64_t *bm, unsigned *block_counts)
+{
+    int64_t p = gid();
+    bool drop = false;
+    if (p < n) {
+        uint32_t key = keys[p];
+        drop = ((bm[key >> 6] >> (key & 63)) & 1ull) == 0ull;
+    }
+    count_block(drop, block_counts);
+}
+
+// Keeps every current function when no more than rel * n of them would be
+// dropped: functions go only if more than that fraction goes.  The test reads
+// one device value, so it is uniform over the grid.
+__global__ void k_keep_all_if(const uint32_t *keys, int64_t n, uint64_t *bm, const unsigned long long *dropped,
+                              double rel)
+{
+    if ((double)*dropped > rel * (double)n) return;
+    int64_t p = gid();
+    set_bit_wave(bm, p < n ? keys[p] : 0u, p < n);
+}
+
 __global__ void k_mark(const uint32_t *keys, int64_t n, uint64_t *bm)
 {
     int64_t p = gid();
@@ -1362,6 +1386,15 @@ void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc 
     const unsigned nb = nblocks(n);
     hipLaunchKernelGGL(k_dilate, dim3(nb), dim3(TB), 0, s, keys, psi, n, g, eps2, bm, block_counts);
     hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts, (int64_t)nb, nabove);
+}
+void keep_all_if_few_dropped(const uint32_t *keys, int64_t n, uint64_t *bm, double rel, unsigned *block_counts,
+                             unsigned long long *dropped, hipStream_t s)
+{
+    if (n <= 0) return;
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_count_dropped, dim3(nb), dim3(TB), 0, s, keys, n, bm, block_counts);
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts, (int64_t)nb, dropped);
+    hipLaunchKernelGGL(k_keep_all_if, dim3(nb), dim3(TB), 0, s, keys, n, bm, dropped, rel);
 }
 void mark_keys(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s)
 {

@@ -176,6 +176,56 @@ def test_prune_edge_cases(torch):
     assert np.array_equal(gl.state()[0], o.state()[0])
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_prune_relative_exclusion_bit_exact(seed, torch):
+    """Relative exclusion threshold (Sec. II.E) below, at and above the dropped
+    fraction: identical sets and carried coefficients."""
+    cd = card("small_4d")
+    o = Oracle(cd)
+    eps = 1e-3
+    keys = random_active_set(o.n, 0.35, seed)
+    rng = np.random.default_rng(seed)
+    c = random_complex(keys.size, seed) * np.exp(rng.uniform(-12, 0, keys.size))
+    c[::17] = eps
+    o.set_state(keys, c)
+    o.prune(eps=eps)
+    dropped = np.setdiff1d(keys, o.state()[0]).size
+    n = keys.size
+    g = make(cd, torch)
+    for r in (0.0, (dropped - 0.5) / n, dropped / n, (dropped + 0.5) / n, 1.0):
+        say(f"relative exclusion seed {seed} r={r:.6f} (dropped {dropped} of {n})")
+        o.set_state(keys, c)
+        nab = o.prune(eps=eps, rel_excl=r)
+        g.set_state(keys, c)
+        g.set_relative_exclusion(r)
+        assert g.prune(eps=eps)[1] == nab
+        kg, cg = g.state()
+        ko, co = o.state()
+        assert np.array_equal(kg, ko)
+        assert np.array_equal(cg, co)
+
+
+def test_relative_exclusion_trajectory(torch):
+    """small_3d, 40 steps with r = 0.05 against the oracle's step/adapt loop."""
+    cd = card("small_3d")
+    r = 0.05
+    o = Oracle(cd)
+    g = make(cd, torch)
+    o.init_state()
+    g.init_state()
+    g.set_relative_exclusion(r)
+    tg = g.propagate(nsteps=40)
+    for st in range(1, 41):
+        o.sil_step()
+        o.prune(rel_excl=r)
+        ob = o.observe()
+        assert int(ob["n_active"]) == int(tg[st, 5]), st
+        for col, nm in ((1, "norm2"), (3, "acf_re"), (4, "acf_im"), (6, "n_above")):
+            assert abs(tg[st, col] - ob[nm]) < 1e-10, (st, nm)
+    assert np.array_equal(g.state()[0], o.state()[0])
+    say(f"  |A| at the end {int(tg[-1, 5])}")
+
+
 @pytest.mark.parametrize("name", ["hh2d", "small_3d", "morse4d", "quartic6d"])
 def test_initial_state(name, torch):
     cd = card(name)
@@ -659,6 +709,7 @@ def test_grid_near_key_limit(torch):
     ref = o.apply_def(keys, x)
     g = make(cd, torch)
     g.set_state(keys, x)
+    g.set_reference()
     xt = torch.from_numpy(x).cuda()
     yt = torch.zeros_like(xt)
     g.apply_h(xt, yt)
@@ -674,8 +725,6 @@ def test_grid_near_key_limit(torch):
     tr, _ = o.propagate(nsteps=3, eps=eps)
     tg = g.propagate(nsteps=3, eps=eps)
     assert np.array_equal(tg[:, 5], tr[:, 5])
-    # norm, energy and |S| (C(t) needs the reference packet that only the
-    # context's initial-packet call sets, not a state set from the host)
-    for col in (1, 2, 6):
+    for col in (1, 2, 3, 4, 6):
         assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
     assert np.array_equal(g.state()[0], o.state()[0])

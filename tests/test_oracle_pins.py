@@ -470,6 +470,42 @@ def test_prune_matches_bruteforce(seed):
     assert np.array_equal(c2, np.array([lookup.get(k, 0j) for k in k2.tolist()]))
 
 
+def adversarial_prune_state(o, seed, eps=1e-3):
+    keys = random_active_set(o.n, 0.35, seed)
+    rng = np.random.default_rng(seed)
+    c = random_complex(keys.size, seed) * np.exp(rng.uniform(-12, 0, keys.size))
+    c[::17] = eps
+    c[5::23] = 0.0
+    return keys, c
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_prune_relative_exclusion_matches_bruteforce(seed):
+    """Sec. II.E: functions are excluded only if more than r |A| of them would
+    go; otherwise A' is united with A.  Thresholds just below, at and just
+    above the dropped count."""
+    cd = card("small_3d")
+    o = orc.Oracle(cd)
+    eps = 1e-3
+    keys, c = adversarial_prune_state(o, seed, eps)
+    plain = brute_adapt(o.n, keys, c, eps)
+    dropped = np.setdiff1d(keys, plain).size
+    n = keys.size
+    assert 0 < dropped < n
+    union = np.union1d(plain, keys).astype(np.uint64)
+    cases = [(0.0, plain), ((dropped - 0.5) / n, plain), ((dropped + 0.5) / n, union), (1.0, union)]
+    r_eq = dropped / n
+    if r_eq * n == dropped:
+        cases.append((r_eq, union))
+    lookup = dict(zip(keys.tolist(), c))
+    for r, want in cases:
+        o.set_state(keys, c)
+        o.prune(eps=eps, rel_excl=r)
+        k2, c2 = o.state()
+        assert np.array_equal(k2, want), r
+        assert np.array_equal(c2, np.array([lookup.get(k, 0j) for k in k2.tolist()]))
+
+
 def test_prune_lattice_stencil_matches_bruteforce():
     cd = card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0])
     o = orc.Oracle(cd)
