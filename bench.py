@@ -69,23 +69,22 @@ def cpu_baseline(cd, reps=50):
                       f"(|A0| = {keys.size}), single thread, {dt:.1f} s"}
 
 
-def timed_steps(g, steps, warmup, m):
-    """Whole-path steps (step + adaption); returns (updates/s, ms per step)."""
+def timed_steps(g, steps, warmup):
+    """Whole-path steps through the library's propagation loop (SIL step,
+    adaption, fiber tables and potential cache of the new set, observable
+    record), one call for all steps.  Returns (updates/s, ms per step, trace);
+    an update is one active point through one H*psi product, so step s counts
+    its Krylov dimension times the size of the set it acted on."""
     import torch
-    for _ in range(warmup):
-        g.step()
-        g.prune()
+    if warmup:
+        g.propagate(nsteps=warmup)
     torch.cuda.synchronize()
-    upd = 0
-    na = g.active_count()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        upd += m * na
-        g.step()
-        na, _ = g.prune()
+    tr = g.propagate(nsteps=steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return upd / wall, wall * 1e3 / steps
+    upd = float(np.sum(tr[1:, 7] * tr[:-1, 5]))
+    return upd / wall, wall * 1e3 / steps, tr
 
 
 def secondary(stream, steps, warmup, adjoint_steps):
@@ -102,7 +101,7 @@ def secondary(stream, steps, warmup, adjoint_steps):
         g.propagate(nsteps=20)
         ms_h = g.time_apply(20)
         na = g.active_count()
-        rate, ms = timed_steps(g, steps, warmup, cd["krylov"])
+        rate, ms, _ = timed_steps(g, steps, warmup)
         out[f"morse4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "hpsi_updates_per_s": na / (ms_h * 1e-3),
                                  "updates_per_s": rate, "ms_per_step": ms,
                                  "from": "step 20 of the 4D coupled Morse card (32^4, eps 1e-6, dt 0.1, m 10)"}
@@ -113,7 +112,7 @@ def secondary(stream, steps, warmup, adjoint_steps):
         g.init_state()
         ms_h = g.time_apply(10)
         na = g.active_count()
-        rate, ms = timed_steps(g, steps, warmup, cd["krylov"])
+        rate, ms, _ = timed_steps(g, steps, warmup)
         out[f"pvb4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
                                "from": "initial set of the 4D phase-space lattice card (48^4, 6x8 lattice per "
                                        "dimension), complex factors on the matrix cores"}
@@ -198,22 +197,15 @@ def main():
     achieved = bpp * n_snap / (ms_h * 1e-3) / 1e9
 
     # whole-path steps
-    for _ in range(args.warmup):
-        g.step()
-        g.prune()
-    torch.cuda.synchronize()
-    updates = 0
-    na = g.active_count()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        updates += m * na          # the step's m products act on the current set
-        g.step()
-        na, _ = g.prune()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    value = updates / wall
-    obs64 = g.observables()
+    value, ms_step, _ = timed_steps(g, args.steps, args.warmup)
+    obs64 = g.observables()      # the FP32 leg is compared with this state
+    # where a step's time goes: a few more steps with the phase events on
+    # (outside the timed region; the events cost a few us per step)
+    g.enable_timings(True)
+    nph = min(args.steps, 5)
+    g.propagate(nsteps=nph)
+    phases = {k: v / nph for k, v in g.timings().items()}
+    g.enable_timings(False)
 
     out = {
         "metric": "pruned H*psi active-point updates/s (whole step) + steps/s",
@@ -227,6 +219,7 @@ def main():
         "hpsi_updates_per_s": hpsi_rate,
         "hpsi_ms": ms_h,
         "active_points_at_snapshot": int(n_snap),
+        "phase_ms_per_step": phases,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -250,25 +243,13 @@ def main():
         g32.init_state()
         g32.set_state(snap_keys, snap_c)
         ms32 = g32.time_apply(50)
-        for _ in range(args.warmup):
-            g32.step()
-            g32.prune()
-        torch.cuda.synchronize()
-        upd32 = 0
-        na = g32.active_count()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            upd32 += m * na
-            g32.step()
-            na, _ = g32.prune()
-        torch.cuda.synchronize()
-        wall32 = time.perf_counter() - t0
+        value32, ms_step32, _ = timed_steps(g32, args.steps, args.warmup)
         bpp32 = bytes_per_point(D, 1)
         obs32 = g32.observables()
         err = {k: abs(obs32[k] - obs64[k]) for k in ("norm2", "acf_re", "acf_im")}
         err["energy_rel"] = abs(obs32["energy"] - obs64["energy"]) / abs(obs64["energy"])
         err["n_active_rel"] = abs(obs32["n_active"] - obs64["n_active"]) / obs64["n_active"]
-        out["fp32"] = {"value": upd32 / wall32, "ms_per_step": wall32 * 1e3 / args.steps,
+        out["fp32"] = {"value": value32, "ms_per_step": ms_step32,
                        "error_vs_fp64_after_steps": err,
                        "hpsi_updates_per_s": n_snap / (ms32 * 1e-3), "hpsi_ms": ms32,
                        "roofline_frac": bpp32 * n_snap / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,

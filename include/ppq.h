@@ -266,6 +266,27 @@ int ppq_time_apply(ppq_ctx *ctx, int nrep, double *ms_per_apply);
    (lines of the set along dimension k), k < D.  Synchronises. */
 int ppq_fiber_counts(ppq_ctx *ctx, int64_t *nf);
 
+/* Phases of a propagation step, for ppq_timings. */
+enum {
+    PPQ_PHASE_HPSI = 0,      /* the m products H_A v_j of the Krylov build (Sec. II.B.2) */
+    PPQ_PHASE_KRYLOV = 1,    /* normalisation, CGS2 dot products and updates, small exponential, recombination */
+    PPQ_PHASE_ADAPT = 2,     /* threshold, neighbours, compaction and coefficient carry (Sec. II.E) */
+    PPQ_PHASE_TABLES = 3,    /* fiber tables of the new set and its potential cache (appendix) */
+    PPQ_PHASE_OBS = 4,       /* observable records */
+    PPQ_PHASE_N = 5
+};
+
+/* Turns per-phase timing on (on != 0: accumulators reset) or off.  While on,
+   ppq_step, ppq_prune and ppq_propagate record a HIP event on the context
+   stream at every phase boundary; the time between consecutive events goes to
+   the phase that started at the first (GPU time line, so host waits inside a
+   phase count for it).  Off by default: no events are recorded. */
+int ppq_enable_timings(ppq_ctx *ctx, int on);
+
+/* Milliseconds per phase accumulated since timing was turned on:
+   ms[PPQ_PHASE_N] (host).  Synchronises. */
+int ppq_timings(ppq_ctx *ctx, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

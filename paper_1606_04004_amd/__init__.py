@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import _ppq
-from ._ppq import OBS_FIELDS, OBS_N, PPQ_FP32, PPQ_FP64, PPQError  # noqa: F401
+from ._ppq import OBS_FIELDS, OBS_N, PHASES, PPQ_FP32, PPQ_FP64, PPQError  # noqa: F401
 
 __all__ = ["Propagator", "PPQError", "PPQ_FP64", "PPQ_FP32", "OBS_FIELDS"]
 
@@ -242,6 +242,15 @@ class Propagator:
         ms = ctypes.c_double(0.0)
         self._call("ppq_time_apply", int(nrep), ctypes.byref(ms))
         return ms.value
+
+    def enable_timings(self, on=True):
+        self._call("ppq_enable_timings", 1 if on else 0)
+
+    def timings(self):
+        """Milliseconds per phase since timing was turned on (dict by phase name)."""
+        ms = np.zeros(len(PHASES))
+        self._call("ppq_timings", ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return dict(zip(PHASES, ms.tolist()))
 
     def fiber_counts(self):
         nf = np.zeros(self.D, dtype=np.int64)

@@ -16,6 +16,7 @@ PPQ_FP64, PPQ_FP32 = 0, 1
 PPQ_FAC_POWER, PPQ_FAC_MORSE, PPQ_FAC_TABLE, PPQ_FAC_MORSE_DA = 0, 1, 2, 3
 OBS_FIELDS = ("t", "norm2", "energy", "acf_re", "acf_im", "n_active", "n_above", "krylov_used")
 OBS_N = 8
+PHASES = ("hpsi", "krylov", "adapt", "tables", "obs")  # ppq_timings order
 
 # every exported symbol and its (restype, argtypes)
 _vp = ctypes.c_void_p
@@ -53,6 +54,8 @@ SIGNATURES = {
     "ppq_adjoint_gradient": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "ppq_time_apply": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "ppq_fiber_counts": (ctypes.c_int, [_vp, _i64p]),
+    "ppq_enable_timings": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "ppq_timings": (ctypes.c_int, [_vp, _dp]),
 }
 
 _LIB = None

@@ -179,6 +179,11 @@ struct ppq_ctx {
     int tab_nmax = 0;
     double *qtab = nullptr;  // grid points [MAXD][NMAX_FIBER], then MAXD results (position expectations)
     double rel_excl = 0.0;   // relative exclusion threshold of adaption
+    // fiber tables of all non-last dimensions at once (see fiber_tables_all)
+    uint64_t *bmB = nullptr;
+    uint32_t *pfxB = nullptr, *flagsB = nullptr, *fidxB = nullptr, *scanB = nullptr, *cntB = nullptr;
+    uint64_t *tmaskB = nullptr;
+    int64_t bat_cap = 0;     // entries per dimension of flagsB/fidxB/tmaskB (0: not allocated)
 
     // records
     double *rec = nullptr;
@@ -186,6 +191,12 @@ struct ppq_ctx {
 
     // measurement
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // opt-in phase timing: events recorded at phase boundaries
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    std::vector<int> tlabel;  // phase started at each recorded event (-1: none)
+    size_t tcount = 0;
+    double tms[PPQ_PHASE_N] = {};
 
     // adjoint: derivative terms dV/dtheta_p, recorded trajectory, work buffers
     std::vector<Term> dterms;
@@ -257,6 +268,14 @@ void free_state_buffers(ppq_ctx *c)
         dfree(c->big[i]);
     }
     for (int k = 0; k < MAXD; ++k) dfree(c->fch[k]);
+    dfree(c->bmB);
+    dfree(c->pfxB);
+    dfree(c->flagsB);
+    dfree(c->fidxB);
+    dfree(c->scanB);
+    dfree(c->cntB);
+    dfree(c->tmaskB);
+    c->bat_cap = 0;
     c->cap = 0;
 }
 
@@ -719,6 +738,42 @@ void build_inner_first(ppq_ctx *c)
     }
 }
 
+// Device memory the one-pass tables of all non-last dimensions need, or 0 if
+// they do not apply (one dimension; concatenated ranks beyond 32 bits).
+constexpr int64_t BATCH_BYTES_MAX = 8ll << 30;
+int64_t batched_bytes(const ppq_ctx *c)
+{
+    const int64_t nd = c->g.D - 1;
+    if (nd < 1 || nd * c->cap >= (1ll << 32)) return 0;
+    const int64_t words = nd * c->nwords + 2;
+    return words * 12 + nd * c->cap * 16 + scan_tmp_words(std::max(nd * c->cap, words)) * 4;
+}
+
+bool ensure_batched(ppq_ctx *c)
+{
+    const int64_t bytes = batched_bytes(c);
+    if (bytes == 0 || bytes > BATCH_BYTES_MAX) return false;
+    if (c->bat_cap == c->cap) return true;
+    const int64_t nd = c->g.D - 1, words = nd * c->nwords + 2;
+    dfree(c->bmB);
+    dfree(c->pfxB);
+    dfree(c->flagsB);
+    dfree(c->fidxB);
+    dfree(c->scanB);
+    dfree(c->cntB);
+    dfree(c->tmaskB);
+    c->bat_cap = 0;
+    c->bmB = dalloc<uint64_t>(words);
+    c->pfxB = dalloc<uint32_t>(words);
+    c->flagsB = dalloc<uint32_t>(nd * c->cap);
+    c->fidxB = dalloc<uint32_t>(nd * c->cap);
+    c->tmaskB = dalloc<uint64_t>(nd * c->cap);
+    c->scanB = dalloc<uint32_t>(scan_tmp_words(std::max(nd * c->cap, words)));
+    c->cntB = dalloc<uint32_t>(2 + MAXD);
+    c->bat_cap = c->cap;
+    return true;
+}
+
 void build_derived(ppq_ctx *c)
 {
     if (c->derived_valid) return;
@@ -739,9 +794,27 @@ void build_derived(ppq_ctx *c)
     last_fill(keys, n, c->g.n[D - 1], c->flags, c->fidx, &c->small[D - 1], c->off[D - 1], c->mask[D - 1], s);
     last_info(keys, n, c->g.n[D - 1], c->info[D - 1], s);
     if (try_block) chunk_fibers(c->chunk[0], n, BLOCK_WINDOW, c->fidx, &c->small[D - 1], c->fch[D - 1], s);
-    for (int k = try_block ? c->split : 0; k < D - 1; ++k) {
-        build_row_major(c, k);
-        if (try_block) chunk_fibers(c->chunk[0], n, BLOCK_WINDOW, c->fidx, &c->small[k], c->fch[k], s);
+    // the per-point fiber info of dimensions other than the last is read only
+    // by the point-parallel-everywhere layout, which takes the per-dimension path
+    if (!try_block && c->hpsi_variant != 1 && n > 0 && D > 1 && ensure_batched(c)) {
+        RotAll r{};
+        TabPtrs t{};
+        r.nd = D - 1;
+        r.nwords = c->nwords;
+        for (int k = 0; k < D - 1; ++k) {
+            r.sk[k] = c->g.stride[k];
+            r.nk[k] = (uint32_t)c->g.n[k];
+            t.pi[k] = c->pi[k];
+            t.off[k] = c->off[k];
+            t.mask[k] = c->mask[k];
+        }
+        fiber_tables_all(keys, n, r, c->bmB, c->pfxB, t, c->flagsB, c->fidxB, c->tmaskB, c->scanB, c->cntB, c->small,
+                         s);
+    } else {
+        for (int k = try_block ? c->split : 0; k < D - 1; ++k) {
+            build_row_major(c, k);
+            if (try_block) chunk_fibers(c->chunk[0], n, BLOCK_WINDOW, c->fidx, &c->small[k], c->fch[k], s);
+        }
     }
     if (try_block) build_inner_first(c);
     if (!c->any_lattice) {
@@ -1007,6 +1080,47 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
 
 // Lanczos/Arnoldi basis of `src` (FP64 master vector on the current set) in
 // Vb with the small matrix and norm in ks; m H-applications, CGS2.
+// ---- opt-in phase timing ------------------------------------------------------
+constexpr size_t TIMING_EVENTS = 4096;
+constexpr int PHASE_NONE = -1;
+
+// Adds the intervals between the recorded events to their phases and keeps
+// the last event as the start of the next interval.  The last event must have
+// completed.
+void timing_flush(ppq_ctx *c)
+{
+    for (size_t i = 0; i + 1 < c->tcount; ++i) {
+        float ms = 0.0f;
+        ck(hipEventElapsedTime(&ms, c->tev[i], c->tev[i + 1]), "elapsed");
+        if (c->tlabel[i] >= 0) c->tms[c->tlabel[i]] += ms;
+    }
+    if (c->tcount > 1) {
+        std::swap(c->tev[0], c->tev[c->tcount - 1]);
+        c->tlabel[0] = c->tlabel[c->tcount - 1];
+        c->tcount = 1;
+    }
+}
+
+// Records a phase boundary: `phase` starts now (PHASE_NONE: nothing runs).
+void mark(ppq_ctx *c, int phase)
+{
+    if (!c->timing) return;
+    if (c->tcount == c->tev.size()) {
+        if (c->tev.size() < TIMING_EVENTS) {
+            hipEvent_t e;
+            ck(hipEventCreate(&e), "event");
+            c->tev.push_back(e);
+            c->tlabel.push_back(PHASE_NONE);
+        } else {
+            ck(hipEventSynchronize(c->tev[c->tcount - 1]), "event sync");
+            timing_flush(c);
+        }
+    }
+    ck(hipEventRecord(c->tev[c->tcount], c->stream), "event");
+    c->tlabel[c->tcount] = phase;
+    ++c->tcount;
+}
+
 template <class C>
 void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
 {
@@ -1020,7 +1134,9 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
     normalise_from_master<C>(src, n, ks, Vb, s);
     for (int j = 0; j < m; ++j) {
         const C *vj = Vb + (int64_t)j * ld;
+        mark(c, PPQ_PHASE_HPSI);
         apply_internal(c, vj, w, meff, j);
+        mark(c, PPQ_PHASE_KRYLOV);
         const bool last = (j == m - 1);
         if (last && herm) {
             // only alpha_{m-1} = <v_j|H v_j> enters the tridiagonal matrix
@@ -1037,6 +1153,7 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
 template <class C>
 void step_impl(ppq_ctx *c, double dt, int m)
 {
+    mark(c, PPQ_PHASE_KRYLOV);
     C *Vb = (C *)c->Vk;
     krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m);
     krylov_expv(c->ks, m, dt, c->any_lattice ? 0 : 1, c->stream);
@@ -1046,6 +1163,7 @@ void step_impl(ppq_ctx *c, double dt, int m)
 
 void do_step(ppq_ctx *c, double dt, int m)
 {
+    mark(c, PPQ_PHASE_TABLES);
     build_derived(c);
     ensure_krylov(c, m);
     if (c->nact == 0) return;
@@ -1056,6 +1174,7 @@ void do_step(ppq_ctx *c, double dt, int m)
 // adaption; returns false (state untouched) only on allocation failure
 void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
 {
+    mark(c, PPQ_PHASE_ADAPT);
     hipStream_t s = c->stream;
     const int64_t n_old = c->nact;
     double eps2 = eps * eps;
@@ -1098,13 +1217,8 @@ void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
 
 void set_record_host(ppq_ctx *c, int64_t r, double t, int krylov)
 {
-    // t, |A| and Krylov dimension are host-known; written via a small H2D copy
-    double vals[3] = {t, (double)c->nact, (double)krylov};
-    double *rec = c->rec + r * PPQ_OBS_N;
-    ck(hipMemcpyAsync(rec + PPQ_OBS_T, &vals[0], sizeof(double), hipMemcpyHostToDevice, c->stream), "rec");
-    ck(hipMemcpyAsync(rec + PPQ_OBS_NACTIVE, &vals[1], sizeof(double), hipMemcpyHostToDevice, c->stream), "rec");
-    ck(hipMemcpyAsync(rec + PPQ_OBS_KRYLOV, &vals[2], sizeof(double), hipMemcpyHostToDevice, c->stream), "rec");
-    ck(hipStreamSynchronize(c->stream), "rec");
+    // t, |A| and the Krylov dimension are host-known: kernel arguments, no sync
+    set_record(c->rec + r * PPQ_OBS_N, t, (double)c->nact, (double)krylov, c->stream);
 }
 
 void ensure_records(ppq_ctx *c, int64_t nrec)
@@ -1502,6 +1616,7 @@ void ppq_destroy(ppq_ctx *c)
     if (c->h_small) (void)hipHostFree(c->h_small);
     if (c->h_count) (void)hipHostFree(c->h_count);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -1799,7 +1914,10 @@ int ppq_step(ppq_ctx *c, double dt, int m)
     PPQ_GUARD(c)
     if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
     if (m < 1 || m > MAXM || !std::isfinite(dt)) return fail(c, PPQ_E_ARG, "1 <= m <= 16, finite dt");
-    PPQ_TRY(c, { do_step(c, dt, m); })
+    PPQ_TRY(c, {
+        do_step(c, dt, m);
+        mark(c, PHASE_NONE);
+    })
     return PPQ_OK;
 }
 
@@ -1812,9 +1930,36 @@ int ppq_prune(ppq_ctx *c, double eps, int64_t *n_active, int64_t *n_above)
         if (!c->scan_tmp) ensure_capacity(c, 1024);
         int64_t nab = 0;
         do_prune(c, eps, &nab);
+        mark(c, PHASE_NONE);
         ck(hipStreamSynchronize(c->stream), "prune");
         if (n_active) *n_active = c->nact;
         if (n_above) *n_above = nab;
+    })
+    return PPQ_OK;
+}
+
+int ppq_enable_timings(ppq_ctx *c, int on)
+{
+    PPQ_GUARD(c)
+    PPQ_TRY(c, {
+        ck(hipStreamSynchronize(c->stream), "timings");
+        if (c->timing) timing_flush(c);  // keep what the recorded events measured
+        c->timing = on != 0;
+        c->tcount = 0;
+        if (c->timing)
+            for (double &v : c->tms) v = 0.0;
+    })
+    return PPQ_OK;
+}
+
+int ppq_timings(ppq_ctx *c, double *ms)
+{
+    PPQ_GUARD(c)
+    if (!ms) return fail(c, PPQ_E_ARG, "null argument");
+    PPQ_TRY(c, {
+        ck(hipStreamSynchronize(c->stream), "timings");
+        timing_flush(c);
+        for (int i = 0; i < PPQ_PHASE_N; ++i) ms[i] = c->tms[i];
     })
     return PPQ_OK;
 }
@@ -1836,10 +1981,13 @@ int ppq_propagate(ppq_ctx *c, int nsteps, double dt, int m, double eps, double *
         if (!c->scan_tmp) ensure_capacity(c, 1024);
         ensure_records(c, (int64_t)nsteps + 1);
         double eps_obs = eps < 0 ? 0.0 : eps;
+        mark(c, PPQ_PHASE_TABLES);
         build_derived(c);
+        mark(c, PPQ_PHASE_OBS);
         observe_into(c, 0, eps_obs);
         set_record_host(c, 0, 0.0, 0);
         for (int st = 1; st <= nsteps; ++st) {
+            mark(c, PPQ_PHASE_TABLES);
             build_derived(c);
             ensure_krylov(c, m);
             if (c->nact) {
@@ -1849,12 +1997,15 @@ int ppq_propagate(ppq_ctx *c, int nsteps, double dt, int m, double eps, double *
                 copy_alpha0(c->ks, c->rec + (int64_t)(st - 1) * PPQ_OBS_N + PPQ_OBS_ENERGY, c->stream);
             }
             if (eps >= 0.0) do_prune(c, eps, nullptr);
+            mark(c, PPQ_PHASE_TABLES);
             build_derived(c);
+            mark(c, PPQ_PHASE_OBS);
             observe_into(c, st, eps_obs);
             set_record_host(c, st, st * dt, m);
             if (c->nact) copy_meff(c->ks, c->rec + (int64_t)st * PPQ_OBS_N + PPQ_OBS_KRYLOV, c->stream);
         }
         energy_into(c, nsteps);
+        mark(c, PHASE_NONE);
         ck(hipStreamSynchronize(c->stream), "propagate");
         if (trace) {
             ck(hipMemcpy(trace, c->rec, sizeof(double) * PPQ_OBS_N * ((int64_t)nsteps + 1), hipMemcpyDeviceToHost),
@@ -1981,6 +2132,7 @@ int ppq_adjoint_record(ppq_ctx *c, const double *centre, const double *momentum,
         c->rec_dt = dt;
         c->rec_every = checkpoint_every;
         c->recorded = true;
+        mark(c, PHASE_NONE);
         if (J) *J = c->rec_C.x * c->rec_C.x + c->rec_C.y * c->rec_C.y;
     })
     return PPQ_OK;
@@ -2011,6 +2163,7 @@ int ppq_adjoint_frozen(ppq_ctx *c, const double *centre, const double *momentum,
         }
         double2 C = overlap_with_packet(c);
         *J = C.x * C.x + C.y * C.y;
+        mark(c, PHASE_NONE);
     })
     return PPQ_OK;
 }
@@ -2042,6 +2195,7 @@ int ppq_adjoint_gradient(ppq_ctx *c, double *dJ_dparam, double *dJ_dcentre, doub
             if (dJ_dcentre) dJ_dcentre[k] = grad(dC[c->nparam + 2 * k]);
             if (dJ_dmomentum) dJ_dmomentum[k] = grad(dC[c->nparam + 2 * k + 1]);
         }
+        mark(c, PHASE_NONE);
     })
     return PPQ_OK;
 }

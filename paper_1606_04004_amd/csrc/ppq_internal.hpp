@@ -90,6 +90,23 @@ struct RotFrame {
     uint32_t rin, rout;  // inner-first frame (S_in, total / S_in); rin == 0: row-major frame
 };
 inline RotFrame row_major_rot(const GridDesc &g, int k) { return RotFrame{g.stride[k], (uint32_t)g.n[k], 0u, 0u}; }
+// fiber tables of dimensions 0..nd-1 (row-major frames) in one set of launches
+struct RotAll {
+    int nd;                 // dimensions 0..nd-1 (all but the last)
+    uint32_t sk[MAXD];      // stride of the digit moved last
+    uint32_t nk[MAXD];      // its size
+    int64_t nwords;         // words per rotated bitmap
+};
+struct TabPtrs {
+    uint32_t *pi[MAXD];
+    uint32_t *off[MAXD];
+    uint64_t *mask[MAXD];
+};
+// bm: nd*nwords + 2 words; prefix: nd*nwords; flags, fidx, tmpmask: nd*n entries;
+// counters: 2 + nd entries of scratch; nf[k] receives dimension k's fiber count.
+void fiber_tables_all(const uint32_t *keys, int64_t n, const RotAll &r, uint64_t *bm, uint32_t *prefix,
+                      const TabPtrs &t, uint32_t *flags, uint32_t *fidx, uint64_t *tmpmask, uint32_t *scan_tmp,
+                      uint32_t *counters, uint32_t *nf, hipStream_t s);
 void rot_set(const uint32_t *keys, int64_t n, const RotFrame &f, uint64_t *bm, hipStream_t s);
 void rot_rank(const uint32_t *keys, int64_t n, const RotFrame &f, const uint64_t *bm, const uint32_t *prefix,
               const uint32_t *map, uint32_t *pi, uint32_t *inv, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,
@@ -233,6 +250,7 @@ void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const Grid
                  int nmax, double eps2, double2 *partial, hipStream_t s);
 void obs_final(const double2 *partial, int nblocks, double *rec, hipStream_t s);
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s);
+void set_record(double *rec, double t, double nact, double krylov, hipStream_t s);
 // position expectations out[D] (device): two launches, partials in `partial`
 void expect_q(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, const double *q, int nmax,
               unsigned nan_mask, double2 *partial, double *out, hipStream_t s);

@@ -440,6 +440,72 @@ __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_
     if (info) info[q] = (uint8_t)(d | (start ? 0x80u : 0u));
 }
 
+// ---- fiber tables of every non-last dimension in one set of launches ----------
+// The D-1 rotated bitmaps (digit k moved last, k < D-1) are concatenated, each
+// nwords long.  Every bitmap holds exactly n bits (rotation permutes the keys),
+// so one exclusive prefix over the concatenation gives bitmap k's ranks offset
+// by k n, and one scan over the concatenated fiber-start flags gives dimension
+// k's fiber numbers offset by the count of the earlier dimensions.
+__global__ void k_rot_set_all(const uint32_t *keys, int64_t n, RotAll r, uint64_t *bm)
+{
+    int64_t p = gid();
+    const bool valid = p < n;
+    const uint32_t key = valid ? keys[p] : 0u;
+    for (int k = 0; k < r.nd; ++k) {
+        uint32_t d, rk = 0;
+        if (valid) rk = rotate_key(key, r.sk[k], r.nk[k], &d);
+        set_bit_wave(bm + (int64_t)k * r.nwords, rk, valid);
+    }
+}
+
+__global__ void k_rot_rank_all(const uint32_t *keys, int64_t n, RotAll r, const uint64_t *bm, const uint32_t *prefix,
+                               TabPtrs t, uint32_t *flags, uint64_t *tmpmask)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    const uint32_t key = keys[p];
+    for (int k = 0; k < r.nd; ++k) {
+        const uint64_t *b = bm + (int64_t)k * r.nwords;
+        uint32_t d;
+        const uint32_t rk = rotate_key(key, r.sk[k], r.nk[k], &d);
+        const uint64_t word = b[rk >> 6];
+        const uint32_t q = prefix[(int64_t)k * r.nwords + (rk >> 6)] - (uint32_t)((int64_t)k * n) +
+                           (uint32_t)__popcll(word & ((1ull << (rk & 63)) - 1ull));
+        t.pi[k][q] = (uint32_t)p;
+        const uint64_t m = extract_bits(b, rk - d, (int)r.nk[k]);
+        const bool start = (m & ((1ull << d) - 1ull)) == 0;
+        const int64_t i = (int64_t)k * n + q;
+        flags[i] = start ? 1u : 0u;
+        if (start) tmpmask[i] = m;
+    }
+}
+
+// Per dimension: first fiber number (base), fiber count (nf) and the end
+// sentinel off_k[nf_k] = n.  `total` is the scan's total over all dimensions.
+__global__ void k_seg_counts(const uint32_t *fidx, int64_t n, int nd, const uint32_t *total, TabPtrs t,
+                             uint32_t *base, uint32_t *nf)
+{
+    const int k = threadIdx.x;
+    if (k >= nd) return;
+    const uint32_t b0 = fidx[(int64_t)k * n];
+    const uint32_t b1 = (k + 1 < nd) ? fidx[(int64_t)(k + 1) * n] : *total;
+    base[k] = b0;
+    nf[k] = b1 - b0;
+    t.off[k][b1 - b0] = (uint32_t)n;
+}
+
+__global__ void k_fib_fill_all(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
+                               int nd, const uint32_t *base, TabPtrs t)
+{
+    int64_t i = gid();
+    if (i >= (int64_t)nd * n || !flags[i]) return;
+    const int k = (int)(i / n);
+    const uint32_t q = (uint32_t)(i - (int64_t)k * n);
+    const uint32_t f = fidx[i] - base[k];
+    t.off[k][f] = q;
+    t.mask[k][f] = tmpmask[i];
+}
+
 // Chunks of whole blocks for the block-fused H*psi.  A block is a maximal run
 // of frame positions with the same block id (key / S_in in the row-major frame,
 // key mod S_in in the inner-first frame, both non-decreasing along the frame).
@@ -1041,6 +1107,14 @@ __global__ __launch_bounds__(TB) void k_expq_final(const double2 *partial, int n
     }
 }
 
+// host-known fields of one observable record
+__global__ void k_set_record(double *rec, double t, double nact, double krylov)
+{
+    rec[PPQ_OBS_T] = t;
+    rec[PPQ_OBS_NACTIVE] = nact;
+    rec[PPQ_OBS_KRYLOV] = krylov;
+}
+
 __global__ void k_copy_alpha0(const KState *ks, double *dst) { *dst = ks->alpha[0]; }
 __global__ void k_copy_meff(const KState *ks, double *dst) { *dst = (double)ks->meff; }
 
@@ -1464,6 +1538,22 @@ void last_info(const uint32_t *keys, int64_t n, int nlast, uint8_t *info, hipStr
     if (n <= 0) return;
     hipLaunchKernelGGL(k_last_info, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, nlast, info);
 }
+void fiber_tables_all(const uint32_t *keys, int64_t n, const RotAll &r, uint64_t *bm, uint32_t *prefix,
+                      const TabPtrs &t, uint32_t *flags, uint32_t *fidx, uint64_t *tmpmask, uint32_t *scan_tmp,
+                      uint32_t *counters, uint32_t *nf, hipStream_t s)
+{
+    if (n <= 0 || r.nd <= 0) return;
+    const int64_t words = (int64_t)r.nd * r.nwords;
+    const int64_t m = (int64_t)r.nd * n;
+    fill_u64(bm, words + 2, 0ull, s);
+    hipLaunchKernelGGL(k_rot_set_all, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, r, bm);
+    scan_popcount(bm, words, prefix, &counters[0], scan_tmp, s);
+    hipLaunchKernelGGL(k_rot_rank_all, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, r, bm, prefix, t, flags, tmpmask);
+    scan_u32(flags, m, fidx, &counters[1], scan_tmp, s);
+    hipLaunchKernelGGL(k_seg_counts, dim3(1), dim3(64), 0, s, fidx, n, r.nd, &counters[1], t, &counters[2], nf);
+    hipLaunchKernelGGL(k_fib_fill_all, dim3(nblocks(m)), dim3(TB), 0, s, flags, fidx, tmpmask, n, r.nd, &counters[2],
+                       t);
+}
 void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n, const uint32_t *nf,
               uint32_t *off, uint64_t *mask, hipStream_t s)
 {
@@ -1628,6 +1718,10 @@ void expect_q(const uint32_t *keys, const double2 *psi, int64_t n, const GridDes
 {
     hipLaunchKernelGGL(k_expq_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, keys, psi, n, g, q, nmax, partial);
     hipLaunchKernelGGL(k_expq_final, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, g.D, nan_mask, out);
+}
+void set_record(double *rec, double t, double nact, double krylov, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_record, dim3(1), dim3(1), 0, s, rec, t, nact, krylov);
 }
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s)
 {

@@ -378,6 +378,36 @@ def test_expect_q_edge_cases(torch):
     assert np.all(np.isnan(gl.expect_q()))
 
 
+def test_phase_timings(torch):
+    """Phase events leave the trajectory bit-identical; every phase of a step
+    takes time; the phases add up to at most the host's wall time."""
+    import time
+    cd = card("morse4d")
+    a = make(cd, torch)
+    b = make(cd, torch)
+    a.init_state()
+    b.init_state()
+    ta = a.propagate(nsteps=10)
+    b.enable_timings(True)
+    t0 = time.perf_counter()
+    tb = b.propagate(nsteps=10)
+    wall = (time.perf_counter() - t0) * 1e3
+    ph = b.timings()
+    say(f"phases (ms): {ph}, wall {wall:.2f} ms")
+    assert np.array_equal(ta, tb)
+    assert np.array_equal(a.state()[1], b.state()[1])
+    assert all(v > 0.0 for v in ph.values())
+    assert sum(ph.values()) <= wall
+    b.enable_timings(False)
+    b.propagate(nsteps=2)
+    assert b.timings() == ph
+    b.enable_timings(True)
+    b.step()
+    b.prune()
+    ph2 = b.timings()
+    assert ph2["hpsi"] > 0 and ph2["krylov"] > 0 and ph2["adapt"] > 0 and ph2["obs"] == 0.0
+
+
 def test_shadow_steps_morse4d(torch):
     """Each step of the GPU map from the oracle's state equals the oracle's step:
     identical adapted set, coefficients within 1e-12 (relative to the largest)."""
