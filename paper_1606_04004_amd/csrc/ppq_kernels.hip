@@ -1011,18 +1011,41 @@ __global__ __launch_bounds__(TB) void k_dot_partial(const double2 *a, const doub
 __global__ __launch_bounds__(TB) void k_obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, GridDesc g,
                                                     const double2 *bra, int nmax, double eps2, double2 *partial)
 {
+    // the 1D tables of the reference packet (at most MAXD x 64 entries) in LDS
+    __shared__ double2 sbra[MAXD * NMAX_FIBER];
+    for (int i = threadIdx.x; i < g.D * nmax; i += TB) sbra[i] = bra[i];
+    __syncthreads();
     double2 acc[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
-        double2 c = psi[p];
-        acc[0].x = fma(c.x, c.x, fma(c.y, c.y, acc[0].x));
-        uint32_t key = keys[p];
-        double2 v = make_double2(1.0, 0.0);
-        for (int k = 0; k < g.D; ++k) {
-            int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
-            v = cmul(v, bra[k * nmax + d]);
+    // OBS_U points per thread and pass, every load issued before the first
+    // use (one memory latency per pass instead of one per point)
+    constexpr int OBS_U = 4;
+    const int64_t stride = (int64_t)gridDim.x * TB;
+    for (int64_t p0 = gid(); p0 < n; p0 += stride * OBS_U) {
+        double2 c[OBS_U];
+        uint32_t key[OBS_U];
+#pragma unroll
+        for (int u = 0; u < OBS_U; ++u) {
+            const int64_t p = p0 + u * stride;
+            c[u] = p < n ? psi[p] : make_double2(0.0, 0.0);
+            key[u] = p < n ? keys[p] : 0u;
         }
-        cdot_acc(acc[1], v, c);
-        if (above_eps(c, eps2)) acc[2].x += 1.0;
+        double2 v[OBS_U];
+#pragma unroll
+        for (int u = 0; u < OBS_U; ++u) v[u] = make_double2(1.0, 0.0);
+        for (int k = 0; k < g.D; ++k) {
+#pragma unroll
+            for (int u = 0; u < OBS_U; ++u) {
+                const int d = (int)((key[u] / g.stride[k]) % (uint32_t)g.n[k]);
+                v[u] = cmul(v[u], sbra[k * nmax + d]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < OBS_U; ++u) {
+            if (p0 + u * stride >= n) continue;
+            acc[0].x = fma(c[u].x, c[u].x, fma(c[u].y, c[u].y, acc[0].x));
+            cdot_acc(acc[1], v[u], c[u]);
+            if (above_eps(c[u], eps2)) acc[2].x += 1.0;
+        }
     }
     block_reduce_store<3>(acc, partial);
 }
