@@ -932,14 +932,14 @@ void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
             return;
         }
         if (c->hpsi_variant == 2 || c->hpsi_variant == 4) {
-            // FP64: point-parallel last dimension and lane-per-fiber passes while
-            // fibers are short; FP32: matrix cores in every pass
+            // point-parallel last dimension and lane-per-fiber passes while
+            // fibers are short (gather-bound, no dense tile forms); fibers
+            // averaging more than 16 points form dense tiles: matrix cores
             const int64_t n = c->nact;
+            auto longf = [&](int k) { return c->nf[k] > 0 && n > 16 * c->nf[k]; };
             if (c->precision == PPQ_FP64) {
                 const double2 *x = (const double2 *)xv;
                 double2 *y = (double2 *)yv;
-                // fibers averaging more than 16 points form dense tiles: matrix cores
-                auto longf = [&](int k) { return c->nf[k] > 0 && n > 16 * c->nf[k]; };
                 if (longf(D - 1))
                     hpsi_mfma_f64(pass_of(c, D - 1), c->T64p[D - 1], x, c->V64, y, true, skip_if, skip_j, s);
                 else
@@ -951,12 +951,18 @@ void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
                     else hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
                 }
             } else {
-                // complex FP32 on the matrix cores, every dimension
                 const float2 *x = (const float2 *)xv;
                 float2 *y = (float2 *)yv;
-                hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
-                for (int k = D - 2; k >= 0; --k)
-                    hpsi_mfma_f32(pass_of(c, k), c->T32p[k], x, nullptr, y, false, skip_if, skip_j, s);
+                if (longf(D - 1))
+                    hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
+                else
+                    hpsi_pt_f32(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T32[D - 1], x, c->V32, y, true,
+                                skip_if, skip_j, s);
+                for (int k = D - 2; k >= 0; --k) {
+                    if (longf(k)) hpsi_mfma_f32(pass_of(c, k), c->T32p[k], x, nullptr, y, false, skip_if, skip_j, s);
+                    else if (c->nb[k] <= 32) hpsi_acc_f32(pass_of(c, k), c->T32[k], x, y, skip_if, skip_j, s);
+                    else hpsi_real_f32(pass_of(c, k), c->T32[k], x, nullptr, y, false, skip_if, skip_j, s);
+                }
             }
             return;
         }
