@@ -758,3 +758,53 @@ def test_grid_near_key_limit(torch):
     for col in (1, 2, 3, 4, 6):
         assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
     assert np.array_equal(g.state()[0], o.state()[0])
+
+
+# ---------------------------------------------------------------------------
+# argument and state errors: each is refused with its code and leaves the
+# context's state as it was (host-side validation, no kernel sees the input)
+# ---------------------------------------------------------------------------
+def test_errors_leave_state_unchanged(torch):
+    from paper_1606_04004_amd import PPQError
+    from paper_1606_04004_amd._ppq import STATUS
+    code_of = {v: k for k, v in STATUS.items()}
+    E_ARG, E_STATE, E_NUMERIC = code_of["PPQ_E_ARG"], code_of["PPQ_E_STATE"], code_of["PPQ_E_NUMERIC"]
+    cd = card("small_3d")
+    g = make(cd, torch)
+    say("errors: no state yet")
+    for fn in (g.expect_q, g.step, lambda: g.prune(eps=1e-3), lambda: g.observables()):
+        with pytest.raises(PPQError) as e:
+            fn()
+        assert e.value.code == E_STATE
+    g.init_state()
+    k0, c0 = g.state()
+    total = int(np.prod(cd["n"]))
+    bad = [
+        ("unsorted keys", lambda: g.set_state(k0[::-1].copy(), c0[::-1].copy()), E_ARG),
+        ("key beyond the grid", lambda: g.set_state(np.array([0, total], np.uint64), np.ones(2, complex)),
+         E_ARG),
+        ("non-finite coefficient", lambda: g.set_state(k0, np.where(np.arange(k0.size) == 3, np.nan, c0)),
+         E_NUMERIC),
+        ("Krylov order 0", lambda: g.step(m=0), E_ARG),
+        ("Krylov order 17", lambda: g.step(m=17), E_ARG),
+        ("non-finite dt", lambda: g.step(dt=float("inf")), E_ARG),
+        ("negative threshold", lambda: g.prune(eps=-1.0), E_ARG),
+        ("negative relative exclusion", lambda: g.set_relative_exclusion(-0.1), E_ARG),
+        ("NaN relative exclusion", lambda: g.set_relative_exclusion(float("nan")), E_ARG),
+        ("zero reference width", lambda: g.set_reference(width=[0.0, 1.0, 1.0]), E_ARG),
+        ("capacity beyond the grid", lambda: g.reserve(total + 1), E_ARG),
+    ]
+    for what, fn, code in bad:
+        say(f"errors: {what}")
+        with pytest.raises(PPQError) as e:
+            fn()
+        assert e.value.code == code, what
+        k1, c1 = g.state()
+        assert np.array_equal(k1, k0) and np.array_equal(c1, c0), what
+    # the context still works, and matches a fresh one
+    o = Oracle(cd)
+    o.init_state()
+    tr, _ = o.propagate(nsteps=5)
+    tg = g.propagate(nsteps=5)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    assert np.max(np.abs(tg[:, 1] - tr[:, 1])) < 1e-10
