@@ -425,11 +425,14 @@ std::vector<double> factor_values(const ppq_ctx *c, const Factor &f)
     return v;
 }
 
+// Copies a host table to a new device buffer.  Waits for the copy: the
+// callers' host vectors go out of scope on return (set-up paths only).
 template <class T>
 T *upload(const std::vector<T> &h, hipStream_t s)
 {
     T *d = dalloc<T>((int64_t)h.size());
     ck(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+    ck(hipStreamSynchronize(s), "upload");
     return d;
 }
 
