@@ -33,9 +33,10 @@
  *   - A context is used by one host thread at a time.
  *
  * Environment (read at ppq_create; for measurement and comparison only)
- *   PPQ_HPSI=2  (default) per-dimension fiber passes: matrix cores for the
- *               FP32 form, for long fibers (mean length > 16) and for complex
- *               lattice factors; vector FMA for short FP64 fibers.
+ *   PPQ_HPSI=2  (default) per-dimension fiber passes: matrix cores for long
+ *               fibers (mean length > 16), for complex lattice factors and
+ *               for the FP32 last-dimension pass; vector FMA for the other
+ *               short-fiber passes.
  *   PPQ_HPSI=3  vector FMA in every pass (comparison).
  *   PPQ_HPSI=1  point-parallel in every pass; PPQ_HPSI=0 lane per fiber in
  *               every pass (earlier layouts, for comparison).
