@@ -191,6 +191,9 @@ struct ppq_ctx {
 
     // measurement
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev_nf = nullptr;    // fiber counts of the last table build copied to h_small
+    bool nf_pending = false;       // nf[] not yet read from h_small (see ensure_nf)
+    int64_t nf_n = 0;              // set size of that build
     // opt-in phase timing: events recorded at phase boundaries
     bool timing = false;
     std::vector<hipEvent_t> tev;
@@ -693,6 +696,8 @@ void build_operator(ppq_ctx *c)
     c->v_partial = false;
 }
 
+void ensure_nf(ppq_ctx *c);
+
 // ---- derived tables of the current set --------------------------------------
 // Row-major fiber tables of dimension k (k < D - 1): pi_k, off_k, mask_k, info_k.
 void build_row_major(ppq_ctx *c, int k)
@@ -747,8 +752,8 @@ constexpr int64_t BATCH_BYTES_MAX = 8ll << 30;
 int64_t batched_bytes(const ppq_ctx *c)
 {
     const int64_t nd = c->g.D - 1;
-    if (nd < 1 || nd * c->cap >= (1ll << 32)) return 0;
-    const int64_t words = nd * c->nwords + 2;
+    if (nd < 1 || (nd + 1) * c->cap >= (1ll << 32)) return 0;
+    const int64_t words = (nd + 1) * c->nwords + 2;
     return words * 12 + nd * c->cap * 16 + scan_tmp_words(std::max(nd * c->cap, words)) * 4;
 }
 
@@ -757,7 +762,7 @@ bool ensure_batched(ppq_ctx *c)
     const int64_t bytes = batched_bytes(c);
     if (bytes == 0 || bytes > BATCH_BYTES_MAX) return false;
     if (c->bat_cap == c->cap) return true;
-    const int64_t nd = c->g.D - 1, words = nd * c->nwords + 2;
+    const int64_t nd = c->g.D - 1, words = (nd + 1) * c->nwords + 2;
     dfree(c->bmB);
     dfree(c->pfxB);
     dfree(c->flagsB);
@@ -828,11 +833,16 @@ void build_derived(ppq_ctx *c)
         c->v_valid = true;
         c->v_partial = false;
     }
+    // The fiber counts size the H*psi launches only: the host reads them when
+    // the first product is issued (ensure_nf), so the work queued in between
+    // (observables, the next step's normalisation) hides the round trip.
     ck(hipMemcpyAsync(c->h_small, c->small, sizeof(uint32_t) * (2 * MAXD + 4), hipMemcpyDeviceToHost, s), "nf");
-    ck(hipStreamSynchronize(s), "fibers");
-    for (int k = 0; k < D; ++k) c->nf[k] = n > 0 ? c->h_small[k] : 0;
+    ck(hipEventRecord(c->ev_nf, s), "nf");
+    c->nf_pending = true;
+    c->nf_n = n;
     c->block_mode = false;
     if (try_block) {
+        ensure_nf(c);
         const uint32_t *cnt = c->h_small + 2 * MAXD;
         for (int i = 0; i < 2; ++i) {
             c->nch[i] = (uint32_t)((n + BLOCK_WINDOW - 1) / BLOCK_WINDOW);
@@ -894,6 +904,7 @@ FiberPass pass_of(const ppq_ctx *c, int k)
 // y = P H P x on the current set (device vectors of the context precision)
 void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
 {
+    ensure_nf(c);
     const int D = c->g.D;
     hipStream_t s = c->stream;
     if (c->nact == 0) return;
@@ -1087,8 +1098,15 @@ void apply_internal(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
     ck(hipGetLastError(), "H*psi launch");
 }
 
-// Lanczos/Arnoldi basis of `src` (FP64 master vector on the current set) in
-// Vb with the small matrix and norm in ks; m H-applications, CGS2.
+// Host copy of the fiber counts of the last table build (waits for its copy).
+void ensure_nf(ppq_ctx *c)
+{
+    if (!c->nf_pending) return;
+    ck(hipEventSynchronize(c->ev_nf), "fibers");
+    for (int k = 0; k < c->g.D; ++k) c->nf[k] = c->nf_n > 0 ? c->h_small[k] : 0;
+    c->nf_pending = false;
+}
+
 // ---- opt-in phase timing ------------------------------------------------------
 constexpr size_t TIMING_EVENTS = 4096;
 constexpr int PHASE_NONE = -1;
@@ -1130,6 +1148,8 @@ void mark(ppq_ctx *c, int phase)
     ++c->tcount;
 }
 
+// Lanczos/Arnoldi basis of `src` (FP64 master vector on the current set) in
+// Vb with the small matrix and norm in ks; m H-applications, CGS2.
 template <class C>
 void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
 {
@@ -1576,6 +1596,7 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
         c->count = dalloc<unsigned long long>(2);
         ck(hipHostMalloc((void **)&c->h_small, sizeof(uint32_t) * 4 * MAXD, hipHostMallocDefault), "pinned");
         ck(hipHostMalloc((void **)&c->h_count, sizeof(unsigned long long) * 2, hipHostMallocDefault), "pinned");
+        ck(hipEventCreateWithFlags(&c->ev_nf, hipEventDisableTiming), "event");
         ck(hipEventCreate(&c->ev0), "event");
         ck(hipEventCreate(&c->ev1), "event");
     } catch (const HipError &e) {
@@ -1625,6 +1646,7 @@ void ppq_destroy(ppq_ctx *c)
     if (c->h_small) (void)hipHostFree(c->h_small);
     if (c->h_count) (void)hipHostFree(c->h_count);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev_nf) (void)hipEventDestroy(c->ev_nf);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -2242,6 +2264,7 @@ int ppq_fiber_counts(ppq_ctx *c, int64_t *nf)
     if (!nf) return fail(c, PPQ_E_ARG, "nf is NULL");
     PPQ_TRY(c, {
         build_derived(c);
+        ensure_nf(c);
         for (int k = 0; k < c->g.D; ++k) nf[k] = c->nf[k];
     })
     return PPQ_OK;

@@ -102,7 +102,8 @@ struct TabPtrs {
     uint32_t *off[MAXD];
     uint64_t *mask[MAXD];
 };
-// bm: nd*nwords + 2 words; prefix: nd*nwords; flags, fidx, tmpmask: nd*n entries;
+// bm, prefix: (nd+1)*nwords + 2 words (nd rotated segments, then the row-major
+// one); flags, fidx, tmpmask: nd*n entries;
 // counters: 2 + nd entries of scratch; nf[k] receives dimension k's fiber count.
 void fiber_tables_all(const uint32_t *keys, int64_t n, const RotAll &r, uint64_t *bm, uint32_t *prefix,
                       const TabPtrs &t, uint32_t *flags, uint32_t *fidx, uint64_t *tmpmask, uint32_t *scan_tmp,

@@ -456,6 +456,101 @@ __global__ void k_rot_set_all(const uint32_t *keys, int64_t n, RotAll r, uint64_
         if (valid) rk = rotate_key(key, r.sk[k], r.nk[k], &d);
         set_bit_wave(bm + (int64_t)k * r.nwords, rk, valid);
     }
+    // segment nd: the row-major bitmap of the set itself (point positions)
+    set_bit_wave(bm + (int64_t)r.nd * r.nwords, key, valid);
+}
+
+// The r-th (0-based) set bit of v (r < popcount(v)): six halving steps.
+__device__ inline int select_bit(uint64_t v, int r)
+{
+    int pos = 0;
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+        const int c = __popcll(v & ((1ull << sh) - 1ull));
+        if (r >= c) {
+            r -= c;
+            v >>= sh;
+            pos += sh;
+        }
+    }
+    return pos;
+}
+
+// Rank order gather: the rotated bitmaps are walked word by word, so the
+// points of dimension k come out in rank order q and every table write is
+// contiguous.  A wavefront takes 64 consecutive words of the concatenated
+// rotated segments; their set bits are dealt out to the lanes 64 at a time
+// (a dense word's bits spread over the wavefront instead of one lane).  For
+// the bit of rotated key rk: q from the segment's prefix, the point's
+// position p from the row-major segment (rank of the un-rotated key), the
+// fiber start and mask from the n_k-bit window holding rk.
+__global__ __launch_bounds__(TB) void k_rank_gather(int64_t n, RotAll r, const uint64_t *bm, const uint32_t *prefix,
+                                                    TabPtrs t, uint32_t *flags, uint64_t *tmpmask)
+{
+    __shared__ uint64_t s_word[TB];
+    __shared__ uint32_t s_off[TB];
+    __shared__ uint32_t s_q0[TB];
+    __shared__ uint32_t s_w[TB];
+    const int lane = threadIdx.x & 63, wbase = threadIdx.x & ~63;
+    const int64_t nw = (int64_t)r.nd * r.nwords;
+    const int64_t w = (int64_t)blockIdx.x * TB + threadIdx.x;
+    uint64_t word = 0;
+    uint32_t q0 = 0;
+    if (w < nw) {
+        word = bm[w];
+        const int k = (int)(w / r.nwords);
+        q0 = prefix[w] - (uint32_t)((int64_t)k * n);
+    }
+    const uint32_t cnt = (uint32_t)__popcll(word);
+    // exclusive prefix of the counts over the wavefront
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    s_word[threadIdx.x] = word;
+    s_off[threadIdx.x] = incl - cnt;
+    s_q0[threadIdx.x] = q0;
+    s_w[threadIdx.x] = (uint32_t)(w < nw ? w % r.nwords : 0);
+    __syncthreads();
+    const uint64_t *rowm = bm + nw;            // row-major segment
+    const uint32_t *rowp = prefix + nw;
+    const uint32_t rbase = (uint32_t)((int64_t)r.nd * n);
+    for (uint32_t b0 = 0; b0 < total; b0 += 64) {
+        const uint32_t b = b0 + lane;
+        if (b >= total) break;
+        // source lane: the last lane whose offset is <= b (offsets ascend)
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[wbase + mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        const int src = wbase + lo;
+        const int rr = (int)(b - s_off[src]);
+        const uint64_t sw = s_word[src];
+        const int pos = select_bit(sw, rr);
+        const int64_t wg = (int64_t)blockIdx.x * TB + src;  // global word index
+        const int k = (int)(wg / r.nwords);
+        const uint32_t rk = s_w[src] * 64u + (uint32_t)pos;
+        const uint32_t q = s_q0[src] + (uint32_t)rr;
+        // un-rotate: rk = (hi * sk + lo) * nk + d  ->  key = (hi * nk + d) * sk + lo
+        const uint32_t nk = r.nk[k], sk = r.sk[k];
+        const uint32_t d = rk % nk, tq = rk / nk;
+        const uint32_t khi = tq / sk, klo = tq - khi * sk;
+        const uint32_t key = (khi * nk + d) * sk + klo;
+        const uint32_t p = rowp[key >> 6] - rbase +
+                           (uint32_t)__popcll(rowm[key >> 6] & ((1ull << (key & 63)) - 1ull));
+        t.pi[k][q] = p;
+        const uint64_t *seg = bm + (int64_t)k * r.nwords;
+        const uint64_t m = extract_bits(seg, rk - d, (int)nk);
+        const bool start = (m & ((1ull << d) - 1ull)) == 0;
+        const int64_t i = (int64_t)k * n + q;
+        flags[i] = start ? 1u : 0u;
+        if (start) tmpmask[i] = m;
+    }
 }
 
 __global__ void k_rot_rank_all(const uint32_t *keys, int64_t n, RotAll r, const uint64_t *bm, const uint32_t *prefix,
@@ -1566,12 +1661,13 @@ void fiber_tables_all(const uint32_t *keys, int64_t n, const RotAll &r, uint64_t
                       uint32_t *counters, uint32_t *nf, hipStream_t s)
 {
     if (n <= 0 || r.nd <= 0) return;
-    const int64_t words = (int64_t)r.nd * r.nwords;
+    const int64_t words = (int64_t)(r.nd + 1) * r.nwords;  // nd rotated segments + the row-major one
     const int64_t m = (int64_t)r.nd * n;
     fill_u64(bm, words + 2, 0ull, s);
     hipLaunchKernelGGL(k_rot_set_all, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, r, bm);
     scan_popcount(bm, words, prefix, &counters[0], scan_tmp, s);
-    hipLaunchKernelGGL(k_rot_rank_all, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, r, bm, prefix, t, flags, tmpmask);
+    hipLaunchKernelGGL(k_rank_gather, dim3(nblocks((int64_t)r.nd * r.nwords)), dim3(TB), 0, s, n, r, bm, prefix, t,
+                       flags, tmpmask);
     scan_u32(flags, m, fidx, &counters[1], scan_tmp, s);
     hipLaunchKernelGGL(k_seg_counts, dim3(1), dim3(64), 0, s, fidx, n, r.nd, &counters[1], t, &counters[2], nf);
     hipLaunchKernelGGL(k_fib_fill_all, dim3(nblocks(m)), dim3(TB), 0, s, flags, fidx, tmpmask, n, r.nd, &counters[2],
