@@ -441,11 +441,12 @@ __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_
 }
 
 // ---- fiber tables of every non-last dimension in one set of launches ----------
-// The D-1 rotated bitmaps (digit k moved last, k < D-1) are concatenated, each
-// nwords long.  Every bitmap holds exactly n bits (rotation permutes the keys),
-// so one exclusive prefix over the concatenation gives bitmap k's ranks offset
-// by k n, and one scan over the concatenated fiber-start flags gives dimension
-// k's fiber numbers offset by the count of the earlier dimensions.
+// The D-1 rotated bitmaps (digit k moved last, k < D-1) and the row-major
+// bitmap of the set are concatenated, each nwords long.  Every bitmap holds
+// exactly n bits (rotation permutes the keys), so one exclusive prefix over the
+// concatenation gives bitmap k's ranks offset by k n, and one scan over the
+// concatenated fiber-start flags gives dimension k's fiber numbers offset by
+// the count of the earlier dimensions.
 __global__ void k_rot_set_all(const uint32_t *keys, int64_t n, RotAll r, uint64_t *bm)
 {
     int64_t p = gid();
@@ -546,28 +547,6 @@ __global__ __launch_bounds__(TB) void k_rank_gather(int64_t n, RotAll r, const u
         t.pi[k][q] = p;
         const uint64_t *seg = bm + (int64_t)k * r.nwords;
         const uint64_t m = extract_bits(seg, rk - d, (int)nk);
-        const bool start = (m & ((1ull << d) - 1ull)) == 0;
-        const int64_t i = (int64_t)k * n + q;
-        flags[i] = start ? 1u : 0u;
-        if (start) tmpmask[i] = m;
-    }
-}
-
-__global__ void k_rot_rank_all(const uint32_t *keys, int64_t n, RotAll r, const uint64_t *bm, const uint32_t *prefix,
-                               TabPtrs t, uint32_t *flags, uint64_t *tmpmask)
-{
-    int64_t p = gid();
-    if (p >= n) return;
-    const uint32_t key = keys[p];
-    for (int k = 0; k < r.nd; ++k) {
-        const uint64_t *b = bm + (int64_t)k * r.nwords;
-        uint32_t d;
-        const uint32_t rk = rotate_key(key, r.sk[k], r.nk[k], &d);
-        const uint64_t word = b[rk >> 6];
-        const uint32_t q = prefix[(int64_t)k * r.nwords + (rk >> 6)] - (uint32_t)((int64_t)k * n) +
-                           (uint32_t)__popcll(word & ((1ull << (rk & 63)) - 1ull));
-        t.pi[k][q] = (uint32_t)p;
-        const uint64_t m = extract_bits(b, rk - d, (int)r.nk[k]);
         const bool start = (m & ((1ull << d) - 1ull)) == 0;
         const int64_t i = (int64_t)k * n + q;
         flags[i] = start ? 1u : 0u;
