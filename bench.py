@@ -246,10 +246,14 @@ def main():
         value32, ms_step32, _ = timed_steps(g32, args.steps, args.warmup)
         bpp32 = bytes_per_point(D, 1)
         obs32 = g32.observables()
+        g32.enable_timings(True)
+        g32.propagate(nsteps=nph)
+        phases32 = {k: v / nph for k, v in g32.timings().items()}
+        g32.enable_timings(False)
         err = {k: abs(obs32[k] - obs64[k]) for k in ("norm2", "acf_re", "acf_im")}
         err["energy_rel"] = abs(obs32["energy"] - obs64["energy"]) / abs(obs64["energy"])
         err["n_active_rel"] = abs(obs32["n_active"] - obs64["n_active"]) / obs64["n_active"]
-        out["fp32"] = {"value": value32, "ms_per_step": ms_step32,
+        out["fp32"] = {"value": value32, "ms_per_step": ms_step32, "phase_ms_per_step": phases32,
                        "error_vs_fp64_after_steps": err,
                        "hpsi_updates_per_s": n_snap / (ms32 * 1e-3), "hpsi_ms": ms32,
                        "roofline_frac": bpp32 * n_snap / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
