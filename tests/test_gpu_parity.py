@@ -408,6 +408,52 @@ def test_phase_timings(torch):
     assert ph2["hpsi"] > 0 and ph2["krylov"] > 0 and ph2["adapt"] > 0 and ph2["obs"] == 0.0
 
 
+def test_fp32_form_expect_q_and_relative_exclusion(torch):
+    """The FP32 form keeps the FP64 master state: its position expectations
+    match the oracle's on the same state, and its adaption (with a relative
+    exclusion threshold) is bit-exact."""
+    cd = card("small_4d")
+    o = Oracle(cd)
+    g = make(cd, torch, precision=1)
+    g.init_state()
+    g.propagate(nsteps=5)
+    kg, cg = g.state()
+    o.set_state(kg, cg)
+    assert np.max(np.abs(g.expect_q() - o.expect_q())) < 1e-13 * _box_scale(cd)
+    eps = 1e-3
+    keys = random_active_set(o.n, 0.35, 7)
+    c = random_complex(keys.size, 7) * np.exp(np.random.default_rng(7).uniform(-12, 0, keys.size))
+    o.set_state(keys, c)
+    o.prune(eps=eps)
+    dropped = np.setdiff1d(keys, o.state()[0]).size
+    for r in (0.0, (dropped + 0.5) / keys.size):
+        say(f"fp32 form adaption, relative exclusion {r:.5f}")
+        o.set_state(keys, c)
+        nab = o.prune(eps=eps, rel_excl=r)
+        g.set_state(keys, c)
+        g.set_relative_exclusion(r)
+        assert g.prune(eps=eps)[1] == nab
+        assert np.array_equal(g.state()[0], o.state()[0])
+        assert np.array_equal(g.state()[1], o.state()[1])
+
+
+def test_lattice_reference_and_expect_q(torch):
+    """Lattice card: C(t) from a state set on the host, with the reference
+    packet given separately, equals the initial-packet run; position
+    expectations are NaN on lattice dimensions."""
+    cd = lattice_card(eps=1e-4)
+    a = make(cd, torch)
+    a.init_state()
+    keys, c = a.state()
+    b = make(cd, torch)
+    b.set_state(keys, c)
+    b.set_reference()
+    ta = a.propagate(nsteps=5, dt=0.05)
+    tb = b.propagate(nsteps=5, dt=0.05)
+    assert np.array_equal(ta, tb)
+    assert np.all(np.isnan(b.expect_q()))
+
+
 def test_shadow_steps_morse4d(torch):
     """Each step of the GPU map from the oracle's state equals the oracle's step:
     identical adapted set, coefficients within 1e-12 (relative to the largest)."""
