@@ -135,6 +135,12 @@ int ppq_set_lattice(ppq_ctx *ctx, int k, int n_s, int n_l);
 int ppq_add_potential_term(ppq_ctx *ctx, double coef, int nfac, const int32_t *dims, const int32_t *kinds,
                            const double *params, const double *tables);
 
+/* Removes every potential term (the kinetic factors stay), so that a new
+   sum-of-products potential can be added term by term (Sec. II.A, II.E); the
+   state and its active set are kept.  The derivative terms of the adjoint
+   are not touched. */
+int ppq_clear_potential(ppq_ctx *ctx);
+
 /* Capacity of the active set (number of functions).  Grows automatically when
    adaption needs more; reserving ahead avoids reallocation inside a run. */
 int ppq_reserve(ppq_ctx *ctx, int64_t max_active);

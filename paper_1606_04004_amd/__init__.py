@@ -90,6 +90,10 @@ class Propagator:
                 tables += list(f["values"])
         return dims, kinds, params, tables
 
+    def clear_potential(self):
+        """Removes every potential term (add_term adds new ones)."""
+        self._call("ppq_clear_potential")
+
     def add_term(self, coef, factors):
         dims, kinds, params, tables = self._factors(factors)
         d, pd = _i32(dims or [0])

@@ -1805,6 +1805,18 @@ int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dim
     return PPQ_OK;
 }
 
+int ppq_clear_potential(ppq_ctx *c)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    c->terms.clear();
+    c->op_dirty = true;
+    c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
+    return PPQ_OK;
+}
+
 int ppq_reserve(ppq_ctx *c, int64_t max_active)
 {
     PPQ_GUARD(c)
