@@ -175,11 +175,26 @@ int ppq_active_count(const ppq_ctx *ctx, int64_t *count);
    are written when cap >= |A| (else PPQ_E_ARG with *count set). */
 int ppq_get_state(ppq_ctx *ctx, int64_t cap, int64_t *count, uint64_t *keys, double *coeff);
 
+/* Device forms of ppq_set_state / ppq_get_state: keys (uint64) and
+   coefficients (interleaved complex FP64) are device pointers, so a state
+   moves between the library and device tensors without crossing PCIe.
+   ppq_set_state_device checks the keys (strictly ascending, in range) and the
+   coefficients (finite) on the device while copying them into a spare buffer
+   and synchronises; on a violation it returns PPQ_E_ARG (keys) or
+   PPQ_E_NUMERIC (coefficients) and the state is unchanged.
+   ppq_get_state_device writes *count = |A| on the host and, when cap >= |A|,
+   the keys and coefficients in stream order on the context stream (no
+   synchronisation; the buffers must stay valid until that work has run).
+   Pointers that are not device (or managed) memory give PPQ_E_ARG. */
+int ppq_set_state_device(ppq_ctx *ctx, int64_t count, const uint64_t *keys, const double *coeff);
+int ppq_get_state_device(ppq_ctx *ctx, int64_t cap, int64_t *count, uint64_t *keys, double *coeff);
+
 /* y = P_A H P_A x on the current active set (the pruned product of Sec. II.B.2
    computed fiber by fiber as in the appendix).  x, y: device arrays of |A|
    complex values in key order -- interleaved FP64 for PPQ_FP64 contexts,
    interleaved FP32 for PPQ_FP32 contexts; x and y must not overlap.
-   Enqueued on the context stream; no synchronisation. */
+   Enqueued on the context stream; no synchronisation.  PPQ_E_ARG when x or y
+   is not device (or managed) memory. */
 int ppq_apply_h(ppq_ctx *ctx, const void *x, void *y);
 
 /* One short-iterative Lanczos (Arnoldi if any lattice dimension) step of

@@ -180,6 +180,28 @@ class Propagator:
         w, pw = _d(ps["width"] if width is None else width)
         self._call("ppq_set_reference", pc, pm, pw)
 
+    def set_state_device(self, keys, coeff):
+        """State from device tensors: keys (int64/uint64 view, ascending) and
+        coefficients (complex128), both on the context's device."""
+        if keys.numel() != coeff.numel() or keys.element_size() != 8 or coeff.element_size() != 16:
+            raise ValueError("keys: 8-byte integers, coeff: complex128, of one length")
+        if not (keys.is_contiguous() and coeff.is_contiguous()):
+            raise ValueError("keys and coeff must be contiguous")
+        n = int(keys.numel())
+        self._call("ppq_set_state_device", n, ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(coeff.data_ptr()))
+
+    def state_device(self, keys, coeff):
+        """Writes the state into device tensors (int64 keys, complex128
+        coefficients, each at least |A| long, stream-ordered); returns |A|."""
+        if keys.element_size() != 8 or coeff.element_size() != 16:
+            raise ValueError("keys: 8-byte integers, coeff: complex128")
+        if not (keys.is_contiguous() and coeff.is_contiguous()):
+            raise ValueError("keys and coeff must be contiguous")
+        cnt = ctypes.c_int64(0)
+        self._call("ppq_get_state_device", int(min(keys.numel(), coeff.numel())), ctypes.byref(cnt),
+                   ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(coeff.data_ptr()))
+        return cnt.value
+
     def active_count(self):
         n = ctypes.c_int64(0)
         self._call("ppq_active_count", ctypes.byref(n))

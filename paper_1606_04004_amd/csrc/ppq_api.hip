@@ -1940,11 +1940,84 @@ int ppq_get_state(ppq_ctx *c, int64_t cap, int64_t *count, uint64_t *keys, doubl
     return PPQ_OK;
 }
 
+// True for memory the device can address as device memory (a hipMalloc'ed or
+// managed allocation); a plain host pointer would fault a kernel.
+bool device_pointer(const void *p)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+int ppq_set_state_device(ppq_ctx *c, int64_t count, const uint64_t *keys, const double *coeff)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (count < 0 || count > (int64_t)c->g.total || (count > 0 && (!keys || !coeff)))
+        return fail(c, PPQ_E_ARG, "bad state arguments");
+    if (count > 0 && (!device_pointer(keys) || !device_pointer(coeff)))
+        return fail(c, PPQ_E_ARG, "keys and coefficients must be device memory");
+    int status = PPQ_OK;
+    PPQ_TRY(c, {
+        ensure_capacity(c, std::max<int64_t>(count, 1));  // keeps the current state
+        const int nxt = 1 - c->cur;
+        take_state(keys, reinterpret_cast<const double2 *>(coeff), count, c->g.total, c->keys[nxt], c->psi[nxt],
+                   c->flags, c->count, c->stream);
+        unsigned long long bad[2] = {0, 0};
+        if (count > 0) {
+            ck(hipMemcpyAsync(c->h_count, c->count, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                              c->stream),
+               "state check");
+            ck(hipStreamSynchronize(c->stream), "state check");
+            bad[0] = c->h_count[0];
+            bad[1] = c->h_count[1];
+        }
+        if (bad[0]) {
+            status = fail(c, PPQ_E_ARG, "keys must be strictly ascending and in range");
+        } else if (bad[1]) {
+            status = fail(c, PPQ_E_NUMERIC, "non-finite coefficient");
+        } else {
+            // the checked copy becomes the state (the previous one is dropped)
+            c->cur = nxt;
+            c->nact = count;
+            c->has_state = true;
+            c->derived_valid = false;
+            c->v_valid = false;
+            c->v_partial = false;
+        }
+    })
+    return status;
+}
+
+int ppq_get_state_device(ppq_ctx *c, int64_t cap, int64_t *count, uint64_t *keys, double *coeff)
+{
+    PPQ_GUARD(c)
+    if (!count) return fail(c, PPQ_E_ARG, "count is NULL");
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    *count = c->nact;
+    if (cap < c->nact) return fail(c, PPQ_E_ARG, "buffer too small");
+    if (c->nact && (!keys || !coeff)) return fail(c, PPQ_E_ARG, "null buffers");
+    if (c->nact && (!device_pointer(keys) || !device_pointer(coeff)))
+        return fail(c, PPQ_E_ARG, "keys and coefficients must be device memory");
+    PPQ_TRY(c, {
+        give_keys(c->keys[c->cur], c->nact, keys, c->stream);
+        if (c->nact)
+            ck(hipMemcpyAsync(coeff, c->psi[c->cur], c->nact * sizeof(double2), hipMemcpyDeviceToDevice, c->stream),
+               "get psi");
+        ck(hipGetLastError(), "get state");
+    })
+    return PPQ_OK;
+}
+
 int ppq_apply_h(ppq_ctx *c, const void *x, void *y)
 {
     PPQ_GUARD(c)
     if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
     if (c->nact && (!x || !y || x == y)) return fail(c, PPQ_E_ARG, "x and y must be distinct device pointers");
+    if (c->nact && (!device_pointer(x) || !device_pointer(y))) return fail(c, PPQ_E_ARG, "x and y must be device memory");
     PPQ_TRY(c, {
         build_derived(c);
         apply_internal(c, x, y, nullptr, 0);

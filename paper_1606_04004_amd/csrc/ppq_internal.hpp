@@ -252,6 +252,12 @@ void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const Grid
 void obs_final(const double2 *partial, int nblocks, double *rec, hipStream_t s);
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s);
 void set_record(double *rec, double t, double nact, double krylov, hipStream_t s);
+// device state transfer: caller keys/coefficients into the context's buffers,
+// with violation counts bad[0] (keys) and bad[1] (non-finite values);
+// block_counts holds 2 * nblocks(n) entries
+void take_state(const uint64_t *keys, const double2 *coeff, int64_t n, uint64_t total, uint32_t *k32, double2 *psi,
+                unsigned *block_counts, unsigned long long *bad, hipStream_t s);
+void give_keys(const uint32_t *k32, int64_t n, uint64_t *keys, hipStream_t s);
 // position expectations out[D] (device): two launches, partials in `partial`
 void expect_q(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, const double *q, int nmax,
               unsigned nan_mask, double2 *partial, double *out, hipStream_t s);

@@ -1204,6 +1204,33 @@ __global__ __launch_bounds__(TB) void k_expq_final(const double2 *partial, int n
     }
 }
 
+// ---- device-side state transfer ---------------------------------------------------
+// Checks caller keys (strictly ascending, below the grid size) and coefficients
+// (finite) while converting them: bad[0] counts key violations, bad[1]
+// non-finite coefficients (per-block counts summed by one fixed-order kernel).
+__global__ void k_take_state(const uint64_t *keys, const double2 *coeff, int64_t n, uint64_t total, uint32_t *k32,
+                             double2 *psi, unsigned *block_bad_keys, unsigned *block_bad_vals)
+{
+    int64_t p = gid();
+    bool bad_key = false, bad_val = false;
+    if (p < n) {
+        const uint64_t k = keys[p];
+        bad_key = k >= total || (p > 0 && keys[p - 1] >= k);
+        const double2 c = coeff[p];
+        bad_val = !isfinite(c.x) || !isfinite(c.y);
+        k32[p] = (uint32_t)k;
+        psi[p] = c;
+    }
+    count_block(bad_key, block_bad_keys);
+    count_block(bad_val, block_bad_vals);
+}
+
+__global__ void k_give_keys(const uint32_t *k32, int64_t n, uint64_t *keys)
+{
+    int64_t p = gid();
+    if (p < n) keys[p] = k32[p];
+}
+
 // host-known fields of one observable record
 __global__ void k_set_record(double *rec, double t, double nact, double krylov)
 {
@@ -1816,6 +1843,21 @@ void expect_q(const uint32_t *keys, const double2 *psi, int64_t n, const GridDes
 {
     hipLaunchKernelGGL(k_expq_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, keys, psi, n, g, q, nmax, partial);
     hipLaunchKernelGGL(k_expq_final, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, g.D, nan_mask, out);
+}
+void take_state(const uint64_t *keys, const double2 *coeff, int64_t n, uint64_t total, uint32_t *k32, double2 *psi,
+                unsigned *block_counts, unsigned long long *bad, hipStream_t s)
+{
+    if (n <= 0) return;
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_take_state, dim3(nb), dim3(TB), 0, s, keys, coeff, n, total, k32, psi, block_counts,
+                       block_counts + nb);
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts, (int64_t)nb, bad);
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts + nb, (int64_t)nb, bad + 1);
+}
+void give_keys(const uint32_t *k32, int64_t n, uint64_t *keys, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_give_keys, dim3(nblocks(n)), dim3(TB), 0, s, k32, n, keys);
 }
 void set_record(double *rec, double t, double nact, double krylov, hipStream_t s)
 {

@@ -882,3 +882,46 @@ def test_clear_potential(torch):
     assert np.array_equal(tg[:, 5], tr[:, 5])
     for col in (1, 2, 3, 4, 6):
         assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+
+
+def test_device_state_transfer(torch):
+    """State to and from device tensors: identical to the host path; bad keys,
+    non-finite values and host pointers are refused with the state unchanged."""
+    from paper_1606_04004_amd import PPQError
+    from paper_1606_04004_amd._ppq import STATUS
+    code_of = {v: k for k, v in STATUS.items()}
+    cd = card("small_3d")
+    total = int(np.prod(cd["n"]))
+    g = make(cd, torch)
+    g.init_state()
+    k_host, c_host = g.state()
+    n = k_host.size
+    kt = torch.zeros(n + 5, dtype=torch.int64, device="cuda")
+    ct = torch.zeros(n + 5, dtype=torch.complex128, device="cuda")
+    assert g.state_device(kt, ct) == n
+    torch.cuda.synchronize()
+    assert np.array_equal(kt[:n].cpu().numpy().astype(np.uint64), k_host)
+    assert np.array_equal(ct[:n].cpu().numpy(), c_host)
+    h = make(cd, torch)
+    h.set_state_device(kt[:n], ct[:n])
+    kh, ch = h.state()
+    assert np.array_equal(kh, k_host) and np.array_equal(ch, c_host)
+    bad_keys = kt[:n].flip(0).contiguous()
+    beyond = kt[:n].clone()
+    beyond[-1] = total
+    nan_c = ct[:n].clone()
+    nan_c[3] = complex(float("nan"), 0.0)
+    for what, args, code in (("descending keys", (bad_keys, ct[:n]), "PPQ_E_ARG"),
+                             ("key beyond the grid", (beyond, ct[:n]), "PPQ_E_ARG"),
+                             ("non-finite coefficient", (kt[:n], nan_c), "PPQ_E_NUMERIC"),
+                             ("host tensors", (kt[:n].cpu(), ct[:n].cpu()), "PPQ_E_ARG")):
+        say(f"device state: {what}")
+        with pytest.raises(PPQError) as e:
+            h.set_state_device(*args)
+        assert e.value.code == code_of[code], what
+        kh, ch = h.state()
+        assert np.array_equal(kh, k_host) and np.array_equal(ch, c_host), what
+    ta = g.propagate(nsteps=5)
+    h.set_reference()
+    tb = h.propagate(nsteps=5)
+    assert np.array_equal(ta, tb)
