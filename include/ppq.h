@@ -135,6 +135,16 @@ int ppq_set_lattice(ppq_ctx *ctx, int k, int n_s, int n_l);
 int ppq_add_potential_term(ppq_ctx *ctx, double coef, int nfac, const int32_t *dims, const int32_t *kinds,
                            const double *params, const double *tables);
 
+/* Replaces the one-dimensional operator of dimension k (by default the
+   sine-DVR kinetic energy of ppq_set_grid) by h, a real symmetric n_k x n_k
+   matrix in the dimension's DVR basis, row-major (host, copied): any 1D
+   factor of the sum-of-products operator (Sec. II.A, Eq. matvecprod_sequential),
+   e.g. the kinetic matrix of another DVR.  On a phase-space lattice
+   dimension it is transformed like the kinetic matrix.  h = NULL restores
+   the sine-DVR kinetic energy.  PPQ_E_ARG unless h is exactly symmetric;
+   PPQ_E_NUMERIC for non-finite entries. */
+int ppq_set_factor(ppq_ctx *ctx, int k, const double *h);
+
 /* Removes every potential term (the kinetic factors stay), so that a new
    sum-of-products potential can be added term by term (Sec. II.A, II.E); the
    state and its active set are kept.  The derivative terms of the adjoint

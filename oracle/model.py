@@ -86,6 +86,9 @@ class Model:
             self.q.append(qk)
             self.dx.append(dxk)
             self.T.append(sine_dvr_kinetic(self.n[k], card["lo"][k], card["hi"][k], card["mass"]))
+        # a card may replace the 1D operator of a dimension by its own matrix
+        for k, h in card.get("dim_factors", {}).items():
+            self.T[int(k)] = np.array(h, dtype=np.float64).reshape(self.n[int(k)], self.n[int(k)])
         ps = card["psi0"]
         self.g0 = [gaussian_1d(self.q[k], ps["centre"][k], ps["momentum"][k], ps["width"][k])
                    for k in range(D)]

@@ -56,6 +56,8 @@ class Propagator:
             ns, nl = card["lattice"]
             for k in range(self.D):
                 self._call("ppq_set_lattice", k, int(ns), int(nl))
+        for k, h in card.get("dim_factors", {}).items():
+            self.set_factor(int(k), h)
         for t in card["terms"]:
             self.add_term(t["coef"], t["factors"])
 
@@ -89,6 +91,15 @@ class Propagator:
                 params += [0.0, 0.0]
                 tables += list(f["values"])
         return dims, kinds, params, tables
+
+    def set_factor(self, k, h):
+        """1D operator of dimension k (real symmetric n_k x n_k); None restores
+        the sine-DVR kinetic energy."""
+        if h is None:
+            self._call("ppq_set_factor", int(k), None)
+            return
+        a, pa = _d(np.asarray(h, dtype=np.float64).reshape(-1))
+        self._call("ppq_set_factor", int(k), pa)
 
     def clear_potential(self):
         """Removes every potential term (add_term adds new ones)."""

@@ -42,6 +42,7 @@ SIGNATURES = {
     "ppq_prune": (ctypes.c_int, [_vp, ctypes.c_double, _i64p, _i64p]),
     "ppq_set_reference": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "ppq_clear_potential": (ctypes.c_int, [_vp]),
+    "ppq_set_factor": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "ppq_set_state_device": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, _vp]),
     "ppq_get_state_device": (ctypes.c_int, [_vp, ctypes.c_int64, _i64p, _vp, _vp]),
     "ppq_set_relative_exclusion": (ctypes.c_int, [_vp, ctypes.c_double]),

@@ -179,6 +179,7 @@ struct ppq_ctx {
     int tab_nmax = 0;
     double *qtab = nullptr;  // grid points [MAXD][NMAX_FIBER], then MAXD results (position expectations)
     double rel_excl = 0.0;   // relative exclusion threshold of adaption
+    std::vector<double> factor[MAXD];  // caller's 1D factor per dimension (empty: sine-DVR kinetic)
     // fiber tables of all non-last dimensions at once (see fiber_tables_all)
     uint64_t *bmB = nullptr;
     uint32_t *pfxB = nullptr, *flagsB = nullptr, *fidxB = nullptr, *scanB = nullptr, *cntB = nullptr;
@@ -461,6 +462,14 @@ std::vector<cd> similarity(const LatticeMaps &L, const std::vector<cd> &h, int n
     return matmul(matmul(L.Gadj, h, n), L.GinvAdj, n);
 }
 
+// The one-dimensional operator of dimension k in its DVR basis: the caller's
+// factor when one was set, else the sine-DVR kinetic energy.
+std::vector<double> dim_factor(const ppq_ctx *c, int k)
+{
+    if (!c->factor[k].empty()) return c->factor[k];
+    return sine_dvr_kinetic(c->g.n[k], c->lo[k], c->hi[k], c->mass);
+}
+
 void build_operator(ppq_ctx *c)
 {
     if (!c->op_dirty) return;
@@ -492,7 +501,7 @@ void build_operator(ppq_ctx *c)
     if (!c->any_lattice) {
         for (int k = 0; k < D; ++k) {
             int n = c->g.n[k], b = c->nb[k];
-            std::vector<double> T = sine_dvr_kinetic(n, c->lo[k], c->hi[k], c->mass);
+            std::vector<double> T = dim_factor(c, k);
             std::vector<double> P((size_t)b * b, 0.0);
             std::vector<float> Pf((size_t)b * b, 0.0f);
             for (int i = 0; i < n; ++i)
@@ -617,7 +626,7 @@ void build_operator(ppq_ctx *c)
         std::vector<std::vector<cd>> Hk(D);
         for (int k = 0; k < D; ++k) {
             int n = c->g.n[k];
-            std::vector<double> T = sine_dvr_kinetic(n, c->lo[k], c->hi[k], c->mass);
+            std::vector<double> T = dim_factor(c, k);
             std::vector<cd> h((size_t)n * n);
             for (size_t i = 0; i < h.size(); ++i) h[i] = T[i];
             Hk[k] = h;  // DVR-space sum, transformed at the end
@@ -1711,6 +1720,7 @@ int ppq_set_grid(ppq_ctx *c, int D, const int32_t *n, const double *lo, const do
             c->hi[k] = hi[k];
             c->nb[k] = bucket(n[k]);
             c->lattice[k] = false;
+            c->factor[k].clear();
         }
         c->mass = mass;
         c->split = D / 2;
@@ -1798,6 +1808,30 @@ int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dim
         if (nd > 2) return fail(c, PPQ_E_UNSUPPORTED, "lattice bases support terms on at most two dimensions");
     }
     c->terms.push_back(t);
+    c->op_dirty = true;
+    c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
+    return PPQ_OK;
+}
+
+int ppq_set_factor(ppq_ctx *c, int k, const double *h)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (k < 0 || k >= c->g.D) return fail(c, PPQ_E_ARG, "dimension out of range");
+    const int n = c->g.n[k];
+    if (h) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double v = h[(size_t)i * n + j];
+                if (!std::isfinite(v)) return fail(c, PPQ_E_NUMERIC, "non-finite factor entry");
+                if (v != h[(size_t)j * n + i]) return fail(c, PPQ_E_ARG, "factor must be symmetric");
+            }
+        c->factor[k].assign(h, h + (size_t)n * n);
+    } else {
+        c->factor[k].clear();
+    }
     c->op_dirty = true;
     c->derived_valid = false;
     c->v_valid = false;

@@ -925,3 +925,72 @@ def test_device_state_transfer(torch):
     h.set_reference()
     tb = h.propagate(nsteps=5)
     assert np.array_equal(ta, tb)
+
+
+def _custom_factor_card(seed):
+    from oracle.model import sine_dvr_kinetic
+    cd = card("small_3d")
+    rng = np.random.default_rng(seed)
+    fac = {}
+    for k in (0, 2):
+        n = cd["n"][k]
+        m = sine_dvr_kinetic(n, cd["lo"][k], cd["hi"][k], cd["mass"]) + 0.3 * rng.standard_normal((n, n)) / n
+        fac[k] = ((m + m.T) / 2.0).tolist()
+    cd["dim_factors"] = fac
+    return cd
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_custom_dim_factors(prec, torch):
+    """The caller's own 1D matrices on two dimensions: products against the
+    oracle (FP64 1e-13, FP32 2e-6), a 10-step trajectory (FP64), restoring
+    the sine-DVR matrix, and refusal of a non-symmetric matrix."""
+    from paper_1606_04004_amd import PPQError
+    cd = _custom_factor_card(3)
+    o = Oracle(cd)
+    g = make(cd, torch, precision=prec)
+    for fill, seed in ((1.0, 1), (0.4, 2)):
+        keys = (np.arange(int(np.prod(cd["n"])), dtype=np.uint64) if fill == 1.0
+                else random_active_set(cd["n"], fill, seed))
+        x = random_complex(keys.size, seed + 20)
+        say(f"custom factors prec {prec} |A|={keys.size}")
+        g.set_state(keys, x)
+        if prec == 0:
+            xt = torch.from_numpy(x).cuda()
+            ref = o.apply_def(keys, x)
+        else:
+            xt = torch.from_numpy(x.astype(np.complex64)).cuda()
+            ref = o.apply_def(keys, x.astype(np.complex64).astype(np.complex128))
+        yt = torch.zeros_like(xt)
+        g.apply_h(xt, yt)
+        torch.cuda.synchronize()
+        err = np.max(np.abs(yt.cpu().numpy().astype(np.complex128) - ref)) / np.max(np.abs(ref))
+        say(f"  rel err {err:.2e}")
+        assert err < (1e-13 if prec == 0 else 2e-6)
+    if prec == 0:
+        o.init_state()
+        g.init_state()
+        tr, _ = o.propagate(nsteps=10)
+        tg = g.propagate(nsteps=10)
+        assert np.array_equal(tg[:, 5], tr[:, 5])
+        for col in (1, 2, 3, 4, 6):
+            assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    # restoring the sine-DVR matrices gives the plain card's product
+    plain = card("small_3d")
+    op = Oracle(plain)
+    g.set_factor(0, None)
+    g.set_factor(2, None)
+    keys = random_active_set(plain["n"], 0.4, 9)
+    x = random_complex(keys.size, 9)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x if prec == 0 else x.astype(np.complex64)).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    ref = op.apply_def(keys, x if prec == 0 else x.astype(np.complex64).astype(np.complex128))
+    assert np.max(np.abs(yt.cpu().numpy().astype(np.complex128) - ref)) / np.max(np.abs(ref)) < (
+        1e-13 if prec == 0 else 2e-6)
+    h = np.array(cd["dim_factors"][0])
+    h[0, 1] += 1e-9
+    with pytest.raises(PPQError):
+        g.set_factor(0, h)

@@ -167,6 +167,35 @@ def test_apply_def_pruned_equals_restricted_kronecker(n, seed, fill):
         assert np.max(np.abs(y - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
 
 
+def custom_factor_card(seed, terms=True):
+    """small_3d with its own symmetric 1D matrices on dimensions 0 and 2."""
+    cd = card("small_3d")
+    if not terms:
+        cd["terms"] = []
+    rng = np.random.default_rng(seed)
+    fac = {}
+    for k in (0, 2):
+        n = cd["n"][k]
+        m = sine_dvr_kinetic(n, cd["lo"][k], cd["hi"][k], cd["mass"]) + 0.3 * rng.standard_normal((n, n)) / n
+        fac[k] = ((m + m.T) / 2.0).tolist()
+    cd["dim_factors"] = fac
+    return cd
+
+
+def test_card_dim_factors_equal_kronecker_sum():
+    """A card's own 1D matrices: with no potential, O-def on the full grid is
+    the Kronecker sum of the per-dimension matrices (dense)."""
+    cd = custom_factor_card(5, terms=False)
+    o = orc.Oracle(cd)
+    n = cd["n"]
+    hs = [np.array(cd["dim_factors"][k]) if k in cd["dim_factors"]
+          else sine_dvr_kinetic(n[k], cd["lo"][k], cd["hi"][k], cd["mass"]) for k in range(3)]
+    H = sum(kron_dim(n, k, hs[k]) for k in range(3))
+    keys = o.full_keys()
+    x = random_complex(keys.size, 6)
+    assert np.max(np.abs(o.apply_def(keys, x) - H @ x)) < 1e-12 * np.max(np.abs(H @ x))
+
+
 @pytest.mark.parametrize("n,seed", [((6, 7), 11), ((5, 4, 6), 12), ((4, 5, 3, 4), 13), ((3, 3, 3, 3, 3, 3), 14)])
 def test_apply_fib_equals_def(n, seed):
     op = RandomOp(n, seed)
