@@ -220,6 +220,15 @@ int ppq_step(ppq_ctx *ctx, double dt, int m);
    n_active / n_above (may be NULL) receive |A'| and the kept count. */
 int ppq_prune(ppq_ctx *ctx, double eps, int64_t *n_active, int64_t *n_above);
 
+/* Neighbour stencil of every later adaption and of the initial set
+   (Sec. III.A): 1 (default) adds the 2D nearest neighbours, +-1 in one
+   dimension (ball radius 1); 2 also adds every change of +-1 in two
+   dimensions at once, 2D^2 neighbours in all (ball radius sqrt(2)).  The
+   paper finds radius 1 best and uses it throughout.  Stencil 2 is built for
+   DVR dimensions only (PPQ_E_UNSUPPORTED with lattice dimensions);
+   PPQ_E_ARG for other values. */
+int ppq_set_stencil(ppq_ctx *ctx, int stencil);
+
 /* Relative exclusion threshold r >= 0 of every later adaption (ppq_prune,
    ppq_propagate, the adjoint recording), Sec. II.E: functions are excluded
    only when more than r * |A| of them would go; otherwise the new set is

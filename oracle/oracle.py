@@ -53,6 +53,7 @@ def lib():
         L.orc_state_count.argtypes = [vp]
         L.orc_state_get.argtypes = [vp, _c_u64_p, _c_double_p]
         L.orc_sil_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _c_double_p]
+        L.orc_set_stencil.argtypes = [vp, ctypes.c_int]
         L.orc_prune.restype = ctypes.c_int64
         L.orc_prune.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double]
         L.orc_init_product.restype = ctypes.c_int64
@@ -145,6 +146,8 @@ class Oracle:
             ns, nl = m.lattice
             for k in range(self.D):
                 L.orc_set_lattice(self._m, k, ns, nl)
+        if card.get("stencil", 1) != 1 and L.orc_set_stencil(self._m, int(card["stencil"])) != 0:
+            raise ValueError("stencil 2 is defined for DVR dimensions only")
         self.arnoldi = 1 if m.pvb else 0
         self._init_tabs = self._pack(m.init_tables())
         self._bra_tabs = self._pack(m.bra_tables())

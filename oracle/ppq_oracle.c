@@ -57,6 +57,7 @@ typedef struct orc_model {
     int *pk1, *pk2;             /* applied as coef * h1(k1) (h2(k2) x), k2 first */
     zd **ph1, **ph2;
     int lat_s[ORC_MAXD], lat_l[ORC_MAXD]; /* phase-space lattice shape per dim; 0 = line */
+    int stencil;                /* adaption neighbours: 1 = ball radius 1, 2 = radius sqrt(2) */
 } orc_model;
 
 orc_model *orc_new(int D, const int32_t *n)
@@ -64,6 +65,7 @@ orc_model *orc_new(int D, const int32_t *n)
     if (D < 1 || D > ORC_MAXD) return NULL;
     orc_model *m = calloc(1, sizeof(*m));
     m->D = D;
+    m->stencil = 1;
     m->nmax = 0;
     for (int k = 0; k < D; ++k) {
         m->n[k] = n[k];
@@ -682,6 +684,28 @@ static void insert_with_neighbours(const orc_model *m, keyset *set, uint64_t key
             if (l + 1 < nl) ks_insert(set, key + sk);
         }
     }
+    /* ball radius sqrt(2) (Sec. III.A): a change of +-1 in two dimensions at
+       once as well, 2D^2 neighbours in all (DVR dimensions) */
+    if (m->stencil == 2)
+        for (int k = 0; k < m->D; ++k)
+            for (int l = k + 1; l < m->D; ++l)
+                for (int a = -1; a <= 1; a += 2)
+                    for (int b = -1; b <= 1; b += 2) {
+                        int dk = digit(m, key, k) + a, dl = digit(m, key, l) + b;
+                        if (dk < 0 || dk >= m->n[k] || dl < 0 || dl >= m->n[l]) continue;
+                        ks_insert(set, key + (int64_t)a * (int64_t)m->stride[k] + (int64_t)b * (int64_t)m->stride[l]);
+                    }
+}
+
+/* Selects the adaption stencil (1: radius 1; 2: radius sqrt(2), DVR only). */
+int orc_set_stencil(orc_model *m, int stencil)
+{
+    if (stencil != 1 && stencil != 2) return -1;
+    if (stencil == 2)
+        for (int k = 0; k < m->D; ++k)
+            if (m->lat_s[k]) return -1;
+    m->stencil = stencil;
+    return 0;
 }
 
 static void set_from_keyset(keyset *set, uint64_t **out, int64_t *nout)

@@ -58,6 +58,8 @@ class Propagator:
                 self._call("ppq_set_lattice", k, int(ns), int(nl))
         for k, h in card.get("dim_factors", {}).items():
             self.set_factor(int(k), h)
+        if card.get("stencil", 1) != 1:
+            self.set_stencil(card["stencil"])
         for t in card["terms"]:
             self.add_term(t["coef"], t["factors"])
 
@@ -91,6 +93,11 @@ class Propagator:
                 params += [0.0, 0.0]
                 tables += list(f["values"])
         return dims, kinds, params, tables
+
+    def set_stencil(self, stencil):
+        """Adaption stencil: 1 (ball radius 1, 2D neighbours) or 2 (radius
+        sqrt(2), 2D^2 neighbours)."""
+        self._call("ppq_set_stencil", int(stencil))
 
     def set_factor(self, k, h):
         """1D operator of dimension k (real symmetric n_k x n_k); None restores

@@ -1759,6 +1759,7 @@ int ppq_set_lattice(ppq_ctx *c, int k, int ns, int nl)
     if (k < 0 || k >= c->g.D || ns < 1 || nl < 1 || ns * nl != c->g.n[k])
         return fail(c, PPQ_E_ARG, "lattice shape must satisfy n_s * n_l == n[k]");
     if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set lattices before adding terms");
+    if (c->g.pairs) return fail(c, PPQ_E_UNSUPPORTED, "the radius-sqrt(2) stencil is built for DVR dimensions only");
     c->g.lat_s[k] = ns;
     c->g.lat_l[k] = nl;
     c->lattice[k] = true;
@@ -1836,6 +1837,17 @@ int ppq_set_factor(ppq_ctx *c, int k, const double *h)
     c->derived_valid = false;
     c->v_valid = false;
     c->v_partial = false;
+    return PPQ_OK;
+}
+
+int ppq_set_stencil(ppq_ctx *c, int stencil)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (stencil != 1 && stencil != 2) return fail(c, PPQ_E_ARG, "stencil must be 1 or 2");
+    if (stencil == 2 && c->any_lattice)
+        return fail(c, PPQ_E_UNSUPPORTED, "the radius-sqrt(2) stencil is built for DVR dimensions only");
+    c->g.pairs = stencil == 2 ? 1 : 0;
     return PPQ_OK;
 }
 

@@ -24,6 +24,8 @@ struct GridDesc {
     int lat_s[MAXD];        // phase-space lattice shape; lat_s == 0 -> +-1 line stencil
     int lat_l[MAXD];
     uint32_t total;
+    int pairs;              // adaption stencil: 0 = +-1 in one dimension (2D neighbours),
+                            // 1 = also +-1 in two dimensions at once (2D^2 neighbours)
 };
 
 // Diagonal potential as a sum of products of 1D tables.

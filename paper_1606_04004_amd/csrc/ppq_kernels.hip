@@ -76,6 +76,23 @@ __device__ inline void set_with_neighbours(const GridDesc &g, uint64_t *bm, uint
             set_bit_wave(bm, key + sk, keep && l + 1 < nl);
         }
     }
+    // radius sqrt(2) (Sec. III.A): also every change of +-1 in two dimensions
+    // at once (DVR dimensions only)
+    if (g.pairs) {
+        for (int k = 0; k < g.D; ++k) {
+            const uint32_t sk = g.stride[k];
+            const int dk = (int)((key / sk) % (uint32_t)g.n[k]);
+            for (int l = k + 1; l < g.D; ++l) {
+                const uint32_t sl = g.stride[l];
+                const int dl = (int)((key / sl) % (uint32_t)g.n[l]);
+                const bool kd = dk > 0, ku = dk + 1 < g.n[k], ld = dl > 0, lu = dl + 1 < g.n[l];
+                set_bit_wave(bm, key - sk - sl, keep && kd && ld);
+                set_bit_wave(bm, key - sk + sl, keep && kd && lu);
+                set_bit_wave(bm, key + sk - sl, keep && ku && ld);
+                set_bit_wave(bm, key + sk + sl, keep && ku && lu);
+            }
+        }
+    }
 }
 
 // Counts `pred` over the block and adds the block's total with one atomic

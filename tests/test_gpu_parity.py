@@ -994,3 +994,36 @@ def test_custom_dim_factors(prec, torch):
     h[0, 1] += 1e-9
     with pytest.raises(PPQError):
         g.set_factor(0, h)
+
+
+@pytest.mark.parametrize("name", ["small_3d", "small_4d", "small_6d"])
+def test_radius_sqrt2_stencil(name, torch):
+    """Ball radius sqrt(2) (2D^2 neighbours): adaption bit-exact on adversarial
+    states, the same initial set, and a 10-step trajectory."""
+    from paper_1606_04004_amd import PPQError
+    cd = card(name, stencil=2)
+    o = Oracle(cd)
+    g = make(cd, torch)
+    for seed in (1, 2):
+        keys = random_active_set(o.n, 0.3, seed)
+        rng = np.random.default_rng(seed)
+        c = random_complex(keys.size, seed) * np.exp(rng.uniform(-12, 0, keys.size))
+        c[::17] = 1e-3
+        say(f"radius sqrt2 {name} seed {seed} |A|={keys.size}")
+        o.set_state(keys, c)
+        nab = o.prune(eps=1e-3)
+        g.set_state(keys, c)
+        assert g.prune(eps=1e-3)[1] == nab
+        assert np.array_equal(g.state()[0], o.state()[0])
+        assert np.array_equal(g.state()[1], o.state()[1])
+    o.init_state()
+    g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=10)
+    tg = g.propagate(nsteps=10)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 2, 3, 4, 6):
+        assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    gl = make(lattice_card(), torch)
+    with pytest.raises(PPQError):
+        gl.set_stencil(2)

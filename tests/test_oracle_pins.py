@@ -535,6 +535,51 @@ def test_prune_relative_exclusion_matches_bruteforce(seed):
         assert np.array_equal(c2, np.array([lookup.get(k, 0j) for k in k2.tolist()]))
 
 
+def brute_adapt_pairs(n, keys, c, eps):
+    """Ball radius sqrt(2): the radius-1 set plus every +-1 change in two
+    dimensions at once (brute force over the kept points)."""
+    n = list(n)
+    out = set(brute_adapt(n, keys, c, eps).tolist())
+    for key, v in zip(keys.tolist(), c):
+        if v.real * v.real + v.imag * v.imag >= eps * eps:
+            d = list(np.unravel_index(key, n))
+            for k in range(len(n)):
+                for l in range(k + 1, len(n)):
+                    for a in (-1, 1):
+                        for b in (-1, 1):
+                            e = d.copy()
+                            e[k] += a
+                            e[l] += b
+                            if 0 <= e[k] < n[k] and 0 <= e[l] < n[l]:
+                                out.add(int(np.ravel_multi_index(e, n)))
+    return np.array(sorted(out), dtype=np.uint64)
+
+
+def test_prune_radius_sqrt2_stencil():
+    """Sec. III.A's intermediate stencil: 2D^2 neighbours of an interior point,
+    D + D(D-1)/2 of a corner, and brute force on adversarial states."""
+    for name in ("small_3d", "small_4d"):
+        cd = card(name, stencil=2)
+        o = orc.Oracle(cd)
+        n = cd["n"]
+        D = len(n)
+        for idx, want in (([v // 2 for v in n], 1 + 2 * D * D), ([0] * D, 1 + D + D * (D - 1) // 2)):
+            key = np.ravel_multi_index(idx, n)
+            o.set_state(np.array([key], dtype=np.uint64), np.array([1.0 + 0j]))
+            o.prune(eps=0.5)
+            assert o.state()[0].size == want, (name, idx)
+    cd = card("small_3d", stencil=2)
+    o = orc.Oracle(cd)
+    for seed in (1, 2):
+        keys, c = adversarial_prune_state(o, seed)
+        o.set_state(keys, c)
+        o.prune(eps=1e-3)
+        assert np.array_equal(o.state()[0], brute_adapt_pairs(o.n, keys, c, 1e-3))
+    with pytest.raises(ValueError):
+        orc.Oracle(card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0],
+                        stencil=2))
+
+
 def test_prune_lattice_stencil_matches_bruteforce():
     cd = card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0])
     o = orc.Oracle(cd)
