@@ -133,7 +133,37 @@ def secondary(stream, steps, warmup, adjoint_steps):
                                    "backward_s": t2 - t1, "gradient_components": int(dp.size + dc.size + dm.size),
                                    "grad_norm": float(np.sqrt(np.sum(dp ** 2) + np.sum(dc ** 2) + np.sum(dm ** 2)))}
         del g
+    out["hh2d_accuracy"] = accuracy_sweep(stream)
     return out
+
+
+def accuracy_sweep(stream):
+    """The paper's accuracy measure on the 2D card (Sec. III.A): the
+    infidelity of C(t), sqrt(sum_n |C_pruned(t_n) - C_exact(t_n)|^2) over all
+    200 records, against the mean number of functions used (percent of the
+    48^2 grid), per threshold and neighbour stencil; the exact run keeps the
+    full grid without adaption."""
+    import paper_1606_04004_amd as ppq
+    from workloads import card
+    cd = card("hh2d")
+    total = int(np.prod(cd["n"]))
+    g = ppq.Propagator(cd, precision=ppq.PPQ_FP64, device=0, stream=stream)
+    g.init_state(eps=0.0)
+    ref = g.propagate(prune=False)
+    c_ref = ref[:, 3] + 1j * ref[:, 4]
+    del g
+    rows = []
+    for stencil in (1, 2):
+        for eps in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+            g = ppq.Propagator(dict(cd, stencil=stencil), precision=ppq.PPQ_FP64, device=0, stream=stream)
+            g.init_state(eps=eps)
+            tr = g.propagate(eps=eps)
+            c = tr[:, 3] + 1j * tr[:, 4]
+            rows.append({"stencil": stencil, "eps": eps,
+                         "mean_basis_percent": float(100.0 * np.mean(tr[:, 5]) / total),
+                         "infidelity": float(np.sqrt(np.sum(np.abs(c - c_ref) ** 2)))})
+            del g
+    return rows
 
 
 def traffic_probe(stream):
