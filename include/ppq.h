@@ -256,6 +256,14 @@ int ppq_observables(ppq_ctx *ctx, double eps, double *out);
    state give NaN.  PPQ_E_STATE without a state. */
 int ppq_expect_q(ppq_ctx *ctx, double *q);
 
+/* Autocorrelation at twice the current time, C(2t) = <psi(t)*|psi(t)> =
+   sum_I c_I^2 over the active set (no complex conjugate): valid when the
+   initial packet is real (zero momentum) and the operator real symmetric,
+   so that one propagation to t gives C up to 2t (the identity that follows
+   Eq. acorr).  c2t: 2 doubles (re, im), host.  Synchronises.
+   PPQ_E_UNSUPPORTED on lattice contexts. */
+int ppq_acf_doubled(ppq_ctx *ctx, double *c2t);
+
 /* ---- adjoint gradient of the survival probability (added form) ----------
    J(theta) = |<psi0(centre, momentum)|psi(T)>|^2 after nsteps steps of the
    pruned propagation.  The active-set trajectory {A_n} of the recording run

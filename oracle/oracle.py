@@ -274,6 +274,13 @@ class Oracle:
         lib().orc_observe(self._m, self._fib_now(), self._s, _dp(self._bra_tabs.view(np.float64)), eps, _dp(out))
         return dict(zip(OBS_FIELDS[1:7], out))
 
+    def acf_doubled(self):
+        """C(2t) = <psi(t)*|psi(t)> = sum_I c_I^2 (no conjugate), the
+        autocorrelation at twice the time for a real initial packet and a real
+        symmetric operator (the identity after Eq. acorr)."""
+        _, c = self.state()
+        return complex(np.sum(c * c))
+
     def expect_q(self):
         """Position expectation per dimension of the current state,
         <q_k> = sum_I |c_I|^2 q_k(i_k) / sum_I |c_I|^2.

@@ -276,6 +276,12 @@ class Propagator:
         self._call("ppq_observables", float(eps), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return dict(zip(OBS_FIELDS[1:7], out[1:7]))
 
+    def acf_doubled(self):
+        """C(2t) = sum_I c_I^2 of the current state (real packet, real symmetric operator)."""
+        out = np.zeros(2)
+        self._call("ppq_acf_doubled", out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return complex(out[0], out[1])
+
     def expect_q(self):
         """<q_k> per dimension of the current state (NaN on lattice dimensions)."""
         out = np.zeros(self.D)

@@ -179,6 +179,7 @@ struct ppq_ctx {
     int tab_nmax = 0;
     double *qtab = nullptr;  // grid points [MAXD][NMAX_FIBER], then MAXD results (position expectations)
     double rel_excl = 0.0;   // relative exclusion threshold of adaption
+    double2 *acf2 = nullptr;  // C(2t) result (device)
     std::vector<double> factor[MAXD];  // caller's 1D factor per dimension (empty: sine-DVR kinetic)
     // fiber tables of all non-last dimensions at once (see fiber_tables_all)
     uint64_t *bmB = nullptr;
@@ -1637,6 +1638,7 @@ void ppq_destroy(ppq_ctx *c)
     dfree(c->init_tabs);
     dfree(c->bra_tabs);
     dfree(c->qtab);
+    dfree(c->acf2);
     dfree(c->rec);
     clear_record(c);
     dfree(c->rec_keys);
@@ -2223,6 +2225,25 @@ int ppq_expect_q(ppq_ctx *c, double *q)
         ck(hipGetLastError(), "expect_q launch");
         ck(hipStreamSynchronize(c->stream), "expect_q");
         ck(hipMemcpy(q, res, sizeof(double) * D, hipMemcpyDeviceToHost), "expect_q result");
+    })
+    return PPQ_OK;
+}
+
+int ppq_acf_doubled(ppq_ctx *c, double *c2t)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (!c2t) return fail(c, PPQ_E_ARG, "bad arguments");
+    if (c->any_lattice) return fail(c, PPQ_E_UNSUPPORTED, "C(2t) needs a real symmetric operator (DVR dimensions)");
+    PPQ_TRY(c, {
+        if (!c->acf2) c->acf2 = dalloc<double2>(1);
+        sum_of_squares(c->psi[c->cur], c->nact, c->partial, c->acf2, c->stream);
+        ck(hipGetLastError(), "C(2t) launch");
+        ck(hipStreamSynchronize(c->stream), "C(2t)");
+        double2 v;
+        ck(hipMemcpy(&v, c->acf2, sizeof(double2), hipMemcpyDeviceToHost), "C(2t) result");
+        c2t[0] = v.x;
+        c2t[1] = v.y;
     })
     return PPQ_OK;
 }

@@ -254,6 +254,8 @@ void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const Grid
 void obs_final(const double2 *partial, int nblocks, double *rec, hipStream_t s);
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s);
 void set_record(double *rec, double t, double nact, double krylov, hipStream_t s);
+// *out = sum_I psi_I^2 (device), fixed-order; partials in `partial`
+void sum_of_squares(const double2 *psi, int64_t n, double2 *partial, double2 *out, hipStream_t s);
 // device state transfer: caller keys/coefficients into the context's buffers,
 // with violation counts bad[0] (keys) and bad[1] (non-finite values);
 // block_counts holds 2 * nblocks(n) entries

@@ -1098,6 +1098,41 @@ __global__ __launch_bounds__(TB) void k_dot_partial(const double2 *a, const doub
     block_reduce_store<1>(acc, partial);
 }
 
+// ---- autocorrelation at twice the time --------------------------------------------
+// sum_I c_I^2 (no conjugate): C(2t) = <psi(t)*|psi(t)> when the initial packet
+// is real and the operator real symmetric (Eq. acorr and the text after it).
+__global__ __launch_bounds__(TB) void k_sq_partial(const double2 *psi, int64_t n, double2 *partial)
+{
+    double2 acc[1] = {make_double2(0.0, 0.0)};
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        const double2 c = psi[p];
+        acc[0].x = fma(c.x, c.x, fma(-c.y, c.y, acc[0].x));
+        acc[0].y = fma(2.0 * c.x, c.y, acc[0].y);
+    }
+    block_reduce_store<1>(acc, partial);
+}
+
+// fixed-order sum of the first partial of nb blocks into *out
+__global__ __launch_bounds__(TB) void k_sum_partial1(const double2 *partial, int nb, double2 *out)
+{
+    __shared__ double2 red[TB];
+    double2 s = make_double2(0.0, 0.0);
+    for (int b = threadIdx.x; b < nb; b += TB) {
+        s.x += partial[(int64_t)b * PSTRIDE].x;
+        s.y += partial[(int64_t)b * PSTRIDE].y;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = TB / 2; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            red[threadIdx.x].x += red[threadIdx.x + st].x;
+            red[threadIdx.x].y += red[threadIdx.x + st].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 // ---- observables ------------------------------------------------------------------
 __global__ __launch_bounds__(TB) void k_obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, GridDesc g,
                                                     const double2 *bra, int nmax, double eps2, double2 *partial)
@@ -1875,6 +1910,11 @@ void give_keys(const uint32_t *k32, int64_t n, uint64_t *keys, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_give_keys, dim3(nblocks(n)), dim3(TB), 0, s, k32, n, keys);
+}
+void sum_of_squares(const double2 *psi, int64_t n, double2 *partial, double2 *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sq_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, psi, n, partial);
+    hipLaunchKernelGGL(k_sum_partial1, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, out);
 }
 void set_record(double *rec, double t, double nact, double krylov, hipStream_t s)
 {

@@ -1027,3 +1027,29 @@ def test_radius_sqrt2_stencil(name, torch):
     gl = make(lattice_card(), torch)
     with pytest.raises(PPQError):
         gl.set_stencil(2)
+
+
+def test_acf_doubled(torch):
+    """C(2t) = sum c^2: the oracle's on the same state (1e-13), and, unpruned
+    with a real packet, the C(t) record at twice the time (1e-9)."""
+    cd = card("small_3d")
+    cd["psi0"] = dict(cd["psi0"], momentum=[0.0, 0.0, 0.0])
+    o = Oracle(cd)
+    g = make(cd, torch)
+    g.init_state()
+    g.propagate(nsteps=10)
+    kg, cg = g.state()
+    o.set_state(kg, cg)
+    assert abs(g.acf_doubled() - o.acf_doubled()) < 1e-13
+    g.init_state(eps=0.0)
+    tr = g.propagate(nsteps=20, prune=False)
+    g.init_state(eps=0.0)
+    g.propagate(nsteps=10, prune=False)
+    c2 = g.acf_doubled()
+    say(f"C(2t) {c2} record {tr[20, 3]} {tr[20, 4]}")
+    assert abs(c2 - complex(tr[20, 3], tr[20, 4])) < 1e-9
+    gl = make(lattice_card(), torch)
+    gl.init_state()
+    from paper_1606_04004_amd import PPQError
+    with pytest.raises(PPQError):
+        gl.acf_doubled()

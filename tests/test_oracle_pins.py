@@ -361,6 +361,27 @@ def test_expect_q_follows_classical_trajectory():
         assert np.max(np.abs(o.expect_q() - (q0 * np.cos(t) + p0 * np.sin(t)))) < 1e-9
 
 
+def test_acf_doubled_closed_form():
+    """Real packet (zero momentum) on the uncoupled oscillator: sum c^2 after
+    propagating to t is the closed-form C(2t)."""
+    cd = _coherent_card()
+    cd["psi0"] = dict(cd["psi0"], momentum=[0.0, 0.0])
+    o = orc.Oracle(cd)
+    keys, c0 = _full_state(o)
+    o.set_state(keys, c0)
+    dt = 0.05
+    for st in range(1, 31):
+        o.sil_step(dt=dt, m=16)
+        if st % 10:
+            continue
+        t2 = 2 * st * dt
+        ref = 1.0 + 0j
+        for k in range(2):
+            a = cd["psi0"]["centre"][k] / np.sqrt(2.0)
+            ref *= np.exp(-0.5j * t2) * np.exp(-abs(a) ** 2 * (1.0 - np.exp(-1j * t2)))
+        assert abs(o.acf_doubled() - ref) < 1e-9
+
+
 def test_expect_q_special_cases():
     """One grid point: <q_k> is that point's coordinate for any weight; a state
     mirror-symmetric in dimension k on a symmetric box: <q_k> = 0; lattice
