@@ -72,6 +72,27 @@ def pvb_projection(q, dx_grid, lo, hi, ns, nl):
     return G
 
 
+def pw_projection(q, dx_grid, lo, hi, nx, npm):
+    """Projected Weylets (Sec. II.D): W = Phi S^{-1/2}, Phi[j, s*npm+l] =
+    sqrt(dx_grid) phi_sl(q_j) with the momentum-symmetrized Gaussians of
+    Eq. sG_def on a doubly dense lattice (dX dP = pi, p_l = (l + 1/2) dP > 0),
+    S = Phi^T Phi (Loewdin)."""
+    dX = (hi - lo) / nx
+    dP = np.pi / dX
+    alpha = dP / (2.0 * dX)
+    xs = lo + (np.arange(nx) + 0.5) * dX
+    pl = (np.arange(npm) + 0.5) * dP
+    shift = np.sqrt(np.pi / (8.0 * alpha))
+    Phi = np.empty((q.size, nx * npm))
+    for s in range(nx):
+        for l in range(npm):
+            d = q - xs[s]
+            Phi[:, s * npm + l] = (np.sqrt(dx_grid) * (8.0 * alpha / np.pi) ** 0.25 * np.exp(-alpha * d * d)
+                                   * np.sin(pl[l] * (d - shift)))
+    w, V = np.linalg.eigh(Phi.T @ Phi)
+    return (Phi @ (V * w ** -0.5) @ V.T).astype(np.complex128)
+
+
 class Model:
     """All 1D ingredients of a card, in the oracle's own FP64 construction."""
 
@@ -92,11 +113,14 @@ class Model:
         ps = card["psi0"]
         self.g0 = [gaussian_1d(self.q[k], ps["centre"][k], ps["momentum"][k], ps["width"][k])
                    for k in range(D)]
-        self.pvb = card.get("basis", "dvr") == "pvb"
+        # phase-space lattice bases: projected von Neumann ("pvb", biorthogonal)
+        # or projected Weylets ("pw", orthogonal); both act as a = G^+ c
+        self.pvb = card.get("basis", "dvr") in ("pvb", "pw")
         if self.pvb:
             ns, nl = card["lattice"]
             self.lattice = (ns, nl)
-            self.G = [pvb_projection(self.q[k], self.dx[k], card["lo"][k], card["hi"][k], ns, nl)
+            proj = pw_projection if card["basis"] == "pw" else pvb_projection
+            self.G = [proj(self.q[k], self.dx[k], card["lo"][k], card["hi"][k], ns, nl)
                       for k in range(D)]
             self.Ginv = [np.linalg.inv(G) for G in self.G]
             self.GinvH = [np.linalg.inv(G.conj().T) for G in self.G]

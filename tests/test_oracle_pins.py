@@ -694,6 +694,41 @@ def test_pvb_unpruned_dynamics_is_similarity_of_dvr():
     assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
 
 
+def test_pw_basis_is_orthogonal():
+    """Projected Weylets (Sec. II.D): W = Phi S^{-1/2} is real and orthogonal,
+    and its columns span the DVR space (W W^T = I as well)."""
+    from oracle.model import pw_projection
+    for n, lo, hi, nx, npm in ((12, -5.0, 5.0, 3, 4), (48, -3.0, 9.0, 6, 8)):
+        q, dx = sine_dvr_grid(n, lo, hi)
+        W = pw_projection(q, dx, lo, hi, nx, npm)
+        assert np.max(np.abs(W.imag)) == 0.0
+        assert np.max(np.abs(W.conj().T @ W - np.eye(n))) < 1e-12
+        assert np.max(np.abs(W @ W.conj().T - np.eye(n))) < 1e-12
+
+
+def test_pw_unpruned_dynamics_is_similarity_of_dvr():
+    """a = W^T c: unpruned projected-Weylet dynamics maps back to the DVR
+    dynamics exactly, and C(t) agrees."""
+    base = card("small_4d", n=[12, 12, 12, 12])
+    base["terms"] = base["terms"][:2] + base["terms"][4:6]
+    lat = dict(base, basis="pw", lattice=[3, 4])
+    od = orc.Oracle(base)
+    ol = orc.Oracle(lat)
+    kd, cd0 = _full_state(od)
+    kl, cl0 = _full_state(ol)
+    od.set_state(kd, cd0)
+    ol.set_state(kl, cl0)
+    td, _ = od.propagate(nsteps=8, dt=0.05, m=12, prune=False)
+    tl, _ = ol.propagate(nsteps=8, dt=0.05, m=12, prune=False)
+    assert np.max(np.abs((td[:, 3] + 1j * td[:, 4]) - (tl[:, 3] + 1j * tl[:, 4]))) < 1e-9
+    _, cdv = od.state()
+    _, clat = ol.state()
+    c_back = clat.reshape(ol.n)
+    for k in range(4):
+        c_back = np.moveaxis(np.tensordot(ol.model.G[k], c_back, axes=([1], [k])), 0, k)
+    assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
+
+
 def test_pvb_coefficients_are_overlaps():
     """Eq. psi_exp_pvb: lattice coefficients are G^+ c_chi; G's columns are the projected Gaussians."""
     q, dx = sine_dvr_grid(16, -6.0, 6.0)
