@@ -125,6 +125,17 @@ int ppq_get_grid(const ppq_ctx *ctx, int k, double *q);
    lattice cells (s+-1, l), (s, l+-1).  Must be called before adding terms. */
 int ppq_set_lattice(ppq_ctx *ctx, int k, int n_s, int n_l);
 
+/* Makes dimension k a projected-Weylet basis (Sec. II.D): the
+   momentum-symmetrized Gaussians of Eq. sG_def on a doubly dense lattice of
+   n_x cells (x_s = lo + (s + 1/2) dx, dx = (hi-lo)/n_x) and n_p momenta
+   (p_l = (l + 1/2) dp > 0, dp = pi / dx, alpha = dp / (2 dx)), projected on
+   the DVR grid (Eq. psG_def) and orthogonalised, W = Phi S^{-1/2}:
+   a real orthogonal basis used like the lattice of ppq_set_lattice (a = W^T c,
+   factors W^T h W, Arnoldi steps, lattice-cell neighbours in adaption).
+   n_x * n_p == n[k].  PPQ_E_NUMERIC if the lattice's functions are linearly
+   dependent.  Must be called before adding terms. */
+int ppq_set_weylets(ppq_ctx *ctx, int k, int n_x, int n_p);
+
 /* Adds the potential term coef * prod_f factor_f(q_{dims[f]}) (a product of
    diagonal 1D factors: Sec. II.E, potential as a sum of products of diagonal
    matrices).  kinds[f] is a ppq_factor_kind, params holds 2 doubles per

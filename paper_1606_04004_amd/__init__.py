@@ -52,10 +52,11 @@ class Propagator:
         lo, plo = _d(card["lo"])
         hi, phi = _d(card["hi"])
         self._call("ppq_set_grid", self.D, pn, plo, phi, float(card["mass"]))
-        if card.get("basis", "dvr") == "pvb":
+        if card.get("basis", "dvr") in ("pvb", "pw"):
             ns, nl = card["lattice"]
+            call = "ppq_set_weylets" if card["basis"] == "pw" else "ppq_set_lattice"
             for k in range(self.D):
-                self._call("ppq_set_lattice", k, int(ns), int(nl))
+                self._call(call, k, int(ns), int(nl))
         for k, h in card.get("dim_factors", {}).items():
             self.set_factor(int(k), h)
         if card.get("stencil", 1) != 1:

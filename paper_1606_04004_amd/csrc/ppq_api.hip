@@ -88,6 +88,7 @@ struct ppq_ctx {
     double lo[MAXD]{}, hi[MAXD]{}, mass = 1.0;
     int nb[MAXD]{};  // padded 1D size per dimension
     bool lattice[MAXD]{};
+    bool weylets[MAXD]{};   // lattice dimension built from projected Weylets (else projected von Neumann)
     bool any_lattice = false;
     int64_t nwords = 0;
 
@@ -450,7 +451,8 @@ LatticeMaps lattice_maps(const ppq_ctx *c, int k)
 {
     LatticeMaps L;
     int n = c->g.n[k];
-    L.G = pvb_projection(n, c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k]);
+    L.G = c->weylets[k] ? weylet_projection(n, c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k])
+                        : pvb_projection(n, c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k]);
     L.Gadj = adjoint(L.G, n);
     L.GinvAdj = L.Gadj;
     if (!invert(L.GinvAdj, n)) throw std::runtime_error("singular lattice projection");
@@ -1722,6 +1724,7 @@ int ppq_set_grid(ppq_ctx *c, int D, const int32_t *n, const double *lo, const do
             c->hi[k] = hi[k];
             c->nb[k] = bucket(n[k]);
             c->lattice[k] = false;
+            c->weylets[k] = false;
             c->factor[k].clear();
         }
         c->mass = mass;
@@ -1754,17 +1757,21 @@ int ppq_get_grid(const ppq_ctx *c, int k, double *q)
     return PPQ_OK;
 }
 
-int ppq_set_lattice(ppq_ctx *c, int k, int ns, int nl)
+static int set_lattice_kind(ppq_ctx *c, int k, int ns, int nl, bool weylets)
 {
-    PPQ_GUARD(c)
     if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
     if (k < 0 || k >= c->g.D || ns < 1 || nl < 1 || ns * nl != c->g.n[k])
         return fail(c, PPQ_E_ARG, "lattice shape must satisfy n_s * n_l == n[k]");
     if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set lattices before adding terms");
     if (c->g.pairs) return fail(c, PPQ_E_UNSUPPORTED, "the radius-sqrt(2) stencil is built for DVR dimensions only");
+    if (weylets) {
+        // fails early on a lattice whose symmetrized Gaussians are linearly dependent
+        PPQ_TRY(c, { (void)weylet_projection(c->g.n[k], c->lo[k], c->hi[k], ns, nl); })
+    }
     c->g.lat_s[k] = ns;
     c->g.lat_l[k] = nl;
     c->lattice[k] = true;
+    c->weylets[k] = weylets;
     c->any_lattice = true;
     c->block_ok = false;
     c->op_dirty = true;
@@ -1772,6 +1779,18 @@ int ppq_set_lattice(ppq_ctx *c, int k, int ns, int nl)
     c->v_valid = false;
     c->v_partial = false;
     return PPQ_OK;
+}
+
+int ppq_set_lattice(ppq_ctx *c, int k, int ns, int nl)
+{
+    PPQ_GUARD(c)
+    return set_lattice_kind(c, k, ns, nl, false);
+}
+
+int ppq_set_weylets(ppq_ctx *c, int k, int nx, int np)
+{
+    PPQ_GUARD(c)
+    return set_lattice_kind(c, k, nx, np, true);
 }
 
 int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dims, const int32_t *kinds,

@@ -62,6 +62,103 @@ std::vector<cd> pvb_projection(int n, double lo, double hi, int ns, int nl)
     return G;
 }
 
+// Real symmetric eigen-decomposition by cyclic Jacobi rotations (a is
+// consumed): w receives the eigenvalues, v the eigenvectors as columns.
+static void jacobi_eigen(std::vector<double> a, int n, std::vector<double> &w, std::vector<double> &v)
+{
+    v.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) v[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double x = a[(size_t)i * n + j];
+                if (i == j) diag += x * x;
+                else off += x * x;
+            }
+        if (off <= 1e-30 * diag) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+                    a[(size_t)k * n + p] = c * akp - sn * akq;
+                    a[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+                    a[(size_t)p * n + k] = c * apk - sn * aqk;
+                    a[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = v[(size_t)k * n + p], vkq = v[(size_t)k * n + q];
+                    v[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    v[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
+}
+
+// Projected Weylets (Sec. II.D): the momentum-symmetrized Gaussians of
+// Eq. sG_def on a doubly dense lattice (cell dx, dp = pi / dx, momenta
+// p_l = (l + 1/2) dp > 0, alpha = dp / (2 dx)), projected on the sine-DVR
+// grid (Eq. psG_def) as Phi, then orthogonalised: W = Phi S^{-1/2},
+// S = Phi^T Phi.  Returned as a complex n x n matrix (real values).
+std::vector<cd> weylet_projection(int n, double lo, double hi, int nx, int np)
+{
+    std::vector<double> q = sine_dvr_points(n, lo, hi);
+    const double dxg = (hi - lo) / (n + 1);
+    const double cell = (hi - lo) / nx;
+    const double dp = M_PI / cell;
+    const double a = dp / (2.0 * cell);
+    const double pref = std::sqrt(dxg) * std::pow(8.0 * a / M_PI, 0.25);
+    const double shift = std::sqrt(M_PI / (8.0 * a));
+    std::vector<double> phi((size_t)n * n);
+    for (int s = 0; s < nx; ++s) {
+        const double xs = lo + (s + 0.5) * cell;
+        for (int l = 0; l < np; ++l) {
+            const double pl = (l + 0.5) * dp;
+            for (int j = 0; j < n; ++j) {
+                const double d = q[j] - xs;
+                phi[(size_t)j * n + (s * np + l)] = pref * std::exp(-a * d * d) * std::sin(pl * (d - shift));
+            }
+        }
+    }
+    std::vector<double> S((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int r = 0; r < n; ++r) acc += phi[(size_t)r * n + i] * phi[(size_t)r * n + j];
+            S[(size_t)i * n + j] = acc;
+        }
+    std::vector<double> w, v;
+    jacobi_eigen(S, n, w, v);
+    double wmax = 0.0;
+    for (double x : w) wmax = std::max(wmax, x);
+    std::vector<double> sih((size_t)n * n, 0.0);  // S^{-1/2} = V diag(w^-1/2) V^T
+    for (int k = 0; k < n; ++k) {
+        if (!(w[k] > 1e-14 * wmax)) throw std::runtime_error("linearly dependent Weylet lattice");
+        const double f = 1.0 / std::sqrt(w[k]);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) sih[(size_t)i * n + j] += v[(size_t)i * n + k] * f * v[(size_t)j * n + k];
+    }
+    std::vector<cd> W((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int r = 0; r < n; ++r) acc += phi[(size_t)i * n + r] * sih[(size_t)r * n + j];
+            W[(size_t)i * n + j] = acc;
+        }
+    return W;
+}
+
 bool invert(std::vector<cd> &a, int n)
 {
     std::vector<cd> inv((size_t)n * n, cd(0.0, 0.0));

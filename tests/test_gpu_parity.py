@@ -1053,3 +1053,67 @@ def test_acf_doubled(torch):
     from paper_1606_04004_amd import PPQError
     with pytest.raises(PPQError):
         gl.acf_doubled()
+
+
+def weylet_card(n=12, nx=3, npm=4, **kw):
+    base = card("small_4d", n=[n, n, n, n], **kw)
+    return dict(base, name="small_weylet4d", basis="pw", lattice=[nx, npm])
+
+
+def test_weylet_products(torch):
+    """Projected Weylets (real orthogonal W, dense factors W^T h W and the
+    truncated pair terms): products on random sets against the oracle."""
+    cd = weylet_card()
+    o = Oracle(cd)
+    g = make(cd, torch)
+    for fill, seed in ((1.0, 1), (0.3, 2), (0.05, 3)):
+        keys = (np.arange(int(np.prod(cd["n"])), dtype=np.uint64) if fill == 1.0
+                else random_active_set(cd["n"], fill, seed))
+        x = random_complex(keys.size, seed + 30)
+        say(f"weylet product |A|={keys.size}")
+        g.set_state(keys, x)
+        xt = torch.from_numpy(x).cuda()
+        yt = torch.zeros_like(xt)
+        g.apply_h(xt, yt)
+        torch.cuda.synchronize()
+        ref = o.apply_def(keys, x)
+        err = np.max(np.abs(yt.cpu().numpy() - ref)) / np.max(np.abs(ref))
+        say(f"  rel err {err:.2e}")
+        assert err < 1e-13
+
+
+def test_weylet_trajectory(torch):
+    """Projected Weylets: identical initial set, sets and observables over 10
+    steps (Arnoldi, lattice-cell stencil)."""
+    cd = weylet_card(eps=1e-4)
+    o = Oracle(cd)
+    o.init_state()
+    g = make(cd, torch)
+    g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=10, dt=0.05)
+    tg = g.propagate(nsteps=10, dt=0.05)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 2, 3, 4, 6):
+        d = np.max(np.abs(tg[:, col] - tr[:, col]))
+        say(f"  col {col}: {d:.2e}")
+        assert d < 1e-10
+
+
+def test_weylet_full_size_card(torch):
+    """The 4D lattice card's size (48^4) with projected Weylets on a 6 x 8
+    doubly dense lattice: identical initial set and two steps."""
+    cd = dict(card("pvb4d"), basis="pw")
+    say("pw 48^4: 2 steps")
+    o = Oracle(cd)
+    o.init_state()
+    g = make(cd, torch)
+    g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=2)
+    tg = g.propagate(nsteps=2)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 2, 3, 4, 6):
+        d = np.max(np.abs(tg[:, col] - tr[:, col]))
+        say(f"  col {col}: {d:.2e}")
+        assert d < 1e-10
