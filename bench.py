@@ -117,6 +117,17 @@ def secondary(stream, steps, warmup, adjoint_steps):
                                "from": "initial set of the 4D phase-space lattice card (48^4, 6x8 lattice per "
                                        "dimension), complex factors on the matrix cores"}
         del g
+    cd = dict(card("pvb4d"), basis="pw")
+    for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
+        g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
+        g.init_state()
+        na = g.active_count()
+        ms_h = g.time_apply(10)
+        rate, ms, _ = timed_steps(g, steps, warmup)
+        out[f"pw4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
+                              "from": "initial set of the 4D Morse model in projected Weylets (48^4, 6x8 "
+                                      "doubly dense lattice per dimension)"}
+        del g
     cd = card("adjoint4d", nsteps=adjoint_steps)
     for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
@@ -140,9 +151,11 @@ def secondary(stream, steps, warmup, adjoint_steps):
 def accuracy_sweep(stream):
     """The paper's accuracy measure on the 2D card (Sec. III.A): the
     infidelity of C(t), sqrt(sum_n |C_pruned(t_n) - C_exact(t_n)|^2) over all
-    200 records, against the mean number of functions used (percent of the
-    48^2 grid), per threshold and neighbour stencil; the exact run keeps the
-    full grid without adaption."""
+    201 records, against the mean number of functions used (percent of the
+    48^2 grid), per threshold, for the DVR with either neighbour stencil and
+    for the projected von Neumann and projected Weylet lattices (6 x 8 per
+    dimension); the exact run keeps the full DVR grid without adaption (all
+    three bases are similarity transforms of it)."""
     import paper_1606_04004_amd as ppq
     from workloads import card
     cd = card("hh2d")
@@ -153,13 +166,15 @@ def accuracy_sweep(stream):
     c_ref = ref[:, 3] + 1j * ref[:, 4]
     del g
     rows = []
-    for stencil in (1, 2):
+    variants = (("dvr", 1, {}), ("dvr", 2, {"stencil": 2}),
+                ("pvb", 1, {"basis": "pvb", "lattice": [6, 8]}), ("pw", 1, {"basis": "pw", "lattice": [6, 8]}))
+    for basis, stencil, extra in variants:
         for eps in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
-            g = ppq.Propagator(dict(cd, stencil=stencil), precision=ppq.PPQ_FP64, device=0, stream=stream)
+            g = ppq.Propagator(dict(cd, **extra), precision=ppq.PPQ_FP64, device=0, stream=stream)
             g.init_state(eps=eps)
             tr = g.propagate(eps=eps)
             c = tr[:, 3] + 1j * tr[:, 4]
-            rows.append({"stencil": stencil, "eps": eps,
+            rows.append({"basis": basis, "stencil": stencil, "eps": eps,
                          "mean_basis_percent": float(100.0 * np.mean(tr[:, 5]) / total),
                          "infidelity": float(np.sqrt(np.sum(np.abs(c - c_ref) ** 2)))})
             del g
