@@ -115,6 +115,14 @@ int ppq_set_grid(ppq_ctx *ctx, int D, const int32_t *n, const double *lo, const 
 /* Grid points of dimension k (n[k] doubles, host). */
 int ppq_get_grid(const ppq_ctx *ctx, int k, double *q);
 
+/* Makes dimension k a periodic Fourier grid (the FGH DVR the paper uses
+   under its lattices, Sec. III.A): points x_j = lo + j (hi-lo)/n, j = 0..n-1,
+   over the period hi - lo, and kinetic energy -1/(2 mass) d^2/dx^2 from its
+   spectral definition with |k| <= (n-1) pi/(hi-lo).  n[k] must be odd
+   (PPQ_E_ARG).  DVR dimensions only (PPQ_E_UNSUPPORTED after
+   ppq_set_lattice / ppq_set_weylets); must be called before adding terms. */
+int ppq_set_fgh(ppq_ctx *ctx, int k);
+
 /* Makes dimension k a phase-space lattice basis: n_s x n_l von Neumann
    Gaussians projected on the DVR grid and used biorthogonally (Sec. II.B.1,
    Eqs. pvN_def, pvb_def, psi_exp_pvb), n_s * n_l == n[k].  Cells are centred

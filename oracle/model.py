@@ -27,6 +27,26 @@ def sine_dvr_grid(n, lo, hi):
     return lo + dx * np.arange(1, n + 1), dx
 
 
+def fgh_grid(n, lo, hi):
+    """Periodic Fourier grid: x_j = lo + j L / n, j = 0..n-1, L = hi - lo."""
+    dx = (hi - lo) / n
+    return lo + dx * np.arange(n), dx
+
+
+def fgh_kinetic(n, lo, hi, mass):
+    """-1/(2 mass) d^2/dx^2 on the periodic Fourier grid of odd n, in closed
+    form: T_ii = (pi/L)^2 (n^2 - 1) / (6 mass),
+    T_ij = (pi/L)^2 (-1)^(i-j) cos(pi (i-j)/n) / (mass sin^2(pi (i-j)/n))."""
+    L = hi - lo
+    d = np.arange(n)[:, None] - np.arange(n)[None, :]
+    T = np.empty((n, n))
+    off = d != 0
+    dd = d[off]
+    T[off] = (np.pi / L) ** 2 * (-1.0) ** dd * np.cos(np.pi * dd / n) / (mass * np.sin(np.pi * dd / n) ** 2)
+    np.fill_diagonal(T, (np.pi / L) ** 2 * (n * n - 1) / (6.0 * mass))
+    return T
+
+
 def sine_dvr_kinetic(n, lo, hi, mass):
     """Closed-form sine-DVR kinetic matrix (hbar = 1)."""
     L = hi - lo
@@ -102,11 +122,13 @@ class Model:
         self.D = D
         self.n = [int(v) for v in card["n"]]
         self.q, self.dx, self.T = [], [], []
+        fgh = set(int(k) for k in card.get("fgh", []))
         for k in range(D):
-            qk, dxk = sine_dvr_grid(self.n[k], card["lo"][k], card["hi"][k])
+            grid, kin = (fgh_grid, fgh_kinetic) if k in fgh else (sine_dvr_grid, sine_dvr_kinetic)
+            qk, dxk = grid(self.n[k], card["lo"][k], card["hi"][k])
             self.q.append(qk)
             self.dx.append(dxk)
-            self.T.append(sine_dvr_kinetic(self.n[k], card["lo"][k], card["hi"][k], card["mass"]))
+            self.T.append(kin(self.n[k], card["lo"][k], card["hi"][k], card["mass"]))
         # a card may replace the 1D operator of a dimension by its own matrix
         for k, h in card.get("dim_factors", {}).items():
             self.T[int(k)] = np.array(h, dtype=np.float64).reshape(self.n[int(k)], self.n[int(k)])

@@ -52,6 +52,8 @@ class Propagator:
         lo, plo = _d(card["lo"])
         hi, phi = _d(card["hi"])
         self._call("ppq_set_grid", self.D, pn, plo, phi, float(card["mass"]))
+        for k in card.get("fgh", []):
+            self._call("ppq_set_fgh", int(k))
         if card.get("basis", "dvr") in ("pvb", "pw"):
             ns, nl = card["lattice"]
             call = "ppq_set_weylets" if card["basis"] == "pw" else "ppq_set_lattice"

@@ -45,6 +45,7 @@ SIGNATURES = {
     "ppq_set_factor": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "ppq_set_stencil": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ppq_set_weylets": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ppq_set_fgh": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ppq_set_state_device": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, _vp]),
     "ppq_get_state_device": (ctypes.c_int, [_vp, ctypes.c_int64, _i64p, _vp, _vp]),
     "ppq_set_relative_exclusion": (ctypes.c_int, [_vp, ctypes.c_double]),

@@ -89,6 +89,7 @@ struct ppq_ctx {
     int nb[MAXD]{};  // padded 1D size per dimension
     bool lattice[MAXD]{};
     bool weylets[MAXD]{};   // lattice dimension built from projected Weylets (else projected von Neumann)
+    bool fgh[MAXD]{};       // periodic Fourier-grid dimension (else sine-DVR)
     bool any_lattice = false;
     int64_t nwords = 0;
 
@@ -406,11 +407,22 @@ void ensure_zbuf(ppq_ctx *c)
 }
 
 // ---- operator assembly -------------------------------------------------------
+// Grid points of dimension k: sine-DVR interior points of the box, or the
+// periodic Fourier grid x_j = lo + j (hi - lo) / n, j = 0..n-1.
+std::vector<double> dim_points(const ppq_ctx *c, int k)
+{
+    const int n = c->g.n[k];
+    if (!c->fgh[k]) return sine_dvr_points(n, c->lo[k], c->hi[k]);
+    std::vector<double> q(n);
+    for (int j = 0; j < n; ++j) q[j] = c->lo[k] + j * (c->hi[k] - c->lo[k]) / n;
+    return q;
+}
+
 std::vector<double> factor_values(const ppq_ctx *c, const Factor &f)
 {
     int k = f.dim;
     int n = c->g.n[k];
-    std::vector<double> q = sine_dvr_points(n, c->lo[k], c->hi[k]);
+    std::vector<double> q = dim_points(c, k);
     std::vector<double> v(n);
     for (int i = 0; i < n; ++i) {
         if (f.kind == PPQ_FAC_POWER) {
@@ -466,10 +478,12 @@ std::vector<cd> similarity(const LatticeMaps &L, const std::vector<cd> &h, int n
 }
 
 // The one-dimensional operator of dimension k in its DVR basis: the caller's
-// factor when one was set, else the sine-DVR kinetic energy.
+// factor when one was set, else the kinetic energy of its grid (Fourier grid
+// or sine-DVR).
 std::vector<double> dim_factor(const ppq_ctx *c, int k)
 {
     if (!c->factor[k].empty()) return c->factor[k];
+    if (c->fgh[k]) return fgh_kinetic(c->g.n[k], c->lo[k], c->hi[k], c->mass);
     return sine_dvr_kinetic(c->g.n[k], c->lo[k], c->hi[k], c->mass);
 }
 
@@ -1322,7 +1336,7 @@ void set_packet_tables(ppq_ctx *c, const double *centre, const double *momentum,
     std::vector<double2> dt((size_t)2 * D * nmax, make_double2(0.0, 0.0));
     for (int k = 0; k < D; ++k) {
         int n = c->g.n[k];
-        std::vector<double> q = sine_dvr_points(n, c->lo[k], c->hi[k]);
+        std::vector<double> q = dim_points(c, k);
         std::vector<cd> gk(n), dc(n), dp(n);
         double nrm2 = 0.0;
         for (int i = 0; i < n; ++i) {
@@ -1725,6 +1739,7 @@ int ppq_set_grid(ppq_ctx *c, int D, const int32_t *n, const double *lo, const do
             c->nb[k] = bucket(n[k]);
             c->lattice[k] = false;
             c->weylets[k] = false;
+            c->fgh[k] = false;
             c->factor[k].clear();
         }
         c->mass = mass;
@@ -1752,7 +1767,7 @@ int ppq_get_grid(const ppq_ctx *c, int k, double *q)
 {
     if (!c || !q) return PPQ_E_ARG;
     if (!c->has_grid || k < 0 || k >= c->g.D) return PPQ_E_ARG;
-    std::vector<double> v = sine_dvr_points(c->g.n[k], c->lo[k], c->hi[k]);
+    std::vector<double> v = dim_points(c, k);
     std::memcpy(q, v.data(), v.size() * sizeof(double));
     return PPQ_OK;
 }
@@ -1764,6 +1779,7 @@ static int set_lattice_kind(ppq_ctx *c, int k, int ns, int nl, bool weylets)
         return fail(c, PPQ_E_ARG, "lattice shape must satisfy n_s * n_l == n[k]");
     if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set lattices before adding terms");
     if (c->g.pairs) return fail(c, PPQ_E_UNSUPPORTED, "the radius-sqrt(2) stencil is built for DVR dimensions only");
+    if (c->fgh[k]) return fail(c, PPQ_E_UNSUPPORTED, "lattices are built on sine-DVR dimensions only");
     if (weylets) {
         // fails early on a lattice whose symmetrized Gaussians are linearly dependent
         PPQ_TRY(c, { (void)weylet_projection(c->g.n[k], c->lo[k], c->hi[k], ns, nl); })
@@ -1869,6 +1885,22 @@ int ppq_set_stencil(ppq_ctx *c, int stencil)
     if (stencil == 2 && c->any_lattice)
         return fail(c, PPQ_E_UNSUPPORTED, "the radius-sqrt(2) stencil is built for DVR dimensions only");
     c->g.pairs = stencil == 2 ? 1 : 0;
+    return PPQ_OK;
+}
+
+int ppq_set_fgh(ppq_ctx *c, int k)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    if (k < 0 || k >= c->g.D) return fail(c, PPQ_E_ARG, "dimension out of range");
+    if (c->g.n[k] % 2 == 0) return fail(c, PPQ_E_ARG, "the Fourier grid needs an odd number of points");
+    if (c->lattice[k]) return fail(c, PPQ_E_UNSUPPORTED, "Fourier grids are built for DVR dimensions only");
+    if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set Fourier grids before adding terms");
+    c->fgh[k] = true;
+    c->op_dirty = true;
+    c->derived_valid = false;
+    c->v_valid = false;
+    c->v_partial = false;
     return PPQ_OK;
 }
 
@@ -2232,7 +2264,7 @@ int ppq_expect_q(ppq_ctx *c, double *q)
                 nan_mask |= 1u << k;
                 continue;
             }
-            std::vector<double> pts = sine_dvr_points(c->g.n[k], c->lo[k], c->hi[k]);
+            std::vector<double> pts = dim_points(c, k);
             std::copy(pts.begin(), pts.end(), tab.begin() + (size_t)k * NMAX_FIBER);
         }
         if (!c->qtab) c->qtab = dalloc<double>((int64_t)tab.size());

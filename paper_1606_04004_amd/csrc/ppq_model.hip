@@ -159,6 +159,29 @@ std::vector<cd> weylet_projection(int n, double lo, double hi, int nx, int np)
     return W;
 }
 
+// Kinetic energy -1/(2 mass) d^2/dx^2 on the periodic Fourier grid of n
+// (odd) points over the period hi - lo, from its spectral definition:
+// T_ij = (1/n) sum_m k_m^2 / (2 mass) cos(k_m (x_i - x_j)), k_m = 2 pi m / L,
+// |m| <= (n-1)/2.
+std::vector<double> fgh_kinetic(int n, double lo, double hi, double mass)
+{
+    const double L = hi - lo;
+    const int M = (n - 1) / 2;
+    std::vector<double> T((size_t)n * n);
+    for (int d = 0; d < n; ++d) {
+        double acc = 0.0;
+        for (int m = 1; m <= M; ++m) {
+            const double km = 2.0 * M_PI * m / L;
+            acc += 2.0 * km * km / (2.0 * mass) * std::cos(2.0 * M_PI * m * d / n);
+        }
+        for (int i = 0; i < n; ++i) T[(size_t)i * n + (i + d) % n] = acc / n;
+    }
+    // the entries depend on (i - j) mod n only and are even in it: exactly symmetric
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) T[(size_t)j * n + i] = T[(size_t)i * n + j];
+    return T;
+}
+
 bool invert(std::vector<cd> &a, int n)
 {
     std::vector<cd> inv((size_t)n * n, cd(0.0, 0.0));

@@ -1117,3 +1117,43 @@ def test_weylet_full_size_card(torch):
         d = np.max(np.abs(tg[:, col] - tr[:, col]))
         say(f"  col {col}: {d:.2e}")
         assert d < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fgh_dimensions(prec, torch):
+    """Periodic Fourier grids on two dimensions (points, kinetic matrix,
+    potential and packet on those points): products against the oracle, the
+    initial set and a 10-step trajectory; even sizes are refused."""
+    import ctypes
+    from paper_1606_04004_amd import PPQError
+    cd = card("small_3d", fgh=[0, 1])
+    o = Oracle(cd)
+    g = make(cd, torch, precision=prec)
+    q = np.zeros(cd["n"][0])
+    g.lib.ppq_get_grid(g.ctx, 0, q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert np.allclose(q, o.model.q[0], rtol=0, atol=1e-14)
+    for fill, seed in ((1.0, 1), (0.4, 2)):
+        keys = (np.arange(int(np.prod(cd["n"])), dtype=np.uint64) if fill == 1.0
+                else random_active_set(cd["n"], fill, seed))
+        x = random_complex(keys.size, seed + 40)
+        g.set_state(keys, x)
+        xs = x if prec == 0 else x.astype(np.complex64)
+        xt = torch.from_numpy(xs).cuda()
+        yt = torch.zeros_like(xt)
+        g.apply_h(xt, yt)
+        torch.cuda.synchronize()
+        ref = o.apply_def(keys, xs.astype(np.complex128))
+        err = np.max(np.abs(yt.cpu().numpy().astype(np.complex128) - ref)) / np.max(np.abs(ref))
+        say(f"fgh prec {prec} |A|={keys.size} rel err {err:.2e}")
+        assert err < (1e-13 if prec == 0 else 2e-6)
+    if prec == 0:
+        o.init_state()
+        g.init_state()
+        assert np.array_equal(g.state()[0], o.state()[0])
+        tr, _ = o.propagate(nsteps=10)
+        tg = g.propagate(nsteps=10)
+        assert np.array_equal(tg[:, 5], tr[:, 5])
+        for col in (1, 2, 3, 4, 6):
+            assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    with pytest.raises(PPQError):
+        make(card("small_3d", fgh=[2]), torch)

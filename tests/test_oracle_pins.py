@@ -167,6 +167,29 @@ def test_apply_def_pruned_equals_restricted_kronecker(n, seed, fill):
         assert np.max(np.abs(y - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("n", [5, 15, 33])
+def test_fgh_kinetic_equals_spectral_definition(n):
+    """The closed-form periodic FGH kinetic matrix equals (1/n) sum_k
+    k^2/(2m) exp(i k (x_i - x_j)) over |k| <= (n-1) pi / L."""
+    from oracle.model import fgh_grid, fgh_kinetic
+    lo, hi, mass = -2.0, 3.5, 1.7
+    x, _ = fgh_grid(n, lo, hi)
+    L = hi - lo
+    ks = 2.0 * np.pi * np.arange(-(n - 1) // 2, (n - 1) // 2 + 1) / L
+    ref = np.real(np.exp(1j * ks[None, None, :] * (x[:, None, None] - x[None, :, None]))
+                  @ (ks ** 2 / (2.0 * mass))) / n
+    assert np.max(np.abs(fgh_kinetic(n, lo, hi, mass) - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_fgh_harmonic_eigenvalues():
+    """Harmonic oscillator on a 41-point periodic Fourier grid over [-9, 9):
+    the lowest eigenvalues are k + 1/2."""
+    from oracle.model import fgh_grid, fgh_kinetic
+    x, _ = fgh_grid(41, -9.0, 9.0)
+    w = np.linalg.eigvalsh(fgh_kinetic(41, -9.0, 9.0, 1.0) + np.diag(0.5 * x * x))
+    assert np.max(np.abs(w[:8] - (np.arange(8) + 0.5))) < 1e-9
+
+
 def custom_factor_card(seed, terms=True):
     """small_3d with its own symmetric 1D matrices on dimensions 0 and 2."""
     cd = card("small_3d")

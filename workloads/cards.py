@@ -11,6 +11,8 @@ A card is a plain dict:
                                   f = {"dim": k, "kind": "power", "p": p}     (q_k**p)
                                    or {"dim": k, "kind": "morse", "a": a, "q0": q0}
                                                                   ((1-exp(-a(q_k-q0)))**2)
+  fgh (optional)                  dimensions on a periodic Fourier grid (odd n_k) instead
+                                  of the sine-DVR
   dim_factors (optional)          {k: n_k x n_k real symmetric matrix} replacing the
                                   sine-DVR kinetic matrix of dimension k
   psi0                            product Gaussian: centre, momentum, width per dim
