@@ -156,13 +156,18 @@ def accuracy_sweep(stream):
     for the projected von Neumann and projected Weylet lattices (6 x 8 per
     dimension); the exact run keeps the full DVR grid without adaption (all
     three bases are similarity transforms of it)."""
+    import torch
     import paper_1606_04004_amd as ppq
     from workloads import card
     cd = card("hh2d")
     total = int(np.prod(cd["n"]))
     g = ppq.Propagator(cd, precision=ppq.PPQ_FP64, device=0, stream=stream)
     g.init_state(eps=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     ref = g.propagate(prune=False)
+    torch.cuda.synchronize()
+    ms_exact = (time.perf_counter() - t0) * 1e3 / (ref.shape[0] - 1)
     c_ref = ref[:, 3] + 1j * ref[:, 4]
     del g
     rows = []
@@ -172,13 +177,18 @@ def accuracy_sweep(stream):
         for eps in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
             g = ppq.Propagator(dict(cd, **extra), precision=ppq.PPQ_FP64, device=0, stream=stream)
             g.init_state(eps=eps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             tr = g.propagate(eps=eps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
             c = tr[:, 3] + 1j * tr[:, 4]
             rows.append({"basis": basis, "stencil": stencil, "eps": eps,
                          "mean_basis_percent": float(100.0 * np.mean(tr[:, 5]) / total),
-                         "infidelity": float(np.sqrt(np.sum(np.abs(c - c_ref) ** 2)))})
+                         "infidelity": float(np.sqrt(np.sum(np.abs(c - c_ref) ** 2))),
+                         "ms_per_step": wall * 1e3 / (tr.shape[0] - 1)})
             del g
-    return rows
+    return {"exact_ms_per_step": ms_exact, "runs": rows}
 
 
 def traffic_probe(stream):
