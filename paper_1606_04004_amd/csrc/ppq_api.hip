@@ -1603,7 +1603,10 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
     if (!c) return PPQ_E_OOM;
     c->device = device;
     c->precision = precision;
-    if (const char *v = std::getenv("PPQ_HPSI")) c->hpsi_variant = std::atoi(v);
+    if (const char *v = std::getenv("PPQ_HPSI")) {
+        const int h = std::atoi(v);
+        if (h >= 0 && h <= 4) c->hpsi_variant = h;  // other values keep the default layout
+    }
     try {
         ck(hipSetDevice(device), "hipSetDevice");
         if (hip_stream) {
