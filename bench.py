@@ -97,6 +97,7 @@ def secondary(stream, steps, warmup, adjoint_steps):
     cd = card("morse4d")
     for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
+        g.reserve(min(16_000_000, int(np.prod(cd["n"]))))  # as for the headline
         g.init_state()
         g.propagate(nsteps=20)
         ms_h = g.time_apply(20)
@@ -109,6 +110,7 @@ def secondary(stream, steps, warmup, adjoint_steps):
     cd = card("pvb4d")
     for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
+        g.reserve(min(16_000_000, int(np.prod(cd["n"]))))  # as for the headline
         g.init_state()
         ms_h = g.time_apply(10)
         na = g.active_count()
@@ -120,6 +122,7 @@ def secondary(stream, steps, warmup, adjoint_steps):
     cd = dict(card("pvb4d"), basis="pw")
     for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
+        g.reserve(min(16_000_000, int(np.prod(cd["n"]))))  # as for the headline
         g.init_state()
         na = g.active_count()
         ms_h = g.time_apply(10)

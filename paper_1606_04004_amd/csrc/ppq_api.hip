@@ -326,11 +326,14 @@ void free_operator(ppq_ctx *c)
 }
 
 // (Re)allocates every per-point buffer for at least n points, keeping the
-// current keys and coefficients.
+// current keys and coefficients. A growing set doubles the capacity (never
+// past the grid size, which bounds the active set): each growth frees and
+// allocates every table, so a set that spreads over a few steps should pay
+// for that once or twice, not at every step.
 void ensure_capacity(ppq_ctx *c, int64_t n)
 {
     if (n <= c->cap) return;
-    int64_t nc = std::max<int64_t>(n, c->cap + c->cap / 4);
+    int64_t nc = std::max<int64_t>(n, std::min<int64_t>(2 * c->cap, (int64_t)c->g.total));
     nc = std::max<int64_t>(nc, 1024);
     uint32_t *nk = dalloc<uint32_t>(nc);
     double2 *np = dalloc<double2>(nc);
