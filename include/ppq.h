@@ -228,8 +228,9 @@ int ppq_apply_h(ppq_ctx *ctx, const void *x, void *y);
 
 /* One short-iterative Lanczos (Arnoldi if any lattice dimension) step of
    length dt with Krylov order m (m H-applications, full reorthogonalisation
-   by classical Gram-Schmidt applied twice), on the current set; no
-   adaption.  1 <= m <= 16. */
+   by classical Gram-Schmidt applied twice; in the Lanczos case the first
+   pass subtracts only the three-term recurrence's two projections and the
+   second pass all of them), on the current set; no adaption.  1 <= m <= 16. */
 int ppq_step(ppq_ctx *ctx, double dt, int m);
 
 /* Adaption with threshold eps (Sec. II.E, radius-1 stencil of Sec. III.A):

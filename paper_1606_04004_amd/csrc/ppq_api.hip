@@ -1201,7 +1201,13 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
             cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s);
             break;
         }
-        cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, 0, s);
+        // Hermitian: the first pass needs only alpha_j (two vectors read,
+        // not j + 2); the recurrence supplies the rest, and the second pass
+        // still orthogonalises against every v_i.
+        if (herm)
+            cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s, RED_H1L);
+        else
+            cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, 0, s);
         cgs_update_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, !last, s);
         if (last) break;
         cgs_update_scale<C>(Vb, ld, j + 1, w, Vb + (int64_t)(j + 1) * ld, n, ks, j, s);

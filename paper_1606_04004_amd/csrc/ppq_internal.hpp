@@ -229,12 +229,15 @@ void hpsi_cmfma_f32(const FiberPass &fp, const float2 *H64, const CInput32 &in, 
 // Krylov vector kernels. V_i = Vb + i*ld (elements); C is double2 or float2.
 // Reductions end in the last block to finish, which sums the per-block
 // partials in a fixed order (run-to-run deterministic) and updates KState.
-enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3 };
+// RED_H1L: Hermitian first pass, where only <v_j|w> is reduced; the other
+// first-pass coefficients are those of the three-term recurrence (beta_{j-1}
+// for v_{j-1}, zero below), and the second pass removes what they leave.
+enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3, RED_H1L = 4 };
 template <class C>
 void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, hipStream_t s);
 template <class C>
 void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
-              int j, int m, int ioff, hipStream_t s);
+              int j, int m, int ioff, hipStream_t s, int mode = RED_H1);
 template <class C>
 void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, double2 *partial, unsigned *counter,
                      KState *ks, int j, int m, bool with_norm, hipStream_t s);

@@ -862,11 +862,14 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
     if (mode == RED_NORM0) {
         ks->n0 = sqrt(r[0].x);
         ks->meff = m;
-    } else if (mode == RED_H1) {
+    } else if (mode == RED_H1 || mode == RED_H1L) {
         for (int i = 0; i < nvals; ++i) {
             ks->h1[(i + ioff) * MAXM + j] = r[i];
             if (i + ioff == j) ks->alpha[j] = r[i].x;
         }
+        if (mode == RED_H1L)
+            for (int i = 0; i < j; ++i)
+                ks->h1[i * MAXM + j] = make_double2(i == j - 1 ? ks->beta[j - 1] : 0.0, 0.0);
     } else {  // RED_H2 (+ beta from |w'|^2 - sum |h2_i|^2 when RED_BETA)
         int nh = (mode == RED_BETA) ? nvals - 1 : nvals;
         double hh = 0.0;
@@ -1814,12 +1817,12 @@ void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, K
 }
 template <class C>
 void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
-              int j, int m, int ioff, hipStream_t s)
+              int j, int m, int ioff, hipStream_t s, int mode)
 {
 #define CALL(NV)                                                                                                  \
     hipLaunchKernelGGL((k_cgs_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, counter, ks, j, \
                        m, ioff);                                                                              \
-    hipLaunchKernelGGL(k_finalize<NV>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, (int)RED_H1, m, ioff, NV)
+    hipLaunchKernelGGL(k_finalize<NV>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, mode, m, ioff, NV)
     PPQ_NV_SWITCH(nv, CALL)
 #undef CALL
 }
@@ -1861,7 +1864,7 @@ void lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, cons
 #define PPQ_INST(C)                                                                                               \
     template void norm0<C>(const double2 *, int64_t, double2 *, unsigned *, KState *, int, hipStream_t);          \
     template void cgs_dots<C>(const C *, int64_t, int, const C *, int64_t, double2 *, unsigned *, KState *, int,  \
-                              int, int, hipStream_t);                                                           \
+                              int, int, hipStream_t, int);                                                      \
     template void cgs_update_dots<C>(const C *, int64_t, int, C *, int64_t, double2 *, unsigned *, KState *, int, \
                                      int, bool, hipStream_t);                                                   \
     template void cgs_update_scale<C>(const C *, int64_t, int, const C *, C *, int64_t, const KState *, int,      \
