@@ -259,6 +259,55 @@ def test_single_step(torch):
     assert np.max(np.abs(cg - co)) < 1e-13
 
 
+
+@pytest.mark.parametrize("m", [1, 2, 3, 16])
+def test_single_step_krylov_orders(m, torch):
+    """One SIL step at the extreme Krylov orders (Sec. III.A): m = 1 is the
+    bare alpha_0 phase, m = 2 the first Lanczos recurrence, 16 the largest
+    order the library takes. The Hermitian first Gram-Schmidt pass takes
+    beta_{j-1} from the recurrence; the result must still be the oracle's."""
+    cd = card("small_4d")
+    o = Oracle(cd)
+    o.init_state()
+    keys, c = o.state()
+    g = make(cd, torch)
+    g.set_state(keys, c)
+    say(f"single SIL step small_4d, m = {m}")
+    g.step(m=m)
+    o.sil_step(m=m)
+    _, cg = g.state()
+    _, co = o.state()
+    assert np.max(np.abs(cg - co)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_krylov_space_exhausted(prec, torch):
+    """A set of 5 functions holds at most a 5-dimensional Krylov space: with
+    m = 16 the recurrence breaks down (beta below 1e-13) and the space is
+    truncated. Whatever the order at which either side stops, the coupling
+    left out is of the size of the breakdown threshold, so the steps agree
+    to 1e-12 (FP64), and to the FP32 form's 1e-6."""
+    cd = card("small_4d")
+    o = Oracle(cd)
+    o.init_state()
+    keys, c = o.state()
+    sel = np.argsort(-np.abs(c))[:5]
+    sel.sort()
+    k5, c5 = keys[sel].copy(), c[sel].copy()
+    o.set_state(k5, c5)
+    g = make(cd, torch, precision=prec)
+    g.set_state(k5, c5)
+    say(f"exhausted Krylov space: 5 functions, m = 16, precision {prec}")
+    for _ in range(3):
+        g.step(m=16)
+        o.sil_step(m=16)
+    kg, cg = g.state()
+    ko, co = o.state()
+    assert np.array_equal(kg, ko)
+    assert np.all(np.isfinite(cg))
+    assert abs(np.vdot(co, co).real - np.vdot(c5, c5).real) < 1e-12  # unitary on the set
+    assert np.max(np.abs(cg - co)) < (1e-12 if prec == 0 else 1e-6)
+
 def test_hh2d_trajectory_sets_every_step(torch):
     """Config 1 (2D, 48x48, eps=1e-5): identical active set after every step, 200 steps."""
     cd = card("hh2d")
