@@ -763,6 +763,9 @@ __device__ inline double2 ld2(const float2 *p, int64_t i)
 }
 __device__ inline void st2(double2 *p, int64_t i, double2 v) { p[i] = v; }
 __device__ inline void st2(float2 *p, int64_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+// the value a store of v into a C vector holds, without reading it back
+__device__ inline double2 stored(const double2 *, double2 v) { return v; }
+__device__ inline double2 stored(const float2 *, double2 v) { return make_double2((float)v.x, (float)v.y); }
 
 // conj(a) * b accumulated
 __device__ inline void cdot_acc(double2 &acc, double2 a, double2 b)
@@ -943,7 +946,7 @@ __global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld,
             wv.y -= hc[i].x * vv[i].y + hc[i].y * vv[i].x;
         }
         st2(w, p, wv);
-        double2 wr = ld2(w, p);  // dots against the stored (possibly rounded) vector
+        const double2 wr = stored(w, wv);  // dots against the stored (possibly rounded) vector
 #pragma unroll
         for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], wr);
         acc[NV].x = fma(wr.x, wr.x, fma(wr.y, wr.y, acc[NV].x));
