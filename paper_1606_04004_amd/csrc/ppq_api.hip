@@ -1558,7 +1558,7 @@ void adjoint_backward(ppq_ctx *c, double2 C_N)
             // <d psi0 / d theta | psi_N>
             adj_packet(keys_of(N), c->rec_n[N], c->g, c->init_tabs, c->dtabs, c->tab_nmax, c->psi[c->cur], 1,
                        c->partial, s);
-            adj_accumulate(c->partial, 2 * D, 36, make_double2(1.0, 0.0), c->dC + c->nparam, s);
+            adj_accumulate(c->partial, 2 * D, make_double2(1.0, 0.0), c->dC + c->nparam, s);
         } else {
             // the recomputation must reproduce the stored checkpoint bit for bit
             unsigned long long nd =
@@ -1582,7 +1582,7 @@ void adjoint_backward(ppq_ctx *c, double2 C_N)
             if (c->nparam > 0) {
                 adj_reduce<C>((const C *)c->Vk, (const C *)c->Wk, c->cap, psi_n, c->mu, c->ks, c->ks_b, c->Qd,
                               keys_of(st), nn, c->g, dd, c->partial, s);
-                adj_accumulate(c->partial, c->nparam, 36, make_double2(0.0, -dt), c->dC, s);
+                adj_accumulate(c->partial, c->nparam, make_double2(0.0, -dt), c->dC, s);
             }
             // lambda_st = exp(+i H dt) mu
             krylov_expv(c->ks_b, m, -dt, 1, s);
@@ -1591,7 +1591,7 @@ void adjoint_backward(ppq_ctx *c, double2 C_N)
     }
     // <lambda_0 | d psi0 / d theta>
     adj_packet(keys_of(0), c->rec_n[0], c->g, c->init_tabs, c->dtabs, c->tab_nmax, c->lam, 0, c->partial, s);
-    adj_accumulate(c->partial, 2 * D, 36, make_double2(1.0, 0.0), c->dC + c->nparam, s);
+    adj_accumulate(c->partial, 2 * D, make_double2(1.0, 0.0), c->dC + c->nparam, s);
     ck(hipStreamSynchronize(s), "adjoint");
     (void)C_N;
 }

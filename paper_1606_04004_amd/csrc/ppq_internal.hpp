@@ -289,7 +289,7 @@ template <class C>
 void adj_reduce(const C *Vb, const C *Wb, int64_t ld, const double2 *psi, const double2 *mu, const KState *kf,
                 const KState *kb, const double2 *Q, const uint32_t *keys, int64_t n, const GridDesc &g,
                 const DerivDesc &dd, double2 *partial, hipStream_t s);
-void adj_accumulate(const double2 *partial, int nparam, int stride, double2 coef, double2 *dC, hipStream_t s);
+void adj_accumulate(const double2 *partial, int nparam, double2 coef, double2 *dC, hipStream_t s);
 void adj_packet(const uint32_t *keys, int64_t n, const GridDesc &g, const double2 *tabs, const double2 *dtabs,
                 int nmax, const double2 *vec, int bra, double2 *partial, hipStream_t s);
 unsigned long long count_diff(const double2 *a, const double2 *b, int64_t n, unsigned long long *dcount,

@@ -9,6 +9,10 @@ namespace {
 
 constexpr int TB = 256;  // threads per block for streaming kernels
 constexpr int PSTRIDE = 36;  // partial sums per block (Krylov values, adjoint parameters)
+// Per-block partial sums are stored value-major, [value][block]: the one-block
+// final reductions then read every value's partials as contiguous runs, one
+// 1 KB line group per wavefront load, instead of one cache line per lane.
+__device__ inline int64_t pidx(int64_t b, int i) { return (int64_t)i * RED_BLOCKS + b; }
 
 __device__ inline int64_t gid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
@@ -796,11 +800,11 @@ __device__ inline void block_reduce_store(double2 (&acc)[NV], double2 *partial)
             s.x += red[ww][threadIdx.x].x;
             s.y += red[ww][threadIdx.x].y;
         }
-        partial[(int64_t)blockIdx.x * PSTRIDE + threadIdx.x] = s;
+        partial[pidx(blockIdx.x, threadIdx.x)] = s;
     }
 }
 
-// Final reduction of the per-block partials [nb][PSTRIDE] by one block: every
+// Final reduction of the per-block partials [value][block] by one block: every
 // value at once, each thread a fixed subset of blocks, then a fixed tree
 // (run-to-run deterministic); then the finaliser `mode` updates KState.
 // (A separate launch: a device-scope fence per block to let the last block
@@ -822,7 +826,7 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
 #pragma unroll
         for (int u = 0; u < PER; ++u)
 #pragma unroll
-            for (int i = 0; i < NV; ++i) v[u][i] = partial[(int64_t)(threadIdx.x + u * TB) * PSTRIDE + i];
+            for (int i = 0; i < NV; ++i) v[u][i] = partial[pidx(threadIdx.x + u * TB, i)];
 #pragma unroll
         for (int u = 0; u < PER; ++u)
 #pragma unroll
@@ -834,7 +838,7 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         for (int b = threadIdx.x; b < nb; b += TB) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
-                double2 v = partial[(int64_t)b * PSTRIDE + i];
+                double2 v = partial[pidx(b, i)];
                 tot[i].x += v.x;
                 tot[i].y += v.y;
             }
@@ -1124,8 +1128,8 @@ __global__ __launch_bounds__(TB) void k_sum_partial1(const double2 *partial, int
     __shared__ double2 red[TB];
     double2 s = make_double2(0.0, 0.0);
     for (int b = threadIdx.x; b < nb; b += TB) {
-        s.x += partial[(int64_t)b * PSTRIDE].x;
-        s.y += partial[(int64_t)b * PSTRIDE].y;
+        s.x += partial[pidx(b, 0)].x;
+        s.y += partial[pidx(b, 0)].y;
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -1188,8 +1192,8 @@ __global__ __launch_bounds__(TB) void k_obs_final(const double2 *partial, int nb
     for (int i = 0; i < 3; ++i) {
         double2 s = make_double2(0.0, 0.0);
         for (int b = threadIdx.x; b < nb; b += TB) {
-            s.x += partial[(int64_t)b * PSTRIDE + i].x;
-            s.y += partial[(int64_t)b * PSTRIDE + i].y;
+            s.x += partial[pidx(b, i)].x;
+            s.y += partial[pidx(b, i)].y;
         }
         red[threadIdx.x] = s;
         __syncthreads();
@@ -1246,7 +1250,7 @@ __global__ __launch_bounds__(TB) void k_expq_final(const double2 *partial, int n
     __shared__ double norm2;
     for (int i = 0; i <= D; ++i) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += TB) s += partial[(int64_t)b * PSTRIDE + i].x;
+        for (int b = threadIdx.x; b < nb; b += TB) s += partial[pidx(b, i)].x;
         red[threadIdx.x] = s;
         __syncthreads();
         for (int st = TB / 2; st >= 1; st >>= 1) {
@@ -1304,7 +1308,7 @@ __global__ __launch_bounds__(TB) void k_energy_from_dot(const double2 *partial, 
 {
     __shared__ double red[TB];
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += TB) s += partial[(int64_t)b * PSTRIDE].x;
+    for (int b = threadIdx.x; b < nb; b += TB) s += partial[pidx(b, 0)].x;
     red[threadIdx.x] = s;
     __syncthreads();
     for (int st = TB / 2; st >= 1; st >>= 1) {
@@ -1519,15 +1523,15 @@ __global__ __launch_bounds__(TB) void k_adj_reduce(const C *Vb, const C *Wb, int
 }
 
 // dC[p] += coef * sum over blocks (fixed order), coef = -i dt
-__global__ __launch_bounds__(TB) void k_adj_accumulate(const double2 *partial, int nb, int nparam, int stride,
+__global__ __launch_bounds__(TB) void k_adj_accumulate(const double2 *partial, int nb, int nparam,
                                                        double2 coef, double2 *dC)
 {
     __shared__ double2 red[TB];
     for (int i = 0; i < nparam; ++i) {
         double2 s = make_double2(0.0, 0.0);
         for (int b = threadIdx.x; b < nb; b += TB) {
-            s.x += partial[(int64_t)b * stride + i].x;
-            s.y += partial[(int64_t)b * stride + i].y;
+            s.x += partial[pidx(b, i)].x;
+            s.y += partial[pidx(b, i)].y;
         }
         red[threadIdx.x] = s;
         __syncthreads();
@@ -1968,9 +1972,9 @@ template void adj_reduce<double2>(const double2 *, const double2 *, int64_t, con
 template void adj_reduce<float2>(const float2 *, const float2 *, int64_t, const double2 *, const double2 *,
                                  const KState *, const KState *, const double2 *, const uint32_t *, int64_t,
                                  const GridDesc &, const DerivDesc &, double2 *, hipStream_t);
-void adj_accumulate(const double2 *partial, int nparam, int stride, double2 coef, double2 *dC, hipStream_t s)
+void adj_accumulate(const double2 *partial, int nparam, double2 coef, double2 *dC, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adj_accumulate, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, nparam, stride, coef, dC);
+    hipLaunchKernelGGL(k_adj_accumulate, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, nparam, coef, dC);
 }
 void adj_packet(const uint32_t *keys, int64_t n, const GridDesc &g, const double2 *tabs, const double2 *dtabs,
                 int nmax, const double2 *vec, int bra, double2 *partial, hipStream_t s)
