@@ -171,7 +171,10 @@ int ppq_set_factor(ppq_ctx *ctx, int k, const double *h);
 int ppq_clear_potential(ppq_ctx *ctx);
 
 /* Capacity of the active set (number of functions).  Grows automatically when
-   adaption needs more; reserving ahead avoids reallocation inside a run. */
+   adaption needs more, doubling each time (never past the grid size); each
+   growth reallocates every per-point buffer, so reserving ahead avoids
+   reallocation inside a run.  PPQ_E_ARG unless 1 <= max_active <= the grid
+   size; PPQ_E_STATE without a grid. */
 int ppq_reserve(ppq_ctx *ctx, int64_t max_active);
 
 /* Initial state: product Gaussian psi0(q) = prod_k g_k(q_k),
