@@ -858,9 +858,13 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    // Every loop over r runs to the compile-time NV with a predicate: an index
+    // known only at run time would put r in scratch memory.
     double2 r[NV];
+#pragma unroll
     for (int i = 0; i < NV; ++i) {
         r[i] = vals[0][i];
+#pragma unroll
         for (int w2 = 1; w2 < TB / 64; ++w2) {
             r[i].x += vals[w2][i].x;
             r[i].y += vals[w2][i].y;
@@ -870,22 +874,30 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         ks->n0 = sqrt(r[0].x);
         ks->meff = m;
     } else if (mode == RED_H1 || mode == RED_H1L) {
-        for (int i = 0; i < nvals; ++i) {
-            ks->h1[(i + ioff) * MAXM + j] = r[i];
-            if (i + ioff == j) ks->alpha[j] = r[i].x;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nvals) {
+                ks->h1[(i + ioff) * MAXM + j] = r[i];
+                if (i + ioff == j) ks->alpha[j] = r[i].x;
+            }
         }
         if (mode == RED_H1L)
             for (int i = 0; i < j; ++i)
                 ks->h1[i * MAXM + j] = make_double2(i == j - 1 ? ks->beta[j - 1] : 0.0, 0.0);
     } else {  // RED_H2 (+ beta from |w'|^2 - sum |h2_i|^2 when RED_BETA)
-        int nh = (mode == RED_BETA) ? nvals - 1 : nvals;
-        double hh = 0.0;
-        for (int i = 0; i < nh; ++i) {
-            ks->h2[i * MAXM + j] = r[i];
-            hh += r[i].x * r[i].x + r[i].y * r[i].y;
+        const int nh = (mode == RED_BETA) ? nvals - 1 : nvals;
+        double hh = 0.0, last = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nh) {
+                ks->h2[i * MAXM + j] = r[i];
+                hh += r[i].x * r[i].x + r[i].y * r[i].y;
+            } else if (i == nh) {
+                last = r[i].x;
+            }
         }
         if (mode == RED_BETA) {
-            double b2 = r[nh].x - hh;
+            double b2 = last - hh;
             double b = sqrt(b2 > 0.0 ? b2 : 0.0);
             ks->beta[j] = b;
             if (j < m - 1) {
