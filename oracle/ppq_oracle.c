@@ -25,7 +25,8 @@
  *                      classical Gram-Schmidt applied twice.
  *   orc_prune       -- basis adaption (Sec. II.E): keep |a| >= theta, add the
  *                      2D nearest neighbours (phase-space ball radius 1,
- *                      Sec. III.A), hash set of used functions, then sort.
+ *                      Sec. III.A; radius sqrt(2) and 2 on request), hash set
+ *                      of used functions, then sort.
  *   orc_observe     -- norm, energy, autocorrelation C(t) (Eq. acorr),
  *                      number of used / above-threshold functions.
  */
@@ -57,7 +58,7 @@ typedef struct orc_model {
     int *pk1, *pk2;             /* applied as coef * h1(k1) (h2(k2) x), k2 first */
     zd **ph1, **ph2;
     int lat_s[ORC_MAXD], lat_l[ORC_MAXD]; /* phase-space lattice shape per dim; 0 = line */
-    int stencil;                /* adaption neighbours: 1 = ball radius 1, 2 = radius sqrt(2) */
+    int stencil;                /* adaption neighbours: 1 = ball radius 1, 2 = radius sqrt(2), 3 = radius 2 */
 } orc_model;
 
 orc_model *orc_new(int D, const int32_t *n)
@@ -695,13 +696,33 @@ static void insert_with_neighbours(const orc_model *m, keyset *set, uint64_t key
                         if (dk < 0 || dk >= m->n[k] || dl < 0 || dl >= m->n[l]) continue;
                         ks_insert(set, key + (int64_t)a * (int64_t)m->stride[k] + (int64_t)b * (int64_t)m->stride[l]);
                     }
+    /* ball radius 2 (Sec. III.A): every combination of index changes of
+       -1, 0 or +1 in each dimension, 3^D - 1 neighbours (DVR dimensions);
+       the combinations are counted in base 3, one digit per dimension */
+    if (m->stencil == 3) {
+        int ncomb = 1;
+        for (int k = 0; k < m->D; ++k) ncomb *= 3;
+        for (int c = 0; c < ncomb; ++c) {
+            int rest = c, inside = 1;
+            int64_t shift = 0;
+            for (int k = 0; k < m->D; ++k) {
+                int a = rest % 3 - 1;
+                rest /= 3;
+                int dk = digit(m, key, k) + a;
+                if (dk < 0 || dk >= m->n[k]) inside = 0;
+                shift += (int64_t)a * (int64_t)m->stride[k];
+            }
+            if (inside) ks_insert(set, (uint64_t)((int64_t)key + shift));
+        }
+    }
 }
 
-/* Selects the adaption stencil (1: radius 1; 2: radius sqrt(2), DVR only). */
+/* Selects the adaption stencil (1: radius 1; 2: radius sqrt(2); 3: radius 2;
+   2 and 3 on DVR dimensions only). */
 int orc_set_stencil(orc_model *m, int stencil)
 {
-    if (stencil != 1 && stencil != 2) return -1;
-    if (stencil == 2)
+    if (stencil < 1 || stencil > 3) return -1;
+    if (stencil >= 2)
         for (int k = 0; k < m->D; ++k)
             if (m->lat_s[k]) return -1;
     m->stencil = stencil;

@@ -624,6 +624,60 @@ def test_prune_radius_sqrt2_stencil():
                         stencil=2))
 
 
+
+def dilate_moore(n, keys, c, eps):
+    """Ball radius 2 by morphology: the kept functions as a boolean grid,
+    dilated with the full 3^D structuring element (scipy), i.e. every grid
+    point within Chebyshev distance 1 of a kept one."""
+    from scipy.ndimage import binary_dilation
+    kept = np.zeros(int(np.prod(n)), dtype=bool)
+    k2 = c.real * c.real + c.imag * c.imag
+    kept[keys[k2 >= eps * eps].astype(np.int64)] = True
+    grown = binary_dilation(kept.reshape(n), structure=np.ones((3,) * len(n), dtype=bool))
+    return np.flatnonzero(grown.ravel()).astype(np.uint64)
+
+
+def test_prune_radius2_stencil():
+    """Sec. III.A's most conservative stencil (ball radius 2): every
+    combination of index changes, 3^D - 1 neighbours of an interior point,
+    2^D - 1 of a corner; adversarial states against a morphological dilation
+    of the kept set by the full 3^D block (scipy)."""
+    for name in ("small_3d", "small_4d"):
+        cd = card(name, stencil=3)
+        o = orc.Oracle(cd)
+        n = cd["n"]
+        D = len(n)
+        for idx, want in (([v // 2 for v in n], 3 ** D), ([0] * D, 2 ** D), ([v - 1 for v in n], 2 ** D)):
+            key = np.ravel_multi_index(idx, n)
+            o.set_state(np.array([key], dtype=np.uint64), np.array([1.0 + 0j]))
+            o.prune(eps=0.5)
+            assert o.state()[0].size == want, (name, idx)
+    cd = card("small_3d", stencil=3)
+    o = orc.Oracle(cd)
+    for seed in (1, 2):
+        keys, c = adversarial_prune_state(o, seed)
+        o.set_state(keys, c)
+        o.prune(eps=1e-3)
+        k2, c2 = o.state()
+        assert np.array_equal(k2, dilate_moore(o.n, keys, c, 1e-3))
+        lookup = dict(zip(keys.tolist(), c))
+        assert np.array_equal(c2, np.array([lookup.get(k, 0j) for k in k2.tolist()]))
+    # radius 2 contains radius sqrt(2), which contains radius 1
+    keys, c = adversarial_prune_state(o, 3)
+    sets = []
+    for st in (1, 2, 3):
+        oo = orc.Oracle(card("small_3d", stencil=st))
+        oo.set_state(keys, c)
+        oo.prune(eps=1e-3)
+        sets.append(set(oo.state()[0].tolist()))
+    assert sets[0] < sets[1] < sets[2]
+    for bad in (0, 4):
+        with pytest.raises(ValueError):
+            orc.Oracle(card("small_3d", stencil=bad))
+    with pytest.raises(ValueError):
+        orc.Oracle(card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0],
+                        stencil=3))
+
 def test_prune_lattice_stencil_matches_bruteforce():
     cd = card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0])
     o = orc.Oracle(cd)
