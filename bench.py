@@ -155,8 +155,9 @@ def accuracy_sweep(stream):
     """The paper's accuracy measure on the 2D card (Sec. III.A): the
     infidelity of C(t), sqrt(sum_n |C_pruned(t_n) - C_exact(t_n)|^2) over all
     201 records, against the mean number of functions used (percent of the
-    48^2 grid), per threshold, for the DVR with either neighbour stencil and
-    for the projected von Neumann and projected Weylet lattices (6 x 8 per
+    48^2 grid), per threshold, for the DVR with each of the three neighbour
+    stencils (ball radius 1, sqrt(2), 2) and for the projected von Neumann
+    and projected Weylet lattices (6 x 8 per
     dimension); the exact run keeps the full DVR grid without adaption (all
     three bases are similarity transforms of it)."""
     import torch
@@ -174,7 +175,7 @@ def accuracy_sweep(stream):
     c_ref = ref[:, 3] + 1j * ref[:, 4]
     del g
     rows = []
-    variants = (("dvr", 1, {}), ("dvr", 2, {"stencil": 2}),
+    variants = (("dvr", 1, {}), ("dvr", 2, {"stencil": 2}), ("dvr", 3, {"stencil": 3}),
                 ("pvb", 1, {"basis": "pvb", "lattice": [6, 8]}), ("pw", 1, {"basis": "pw", "lattice": [6, 8]}))
     for basis, stencil, extra in variants:
         for eps in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):

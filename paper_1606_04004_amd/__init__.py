@@ -98,8 +98,8 @@ class Propagator:
         return dims, kinds, params, tables
 
     def set_stencil(self, stencil):
-        """Adaption stencil: 1 (ball radius 1, 2D neighbours) or 2 (radius
-        sqrt(2), 2D^2 neighbours)."""
+        """Adaption stencil: 1 (ball radius 1, 2D neighbours), 2 (radius
+        sqrt(2), 2D^2 neighbours) or 3 (radius 2, 3^D - 1 neighbours)."""
         self._call("ppq_set_stencil", int(stencil))
 
     def set_factor(self, k, h):

@@ -25,7 +25,8 @@ struct GridDesc {
     int lat_l[MAXD];
     uint32_t total;
     int pairs;              // adaption stencil: 0 = +-1 in one dimension (2D neighbours),
-                            // 1 = also +-1 in two dimensions at once (2D^2 neighbours)
+                            // 1 = also +-1 in two dimensions at once (2D^2 neighbours),
+                            // 2 = every combination of -1/0/+1 changes (3^D - 1)
 };
 
 // Diagonal potential as a sum of products of 1D tables.

@@ -61,9 +61,40 @@ __device__ inline void set_bit_wave(uint64_t *bm, uint32_t key, bool valid)
     if (valid && last) atomicOr((unsigned long long *)&bm[w], (unsigned long long)bits);
 }
 
-// Marks `key` and its radius-1 neighbours for lanes with `keep` (wave-collective).
+// Marks `key` and its neighbours of the selected stencil for lanes with `keep`
+// (wave-collective: every lane runs the same loop bounds).
 __device__ inline void set_with_neighbours(const GridDesc &g, uint64_t *bm, uint32_t key, bool keep)
 {
+    if (g.pairs == 2) {
+        // ball radius 2 (Sec. III.A, DVR dimensions): every combination of
+        // -1/0/+1 index changes, the key itself included; the combinations
+        // are counted in base 3, one digit per dimension.  A wavefront with
+        // nothing to keep skips the 3^D combinations (the test is uniform
+        // across its lanes, so the collective calls stay in step).
+        if (__ballot(keep) == 0) return;
+        int dg[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) dg[k] = k < g.D ? (int)((key / g.stride[k]) % (uint32_t)g.n[k]) : 0;
+        int ncomb = 1;
+        for (int k = 0; k < g.D; ++k) ncomb *= 3;
+        for (int cmb = 0; cmb < ncomb; ++cmb) {
+            int rest = cmb;
+            bool inside = keep;
+            int64_t shift = 0;
+#pragma unroll
+            for (int k = 0; k < MAXD; ++k) {
+                if (k < g.D) {
+                    const int a = rest % 3 - 1;
+                    rest /= 3;
+                    const int dk = dg[k] + a;
+                    inside = inside && dk >= 0 && dk < g.n[k];
+                    shift += (int64_t)a * (int64_t)g.stride[k];
+                }
+            }
+            set_bit_wave(bm, (uint32_t)((int64_t)key + shift), inside);
+        }
+        return;
+    }
     set_bit_wave(bm, key, keep);
     for (int k = 0; k < g.D; ++k) {
         uint32_t sk = g.stride[k];

@@ -1078,6 +1078,44 @@ def test_radius_sqrt2_stencil(name, torch):
         gl.set_stencil(2)
 
 
+
+@pytest.mark.parametrize("name", ["small_3d", "small_4d", "small_6d"])
+def test_radius2_stencil(name, torch):
+    """Ball radius 2 (every combination of -1/0/+1 changes, 3^D - 1
+    neighbours): adaption bit-exact on adversarial states, the same initial
+    set, a 10-step trajectory; stencils outside 1..3, and stencil 3 on a
+    lattice, are refused."""
+    from paper_1606_04004_amd import PPQError
+    cd = card(name, stencil=3)
+    o = Oracle(cd)
+    g = make(cd, torch)
+    for seed in (1, 2):
+        keys = random_active_set(o.n, 0.3, seed)
+        rng = np.random.default_rng(seed)
+        c = random_complex(keys.size, seed) * np.exp(rng.uniform(-12, 0, keys.size))
+        c[::17] = 1e-3
+        say(f"radius 2 {name} seed {seed} |A|={keys.size}")
+        o.set_state(keys, c)
+        nab = o.prune(eps=1e-3)
+        g.set_state(keys, c)
+        assert g.prune(eps=1e-3)[1] == nab
+        assert np.array_equal(g.state()[0], o.state()[0])
+        assert np.array_equal(g.state()[1], o.state()[1])
+    o.init_state()
+    g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=10)
+    tg = g.propagate(nsteps=10)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 2, 3, 4, 6):
+        assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    for bad in (0, 4):
+        with pytest.raises(PPQError):
+            g.set_stencil(bad)
+    gl = make(lattice_card(), torch)
+    with pytest.raises(PPQError):
+        gl.set_stencil(3)
+
 def test_acf_doubled(torch):
     """C(2t) = sum c^2: the oracle's on the same state (1e-13), and, unpruned
     with a real packet, the C(t) record at twice the time (1e-9)."""
