@@ -147,7 +147,7 @@ class Oracle:
             for k in range(self.D):
                 L.orc_set_lattice(self._m, k, ns, nl)
         if card.get("stencil", 1) != 1 and L.orc_set_stencil(self._m, int(card["stencil"])) != 0:
-            raise ValueError("stencil must be 1, 2 or 3; 2 and 3 are defined for DVR dimensions only")
+            raise ValueError("stencil must be 1, 2 or 3")
         self.arnoldi = 1 if m.pvb else 0
         self._init_tabs = self._pack(m.init_tables())
         self._bra_tabs = self._pack(m.bra_tables())

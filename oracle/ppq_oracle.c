@@ -666,6 +666,31 @@ static int above(zd c, double eps2)
     return s >= eps2;
 }
 
+/* Phase-space axes of a function: one per DVR dimension (its grid index),
+   two per lattice dimension (the cell index s and the level l of its (s, l)
+   pair).  Fills each axis' index, extent and key stride; returns the count. */
+static int phase_axes(const orc_model *m, uint64_t key, int *idx, int *ext, int64_t *str)
+{
+    int na = 0;
+    for (int k = 0; k < m->D; ++k) {
+        int d = digit(m, key, k);
+        if (m->lat_s[k] == 0) {
+            idx[na] = d;
+            ext[na] = m->n[k];
+            str[na++] = (int64_t)m->stride[k];
+        } else {
+            int nl = m->lat_l[k];
+            idx[na] = d / nl;
+            ext[na] = m->lat_s[k];
+            str[na++] = (int64_t)nl * (int64_t)m->stride[k];
+            idx[na] = d % nl;
+            ext[na] = nl;
+            str[na++] = (int64_t)m->stride[k];
+        }
+    }
+    return na;
+}
+
 /* inserts key and its nearest neighbours (line: +-1; lattice: (s+-1,l), (s,l+-1)) */
 static void insert_with_neighbours(const orc_model *m, keyset *set, uint64_t key)
 {
@@ -685,46 +710,47 @@ static void insert_with_neighbours(const orc_model *m, keyset *set, uint64_t key
             if (l + 1 < nl) ks_insert(set, key + sk);
         }
     }
-    /* ball radius sqrt(2) (Sec. III.A): a change of +-1 in two dimensions at
-       once as well, 2D^2 neighbours in all (DVR dimensions) */
+    if (m->stencil == 1) return;
+    /* the wider balls of Sec. III.A count index changes in phase space: the
+       grid index of each DVR dimension and the cell and level indices of
+       each lattice dimension are separate axes */
+    int idx[2 * ORC_MAXD], ext[2 * ORC_MAXD];
+    int64_t str[2 * ORC_MAXD];
+    int na = phase_axes(m, key, idx, ext, str);
+    /* ball radius sqrt(2): +-1 on two axes at once as well (2D^2 neighbours
+       on a DVR grid) */
     if (m->stencil == 2)
-        for (int k = 0; k < m->D; ++k)
-            for (int l = k + 1; l < m->D; ++l)
-                for (int a = -1; a <= 1; a += 2)
-                    for (int b = -1; b <= 1; b += 2) {
-                        int dk = digit(m, key, k) + a, dl = digit(m, key, l) + b;
-                        if (dk < 0 || dk >= m->n[k] || dl < 0 || dl >= m->n[l]) continue;
-                        ks_insert(set, key + (int64_t)a * (int64_t)m->stride[k] + (int64_t)b * (int64_t)m->stride[l]);
+        for (int a = 0; a < na; ++a)
+            for (int b = a + 1; b < na; ++b)
+                for (int da = -1; da <= 1; da += 2)
+                    for (int db = -1; db <= 1; db += 2) {
+                        if (idx[a] + da < 0 || idx[a] + da >= ext[a] || idx[b] + db < 0 || idx[b] + db >= ext[b])
+                            continue;
+                        ks_insert(set, (uint64_t)((int64_t)key + da * str[a] + db * str[b]));
                     }
-    /* ball radius 2 (Sec. III.A): every combination of index changes of
-       -1, 0 or +1 in each dimension, 3^D - 1 neighbours (DVR dimensions);
-       the combinations are counted in base 3, one digit per dimension */
+    /* ball radius 2: every combination of -1/0/+1 changes over the axes
+       (3^D - 1 neighbours on a DVR grid); combinations counted in base 3 */
     if (m->stencil == 3) {
         int ncomb = 1;
-        for (int k = 0; k < m->D; ++k) ncomb *= 3;
+        for (int a = 0; a < na; ++a) ncomb *= 3;
         for (int c = 0; c < ncomb; ++c) {
             int rest = c, inside = 1;
             int64_t shift = 0;
-            for (int k = 0; k < m->D; ++k) {
-                int a = rest % 3 - 1;
+            for (int a = 0; a < na; ++a) {
+                int da = rest % 3 - 1;
                 rest /= 3;
-                int dk = digit(m, key, k) + a;
-                if (dk < 0 || dk >= m->n[k]) inside = 0;
-                shift += (int64_t)a * (int64_t)m->stride[k];
+                if (idx[a] + da < 0 || idx[a] + da >= ext[a]) inside = 0;
+                shift += da * str[a];
             }
             if (inside) ks_insert(set, (uint64_t)((int64_t)key + shift));
         }
     }
 }
 
-/* Selects the adaption stencil (1: radius 1; 2: radius sqrt(2); 3: radius 2;
-   2 and 3 on DVR dimensions only). */
+/* Selects the adaption stencil (1: radius 1; 2: radius sqrt(2); 3: radius 2). */
 int orc_set_stencil(orc_model *m, int stencil)
 {
     if (stencil < 1 || stencil > 3) return -1;
-    if (stencil >= 2)
-        for (int k = 0; k < m->D; ++k)
-            if (m->lat_s[k]) return -1;
     m->stencil = stencil;
     return 0;
 }

@@ -619,9 +619,6 @@ def test_prune_radius_sqrt2_stencil():
         o.set_state(keys, c)
         o.prune(eps=1e-3)
         assert np.array_equal(o.state()[0], brute_adapt_pairs(o.n, keys, c, 1e-3))
-    with pytest.raises(ValueError):
-        orc.Oracle(card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0],
-                        stencil=2))
 
 
 
@@ -674,19 +671,55 @@ def test_prune_radius2_stencil():
     for bad in (0, 4):
         with pytest.raises(ValueError):
             orc.Oracle(card("small_3d", stencil=bad))
-    with pytest.raises(ValueError):
-        orc.Oracle(card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0],
-                        stencil=3))
 
-def test_prune_lattice_stencil_matches_bruteforce():
-    cd = card("small_2d", n=[12, 12], basis="pvb", lattice=[3, 4], lo=[-5.0, -5.0], hi=[5.0, 5.0])
-    o = orc.Oracle(cd)
-    keys = random_active_set(o.n, 0.3, 9)
-    c = random_complex(keys.size, 9) * 1e-3
-    o.set_state(keys, c)
-    o.prune(eps=1e-3)
-    k2, _ = o.state()
-    assert np.array_equal(k2, brute_adapt(o.n, keys, c, 1e-3, lattice=(3, 4)))
+
+def dilate_phase_space(shape, keys, c, eps, max_changes):
+    """Adaption in phase space by morphology: the kept functions as a boolean
+    array over the phase-space axes (the flat key reshaped to `shape`, which
+    splits each lattice dimension into its cell and level indices), dilated
+    by the block {-1, 0, 1}^axes restricted to at most `max_changes` nonzero
+    entries (1: radius 1, 2: radius sqrt(2), all axes: radius 2)."""
+    import itertools
+    from scipy.ndimage import binary_dilation
+    na = len(shape)
+    st = np.zeros((3,) * na, dtype=bool)
+    for off in itertools.product((0, 1, 2), repeat=na):
+        if sum(o != 1 for o in off) <= max_changes:
+            st[off] = True
+    kept = np.zeros(int(np.prod(shape)), dtype=bool)
+    k2 = c.real * c.real + c.imag * c.imag
+    kept[keys[k2 >= eps * eps].astype(np.int64)] = True
+    grown = binary_dilation(kept.reshape(shape), structure=st)
+    return np.flatnonzero(grown.ravel()).astype(np.uint64)
+
+
+@pytest.mark.parametrize("stencil", [1, 2, 3])
+def test_prune_stencils_on_lattices(stencil):
+    """The three balls of Sec. III.A counted in phase space: on 2D lattices
+    (3 cells x 4 levels, and 4 x 3, per dimension) the adapted set equals a
+    scipy dilation over the four phase-space axes, with carried
+    coefficients; a single interior function gets 1 + 2A, 1 + 2A^2 and 3^A
+    functions for A = 4 axes."""
+    for ns, nl in ((3, 4), (4, 3)):
+        cd = card("small_2d", n=[12, 12], basis="pvb", lattice=[ns, nl], lo=[-5.0, -5.0], hi=[5.0, 5.0],
+                  stencil=stencil)
+        o = orc.Oracle(cd)
+        shape = [ns, nl, ns, nl]
+        na = len(shape)
+        for seed in (1, 2):
+            keys = random_active_set(o.n, 0.3, seed)
+            rng = np.random.default_rng(seed)
+            c = random_complex(keys.size, seed) * np.exp(rng.uniform(-12, 0, keys.size))
+            o.set_state(keys, c)
+            o.prune(eps=1e-3)
+            k2, c2 = o.state()
+            assert np.array_equal(k2, dilate_phase_space(shape, keys, c, 1e-3, {1: 1, 2: 2, 3: na}[stencil]))
+            lookup = dict(zip(keys.tolist(), c))
+            assert np.array_equal(c2, np.array([lookup.get(k, 0j) for k in k2.tolist()]))
+        centre = np.ravel_multi_index([1, 1, 1, 1], shape)
+        o.set_state(np.array([centre], dtype=np.uint64), np.array([1.0 + 0j]))
+        o.prune(eps=0.5)
+        assert o.state()[0].size == {1: 1 + 2 * na, 2: 1 + 2 * na * na, 3: 3 ** na}[stencil]
 
 
 def test_prune_edge_cases():
