@@ -244,13 +244,14 @@ int ppq_step(ppq_ctx *ctx, double dt, int m);
 int ppq_prune(ppq_ctx *ctx, double eps, int64_t *n_active, int64_t *n_above);
 
 /* Neighbour stencil of every later adaption and of the initial set
-   (Sec. III.A): 1 (default) adds the 2D nearest neighbours, +-1 in one
-   dimension (ball radius 1); 2 also adds every change of +-1 in two
-   dimensions at once, 2D^2 neighbours in all (ball radius sqrt(2)); 3 adds
-   every combination of -1/0/+1 changes over all dimensions, 3^D - 1
-   neighbours (ball radius 2).  The paper finds radius 1 best and uses it
-   throughout.  Stencils 2 and 3 are built for DVR dimensions only
-   (PPQ_E_UNSUPPORTED with lattice dimensions); PPQ_E_ARG for other values. */
+   (Sec. III.A), counted over the phase-space axes: one per DVR dimension
+   (its grid index), two per lattice dimension (the cell and the level of
+   its (s, l) pair).  1 (default) adds +-1 on one axis (ball radius 1: 2D
+   neighbours on a DVR grid, (s+-1, l) and (s, l+-1) on a lattice); 2 also
+   adds every change of +-1 on two axes at once (ball radius sqrt(2), 2A^2
+   neighbours for A axes); 3 adds every combination of -1/0/+1 changes over
+   all axes, 3^A - 1 neighbours (ball radius 2).  The paper finds radius 1
+   best and uses it throughout.  PPQ_E_ARG for other values. */
 int ppq_set_stencil(ppq_ctx *ctx, int stencil);
 
 /* Relative exclusion threshold r >= 0 of every later adaption (ppq_prune,

@@ -1790,7 +1790,6 @@ static int set_lattice_kind(ppq_ctx *c, int k, int ns, int nl, bool weylets)
     if (k < 0 || k >= c->g.D || ns < 1 || nl < 1 || ns * nl != c->g.n[k])
         return fail(c, PPQ_E_ARG, "lattice shape must satisfy n_s * n_l == n[k]");
     if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set lattices before adding terms");
-    if (c->g.pairs) return fail(c, PPQ_E_UNSUPPORTED, "stencils 2 and 3 are built for DVR dimensions only");
     if (c->fgh[k]) return fail(c, PPQ_E_UNSUPPORTED, "lattices are built on sine-DVR dimensions only");
     if (weylets) {
         // fails early on a lattice whose symmetrized Gaussians are linearly dependent
@@ -1894,8 +1893,6 @@ int ppq_set_stencil(ppq_ctx *c, int stencil)
     PPQ_GUARD(c)
     if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
     if (stencil < 1 || stencil > 3) return fail(c, PPQ_E_ARG, "stencil must be 1, 2 or 3");
-    if (stencil >= 2 && c->any_lattice)
-        return fail(c, PPQ_E_UNSUPPORTED, "stencils 2 and 3 are built for DVR dimensions only");
     c->g.pairs = stencil - 1;
     return PPQ_OK;
 }

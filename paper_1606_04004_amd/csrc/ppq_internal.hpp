@@ -24,9 +24,10 @@ struct GridDesc {
     int lat_s[MAXD];        // phase-space lattice shape; lat_s == 0 -> +-1 line stencil
     int lat_l[MAXD];
     uint32_t total;
-    int pairs;              // adaption stencil: 0 = +-1 in one dimension (2D neighbours),
-                            // 1 = also +-1 in two dimensions at once (2D^2 neighbours),
-                            // 2 = every combination of -1/0/+1 changes (3^D - 1)
+    int pairs;              // adaption stencil over the phase-space axes (one per DVR
+                            // dimension, cell and level per lattice one): 0 = +-1 on one
+                            // axis, 1 = also +-1 on two axes at once, 2 = every
+                            // combination of -1/0/+1 changes
 };
 
 // Diagonal potential as a sum of products of 1D tables.

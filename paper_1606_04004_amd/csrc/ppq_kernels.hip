@@ -61,34 +61,57 @@ __device__ inline void set_bit_wave(uint64_t *bm, uint32_t key, bool valid)
     if (valid && last) atomicOr((unsigned long long *)&bm[w], (unsigned long long)bits);
 }
 
+// Phase-space axis `part` of dimension k for `key`: the grid index of a DVR
+// dimension (part 0), or the cell (part 0) and level (part 1) index of a
+// lattice dimension; its index, extent and key stride.
+__device__ inline void phase_axis(const GridDesc &g, uint32_t key, int k, int part, int &idx, int &ext, int64_t &str)
+{
+    const int d = (int)((key / g.stride[k]) % (uint32_t)g.n[k]);
+    if (g.lat_s[k] == 0) {
+        idx = d;
+        ext = g.n[k];
+        str = g.stride[k];
+    } else if (part == 0) {
+        idx = d / g.lat_l[k];
+        ext = g.lat_s[k];
+        str = (int64_t)g.lat_l[k] * g.stride[k];
+    } else {
+        idx = d % g.lat_l[k];
+        ext = g.lat_l[k];
+        str = g.stride[k];
+    }
+}
+
 // Marks `key` and its neighbours of the selected stencil for lanes with `keep`
-// (wave-collective: every lane runs the same loop bounds).
+// (wave-collective: every lane runs the same loop bounds, which depend on the
+// grid alone).  The wider balls of Sec. III.A count index changes over the
+// phase-space axes: one per DVR dimension, two (cell, level) per lattice one.
 __device__ inline void set_with_neighbours(const GridDesc &g, uint64_t *bm, uint32_t key, bool keep)
 {
     if (g.pairs == 2) {
-        // ball radius 2 (Sec. III.A, DVR dimensions): every combination of
-        // -1/0/+1 index changes, the key itself included; the combinations
-        // are counted in base 3, one digit per dimension.  A wavefront with
-        // nothing to keep skips the 3^D combinations (the test is uniform
-        // across its lanes, so the collective calls stay in step).
+        // ball radius 2: every combination of -1/0/+1 changes over the axes,
+        // the key itself included; the combinations are counted in base 3,
+        // one digit per axis.  A wavefront with nothing to keep skips them
+        // (the test is uniform across its lanes, so the collective calls
+        // stay in step).
         if (__ballot(keep) == 0) return;
-        int dg[MAXD];
-#pragma unroll
-        for (int k = 0; k < MAXD; ++k) dg[k] = k < g.D ? (int)((key / g.stride[k]) % (uint32_t)g.n[k]) : 0;
+        int naxes = 0;
+        for (int k = 0; k < g.D; ++k) naxes += g.lat_s[k] ? 2 : 1;
         int ncomb = 1;
-        for (int k = 0; k < g.D; ++k) ncomb *= 3;
+        for (int a = 0; a < naxes; ++a) ncomb *= 3;
         for (int cmb = 0; cmb < ncomb; ++cmb) {
             int rest = cmb;
             bool inside = keep;
             int64_t shift = 0;
-#pragma unroll
-            for (int k = 0; k < MAXD; ++k) {
-                if (k < g.D) {
+            for (int k = 0; k < g.D; ++k) {
+                for (int part = 0; part < (g.lat_s[k] ? 2 : 1); ++part) {
+                    int idx, ext;
+                    int64_t str;
+                    phase_axis(g, key, k, part, idx, ext, str);
                     const int a = rest % 3 - 1;
                     rest /= 3;
-                    const int dk = dg[k] + a;
-                    inside = inside && dk >= 0 && dk < g.n[k];
-                    shift += (int64_t)a * (int64_t)g.stride[k];
+                    inside = inside && idx + a >= 0 && idx + a < ext;
+                    shift += a * str;
                 }
             }
             set_bit_wave(bm, (uint32_t)((int64_t)key + shift), inside);
@@ -111,20 +134,25 @@ __device__ inline void set_with_neighbours(const GridDesc &g, uint64_t *bm, uint
             set_bit_wave(bm, key + sk, keep && l + 1 < nl);
         }
     }
-    // radius sqrt(2) (Sec. III.A): also every change of +-1 in two dimensions
-    // at once (DVR dimensions only)
-    if (g.pairs) {
+    // ball radius sqrt(2): also every change of +-1 on two axes at once
+    if (g.pairs == 1) {
         for (int k = 0; k < g.D; ++k) {
-            const uint32_t sk = g.stride[k];
-            const int dk = (int)((key / sk) % (uint32_t)g.n[k]);
-            for (int l = k + 1; l < g.D; ++l) {
-                const uint32_t sl = g.stride[l];
-                const int dl = (int)((key / sl) % (uint32_t)g.n[l]);
-                const bool kd = dk > 0, ku = dk + 1 < g.n[k], ld = dl > 0, lu = dl + 1 < g.n[l];
-                set_bit_wave(bm, key - sk - sl, keep && kd && ld);
-                set_bit_wave(bm, key - sk + sl, keep && kd && lu);
-                set_bit_wave(bm, key + sk - sl, keep && ku && ld);
-                set_bit_wave(bm, key + sk + sl, keep && ku && lu);
+            for (int pk = 0; pk < (g.lat_s[k] ? 2 : 1); ++pk) {
+                int ia, ea;
+                int64_t sa;
+                phase_axis(g, key, k, pk, ia, ea, sa);
+                for (int l = k; l < g.D; ++l) {
+                    for (int pl = (l == k ? pk + 1 : 0); pl < (g.lat_s[l] ? 2 : 1); ++pl) {
+                        int ib, eb;
+                        int64_t sb;
+                        phase_axis(g, key, l, pl, ib, eb, sb);
+                        const bool ad = ia > 0, au = ia + 1 < ea, bd = ib > 0, bu = ib + 1 < eb;
+                        set_bit_wave(bm, (uint32_t)((int64_t)key - sa - sb), keep && ad && bd);
+                        set_bit_wave(bm, (uint32_t)((int64_t)key - sa + sb), keep && ad && bu);
+                        set_bit_wave(bm, (uint32_t)((int64_t)key + sa - sb), keep && au && bd);
+                        set_bit_wave(bm, (uint32_t)((int64_t)key + sa + sb), keep && au && bu);
+                    }
+                }
             }
         }
     }

@@ -1049,7 +1049,6 @@ def test_custom_dim_factors(prec, torch):
 def test_radius_sqrt2_stencil(name, torch):
     """Ball radius sqrt(2) (2D^2 neighbours): adaption bit-exact on adversarial
     states, the same initial set, and a 10-step trajectory."""
-    from paper_1606_04004_amd import PPQError
     cd = card(name, stencil=2)
     o = Oracle(cd)
     g = make(cd, torch)
@@ -1073,9 +1072,6 @@ def test_radius_sqrt2_stencil(name, torch):
     assert np.array_equal(tg[:, 5], tr[:, 5])
     for col in (1, 2, 3, 4, 6):
         assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
-    gl = make(lattice_card(), torch)
-    with pytest.raises(PPQError):
-        gl.set_stencil(2)
 
 
 
@@ -1083,8 +1079,7 @@ def test_radius_sqrt2_stencil(name, torch):
 def test_radius2_stencil(name, torch):
     """Ball radius 2 (every combination of -1/0/+1 changes, 3^D - 1
     neighbours): adaption bit-exact on adversarial states, the same initial
-    set, a 10-step trajectory; stencils outside 1..3, and stencil 3 on a
-    lattice, are refused."""
+    set, a 10-step trajectory; stencils outside 1..3 are refused."""
     from paper_1606_04004_amd import PPQError
     cd = card(name, stencil=3)
     o = Oracle(cd)
@@ -1112,9 +1107,39 @@ def test_radius2_stencil(name, torch):
     for bad in (0, 4):
         with pytest.raises(PPQError):
             g.set_stencil(bad)
-    gl = make(lattice_card(), torch)
-    with pytest.raises(PPQError):
-        gl.set_stencil(3)
+
+
+@pytest.mark.parametrize("stencil", [2, 3])
+def test_wide_stencils_on_lattices(stencil, torch):
+    """Radius sqrt(2) and 2 counted over the phase-space axes (cell and level
+    of each lattice dimension): adaption bit-exact against the oracle on a
+    2D lattice card and a 4D one (3 x 4 per dimension), and a 5-step
+    trajectory with the same sets."""
+    for cd in (dict(card("small_2d", n=[12, 12], lo=[-5.0, -5.0], hi=[5.0, 5.0]), name="small_lattice2d",
+                    basis="pvb", lattice=[3, 4], stencil=stencil),
+               dict(lattice_card(), stencil=stencil)):
+        o = Oracle(cd)
+        g = make(cd, torch)
+        for seed in (1, 2):
+            keys = random_active_set(o.n, 0.3, seed)
+            rng = np.random.default_rng(seed)
+            c = random_complex(keys.size, seed) * np.exp(rng.uniform(-12, 0, keys.size))
+            c[::17] = 1e-3
+            say(f"stencil {stencil} on {cd['name']} seed {seed} |A|={keys.size}")
+            o.set_state(keys, c)
+            nab = o.prune(eps=1e-3)
+            g.set_state(keys, c)
+            assert g.prune(eps=1e-3)[1] == nab
+            assert np.array_equal(g.state()[0], o.state()[0])
+            assert np.array_equal(g.state()[1], o.state()[1])
+        o.init_state()
+        g.init_state()
+        assert np.array_equal(g.state()[0], o.state()[0])
+        tr, _ = o.propagate(nsteps=5)
+        tg = g.propagate(nsteps=5)
+        assert np.array_equal(tg[:, 5], tr[:, 5])
+        for col in (1, 2, 3, 4, 6):
+            assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
 
 def test_acf_doubled(torch):
     """C(2t) = sum c^2: the oracle's on the same state (1e-13), and, unpruned
