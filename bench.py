@@ -156,8 +156,9 @@ def accuracy_sweep(stream):
     infidelity of C(t), sqrt(sum_n |C_pruned(t_n) - C_exact(t_n)|^2) over all
     201 records, against the mean number of functions used (percent of the
     48^2 grid), per threshold, for the DVR with each of the three neighbour
-    stencils (ball radius 1, sqrt(2), 2) and for the projected von Neumann
-    and projected Weylet lattices (6 x 8 per
+    stencils (ball radius 1, sqrt(2), 2), for the projected von Neumann
+    lattice with each stencil (counted over its phase-space axes) and for the
+    projected Weylet lattice (6 x 8 per
     dimension); the exact run keeps the full DVR grid without adaption (all
     three bases are similarity transforms of it)."""
     import torch
@@ -175,8 +176,10 @@ def accuracy_sweep(stream):
     c_ref = ref[:, 3] + 1j * ref[:, 4]
     del g
     rows = []
+    pvb = {"basis": "pvb", "lattice": [6, 8]}
     variants = (("dvr", 1, {}), ("dvr", 2, {"stencil": 2}), ("dvr", 3, {"stencil": 3}),
-                ("pvb", 1, {"basis": "pvb", "lattice": [6, 8]}), ("pw", 1, {"basis": "pw", "lattice": [6, 8]}))
+                ("pvb", 1, pvb), ("pvb", 2, dict(pvb, stencil=2)), ("pvb", 3, dict(pvb, stencil=3)),
+                ("pw", 1, {"basis": "pw", "lattice": [6, 8]}))
     for basis, stencil, extra in variants:
         for eps in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
             g = ppq.Propagator(dict(cd, **extra), precision=ppq.PPQ_FP64, device=0, stream=stream)
