@@ -54,6 +54,7 @@ def lib():
         L.orc_state_get.argtypes = [vp, _c_u64_p, _c_double_p]
         L.orc_sil_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _c_double_p]
         L.orc_set_stencil.argtypes = [vp, ctypes.c_int]
+        L.orc_set_krylov_tol.argtypes = [vp, ctypes.c_double]
         L.orc_prune.restype = ctypes.c_int64
         L.orc_prune.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double]
         L.orc_init_product.restype = ctypes.c_int64
@@ -146,6 +147,8 @@ class Oracle:
             ns, nl = m.lattice
             for k in range(self.D):
                 L.orc_set_lattice(self._m, k, ns, nl)
+        if card.get("krylov_tol", 0.0) and L.orc_set_krylov_tol(self._m, float(card["krylov_tol"])) != 0:
+            raise ValueError("krylov_tol must be >= 0")
         if card.get("stencil", 1) != 1 and L.orc_set_stencil(self._m, int(card["stencil"])) != 0:
             raise ValueError("stencil must be 1, 2 or 3")
         self.arnoldi = 1 if m.pvb else 0

@@ -59,6 +59,7 @@ typedef struct orc_model {
     zd **ph1, **ph2;
     int lat_s[ORC_MAXD], lat_l[ORC_MAXD]; /* phase-space lattice shape per dim; 0 = line */
     int stencil;                /* adaption neighbours: 1 = ball radius 1, 2 = radius sqrt(2), 3 = radius 2 */
+    double krylov_tol;          /* > 0: SIL order chosen per step by the error estimate */
 } orc_model;
 
 orc_model *orc_new(int D, const int32_t *n)
@@ -561,6 +562,11 @@ int orc_sil_step(const orc_model *m, const orc_fib *f, orc_state *s, double dt, 
     double n0 = sqrt(creal(cdot(n, s->c, s->c)));
     for (int64_t i = 0; i < n; ++i) V[0][i] = s->c[i] / n0;
     int meff = mk;
+    /* error estimate of the order-k step, the first Taylor term the Krylov
+       space leaves out: n0 dt^k / k! prod_{i<k} beta_i (Park and Light's
+       estimate for the short-iterative Lanczos); with a tolerance set, the
+       step stops at the first order whose estimate is within it */
+    double est = n0;
     for (int j = 0; j < mk; ++j) {
         orc_apply_fib(m, f, (const double *)V[j], (double *)w);
         for (int i = 0; i <= j; ++i) h1[i] = cdot(n, V[i], w);
@@ -576,6 +582,8 @@ int orc_sil_step(const orc_model *m, const orc_fib *f, orc_state *s, double dt, 
         beta[j] = b;
         if (j < mk - 1) {
             if (b < 1e-13) { meff = j + 1; break; }
+            est = est * dt * b / (double)(j + 1);
+            if (m->krylov_tol > 0.0 && est <= m->krylov_tol) { meff = j + 1; break; }
             hk[(j + 1) * mk + j] = b;
             for (int64_t p = 0; p < n; ++p) V[j + 1][p] = w[p] / b;
         }
@@ -745,6 +753,14 @@ static void insert_with_neighbours(const orc_model *m, keyset *set, uint64_t key
             if (inside) ks_insert(set, (uint64_t)((int64_t)key + shift));
         }
     }
+}
+
+/* Tolerance of the adaptive SIL order (0: always the full order). */
+int orc_set_krylov_tol(orc_model *m, double tol)
+{
+    if (!(tol >= 0.0)) return -1;
+    m->krylov_tol = tol;
+    return 0;
 }
 
 /* Selects the adaption stencil (1: radius 1; 2: radius sqrt(2); 3: radius 2). */

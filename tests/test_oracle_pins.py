@@ -316,6 +316,60 @@ def test_sil_step_matches_dense_exponential():
     assert np.max(np.abs(cg - c)) < 1e-12
 
 
+
+def lanczos_betas(H, c0, m):
+    """beta_0 .. beta_{m-2} of the Lanczos recurrence on a dense H, with a
+    full reorthogonalisation by numpy's QR-free projections."""
+    V = [c0 / np.linalg.norm(c0)]
+    betas = []
+    for j in range(m - 1):
+        w = H @ V[j]
+        for _ in range(2):
+            for v in V:
+                w = w - np.vdot(v, w) * v
+        b = np.linalg.norm(w)
+        betas.append(b)
+        V.append(w / b)
+    return betas
+
+
+def test_adaptive_sil_order():
+    """Adaptive SIL order (the integrator's accuracy tied to a tolerance,
+    Sec. III.A) on a full tiny grid: the order picked is the first k whose
+    estimate n0 dt^k / k! prod_{i<k} beta_i (betas from an independent dense
+    Lanczos) is within the tolerance; the step is then within 10x the
+    tolerance of exp(-iH dt) psi (dense expm); smaller tolerances never pick
+    lower orders; tolerance 0 keeps the full order."""
+    import math
+    o = orc.Oracle(card("small_2d"))
+    keys, c0 = _full_state(o)
+    H = dense_h(o.model)
+    dt, m = 0.05, 16
+    U = sla.expm(-1j * dt * H)
+    betas = lanczos_betas(H, c0, m)
+    n0 = np.linalg.norm(c0)
+    prev = 0
+    for tol in (1e-4, 1e-7, 1e-10):
+        want = m
+        for k in range(1, m):
+            est = n0 * dt ** k / math.factorial(k) * np.prod(betas[:k])
+            if est <= tol:
+                want = k
+                break
+        oo = orc.Oracle(card("small_2d", krylov_tol=tol))
+        oo.set_state(keys, c0)
+        used, _ = oo.sil_step(dt=dt, m=m)
+        _, c1 = oo.state()
+        assert used == want, (tol, used, want)
+        assert 1 < used < m
+        assert np.linalg.norm(c1 - U @ c0) <= 10 * tol
+        assert used >= prev
+        prev = used
+    o.set_state(keys, c0)
+    assert o.sil_step(dt=dt, m=m)[0] == m
+    with pytest.raises(ValueError):
+        orc.Oracle(card("small_2d", krylov_tol=-1.0))
+
 def test_arnoldi_step_matches_dense_exponential():
     """Arnoldi on a non-Hermitian operator: matches expm of the dense restricted operator."""
     n = (4, 5)
