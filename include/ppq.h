@@ -236,6 +236,16 @@ int ppq_apply_h(ppq_ctx *ctx, const void *x, void *y);
    second pass all of them), on the current set; no adaption.  1 <= m <= 16. */
 int ppq_step(ppq_ctx *ctx, double dt, int m);
 
+/* Adaptive SIL order (Sec. III.A adapts the integrator's accuracy to the
+   amplitude threshold).  With tol > 0 every later step (ppq_step,
+   ppq_propagate) stops its Krylov recurrence at the first order k <= m whose
+   estimate n0 dt^k / k! prod_{i<k} beta_i (Park and Light's estimate of the
+   first term the space leaves out; n0 = |psi|) is <= tol; the order used is
+   recorded per step.  0 (default) keeps the full order m.  The decision is
+   taken on the device, with no host wait.  PPQ_E_ARG unless tol is finite
+   and >= 0.  The adjoint entry points need tolerance 0 (PPQ_E_UNSUPPORTED). */
+int ppq_set_krylov_tolerance(ppq_ctx *ctx, double tol);
+
 /* Adaption with threshold eps (Sec. II.E, radius-1 stencil of Sec. III.A):
    A' = {I in A : |c_I| >= eps} plus their nearest neighbours inside the grid;
    coefficients carried over on A cap A', zero on new functions.  |c|^2 is

@@ -63,6 +63,8 @@ class Propagator:
             self.set_factor(int(k), h)
         if card.get("stencil", 1) != 1:
             self.set_stencil(card["stencil"])
+        if card.get("krylov_tol", 0.0):
+            self.set_krylov_tolerance(card["krylov_tol"])
         for t in card["terms"]:
             self.add_term(t["coef"], t["factors"])
 
@@ -260,6 +262,11 @@ class Propagator:
 
     def set_relative_exclusion(self, r):
         self._call("ppq_set_relative_exclusion", float(r))
+
+    def set_krylov_tolerance(self, tol):
+        """Adaptive SIL order: each step stops at the first order whose error
+        estimate is within tol (0: the full order)."""
+        self._call("ppq_set_krylov_tolerance", float(tol))
 
     def propagate(self, nsteps=None, dt=None, m=None, eps=None, prune=True):
         nsteps = self.card["nsteps"] if nsteps is None else nsteps

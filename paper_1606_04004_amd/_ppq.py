@@ -49,6 +49,7 @@ SIGNATURES = {
     "ppq_set_state_device": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, _vp]),
     "ppq_get_state_device": (ctypes.c_int, [_vp, ctypes.c_int64, _i64p, _vp, _vp]),
     "ppq_set_relative_exclusion": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "ppq_set_krylov_tolerance": (ctypes.c_int, [_vp, ctypes.c_double]),
     "ppq_propagate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp]),
     "ppq_observables": (ctypes.c_int, [_vp, ctypes.c_double, _dp]),
     "ppq_expect_q": (ctypes.c_int, [_vp, _dp]),

@@ -181,6 +181,7 @@ struct ppq_ctx {
     int tab_nmax = 0;
     double *qtab = nullptr;  // grid points [MAXD][NMAX_FIBER], then MAXD results (position expectations)
     double rel_excl = 0.0;   // relative exclusion threshold of adaption
+    double krylov_tol = 0.0; // > 0: SIL order chosen per step by its error estimate
     double2 *acf2 = nullptr;  // C(2t) result (device)
     std::vector<double> factor[MAXD];  // caller's 1D factor per dimension (empty: sine-DVR kinetic)
     // fiber tables of all non-last dimensions at once (see fiber_tables_all)
@@ -1179,8 +1180,10 @@ void mark(ppq_ctx *c, int phase)
 
 // Lanczos/Arnoldi basis of `src` (FP64 master vector on the current set) in
 // Vb with the small matrix and norm in ks; m H-applications, CGS2.
+// tol > 0: the order is chosen per step by the error estimate (the adjoint's
+// recorded steps use the full order)
 template <class C>
-void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
+void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, double dt = 0.0, double tol = 0.0)
 {
     hipStream_t s = c->stream;
     const int64_t n = c->nact;
@@ -1188,7 +1191,7 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m)
     C *w = (C *)c->wk;
     const int *meff = &ks->meff;
     const bool herm = !c->any_lattice;
-    norm0<C>(src, n, c->partial, c->counter, ks, m, s);
+    norm0<C>(src, n, c->partial, c->counter, ks, m, dt, tol, s);
     normalise_from_master<C>(src, n, ks, Vb, s);
     for (int j = 0; j < m; ++j) {
         const C *vj = Vb + (int64_t)j * ld;
@@ -1219,7 +1222,7 @@ void step_impl(ppq_ctx *c, double dt, int m)
 {
     mark(c, PPQ_PHASE_KRYLOV);
     C *Vb = (C *)c->Vk;
-    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m);
+    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m, dt, c->krylov_tol);
     krylov_expv(c->ks, m, dt, c->any_lattice ? 0 : 1, c->stream);
     lincomb<C>(Vb, c->cap, c->psi[c->cur], c->nact, c->ks, c->psi_tmp, c->stream);
     std::swap(c->psi[c->cur], c->psi_tmp);
@@ -1318,7 +1321,7 @@ void energy_into(ppq_ctx *c, int64_t r)
         // FP32 form: H acts on the FP32 copy; the inner product is accumulated in FP64
         float2 *x32 = (float2 *)c->Vk;
         KState *ks = c->ks;
-        norm0<float2>(c->psi[c->cur], c->nact, c->partial, c->counter, ks, 1, c->stream);
+        norm0<float2>(c->psi[c->cur], c->nact, c->partial, c->counter, ks, 1, 0.0, 0.0, c->stream);
         normalise_from_master<float2>(c->psi[c->cur], c->nact, ks, x32, c->stream);
         apply_internal(c, x32, c->wk, nullptr, 0);
         cgs_dots<float2>(x32, c->cap, 1, (const float2 *)c->wk, c->nact, c->partial, c->counter, ks, 0, 1, 0,
@@ -2188,6 +2191,14 @@ int ppq_timings(ppq_ctx *c, double *ms)
     return PPQ_OK;
 }
 
+int ppq_set_krylov_tolerance(ppq_ctx *c, double tol)
+{
+    PPQ_GUARD(c)
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, PPQ_E_ARG, "Krylov tolerance must be finite and >= 0");
+    c->krylov_tol = tol;
+    return PPQ_OK;
+}
+
 int ppq_set_relative_exclusion(ppq_ctx *c, double r)
 {
     PPQ_GUARD(c)
@@ -2351,6 +2362,8 @@ int ppq_adjoint_record(ppq_ctx *c, const double *centre, const double *momentum,
     PPQ_GUARD(c)
     if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
     if (c->any_lattice) return fail(c, PPQ_E_UNSUPPORTED, "adjoint gradients are built for DVR dimensions");
+    if (c->krylov_tol > 0.0)
+        return fail(c, PPQ_E_UNSUPPORTED, "adjoint gradients differentiate the full-order step (Krylov tolerance 0)");
     if (nsteps < 1 || m < 1 || m > MAXM || checkpoint_every < 1 || !(eps >= 0.0) || !std::isfinite(dt))
         return fail(c, PPQ_E_ARG, "bad adjoint recording arguments");
     int r = ppq_init_gaussian(c, centre, momentum, width, eps, nullptr);
@@ -2385,6 +2398,7 @@ int ppq_adjoint_frozen(ppq_ctx *c, const double *centre, const double *momentum,
 {
     PPQ_GUARD(c)
     if (!c->recorded) return fail(c, PPQ_E_STATE, "no recorded trajectory");
+    if (c->krylov_tol > 0.0) return fail(c, PPQ_E_UNSUPPORTED, "the recorded steps are full-order (Krylov tolerance 0)");
     if (!centre || !momentum || !J) return fail(c, PPQ_E_ARG, "null argument");
     PPQ_TRY(c, {
         int64_t nmax_set = *std::max_element(c->rec_n.begin(), c->rec_n.end());
@@ -2415,6 +2429,7 @@ int ppq_adjoint_gradient(ppq_ctx *c, double *dJ_dparam, double *dJ_dcentre, doub
 {
     PPQ_GUARD(c)
     if (!c->recorded) return fail(c, PPQ_E_STATE, "no recorded trajectory");
+    if (c->krylov_tol > 0.0) return fail(c, PPQ_E_UNSUPPORTED, "the recorded steps are full-order (Krylov tolerance 0)");
     PPQ_TRY(c, {
         const int D = c->g.D;
         int64_t nmax_set = *std::max_element(c->rec_n.begin(), c->rec_n.end());
@@ -2453,7 +2468,7 @@ int ppq_time_apply(ppq_ctx *c, int nrep, double *ms_per_apply)
         ensure_krylov(c, std::max(c->kv_m, 1));
         const void *x = c->psi[c->cur];
         if (c->precision == PPQ_FP32) {
-            norm0<float2>(c->psi[c->cur], c->nact, c->partial, c->counter, c->ks, 1, c->stream);
+            norm0<float2>(c->psi[c->cur], c->nact, c->partial, c->counter, c->ks, 1, 0.0, 0.0, c->stream);
             normalise_from_master<float2>(c->psi[c->cur], c->nact, c->ks, (float2 *)c->Vk, c->stream);
             x = c->Vk;
         }

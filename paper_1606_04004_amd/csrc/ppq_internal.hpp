@@ -51,6 +51,8 @@ struct KState {
     double2 y[MAXM];           // coefficients of the propagated vector
     double inv_beta;           // 1/beta of the last completed iteration
     double norm2_scratch;
+    double est;                // error estimate of the current order: n0 dt^k/k! prod beta_i
+    double kdt, ktol;          // step and order tolerance of this step (ktol 0: full order)
     int meff;                  // Krylov dimension actually built
     int pad;
 };
@@ -236,7 +238,8 @@ void hpsi_cmfma_f32(const FiberPass &fp, const float2 *H64, const CInput32 &in, 
 // for v_{j-1}, zero below), and the second pass removes what they leave.
 enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3, RED_H1L = 4 };
 template <class C>
-void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, hipStream_t s);
+void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, double dt,
+           double tol, hipStream_t s);
 template <class C>
 void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
               int j, int m, int ioff, hipStream_t s, int mode = RED_H1);

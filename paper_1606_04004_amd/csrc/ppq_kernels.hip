@@ -870,7 +870,7 @@ __device__ inline void block_reduce_store(double2 (&acc)[NV], double2 *partial)
 // finish the sum would write back the L2 of every XCD.)
 template <int NV>
 __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb, KState *ks, int j, int mode, int m,
-                                                 int ioff, int nvals)
+                                                 int ioff, int nvals, double dt, double tol)
 {
     if (mode != RED_NORM0 && j >= ks->meff) return;
     // the partials were just written from every XCD: issue all of this
@@ -932,6 +932,9 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
     if (mode == RED_NORM0) {
         ks->n0 = sqrt(r[0].x);
         ks->meff = m;
+        ks->est = ks->n0;
+        ks->kdt = dt;
+        ks->ktol = tol;
     } else if (mode == RED_H1 || mode == RED_H1L) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
@@ -965,6 +968,12 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
                     ks->inv_beta = 0.0;
                 } else {
                     ks->inv_beta = 1.0 / b;
+                    // Park and Light's estimate of the order-(j+1) step: the
+                    // first Taylor term the Krylov space leaves out; with a
+                    // tolerance, the step stops at the first order within it
+                    const double est = ks->est * ks->kdt * b / (double)(j + 1);
+                    ks->est = est;
+                    if (ks->ktol > 0.0 && est <= ks->ktol) ks->meff = j + 1;
                 }
             }
         }
@@ -1888,10 +1897,12 @@ static unsigned red_blocks(int64_t n)
     }
 
 template <class C>
-void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, hipStream_t s)
+void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, double dt,
+           double tol, hipStream_t s)
 {
     hipLaunchKernelGGL(k_norm0<C>, dim3(RED_BLOCKS), dim3(TB), 0, s, psi, n, partial, counter, ks, m);
-    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, 0, (int)RED_NORM0, m, 0, 1);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, 0, (int)RED_NORM0, m, 0, 1,
+                       dt, tol);
 }
 template <class C>
 void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
@@ -1900,7 +1911,8 @@ void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *p
 #define CALL(NV)                                                                                                  \
     hipLaunchKernelGGL((k_cgs_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, counter, ks, j, \
                        m, ioff);                                                                              \
-    hipLaunchKernelGGL(k_finalize<NV>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, mode, m, ioff, NV)
+    hipLaunchKernelGGL(k_finalize<NV>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, mode, m, ioff, NV, 0.0, \
+                       0.0)
     PPQ_NV_SWITCH(nv, CALL)
 #undef CALL
 }
@@ -1912,7 +1924,7 @@ void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, double2 *
     hipLaunchKernelGGL((k_cgs_update_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, counter, \
                        ks, j, m, with_norm ? 1 : 0);                                                            \
     hipLaunchKernelGGL(k_finalize<NV + 1>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j,                  \
-                       with_norm ? (int)RED_BETA : (int)RED_H2, m, 0, with_norm ? NV + 1 : NV)
+                       with_norm ? (int)RED_BETA : (int)RED_H2, m, 0, with_norm ? NV + 1 : NV, 0.0, 0.0)
     PPQ_NV_SWITCH(nv, CALL)
 #undef CALL
 }
@@ -1940,7 +1952,8 @@ void lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, cons
 }
 
 #define PPQ_INST(C)                                                                                               \
-    template void norm0<C>(const double2 *, int64_t, double2 *, unsigned *, KState *, int, hipStream_t);          \
+    template void norm0<C>(const double2 *, int64_t, double2 *, unsigned *, KState *, int, double, double,        \
+                           hipStream_t);                                                                         \
     template void cgs_dots<C>(const C *, int64_t, int, const C *, int64_t, double2 *, unsigned *, KState *, int,  \
                               int, int, hipStream_t, int);                                                      \
     template void cgs_update_dots<C>(const C *, int64_t, int, C *, int64_t, double2 *, unsigned *, KState *, int, \

@@ -1141,6 +1141,41 @@ def test_wide_stencils_on_lattices(stencil, torch):
         for col in (1, 2, 3, 4, 6):
             assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
 
+
+@pytest.mark.parametrize("which,tol,nsteps", [("hh2d", 1e-8, 25), ("small_4d", 1e-6, 15), ("lattice", 1e-6, 8)])
+def test_adaptive_krylov_order(which, tol, nsteps, torch):
+    """Adaptive SIL order (each step stops at the first order whose estimate
+    is within the tolerance): the order used per step (an integer the device
+    decides) equals the oracle's, and so do the sets and observables, on
+    the 2D and 4D DVR cards and a lattice (Arnoldi) card; the FP32 form
+    stays within its bound; bad tolerances are refused."""
+    from paper_1606_04004_amd import PPQError
+    cd = lattice_card() if which == "lattice" else card(which)
+    cd = dict(cd, krylov_tol=tol)
+    o = Oracle(cd)
+    g = make(cd, torch)
+    o.init_state()
+    g.init_state()
+    tr, _ = o.propagate(nsteps=nsteps)
+    tg = g.propagate(nsteps=nsteps)
+    say(f"adaptive order {which} tol {tol}: orders {tg[1:, 7].astype(int).tolist()}")
+    assert np.array_equal(tg[:, 7], tr[:, 7])
+    assert np.min(tr[1:, 7]) < cd["krylov"]   # the tolerance did truncate
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 2, 3, 4, 6):
+        assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    g32 = make(cd, torch, precision=1)
+    g32.init_state()
+    t32 = g32.propagate(nsteps=nsteps)
+    for col in (1, 3, 4):
+        assert np.max(np.abs(t32[:, col] - tr[:, col])) < 1e-6
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(PPQError):
+            g.set_krylov_tolerance(bad)
+    g.set_krylov_tolerance(0.0)
+    g.init_state()
+    assert np.all(g.propagate(nsteps=2)[1:, 7] == cd["krylov"])
+
 def test_acf_doubled(torch):
     """C(2t) = sum c^2: the oracle's on the same state (1e-13), and, unpruned
     with a real packet, the C(t) record at twice the time (1e-9)."""
