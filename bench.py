@@ -268,6 +268,21 @@ def main():
     g.propagate(nsteps=nph)
     phases = {k: v / nph for k, v in g.timings().items()}
     g.enable_timings(False)
+    # the integrator's accuracy tied to the threshold: the adaptive SIL order
+    # with tolerance eps against the full order, both from the snapshot over
+    # the same steps (outside the headline figure)
+    g.set_state(snap_keys, snap_c)
+    _, ms_full, tr_full = timed_steps(g, args.steps, 0)
+    g.set_state(snap_keys, snap_c)
+    g.set_krylov_tolerance(eps)
+    _, ms_ad, tr_ad = timed_steps(g, args.steps, 0)
+    g.set_krylov_tolerance(0.0)
+    acf = lambda tr: tr[:, 3] + 1j * tr[:, 4]
+    adaptive = {"tolerance": eps, "ms_per_step": ms_ad, "ms_per_step_full_order": ms_full,
+                "orders_used": sorted(set(tr_ad[1:, 7].astype(int).tolist())),
+                "acf_max_diff_vs_full_order": float(np.max(np.abs(acf(tr_ad) - acf(tr_full)))),
+                "norm2_max_diff_vs_full_order": float(np.max(np.abs(tr_ad[:, 1] - tr_full[:, 1]))),
+                "steps": args.steps}
 
     out = {
         "metric": "pruned H*psi active-point updates/s (whole step) + steps/s",
@@ -298,6 +313,8 @@ def main():
                      "kernel": "pruned H*psi (D fiber passes, potential fused in the first)",
                      "bytes_per_point": bpp},
     }
+
+    out["adaptive_order"] = adaptive
 
     if not args.no_fp32:
         g32 = ppq.Propagator(cd, precision=ppq.PPQ_FP32, device=0, stream=stream)
