@@ -119,8 +119,10 @@ int ppq_get_grid(const ppq_ctx *ctx, int k, double *q);
    under its lattices, Sec. III.A): points x_j = lo + j (hi-lo)/n, j = 0..n-1,
    over the period hi - lo, and kinetic energy -1/(2 mass) d^2/dx^2 from its
    spectral definition with |k| <= (n-1) pi/(hi-lo).  n[k] must be odd
-   (PPQ_E_ARG).  DVR dimensions only (PPQ_E_UNSUPPORTED after
-   ppq_set_lattice / ppq_set_weylets); must be called before adding terms. */
+   (PPQ_E_ARG).  A lattice on the dimension (ppq_set_lattice /
+   ppq_set_weylets) is then projected on these points with weight
+   (hi-lo)/n; the Fourier grid must be set first (PPQ_E_STATE after a
+   lattice), and before adding terms. */
 int ppq_set_fgh(ppq_ctx *ctx, int k);
 
 /* Makes dimension k a phase-space lattice basis: n_s x n_l von Neumann

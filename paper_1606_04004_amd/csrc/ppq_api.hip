@@ -422,6 +422,14 @@ std::vector<double> dim_points(const ppq_ctx *c, int k)
     return q;
 }
 
+// Quadrature weight of dimension k's grid: the spacing (hi - lo) / (n + 1) of
+// the sine-DVR, (hi - lo) / n of the periodic Fourier grid.
+double dim_weight(const ppq_ctx *c, int k)
+{
+    const int n = c->g.n[k];
+    return (c->hi[k] - c->lo[k]) / (c->fgh[k] ? n : n + 1);
+}
+
 std::vector<double> factor_values(const ppq_ctx *c, const Factor &f)
 {
     int k = f.dim;
@@ -467,8 +475,9 @@ LatticeMaps lattice_maps(const ppq_ctx *c, int k)
 {
     LatticeMaps L;
     int n = c->g.n[k];
-    L.G = c->weylets[k] ? weylet_projection(n, c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k])
-                        : pvb_projection(n, c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k]);
+    const std::vector<double> q = dim_points(c, k);
+    L.G = c->weylets[k] ? weylet_projection(q, dim_weight(c, k), c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k])
+                        : pvb_projection(q, dim_weight(c, k), c->lo[k], c->hi[k], c->g.lat_s[k], c->g.lat_l[k]);
     L.Gadj = adjoint(L.G, n);
     L.GinvAdj = L.Gadj;
     if (!invert(L.GinvAdj, n)) throw std::runtime_error("singular lattice projection");
@@ -1793,10 +1802,9 @@ static int set_lattice_kind(ppq_ctx *c, int k, int ns, int nl, bool weylets)
     if (k < 0 || k >= c->g.D || ns < 1 || nl < 1 || ns * nl != c->g.n[k])
         return fail(c, PPQ_E_ARG, "lattice shape must satisfy n_s * n_l == n[k]");
     if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set lattices before adding terms");
-    if (c->fgh[k]) return fail(c, PPQ_E_UNSUPPORTED, "lattices are built on sine-DVR dimensions only");
     if (weylets) {
         // fails early on a lattice whose symmetrized Gaussians are linearly dependent
-        PPQ_TRY(c, { (void)weylet_projection(c->g.n[k], c->lo[k], c->hi[k], ns, nl); })
+        PPQ_TRY(c, { (void)weylet_projection(dim_points(c, k), dim_weight(c, k), c->lo[k], c->hi[k], ns, nl); })
     }
     c->g.lat_s[k] = ns;
     c->g.lat_l[k] = nl;
@@ -1906,7 +1914,7 @@ int ppq_set_fgh(ppq_ctx *c, int k)
     if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
     if (k < 0 || k >= c->g.D) return fail(c, PPQ_E_ARG, "dimension out of range");
     if (c->g.n[k] % 2 == 0) return fail(c, PPQ_E_ARG, "the Fourier grid needs an odd number of points");
-    if (c->lattice[k]) return fail(c, PPQ_E_UNSUPPORTED, "Fourier grids are built for DVR dimensions only");
+    if (c->lattice[k]) return fail(c, PPQ_E_STATE, "set Fourier grids before lattices");
     if (!c->terms.empty()) return fail(c, PPQ_E_STATE, "set Fourier grids before adding terms");
     c->fgh[k] = true;
     c->op_dirty = true;

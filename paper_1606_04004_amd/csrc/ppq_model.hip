@@ -40,10 +40,9 @@ std::vector<double> sine_dvr_kinetic(int n, double lo, double hi, double mass)
     return T;
 }
 
-std::vector<cd> pvb_projection(int n, double lo, double hi, int ns, int nl)
+std::vector<cd> pvb_projection(const std::vector<double> &q, double dxg, double lo, double hi, int ns, int nl)
 {
-    std::vector<double> q = sine_dvr_points(n, lo, hi);
-    const double dxg = (hi - lo) / (n + 1);
+    const int n = (int)q.size();
     const double cell = (hi - lo) / ns;
     const double dp = 2.0 * M_PI / cell;
     const double a = dp / (2.0 * cell);
@@ -108,13 +107,12 @@ static void jacobi_eigen(std::vector<double> a, int n, std::vector<double> &w, s
 
 // Projected Weylets (Sec. II.D): the momentum-symmetrized Gaussians of
 // Eq. sG_def on a doubly dense lattice (cell dx, dp = pi / dx, momenta
-// p_l = (l + 1/2) dp > 0, alpha = dp / (2 dx)), projected on the sine-DVR
-// grid (Eq. psG_def) as Phi, then orthogonalised: W = Phi S^{-1/2},
+// p_l = (l + 1/2) dp > 0, alpha = dp / (2 dx)), projected on the grid points
+// q with quadrature weight dxg (Eq. psG_def) as Phi, then orthogonalised: W = Phi S^{-1/2},
 // S = Phi^T Phi.  Returned as a complex n x n matrix (real values).
-std::vector<cd> weylet_projection(int n, double lo, double hi, int nx, int np)
+std::vector<cd> weylet_projection(const std::vector<double> &q, double dxg, double lo, double hi, int nx, int np)
 {
-    std::vector<double> q = sine_dvr_points(n, lo, hi);
-    const double dxg = (hi - lo) / (n + 1);
+    const int n = (int)q.size();
     const double cell = (hi - lo) / nx;
     const double dp = M_PI / cell;
     const double a = dp / (2.0 * cell);

@@ -17,11 +17,11 @@ std::vector<double> sine_dvr_kinetic(int n, double lo, double hi, double mass);
 
 // Projected von Neumann lattice on a sine-DVR grid (n_s * n_l == n):
 // G[j][s*n_l + l] = sqrt(dx) (2a/pi)^{1/4} exp(-a (q_j - x_s)^2 + i p_l (q_j - x_s)).
-std::vector<cd> pvb_projection(int n, double lo, double hi, int ns, int nl);
+std::vector<cd> pvb_projection(const std::vector<double> &q, double dxg, double lo, double hi, int ns, int nl);
 // kinetic energy on the periodic Fourier grid (odd n), row-major n x n
 std::vector<double> fgh_kinetic(int n, double lo, double hi, double mass);
 // projected Weylets (orthogonal, real): W = Phi S^{-1/2} on an nx x np doubly dense lattice
-std::vector<cd> weylet_projection(int n, double lo, double hi, int nx, int np);
+std::vector<cd> weylet_projection(const std::vector<double> &q, double dxg, double lo, double hi, int nx, int np);
 
 // In-place inverse of a dense complex matrix (Gauss-Jordan, partial pivoting).
 // Returns false if singular.

@@ -1176,6 +1176,38 @@ def test_adaptive_krylov_order(which, tol, nsteps, torch):
     g.init_state()
     assert np.all(g.propagate(nsteps=2)[1:, 7] == cd["krylov"])
 
+
+@pytest.mark.parametrize("basis", ["pvb", "pw"])
+def test_lattices_on_fourier_grids(basis, torch):
+    """Lattice bases projected on periodic Fourier grids (15 x 15, 3 x 5
+    cells and momenta per dimension): products against the oracle's on a
+    random set, the initial set, and a 10-step pruned trajectory; a Fourier
+    grid set after the lattice is refused."""
+    from paper_1606_04004_amd import PPQError
+    cd = dict(card("small_2d", n=[15, 15], fgh=[0, 1]), name="fgh_lattice2d", basis=basis, lattice=[3, 5])
+    o = Oracle(cd)
+    g = make(cd, torch)
+    keys = random_active_set(o.n, 0.6, 3)
+    x = random_complex(keys.size, 4)
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    ref = o.apply_def(keys, x)
+    say(f"{basis} on Fourier grids: product error {np.max(np.abs(yt.cpu().numpy() - ref)):.2e}")
+    assert np.max(np.abs(yt.cpu().numpy() - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+    o.init_state()
+    g.init_state()
+    assert np.array_equal(g.state()[0], o.state()[0])
+    tr, _ = o.propagate(nsteps=10)
+    tg = g.propagate(nsteps=10)
+    assert np.array_equal(tg[:, 5], tr[:, 5])
+    for col in (1, 2, 3, 4, 6):
+        assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
+    with pytest.raises(PPQError):
+        g._call("ppq_set_fgh", 0)
+
 def test_acf_doubled(torch):
     """C(2t) = sum c^2: the oracle's on the same state (1e-13), and, unpruned
     with a real packet, the C(t) record at twice the time (1e-9)."""

@@ -893,6 +893,39 @@ def test_pw_unpruned_dynamics_is_similarity_of_dvr():
     assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
 
 
+
+@pytest.mark.parametrize("basis", ["pvb", "pw"])
+def test_lattices_on_fourier_grids_are_similarity_of_fgh(basis):
+    """Lattices projected on periodic Fourier grids (the paper's setting for
+    its double well, Sec. III.A): the unpruned lattice dynamics maps back to
+    the FGH DVR dynamics exactly, C(t) included, on a 15 x 15 grid with a
+    3 x 5 lattice per dimension. The projection uses the FGH points and
+    weight (hi - lo) / n: the middle cell's projected Gaussians have unit
+    norm on the grid (the sine-DVR weight (hi - lo) / (n + 1) would give
+    n / (n + 1))."""
+    base = card("small_2d", n=[15, 15], fgh=[0, 1])
+    lat = dict(base, basis=basis, lattice=[3, 5])
+    od = orc.Oracle(base)
+    ol = orc.Oracle(lat)
+    assert np.allclose(ol.model.q[0], od.model.q[0], rtol=0, atol=0)
+    if basis == "pvb":
+        norms = np.sum(np.abs(ol.model.G[0]) ** 2, axis=0).reshape(3, 5)
+        assert np.max(np.abs(norms[1] - 1.0)) < 1e-3
+    kd, cd0 = _full_state(od)
+    kl, cl0 = _full_state(ol)
+    od.set_state(kd, cd0)
+    ol.set_state(kl, cl0)
+    td, _ = od.propagate(nsteps=8, dt=0.05, m=14, prune=False)
+    tl, _ = ol.propagate(nsteps=8, dt=0.05, m=14, prune=False)
+    assert np.max(np.abs((td[:, 3] + 1j * td[:, 4]) - (tl[:, 3] + 1j * tl[:, 4]))) < 1e-9
+    _, cdv = od.state()
+    _, clat = ol.state()
+    back = ol.model.G if basis == "pw" else ol.model.GinvH
+    c_back = clat.reshape(ol.n)
+    for k in range(2):
+        c_back = np.moveaxis(np.tensordot(back[k], c_back, axes=([1], [k])), 0, k)
+    assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
+
 def test_pvb_coefficients_are_overlaps():
     """Eq. psi_exp_pvb: lattice coefficients are G^+ c_chi; G's columns are the projected Gaussians."""
     q, dx = sine_dvr_grid(16, -6.0, 6.0)
