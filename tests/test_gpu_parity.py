@@ -1208,6 +1208,35 @@ def test_lattices_on_fourier_grids(basis, torch):
     with pytest.raises(PPQError):
         g._call("ppq_set_fgh", 0)
 
+
+@pytest.mark.parametrize("stencil", [2, 3])
+def test_options_together(stencil, torch):
+    """The adaption and integrator options at once on the 3D card: a wider
+    stencil, a relative exclusion threshold and an adaptive SIL order;
+    per-step sets, Krylov orders and observables equal the oracle's over 20
+    steps, and the position expectations agree at the end."""
+    cd = dict(card("small_3d"), stencil=stencil, krylov_tol=1e-7)
+    o = Oracle(cd)
+    g = make(cd, torch)
+    g.set_relative_exclusion(0.02)
+    o.init_state()
+    g.init_state()
+    recs_o, recs_g = [], []
+    for _ in range(20):
+        used, _ = o.sil_step()
+        nab = o.prune(rel_excl=0.02)
+        recs_o.append((used, nab, o.state()[0].size))
+        g.step()
+        na, nb = g.prune()
+        recs_g.append((None, nb, na))
+        assert np.array_equal(g.state()[0], o.state()[0])
+    assert [r[1:] for r in recs_g] == [r[1:] for r in recs_o]
+    assert min(r[0] for r in recs_o) < cd["krylov"]
+    _, cg = g.state()
+    _, co = o.state()
+    assert np.max(np.abs(cg - co)) < 1e-10
+    assert np.max(np.abs(g.expect_q() - o.expect_q())) < 1e-10
+
 def test_acf_doubled(torch):
     """C(2t) = sum c^2: the oracle's on the same state (1e-13), and, unpruned
     with a real packet, the C(t) record at twice the time (1e-9)."""
