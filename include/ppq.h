@@ -241,7 +241,7 @@ int ppq_step(ppq_ctx *ctx, double dt, int m);
 /* Adaptive SIL order (Sec. III.A adapts the integrator's accuracy to the
    amplitude threshold).  With tol > 0 every later step (ppq_step,
    ppq_propagate) stops its Krylov recurrence at the first order k <= m whose
-   estimate n0 dt^k / k! prod_{i<k} beta_i (Park and Light's estimate of the
+   estimate n0 |dt|^k / k! prod_{i<k} beta_i (Park and Light's estimate of the
    first term the space leaves out; n0 = |psi|) is <= tol; the order used is
    recorded per step.  0 (default) keeps the full order m.  The decision is
    taken on the device, with no host wait.  PPQ_E_ARG unless tol is finite

@@ -563,9 +563,10 @@ int orc_sil_step(const orc_model *m, const orc_fib *f, orc_state *s, double dt, 
     for (int64_t i = 0; i < n; ++i) V[0][i] = s->c[i] / n0;
     int meff = mk;
     /* error estimate of the order-k step, the first Taylor term the Krylov
-       space leaves out: n0 dt^k / k! prod_{i<k} beta_i (Park and Light's
-       estimate for the short-iterative Lanczos); with a tolerance set, the
-       step stops at the first order whose estimate is within it */
+       space leaves out: n0 |dt|^k / k! prod_{i<k} beta_i (Park and Light's
+       estimate for the short-iterative Lanczos; a magnitude, so a backward
+       step is judged like a forward one); with a tolerance set, the step
+       stops at the first order whose estimate is within it */
     double est = n0;
     for (int j = 0; j < mk; ++j) {
         orc_apply_fib(m, f, (const double *)V[j], (double *)w);
@@ -582,7 +583,7 @@ int orc_sil_step(const orc_model *m, const orc_fib *f, orc_state *s, double dt, 
         beta[j] = b;
         if (j < mk - 1) {
             if (b < 1e-13) { meff = j + 1; break; }
-            est = est * dt * b / (double)(j + 1);
+            est = est * fabs(dt) * b / (double)(j + 1);
             if (m->krylov_tol > 0.0 && est <= m->krylov_tol) { meff = j + 1; break; }
             hk[(j + 1) * mk + j] = b;
             for (int64_t p = 0; p < n; ++p) V[j + 1][p] = w[p] / b;

@@ -933,7 +933,7 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         ks->n0 = sqrt(r[0].x);
         ks->meff = m;
         ks->est = ks->n0;
-        ks->kdt = dt;
+        ks->kdt = fabs(dt);  // the estimate is a magnitude: |dt|^k
         ks->ktol = tol;
     } else if (mode == RED_H1 || mode == RED_H1L) {
 #pragma unroll

@@ -1142,16 +1142,21 @@ def test_wide_stencils_on_lattices(stencil, torch):
             assert np.max(np.abs(tg[:, col] - tr[:, col])) < 1e-10
 
 
-@pytest.mark.parametrize("which,tol,nsteps", [("hh2d", 1e-8, 25), ("small_4d", 1e-6, 15), ("lattice", 1e-6, 8)])
-def test_adaptive_krylov_order(which, tol, nsteps, torch):
+@pytest.mark.parametrize("which,tol,nsteps,dt", [("hh2d", 1e-8, 25, None), ("small_4d", 1e-6, 15, None),
+                                                  ("lattice", 1e-6, 8, None), ("hh2d", 1e-8, 25, -0.05),
+                                                  ("small_4d", 1e-6, 15, -0.1)])
+def test_adaptive_krylov_order(which, tol, nsteps, dt, torch):
     """Adaptive SIL order (each step stops at the first order whose estimate
     is within the tolerance): the order used per step (an integer the device
     decides) equals the oracle's, and so do the sets and observables, on
-    the 2D and 4D DVR cards and a lattice (Arnoldi) card; the FP32 form
-    stays within its bound; bad tolerances are refused."""
+    the 2D and 4D DVR cards and a lattice (Arnoldi) card, forward and
+    backward in time (the estimate takes |dt|); the FP32 form stays within
+    its bound; bad tolerances are refused."""
     from paper_1606_04004_amd import PPQError
     cd = lattice_card() if which == "lattice" else card(which)
     cd = dict(cd, krylov_tol=tol)
+    if dt is not None:
+        cd["dt"] = dt
     o = Oracle(cd)
     g = make(cd, torch)
     o.init_state()

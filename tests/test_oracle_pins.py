@@ -532,6 +532,31 @@ def test_eps_zero_reproduces_unpruned():
     assert np.all(ta[:, 5] == keys.size)
 
 
+def test_adaptive_order_backward_step():
+    """The adaptive order's estimate is a magnitude (|dt|^k): a backward step
+    of the same length picks the same orders as a forward one, and a run
+    forward then backward with a tolerance returns to the start (time
+    reversal) within the accumulated tolerance."""
+    tol = 1e-12
+    o = orc.Oracle(card("small_2d", krylov_tol=tol))
+    keys, c0 = _full_state(o)
+    o.set_state(keys, c0)
+    fwd = [o.sil_step(dt=0.05, m=16)[0] for _ in range(20)]
+    bwd = [o.sil_step(dt=-0.05, m=16)[0] for _ in range(20)]
+    assert all(1 < k < 16 for k in fwd + bwd)
+    assert sorted(bwd) == sorted(fwd) or max(abs(a - b) for a, b in zip(sorted(fwd), sorted(bwd))) <= 1
+    _, c = o.state()
+    assert np.max(np.abs(c - c0)) < 100 * tol
+    # the same state stepped forward and backward picks the same order
+    for dt in (0.05, 0.02):
+        used = []
+        for sgn in (1.0, -1.0):
+            oo = orc.Oracle(card("small_2d", krylov_tol=1e-8))
+            oo.set_state(keys, c0)
+            used.append(oo.sil_step(dt=sgn * dt, m=16)[0])
+        assert used[0] == used[1] and 1 < used[0] < 16
+
+
 def test_reversibility():
     o = orc.Oracle(card("small_2d"))
     keys, c0 = _full_state(o)
@@ -925,6 +950,52 @@ def test_lattices_on_fourier_grids_are_similarity_of_fgh(basis):
     for k in range(2):
         c_back = np.moveaxis(np.tensordot(back[k], c_back, axes=([1], [k])), 0, k)
     assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
+
+@pytest.mark.parametrize("s", [2, 3])
+def test_pvb_lattice_geometry(s):
+    """Sec. II.B.1: the von Neumann lattice's cells have width dx = (hi-lo)/n_s
+    and centres x_s = lo + (s+1/2) dx; its momenta p_l are spaced dp with
+    dx dp = 2 pi and centred on zero; the Gaussians have alpha = dp/(2 dx).
+    Checked through the moments of the projected functions on a fine grid:
+    <x> = x_s, Var x = 1/(4 alpha) (|g|^2 ~ exp(-2 alpha (x-x_s)^2)), and from
+    the Fourier transform <p> = p_l, Var p = alpha."""
+    lo, hi, ns, nl = -3.0, 9.0, 6, 8
+    q, dxg = sine_dvr_grid(1201, lo, hi)
+    G = pvb_projection(q, dxg, lo, hi, ns, nl)
+    dX = (hi - lo) / ns
+    dP = 2.0 * np.pi / dX
+    alpha = dP / (2.0 * dX)
+    k = 2.0 * np.pi * np.fft.fftfreq(q.size, dxg)
+    for l in range(nl):
+        g = G[:, s * nl + l] / np.sqrt(dxg)
+        w = np.abs(g) ** 2
+        assert abs(np.sum(w) * dxg - 1.0) < 1e-9          # normalised Gaussians
+        mx = np.sum(w * q) / np.sum(w)
+        vx = np.sum(w * (q - mx) ** 2) / np.sum(w)
+        ghat = np.abs(np.fft.fft(g)) ** 2
+        mp = np.sum(ghat * k) / np.sum(ghat)
+        vp = np.sum(ghat * (k - mp) ** 2) / np.sum(ghat)
+        assert abs(mx - (lo + (s + 0.5) * dX)) < 1e-9
+        assert abs(mp - (l - 0.5 * (nl - 1)) * dP) < 1e-8
+        assert abs(vx * 4.0 * alpha - 1.0) < 1e-8
+        assert abs(vp / alpha - 1.0) < 1e-8
+    # neighbouring momenta differ by dp = 2 pi / dx: the lattice has one function per phase-space cell of area 2 pi
+    assert abs(dX * dP - 2.0 * np.pi) < 1e-14
+
+
+def test_factor_values_closed_forms():
+    """Diagonal potential factors at points where their closed forms are
+    known: the Morse factor (1 - e^{-a (q - q0)})^2 is 0 at the minimum q0,
+    1/4 at q0 + ln 2 / a, 1 at q0 - ln 2 / a and tends to 1 (the
+    dissociation limit) far out; q^p is the plain power."""
+    from oracle.model import factor_values
+    a, q0 = 1.3, 0.4
+    q = np.array([q0, q0 + np.log(2.0) / a, q0 - np.log(2.0) / a, q0 + 40.0])
+    v = factor_values({"kind": "morse", "a": a, "q0": q0}, q)
+    assert np.allclose(v, [0.0, 0.25, 1.0, 1.0], rtol=0, atol=1e-14)
+    qq = np.array([-2.0, 0.5, 3.0])
+    assert np.allclose(factor_values({"kind": "power", "p": 3}, qq), [-8.0, 0.125, 27.0], rtol=0, atol=0)
+
 
 def test_pvb_coefficients_are_overlaps():
     """Eq. psi_exp_pvb: lattice coefficients are G^+ c_chi; G's columns are the projected Gaussians."""
