@@ -293,6 +293,21 @@ int ppq_observables(ppq_ctx *ctx, double eps, double *out);
    state give NaN.  PPQ_E_STATE without a state. */
 int ppq_expect_q(ppq_ctx *ctx, double *q);
 
+/* No-allocation form of ppq_expect_q, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, hosts
+   that forbid allocation): the same kernels and the same result, bit for
+   bit, but the grid-point table, the per-block partial sums and the result
+   live in a library-wide device array of 256 KiB (one per GPU, held until
+   the process ends) instead of context buffers; the call makes no device
+   allocation.  Needs D * max n_k doubles of table (always within the array
+   under this build's grid limits; PPQ_E_CAPACITY otherwise).  Every call on
+   one GPU uses that GPU's array: calls that overlap on one GPU (two host
+   threads, or contexts on different streams) race and must be serialised by
+   the caller.  Synchronises the context stream.  q: host array of D doubles.
+   PPQ_E_STATE without a state or when the array's device address could not
+   be obtained. */
+int ppq_expect_q_noalloc(ppq_ctx *ctx, double *q);
+
 /* Autocorrelation at twice the current time, C(2t) = <psi(t)*|psi(t)> =
    sum_I c_I^2 over the active set (no complex conjugate): valid when the
    initial packet is real (zero momentum) and the operator real symmetric,

@@ -298,6 +298,12 @@ class Propagator:
         self._call("ppq_expect_q", out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return out
 
+    def expect_q_noalloc(self):
+        """expect_q through the entry point that allocates no device memory."""
+        out = np.zeros(self.D)
+        self._call("ppq_expect_q_noalloc", out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return out
+
     def time_apply(self, nrep):
         ms = ctypes.c_double(0.0)
         self._call("ppq_time_apply", int(nrep), ctypes.byref(ms))

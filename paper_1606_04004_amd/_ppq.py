@@ -53,6 +53,7 @@ SIGNATURES = {
     "ppq_propagate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp]),
     "ppq_observables": (ctypes.c_int, [_vp, ctypes.c_double, _dp]),
     "ppq_expect_q": (ctypes.c_int, [_vp, _dp]),
+    "ppq_expect_q_noalloc": (ctypes.c_int, [_vp, _dp]),
     "ppq_acf_doubled": (ctypes.c_int, [_vp, _dp]),
     "ppq_set_potential_term": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, _dp]),
     "ppq_add_potential_derivative": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _i32p, _i32p,

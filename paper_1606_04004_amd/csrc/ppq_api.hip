@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -413,12 +414,23 @@ void ensure_zbuf(ppq_ctx *c)
 // ---- operator assembly -------------------------------------------------------
 // Grid points of dimension k: sine-DVR interior points of the box, or the
 // periodic Fourier grid x_j = lo + j (hi - lo) / n, j = 0..n-1.
-std::vector<double> dim_points(const ppq_ctx *c, int k)
+// (written into q[0..n_k), no allocation)
+void dim_points_into(const ppq_ctx *c, int k, double *q)
 {
     const int n = c->g.n[k];
-    if (!c->fgh[k]) return sine_dvr_points(n, c->lo[k], c->hi[k]);
-    std::vector<double> q(n);
-    for (int j = 0; j < n; ++j) q[j] = c->lo[k] + j * (c->hi[k] - c->lo[k]) / n;
+    const double lo = c->lo[k], hi = c->hi[k];
+    if (!c->fgh[k]) {
+        const double dx = (hi - lo) / (n + 1);
+        for (int i = 0; i < n; ++i) q[i] = lo + (i + 1) * dx;
+    } else {
+        for (int j = 0; j < n; ++j) q[j] = lo + j * (hi - lo) / n;
+    }
+}
+
+std::vector<double> dim_points(const ppq_ctx *c, int k)
+{
+    std::vector<double> q(c->g.n[k]);
+    dim_points_into(c, k, q.data());
     return q;
 }
 
@@ -1613,6 +1625,61 @@ void adjoint_backward(ppq_ctx *c, double2 C_N)
 // =============================================================================
 extern "C" {
 
+// ---- device scratch of the no-allocation entry point ------------------------
+// ppq_expect_q_noalloc keeps its grid-point table, its per-block partial sums
+// and its result in this file-scope array instead of context buffers, so it
+// allocates nothing.  Each device that runs the library holds its own copy
+// until the process ends.  In host code the array's name is only a host-side
+// stand-in: every host use goes through the device address taken once per
+// device with hipGetSymbolAddress (scratch_setup, called by ppq_create with
+// the device current).
+constexpr size_t NOALLOC_SCRATCH_BYTES = 256u * 1024u;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+hipError_t g_scratch_err[NOALLOC_MAX_DEVICES];
+bool g_scratch_done[NOALLOC_MAX_DEVICES];
+
+// Address of this device's scratch (the current device must be `device`).
+void scratch_setup(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
+}
+
+void *scratch_of(int device, hipError_t *err)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *err = g_scratch_done[device] ? g_scratch_err[device] : hipErrorNotInitialized;
+    return g_scratch_ptr[device];
+}
+
+// Bytes of scratch ppq_expect_q_noalloc needs: the D x nmax grid-point table
+// and the D results (rounded up to 256 bytes), then the (1 + MAXD) x
+// RED_BLOCKS complex partial sums of the fixed-shape reduction.
+size_t expect_q_scratch_bytes(int D, int nmax, size_t *off_out, size_t *off_partial)
+{
+    const size_t tab = sizeof(double) * (size_t)D * (size_t)nmax;
+    *off_out = tab;
+    const size_t head = (tab + sizeof(double) * MAXD + 255u) / 256u * 256u;
+    *off_partial = head;
+    return head + sizeof(double2) * (size_t)(1 + MAXD) * RED_BLOCKS;
+}
+}  // namespace
+
 int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
 {
     if (!out) return PPQ_E_ARG;
@@ -1630,6 +1697,7 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
     }
     try {
         ck(hipSetDevice(device), "hipSetDevice");
+        scratch_setup(device);  // once per device; a failure is reported by the entry point that needs it
         if (hip_stream) {
             c->stream = (hipStream_t)hip_stream;
         } else {
@@ -2301,6 +2369,47 @@ int ppq_expect_q(ppq_ctx *c, double *q)
            "grid points");
         expect_q(c->keys[c->cur], c->psi[c->cur], c->nact, c->g, c->qtab, NMAX_FIBER, nan_mask, c->partial, res,
                  c->stream);
+        ck(hipGetLastError(), "expect_q launch");
+        ck(hipStreamSynchronize(c->stream), "expect_q");
+        ck(hipMemcpy(q, res, sizeof(double) * D, hipMemcpyDeviceToHost), "expect_q result");
+    })
+    return PPQ_OK;
+}
+
+int ppq_expect_q_noalloc(ppq_ctx *c, double *q)
+{
+    PPQ_GUARD(c)
+    if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
+    if (!q) return fail(c, PPQ_E_ARG, "bad arguments");
+    hipError_t serr;
+    unsigned char *base = (unsigned char *)scratch_of(c->device, &serr);
+    if (!base) return fail(c, PPQ_E_STATE, "device scratch unavailable (hipGetSymbolAddress failed)");
+    const int D = c->g.D;
+    int nmax = 1;
+    for (int k = 0; k < D; ++k) nmax = std::max(nmax, c->g.n[k]);
+    size_t off_out, off_partial;
+    const size_t need = expect_q_scratch_bytes(D, nmax, &off_out, &off_partial);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(c, PPQ_E_CAPACITY, "grid-point table exceeds the no-allocation scratch");
+    PPQ_TRY(c, {
+        // host staging of the table on the stack; the copy is waited for below
+        double tab[MAXD * NMAX_FIBER];
+        unsigned nan_mask = 0;
+        for (int k = 0; k < D; ++k) {
+            if (c->lattice[k]) {
+                nan_mask |= 1u << k;
+                for (int i = 0; i < nmax; ++i) tab[(size_t)k * nmax + i] = 0.0;
+                continue;
+            }
+            dim_points_into(c, k, tab + (size_t)k * nmax);
+            for (int i = c->g.n[k]; i < nmax; ++i) tab[(size_t)k * nmax + i] = 0.0;
+        }
+        double *dtab = (double *)base;
+        double *res = (double *)(base + off_out);
+        double2 *partial = (double2 *)(base + off_partial);
+        ck(hipMemcpyAsync(dtab, tab, sizeof(double) * (size_t)D * nmax, hipMemcpyHostToDevice, c->stream),
+           "grid points");
+        expect_q(c->keys[c->cur], c->psi[c->cur], c->nact, c->g, dtab, nmax, nan_mask, partial, res, c->stream);
         ck(hipGetLastError(), "expect_q launch");
         ck(hipStreamSynchronize(c->stream), "expect_q");
         ck(hipMemcpy(q, res, sizeof(double) * D, hipMemcpyDeviceToHost), "expect_q result");
