@@ -64,6 +64,22 @@ def sine_dvr_kinetic(n, lo, hi, mass):
     return T
 
 
+def is_dense(f):
+    return f["kind"] == "dense"
+
+
+def dense_matrix(f):
+    """A dense factor's matrix in the dimension's DVR basis: "re" plus i "im"."""
+    h = np.array(f["re"], dtype=np.float64)
+    if "im" in f:
+        h = h + 1j * np.array(f["im"], dtype=np.float64)
+    return np.asarray(h, dtype=np.complex128)
+
+
+def term_coef(t):
+    return complex(t["coef"], t.get("coef_im", 0.0))
+
+
 def factor_values(f, q):
     if f["kind"] == "power":
         return q ** f["p"]
@@ -154,15 +170,29 @@ class Model:
             return np.asarray(h, dtype=np.complex128)
         return self.G[k].conj().T @ h @ self.GinvH[k]
 
+    def factor_matrix(self, f):
+        """A factor as a matrix in its dimension's DVR basis (diagonal kinds on the diagonal)."""
+        if is_dense(f):
+            return dense_matrix(f)
+        return np.diag(factor_values(f, self.q[f["dim"]])).astype(np.complex128)
+
+    def is_product_term(self, t):
+        """True for a term applied as a product of matrices: any dense factor
+        or a complex coefficient (DVR), any term on two or more dimensions
+        (lattice, where every factor is dense)."""
+        if self.pvb:
+            return len(set(f["dim"] for f in t["factors"])) > 1
+        return any(is_dense(f) for f in t["factors"]) or t.get("coef_im", 0.0) != 0.0
+
     def single_dim_ops(self):
-        """Per dim: kinetic plus every one-factor potential term (dense in the lattice)."""
+        """Per dim: kinetic plus every one-factor term (dense in the lattice)."""
         ops = [self.transform(k, self.T[k]) for k in range(self.D)]
         if self.pvb:
             for t in self.card["terms"]:
                 if len(t["factors"]) == 1:
                     f = t["factors"][0]
                     k = f["dim"]
-                    ops[k] = ops[k] + t["coef"] * self.transform(k, np.diag(factor_values(f, self.q[k])))
+                    ops[k] = ops[k] + term_coef(t) * self.transform(k, self.factor_matrix(f))
         return ops
 
     def diag_terms(self):
@@ -171,6 +201,8 @@ class Model:
         if self.pvb:
             return out
         for t in self.card["terms"]:
+            if self.is_product_term(t):
+                continue
             tabs = {}
             coef = t["coef"]
             for f in t["factors"]:
@@ -180,22 +212,41 @@ class Model:
             out.append((coef, tabs))
         return out
 
-    def pair_terms(self):
-        """Lattice only: two-factor potential terms as (coef, k1, h1, k2, h2), k1 < k2."""
+    def product_terms(self):
+        """Terms applied as products of matrices (Sec. II.B.2), as
+        (coef, dims increasing, matrices acting on the coefficients): the
+        factors on distinct dimensions, each the factor's matrix (lattice:
+        transformed like the kinetic matrix)."""
         out = []
-        if not self.pvb:
-            return out
         for t in self.card["terms"]:
-            if len(t["factors"]) == 1:
+            if not self.is_product_term(t):
                 continue
-            if len(t["factors"]) != 2:
-                raise ValueError("lattice cards support one- and two-factor terms")
-            f1, f2 = sorted(t["factors"], key=lambda f: f["dim"])
-            k1, k2 = f1["dim"], f2["dim"]
-            h1 = self.transform(k1, np.diag(factor_values(f1, self.q[k1])))
-            h2 = self.transform(k2, np.diag(factor_values(f2, self.q[k2])))
-            out.append((t["coef"], k1, h1, k2, h2))
+            fs = sorted(t["factors"], key=lambda f: f["dim"])
+            dims = [f["dim"] for f in fs]
+            if len(set(dims)) != len(dims):
+                raise ValueError("a product term takes one factor per dimension")
+            mats = [self.transform(f["dim"], self.factor_matrix(f)) for f in fs]
+            out.append((term_coef(t), dims, mats))
         return out
+
+    def hermitian(self):
+        """True when the pruned operator is Hermitian, so the propagator may be
+        Lanczos: a DVR basis whose product terms each have one dense factor,
+        Hermitian, and a real coefficient (diagonal factors commute with the
+        truncation).  Two or more dense factors truncated in sequence, a
+        complex coefficient or a lattice basis make it non-Hermitian."""
+        if self.pvb:
+            return False
+        for t in self.card["terms"]:
+            if not self.is_product_term(t):
+                continue
+            dense = [f for f in t["factors"] if is_dense(f)]
+            if t.get("coef_im", 0.0) != 0.0 or len(dense) != 1:
+                return False
+            h = dense_matrix(dense[0])
+            if not np.array_equal(h, h.conj().T):
+                return False
+        return True
 
     def potential_full(self):
         """V on the full grid (DVR cards; tiny grids only)."""

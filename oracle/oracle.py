@@ -38,6 +38,7 @@ def lib():
         L.orc_add_vterm.argtypes = [vp, ctypes.c_double, _c_i32_p, _c_double_p]
         L.orc_add_pair.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                    _c_double_p, _c_double_p]
+        L.orc_add_prod.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _c_i32_p, _c_double_p]
         L.orc_set_lattice.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_apply_def.argtypes = [vp, ctypes.c_int64, _c_u64_p, _c_double_p, _c_double_p]
         L.orc_fib_build.restype = vp
@@ -139,10 +140,11 @@ class Oracle:
                 use[k] = 1
                 tab[k, : v.size] = v
             L.orc_add_vterm(self._m, float(coef), _ip(use), _dp(tab))
-        for coef, k1, h1, k2, h2 in m.pair_terms():
-            a, b = _cplx(h1), _cplx(h2)
-            L.orc_add_pair(self._m, float(np.real(coef)), float(np.imag(coef)), k1, k2,
-                           _dp(a.view(np.float64)), _dp(b.view(np.float64)))
+        for coef, dims, mats in m.product_terms():
+            flat = np.concatenate([_cplx(h).ravel() for h in mats])
+            if L.orc_add_prod(self._m, float(np.real(coef)), float(np.imag(coef)), len(dims),
+                              _ip(np.array(dims, dtype=np.int32)), _dp(flat.view(np.float64))) != 0:
+                raise ValueError("bad product term")
         if m.pvb:
             ns, nl = m.lattice
             for k in range(self.D):
@@ -151,7 +153,7 @@ class Oracle:
             raise ValueError("krylov_tol must be >= 0")
         if card.get("stencil", 1) != 1 and L.orc_set_stencil(self._m, int(card["stencil"])) != 0:
             raise ValueError("stencil must be 1, 2 or 3")
-        self.arnoldi = 1 if m.pvb else 0
+        self.arnoldi = 0 if m.hermitian() else 1
         self._init_tabs = self._pack(m.init_tables())
         self._bra_tabs = self._pack(m.bra_tables())
         self._s = L.orc_state_new()

@@ -53,10 +53,13 @@ typedef struct orc_model {
     double *vcoef;
     int *vuse;                  /* [nv][D] */
     double *vtab;               /* [nv][D][nmax] */
-    int np;                     /* product terms with two dense factors */
+    int np;                     /* product terms with dense factors */
     zd *pcoef;
-    int *pk1, *pk2;             /* applied as coef * h1(k1) (h2(k2) x), k2 first */
-    zd **ph1, **ph2;
+    int *pnf;                   /* [np] number of factors */
+    int *pk;                    /* [np][ORC_MAXD] their dimensions, increasing */
+    zd **ph;                    /* [np][ORC_MAXD] their n_k x n_k matrices; applied
+                                   coef * P h_0 P h_1 ... P h_{nf-1} P x, the last
+                                   (highest) dimension first */
     int lat_s[ORC_MAXD], lat_l[ORC_MAXD]; /* phase-space lattice shape per dim; 0 = line */
     int stencil;                /* adaption neighbours: 1 = ball radius 1, 2 = radius sqrt(2), 3 = radius 2 */
     double krylov_tol;          /* > 0: SIL order chosen per step by the error estimate */
@@ -86,8 +89,9 @@ void orc_free(orc_model *m)
     if (!m) return;
     for (int k = 0; k < m->D; ++k) free(m->h[k]);
     free(m->vcoef); free(m->vuse); free(m->vtab);
-    for (int t = 0; t < m->np; ++t) { free(m->ph1[t]); free(m->ph2[t]); }
-    free(m->pcoef); free(m->pk1); free(m->pk2); free(m->ph1); free(m->ph2);
+    for (int t = 0; t < m->np; ++t)
+        for (int f = 0; f < m->pnf[t]; ++f) free(m->ph[t * ORC_MAXD + f]);
+    free(m->pcoef); free(m->pnf); free(m->pk); free(m->ph);
     free(m);
 }
 
@@ -127,22 +131,49 @@ int orc_add_vterm(orc_model *m, double coef, const int32_t *use, const double *t
     return 0;
 }
 
-/* Product term coef * h1(k1) (x) h2(k2) with k1 < k2, both dense complex. */
-int orc_add_pair(orc_model *m, double cre, double cim, int k1, int k2, const double *h1, const double *h2)
+/* Product term (cre + i cim) * h_0(dims[0]) (x) ... (x) h_{nf-1}(dims[nf-1]) of a
+   sum-of-products operator (Sec. II.B.2), dims strictly increasing, each h_f
+   a dense complex n_k x n_k matrix (interleaved re,im; row-major), the
+   matrices concatenated in factor order.  On an active set it is applied as
+   the sequential product of Eq. matvecprod_sequential with every
+   intermediate truncated to the set: the factor of the highest dimension
+   first (the innermost sum runs over the last index), then the next lower. */
+int orc_add_prod(orc_model *m, double cre, double cim, int nf, const int32_t *dims, const double *mats)
 {
-    if (k1 < 0 || k2 < 0 || k1 >= m->D || k2 >= m->D || k1 == k2) return -1;
+    if (nf < 1 || nf > m->D) return -1;
+    for (int f = 0; f < nf; ++f) {
+        if (dims[f] < 0 || dims[f] >= m->D) return -1;
+        if (f > 0 && dims[f] <= dims[f - 1]) return -1;
+    }
     int t = m->np++;
     m->pcoef = realloc(m->pcoef, sizeof(zd) * m->np);
-    m->pk1 = realloc(m->pk1, sizeof(int) * m->np);
-    m->pk2 = realloc(m->pk2, sizeof(int) * m->np);
-    m->ph1 = realloc(m->ph1, sizeof(zd *) * m->np);
-    m->ph2 = realloc(m->ph2, sizeof(zd *) * m->np);
+    m->pnf = realloc(m->pnf, sizeof(int) * m->np);
+    m->pk = realloc(m->pk, sizeof(int) * ORC_MAXD * m->np);
+    m->ph = realloc(m->ph, sizeof(zd *) * ORC_MAXD * m->np);
     m->pcoef[t] = cre + I * cim;
-    m->pk1[t] = k1;
-    m->pk2[t] = k2;
-    m->ph1[t] = copy_cmat(h1, m->n[k1]);
-    m->ph2[t] = copy_cmat(h2, m->n[k2]);
+    m->pnf[t] = nf;
+    size_t off = 0;
+    for (int f = 0; f < nf; ++f) {
+        int nk = m->n[dims[f]];
+        m->pk[t * ORC_MAXD + f] = dims[f];
+        m->ph[t * ORC_MAXD + f] = copy_cmat(mats + off, nk);
+        off += 2 * (size_t)nk * nk;
+    }
     return 0;
+}
+
+/* Two-factor product term coef * h1(k1) (x) h2(k2), k1 < k2. */
+int orc_add_pair(orc_model *m, double cre, double cim, int k1, int k2, const double *h1, const double *h2)
+{
+    if (k1 < 0 || k2 < 0 || k1 >= m->D || k2 >= m->D || k1 >= k2) return -1;
+    size_t n1 = 2 * (size_t)m->n[k1] * m->n[k1], n2 = 2 * (size_t)m->n[k2] * m->n[k2];
+    double *mats = malloc(sizeof(double) * (n1 + n2));
+    memcpy(mats, h1, sizeof(double) * n1);
+    memcpy(mats + n1, h2, sizeof(double) * n2);
+    int32_t dims[2] = {k1, k2};
+    int r = orc_add_prod(m, cre, cim, 2, dims, mats);
+    free(mats);
+    return r;
 }
 
 int orc_set_lattice(orc_model *m, int k, int ns, int nl)
@@ -217,9 +248,13 @@ int orc_apply_def(const orc_model *m, int64_t n, const uint64_t *keys, const dou
         for (int64_t p = 0; p < n; ++p) y[p] += tmp[p];
     }
     for (int t = 0; t < m->np; ++t) {
-        def_dim(m, m->pk2[t], m->ph2[t], n, keys, x, z);      /* P h2 P x */
-        def_dim(m, m->pk1[t], m->ph1[t], n, keys, z, tmp);    /* P h1 P z */
-        for (int64_t p = 0; p < n; ++p) y[p] += m->pcoef[t] * tmp[p];
+        /* P h_{nf-1} P x first, then each lower factor on the truncated result */
+        for (int64_t p = 0; p < n; ++p) z[p] = x[p];
+        for (int f = m->pnf[t] - 1; f >= 0; --f) {
+            def_dim(m, m->pk[t * ORC_MAXD + f], m->ph[t * ORC_MAXD + f], n, keys, z, tmp);
+            for (int64_t p = 0; p < n; ++p) z[p] = tmp[p];
+        }
+        for (int64_t p = 0; p < n; ++p) y[p] += m->pcoef[t] * z[p];
     }
     free(tmp);
     free(z);
@@ -368,9 +403,12 @@ int orc_apply_fib(const orc_model *m, const orc_fib *f, const double *xin, doubl
     if (m->np) {
         zd *z = malloc(sizeof(zd) * nn), *t2 = malloc(sizeof(zd) * nn);
         for (int t = 0; t < m->np; ++t) {
-            fib_dim(m, f, m->pk2[t], m->ph2[t], x, z, 0, xp, yp);
-            fib_dim(m, f, m->pk1[t], m->ph1[t], z, t2, 0, xp, yp);
-            for (int64_t p = 0; p < n; ++p) y[p] += m->pcoef[t] * t2[p];
+            for (int64_t p = 0; p < n; ++p) z[p] = x[p];
+            for (int g = m->pnf[t] - 1; g >= 0; --g) {
+                fib_dim(m, f, m->pk[t * ORC_MAXD + g], m->ph[t * ORC_MAXD + g], z, t2, 0, xp, yp);
+                for (int64_t p = 0; p < n; ++p) z[p] = t2[p];
+            }
+            for (int64_t p = 0; p < n; ++p) y[p] += m->pcoef[t] * z[p];
         }
         free(z);
         free(t2);

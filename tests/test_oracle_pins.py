@@ -16,6 +16,7 @@ import scipy.linalg as sla
 from oracle import oracle as orc
 from oracle.model import Model, sine_dvr_grid, sine_dvr_kinetic, pvb_projection
 from workloads import card, random_active_set, random_complex, random_dense_factor
+from workloads.cards import _power
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -45,7 +46,7 @@ def dense_h(model):
 class RandomOp:
     """Random non-Hermitian SoP operator made directly in the C oracle."""
 
-    def __init__(self, n, seed, nv=3, npair=2):
+    def __init__(self, n, seed, nv=3, npair=2, ntriple=1):
         L = orc.lib()
         rng = np.random.default_rng(seed)
         self.n = list(n)
@@ -74,6 +75,16 @@ class RandomOp:
             L.orc_add_pair(self.m, c.real, c.imag, int(k1), int(k2),
                            orc._dp(np.ascontiguousarray(h1).view(np.float64)),
                            orc._dp(np.ascontiguousarray(h2).view(np.float64)))
+        # products of three dense factors (general sum-of-products terms)
+        self.prods = []
+        for t in range(ntriple if D > 2 else 0):
+            ks = sorted(int(v) for v in rng.choice(D, size=3, replace=False))
+            hs = [random_dense_factor(n[k], seed + 300 + 10 * t + i) for i, k in enumerate(ks)]
+            c = complex(rng.standard_normal(), rng.standard_normal())
+            self.prods.append((c, ks, hs))
+            flat = np.concatenate([np.ascontiguousarray(h).ravel() for h in hs])
+            assert L.orc_add_prod(self.m, c.real, c.imag, 3, orc._ip(np.array(ks, dtype=np.int32)),
+                                  orc._dp(flat.view(np.float64))) == 0
 
     def __del__(self):
         orc.lib().orc_free(self.m)
@@ -100,6 +111,11 @@ class RandomOp:
             A = kron_dim(n, k1, h1)[np.ix_(idx, idx)]
             B = kron_dim(n, k2, h2)[np.ix_(idx, idx)]
             Hr = Hr + c * (A @ B)
+        for c, ks, hs in self.prods:
+            P = np.eye(idx.size, dtype=np.complex128)
+            for k, h in zip(ks, hs):
+                P = P @ kron_dim(n, k, h)[np.ix_(idx, idx)]
+            Hr = Hr + c * P
         return Hr
 
     def apply_def(self, keys, x):
@@ -228,6 +244,81 @@ def test_apply_fib_equals_def(n, seed):
         yd = op.apply_def(keys, x)
         yf = op.apply_fib(keys, x)
         assert np.max(np.abs(yd - yf)) <= 1e-12 * max(1.0, np.max(np.abs(yd)))
+
+
+def _card_dense_pruned(cd, keys):
+    """Dense reference of a card's pruned operator on a set, built here from
+    the card's matrices: the kinetic Kronecker sum and the diagonal potential
+    restricted to the set, plus every product term as the product of its
+    factors' restricted Kronecker matrices (lowest dimension leftmost, so the
+    highest acts first, each intermediate truncated to the set)."""
+    from oracle.model import dense_matrix, factor_values, sine_dvr_grid, sine_dvr_kinetic
+    n = cd["n"]
+    D = len(n)
+    idx = np.asarray(keys, dtype=np.int64)
+    q = [sine_dvr_grid(n[k], cd["lo"][k], cd["hi"][k])[0] for k in range(D)]
+    H = np.zeros((idx.size, idx.size), dtype=np.complex128)
+    for k in range(D):
+        H += kron_dim(n, k, sine_dvr_kinetic(n[k], cd["lo"][k], cd["hi"][k], cd["mass"]))[np.ix_(idx, idx)]
+    digits = np.unravel_index(idx, n)
+    for t in cd["terms"]:
+        coef = complex(t["coef"], t.get("coef_im", 0.0))
+        fs = sorted(t["factors"], key=lambda f: f["dim"])
+        if all(f["kind"] != "dense" for f in fs) and coef.imag == 0.0:
+            v = np.full(idx.size, coef.real)
+            for f in fs:
+                v = v * factor_values(f, q[f["dim"]])[digits[f["dim"]]]
+            H += np.diag(v)
+            continue
+        P = np.eye(idx.size, dtype=np.complex128)
+        for f in fs:
+            h = dense_matrix(f) if f["kind"] == "dense" else np.diag(factor_values(f, q[f["dim"]]))
+            P = P @ kron_dim(n, f["dim"], h)[np.ix_(idx, idx)]
+        H += coef * P
+    return H
+
+
+@pytest.mark.parametrize("fill,seed", [(1.0, 1), (0.45, 2), (0.2, 3)])
+def test_card_product_terms_match_dense(fill, seed):
+    """General sum-of-products terms of a card (dense real and complex
+    factors, complex coefficients, a three-factor product, diagonal factors
+    in a product): O-def and O-fib equal the dense restricted products."""
+    cd = card("sop3d")
+    o = orc.Oracle(cd)
+    keys = np.arange(int(np.prod(cd["n"]))) if fill == 1.0 else random_active_set(cd["n"], fill, seed)
+    x = random_complex(keys.size, seed + 40)
+    ref = _card_dense_pruned(cd, keys) @ x
+    y_def = o.apply_def(keys, x)
+    assert np.max(np.abs(y_def - ref)) < 1e-13 * np.max(np.abs(ref))
+    y_fib = o.apply_fib(keys, x)
+    assert np.max(np.abs(y_fib - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_product_terms_hermiticity_and_arnoldi():
+    """A product term keeps the pruned operator Hermitian only with one dense
+    Hermitian factor and a real coefficient (diagonal factors commute with
+    the truncation); then the oracle steps with Lanczos, else Arnoldi, and
+    one step of either equals exp(-i H dt) psi on the full grid (scipy)."""
+    base = card("small_3d")
+    sop = card("sop3d")
+    herm = dict(base, terms=base["terms"] + sop["terms"][6:7])   # symmetric dense x diagonal
+    cases = [(base, True), (herm, True), (sop, False),
+             (dict(base, terms=base["terms"] + sop["terms"][7:8]), False),   # complex pair
+             (dict(base, terms=base["terms"] + sop["terms"][9:10]), False)]  # complex diagonal
+    for cd, want in cases:
+        o = orc.Oracle(cd)
+        assert o.model.hermitian() == want
+        assert o.arnoldi == (0 if want else 1)
+        keys = np.arange(int(np.prod(cd["n"])))
+        c0 = random_complex(keys.size, 5)
+        c0 /= np.linalg.norm(c0)
+        H = _card_dense_pruned(cd, keys)
+        if want:
+            assert np.max(np.abs(H - H.conj().T)) < 1e-13
+        o.set_state(keys, c0)
+        o.sil_step(dt=0.05, m=16)
+        _, c1 = o.state()
+        assert np.max(np.abs(c1 - sla.expm(-0.05j * H) @ c0)) < 1e-11
 
 
 def test_apply_single_point_and_empty():
@@ -879,6 +970,37 @@ def test_pvb_unpruned_dynamics_is_similarity_of_dvr():
     _, clat = ol.state()
     c_back = clat.reshape(ol.n)
     for k in range(4):
+        c_back = np.moveaxis(np.tensordot(ol.model.GinvH[k], c_back, axes=([1], [k])), 0, k)
+    assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
+
+
+@pytest.mark.parametrize("basis", ["pvb", "pw"])
+def test_lattice_three_factor_terms_are_similarity_of_dvr(basis):
+    """A three-factor product term (the 6D model's q_k q_l q_m couplings) and
+    a dense factor in a phase-space lattice basis: the unpruned lattice
+    dynamics maps back to the DVR dynamics (a similarity, every factor
+    transformed as G^+ h G^{-+}; W^T h W for Weylets)."""
+    base = card("small_3d", n=[12, 12, 12])
+    rng = np.random.default_rng(4)
+    sym = 0.02 * rng.standard_normal((12, 12))
+    base["terms"] = base["terms"] + [
+        {"coef": 0.004, "factors": [_power(0, 1), _power(1, 1), _power(2, 1)]},
+        {"coef": 0.1, "factors": [{"dim": 1, "kind": "dense", "re": (sym + sym.T).tolist()}, _power(0, 1)]},
+    ]
+    lat = dict(base, basis=basis, lattice=[3, 4])
+    od = orc.Oracle(base)
+    ol = orc.Oracle(lat)
+    kd, cd0 = _full_state(od)
+    kl, cl0 = _full_state(ol)
+    od.set_state(kd, cd0)
+    ol.set_state(kl, cl0)
+    td, _ = od.propagate(nsteps=6, dt=0.05, m=14, prune=False)
+    tl, _ = ol.propagate(nsteps=6, dt=0.05, m=14, prune=False)
+    assert np.max(np.abs((td[:, 3] + 1j * td[:, 4]) - (tl[:, 3] + 1j * tl[:, 4]))) < 1e-9
+    _, cdv = od.state()
+    _, clat = ol.state()
+    c_back = clat.reshape(ol.n)
+    for k in range(3):
         c_back = np.moveaxis(np.tensordot(ol.model.GinvH[k], c_back, axes=([1], [k])), 0, k)
     assert np.max(np.abs(c_back.ravel() - cdv)) < 1e-9
 

@@ -11,6 +11,9 @@ A card is a plain dict:
                                   f = {"dim": k, "kind": "power", "p": p}     (q_k**p)
                                    or {"dim": k, "kind": "morse", "a": a, "q0": q0}
                                                                   ((1-exp(-a(q_k-q0)))**2)
+                                   or {"dim": k, "kind": "dense", "re": [[..]], "im": [[..]]}
+                                      (an n_k x n_k matrix in the DVR basis, "im" optional);
+                                  "coef_im" (optional) makes the coefficient complex
   fgh (optional)                  dimensions on a periodic Fourier grid (odd n_k) instead
                                   of the sine-DVR
   dim_factors (optional)          {k: n_k x n_k real symmetric matrix} replacing the
@@ -146,6 +149,39 @@ def _adjoint4d():
     }
 
 
+def _dense(k, rng, n, scale, kind):
+    """A seeded dense factor on dimension k: "sym" real symmetric, "real"
+    real, "complex" complex (re and im parts drawn independently)."""
+    a = scale * rng.standard_normal((n, n))
+    f = {"dim": k, "kind": "dense"}
+    if kind == "sym":
+        a = 0.5 * (a + a.T)
+    f["re"] = a.tolist()
+    if kind == "complex":
+        f["im"] = (scale * rng.standard_normal((n, n))).tolist()
+    return f
+
+
+def _sop3d():
+    """small_3d's model plus general sum-of-products terms: a real symmetric
+    dense factor times a diagonal one, a complex two-factor product with a
+    complex coefficient, a three-factor real product and a diagonal term
+    with a complex coefficient (drawn once, seed 77)."""
+    c = card("small_3d")
+    rng = np.random.default_rng(77)
+    n = c["n"]
+    c["terms"] = c["terms"] + [
+        {"coef": 0.3, "factors": [_dense(0, rng, n[0], 0.05, "sym"), _power(2, 1)]},
+        {"coef": 0.05, "coef_im": 0.02, "factors": [_dense(1, rng, n[1], 0.1, "complex"),
+                                                    _dense(2, rng, n[2], 0.1, "real")]},
+        {"coef": 0.02, "factors": [_dense(0, rng, n[0], 0.1, "real"), _dense(1, rng, n[1], 0.1, "real"),
+                                   _dense(2, rng, n[2], 0.1, "real")]},
+        {"coef": 0.01, "coef_im": -0.003, "factors": [_power(0, 2)]},
+    ]
+    c["name"] = "sop3d"
+    return c
+
+
 _BUILDERS = {
     "hh2d": _hh2d, "morse4d": _morse4d, "quartic6d": _quartic6d,
     "pvb4d": _pvb4d, "adjoint4d": _adjoint4d,
@@ -162,6 +198,8 @@ def card(name, **overrides):
       small_4d  -> the 4D Morse model on 10 points per dimension
       small_6d  -> the 6D quartic model on 7 points per dimension
       small_adjoint4d -> the adjoint card on 10 points per dimension, 20 steps
+      sop3d     -> small_3d with general sum-of-products terms (dense factors,
+                   complex coefficients, a three-factor product)
     """
     if name in _BUILDERS:
         c = _BUILDERS[name]()
@@ -190,6 +228,8 @@ def card(name, **overrides):
     elif name == "small_adjoint4d":
         c = _adjoint4d()
         c.update({"name": "small_adjoint4d", "n": [10] * 4, "eps": 1e-4, "nsteps": 20, "checkpoint_every": 5})
+    elif name == "sop3d":
+        c = _sop3d()
     elif name == "small_6d":
         c = _quartic6d(n=7)
         c.update({"name": "small_6d", "eps": 1e-4, "nsteps": 10})
