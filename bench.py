@@ -57,20 +57,60 @@ def describe(cd):
             f"[{cd['lo'][0]},{cd['hi'][0]}]^{cd['D']}, eps={cd['eps']}, dt={cd['dt']}, m={cd['krylov']}")
 
 
-def cpu_baseline(cd, reps=50):
-    """The FP64 oracle (one thread) applying H on its own initial set of the card."""
+def cpu_baseline(cd, reps=9, max_threads=16):
+    """The FP64 oracle as it stands (O-fib, the appendix algorithm, serial C)
+    on its own initial set of the card, which stands in for the GPU's
+    step-250 snapshot (3.52M against 3.60M functions; the oracle would need
+    about 20 minutes to propagate there, and its inputs never come from the
+    GPU path).  One thread: the median of `reps` products, and one whole step
+    (SIL step of the card's order, adaption, rebuild of the permutations).
+    All cores: that many threads each applying H to the same set at once (the
+    oracle's tables are read-only, and ctypes releases the GIL during the
+    call), aggregate rate."""
+    import threading
     from oracle.oracle import Oracle
     o = Oracle(cd)
     o.init_state()
     keys, c = o.state()
+    n = keys.size
     o.apply_current(c)  # builds the stored permutations (not timed)
-    t0 = time.perf_counter()
+    times = []
     for _ in range(reps):
+        t0 = time.perf_counter()
         o.apply_current(c)
-    dt = time.perf_counter() - t0
-    return {"value": keys.size * reps / dt, "unit": "active-point updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} O-fib H*psi products on the oracle's initial set of the 6D quartic card "
-                      f"(|A0| = {keys.size}), single thread, {dt:.1f} s"}
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    nthreads = max(1, min(os.cpu_count() or 1, max_threads))
+    per_thread = 3
+    xs = [c.copy() for _ in range(nthreads)]
+
+    def work(i):
+        for _ in range(per_thread):
+            o.apply_current(xs[i])
+    th = [threading.Thread(target=work, args=(i,)) for i in range(nthreads)]
+    t0 = time.perf_counter()
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    wall = time.perf_counter() - t0
+    agg = n * nthreads * per_thread / wall
+    t0 = time.perf_counter()
+    o.sil_step()
+    o.prune()
+    o.apply_current(o.state()[1])  # rebuilds the permutations of the new set
+    step_s = time.perf_counter() - t0
+    try:
+        cpu_model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except (OSError, IndexError):
+        cpu_model = "unknown"
+    return {"value": agg, "unit": "active-point updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"O-fib H*psi on the oracle's initial set of the 6D quartic card (|A0| = {n}): "
+                      f"{nthreads} threads x {per_thread} products at once ({wall:.1f} s); one thread: median of "
+                      f"{reps} products and one whole step",
+            "one_thread": {"hpsi_median_s": med, "updates_per_s": n / med, "step_s": step_s,
+                           "step_updates_per_s": cd["krylov"] * n / step_s},
+            "host": {"nproc": os.cpu_count(), "cpu": cpu_model}}
 
 
 def timed_steps(g, steps, warmup):
@@ -104,7 +144,7 @@ def secondary(stream, steps, warmup, adjoint_steps):
         g.reserve(min(16_000_000, int(np.prod(cd["n"]))))  # as for the headline
         g.init_state()
         g.propagate(nsteps=20)
-        ms_h = g.time_apply(20)
+        ms_h = g.time_apply(100)
         na = g.active_count()
         rate, ms, _ = timed_steps(g, steps, warmup)
         out[f"morse4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "hpsi_updates_per_s": na / (ms_h * 1e-3),
@@ -116,10 +156,23 @@ def secondary(stream, steps, warmup, adjoint_steps):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
         g.reserve(min(16_000_000, int(np.prod(cd["n"]))))  # as for the headline
         g.init_state()
-        ms_h = g.time_apply(10)
+        ms_h = g.time_apply(100)
         na = g.active_count()
+        nf = g.fiber_counts()
+        # algorithmic flops of one product: a complex factor application costs
+        # 8 L flops per point for fibers of mean length L = |A| / nf_k; one per
+        # dimension for the single-dimension factors and two per pair term
+        apps = [k for k in range(cd["D"])]
+        for t in cd["terms"]:
+            dims = sorted(set(f["dim"] for f in t["factors"]))
+            if len(dims) > 1:
+                apps += dims
+        alg = float(sum(8.0 * na * (na / nf[k]) for k in apps))
         rate, ms, _ = timed_steps(g, steps, warmup)
         out[f"pvb4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
+                               "factor_applications": len(apps),
+                               "algorithmic_gflop_per_product": alg / 1e9,
+                               "algorithmic_tflops": alg / (ms_h * 1e-3) / 1e12,
                                "from": "initial set of the 4D phase-space lattice card (48^4, 6x8 lattice per "
                                        "dimension), complex factors on the matrix cores"}
         del g
@@ -129,16 +182,18 @@ def secondary(stream, steps, warmup, adjoint_steps):
         g.reserve(min(16_000_000, int(np.prod(cd["n"]))))  # as for the headline
         g.init_state()
         na = g.active_count()
-        ms_h = g.time_apply(10)
+        ms_h = g.time_apply(100)
         rate, ms, _ = timed_steps(g, steps, warmup)
         out[f"pw4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
                               "from": "initial set of the 4D Morse model in projected Weylets (48^4, 6x8 "
                                       "doubly dense lattice per dimension)"}
         del g
     cd = card("adjoint4d", nsteps=adjoint_steps)
+    grads = {}
     for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
         declare_trainable(g, cd)
+        print(f"[bench] adjoint {tag}: {adjoint_steps} steps ...", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         J = g.adjoint_record()
@@ -147,10 +202,18 @@ def secondary(stream, steps, warmup, adjoint_steps):
         dp, dc, dm = g.adjoint_gradient()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out[f"adjoint4d_{tag}"] = {"steps": adjoint_steps, "J": J, "forward_record_s": t1 - t0,
-                                   "backward_s": t2 - t1, "gradient_components": int(dp.size + dc.size + dm.size),
-                                   "grad_norm": float(np.sqrt(np.sum(dp ** 2) + np.sum(dc ** 2) + np.sum(dm ** 2)))}
+        grads[tag] = np.concatenate([dp, dc, dm])
+        out[f"adjoint4d_{tag}"] = {"steps": adjoint_steps, "checkpoint_every": cd["checkpoint_every"],
+                                   "dt": cd["dt"], "max_krylov_order": cd["krylov"],
+                                   "step_tolerance": 1e-12, "J": J, "forward_record_s": t1 - t0,
+                                   "backward_s": t2 - t1, "final_active": int(g.active_count()),
+                                   "gradient_components": int(grads[tag].size),
+                                   "grad_norm": float(np.linalg.norm(grads[tag]))}
         del g
+    out["adjoint4d_fp32"]["grad_max_rel_err_vs_fp64"] = float(
+        np.max(np.abs(grads["fp32"] - grads["fp64"])) / np.max(np.abs(grads["fp64"])))
+    out["adjoint4d_fp32"]["J_rel_err_vs_fp64"] = abs(out["adjoint4d_fp32"]["J"] - out["adjoint4d_fp64"]["J"]) / \
+        abs(out["adjoint4d_fp64"]["J"])
     out["hh2d_accuracy"] = accuracy_sweep(stream)
     return out
 
@@ -230,7 +293,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--workload", default="quartic6d")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -262,7 +325,7 @@ def main():
     snap_keys, snap_c = g.state()
     # isolated H*psi timing on the snapshot (HIP events on the context stream)
     n_snap = snap_keys.size
-    ms_h = g.time_apply(50)
+    ms_h, ms_h_mean = g.time_apply(100, mean=True)
     hpsi_rate = n_snap / (ms_h * 1e-3)
     bpp = bytes_per_point(D, 0)
     achieved = bpp * n_snap / (ms_h * 1e-3) / 1e9
@@ -306,6 +369,8 @@ def main():
         "steps_per_s": 1e3 / ms_step,
         "hpsi_updates_per_s": hpsi_rate,
         "hpsi_ms": ms_h,
+        "hpsi_ms_mean": ms_h_mean,
+        "hpsi_timing": "median of 100 back-to-back products (HIP events on the context stream)",
         "active_points_at_snapshot": int(n_snap),
         "phase_ms_per_step": phases,
         "higher_is_better": True,
@@ -332,7 +397,7 @@ def main():
         g32.reserve(cap)
         g32.init_state()
         g32.set_state(snap_keys, snap_c)
-        ms32 = g32.time_apply(50)
+        ms32 = g32.time_apply(100)
         value32, ms_step32, _ = timed_steps(g32, args.steps, args.warmup)
         bpp32 = bytes_per_point(D, 1)
         obs32 = g32.observables()

@@ -80,9 +80,13 @@ typedef enum {
     PPQ_FAC_POWER = 0,       /* q_k^p on the grid points;           params = {p, unused} */
     PPQ_FAC_MORSE = 1,       /* (1 - exp(-a (q_k - q0)))^2;          params = {a, q0}   */
     PPQ_FAC_TABLE = 2,       /* caller-supplied values at the n_k grid points          */
-    PPQ_FAC_MORSE_DA = 3     /* 2 (1 - e) e (q_k - q0), e = exp(-a (q_k - q0)): the
+    PPQ_FAC_MORSE_DA = 3,    /* 2 (1 - e) e (q_k - q0), e = exp(-a (q_k - q0)): the
                                 derivative of the Morse factor with respect to a;
                                 params = {a, q0}                                       */
+    PPQ_FAC_DENSE_REAL = 4,  /* dense real n_k x n_k matrix in the dimension's DVR
+                                basis, row-major (ppq_add_term only)                   */
+    PPQ_FAC_DENSE_COMPLEX = 5 /* dense complex n_k x n_k matrix, row-major, (re, im)
+                                interleaved (ppq_add_term only)                        */
 } ppq_factor_kind;
 
 /* Fields of one observable record (ppq_observables, ppq_propagate). */
@@ -94,8 +98,11 @@ enum {
     PPQ_OBS_ACF_IM = 4,      /* imaginary part */
     PPQ_OBS_NACTIVE = 5,     /* |A| */
     PPQ_OBS_NABOVE = 6,      /* |{I in A : |c_I| >= theta}| (1 - this/|A| is the wasted fraction, Sec. III.A) */
-    PPQ_OBS_KRYLOV = 7,      /* Krylov dimension used by the step that produced the record */
-    PPQ_OBS_N = 8
+    PPQ_OBS_KRYLOV = 7,      /* Krylov dimension used by the step that produced the record
+                                (the largest of its substeps under step control) */
+    PPQ_OBS_SUBSTEPS = 8,    /* substeps of that step (1 without step control; 0 in a
+                                record no step produced) */
+    PPQ_OBS_N = 9
 };
 
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t to
@@ -108,8 +115,12 @@ const char *ppq_last_error(const ppq_ctx *ctx);
 /* Direct-product sine-DVR grid (particle-in-a-box DVR of the DVR family,
    Sec. II.A): per dimension n[k] interior points of the box (lo[k], hi[k]),
    q_i = lo + i (hi-lo)/(n+1), i = 1..n.  Sets the kinetic operator
-   -1/(2 mass) d^2/dq^2 on every dimension.  1 <= D <= 8, 2 <= n[k] <= 64,
-   prod n < 2^32.  Clears any operator and state. */
+   -1/(2 mass) d^2/dq^2 on every dimension.  1 <= D <= 8, 2 <= n[k] <= 256,
+   prod n < 2^32.  Dimensions of up to 64 points keep their fibers as 64-bit
+   digit masks and take the matrix-core and mask-driven passes; longer ones
+   keep a digit per fiber entry and take a long-fiber pass (one wavefront per
+   fiber; the block-fused layout is then off).  Clears any operator and
+   state. */
 int ppq_set_grid(ppq_ctx *ctx, int D, const int32_t *n, const double *lo, const double *hi, double mass);
 
 /* Grid points of dimension k (n[k] doubles, host). */
@@ -151,10 +162,37 @@ int ppq_set_weylets(ppq_ctx *ctx, int k, int n_x, int n_p);
    matrices).  kinds[f] is a ppq_factor_kind, params holds 2 doubles per
    factor, tables holds n[dims[f]] doubles per PPQ_FAC_TABLE factor (in factor
    order; may be NULL otherwise).  On DVR dimensions the term stays diagonal;
-   a term touching lattice dimensions becomes a product of dense factors, of
-   which at most two are supported (PPQ_E_UNSUPPORTED otherwise). */
+   a term touching lattice dimensions becomes a product of dense factors
+   (applied as ppq_add_term describes). */
 int ppq_add_potential_term(ppq_ctx *ctx, double coef, int nfac, const int32_t *dims, const int32_t *kinds,
                            const double *params, const double *tables);
+
+/* Adds the general sum-of-products term (c_re + i c_im) prod_f h_f, one
+   factor h_f acting on dimension dims[f] (Sec. II.B.2: the operator is a sum
+   of products of one-dimensional operators).  kinds[f] is a ppq_factor_kind:
+   the diagonal kinds of ppq_add_potential_term, or a dense matrix
+   (PPQ_FAC_DENSE_REAL: n_k^2 doubles, PPQ_FAC_DENSE_COMPLEX: 2 n_k^2 doubles)
+   in the dimension's DVR basis.  params: 2 doubles per factor (as for
+   ppq_add_potential_term; ignored for dense and table kinds); data: the
+   table (n_k doubles) and dense (n_k^2 or 2 n_k^2 doubles) factors one after
+   the other in factor order (host, copied; may be NULL without such
+   factors).  A dense factor must be the only factor on its dimension; a
+   term of no factors is a constant.
+   A term of diagonal factors with c_im = 0 is a potential term (as
+   ppq_add_potential_term).  Any other term acts on a vector on the active
+   set as the sequential pruned product of Sec. II.B.2 (Eq.
+   matvecprod_sequential): its factors one at a time from the highest
+   dimension down, each result truncated to the active set before the next,
+   then times the coefficient; diagonal factors commute with the truncation
+   and are applied to the input.  On lattice dimensions every factor is
+   transformed like the kinetic matrix (G^+ h G^{-+}, W^T h W).  The operator
+   stays Hermitian (Lanczos steps) while every such term on DVR dimensions
+   has one dense factor, Hermitian, and a real coefficient; two or more dense
+   factors in one term, a complex coefficient or a non-Hermitian factor make
+   steps use Arnoldi.  PPQ_E_ARG for bad dimensions, kinds or layout,
+   PPQ_E_NUMERIC for non-finite values (state unchanged). */
+int ppq_add_term(ppq_ctx *ctx, double c_re, double c_im, int nfac, const int32_t *dims, const int32_t *kinds,
+                 const double *params, const double *data);
 
 /* Replaces the one-dimensional operator of dimension k (by default the
    sine-DVR kinetic energy of ppq_set_grid) by h, a real symmetric n_k x n_k
@@ -166,10 +204,11 @@ int ppq_add_potential_term(ppq_ctx *ctx, double coef, int nfac, const int32_t *d
    PPQ_E_NUMERIC for non-finite entries. */
 int ppq_set_factor(ppq_ctx *ctx, int k, const double *h);
 
-/* Removes every potential term (the kinetic factors stay), so that a new
-   sum-of-products potential can be added term by term (Sec. II.A, II.E); the
-   state and its active set are kept.  The derivative terms of the adjoint
-   are not touched. */
+/* Removes every potential and product term (ppq_add_potential_term,
+   ppq_add_term; the kinetic factors stay), so that a new sum-of-products
+   operator can be added term by term (Sec. II.A, II.E); the state and its
+   active set are kept.  The derivative terms of the adjoint are not
+   touched. */
 int ppq_clear_potential(ppq_ctx *ctx);
 
 /* Capacity of the active set (number of functions).  Grows automatically when
@@ -248,6 +287,20 @@ int ppq_step(ppq_ctx *ctx, double dt, int m);
    and >= 0.  The adjoint entry points need tolerance 0 (PPQ_E_UNSUPPORTED). */
 int ppq_set_krylov_tolerance(ppq_ctx *ctx, double tol);
 
+/* Step size control, tied like the adaptive order to the Krylov tolerance
+   (Sec. III.A adapts the integrator's accuracy to the amplitude threshold;
+   with tolerance 0 it has no effect).  With max_substeps > 1 every later step
+   of length dt (ppq_step, ppq_propagate) runs as s substeps of dt/s on the
+   current set: s starts at the previous step's count (1 after a new state);
+   every substep must meet the tolerance at a Krylov order below m, else the
+   step is redone from its start with 2s substeps, and a step needing more
+   than max_substeps fails with PPQ_E_NUMERIC (the state keeps the values
+   from before the step).  After a step whose substeps all stopped at order
+   m/2 or below, the next starts with s/2.  Each attempt waits once for the
+   orders on the host.  The record's PPQ_OBS_SUBSTEPS field gives s.
+   PPQ_E_ARG unless 1 <= max_substeps <= 1024 (1 = off, the default). */
+int ppq_set_step_control(ppq_ctx *ctx, int max_substeps);
+
 /* Adaption with threshold eps (Sec. II.E, radius-1 stencil of Sec. III.A):
    A' = {I in A : |c_I| >= eps} plus their nearest neighbours inside the grid;
    coefficients carried over on A cap A', zero on new functions.  |c|^2 is
@@ -308,12 +361,18 @@ int ppq_expect_q(ppq_ctx *ctx, double *q);
    be obtained. */
 int ppq_expect_q_noalloc(ppq_ctx *ctx, double *q);
 
-/* Autocorrelation at twice the current time, C(2t) = <psi(t)*|psi(t)> =
-   sum_I c_I^2 over the active set (no complex conjugate): valid when the
-   initial packet is real (zero momentum) and the operator real symmetric,
-   so that one propagation to t gives C up to 2t (the identity that follows
-   Eq. acorr).  c2t: 2 doubles (re, im), host.  Synchronises.
-   PPQ_E_UNSUPPORTED on lattice contexts. */
+/* Autocorrelation at twice the current time, C(2t) = <psi(t)*|psi(t)>, no
+   complex conjugate (the identity after Eq. acorr): valid when the initial
+   packet is real (zero momentum) and the operator real symmetric, so that
+   one propagation to t gives C up to 2t.  On DVR dimensions it is
+   sum_I c_I^2 over the active set.  On a phase-space lattice basis the
+   coefficients a are not orthonormal: C(2t) = a^T B^T B a with B =
+   (x)_k G_k^{-+} (c = B a the DVR coefficients; B = W for projected
+   Weylets), evaluated by transforming a to the full DVR grid (two full-grid
+   work tensors, at most 2^28 points, PPQ_E_CAPACITY beyond).  c2t: 2
+   doubles (re, im), host.  Synchronises.  PPQ_E_UNSUPPORTED when a complex
+   coefficient or a complex or non-symmetric dense factor (ppq_add_term)
+   makes the operator other than real symmetric (in the DVR basis). */
 int ppq_acf_doubled(ppq_ctx *ctx, double *c2t);
 
 /* ---- adjoint gradient of the survival probability (added form) ----------
@@ -326,7 +385,8 @@ int ppq_acf_doubled(ppq_ctx *ctx, double *c2t);
    obtained in closed form in the two Krylov spaces (block-triangular
    exponential), psi recomputed from checkpoints every K steps (each
    recomputed segment must reproduce the next checkpoint bit for bit).
-   DVR dimensions only (PPQ_E_UNSUPPORTED on lattice dimensions). */
+   DVR dimensions and diagonal potential terms only (PPQ_E_UNSUPPORTED on
+   lattice dimensions or with product terms of ppq_add_term). */
 
 /* Replaces coefficient and factor parameters (2 per factor, layout of
    ppq_add_potential_term; params may be NULL) of potential term `term`
@@ -356,12 +416,14 @@ int ppq_adjoint_frozen(ppq_ctx *ctx, const double *centre, const double *momentu
 int ppq_adjoint_gradient(ppq_ctx *ctx, double *dJ_dparam, double *dJ_dcentre, double *dJ_dmomentum);
 
 /* Measurement helper: applies H to the current state `nrep` times (after
-   one untimed application), bracketed by HIP events recorded on the context
-   stream, and returns the mean time per application in ms (all fiber passes
-   of one P_A H P_A product).  The input is the state (FP64 contexts) or its
-   normalised FP32 copy (FP32 contexts); the output goes to an internal work
-   vector.  Synchronises. */
-int ppq_time_apply(ppq_ctx *ctx, int nrep, double *ms_per_apply);
+   one untimed application), with a HIP event recorded on the context stream
+   before each application and after the last, and returns the median time
+   of one application in ms (all passes of one P_A H P_A product) and, when
+   ms_mean is not NULL, the mean over the nrep back-to-back applications.
+   The input is the state (FP64 contexts) or its normalised FP32 copy (FP32
+   contexts); the output goes to an internal work vector.  Synchronises.
+   PPQ_E_ARG unless 1 <= nrep <= 100000. */
+int ppq_time_apply(ppq_ctx *ctx, int nrep, double *ms_median, double *ms_mean);
 
 /* Fiber counts of the current set: nf[k] = number of dimension-k fibers
    (lines of the set along dimension k), k < D.  Synchronises. */

@@ -64,6 +64,15 @@ def sine_dvr_kinetic(n, lo, hi, mass):
     return T
 
 
+def lattice_shapes(card):
+    """Per dimension (n_s, n_l): the card's "lattice" is one pair for every
+    dimension or a list of pairs, one per dimension."""
+    lat = card["lattice"]
+    if isinstance(lat[0], (list, tuple)):
+        return [tuple(int(v) for v in p) for p in lat]
+    return [(int(lat[0]), int(lat[1]))] * card["D"]
+
+
 def is_dense(f):
     return f["kind"] == "dense"
 
@@ -155,10 +164,10 @@ class Model:
         # or projected Weylets ("pw", orthogonal); both act as a = G^+ c
         self.pvb = card.get("basis", "dvr") in ("pvb", "pw")
         if self.pvb:
-            ns, nl = card["lattice"]
-            self.lattice = (ns, nl)
+            self.lattices = lattice_shapes(card)
+            self.lattice = self.lattices[0]
             proj = pw_projection if card["basis"] == "pw" else pvb_projection
-            self.G = [proj(self.q[k], self.dx[k], card["lo"][k], card["hi"][k], ns, nl)
+            self.G = [proj(self.q[k], self.dx[k], card["lo"][k], card["hi"][k], *self.lattices[k])
                       for k in range(D)]
             self.Ginv = [np.linalg.inv(G) for G in self.G]
             self.GinvH = [np.linalg.inv(G.conj().T) for G in self.G]

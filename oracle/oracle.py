@@ -14,7 +14,7 @@ from .model import Model
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-OBS_FIELDS = ("t", "norm2", "energy", "acf_re", "acf_im", "n_active", "n_above", "krylov_used")
+OBS_FIELDS = ("t", "norm2", "energy", "acf_re", "acf_im", "n_active", "n_above", "krylov_used", "substeps")
 
 _c_int64_p = ctypes.POINTER(ctypes.c_int64)
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -56,6 +56,7 @@ def lib():
         L.orc_sil_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _c_double_p]
         L.orc_set_stencil.argtypes = [vp, ctypes.c_int]
         L.orc_set_krylov_tol.argtypes = [vp, ctypes.c_double]
+        L.orc_set_max_substeps.argtypes = [vp, ctypes.c_int]
         L.orc_prune.restype = ctypes.c_int64
         L.orc_prune.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double]
         L.orc_init_product.restype = ctypes.c_int64
@@ -146,11 +147,13 @@ class Oracle:
                               _ip(np.array(dims, dtype=np.int32)), _dp(flat.view(np.float64))) != 0:
                 raise ValueError("bad product term")
         if m.pvb:
-            ns, nl = m.lattice
             for k in range(self.D):
+                ns, nl = m.lattices[k]
                 L.orc_set_lattice(self._m, k, ns, nl)
         if card.get("krylov_tol", 0.0) and L.orc_set_krylov_tol(self._m, float(card["krylov_tol"])) != 0:
             raise ValueError("krylov_tol must be >= 0")
+        if card.get("max_substeps", 1) != 1 and L.orc_set_max_substeps(self._m, int(card["max_substeps"])) != 0:
+            raise ValueError("max_substeps must be in [1, 1024]")
         if card.get("stencil", 1) != 1 and L.orc_set_stencil(self._m, int(card["stencil"])) != 0:
             raise ValueError("stencil must be 1, 2 or 3")
         self.arnoldi = 0 if m.hermitian() else 1
@@ -280,11 +283,20 @@ class Oracle:
         return dict(zip(OBS_FIELDS[1:7], out))
 
     def acf_doubled(self):
-        """C(2t) = <psi(t)*|psi(t)> = sum_I c_I^2 (no conjugate), the
-        autocorrelation at twice the time for a real initial packet and a real
-        symmetric operator (the identity after Eq. acorr)."""
-        _, c = self.state()
-        return complex(np.sum(c * c))
+        """C(2t) = <psi(t)*|psi(t)> (no conjugate), the autocorrelation at
+        twice the time for a real initial packet and a real symmetric operator
+        (the identity after Eq. acorr): sum_I c_I^2 on a DVR basis; on a
+        lattice basis a^T B^T B a with B the map from the lattice coefficients
+        to the DVR ones, c = (x)_k G_k^{-+} a, evaluated on the full grid."""
+        keys, c = self.state()
+        if not self.model.pvb:
+            return complex(np.sum(c * c))
+        full = np.zeros(int(np.prod(self.n)), dtype=np.complex128)
+        full[keys.astype(np.int64)] = c
+        full = full.reshape(self.n)
+        for k in range(self.D):
+            full = np.moveaxis(np.tensordot(self.model.GinvH[k], full, axes=([1], [k])), 0, k)
+        return complex(np.sum(full * full))
 
     def expect_q(self):
         """Position expectation per dimension of the current state,
@@ -308,7 +320,7 @@ class Oracle:
         return out
 
     def propagate(self, nsteps=None, dt=None, m=None, eps=None, prune=True):
-        """Returns (trace[nsteps+1, 8], hashes[nsteps+1]); eps<0 or prune=False: no adaption."""
+        """Returns (trace[nsteps+1, 9], hashes[nsteps+1]); eps<0 or prune=False: no adaption."""
         nsteps = self.card["nsteps"] if nsteps is None else nsteps
         dt = self.card["dt"] if dt is None else dt
         m = self.card["krylov"] if m is None else m
@@ -318,8 +330,9 @@ class Oracle:
         trace = np.zeros((nsteps + 1, len(OBS_FIELDS)))
         hashes = np.zeros(nsteps + 1, dtype=np.uint64)
         self._drop_fib()
-        lib().orc_propagate(self._m, self._s, nsteps, dt, m, eps, self.arnoldi,
-                            _dp(self._bra_tabs.view(np.float64)), _dp(trace), _up(hashes))
+        if lib().orc_propagate(self._m, self._s, nsteps, dt, m, eps, self.arnoldi,
+                               _dp(self._bra_tabs.view(np.float64)), _dp(trace), _up(hashes)) != 0:
+            raise RuntimeError("a step did not meet the Krylov tolerance within max_substeps substeps")
         return trace, hashes
 
     # --- frozen-set trajectories (adjoint reference) ----------------------------
@@ -330,8 +343,9 @@ class Oracle:
         eps = self.card["eps"] if eps is None else eps
         sizes = np.zeros(nsteps + 1, dtype=np.int64)
         buf = _c_u64_p()
-        lib().orc_propagate_record(self._m, self._s, nsteps, dt, m, eps, sizes.ctypes.data_as(_c_int64_p),
-                                   ctypes.byref(buf))
+        if lib().orc_propagate_record(self._m, self._s, nsteps, dt, m, eps, sizes.ctypes.data_as(_c_int64_p),
+                                      ctypes.byref(buf)) != 0:
+            raise RuntimeError("a step did not meet the Krylov tolerance within max_substeps substeps")
         total = int(sizes.sum())
         keys = np.ctypeslib.as_array(buf, shape=(total,)).copy() if total else np.zeros(0, np.uint64)
         lib().orc_free_buffer(ctypes.cast(buf, ctypes.c_void_p))
@@ -343,8 +357,9 @@ class Oracle:
         m = self.card["krylov"] if m is None else m
         sizes = np.ascontiguousarray(sizes, dtype=np.int64)
         keys = np.ascontiguousarray(keys, dtype=np.uint64)
-        lib().orc_propagate_frozen(self._m, self._s, sizes.size - 1, dt, m, sizes.ctypes.data_as(_c_int64_p),
-                                   _up(keys))
+        if lib().orc_propagate_frozen(self._m, self._s, sizes.size - 1, dt, m, sizes.ctypes.data_as(_c_int64_p),
+                                      _up(keys)) != 0:
+            raise RuntimeError("a step did not meet the Krylov tolerance within max_substeps substeps")
         self._drop_fib()
 
     # --- helpers for tests ---------------------------------------------------

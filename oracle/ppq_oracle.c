@@ -63,6 +63,7 @@ typedef struct orc_model {
     int lat_s[ORC_MAXD], lat_l[ORC_MAXD]; /* phase-space lattice shape per dim; 0 = line */
     int stencil;                /* adaption neighbours: 1 = ball radius 1, 2 = radius sqrt(2), 3 = radius 2 */
     double krylov_tol;          /* > 0: SIL order chosen per step by the error estimate */
+    int max_substeps;           /* > 1 (with krylov_tol > 0): step size control, see controlled_step */
 } orc_model;
 
 orc_model *orc_new(int D, const int32_t *n)
@@ -536,6 +537,7 @@ typedef struct orc_state {
     int64_t n;
     uint64_t *keys;
     zd *c;
+    int nsub;                   /* substeps the next controlled step starts with */
 } orc_state;
 
 orc_state *orc_state_new(void) { return calloc(1, sizeof(orc_state)); }
@@ -555,6 +557,7 @@ int orc_state_set(orc_state *s, int64_t n, const uint64_t *keys, const double *c
     free(s->keys);
     free(s->c);
     s->n = n;
+    s->nsub = 1;
     s->keys = malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     s->c = malloc(sizeof(zd) * (size_t)(n > 0 ? n : 1));
     if (n) {
@@ -802,6 +805,15 @@ int orc_set_krylov_tol(orc_model *m, double tol)
     return 0;
 }
 
+/* Step size control: with a Krylov tolerance set, each step of length dt runs
+   as s substeps of dt/s (s <= max_substeps; 1 = off). */
+int orc_set_max_substeps(orc_model *m, int smax)
+{
+    if (smax < 1 || smax > 1024) return -1;
+    m->max_substeps = smax;
+    return 0;
+}
+
 /* Selects the adaption stencil (1: radius 1; 2: radius sqrt(2); 3: radius 2). */
 int orc_set_stencil(orc_model *m, int stencil)
 {
@@ -904,7 +916,54 @@ int64_t orc_init_product(const orc_model *m, orc_state *s, const double *tabs_in
 /* ------------------------------------------------------------------------ */
 /* observables                                                              */
 /* ------------------------------------------------------------------------ */
-enum { OBS_T, OBS_NORM2, OBS_ENERGY, OBS_ACF_RE, OBS_ACF_IM, OBS_NACT, OBS_NABOVE, OBS_MEFF, OBS_N };
+enum { OBS_T, OBS_NORM2, OBS_ENERGY, OBS_ACF_RE, OBS_ACF_IM, OBS_NACT, OBS_NABOVE, OBS_MEFF, OBS_NSUB, OBS_N };
+
+/* One step of length dt on the current set with the integrator's accuracy
+   tied to the tolerance (Sec. III.A adapts it to the amplitude threshold; the
+   reading here adapts the Krylov order and, with max_substeps > 1, the step
+   size).  Without control: one SIL step of order mk.  With control: s
+   substeps of dt/s, s starting at the state's nsub; every substep must meet
+   the tolerance at an order below mk (the adaptive order stopped early);
+   if one does not, the step is redone from its start with 2s substeps (error
+   -1 beyond max_substeps).  After a step whose substeps all stopped at order
+   mk/2 or below, the next starts with half as many.  *meff_out: the largest
+   order of the accepted substeps; *nsub_out: their number. */
+static int controlled_step(const orc_model *m, const orc_fib *f, orc_state *s, double dt, int mk, int arnoldi,
+                           int *meff_out, int *nsub_out)
+{
+    if (m->max_substeps <= 1 || !(m->krylov_tol > 0.0)) {
+        *meff_out = orc_sil_step(m, f, s, dt, mk, arnoldi, NULL);
+        *nsub_out = 1;
+        return 0;
+    }
+    int sub = s->nsub < 1 ? 1 : s->nsub;
+    if (sub > m->max_substeps) sub = m->max_substeps;
+    zd *save = malloc(sizeof(zd) * (size_t)(s->n > 0 ? s->n : 1));
+    memcpy(save, s->c, sizeof(zd) * (size_t)s->n);
+    int mo = 0;
+    for (;;) {
+        int ok = 1;
+        mo = 0;
+        const double h = dt / (double)sub;
+        for (int j = 0; j < sub && ok; ++j) {
+            int me = orc_sil_step(m, f, s, h, mk, arnoldi, NULL);
+            if (me > mo) mo = me;
+            if (me >= mk) ok = 0;
+        }
+        if (ok) break;
+        memcpy(s->c, save, sizeof(zd) * (size_t)s->n);
+        sub *= 2;
+        if (sub > m->max_substeps) {
+            free(save);
+            return -1;
+        }
+    }
+    free(save);
+    *meff_out = mo;
+    *nsub_out = sub;
+    s->nsub = (mo <= mk / 2 && sub > 1) ? sub / 2 : sub;
+    return 0;
+}
 
 /* out: [norm2, energy, acf_re, acf_im, n_active, n_above]; bra is [D][nmax] complex */
 int orc_observe(const orc_model *m, const orc_fib *f, const orc_state *s, const double *bra_in,
@@ -964,9 +1023,14 @@ int orc_propagate(const orc_model *m, orc_state *s, int nsteps, double dt, int m
     trace[OBS_T] = 0.0;
     for (int i = 0; i < 6; ++i) trace[1 + i] = o[i];
     trace[OBS_MEFF] = 0.0;
+    trace[OBS_NSUB] = 0.0;
     if (hashes) hashes[0] = orc_set_hash(s->n, s->keys);
     for (int st = 1; st <= nsteps; ++st) {
-        int meff = orc_sil_step(m, f, s, dt, mk, arnoldi, NULL);
+        int meff, nsub;
+        if (controlled_step(m, f, s, dt, mk, arnoldi, &meff, &nsub) != 0) {
+            orc_fib_free(f);
+            return -1;
+        }
         if (eps >= 0.0) {
             orc_prune(m, s, eps, 0.0);
             orc_fib_free(f);
@@ -977,6 +1041,7 @@ int orc_propagate(const orc_model *m, orc_state *s, int nsteps, double dt, int m
         r[OBS_T] = st * dt;
         for (int i = 0; i < 6; ++i) r[1 + i] = o[i];
         r[OBS_MEFF] = meff;
+        r[OBS_NSUB] = nsub;
         if (hashes) hashes[st] = orc_set_hash(s->n, s->keys);
     }
     orc_fib_free(f);
@@ -1053,8 +1118,13 @@ int orc_propagate_record(const orc_model *m, orc_state *s, int nsteps, double dt
     for (int st = 0; st <= nsteps; ++st) {
         if (st > 0) {
             orc_fib *f = orc_fib_build(m, s->n, s->keys);
-            orc_sil_step(m, f, s, dt, mk, 0, NULL);
+            int meff, nsub;
+            int r = controlled_step(m, f, s, dt, mk, 0, &meff, &nsub);
             orc_fib_free(f);
+            if (r != 0) {
+                free(buf);
+                return -1;
+            }
             orc_prune(m, s, eps, 0.0);
         }
         set_sizes[st] = s->n;
@@ -1079,8 +1149,10 @@ int orc_propagate_frozen(const orc_model *m, orc_state *s, int nsteps, double dt
     int64_t off = set_sizes[0];
     for (int st = 1; st <= nsteps; ++st) {
         orc_fib *f = orc_fib_build(m, s->n, s->keys);
-        orc_sil_step(m, f, s, dt, mk, 0, NULL);
+        int meff, nsub;
+        int r = controlled_step(m, f, s, dt, mk, 0, &meff, &nsub);
         orc_fib_free(f);
+        if (r != 0) return -1;
         remap_to(s, set_sizes[st], keys + off);
         off += set_sizes[st];
     }

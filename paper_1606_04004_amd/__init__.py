@@ -14,7 +14,7 @@ from ._ppq import OBS_FIELDS, OBS_N, PHASES, PPQ_FP32, PPQ_FP64, PPQError  # noq
 __all__ = ["Propagator", "PPQError", "PPQ_FP64", "PPQ_FP32", "OBS_FIELDS"]
 
 _KIND = {"power": _ppq.PPQ_FAC_POWER, "morse": _ppq.PPQ_FAC_MORSE, "table": _ppq.PPQ_FAC_TABLE,
-         "morse_da": _ppq.PPQ_FAC_MORSE_DA}
+         "morse_da": _ppq.PPQ_FAC_MORSE_DA, "dense": _ppq.PPQ_FAC_DENSE_REAL}
 
 
 def _d(a):
@@ -55,18 +55,21 @@ class Propagator:
         for k in card.get("fgh", []):
             self._call("ppq_set_fgh", int(k))
         if card.get("basis", "dvr") in ("pvb", "pw"):
-            ns, nl = card["lattice"]
+            lat = card["lattice"]
+            shapes = lat if isinstance(lat[0], (list, tuple)) else [lat] * self.D
             call = "ppq_set_weylets" if card["basis"] == "pw" else "ppq_set_lattice"
             for k in range(self.D):
-                self._call(call, k, int(ns), int(nl))
+                self._call(call, k, int(shapes[k][0]), int(shapes[k][1]))
         for k, h in card.get("dim_factors", {}).items():
             self.set_factor(int(k), h)
         if card.get("stencil", 1) != 1:
             self.set_stencil(card["stencil"])
         if card.get("krylov_tol", 0.0):
             self.set_krylov_tolerance(card["krylov_tol"])
+        if card.get("max_substeps", 1) != 1:
+            self.set_step_control(card["max_substeps"])
         for t in card["terms"]:
-            self.add_term(t["coef"], t["factors"])
+            self.add_term(t["coef"], t["factors"], t.get("coef_im", 0.0))
 
     # ---- plumbing -----------------------------------------------------------
     def _call(self, name, *args):
@@ -94,6 +97,16 @@ class Propagator:
                 params += [float(f["p"]), 0.0]
             elif f["kind"] in ("morse", "morse_da"):
                 params += [float(f["a"]), float(f["q0"])]
+            elif f["kind"] == "dense":
+                params += [0.0, 0.0]
+                re = np.asarray(f["re"], dtype=np.float64)
+                if "im" in f:
+                    kinds[-1] = _ppq.PPQ_FAC_DENSE_COMPLEX
+                    m = re + 1j * np.asarray(f["im"], dtype=np.float64)
+                    tables += list(np.ascontiguousarray(m, dtype=np.complex128).view(np.float64).ravel())
+                else:
+                    kinds[-1] = _ppq.PPQ_FAC_DENSE_REAL
+                    tables += list(re.ravel())
             else:
                 params += [0.0, 0.0]
                 tables += list(f["values"])
@@ -117,7 +130,18 @@ class Propagator:
         """Removes every potential term (add_term adds new ones)."""
         self._call("ppq_clear_potential")
 
-    def add_term(self, coef, factors):
+    def add_term(self, coef, factors, coef_im=0.0):
+        """A sum-of-products term (ppq_add_term): diagonal factors and dense
+        matrices ({"kind": "dense", "re": ..., "im": ...}), complex coefficient."""
+        dims, kinds, params, tables = self._factors(factors)
+        d, pd = _i32(dims or [0])
+        k, pk = _i32(kinds or [0])
+        p, pp = _d(params or [0.0])
+        tb, ptb = _d(tables or [0.0])
+        self._call("ppq_add_term", float(coef), float(coef_im), len(factors), pd, pk, pp, ptb if tables else None)
+
+    def add_potential_term(self, coef, factors):
+        """A diagonal potential term (ppq_add_potential_term)."""
         dims, kinds, params, tables = self._factors(factors)
         d, pd = _i32(dims or [0])
         k, pk = _i32(kinds or [0])
@@ -268,6 +292,11 @@ class Propagator:
         estimate is within tol (0: the full order)."""
         self._call("ppq_set_krylov_tolerance", float(tol))
 
+    def set_step_control(self, max_substeps):
+        """Step size control under the Krylov tolerance: each step as up to
+        max_substeps substeps (1 = off)."""
+        self._call("ppq_set_step_control", int(max_substeps))
+
     def propagate(self, nsteps=None, dt=None, m=None, eps=None, prune=True):
         nsteps = self.card["nsteps"] if nsteps is None else nsteps
         dt = self.card["dt"] if dt is None else dt
@@ -304,10 +333,12 @@ class Propagator:
         self._call("ppq_expect_q_noalloc", out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return out
 
-    def time_apply(self, nrep):
-        ms = ctypes.c_double(0.0)
-        self._call("ppq_time_apply", int(nrep), ctypes.byref(ms))
-        return ms.value
+    def time_apply(self, nrep, mean=False):
+        """Median ms of one H application over nrep (with mean=True: (median, mean))."""
+        med = ctypes.c_double(0.0)
+        avg = ctypes.c_double(0.0)
+        self._call("ppq_time_apply", int(nrep), ctypes.byref(med), ctypes.byref(avg))
+        return (med.value, avg.value) if mean else med.value
 
     def enable_timings(self, on=True):
         self._call("ppq_enable_timings", 1 if on else 0)

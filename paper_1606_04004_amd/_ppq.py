@@ -14,8 +14,9 @@ STATUS = {0: "PPQ_OK", -1: "PPQ_E_ARG", -2: "PPQ_E_STATE", -3: "PPQ_E_OOM", -4: 
           -5: "PPQ_E_HIP", -6: "PPQ_E_NUMERIC", -7: "PPQ_E_UNSUPPORTED"}
 PPQ_FP64, PPQ_FP32 = 0, 1
 PPQ_FAC_POWER, PPQ_FAC_MORSE, PPQ_FAC_TABLE, PPQ_FAC_MORSE_DA = 0, 1, 2, 3
-OBS_FIELDS = ("t", "norm2", "energy", "acf_re", "acf_im", "n_active", "n_above", "krylov_used")
-OBS_N = 8
+PPQ_FAC_DENSE_REAL, PPQ_FAC_DENSE_COMPLEX = 4, 5
+OBS_FIELDS = ("t", "norm2", "energy", "acf_re", "acf_im", "n_active", "n_above", "krylov_used", "substeps")
+OBS_N = 9
 PHASES = ("hpsi", "krylov", "adapt", "tables", "obs")  # ppq_timings order
 
 # every exported symbol and its (restype, argtypes)
@@ -32,6 +33,7 @@ SIGNATURES = {
     "ppq_get_grid": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "ppq_set_lattice": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "ppq_add_potential_term": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int, _i32p, _i32p, _dp, _dp]),
+    "ppq_add_term": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _i32p, _i32p, _dp, _dp]),
     "ppq_reserve": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "ppq_init_gaussian": (ctypes.c_int, [_vp, _dp, _dp, _dp, ctypes.c_double, _i64p]),
     "ppq_set_state": (ctypes.c_int, [_vp, ctypes.c_int64, _u64p, _dp]),
@@ -50,6 +52,7 @@ SIGNATURES = {
     "ppq_get_state_device": (ctypes.c_int, [_vp, ctypes.c_int64, _i64p, _vp, _vp]),
     "ppq_set_relative_exclusion": (ctypes.c_int, [_vp, ctypes.c_double]),
     "ppq_set_krylov_tolerance": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "ppq_set_step_control": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ppq_propagate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp]),
     "ppq_observables": (ctypes.c_int, [_vp, ctypes.c_double, _dp]),
     "ppq_expect_q": (ctypes.c_int, [_vp, _dp]),
@@ -62,7 +65,7 @@ SIGNATURES = {
                                           ctypes.c_int, ctypes.c_int, _dp]),
     "ppq_adjoint_frozen": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "ppq_adjoint_gradient": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
-    "ppq_time_apply": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "ppq_time_apply": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
     "ppq_fiber_counts": (ctypes.c_int, [_vp, _i64p]),
     "ppq_enable_timings": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ppq_timings": (ctypes.c_int, [_vp, _dp]),

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ppq_internal.hpp"
@@ -26,15 +27,31 @@ struct Factor {
 };
 struct Term {
     double coef;
+    double coef_im = 0.0;  // imaginary part of the coefficient (ppq_add_term)
     std::vector<Factor> f;
 };
 
-// a product term with two dense (lattice) factors, grouped for evaluation
+// a product term with two dense factors and no diagonal ones, grouped with
+// the others sharing its inner factor for evaluation
 struct PairTerm {
-    double coef;
+    double cre, cim;  // coefficient
     int k1, f1;  // outer factor (lower dimension), index into dense factor list
     int k2, f2;  // inner factor (applied first)
 };
+
+// any other product term: diagonal factors (DVR dimensions in `use`, values
+// in a [D][nmax] table) scale the input, then the dense factors act from the
+// highest dimension down, each result truncated to the set
+struct ProdTerm {
+    double cre, cim;
+    int nf = 0;        // dense factors, dimensions increasing
+    int k[MAXD]{};
+    int fid[MAXD]{};   // index into the dense factor list
+    unsigned use = 0;  // dimensions with a diagonal factor
+    int diag = -1;     // index of the diagonal table (ctx->PD64)
+};
+
+inline bool dense_kind(int kind) { return kind == PPQ_FAC_DENSE_REAL || kind == PPQ_FAC_DENSE_COMPLEX; }
 
 int bucket(int n)
 {
@@ -43,7 +60,8 @@ int bucket(int n)
     if (n <= 24) return 24;
     if (n <= 32) return 32;
     if (n <= 48) return 48;
-    return 64;
+    if (n <= 64) return 64;
+    return n;  // a long dimension: its factor is stored unpadded
 }
 
 struct HipError {
@@ -112,6 +130,15 @@ struct ppq_ctx {
     std::vector<float2 *> F32;
     std::vector<int> Fdim;
     std::vector<PairTerm> pairs;
+    std::vector<ProdTerm> chains;
+    std::vector<double *> PD64;   // diagonal tables of chain terms, [D][pd_nmax]
+    int pd_nmax = 0;
+    bool hermitian = true;        // P H P Hermitian: Lanczos (else Arnoldi)
+    bool real_sym = true;         // ... and real symmetric (C(2t) from the state at t)
+    bool dvr_real_sym = true;     // the operator in the DVR basis is real symmetric
+                                  // (lattice bases: a similarity of it)
+    double2 *full[2]{};           // full-grid tensors of C(2t) on lattice bases
+    int64_t full_cap = 0;
     double *pot_coef = nullptr;
     int *pot_tab = nullptr;
     double *pot_tabs = nullptr;
@@ -141,7 +168,8 @@ struct ppq_ctx {
     uint64_t *mask[MAXD]{};
     uint8_t *info[MAXD]{};
     int64_t nf[MAXD]{};
-    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides; 4 = block-fused)
+    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides; 4, 5 = block-fused)
+    uint32_t blk_window = BLOCK_WINDOW;  // chunk window of the block layouts (PPQ_BLOCK_WINDOW)
 
     // block-fused H*psi: outer dimensions [0, split) through the inner-first
     // frame, inner dimensions [split, D) in the row-major frame
@@ -183,6 +211,13 @@ struct ppq_ctx {
     double *qtab = nullptr;  // grid points [MAXD][NMAX_FIBER], then MAXD results (position expectations)
     double rel_excl = 0.0;   // relative exclusion threshold of adaption
     double krylov_tol = 0.0; // > 0: SIL order chosen per step by its error estimate
+    int max_substeps = 1;    // > 1 (with krylov_tol > 0): step size control
+    int nsub = 1;            // substeps the next controlled step starts with
+    double *sub_meff = nullptr;    // device: Krylov order of each substep of an attempt
+    double *h_sub_meff = nullptr;  // pinned mirror
+    int sub_cap = 0;
+    double2 *psi_save = nullptr;   // the state at the start of a controlled step
+    int64_t psi_save_cap = 0;
     double2 *acf2 = nullptr;  // C(2t) result (device)
     std::vector<double> factor[MAXD];  // caller's 1D factor per dimension (empty: sine-DVR kinetic)
     // fiber tables of all non-last dimensions at once (see fiber_tables_all)
@@ -219,6 +254,8 @@ struct ppq_ctx {
     double rec_centre[MAXD]{}, rec_momentum[MAXD]{};
     bool recorded = false;
     int rec_steps = 0, rec_m = 0, rec_every = 0;
+    double rec_tol = 0.0;          // Krylov tolerance of the recorded steps
+    std::vector<int> rec_sub;      // substeps of each recorded step
     double rec_dt = 0.0;
     double2 rec_C = make_double2(0.0, 0.0);
     uint32_t *rec_keys = nullptr;
@@ -256,6 +293,8 @@ void free_state_buffers(ppq_ctx *c)
         dfree(c->psi[i]);
     }
     dfree(c->psi_tmp);
+    dfree(c->psi_save);
+    c->psi_save_cap = 0;
     dfree(c->V64);
     dfree(c->V32);
     dfree(c->Vt64);
@@ -320,6 +359,9 @@ void free_operator(ppq_ctx *c)
     c->F32p.clear();
     c->Fdim.clear();
     c->pairs.clear();
+    for (auto &p : c->PD64) dfree(p);
+    c->PD64.clear();
+    c->chains.clear();
     dfree(c->pot_coef);
     dfree(c->pot_tab);
     dfree(c->pot_tabs);
@@ -401,7 +443,7 @@ void ensure_krylov(ppq_ctx *c, int m)
 
 void ensure_zbuf(ppq_ctx *c)
 {
-    size_t need = c->F64.size();
+    size_t need = std::max(c->F64.size(), c->chains.empty() ? (size_t)0 : (size_t)3);
     if (c->zbuf.size() >= need && c->kv_cap == c->cap && c->Vk) return;
     size_t es = c->precision == PPQ_FP64 ? sizeof(double2) : sizeof(float2);
     while (c->zbuf.size() < need) {
@@ -512,6 +554,40 @@ std::vector<double> dim_factor(const ppq_ctx *c, int k)
     return sine_dvr_kinetic(c->g.n[k], c->lo[k], c->hi[k], c->mass);
 }
 
+// A term applied as a product of matrices (Sec. II.B.2): on a DVR basis one
+// with a dense factor or a complex coefficient; on a lattice basis, where
+// every factor is dense, one on two or more dimensions (single-dimension terms
+// are summed into that dimension's operator).
+bool is_product(const ppq_ctx *c, const Term &t)
+{
+    if (c->any_lattice) {
+        unsigned used = 0;
+        for (const Factor &f : t.f) used |= 1u << f.dim;
+        return __builtin_popcount(used) > 1;
+    }
+    if (t.coef_im != 0.0) return true;
+    for (const Factor &f : t.f)
+        if (dense_kind(f.kind)) return true;
+    return false;
+}
+
+// A factor as an n_k x n_k complex matrix in its dimension's DVR basis
+// (diagonal kinds on the diagonal).
+std::vector<cd> factor_matrix(const ppq_ctx *c, const Factor &f)
+{
+    const int n = c->g.n[f.dim];
+    std::vector<cd> h((size_t)n * n, cd(0.0, 0.0));
+    if (f.kind == PPQ_FAC_DENSE_REAL) {
+        for (size_t i = 0; i < h.size(); ++i) h[i] = cd(f.table[i], 0.0);
+    } else if (f.kind == PPQ_FAC_DENSE_COMPLEX) {
+        for (size_t i = 0; i < h.size(); ++i) h[i] = cd(f.table[2 * i], f.table[2 * i + 1]);
+    } else {
+        const std::vector<double> v = factor_values(c, f);
+        for (int i = 0; i < n; ++i) h[(size_t)i * n + i] = cd(v[i], 0.0);
+    }
+    return h;
+}
+
 void build_operator(ppq_ctx *c)
 {
     if (!c->op_dirty) return;
@@ -535,11 +611,94 @@ void build_operator(ppq_ctx *c)
     c->F32p.clear();
     c->Fdim.clear();
     c->pairs.clear();
+    for (auto &p : c->PD64) dfree(p);
+    c->PD64.clear();
+    c->chains.clear();
     dfree(c->pot_coef);
     dfree(c->pot_tab);
     dfree(c->pot_tabs);
     const int D = c->g.D;
     hipStream_t s = c->stream;
+    auto pad_upload = [&](const std::vector<cd> &h, int n, int b, double2 **d64, float2 **d32) {
+        std::vector<double2> P((size_t)b * b, make_double2(0.0, 0.0));
+        std::vector<float2> Pf((size_t)b * b, make_float2(0.f, 0.f));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                cd v = h[(size_t)i * n + j];
+                P[(size_t)i * b + j] = make_double2(v.real(), v.imag());
+                Pf[(size_t)i * b + j] = make_float2((float)v.real(), (float)v.imag());
+            }
+        *d64 = upload(P, s);
+        *d32 = upload(Pf, s);
+    };
+    // distinct dense factors of product terms, keyed by (dim, matrix), as they
+    // act on the coefficients (transformed on lattice dimensions)
+    std::vector<std::vector<cd>> fmats;
+    auto factor_id = [&](int k, const std::vector<cd> &m) {
+        for (size_t i = 0; i < fmats.size(); ++i)
+            if (c->Fdim[i] == k && fmats[i] == m) return (int)i;
+        fmats.push_back(m);
+        c->Fdim.push_back(k);
+        return (int)fmats.size() - 1;
+    };
+    int pd_nmax = 1;
+    for (int k = 0; k < D; ++k) pd_nmax = std::max(pd_nmax, c->g.n[k]);
+    c->pd_nmax = pd_nmax;
+    // Registers a product term given its dense factors (dimensions increasing)
+    // and, on DVR dimensions, the values of its diagonal factors per dimension.
+    auto add_product = [&](double cre, double cim, const std::vector<int> &dk,
+                           const std::vector<std::vector<cd>> &dm, const std::vector<std::vector<double>> &diag) {
+        unsigned use = 0;
+        for (int k = 0; k < D; ++k)
+            if (!diag[k].empty()) use |= 1u << k;
+        if (use == 0 && dk.size() == 2) {
+            PairTerm p;
+            p.cre = cre;
+            p.cim = cim;
+            p.k1 = dk[0];
+            p.k2 = dk[1];
+            p.f1 = factor_id(dk[0], dm[0]);
+            p.f2 = factor_id(dk[1], dm[1]);
+            c->pairs.push_back(p);
+            return;
+        }
+        ProdTerm pt;
+        pt.cre = cre;
+        pt.cim = cim;
+        pt.nf = (int)dk.size();
+        for (int f = 0; f < pt.nf; ++f) {
+            pt.k[f] = dk[f];
+            pt.fid[f] = factor_id(dk[f], dm[f]);
+        }
+        pt.use = use;
+        if (use) {
+            std::vector<double> tab((size_t)D * pd_nmax, 1.0);
+            for (int k = 0; k < D; ++k)
+                for (size_t i = 0; i < diag[k].size(); ++i) tab[(size_t)k * pd_nmax + i] = diag[k][i];
+            pt.diag = (int)c->PD64.size();
+            c->PD64.push_back(upload(tab, s));
+        }
+        c->chains.push_back(pt);
+    };
+    c->hermitian = !c->any_lattice;
+    c->real_sym = !c->any_lattice;
+    // in the DVR basis: real coefficients and real symmetric dense factors
+    c->dvr_real_sym = true;
+    for (const Term &t : c->terms) {
+        c->dvr_real_sym = c->dvr_real_sym && t.coef_im == 0.0;
+        for (const Factor &f : t.f) {
+            if (f.kind == PPQ_FAC_DENSE_COMPLEX) c->dvr_real_sym = false;
+            if (f.kind == PPQ_FAC_DENSE_REAL) {
+                const int n = c->g.n[f.dim];
+                for (int i = 0; i < n && c->dvr_real_sym; ++i)
+                    for (int j = 0; j < i; ++j)
+                        if (f.table[(size_t)i * n + j] != f.table[(size_t)j * n + i]) {
+                            c->dvr_real_sym = false;
+                            break;
+                        }
+            }
+        }
+    }
     if (!c->any_lattice) {
         for (int k = 0; k < D; ++k) {
             int n = c->g.n[k], b = c->nb[k];
@@ -553,6 +712,7 @@ void build_operator(ppq_ctx *c)
                 }
             c->T64[k] = upload(P, s);
             c->T32[k] = upload(Pf, s);
+            if (n > NMAX_MASK) continue;  // long dimensions take no matrix-core tiles
             std::vector<float> P64((size_t)64 * 64, 0.0f);
             std::vector<double> D64((size_t)64 * 64, 0.0);
             for (int i = 0; i < n; ++i)
@@ -569,6 +729,7 @@ void build_operator(ppq_ctx *c)
         std::vector<double> coef, tabs;
         std::vector<int> tab;
         for (const Term &t : c->terms) {
+            if (is_product(c, t)) continue;
             std::vector<int> idx(D, -1);
             std::vector<std::vector<double>> per(D);
             for (const Factor &f : t.f) {
@@ -602,8 +763,8 @@ void build_operator(ppq_ctx *c)
             for (int k = 0; k < D; ++k) nf += tab[(size_t)t * D + k] >= 0;
             maxf = std::max(maxf, nf);
         }
-        if (c->pot_nterm > 256 || (int64_t)tabs.size() > 1024 || maxf > 4)
-            throw std::invalid_argument("potential: at most 256 terms of at most 4 factors, 1024 distinct table values");
+        if (c->pot_nterm > 256 || (int64_t)tabs.size() > 2048 || maxf > 4)
+            throw std::invalid_argument("potential: at most 256 terms of at most 4 factors, 2048 distinct table values");
         if (coef.empty()) {
             coef.push_back(0.0);
             tab.assign(D, -1);
@@ -645,8 +806,8 @@ void build_operator(ppq_ctx *c)
             }
             c->d_nterm = (int)dcoef.size();
             c->d_ntab = (int)(dtabsv.size() / nmax);
-            if (c->d_nterm > 256 || (int64_t)dtabsv.size() > 1024)
-                throw std::invalid_argument("derivative terms: at most 256 terms, 1024 distinct table values");
+            if (c->d_nterm > 256 || (int64_t)dtabsv.size() > 2048)
+                throw std::invalid_argument("derivative terms: at most 256 terms, 2048 distinct table values");
             if (dcoef.empty()) {
                 dcoef.push_back(0.0);
                 dpar.push_back(0);
@@ -662,6 +823,49 @@ void build_operator(ppq_ctx *c)
             c->d_dtab = upload(dtab, s);
             c->d_dtabs = upload(dtabsv, s);
         }
+        // product terms: dense factors as matrices, diagonal ones as values.
+        // The operator stays Hermitian with one Hermitian dense factor and a
+        // real coefficient per term (the diagonal factors commute with it and
+        // with the truncation); real symmetric when that factor is real.
+        for (const Term &t : c->terms) {
+            if (!is_product(c, t)) continue;
+            std::vector<int> dk;
+            std::vector<std::vector<cd>> dm;
+            std::vector<std::vector<double>> diag(D);
+            for (const Factor &f : t.f) {
+                if (dense_kind(f.kind)) {
+                    dk.push_back(f.dim);
+                    dm.push_back(factor_matrix(c, f));
+                } else {
+                    std::vector<double> v = factor_values(c, f);
+                    if (diag[f.dim].empty()) diag[f.dim] = v;
+                    else
+                        for (size_t i = 0; i < v.size(); ++i) diag[f.dim][i] *= v[i];
+                }
+            }
+            std::vector<size_t> order(dk.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+            std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return dk[a] < dk[b]; });
+            std::vector<int> dks;
+            std::vector<std::vector<cd>> dms;
+            for (size_t i : order) {
+                dks.push_back(dk[i]);
+                dms.push_back(dm[i]);
+            }
+            bool herm = t.coef_im == 0.0 && dks.size() == 1, real = herm;
+            if (herm) {
+                const int n = c->g.n[dks[0]];
+                const std::vector<cd> &h = dms[0];
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        herm = herm && h[(size_t)i * n + j] == std::conj(h[(size_t)j * n + i]);
+                        real = real && h[(size_t)i * n + j].imag() == 0.0;
+                    }
+            }
+            c->hermitian = c->hermitian && herm;
+            c->real_sym = c->real_sym && herm && real;
+            add_product(t.coef, t.coef_im, dks, dms, diag);
+        }
     } else {
         std::vector<LatticeMaps> L(D);
         for (int k = 0; k < D; ++k) L[k] = lattice_maps(c, k);
@@ -673,73 +877,48 @@ void build_operator(ppq_ctx *c)
             for (size_t i = 0; i < h.size(); ++i) h[i] = T[i];
             Hk[k] = h;  // DVR-space sum, transformed at the end
         }
-        // distinct dense factors of product terms keyed by (dim, values)
-        std::vector<std::vector<double>> fvals;
-        auto factor_id = [&](int k, const std::vector<double> &v) {
-            for (size_t i = 0; i < fvals.size(); ++i)
-                if (c->Fdim[i] == k && fvals[i] == v) return (int)i;
-            fvals.push_back(v);
-            c->Fdim.push_back(k);
-            return (int)fvals.size() - 1;
-        };
         for (const Term &t : c->terms) {
-            std::vector<std::vector<double>> per(D);
+            // per dimension, the product of the term's factors on it (several
+            // diagonal factors multiply; a dense factor is alone on its dimension)
+            std::vector<std::vector<cd>> per(D);
             for (const Factor &f : t.f) {
-                std::vector<double> v = factor_values(c, f);
-                if (per[f.dim].empty()) per[f.dim] = v;
-                else
-                    for (size_t i = 0; i < v.size(); ++i) per[f.dim][i] *= v[i];
+                std::vector<cd> m = factor_matrix(c, f);
+                per[f.dim] = per[f.dim].empty() ? m : matmul(per[f.dim], m, c->g.n[f.dim]);
             }
             std::vector<int> dims;
             for (int k = 0; k < D; ++k)
                 if (!per[k].empty()) dims.push_back(k);
+            const cd coef(t.coef, t.coef_im);
             if (dims.size() == 1) {
-                int k = dims[0], n = c->g.n[k];
-                for (int i = 0; i < n; ++i) Hk[k][(size_t)i * n + i] += t.coef * per[k][i];
-            } else if (dims.size() == 2) {
-                PairTerm p;
-                p.coef = t.coef;
-                p.k1 = dims[0];
-                p.k2 = dims[1];
-                p.f1 = factor_id(dims[0], per[dims[0]]);
-                p.f2 = factor_id(dims[1], per[dims[1]]);
-                c->pairs.push_back(p);
-            } else if (!dims.empty()) {
-                throw std::invalid_argument("lattice bases support potential terms on at most two dimensions");
+                const int k = dims[0];
+                for (size_t i = 0; i < Hk[k].size(); ++i) Hk[k][i] += coef * per[k][i];
+            } else if (dims.size() >= 2) {
+                std::vector<std::vector<cd>> dms;
+                for (int k : dims) dms.push_back(similarity(L[k], per[k], c->g.n[k]));
+                add_product(t.coef, t.coef_im, dims, dms, std::vector<std::vector<double>>(D));
             }
         }
-        auto pad_upload = [&](const std::vector<cd> &h, int n, int b, double2 **d64, float2 **d32) {
-            std::vector<double2> P((size_t)b * b, make_double2(0.0, 0.0));
-            std::vector<float2> Pf((size_t)b * b, make_float2(0.f, 0.f));
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j) {
-                    cd v = h[(size_t)i * n + j];
-                    P[(size_t)i * b + j] = make_double2(v.real(), v.imag());
-                    Pf[(size_t)i * b + j] = make_float2((float)v.real(), (float)v.imag());
-                }
-            *d64 = upload(P, s);
-            *d32 = upload(Pf, s);
-        };
         for (int k = 0; k < D; ++k) {
             int n = c->g.n[k];
             std::vector<cd> ht = similarity(L[k], Hk[k], n);
             pad_upload(ht, n, c->nb[k], &c->H64[k], &c->H32[k]);
-            pad_upload(ht, n, 64, &c->H64p[k], &c->H32p[k]);
+            if (n <= NMAX_MASK) pad_upload(ht, n, 64, &c->H64p[k], &c->H32p[k]);
         }
-        for (size_t i = 0; i < fvals.size(); ++i) {
-            int k = c->Fdim[i], n = c->g.n[k];
-            std::vector<cd> h((size_t)n * n, cd(0.0, 0.0));
-            for (int j = 0; j < n; ++j) h[(size_t)j * n + j] = fvals[i][j];
-            std::vector<cd> ht = similarity(L[k], h, n);
-            double2 *d64;
-            float2 *d32;
-            pad_upload(ht, n, c->nb[k], &d64, &d32);
-            c->F64.push_back(d64);
-            c->F32.push_back(d32);
-            pad_upload(ht, n, 64, &d64, &d32);
-            c->F64p.push_back(d64);
-            c->F32p.push_back(d32);
-        }
+    }
+    // dense factors of the product terms, unpadded (nb x nb) and as 64 x 64
+    // matrix-core tiles
+    for (size_t i = 0; i < fmats.size(); ++i) {
+        const int k = c->Fdim[i], n = c->g.n[k];
+        double2 *d64;
+        float2 *d32;
+        pad_upload(fmats[i], n, c->nb[k], &d64, &d32);
+        c->F64.push_back(d64);
+        c->F32.push_back(d32);
+        d64 = nullptr;
+        d32 = nullptr;
+        if (n <= NMAX_MASK) pad_upload(fmats[i], n, 64, &d64, &d32);
+        c->F64p.push_back(d64);
+        c->F32p.push_back(d32);
     }
     ck(hipStreamSynchronize(s), "operator upload");
     c->op_dirty = false;
@@ -748,6 +927,16 @@ void build_operator(ppq_ctx *c)
 }
 
 void ensure_nf(ppq_ctx *c);
+
+// Dimensions longer than a fiber-mask word take the long-fiber tables and pass.
+bool is_long(const ppq_ctx *c, int k) { return c->g.n[k] > NMAX_MASK; }
+
+bool any_long(const ppq_ctx *c)
+{
+    for (int k = 0; k < c->g.D; ++k)
+        if (is_long(c, k)) return true;
+    return false;
+}
 
 // ---- derived tables of the current set --------------------------------------
 // Row-major fiber tables of dimension k (k < D - 1): pi_k, off_k, mask_k, info_k.
@@ -761,11 +950,13 @@ void build_row_major(ppq_ctx *c, int k)
     rot_set(keys, n, fr, c->bm, s);
     scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
     // the per-point fiber info of dimensions other than the last is read only
-    // by the point-parallel-everywhere layout
+    // by the point-parallel-everywhere layout and (as plain digits) by the
+    // long-fiber pass of dimensions longer than a mask word
+    const bool lng = is_long(c, k);
     rot_rank(keys, n, fr, c->bm, c->prefix, nullptr, c->pi[k], nullptr, c->flags, c->tmpmask,
-             c->hpsi_variant == 1 ? c->info[k] : nullptr, s);
+             (c->hpsi_variant == 1 || lng) ? c->info[k] : nullptr, s);
     scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
-    fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
+    fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], lng ? nullptr : c->mask[k], s);
 }
 
 // Tables of the outer dimensions [0, split) in the inner-first frame (digit
@@ -791,9 +982,10 @@ void build_inner_first(ppq_ctx *c)
         scan_u32(c->flags, n, c->fidx, &c->small[k], c->scan_tmp, s);
         fib_fill(c->flags, c->fidx, c->tmpmask, n, &c->small[k], c->off[k], c->mask[k], s);
         if (frame)
-            make_chunks(keys, c->P_R, n, sin, true, BLOCK_WINDOW, block_cap_small(c->precision), c->chunk[1],
+            make_chunks(keys, c->P_R, n, sin, true, c->blk_window,
+                        c->hpsi_variant == 5 ? block2_cap_small(c->precision) : block_cap_small(c->precision), c->chunk[1],
                         c->big[1], c->small + 2 * MAXD + 2, s);
-        chunk_fibers(c->chunk[1], n, BLOCK_WINDOW, c->fidx, &c->small[k], c->fch[k], s);
+        chunk_fibers(c->chunk[1], n, c->blk_window, c->fidx, &c->small[k], c->fch[k], s);
     }
 }
 
@@ -810,6 +1002,8 @@ int64_t batched_bytes(const ppq_ctx *c)
 
 bool ensure_batched(ppq_ctx *c)
 {
+    // the one-pass tables describe fibers by masks: dimensions of at most 64 points
+    if (any_long(c)) return false;
     const int64_t bytes = batched_bytes(c);
     if (bytes == 0 || bytes > BATCH_BYTES_MAX) return false;
     if (c->bat_cap == c->cap) return true;
@@ -841,10 +1035,12 @@ void build_derived(ppq_ctx *c)
     const int64_t n = c->nact;
     hipStream_t s = c->stream;
     const uint32_t *keys = c->keys[c->cur];
-    const bool try_block = c->block_ok && c->hpsi_variant == 4 && n > 0;
+    const bool try_block = c->block_ok && (c->hpsi_variant == 4 || c->hpsi_variant == 5) && n > 0 &&
+                           c->pairs.empty() && c->chains.empty();
+    const uint32_t cap_s = c->hpsi_variant == 5 ? block2_cap_small(c->precision) : block_cap_small(c->precision);
     if (try_block) {
         fill_u32(c->small + 2 * MAXD, 4, 0u, s);
-        make_chunks(keys, nullptr, n, c->g.stride[c->split - 1], false, BLOCK_WINDOW, block_cap_small(c->precision),
+        make_chunks(keys, nullptr, n, c->g.stride[c->split - 1], false, c->blk_window, cap_s,
                     c->chunk[0], c->big[0], c->small + 2 * MAXD, s);
     }
     // last dimension: contiguous runs
@@ -852,7 +1048,7 @@ void build_derived(ppq_ctx *c)
     scan_u32(c->flags, n, c->fidx, &c->small[D - 1], c->scan_tmp, s);
     last_fill(keys, n, c->g.n[D - 1], c->flags, c->fidx, &c->small[D - 1], c->off[D - 1], c->mask[D - 1], s);
     last_info(keys, n, c->g.n[D - 1], c->info[D - 1], s);
-    if (try_block) chunk_fibers(c->chunk[0], n, BLOCK_WINDOW, c->fidx, &c->small[D - 1], c->fch[D - 1], s);
+    if (try_block) chunk_fibers(c->chunk[0], n, c->blk_window, c->fidx, &c->small[D - 1], c->fch[D - 1], s);
     // the per-point fiber info of dimensions other than the last is read only
     // by the point-parallel-everywhere layout, which takes the per-dimension path
     if (!try_block && c->hpsi_variant != 1 && n > 0 && D > 1 && ensure_batched(c)) {
@@ -872,7 +1068,7 @@ void build_derived(ppq_ctx *c)
     } else {
         for (int k = try_block ? c->split : 0; k < D - 1; ++k) {
             build_row_major(c, k);
-            if (try_block) chunk_fibers(c->chunk[0], n, BLOCK_WINDOW, c->fidx, &c->small[k], c->fch[k], s);
+            if (try_block) chunk_fibers(c->chunk[0], n, c->blk_window, c->fidx, &c->small[k], c->fch[k], s);
         }
     }
     if (try_block) build_inner_first(c);
@@ -896,7 +1092,7 @@ void build_derived(ppq_ctx *c)
         ensure_nf(c);
         const uint32_t *cnt = c->h_small + 2 * MAXD;
         for (int i = 0; i < 2; ++i) {
-            c->nch[i] = (uint32_t)((n + BLOCK_WINDOW - 1) / BLOCK_WINDOW);
+            c->nch[i] = (uint32_t)((n + c->blk_window - 1) / c->blk_window);
             c->nbig[i] = cnt[2 * i];
             c->maxch[i] = cnt[2 * i + 1];
         }
@@ -936,9 +1132,20 @@ BlockPass block_pass(const ppq_ctx *c, int which)
     bp.P = which == 0 ? nullptr : c->P_R;
     bp.big = c->big[which];
     bp.nbig = c->nbig[which];
-    bp.cap_small = block_cap_small(c->precision);
+    bp.cap_small = c->hpsi_variant == 5 ? block2_cap_small(c->precision) : block_cap_small(c->precision);
     bp.cap_big = bp.nbig ? (c->maxch[which] + 63u) / 64u * 64u : 0u;
     return bp;
+}
+
+LongPass long_pass_of(const ppq_ctx *c, int k)
+{
+    LongPass lp;
+    lp.pi = (k == c->g.D - 1) ? nullptr : c->pi[k];
+    lp.off = c->off[k];
+    lp.dig = c->info[k];
+    lp.nf = c->nf[k];
+    lp.n = c->g.n[k];
+    return lp;
 }
 
 FiberPass pass_of(const ppq_ctx *c, int k)
@@ -952,13 +1159,38 @@ FiberPass pass_of(const ppq_ctx *c, int k)
     return fp;
 }
 
-// y = P H P x on the current set (device vectors of the context precision)
-void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
+// y = P H_1 P x: the one-dimensional factors and the diagonal potential
+void apply_single(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
 {
     ensure_nf(c);
     const int D = c->g.D;
     hipStream_t s = c->stream;
     if (c->nact == 0) return;
+    if (!c->any_lattice && any_long(c)) {
+        // dimensions longer than a mask word: the long-fiber pass; the others
+        // one lane per fiber; the last dimension's pass writes y with V fused
+        for (int k = D - 1; k >= 0; --k) {
+            const bool first = k == D - 1;
+            if (c->precision == PPQ_FP64) {
+                const double2 *x = (const double2 *)xv;
+                double2 *y = (double2 *)yv;
+                if (is_long(c, k))
+                    hpsi_long_real_f64(long_pass_of(c, k), c->T64[k], x, first ? c->V64 : nullptr, y, first, skip_if,
+                                       skip_j, s);
+                else
+                    hpsi_real_f64(pass_of(c, k), c->T64[k], x, first ? c->V64 : nullptr, y, first, skip_if, skip_j, s);
+            } else {
+                const float2 *x = (const float2 *)xv;
+                float2 *y = (float2 *)yv;
+                if (is_long(c, k))
+                    hpsi_long_real_f32(long_pass_of(c, k), c->T32[k], x, first ? c->V32 : nullptr, y, first, skip_if,
+                                       skip_j, s);
+                else
+                    hpsi_real_f32(pass_of(c, k), c->T32[k], x, first ? c->V32 : nullptr, y, first, skip_if, skip_j, s);
+            }
+        }
+        return;
+    }
     if (!c->any_lattice) {
         if (c->block_mode) {
             // inner-first pass over the outer dimensions writes y, the row-major
@@ -968,14 +1200,16 @@ void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
                 const double *To[BLOCK_MAXDIM], *Ti[BLOCK_MAXDIM];
                 for (int i = 0; i < outer.ndim; ++i) To[i] = c->T64[outer.dim[i]];
                 for (int i = 0; i < inner.ndim; ++i) Ti[i] = c->T64[inner.dim[i]];
-                hpsi_block_f64(outer, To, (const double2 *)xv, nullptr, (double2 *)yv, false, skip_if, skip_j, s);
-                hpsi_block_f64(inner, Ti, (const double2 *)xv, c->V64, (double2 *)yv, true, skip_if, skip_j, s);
+                auto run = c->hpsi_variant == 5 ? hpsi_block2_f64 : hpsi_block_f64;
+                run(outer, To, (const double2 *)xv, nullptr, (double2 *)yv, false, skip_if, skip_j, s);
+                run(inner, Ti, (const double2 *)xv, c->V64, (double2 *)yv, true, skip_if, skip_j, s);
             } else {
                 const float *To[BLOCK_MAXDIM], *Ti[BLOCK_MAXDIM];
                 for (int i = 0; i < outer.ndim; ++i) To[i] = c->T32[outer.dim[i]];
                 for (int i = 0; i < inner.ndim; ++i) Ti[i] = c->T32[inner.dim[i]];
-                hpsi_block_f32(outer, To, (const float2 *)xv, nullptr, (float2 *)yv, false, skip_if, skip_j, s);
-                hpsi_block_f32(inner, Ti, (const float2 *)xv, c->V32, (float2 *)yv, true, skip_if, skip_j, s);
+                auto run = c->hpsi_variant == 5 ? hpsi_block2_f32 : hpsi_block_f32;
+                run(outer, To, (const float2 *)xv, nullptr, (float2 *)yv, false, skip_if, skip_j, s);
+                run(inner, Ti, (const float2 *)xv, c->V32, (float2 *)yv, true, skip_if, skip_j, s);
             }
             return;
         }
@@ -1065,25 +1299,8 @@ void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
         }
         return;
     }
-    // lattice: single-dimension factors, then product terms (inner factor first,
-    // truncated to the set, then the outer factor on a combination of inner results)
-    ensure_zbuf(c);
-    std::vector<int> inner_ids;
-    for (const PairTerm &p : c->pairs)
-        if (std::find(inner_ids.begin(), inner_ids.end(), p.f2) == inner_ids.end()) inner_ids.push_back(p.f2);
-    std::vector<int> outer_ids;
-    for (const PairTerm &p : c->pairs)
-        if (std::find(outer_ids.begin(), outer_ids.end(), p.f1) == outer_ids.end()) outer_ids.push_back(p.f1);
-    // complex factors on the matrix cores (PPQ_HPSI=3: vector FMA)
+    // lattice: the single-dimension factors (complex; product terms follow)
     const bool mf = c->hpsi_variant != 3;
-    auto cpass64 = [&](int k, const double2 *Hn, const double2 *Hp, const CInput &in, double2 *out, bool acc) {
-        if (mf) hpsi_cmfma_f64(pass_of(c, k), Hp, in, out, acc, skip_if, skip_j, s);
-        else hpsi_cplx_f64(pass_of(c, k), Hn, in, out, acc, nullptr, skip_if, skip_j, s);
-    };
-    auto cpass32 = [&](int k, const float2 *Hn, const float2 *Hp, const CInput32 &in, float2 *out, bool acc) {
-        if (mf) hpsi_cmfma_f32(pass_of(c, k), Hp, in, out, acc, skip_if, skip_j, s);
-        else hpsi_cplx_f32(pass_of(c, k), Hn, in, out, acc, nullptr, skip_if, skip_j, s);
-    };
     if (c->precision == PPQ_FP64) {
         const double2 *x = (const double2 *)xv;
         double2 *y = (double2 *)yv;
@@ -1091,25 +1308,10 @@ void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
         in.nin = 1;
         in.x[0] = x;
         in.c[0] = make_double2(1.0, 0.0);
-        cpass64(D - 1, c->H64[D - 1], c->H64p[D - 1], in, y, false);
-        for (int k = D - 2; k >= 0; --k) cpass64(k, c->H64[k], c->H64p[k], in, y, true);
-        for (size_t i = 0; i < inner_ids.size(); ++i) {
-            int f = inner_ids[i];
-            cpass64(c->Fdim[f], c->F64[f], c->F64p[f], in, (double2 *)c->zbuf[i], false);
-        }
-        for (int f : outer_ids) {
-            CInput acc{};
-            for (const PairTerm &p : c->pairs) {
-                if (p.f1 != f) continue;
-                int zi = (int)(std::find(inner_ids.begin(), inner_ids.end(), p.f2) - inner_ids.begin());
-                acc.x[acc.nin] = (const double2 *)c->zbuf[zi];
-                acc.c[acc.nin] = make_double2(p.coef, 0.0);
-                if (++acc.nin == 4) {
-                    cpass64(c->Fdim[f], c->F64[f], c->F64p[f], acc, y, true);
-                    acc.nin = 0;
-                }
-            }
-            if (acc.nin) cpass64(c->Fdim[f], c->F64[f], c->F64p[f], acc, y, true);
+        for (int k = D - 1; k >= 0; --k) {
+            if (is_long(c, k)) hpsi_long_cplx_f64(long_pass_of(c, k), c->H64[k], in, y, k < D - 1, skip_if, skip_j, s);
+            else if (mf) hpsi_cmfma_f64(pass_of(c, k), c->H64p[k], in, y, k < D - 1, skip_if, skip_j, s);
+            else hpsi_cplx_f64(pass_of(c, k), c->H64[k], in, y, k < D - 1, nullptr, skip_if, skip_j, s);
         }
     } else {
         const float2 *x = (const float2 *)xv;
@@ -1118,27 +1320,118 @@ void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
         in.nin = 1;
         in.x[0] = x;
         in.c[0] = make_float2(1.f, 0.f);
-        cpass32(D - 1, c->H32[D - 1], c->H32p[D - 1], in, y, false);
-        for (int k = D - 2; k >= 0; --k) cpass32(k, c->H32[k], c->H32p[k], in, y, true);
-        for (size_t i = 0; i < inner_ids.size(); ++i) {
-            int f = inner_ids[i];
-            cpass32(c->Fdim[f], c->F32[f], c->F32p[f], in, (float2 *)c->zbuf[i], false);
-        }
-        for (int f : outer_ids) {
-            CInput32 acc{};
-            for (const PairTerm &p : c->pairs) {
-                if (p.f1 != f) continue;
-                int zi = (int)(std::find(inner_ids.begin(), inner_ids.end(), p.f2) - inner_ids.begin());
-                acc.x[acc.nin] = (const float2 *)c->zbuf[zi];
-                acc.c[acc.nin] = make_float2((float)p.coef, 0.f);
-                if (++acc.nin == 4) {
-                    cpass32(c->Fdim[f], c->F32[f], c->F32p[f], acc, y, true);
-                    acc.nin = 0;
-                }
-            }
-            if (acc.nin) cpass32(c->Fdim[f], c->F32[f], c->F32p[f], acc, y, true);
+        for (int k = D - 1; k >= 0; --k) {
+            if (is_long(c, k)) hpsi_long_cplx_f32(long_pass_of(c, k), c->H32[k], in, y, k < D - 1, skip_if, skip_j, s);
+            else if (mf) hpsi_cmfma_f32(pass_of(c, k), c->H32p[k], in, y, k < D - 1, skip_if, skip_j, s);
+            else hpsi_cplx_f32(pass_of(c, k), c->H32[k], in, y, k < D - 1, nullptr, skip_if, skip_j, s);
         }
     }
+}
+
+// y += the product terms (Sec. II.B.2; each intermediate truncated to the
+// set).  Two-factor terms without diagonal factors are grouped by their inner
+// factor: it is applied once per distinct factor, and each outer factor acts
+// on a weighted sum (the coefficients) of up to four inner results.  Other
+// terms go one at a time: their diagonal factors scale the input (diagonal
+// matrices commute with the truncation), then the dense factors act from the
+// highest dimension down, the last one adding coef times its result to y.
+template <class C, class CIn, class W>
+void apply_products_t(ppq_ctx *c, const C *x, C *y, const int *skip_if, int skip_j,
+                      const std::vector<const void *> &Fn, const std::vector<const void *> &Fp,
+                      W (*mk)(double, double))
+{
+    hipStream_t s = c->stream;
+    const bool mf = c->hpsi_variant != 3;
+    auto cpass = [&](int k, int f, const CIn &in, C *out, bool acc) {
+        if constexpr (std::is_same<C, double2>::value) {
+            if (is_long(c, k))
+                hpsi_long_cplx_f64(long_pass_of(c, k), (const double2 *)Fn[f], in, out, acc, skip_if, skip_j, s);
+            else if (mf) hpsi_cmfma_f64(pass_of(c, k), (const double2 *)Fp[f], in, out, acc, skip_if, skip_j, s);
+            else hpsi_cplx_f64(pass_of(c, k), (const double2 *)Fn[f], in, out, acc, nullptr, skip_if, skip_j, s);
+        } else {
+            if (is_long(c, k))
+                hpsi_long_cplx_f32(long_pass_of(c, k), (const float2 *)Fn[f], in, out, acc, skip_if, skip_j, s);
+            else if (mf) hpsi_cmfma_f32(pass_of(c, k), (const float2 *)Fp[f], in, out, acc, skip_if, skip_j, s);
+            else hpsi_cplx_f32(pass_of(c, k), (const float2 *)Fn[f], in, out, acc, nullptr, skip_if, skip_j, s);
+        }
+    };
+    C **z = (C **)c->zbuf.data();
+    std::vector<int> inner_ids, outer_ids;
+    for (const PairTerm &p : c->pairs) {
+        if (std::find(inner_ids.begin(), inner_ids.end(), p.f2) == inner_ids.end()) inner_ids.push_back(p.f2);
+        if (std::find(outer_ids.begin(), outer_ids.end(), p.f1) == outer_ids.end()) outer_ids.push_back(p.f1);
+    }
+    CIn one{};
+    one.nin = 1;
+    one.x[0] = x;
+    one.c[0] = mk(1.0, 0.0);
+    for (size_t i = 0; i < inner_ids.size(); ++i) cpass(c->Fdim[inner_ids[i]], inner_ids[i], one, z[i], false);
+    for (int f : outer_ids) {
+        CIn acc{};
+        for (const PairTerm &p : c->pairs) {
+            if (p.f1 != f) continue;
+            const int zi = (int)(std::find(inner_ids.begin(), inner_ids.end(), p.f2) - inner_ids.begin());
+            acc.x[acc.nin] = z[zi];
+            acc.c[acc.nin] = mk(p.cre, p.cim);
+            if (++acc.nin == 4) {
+                cpass(c->Fdim[f], f, acc, y, true);
+                acc.nin = 0;
+            }
+        }
+        if (acc.nin) cpass(c->Fdim[f], f, acc, y, true);
+    }
+    for (const ProdTerm &t : c->chains) {
+        const C *src = x;
+        if (t.use || t.nf == 0) {
+            // the diagonal factors (none: a constant term): straight into y for a
+            // term without dense ones
+            const bool alone = t.nf == 0;
+            diag_scale<C>(c->keys[c->cur], x, c->nact, c->g, t.use ? c->PD64[t.diag] : nullptr, c->pd_nmax, t.use,
+                          alone ? make_double2(t.cre, t.cim) : make_double2(1.0, 0.0), alone ? y : z[0], alone,
+                          skip_if, skip_j, s);
+            if (alone) continue;
+            src = z[0];
+        }
+        for (int f = t.nf - 1; f >= 0; --f) {
+            CIn in{};
+            in.nin = 1;
+            in.x[0] = src;
+            if (f == 0) {
+                in.c[0] = mk(t.cre, t.cim);
+                cpass(t.k[f], t.fid[f], in, y, true);
+            } else {
+                in.c[0] = mk(1.0, 0.0);
+                C *dst = (src == z[1]) ? z[2] : z[1];
+                cpass(t.k[f], t.fid[f], in, dst, false);
+                src = dst;
+            }
+        }
+    }
+}
+
+inline double2 mk64(double r, double i) { return make_double2(r, i); }
+inline float2 mk32(double r, double i) { return make_float2((float)r, (float)i); }
+
+void apply_products(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
+{
+    if (c->pairs.empty() && c->chains.empty()) return;
+    ensure_zbuf(c);
+    if (c->precision == PPQ_FP64) {
+        std::vector<const void *> Fn(c->F64.begin(), c->F64.end()), Fp(c->F64p.begin(), c->F64p.end());
+        apply_products_t<double2, CInput, double2>(c, (const double2 *)xv, (double2 *)yv, skip_if, skip_j, Fn, Fp,
+                                                   mk64);
+    } else {
+        std::vector<const void *> Fn(c->F32.begin(), c->F32.end()), Fp(c->F32p.begin(), c->F32p.end());
+        apply_products_t<float2, CInput32, float2>(c, (const float2 *)xv, (float2 *)yv, skip_if, skip_j, Fn, Fp,
+                                                   mk32);
+    }
+}
+
+// y = P H P x on the current set (device vectors of the context precision)
+void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
+{
+    apply_single(c, xv, yv, skip_if, skip_j);
+    if (c->nact > 0) apply_products(c, xv, yv, skip_if, skip_j);
 }
 
 // Launch errors (a configuration the device refuses) surface here rather than
@@ -1211,7 +1504,7 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, doub
     const int64_t ld = c->cap;
     C *w = (C *)c->wk;
     const int *meff = &ks->meff;
-    const bool herm = !c->any_lattice;
+    const bool herm = c->hermitian;
     norm0<C>(src, n, c->partial, c->counter, ks, m, dt, tol, s);
     normalise_from_master<C>(src, n, ks, Vb, s);
     for (int j = 0; j < m; ++j) {
@@ -1239,24 +1532,100 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, doub
 }
 
 template <class C>
-void step_impl(ppq_ctx *c, double dt, int m)
+void step_impl(ppq_ctx *c, double dt, int m, double tol)
 {
     mark(c, PPQ_PHASE_KRYLOV);
     C *Vb = (C *)c->Vk;
-    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m, dt, c->krylov_tol);
-    krylov_expv(c->ks, m, dt, c->any_lattice ? 0 : 1, c->stream);
+    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m, dt, tol);
+    krylov_expv(c->ks, m, dt, c->hermitian ? 1 : 0, c->stream);
     lincomb<C>(Vb, c->cap, c->psi[c->cur], c->nact, c->ks, c->psi_tmp, c->stream);
     std::swap(c->psi[c->cur], c->psi_tmp);
 }
 
-void do_step(ppq_ctx *c, double dt, int m)
+// Outcome of one step: the Krylov order (-1: only on the device, in ks) and
+// the number of substeps.
+struct StepInfo {
+    int meff = -1;
+    int nsub = 1;
+};
+
+void step_any(ppq_ctx *c, double dt, int m)
+{
+    if (c->precision == PPQ_FP64) step_impl<double2>(c, dt, m, c->krylov_tol);
+    else step_impl<float2>(c, dt, m, c->krylov_tol);
+}
+
+// One step of length dt on the current set (tables built).  Without step
+// control one SIL step.  With control (max_substeps > 1 and a Krylov
+// tolerance) s substeps of dt/s, s from the previous step; each substep's
+// order goes to sub_meff and the host reads them once per attempt: an order
+// of m means the tolerance was not met below m, and the step is redone from
+// its saved start with 2s substeps.  alpha0_dst (device, may be NULL)
+// receives alpha_0 of the first substep: the energy of the state at the start.
+StepInfo advance(ppq_ctx *c, double dt, int m, double *alpha0_dst)
+{
+    StepInfo info;
+    hipStream_t s = c->stream;
+    if (c->nact == 0) return info;
+    if (c->max_substeps <= 1 || !(c->krylov_tol > 0.0)) {
+        step_any(c, dt, m);
+        if (alpha0_dst) copy_alpha0(c->ks, alpha0_dst, s);
+        return info;
+    }
+    if (c->sub_cap < c->max_substeps) {
+        dfree(c->sub_meff);
+        if (c->h_sub_meff) (void)hipHostFree(c->h_sub_meff);
+        c->h_sub_meff = nullptr;
+        c->sub_meff = dalloc<double>(c->max_substeps);
+        ck(hipHostMalloc((void **)&c->h_sub_meff, sizeof(double) * c->max_substeps, hipHostMallocDefault),
+           "pinned");
+        c->sub_cap = c->max_substeps;
+    }
+    if (c->psi_save_cap < c->cap) {
+        dfree(c->psi_save);
+        c->psi_save = dalloc<double2>(c->cap);
+        c->psi_save_cap = c->cap;
+    }
+    ck(hipMemcpyAsync(c->psi_save, c->psi[c->cur], c->nact * sizeof(double2), hipMemcpyDeviceToDevice, s), "save");
+    int sub = std::min(std::max(c->nsub, 1), c->max_substeps);
+    for (;;) {
+        const double h = dt / (double)sub;
+        for (int j = 0; j < sub; ++j) {
+            step_any(c, h, m);
+            if (j == 0 && alpha0_dst) copy_alpha0(c->ks, alpha0_dst, s);
+            copy_meff(c->ks, c->sub_meff + j, s);
+        }
+        ck(hipMemcpyAsync(c->h_sub_meff, c->sub_meff, sizeof(double) * sub, hipMemcpyDeviceToHost, s), "orders");
+        ck(hipStreamSynchronize(s), "orders");
+        int mo = 0;
+        bool ok = true;
+        for (int j = 0; j < sub; ++j) {
+            const int me = (int)c->h_sub_meff[j];
+            mo = std::max(mo, me);
+            ok = ok && me < m;
+        }
+        if (ok) {
+            info.meff = mo;
+            info.nsub = sub;
+            c->nsub = (mo <= m / 2 && sub > 1) ? sub / 2 : sub;
+            return info;
+        }
+        ck(hipMemcpyAsync(c->psi[c->cur], c->psi_save, c->nact * sizeof(double2), hipMemcpyDeviceToDevice, s),
+           "restore");
+        sub *= 2;
+        if (sub > c->max_substeps) {
+            ck(hipStreamSynchronize(s), "restore");
+            throw std::runtime_error("a step does not meet the Krylov tolerance within the allowed substeps");
+        }
+    }
+}
+
+StepInfo do_step(ppq_ctx *c, double dt, int m)
 {
     mark(c, PPQ_PHASE_TABLES);
     build_derived(c);
     ensure_krylov(c, m);
-    if (c->nact == 0) return;
-    if (c->precision == PPQ_FP64) step_impl<double2>(c, dt, m);
-    else step_impl<float2>(c, dt, m);
+    return advance(c, dt, m, nullptr);
 }
 
 // adaption; returns false (state untouched) only on allocation failure
@@ -1303,10 +1672,11 @@ void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
     c->v_partial = carry;
 }
 
-void set_record_host(ppq_ctx *c, int64_t r, double t, int krylov)
+void set_record_host(ppq_ctx *c, int64_t r, double t, int krylov, int nsub = 1)
 {
-    // t, |A| and the Krylov dimension are host-known: kernel arguments, no sync
-    set_record(c->rec + r * PPQ_OBS_N, t, (double)c->nact, (double)krylov, c->stream);
+    // t, |A|, the Krylov dimension and the substeps are host-known: kernel
+    // arguments, no sync
+    set_record(c->rec + r * PPQ_OBS_N, t, (double)c->nact, (double)krylov, (double)nsub, c->stream);
 }
 
 void ensure_records(ppq_ctx *c, int64_t nrec)
@@ -1444,6 +1814,7 @@ void set_current_set(ppq_ctx *c, const uint32_t *keys_dev, int64_t n)
               "set keys");
     c->nact = n;
     c->has_state = true;
+    c->nsub = 1;
     c->derived_valid = false;
     c->v_valid = false;
     c->v_partial = false;
@@ -1496,6 +1867,7 @@ void clear_record(ppq_ctx *c)
     c->ckpt.clear();
     c->rec_off.clear();
     c->rec_n.clear();
+    c->rec_sub.clear();
     c->recorded = false;
 }
 
@@ -1519,6 +1891,7 @@ double2 overlap_with_packet(ppq_ctx *c)
     return make_double2(r[PPQ_OBS_ACF_RE], r[PPQ_OBS_ACF_IM]);
 }
 
+// K: the most states one recomputed segment holds (its steps' substeps)
 void ensure_adjoint_buffers(ppq_ctx *c, int m, int K)
 {
     const size_t es = c->precision == PPQ_FP64 ? sizeof(double2) : sizeof(float2);
@@ -1563,19 +1936,27 @@ void adjoint_backward(ppq_ctx *c, double2 C_N)
     // lambda_N = psi0 restricted to A_N
     product_values(keys_of(N), c->rec_n[N], c->g, c->bra_tabs, c->tab_nmax, c->lam, s);
     const int nseg = (N + K - 1) / K;
+    std::vector<int> slot(N + 1, 0);  // first segment state of each step
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int a = sg * K, e = std::min(a + K, N);
         set_current_set(c, keys_of(a), c->rec_n[a]);
         if (c->rec_n[a])
             ck(hipMemcpyAsync(c->psi[c->cur], c->ckpt[sg], c->rec_n[a] * sizeof(double2), hipMemcpyDeviceToDevice, s),
                "restore");
+        // recompute the segment, keeping the state at the start of every substep
+        int idx = 0;
         for (int st = a; st < e; ++st) {
-            if (c->nact)
-                ck(hipMemcpyAsync(c->seg + (int64_t)(st - a) * c->cap, c->psi[c->cur], c->nact * sizeof(double2),
-                                  hipMemcpyDeviceToDevice, s),
-                   "segment");
+            const int ns = c->rec_sub[st];
+            const double h = dt / (double)ns;
+            slot[st] = idx;
             build_derived(c);
-            if (c->nact) step_impl<C>(c, dt, m);
+            for (int j = 0; j < ns; ++j, ++idx) {
+                if (c->nact)
+                    ck(hipMemcpyAsync(c->seg + (int64_t)idx * c->cap, c->psi[c->cur], c->nact * sizeof(double2),
+                                      hipMemcpyDeviceToDevice, s),
+                       "segment");
+                if (c->nact) step_impl<C>(c, h, m, c->rec_tol);
+            }
             frozen_remap(c, keys_of(st + 1), c->rec_n[st + 1]);
         }
         if (e == N) {
@@ -1599,18 +1980,25 @@ void adjoint_backward(ppq_ctx *c, double2 C_N)
             set_current_set(c, keys_of(st), nn);
             build_derived(c);
             if (nn == 0) continue;
-            const double2 *psi_n = c->seg + (int64_t)(st - a) * c->cap;
-            krylov_build<C>(c, psi_n, (C *)c->Vk, c->ks, m);
-            krylov_build<C>(c, c->mu, (C *)c->Wk, c->ks_b, m);
-            adj_q(c->ks, c->ks_b, dt, c->Qd, s);
-            if (c->nparam > 0) {
-                adj_reduce<C>((const C *)c->Vk, (const C *)c->Wk, c->cap, psi_n, c->mu, c->ks, c->ks_b, c->Qd,
-                              keys_of(st), nn, c->g, dd, c->partial, s);
-                adj_accumulate(c->partial, c->nparam, make_double2(0.0, -dt), c->dC, s);
+            // the substeps of the step, last first: each is a step map exp(-i H h)
+            // on the same set, so the recursion runs through them as through steps
+            const int ns = c->rec_sub[st];
+            const double h = dt / (double)ns;
+            for (int j = ns - 1; j >= 0; --j) {
+                const double2 *psi_n = c->seg + (int64_t)(slot[st] + j) * c->cap;
+                krylov_build<C>(c, psi_n, (C *)c->Vk, c->ks, m);
+                krylov_build<C>(c, c->mu, (C *)c->Wk, c->ks_b, m);
+                adj_q(c->ks, c->ks_b, h, c->Qd, s);
+                if (c->nparam > 0) {
+                    adj_reduce<C>((const C *)c->Vk, (const C *)c->Wk, c->cap, psi_n, c->mu, c->ks, c->ks_b, c->Qd,
+                                  keys_of(st), nn, c->g, dd, c->partial, s);
+                    adj_accumulate(c->partial, c->nparam, make_double2(0.0, -h), c->dC, s);
+                }
+                // lambda = exp(+i H h) mu
+                krylov_expv(c->ks_b, m, -h, 1, s);
+                lincomb<C>((const C *)c->Wk, c->cap, c->mu, nn, c->ks_b, c->lam, s);
+                if (j > 0) std::swap(c->mu, c->lam);
             }
-            // lambda_st = exp(+i H dt) mu
-            krylov_expv(c->ks_b, m, -dt, 1, s);
-            lincomb<C>((const C *)c->Wk, c->cap, c->mu, nn, c->ks_b, c->lam, s);
         }
     }
     // <lambda_0 | d psi0 / d theta>
@@ -1618,6 +2006,18 @@ void adjoint_backward(ppq_ctx *c, double2 C_N)
     adj_accumulate(c->partial, 2 * D, make_double2(1.0, 0.0), c->dC + c->nparam, s);
     ck(hipStreamSynchronize(s), "adjoint");
     (void)C_N;
+}
+
+// the most states a recomputed segment holds
+int max_segment_states(const ppq_ctx *c)
+{
+    int best = 1;
+    for (int a = 0; a < c->rec_steps; a += c->rec_every) {
+        int t = 0;
+        for (int st = a; st < std::min(a + c->rec_every, c->rec_steps); ++st) t += c->rec_sub[st];
+        best = std::max(best, t);
+    }
+    return best;
 }
 
 }  // namespace
@@ -1693,7 +2093,11 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
     c->precision = precision;
     if (const char *v = std::getenv("PPQ_HPSI")) {
         const int h = std::atoi(v);
-        if (h >= 0 && h <= 4) c->hpsi_variant = h;  // other values keep the default layout
+        if (h >= 0 && h <= 5) c->hpsi_variant = h;  // other values keep the default layout
+    }
+    if (const char *v = std::getenv("PPQ_BLOCK_WINDOW")) {
+        const long w = std::atol(v);
+        if (w >= (long)BLOCK_WINDOW && w <= (1l << 20)) c->blk_window = (uint32_t)w;
     }
     try {
         ck(hipSetDevice(device), "hipSetDevice");
@@ -1741,6 +2145,9 @@ void ppq_destroy(ppq_ctx *c)
     dfree(c->ks);
     dfree(c->partial);
     dfree(c->counter);
+    for (auto &p : c->full) dfree(p);
+    dfree(c->sub_meff);
+    if (c->h_sub_meff) (void)hipHostFree(c->h_sub_meff);
     dfree(c->small);
     dfree(c->count);
     dfree(c->init_tabs);
@@ -1798,7 +2205,7 @@ int ppq_set_grid(ppq_ctx *c, int D, const int32_t *n, const double *lo, const do
     if (D < 1 || D > MAXD || !n || !lo || !hi || !(mass > 0.0)) return fail(c, PPQ_E_ARG, "bad grid arguments");
     uint64_t total = 1;
     for (int k = 0; k < D; ++k) {
-        if (n[k] < 2 || n[k] > NMAX_FIBER) return fail(c, PPQ_E_ARG, "n[k] must be in [2, 64]");
+        if (n[k] < 2 || n[k] > NMAX_FIBER) return fail(c, PPQ_E_ARG, "n[k] must be in [2, 256]");
         if (!(hi[k] > lo[k])) return fail(c, PPQ_E_ARG, "box must have hi > lo");
         total *= (uint64_t)n[k];
         if (total >= (1ull << 32)) return fail(c, PPQ_E_CAPACITY, "grid size must be < 2^32");
@@ -1899,15 +2306,18 @@ int ppq_set_weylets(ppq_ctx *c, int k, int nx, int np)
     return set_lattice_kind(c, k, nx, np, true);
 }
 
-int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dims, const int32_t *kinds,
-                           const double *params, const double *tables)
+namespace {
+// Parses the factors of one term (layout of ppq_add_term); dense kinds only
+// when allow_dense.  Returns PPQ_OK or the error (message set).
+int parse_term(ppq_ctx *c, double cre, double cim, int nfac, const int32_t *dims, const int32_t *kinds,
+               const double *params, const double *data, bool allow_dense, Term &t)
 {
-    PPQ_GUARD(c)
-    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
     if (nfac < 0 || nfac > 4 * MAXD || (nfac > 0 && (!dims || !kinds))) return fail(c, PPQ_E_ARG, "bad factors");
-    Term t;
-    t.coef = coef;
+    if (!std::isfinite(cre) || !std::isfinite(cim)) return fail(c, PPQ_E_NUMERIC, "non-finite coefficient");
+    t.coef = cre;
+    t.coef_im = cim;
     int64_t toff = 0;
+    unsigned dense_dims = 0, all_dims = 0;
     for (int f = 0; f < nfac; ++f) {
         Factor fa;
         fa.dim = dims[f];
@@ -1915,31 +2325,66 @@ int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dim
         if (fa.dim < 0 || fa.dim >= c->g.D) return fail(c, PPQ_E_ARG, "factor dimension out of range");
         fa.p0 = params ? params[2 * f] : 0.0;
         fa.p1 = params ? params[2 * f + 1] : 0.0;
+        const int64_t n = c->g.n[fa.dim];
         if (fa.kind == PPQ_FAC_POWER) {
             if (fa.p0 < 0 || fa.p0 > 16 || fa.p0 != std::floor(fa.p0))
                 return fail(c, PPQ_E_ARG, "power must be an integer in [0, 16]");
         } else if (fa.kind == PPQ_FAC_MORSE || fa.kind == PPQ_FAC_MORSE_DA) {
-        } else if (fa.kind == PPQ_FAC_TABLE) {
-            if (!tables) return fail(c, PPQ_E_ARG, "table factor without tables");
-            fa.table.assign(tables + toff, tables + toff + c->g.n[fa.dim]);
-            toff += c->g.n[fa.dim];
+        } else if (fa.kind == PPQ_FAC_TABLE || (allow_dense && dense_kind(fa.kind))) {
+            const int64_t len = fa.kind == PPQ_FAC_TABLE ? n : fa.kind == PPQ_FAC_DENSE_REAL ? n * n : 2 * n * n;
+            if (!data) return fail(c, PPQ_E_ARG, "table or dense factor without data");
+            fa.table.assign(data + toff, data + toff + len);
+            toff += len;
+            for (double v : fa.table)
+                if (!std::isfinite(v)) return fail(c, PPQ_E_NUMERIC, "non-finite factor entry");
+            if (dense_kind(fa.kind)) {
+                if ((dense_dims | all_dims) >> fa.dim & 1u)
+                    return fail(c, PPQ_E_ARG, "a dense factor must be the only factor on its dimension");
+                dense_dims |= 1u << fa.dim;
+            }
         } else {
             return fail(c, PPQ_E_ARG, "unknown factor kind");
         }
+        if (!dense_kind(fa.kind) && (dense_dims >> fa.dim & 1u))
+            return fail(c, PPQ_E_ARG, "a dense factor must be the only factor on its dimension");
+        all_dims |= 1u << fa.dim;
         t.f.push_back(fa);
     }
-    if (c->any_lattice) {
-        int used[MAXD] = {0};
-        int nd = 0;
-        for (auto &fa : t.f)
-            if (!used[fa.dim]++) ++nd;
-        if (nd > 2) return fail(c, PPQ_E_UNSUPPORTED, "lattice bases support terms on at most two dimensions");
-    }
-    c->terms.push_back(t);
+    return PPQ_OK;
+}
+
+void operator_changed(ppq_ctx *c)
+{
     c->op_dirty = true;
     c->derived_valid = false;
     c->v_valid = false;
     c->v_partial = false;
+}
+}  // namespace
+
+int ppq_add_potential_term(ppq_ctx *c, double coef, int nfac, const int32_t *dims, const int32_t *kinds,
+                           const double *params, const double *tables)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    Term t;
+    const int r = parse_term(c, coef, 0.0, nfac, dims, kinds, params, tables, false, t);
+    if (r != PPQ_OK) return r;
+    c->terms.push_back(t);
+    operator_changed(c);
+    return PPQ_OK;
+}
+
+int ppq_add_term(ppq_ctx *c, double c_re, double c_im, int nfac, const int32_t *dims, const int32_t *kinds,
+                 const double *params, const double *data)
+{
+    PPQ_GUARD(c)
+    if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
+    Term t;
+    const int r = parse_term(c, c_re, c_im, nfac, dims, kinds, params, data, true, t);
+    if (r != PPQ_OK) return r;
+    c->terms.push_back(t);
+    operator_changed(c);
     return PPQ_OK;
 }
 
@@ -2041,6 +2486,7 @@ int ppq_init_gaussian(ppq_ctx *c, const double *centre, const double *momentum, 
         product_values(c->keys[c->cur], n0, c->g, c->init_tabs, nmax, c->psi[c->cur], s);
         c->nact = n0;
         c->has_state = true;
+        c->nsub = 1;
         c->derived_valid = false;
         c->v_valid = false;
         c->v_partial = false;
@@ -2089,6 +2535,7 @@ int ppq_set_state(ppq_ctx *c, int64_t count, const uint64_t *keys, const double 
         ck(hipStreamSynchronize(c->stream), "set state");
         c->nact = count;
         c->has_state = true;
+        c->nsub = 1;
         c->derived_valid = false;
         c->v_valid = false;
         c->v_partial = false;
@@ -2171,6 +2618,7 @@ int ppq_set_state_device(ppq_ctx *c, int64_t count, const uint64_t *keys, const 
             c->cur = nxt;
             c->nact = count;
             c->has_state = true;
+            c->nsub = 1;
             c->derived_valid = false;
             c->v_valid = false;
             c->v_partial = false;
@@ -2275,6 +2723,14 @@ int ppq_set_krylov_tolerance(ppq_ctx *c, double tol)
     return PPQ_OK;
 }
 
+int ppq_set_step_control(ppq_ctx *c, int max_substeps)
+{
+    PPQ_GUARD(c)
+    if (max_substeps < 1 || max_substeps > 1024) return fail(c, PPQ_E_ARG, "max_substeps must be in [1, 1024]");
+    c->max_substeps = max_substeps;
+    return PPQ_OK;
+}
+
 int ppq_set_relative_exclusion(ppq_ctx *c, double r)
 {
     PPQ_GUARD(c)
@@ -2296,24 +2752,21 @@ int ppq_propagate(ppq_ctx *c, int nsteps, double dt, int m, double eps, double *
         build_derived(c);
         mark(c, PPQ_PHASE_OBS);
         observe_into(c, 0, eps_obs);
-        set_record_host(c, 0, 0.0, 0);
+        set_record_host(c, 0, 0.0, 0, 0);
         for (int st = 1; st <= nsteps; ++st) {
             mark(c, PPQ_PHASE_TABLES);
             build_derived(c);
             ensure_krylov(c, m);
-            if (c->nact) {
-                if (c->precision == PPQ_FP64) step_impl<double2>(c, dt, m);
-                else step_impl<float2>(c, dt, m);
-                // energy of the previous record = alpha_0 of this step
-                copy_alpha0(c->ks, c->rec + (int64_t)(st - 1) * PPQ_OBS_N + PPQ_OBS_ENERGY, c->stream);
-            }
+            // energy of the previous record = alpha_0 of this step
+            const bool had = c->nact > 0;
+            const StepInfo info = advance(c, dt, m, c->rec + (int64_t)(st - 1) * PPQ_OBS_N + PPQ_OBS_ENERGY);
             if (eps >= 0.0) do_prune(c, eps, nullptr);
             mark(c, PPQ_PHASE_TABLES);
             build_derived(c);
             mark(c, PPQ_PHASE_OBS);
             observe_into(c, st, eps_obs);
-            set_record_host(c, st, st * dt, m);
-            if (c->nact) copy_meff(c->ks, c->rec + (int64_t)st * PPQ_OBS_N + PPQ_OBS_KRYLOV, c->stream);
+            set_record_host(c, st, st * dt, info.meff >= 0 ? info.meff : m, info.nsub);
+            if (had && info.meff < 0) copy_meff(c->ks, c->rec + (int64_t)st * PPQ_OBS_N + PPQ_OBS_KRYLOV, c->stream);
         }
         energy_into(c, nsteps);
         mark(c, PHASE_NONE);
@@ -2337,7 +2790,7 @@ int ppq_observables(ppq_ctx *c, double eps, double *out)
         ensure_records(c, 1);
         build_derived(c);
         observe_into(c, 0, eps);
-        set_record_host(c, 0, 0.0, 0);
+        set_record_host(c, 0, 0.0, 0, 0);
         energy_into(c, 0);
         ck(hipStreamSynchronize(c->stream), "observables");
         ck(hipMemcpy(out, c->rec, sizeof(double) * PPQ_OBS_N, hipMemcpyDeviceToHost), "obs");
@@ -2422,10 +2875,44 @@ int ppq_acf_doubled(ppq_ctx *c, double *c2t)
     PPQ_GUARD(c)
     if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
     if (!c2t) return fail(c, PPQ_E_ARG, "bad arguments");
-    if (c->any_lattice) return fail(c, PPQ_E_UNSUPPORTED, "C(2t) needs a real symmetric operator (DVR dimensions)");
+    PPQ_TRY(c, { build_operator(c); })
+    if (!c->any_lattice && !c->real_sym) return fail(c, PPQ_E_UNSUPPORTED, "C(2t) needs a real symmetric operator");
+    if (c->any_lattice && !c->dvr_real_sym)
+        return fail(c, PPQ_E_UNSUPPORTED, "C(2t) needs an operator real symmetric in the DVR basis");
+    if (c->any_lattice && c->g.total > ACF2_MAX_FULL)
+        return fail(c, PPQ_E_CAPACITY, "C(2t) on a lattice basis transforms the full grid: at most 2^28 points");
     PPQ_TRY(c, {
         if (!c->acf2) c->acf2 = dalloc<double2>(1);
-        sum_of_squares(c->psi[c->cur], c->nact, c->partial, c->acf2, c->stream);
+        if (!c->any_lattice) {
+            sum_of_squares(c->psi[c->cur], c->nact, c->partial, c->acf2, c->stream);
+        } else {
+            // DVR coefficients on the full grid, c = (x)_k B_k a with B_k =
+            // G_k^{-+} (a = G^+ c), then C(2t) = c^T c = a^T B^T B a
+            const int64_t total = c->g.total;
+            if (c->full_cap < total) {
+                for (auto &p : c->full) dfree(p);
+                c->full[0] = dalloc<double2>(total);
+                c->full[1] = dalloc<double2>(total);
+                c->full_cap = total;
+            }
+            hipStream_t s = c->stream;
+            fill_zero_bytes(c->full[0], total * (int64_t)sizeof(double2), s);
+            scatter_full(c->keys[c->cur], c->psi[c->cur], c->nact, c->full[0], s);
+            int cur = 0;
+            for (int k = 0; k < c->g.D; ++k) {
+                if (!c->lattice[k]) continue;
+                const int n = c->g.n[k];
+                const LatticeMaps L = lattice_maps(c, k);
+                std::vector<double2> B((size_t)n * n);
+                for (size_t i = 0; i < B.size(); ++i) B[i] = make_double2(L.GinvAdj[i].real(), L.GinvAdj[i].imag());
+                double2 *dB = upload(B, s);
+                transform_full(c->full[cur], c->full[1 - cur], total, (int64_t)c->g.stride[k], n, dB, s);
+                ck(hipStreamSynchronize(s), "C(2t) transform");
+                dfree(dB);
+                cur = 1 - cur;
+            }
+            sum_of_squares(c->full[cur], total, c->partial, c->acf2, s);
+        }
         ck(hipGetLastError(), "C(2t) launch");
         ck(hipStreamSynchronize(c->stream), "C(2t)");
         double2 v;
@@ -2479,22 +2966,46 @@ int ppq_adjoint_record(ppq_ctx *c, const double *centre, const double *momentum,
     PPQ_GUARD(c)
     if (!c->has_grid) return fail(c, PPQ_E_STATE, "no grid");
     if (c->any_lattice) return fail(c, PPQ_E_UNSUPPORTED, "adjoint gradients are built for DVR dimensions");
-    if (c->krylov_tol > 0.0)
-        return fail(c, PPQ_E_UNSUPPORTED, "adjoint gradients differentiate the full-order step (Krylov tolerance 0)");
-    if (nsteps < 1 || m < 1 || m > MAXM || checkpoint_every < 1 || !(eps >= 0.0) || !std::isfinite(dt))
+    for (const Term &t : c->terms)
+        if (is_product(c, t))
+            return fail(c, PPQ_E_UNSUPPORTED, "adjoint gradients are built for diagonal potential terms");
+    if (nsteps < 1 || m < 2 || m > MAXM || checkpoint_every < 1 || !(eps >= 0.0) || !std::isfinite(dt))
         return fail(c, PPQ_E_ARG, "bad adjoint recording arguments");
     int r = ppq_init_gaussian(c, centre, momentum, width, eps, nullptr);
     if (r != PPQ_OK) return r;
-    PPQ_TRY(c, {
+    // the recorded steps follow exp(-i H dt) to the tolerance: adaptive order
+    // below m and step control (the settings are restored afterwards)
+    const double tau = c->krylov_tol > 0.0 ? c->krylov_tol : ADJ_KRYLOV_TOL;
+    const double tol_keep = c->krylov_tol;
+    const int sub_keep = c->max_substeps;
+    c->krylov_tol = tau;
+    c->max_substeps = sub_keep > 1 ? sub_keep : 1024;
+    int rc = PPQ_OK;
+    try {
         clear_record(c);
         record_append(c);
         checkpoint_now(c);
         for (int st = 1; st <= nsteps; ++st) {
-            do_step(c, dt, m);
+            const StepInfo info = do_step(c, dt, m);
+            c->rec_sub.push_back(info.nsub);
             do_prune(c, eps, nullptr);
             record_append(c);
             if (st % checkpoint_every == 0 && st < nsteps) checkpoint_now(c);
         }
+    } catch (const HipError &e) {
+        rc = hip_fail(c, e);
+    } catch (const std::bad_alloc &) {
+        rc = fail(c, PPQ_E_OOM, "device allocation failed");
+    } catch (const std::exception &e) {
+        rc = fail(c, PPQ_E_NUMERIC, e.what());
+    }
+    c->krylov_tol = tol_keep;
+    c->max_substeps = sub_keep;
+    if (rc != PPQ_OK) {
+        clear_record(c);
+        return rc;
+    }
+    PPQ_TRY(c, {
         c->rec_C = overlap_with_packet(c);
         for (int k = 0; k < c->g.D; ++k) {
             c->rec_centre[k] = centre[k];
@@ -2503,6 +3014,7 @@ int ppq_adjoint_record(ppq_ctx *c, const double *centre, const double *momentum,
         c->rec_steps = nsteps;
         c->rec_m = m;
         c->rec_dt = dt;
+        c->rec_tol = tau;
         c->rec_every = checkpoint_every;
         c->recorded = true;
         mark(c, PHASE_NONE);
@@ -2515,7 +3027,6 @@ int ppq_adjoint_frozen(ppq_ctx *c, const double *centre, const double *momentum,
 {
     PPQ_GUARD(c)
     if (!c->recorded) return fail(c, PPQ_E_STATE, "no recorded trajectory");
-    if (c->krylov_tol > 0.0) return fail(c, PPQ_E_UNSUPPORTED, "the recorded steps are full-order (Krylov tolerance 0)");
     if (!centre || !momentum || !J) return fail(c, PPQ_E_ARG, "null argument");
     PPQ_TRY(c, {
         int64_t nmax_set = *std::max_element(c->rec_n.begin(), c->rec_n.end());
@@ -2529,9 +3040,12 @@ int ppq_adjoint_frozen(ppq_ctx *c, const double *centre, const double *momentum,
         for (int st = 1; st <= c->rec_steps; ++st) {
             build_derived(c);
             ensure_krylov(c, c->rec_m);
-            if (c->nact) {
-                if (c->precision == PPQ_FP64) step_impl<double2>(c, c->rec_dt, c->rec_m);
-                else step_impl<float2>(c, c->rec_dt, c->rec_m);
+            // the recording's substeps, each at its tolerance
+            const int ns = c->rec_sub[st - 1];
+            const double h = c->rec_dt / (double)ns;
+            for (int j = 0; j < ns && c->nact; ++j) {
+                if (c->precision == PPQ_FP64) step_impl<double2>(c, h, c->rec_m, c->rec_tol);
+                else step_impl<float2>(c, h, c->rec_m, c->rec_tol);
             }
             frozen_remap(c, keys_of(st), c->rec_n[st]);
         }
@@ -2546,7 +3060,6 @@ int ppq_adjoint_gradient(ppq_ctx *c, double *dJ_dparam, double *dJ_dcentre, doub
 {
     PPQ_GUARD(c)
     if (!c->recorded) return fail(c, PPQ_E_STATE, "no recorded trajectory");
-    if (c->krylov_tol > 0.0) return fail(c, PPQ_E_UNSUPPORTED, "the recorded steps are full-order (Krylov tolerance 0)");
     PPQ_TRY(c, {
         const int D = c->g.D;
         int64_t nmax_set = *std::max_element(c->rec_n.begin(), c->rec_n.end());
@@ -2557,7 +3070,7 @@ int ppq_adjoint_gradient(ppq_ctx *c, double *dJ_dparam, double *dJ_dcentre, doub
         set_packet_tables(c, c->rec_centre, c->rec_momentum, w);
         build_operator(c);
         ensure_krylov(c, c->rec_m);
-        ensure_adjoint_buffers(c, c->rec_m, c->rec_every);
+        ensure_adjoint_buffers(c, c->rec_m, max_segment_states(c));
         if (c->precision == PPQ_FP64) adjoint_backward<double2>(c, c->rec_C);
         else adjoint_backward<float2>(c, c->rec_C);
         std::vector<double2> dC(ADJ_MAXP + 2 * MAXD);
@@ -2575,11 +3088,11 @@ int ppq_adjoint_gradient(ppq_ctx *c, double *dJ_dparam, double *dJ_dcentre, doub
     return PPQ_OK;
 }
 
-int ppq_time_apply(ppq_ctx *c, int nrep, double *ms_per_apply)
+int ppq_time_apply(ppq_ctx *c, int nrep, double *ms_median, double *ms_mean)
 {
     PPQ_GUARD(c)
     if (!c->has_state) return fail(c, PPQ_E_STATE, "no state");
-    if (nrep < 1 || !ms_per_apply) return fail(c, PPQ_E_ARG, "nrep >= 1");
+    if (nrep < 1 || nrep > 100000 || !ms_median) return fail(c, PPQ_E_ARG, "1 <= nrep <= 100000");
     PPQ_TRY(c, {
         build_derived(c);
         ensure_krylov(c, std::max(c->kv_m, 1));
@@ -2590,13 +3103,33 @@ int ppq_time_apply(ppq_ctx *c, int nrep, double *ms_per_apply)
             x = c->Vk;
         }
         apply_internal(c, x, c->wk, nullptr, 0);
-        ck(hipEventRecord(c->ev0, c->stream), "event");
-        for (int r = 0; r < nrep; ++r) apply_internal(c, x, c->wk, nullptr, 0);
-        ck(hipEventRecord(c->ev1, c->stream), "event");
-        ck(hipEventSynchronize(c->ev1), "event sync");
-        float ms = 0.f;
-        ck(hipEventElapsedTime(&ms, c->ev0, c->ev1), "elapsed");
-        *ms_per_apply = (double)ms / nrep;
+        // one event between consecutive applications: nrep intervals
+        std::vector<hipEvent_t> ev(nrep + 1, nullptr);
+        int made = 0;
+        try {
+            for (; made <= nrep; ++made) ck(hipEventCreate(&ev[made]), "event");
+            for (int r = 0; r < nrep; ++r) {
+                ck(hipEventRecord(ev[r], c->stream), "event");
+                apply_internal(c, x, c->wk, nullptr, 0);
+            }
+            ck(hipEventRecord(ev[nrep], c->stream), "event");
+            ck(hipEventSynchronize(ev[nrep]), "event sync");
+            std::vector<double> t(nrep);
+            for (int r = 0; r < nrep; ++r) {
+                float ms = 0.f;
+                ck(hipEventElapsedTime(&ms, ev[r], ev[r + 1]), "elapsed");
+                t[r] = ms;
+            }
+            float total = 0.f;
+            ck(hipEventElapsedTime(&total, ev[0], ev[nrep]), "elapsed");
+            std::sort(t.begin(), t.end());
+            *ms_median = nrep % 2 ? t[nrep / 2] : 0.5 * (t[nrep / 2 - 1] + t[nrep / 2]);
+            if (ms_mean) *ms_mean = (double)total / nrep;
+        } catch (...) {
+            for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+            throw;
+        }
+        for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
     })
     return PPQ_OK;
 }

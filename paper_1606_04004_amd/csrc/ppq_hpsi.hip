@@ -954,6 +954,281 @@ __global__ __launch_bounds__(NT) void k_hpsi_block(BlockArgs<R> a, const typenam
     }
 }
 
+// ---- long fibers (dimensions of more than 64 points) --------------------------
+// One wavefront per fiber (a one-wave workgroup).  The fiber's members (their
+// positions, digits and input values, up to 256) are staged in LDS; each lane
+// then computes the output of members lane, lane + 64, ...: the row of h at
+// the member's digit against the members' values, exactly L^2 products per
+// fiber.  h is the unpadded n x n factor (real, or complex interleaved).
+// MODE 0: y = h x; 1: y += h x; 2: y = h x + V x.  x is the weighted sum of
+// up to four inputs (one unweighted input for real factors).
+constexpr int LB = 64;
+
+template <class R, bool CPLX, int MODE>
+__global__ __launch_bounds__(LB) void k_hpsi_long(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
+                                                  const uint8_t *__restrict__ dig, int64_t nf, int n,
+                                                  const void *__restrict__ Hv, MfIn<R> in, const R *__restrict__ V,
+                                                  typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
+{
+    using C = typename Cx<R>::T;
+    if (skip_if && skip_j >= *skip_if) return;
+    const int64_t f = blockIdx.x;
+    if (f >= nf) return;
+    __shared__ C sx[NMAX_FIBER];
+    __shared__ uint32_t sp[NMAX_FIBER];
+    __shared__ int sd[NMAX_FIBER];
+    const uint32_t q0 = off[f];
+    const int L = (int)(off[f + 1] - q0);
+    const int lane = threadIdx.x;
+    for (int t = lane; t < L; t += LB) {
+        const uint32_t q = q0 + (uint32_t)t;
+        const uint32_t p = pi ? pi[q] : q;
+        C v;
+        if (CPLX) {
+            v = Cx<R>::make(0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i < in.nin) {
+                    const C u = in.x[i][p];
+                    const C c = in.c[i];
+                    v.x = fma(c.x, u.x, fma(-c.y, u.y, v.x));
+                    v.y = fma(c.x, u.y, fma(c.y, u.x, v.y));
+                }
+            }
+        } else {
+            v = in.x[0][p];
+        }
+        sx[t] = v;
+        sp[t] = p;
+        sd[t] = dig[q];
+    }
+    __syncthreads();
+    for (int t = lane; t < L; t += LB) {
+        const int l = sd[t];
+        R ar = 0, ai = 0;
+        if (CPLX) {
+            const C *Hr = reinterpret_cast<const C *>(Hv) + (size_t)l * n;
+            for (int u = 0; u < L; ++u) {
+                const C h = Hr[sd[u]];
+                const C v = sx[u];
+                ar = fma(h.x, v.x, fma(-h.y, v.y, ar));
+                ai = fma(h.x, v.y, fma(h.y, v.x, ai));
+            }
+        } else {
+            const R *Hr = reinterpret_cast<const R *>(Hv) + (size_t)l * n;
+            for (int u = 0; u < L; ++u) {
+                const R h = Hr[sd[u]];
+                const C v = sx[u];
+                ar = fma(h, v.x, ar);
+                ai = fma(h, v.y, ai);
+            }
+        }
+        const uint32_t p = sp[t];
+        if (MODE == 2) {
+            const R vv = V[p];
+            const C xv = sx[t];
+            y[p] = Cx<R>::make(fma(vv, xv.x, ar), fma(vv, xv.y, ai));
+        } else if (MODE == 1) {
+            const C o2 = y[p];
+            y[p] = Cx<R>::make(o2.x + ar, o2.y + ai);
+        } else {
+            y[p] = Cx<R>::make(ar, ai);
+        }
+    }
+}
+
+template <class R, bool CPLX>
+void launch_long(const LongPass &lp, const void *H, const MfIn<R> &in, const R *V, typename Cx<R>::T *y, int mode,
+                 const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (lp.nf <= 0) return;
+#define L(MD)                                                                                                     \
+    hipLaunchKernelGGL((k_hpsi_long<R, CPLX, MD>), dim3((unsigned)lp.nf), dim3(LB), 0, s, lp.pi, lp.off, lp.dig, \
+                       lp.nf, lp.n, H, in, V, y, skip_if, skip_j)
+    if (mode == 2) L(2);
+    else if (mode == 1) L(1);
+    else L(0);
+#undef L
+}
+
+// ---- block-fused form, one lane per fiber over the whole window -------------
+// Same chunks as k_hpsi_block (whole blocks of the pass, x and y staged in
+// LDS, y written once), but each lane loads its fiber's window of x from LDS
+// once and computes every output row of the window (rolled loop; rows no
+// lane of the wavefront holds are skipped), adding each to y in LDS.  A
+// wave task is a batch of 64 fibers, so a chunk should hold a few hundred
+// fibers per dimension for every wavefront of the workgroup to get work.
+template <class R, int W>
+__device__ __forceinline__ void body_blk2(uint32_t o, uint64_t m, uint64_t wm, int ws, const uint16_t *lq,
+                                          const R *__restrict__ T, int nb, const typename Cx<R>::T *xs,
+                                          typename Cx<R>::T *ys)
+{
+    using C = typename Cx<R>::T;
+    using CR = __attribute__((address_space(4))) const R;
+    C xw[W];
+    {
+        uint32_t q[W];
+        bool on[W];
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            const int j = ws + jj;
+            on[jj] = (m >> j) & 1ull;
+            q[jj] = on[jj] ? o + (uint32_t)__popcll(m & ((1ull << j) - 1ull)) : o;
+        }
+        if (lq) {
+#pragma unroll
+            for (int jj = 0; jj < W; ++jj) q[jj] = lq[q[jj]];
+        }
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            const C v = xs[q[jj]];
+            xw[jj] = on[jj] ? v : Cx<R>::make(0, 0);
+        }
+    }
+    CR *Tw = (CR *)(T + ws * nb + ws);
+#pragma unroll 1
+    for (int ll = 0; ll < W; ++ll) {
+        const int l = ws + ll;
+        if (!((wm >> l) & 1ull)) continue;  // wave-uniform
+        CR *Tr = Tw + ll * nb;
+        R ar = 0, ai = 0;
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            const R t = Tr[jj];
+            ar = fma(t, xw[jj].x, ar);
+            ai = fma(t, xw[jj].y, ai);
+        }
+        if ((m >> l) & 1ull) {
+            uint32_t q = o + (uint32_t)__popcll(m & ((1ull << l) - 1ull));
+            if (lq) q = lq[q];
+            const C v = ys[q];
+            ys[q] = Cx<R>::make(v.x + ar, v.y + ai);
+        }
+    }
+}
+
+template <class R, int NBMAX, int NT, int SU>
+__global__ __launch_bounds__(NT) void k_hpsi_blk2(BlockArgs<R> a, const typename Cx<R>::T *__restrict__ x,
+                                                  typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
+{
+    using C = typename Cx<R>::T;
+    if (skip_if && skip_j >= *skip_if) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t ci;
+    if (a.list) {
+        ci = a.list[blockIdx.x];
+    } else {
+        // consecutive chunks on one XCD (workgroups are dealt round-robin over 8)
+        const uint32_t per = (a.nch + 7) / 8, i = blockIdx.x >> 3;
+        ci = (blockIdx.x & 7) * per + i;
+        if (i >= per || ci >= a.nch) return;
+    }
+    const uint32_t c0 = a.chunk[ci], c1 = a.chunk[ci + 1], len = c1 - c0;
+    if (len == 0 || len > a.cap) return;
+    C *xs = reinterpret_cast<C *>(smem);
+    C *ys = xs + a.cap;
+    uint16_t *lpb = reinterpret_cast<uint16_t *>(ys + a.cap);
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int nd = a.ndim;
+    // stage the chunk: positions, x, y or V x, and the local frame rank of
+    // every fiber-order rank of the permuted dimensions; all loads first
+    uint32_t p[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const uint32_t i = u * NT + tid;
+        p[u] = i < len ? (a.P ? a.P[c0 + i] : c0 + i) : 0xffffffffu;
+    }
+    int slot[4];
+    int ns = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        slot[d] = -1;
+        if (d < nd && a.pi[d]) slot[d] = ns++;
+    }
+    {
+        C xv[SU], yv[SU];
+        R vv[SU];
+        uint16_t lr[3][SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            xv[u] = Cx<R>::make(0, 0);
+            yv[u] = Cx<R>::make(0, 0);
+            vv[u] = 0;
+            const uint32_t i = u * NT + tid;
+            if (p[u] != 0xffffffffu) {
+                xv[u] = x[p[u]];
+                if (a.accumulate) yv[u] = y[p[u]];
+                if (a.V) vv[u] = a.V[p[u]];
+            }
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int sl = slot[d];
+                if (sl >= 0 && sl < 3) lr[sl][u] = i < len ? (uint16_t)(a.pi[d][c0 + i] - c0) : (uint16_t)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const uint32_t i = u * NT + tid;
+            if (i < len) {
+                xs[i] = xv[u];
+                ys[i] = a.V ? Cx<R>::make(fma(vv[u], xv[u].x, yv[u].x), fma(vv[u], xv[u].y, yv[u].y)) : yv[u];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < ns) lpb[k * a.cap + i] = lr[k][u];
+            }
+        }
+    }
+    __syncthreads();
+    for (int d = 0; d < nd; ++d) {
+        const int sl = d == 0 ? slot[0] : d == 1 ? slot[1] : d == 2 ? slot[2] : slot[3];
+        const uint16_t *lq = sl >= 0 ? lpb + sl * a.cap : nullptr;
+        const uint32_t f0 = a.fch[d][ci], f1 = a.fch[d][ci + 1];
+        const uint32_t *off = a.off[d];
+        const uint64_t *mk = a.mask[d];
+        const R *T = a.T[d];
+        const int nb = a.nb[d];
+        const uint32_t nbatch = (f1 - f0 + 63) / 64;
+        for (uint32_t b = (uint32_t)wave; b < nbatch; b += NT / 64) {
+            const uint32_t f = f0 + b * 64 + (uint32_t)lane;
+            uint64_t m = 0;
+            uint32_t o = 0;
+            if (f < f1) {
+                m = mk[f];
+                o = off[f] - c0;
+            }
+            const uint64_t wm = wave_or64(m);
+            if (wm == 0) continue;
+            const int wlo = __ffsll((unsigned long long)wm) - 1;
+            const int whi = 63 - __clzll((long long)wm);
+            const int width = whi - wlo + 1;
+#define PPQ_B2(WW)                                                          \
+    {                                                                       \
+        const int ws = wlo < nb - (WW) ? wlo : nb - (WW);                   \
+        body_blk2<R, WW>(o, m, wm, ws, lq, T, nb, xs, ys);                  \
+        continue;                                                           \
+    }
+            if (width <= 8) PPQ_B2(8)
+            if constexpr (NBMAX >= 16) {
+                if (width <= 16) PPQ_B2(16)
+            }
+            if constexpr (NBMAX >= 24) {
+                if (width <= 24) PPQ_B2(24)
+            }
+            if constexpr (NBMAX >= 32) {
+                if (width <= 32) PPQ_B2(32)
+            }
+#undef PPQ_B2
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const uint32_t i = u * NT + tid;
+        if (i < len) y[p[u]] = ys[i];
+    }
+}
+
 }  // namespace
 
 void hpsi_real_f64(const FiberPass &fp, const double *T, const double2 *x, const double *V, double2 *y, bool first,
@@ -1176,6 +1451,135 @@ void launch_block(const BlockPass &bp, const R *const *T, const typename Cx<R>::
         a.list = bp.big;
         go(dim3(bp.nbig), bp.cap_big, true);
     }
+}
+
+// The one-lane-per-fiber block pass: 256-thread workgroups for chunks up to
+// cap_small points, 512-thread ones (one per chunk) for the longer chunks.
+template <class R>
+void launch_block2(const BlockPass &bp, const R *const *T, const typename Cx<R>::T *x, const R *V,
+                   typename Cx<R>::T *y, bool accumulate, const int *skip_if, int skip_j, hipStream_t s)
+{
+    using C = typename Cx<R>::T;
+    if (bp.nch == 0) return;
+    BlockArgs<R> a{};
+    a.ndim = bp.ndim;
+    int nbmax = 8;
+    for (int d = 0; d < bp.ndim; ++d) {
+        a.pi[d] = bp.pi[d];
+        a.off[d] = bp.off[d];
+        a.mask[d] = bp.mask[d];
+        a.fch[d] = bp.fch[d];
+        a.T[d] = T[d];
+        a.nb[d] = bp.nb[d];
+        nbmax = std::max(nbmax, bp.nb[d]);
+    }
+    a.chunk = bp.chunk;
+    a.nch = bp.nch;
+    a.P = bp.P;
+    a.accumulate = accumulate ? 1 : 0;
+    a.V = V;
+    int npi = 0;
+    for (int d = 0; d < bp.ndim; ++d) npi += bp.pi[d] ? 1 : 0;
+    const size_t bpp = 2 * sizeof(C) + sizeof(uint16_t) * (size_t)npi;
+    // points per thread of the two launches: NT * SU covers their capacity
+    // (the main launch's cap_small; the LDS limit for the long chunks)
+    constexpr int SU_S = sizeof(R) == 8 ? 8 : 16, SU_B = sizeof(R) == 8 ? 10 : 16;
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        const void *fns[] = {
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 8, 256, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 16, 256, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 24, 256, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 32, 256, SU_S>),
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 8, 512, SU_B>),
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 16, 512, SU_B>),
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 24, 512, SU_B>),
+            reinterpret_cast<const void *>(&k_hpsi_blk2<R, 32, 512, SU_B>),
+        };
+        for (const void *f : fns)
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES) != hipSuccess)
+                (void)hipGetLastError();
+    });
+    auto go = [&](dim3 grid, uint32_t cap, bool wide) {
+        a.cap = cap;
+        const size_t lds = (size_t)cap * bpp;
+#define PPQ_GO(NB, NT, SU) \
+    hipLaunchKernelGGL((k_hpsi_blk2<R, NB, NT, SU>), grid, dim3(NT), lds, s, a, x, y, skip_if, skip_j)
+        if (wide) {
+            if (nbmax <= 8) PPQ_GO(8, 512, SU_B);
+            else if (nbmax <= 16) PPQ_GO(16, 512, SU_B);
+            else if (nbmax <= 24) PPQ_GO(24, 512, SU_B);
+            else PPQ_GO(32, 512, SU_B);
+        } else {
+            if (nbmax <= 8) PPQ_GO(8, 256, SU_S);
+            else if (nbmax <= 16) PPQ_GO(16, 256, SU_S);
+            else if (nbmax <= 24) PPQ_GO(24, 256, SU_S);
+            else PPQ_GO(32, 256, SU_S);
+        }
+#undef PPQ_GO
+    };
+    a.list = nullptr;
+    go(dim3(8 * ((bp.nch + 7) / 8)), bp.cap_small, false);
+    if (bp.nbig > 0) {
+        a.list = bp.big;
+        go(dim3(bp.nbig), bp.cap_big, true);
+    }
+}
+
+void hpsi_block2_f64(const BlockPass &bp, const double *const *T, const double2 *x, const double *V, double2 *y,
+                     bool accumulate, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_block2<double>(bp, T, x, V, y, accumulate, skip_if, skip_j, s);
+}
+
+void hpsi_block2_f32(const BlockPass &bp, const float *const *T, const float2 *x, const float *V, float2 *y,
+                     bool accumulate, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_block2<float>(bp, T, x, V, y, accumulate, skip_if, skip_j, s);
+}
+
+void hpsi_long_real_f64(const LongPass &lp, const double *T, const double2 *x, const double *V, double2 *y,
+                        bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<double> in{};
+    in.nin = 1;
+    in.x[0] = x;
+    in.c[0] = make_double2(1.0, 0.0);
+    launch_long<double, false>(lp, T, in, V, y, first ? 2 : 1, skip_if, skip_j, s);
+}
+
+void hpsi_long_real_f32(const LongPass &lp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
+                        const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<float> in{};
+    in.nin = 1;
+    in.x[0] = x;
+    in.c[0] = make_float2(1.f, 0.f);
+    launch_long<float, false>(lp, T, in, V, y, first ? 2 : 1, skip_if, skip_j, s);
+}
+
+void hpsi_long_cplx_f64(const LongPass &lp, const double2 *H, const CInput &in, double2 *y, bool accumulate,
+                        const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<double> a{};
+    a.nin = in.nin;
+    for (int i = 0; i < 4; ++i) {
+        a.x[i] = in.x[i];
+        a.c[i] = in.c[i];
+    }
+    launch_long<double, true>(lp, H, a, nullptr, y, accumulate ? 1 : 0, skip_if, skip_j, s);
+}
+
+void hpsi_long_cplx_f32(const LongPass &lp, const float2 *H, const CInput32 &in, float2 *y, bool accumulate,
+                        const int *skip_if, int skip_j, hipStream_t s)
+{
+    MfIn<float> a{};
+    a.nin = in.nin;
+    for (int i = 0; i < 4; ++i) {
+        a.x[i] = in.x[i];
+        a.c[i] = in.c[i];
+    }
+    launch_long<float, true>(lp, H, a, nullptr, y, accumulate ? 1 : 0, skip_if, skip_j, s);
 }
 
 void hpsi_block_f64(const BlockPass &bp, const double *const *T, const double2 *x, const double *V, double2 *y,

@@ -12,9 +12,13 @@ namespace ppq {
 
 constexpr int MAXD = 8;
 constexpr int MAXM = 16;        // largest Krylov order
-constexpr int NMAX_FIBER = 64;  // largest 1D basis (fiber masks are 64-bit)
+constexpr int NMAX_FIBER = 256;  // largest 1D basis (digits are 8-bit in the fiber tables)
+constexpr int NMAX_MASK = 64;    // largest 1D basis with fiber masks (one 64-bit word) and
+                                 // the mask-driven kernels; longer dimensions keep a digit
+                                 // per fiber entry and take the long-fiber pass
 constexpr int RED_BLOCKS = 1024;  // blocks of the fixed-shape reductions
 constexpr int PSTRIDE_H = 36;  // partial sums per block (matches the kernels)
+constexpr int64_t ACF2_MAX_FULL = int64_t(1) << 28;  // full grid of C(2t) on lattice bases
 
 // Grid geometry passed by value to kernels.
 struct GridDesc {
@@ -146,6 +150,25 @@ struct FiberPass {
     int64_t nf;
     int nmax;               // padded 1D size (matrix leading dimension)
 };
+// a pass over a dimension longer than NMAX_MASK: fibers as (off) runs of the
+// dimension's order with the digit of every entry (no masks)
+struct LongPass {
+    const uint32_t *pi;     // nullptr for the last dimension (identity)
+    const uint32_t *off;    // [nf + 1]
+    const uint8_t *dig;     // digit of each entry in the dimension's order
+    int64_t nf;
+    int n;                  // size of the dimension (leading dimension of h)
+};
+void hpsi_long_real_f64(const LongPass &lp, const double *T, const double2 *x, const double *V, double2 *y,
+                        bool first, const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_long_real_f32(const LongPass &lp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
+                        const int *skip_if, int skip_j, hipStream_t s);
+struct CInput;
+struct CInput32;
+void hpsi_long_cplx_f64(const LongPass &lp, const double2 *H, const CInput &in, double2 *y, bool accumulate,
+                        const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_long_cplx_f32(const LongPass &lp, const float2 *H, const CInput32 &in, float2 *y, bool accumulate,
+                        const int *skip_if, int skip_j, hipStream_t s);
 // real factor (DVR), FP64; first==true writes y = (T + V) x, else y += T x
 void hpsi_real_f64(const FiberPass &fp, const double *T, const double2 *x, const double *V, double2 *y,
                    bool first, const int *skip_if, int skip_j, hipStream_t s);
@@ -176,7 +199,8 @@ void hpsi_mfma_f64(const FiberPass &fp, const double *T64, const double2 *x, con
 // chunks of whole blocks staged in LDS (see ppq_hpsi.hip)
 constexpr int BLOCK_MAXDIM = 4;
 constexpr int BLOCK_MAXNB = 32;
-constexpr uint32_t BLOCK_WINDOW = 512;  // chunk t starts at the first block start >= t * BLOCK_WINDOW
+constexpr uint32_t BLOCK_WINDOW = 512;  // chunk t starts at the first block start >= t * window;
+                                        // window >= BLOCK_WINDOW (chunk tables are sized for it)
 constexpr uint32_t LDS_BYTES = 160u * 1024u;
 // LDS per staged point: x and y (complex) and a 16-bit local rank per
 // dimension with a permutation
@@ -194,6 +218,9 @@ inline uint32_t block_cap_max(int precision, int npi)
     const uint32_t thr = precision == PPQ_FP64 ? 5u * 1024u : 8u * 1024u;
     return lds < thr ? lds : thr;
 }
+// the one-lane-per-fiber block pass: 256-thread workgroups with 8 (FP64) or
+// 16 (FP32) points per thread
+inline uint32_t block2_cap_small(int precision) { return precision == PPQ_FP64 ? 2048u : 4096u; }
 struct BlockPass {
     int ndim;
     int dim[BLOCK_MAXDIM];
@@ -214,6 +241,11 @@ void hpsi_block_f64(const BlockPass &bp, const double *const *T, const double2 *
                     bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
 void hpsi_block_f32(const BlockPass &bp, const float *const *T, const float2 *x, const float *V, float2 *y,
                     bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
+// the same passes with one lane per fiber over the whole window (see ppq_hpsi.hip)
+void hpsi_block2_f64(const BlockPass &bp, const double *const *T, const double2 *x, const double *V, double2 *y,
+                     bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_block2_f32(const BlockPass &bp, const float *const *T, const float2 *x, const float *V, float2 *y,
+                     bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
 // FP32 forms
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);
@@ -229,6 +261,18 @@ void hpsi_cmfma_f64(const FiberPass &fp, const double2 *H64, const CInput &in, d
                     const int *skip_if, int skip_j, hipStream_t s);
 void hpsi_cmfma_f32(const FiberPass &fp, const float2 *H64, const CInput32 &in, float2 *y, bool accumulate,
                     const int *skip_if, int skip_j, hipStream_t s);
+
+// full-grid tensors (C(2t) on lattice bases): full[keys[p]] = psi[p]; and
+// y = B applied along the digit of the given stride (size nk, B nk x nk)
+void scatter_full(const uint32_t *keys, const double2 *psi, int64_t n, double2 *full, hipStream_t s);
+void transform_full(const double2 *x, double2 *y, int64_t total, int64_t stride, int nk, const double2 *B,
+                    hipStream_t s);
+
+// y (= or +=) w D(I) x with D(I) = prod_{k in use} tab[k * nmax + i_k] (the
+// diagonal factors of a product term); C is double2 or float2
+template <class C>
+void diag_scale(const uint32_t *keys, const C *x, int64_t n, const GridDesc &g, const double *tab, int nmax,
+                unsigned use, double2 w, C *y, bool acc, const int *skip_if, int skip_j, hipStream_t s);
 
 // Krylov vector kernels. V_i = Vb + i*ld (elements); C is double2 or float2.
 // Reductions end in the last block to finish, which sums the per-block
@@ -261,7 +305,7 @@ void obs_partial(const uint32_t *keys, const double2 *psi, int64_t n, const Grid
                  int nmax, double eps2, double2 *partial, hipStream_t s);
 void obs_final(const double2 *partial, int nblocks, double *rec, hipStream_t s);
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s);
-void set_record(double *rec, double t, double nact, double krylov, hipStream_t s);
+void set_record(double *rec, double t, double nact, double krylov, double nsub, hipStream_t s);
 // *out = sum_I psi_I^2 (device), fixed-order; partials in `partial`
 void sum_of_squares(const double2 *psi, int64_t n, double2 *partial, double2 *out, hipStream_t s);
 // device state transfer: caller keys/coefficients into the context's buffers,
@@ -286,6 +330,8 @@ struct DerivDesc {
     int ntab;
 };
 constexpr int ADJ_MAXP = 32;
+// Krylov tolerance of the adjoint's recorded steps unless the context sets one
+constexpr double ADJ_KRYLOV_TOL = 1e-12;
 void gather_remap(const uint32_t *keys, int64_t n, const uint64_t *bm, const uint32_t *prefix, const double2 *lam,
                   double2 *mu, hipStream_t s);
 void mark_keys_wave(const uint32_t *keys, int64_t n, uint64_t *bm, hipStream_t s);

@@ -1,6 +1,8 @@
 // gfx950 kernels: scans, adaption (flag / dilate / compact / remap), fiber
 // tables, potential cache, Krylov vector work, small exponential, observables.
 // The fiber contraction kernels live in ppq_hpsi.hip.
+#include <algorithm>
+
 #include "ppq_internal.hpp"
 
 namespace ppq {
@@ -429,12 +431,15 @@ __global__ void k_last_flags(const uint32_t *keys, int64_t n, int nl, uint32_t *
     flags[p] = (p == 0 || keys[p] / (uint32_t)nl != keys[p - 1] / (uint32_t)nl) ? 1u : 0u;
 }
 
+// info[p] = the digit, with the fiber-start flag in bit 7 (dimensions of at
+// most 64 points); a longer dimension (up to 256 points) keeps the digit alone
 __global__ void k_last_info(const uint32_t *keys, int64_t n, int nl, uint8_t *info)
 {
     int64_t p = gid();
     if (p >= n) return;
     bool start = (p == 0 || keys[p] / (uint32_t)nl != keys[p - 1] / (uint32_t)nl);
-    info[p] = (uint8_t)((keys[p] % (uint32_t)nl) | (start ? 0x80u : 0u));
+    const uint32_t flag = (start && nl <= NMAX_MASK) ? 0x80u : 0u;
+    info[p] = (uint8_t)((keys[p] % (uint32_t)nl) | flag);
 }
 
 __global__ void k_last_fill(const uint32_t *keys, int64_t n, int nl, const uint32_t *flags, const uint32_t *fidx,
@@ -446,8 +451,9 @@ __global__ void k_last_fill(const uint32_t *keys, int64_t n, int nl, const uint3
     uint32_t f = fidx[p];
     uint32_t fk = keys[p] / (uint32_t)nl;
     uint64_t m = 0;
-    // the fiber's keys are consecutive: read them 8 at a time (independent loads)
-    bool more = true;
+    // the fiber's keys are consecutive: read them 8 at a time (independent
+    // loads); a dimension longer than a mask word keeps no mask
+    bool more = nl <= NMAX_MASK;
     for (int64_t q0 = p; more && q0 < n; q0 += 8) {
         uint32_t kv[8];
 #pragma unroll
@@ -459,7 +465,7 @@ __global__ void k_last_fill(const uint32_t *keys, int64_t n, int nl, const uint3
         }
     }
     off[f] = (uint32_t)p;
-    mask[f] = m;
+    if (nl <= NMAX_MASK) mask[f] = m;
 }
 
 __device__ inline uint32_t rotate_key(uint32_t key, uint32_t sk, uint32_t nk, uint32_t *dig)
@@ -513,6 +519,20 @@ __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_
     uint32_t q = prefix[rk >> 6] + (uint32_t)__popcll(word & ((1ull << (rk & 63)) - 1ull));
     pi[q] = map ? map[p] : (uint32_t)p;
     if (inv) inv[p] = q;
+    if (nk > (uint32_t)NMAX_MASK) {
+        // a dimension longer than a mask word: the entry starts a fiber when no
+        // bit of its fiber lies below it; info keeps the digit alone
+        bool start = true;
+        for (uint32_t b = rk - d; b < rk && start; b = (b | 63u) + 1u) {
+            const uint32_t e = (b | 63u) + 1u < rk ? (b | 63u) + 1u : rk;
+            const uint64_t w = bm[b >> 6] >> (b & 63u);
+            const uint32_t len = e - b;
+            start = (len >= 64 ? w : (w & ((1ull << len) - 1ull))) == 0;
+        }
+        flags[q] = start ? 1u : 0u;
+        if (info) info[q] = (uint8_t)d;
+        return;
+    }
     uint64_t m = extract_bits(bm, rk - d, (int)nk);
     bool start = (m & ((1ull << d) - 1ull)) == 0;
     flags[q] = start ? 1u : 0u;
@@ -710,14 +730,14 @@ __global__ void k_fib_fill(const uint32_t *flags, const uint32_t *fidx, const ui
     if (q >= n || !flags[q]) return;
     uint32_t f = fidx[q];
     off[f] = (uint32_t)q;
-    mask[f] = tmpmask[q];
+    if (mask) mask[f] = tmpmask[q];
 }
 
 // ---- potential cache -----------------------------------------------------------
 // Potential cache: V_I = sum_t coef_t prod_f tab_{t,f}[digit_{dim_{t,f}}(I)].
 // Term descriptors and the (deduplicated) 1D tables are staged in LDS.
 constexpr int POT_MAX_TERMS = 256;
-constexpr int POT_MAX_TAB = 1024;
+constexpr int POT_MAX_TAB = 2048;
 constexpr int POT_MAX_FAC = 4;
 
 __device__ inline int select_digit(const int (&d)[MAXD], int k)
@@ -1374,11 +1394,12 @@ __global__ void k_give_keys(const uint32_t *k32, int64_t n, uint64_t *keys)
 }
 
 // host-known fields of one observable record
-__global__ void k_set_record(double *rec, double t, double nact, double krylov)
+__global__ void k_set_record(double *rec, double t, double nact, double krylov, double nsub)
 {
     rec[PPQ_OBS_T] = t;
     rec[PPQ_OBS_NACTIVE] = nact;
     rec[PPQ_OBS_KRYLOV] = krylov;
+    rec[PPQ_OBS_SUBSTEPS] = nsub;
 }
 
 __global__ void k_copy_alpha0(const KState *ks, double *dst) { *dst = ks->alpha[0]; }
@@ -2010,9 +2031,9 @@ void sum_of_squares(const double2 *psi, int64_t n, double2 *partial, double2 *ou
     hipLaunchKernelGGL(k_sq_partial, dim3(RED_BLOCKS), dim3(TB), 0, s, psi, n, partial);
     hipLaunchKernelGGL(k_sum_partial1, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, out);
 }
-void set_record(double *rec, double t, double nact, double krylov, hipStream_t s)
+void set_record(double *rec, double t, double nact, double krylov, double nsub, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_record, dim3(1), dim3(1), 0, s, rec, t, nact, krylov);
+    hipLaunchKernelGGL(k_set_record, dim3(1), dim3(1), 0, s, rec, t, nact, krylov, nsub);
 }
 void copy_alpha0(const KState *ks, double *dst, hipStream_t s)
 {
@@ -2066,6 +2087,89 @@ void adj_packet(const uint32_t *keys, int64_t n, const GridDesc &g, const double
     hipLaunchKernelGGL(k_adj_packet, dim3(RED_BLOCKS), dim3(TB), 0, s, keys, n, g, tabs, dtabs, nmax, vec, bra,
                        partial);
 }
+
+// ---- full-grid transform (C(2t) on lattice bases) ---------------------------
+// y[I] = sum_j B[l][j] x[I with digit k -> j], l = i_k: the dense transform of
+// a full-grid tensor along dimension k (stride of digit k, nk its size).
+__global__ void k_modek(const double2 *__restrict__ x, double2 *__restrict__ y, int64_t total, int64_t stride, int nk,
+                        const double2 *__restrict__ B)
+{
+    for (int64_t I = gid(); I < total; I += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)((I / stride) % nk);
+        const int64_t base = I - (int64_t)l * stride;
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < nk; ++j) {
+            const double2 b = B[l * nk + j], v = x[base + (int64_t)j * stride];
+            re += b.x * v.x - b.y * v.y;
+            im += b.x * v.y + b.y * v.x;
+        }
+        y[I] = make_double2(re, im);
+    }
+}
+
+__global__ void k_scatter_full(const uint32_t *keys, const double2 *psi, int64_t n, double2 *full)
+{
+    const int64_t p = gid();
+    if (p < n) full[keys[p]] = psi[p];
+}
+
+void scatter_full(const uint32_t *keys, const double2 *psi, int64_t n, double2 *full, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scatter_full, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, psi, n, full);
+}
+
+void transform_full(const double2 *x, double2 *y, int64_t total, int64_t stride, int nk, const double2 *B,
+                    hipStream_t s)
+{
+    const int64_t nb = std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_modek, dim3((unsigned)nb), dim3(256), 0, s, x, y, total, stride, nk, B);
+}
+
+// ---- diagonal factors of a product term -------------------------------------
+// y (= or +=) w D(I) x_I with D(I) = prod over the dimensions in `use` of
+// tab[k][i_k]: the diagonal (DVR) factors of a sum-of-products term.  They
+// commute with the truncation to the active set, so they act on the input of
+// the term's chain of dense factors.  D is formed in FP64 in increasing k.
+template <class C>
+__global__ void k_diag_scale(const uint32_t *keys, const C *x, int64_t n, GridDesc g, const double *tab, int nmax,
+                             unsigned use, double2 w, C *y, int acc, const int *skip_if, int skip_j)
+{
+    if (skip_if && skip_j >= *skip_if) return;
+    const int64_t p = gid();
+    if (p >= n) return;
+    const uint32_t key = keys[p];
+    double d = 1.0;
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k)
+        if (k < g.D && ((use >> k) & 1u)) d *= tab[k * nmax + (int)((key / g.stride[k]) % (uint32_t)g.n[k])];
+    const double wr = w.x * d, wi = w.y * d;
+    const C v = x[p];
+    const double vr = v.x, vi = v.y;
+    double r = wr * vr - wi * vi, i = wr * vi + wi * vr;
+    if (acc) {
+        r += y[p].x;
+        i += y[p].y;
+    }
+    C o;
+    o.x = r;
+    o.y = i;
+    y[p] = o;
+}
+
+template <class C>
+void diag_scale(const uint32_t *keys, const C *x, int64_t n, const GridDesc &g, const double *tab, int nmax,
+                unsigned use, double2 w, C *y, bool acc, const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (n <= 0) return;
+    const int nb = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_diag_scale<C>, dim3(nb), dim3(256), 0, s, keys, x, n, g, tab, nmax, use, w, y, acc ? 1 : 0,
+                       skip_if, skip_j);
+}
+template void diag_scale<double2>(const uint32_t *, const double2 *, int64_t, const GridDesc &, const double *, int,
+                                  unsigned, double2, double2 *, bool, const int *, int, hipStream_t);
+template void diag_scale<float2>(const uint32_t *, const float2 *, int64_t, const GridDesc &, const double *, int,
+                                 unsigned, double2, float2 *, bool, const int *, int, hipStream_t);
 
 void copy_meff(const KState *ks, double *dst, hipStream_t s)
 {

@@ -550,6 +550,35 @@ def test_acf_doubled_closed_form():
         assert abs(o.acf_doubled() - ref) < 1e-9
 
 
+@pytest.mark.parametrize("basis", ["pvb", "pw"])
+def test_acf_doubled_on_lattices(basis):
+    """C(2t) on a phase-space lattice basis is a^T B^T B a with B the map
+    from the lattice coefficients to the DVR ones (the form after Eq. acorr):
+    for a real packet, unpruned, it equals the C(t) record at twice the time
+    (the dual-bra overlap) and the DVR run's sum of squares at t."""
+    base = card("small_4d", n=[12, 12, 12, 12])
+    base["terms"] = base["terms"][:2] + base["terms"][4:6]
+    base["psi0"] = dict(base["psi0"], momentum=[0.0] * 4)
+    lat = dict(base, basis=basis, lattice=[3, 4])
+    ol = orc.Oracle(lat)
+    od = orc.Oracle(base)
+    for o in (ol, od):
+        k, c0 = _full_state(o)
+        o.set_state(k, c0)
+    tr, _ = ol.propagate(nsteps=12, dt=0.05, m=14, prune=False)
+    for o in (ol, od):
+        k, c0 = _full_state(o)
+        o.set_state(k, c0)
+        o.propagate(nsteps=6, dt=0.05, m=14, prune=False)
+    c2 = ol.acf_doubled()
+    assert abs(c2 - complex(tr[12, 3], tr[12, 4])) < 1e-9
+    assert abs(c2 - od.acf_doubled()) < 1e-9
+    # the plain sum of squares of the lattice coefficients is not it (B^T B != I for pvb)
+    if basis == "pvb":
+        _, a = ol.state()
+        assert abs(complex(np.sum(a * a)) - c2) > 1e-3
+
+
 def test_expect_q_special_cases():
     """One grid point: <q_k> is that point's coordinate for any weight; a state
     mirror-symmetric in dimension k on a symmetric box: <q_k> = 0; lattice
@@ -646,6 +675,48 @@ def test_adaptive_order_backward_step():
             oo.set_state(keys, c0)
             used.append(oo.sil_step(dt=sgn * dt, m=16)[0])
         assert used[0] == used[1] and 1 < used[0] < 16
+
+
+def test_step_control_substeps():
+    """Step size control (the integrator's accuracy tied to the tolerance,
+    Sec. III.A): a step too long for the Krylov order at the tolerance runs
+    as substeps, each meeting the tolerance below the order, and the step is
+    then within a few times the tolerance of exp(-i H dt) (dense expm);
+    without control the same order misses it by far.  The count follows the
+    rule: doubled until every substep stops early, halved after a step whose
+    substeps all stopped at order m/2 or below."""
+    cd0 = card("small_2d")
+    o = orc.Oracle(cd0)
+    keys, c0 = _full_state(o)
+    H = dense_h(o.model)
+    dt, m, tol = 0.4, 10, 1e-10
+    U = sla.expm(-1j * dt * H)
+    plain = orc.Oracle(card("small_2d"))
+    plain.set_state(keys, c0)
+    plain.sil_step(dt=dt, m=m)
+    err_plain = np.linalg.norm(plain.state()[1] - U @ c0)
+    ctl = orc.Oracle(card("small_2d", krylov_tol=tol, max_substeps=64))
+    ctl.set_state(keys, c0)
+    tr, _ = ctl.propagate(nsteps=1, dt=dt, m=m, prune=False)
+    err_ctl = np.linalg.norm(ctl.state()[1] - U @ c0)
+    nsub = int(tr[1, 8])
+    assert nsub > 1 and nsub & (nsub - 1) == 0          # a power of two
+    assert tr[1, 7] < m
+    assert err_ctl < 10 * nsub * tol < err_plain
+    # a long run keeps every step within its substeps' tolerance
+    ctl.set_state(keys, c0)
+    tr, _ = ctl.propagate(nsteps=6, dt=dt, m=m, prune=False)
+    U6 = np.linalg.matrix_power(U, 6)
+    assert np.linalg.norm(ctl.state()[1] - U6 @ c0) < 60 * int(tr[1:, 8].max()) * tol
+    assert np.all(tr[1:, 7] < m)
+    # a short step needs one substep; too few allowed substeps is an error
+    ctl.set_state(keys, c0)
+    tr, _ = ctl.propagate(nsteps=1, dt=0.01, m=m, prune=False)
+    assert tr[1, 8] == 1
+    tight = orc.Oracle(card("small_2d", krylov_tol=1e-14, max_substeps=2))
+    tight.set_state(keys, c0)
+    with pytest.raises(RuntimeError):
+        tight.propagate(nsteps=1, dt=2.0, m=6, prune=False)
 
 
 def test_reversibility():

@@ -20,8 +20,11 @@ A card is a plain dict:
                                   sine-DVR kinetic matrix of dimension k
   psi0                            product Gaussian: centre, momentum, width per dim
   eps, dt, nsteps, krylov         threshold, time step, steps, Krylov order
-  basis                           "dvr" or "pvb" (phase-space lattice per dim, see
-                                  "lattice": [n_s, n_l] with n_s*n_l == n)
+  basis                           "dvr", "pvb" or "pw" (phase-space lattice per dim, see
+                                  "lattice": [n_s, n_l] with n_s*n_l == n, or one such
+                                  pair per dimension)
+  krylov_tol, max_substeps        (optional) integrator accuracy: adaptive order and
+                                  step control
   params (adjoint card only)      names of the trainable coefficients
 
 Random model coefficients are drawn here once with numpy's PCG64 generator
@@ -32,7 +35,7 @@ import copy
 
 import numpy as np
 
-CARD_NAMES = ("hh2d", "morse4d", "quartic6d", "pvb4d", "adjoint4d")
+CARD_NAMES = ("hh2d", "morse4d", "quartic6d", "pvb4d", "adjoint4d", "dwell2d")
 
 _SEED_MORSE = 1606
 _SEED_QUARTIC = 4004
@@ -145,7 +148,7 @@ def _adjoint4d():
         "name": "adjoint4d", "D": 4, "n": [32] * 4, "lo": [-3.0] * 4, "hi": [9.0] * 4,
         "mass": 1.0, "terms": terms, "basis": "dvr", "params": params, "trainable": trainable,
         "psi0": {"centre": [0.5, 0.0, 0.0, 0.0], "momentum": [0.0] * 4, "width": [0.5] * 4},
-        "eps": 1e-6, "dt": 0.05, "nsteps": 2000, "krylov": 10, "checkpoint_every": 50,
+        "eps": 1e-6, "dt": 0.05, "nsteps": 2000, "krylov": 16, "checkpoint_every": 50,
     }
 
 
@@ -182,9 +185,35 @@ def _sop3d():
     return c
 
 
+def _dwell2d():
+    """The paper's two-dimensional double well (Sec. III.A, Eqs. ex_dwell and
+    ex_dwell_psiInitial): mass 200, V = 6.4 (x-1)^2 (x-2)^2 + 37.5 (y-2)^2 +
+    10 x^2 y written out in powers of x and y (sum-of-products terms, plus its
+    constant 175.6), the real Gaussian exp(-(x-2.1)^2/0.04 - (y-2.05)^2/0.02)
+    (widths sqrt(0.02) and 0.1 in exp(-(q-c)^2/(2 w^2))), Fourier grids of
+    165 x 81 points on x in [-0.5, 3.7], y in [1.0, 2.9] (the phase-space
+    lattices take 15 x 11 and 9 x 9 on them), propagated to t_e = 24.6."""
+    terms = [
+        {"coef": 6.4, "factors": [_power(0, 4)]},
+        {"coef": -38.4, "factors": [_power(0, 3)]},
+        {"coef": 83.2, "factors": [_power(0, 2)]},
+        {"coef": -76.8, "factors": [_power(0, 1)]},
+        {"coef": 37.5, "factors": [_power(1, 2)]},
+        {"coef": -150.0, "factors": [_power(1, 1)]},
+        {"coef": 10.0, "factors": [_power(0, 2), _power(1, 1)]},
+        {"coef": 175.6, "factors": []},
+    ]
+    return {
+        "name": "dwell2d", "D": 2, "n": [165, 81], "lo": [-0.5, 1.0], "hi": [3.7, 2.9], "fgh": [0, 1],
+        "mass": 200.0, "terms": terms, "basis": "dvr", "lattice": [[15, 11], [9, 9]],
+        "psi0": {"centre": [2.1, 2.05], "momentum": [0.0, 0.0], "width": [0.02 ** 0.5, 0.1]},
+        "eps": 1e-5, "dt": 0.1, "nsteps": 246, "krylov": 16, "krylov_tol": 1e-10, "max_substeps": 64,
+    }
+
+
 _BUILDERS = {
     "hh2d": _hh2d, "morse4d": _morse4d, "quartic6d": _quartic6d,
-    "pvb4d": _pvb4d, "adjoint4d": _adjoint4d,
+    "pvb4d": _pvb4d, "adjoint4d": _adjoint4d, "dwell2d": _dwell2d,
 }
 
 
