@@ -215,6 +215,7 @@ def secondary(stream, steps, warmup, adjoint_steps):
     out["adjoint4d_fp32"]["J_rel_err_vs_fp64"] = abs(out["adjoint4d_fp32"]["J"] - out["adjoint4d_fp64"]["J"]) / \
         abs(out["adjoint4d_fp64"]["J"])
     out["hh2d_accuracy"] = accuracy_sweep(stream)
+    out["dwell2d_accuracy"] = dwell_sweep(stream)
     return out
 
 
@@ -268,6 +269,50 @@ def accuracy_sweep(stream):
                          "ms_per_step": wall * 1e3 / (tr.shape[0] - 1)})
             del g
     return {"exact_ms_per_step": ms_exact, "runs": rows}
+
+
+def dwell_sweep(stream):
+    """The paper's 2D double well (Sec. III.A, Figs. 3 and 4): for the pruned
+    Fourier-grid DVR, the projected von Neumann lattice (15 x 11 and 9 x 9)
+    and projected Weylets, per threshold the infidelity of C(t) over the run
+    to t_e = 24.6 against the unpruned 165 x 81 Fourier-grid run, the mean
+    share of the 13365-function basis used and the time per step.  Every run
+    keeps the integrator within 1e-10 per step (adaptive order up to 15,
+    substeps as needed), so the infidelity is the pruning error."""
+    import torch
+    import paper_1606_04004_amd as ppq
+    from workloads import card
+    base = card("dwell2d")
+    total = int(np.prod(base["n"]))
+    g = ppq.Propagator(base, precision=ppq.PPQ_FP64, device=0, stream=stream)
+    g.init_state(eps=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = g.propagate(prune=False)
+    torch.cuda.synchronize()
+    ms_exact = (time.perf_counter() - t0) * 1e3 / (ref.shape[0] - 1)
+    c_ref = ref[:, 3] + 1j * ref[:, 4]
+    del g
+    rows = []
+    for basis in ("dvr", "pw", "pvb"):
+        for eps in (1e-2, 1e-3, 1e-4, 1e-5):
+            cd = card("dwell2d", basis=basis)
+            g = ppq.Propagator(cd, precision=ppq.PPQ_FP64, device=0, stream=stream)
+            g.init_state(eps=eps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tr = g.propagate(eps=eps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            c = tr[:, 3] + 1j * tr[:, 4]
+            rows.append({"basis": basis, "eps": eps,
+                         "mean_basis_percent": float(100.0 * np.mean(tr[:, 5]) / total),
+                         "infidelity": float(np.sqrt(np.sum(np.abs(c - c_ref) ** 2))),
+                         "mean_substeps": float(np.mean(tr[1:, 8])),
+                         "ms_per_step": wall * 1e3 / (tr.shape[0] - 1)})
+            print(f"[bench] double well {basis} eps {eps}: {rows[-1]}", file=sys.stderr, flush=True)
+            del g
+    return {"exact_ms_per_step": ms_exact, "t_end": base["dt"] * base["nsteps"], "runs": rows}
 
 
 def traffic_probe(stream):
