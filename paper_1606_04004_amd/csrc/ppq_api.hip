@@ -168,8 +168,9 @@ struct ppq_ctx {
     uint64_t *mask[MAXD]{};
     uint8_t *info[MAXD]{};
     int64_t nf[MAXD]{};
-    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides; 4, 5 = block-fused)
+    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides; 4, 5 = block-fused, 6 = plane passes)
     uint32_t blk_window = BLOCK_WINDOW;  // chunk window of the block layouts (PPQ_BLOCK_WINDOW)
+    int blk_unroll = 1;                  // one-lane-per-fiber block pass: row loop unrolled (PPQ_BLOCK_UNROLL)
 
     // block-fused H*psi: outer dimensions [0, split) through the inner-first
     // frame, inner dimensions [split, D) in the row-major frame
@@ -180,6 +181,17 @@ struct ppq_ctx {
     uint32_t *chunk[2]{}, *big[2]{};
     uint32_t *fch[MAXD]{};  // first fiber of each chunk, per dimension
     uint32_t nch[2]{}, nbig[2]{}, maxch[2]{};
+
+    // plane passes: pairs of adjacent dimensions (D-2, D-1), (D-4, D-3), ...;
+    // an odd first dimension keeps its own pass
+    bool plane_ok = false;    // the operator and grid admit them
+    bool plane_mode = false;  // the current set's plane tables are built
+    int npl = 0;
+    int pl_a[MAXD]{};         // first dimension of each pair
+    uint32_t *plP[MAXD]{}, *pltask[MAXD]{};
+    uint16_t *pldig[MAXD]{};
+    uint32_t *pl_poff = nullptr;  // plane starts while the tables are built
+    int64_t pl_cap = 0;
 
     // work
     uint32_t *flags = nullptr, *fidx = nullptr;
@@ -324,6 +336,14 @@ void free_state_buffers(ppq_ctx *c)
     dfree(c->cntB);
     dfree(c->tmaskB);
     c->bat_cap = 0;
+    for (int i = 0; i < MAXD; ++i) {
+        dfree(c->plP[i]);
+        dfree(c->pltask[i]);
+        dfree(c->pldig[i]);
+    }
+    dfree(c->pl_poff);
+    c->pl_cap = 0;
+    c->plane_mode = false;
     c->cap = 0;
 }
 
@@ -1027,10 +1047,53 @@ bool ensure_batched(ppq_ctx *c)
     return true;
 }
 
+// Plane tables of every pair (allocated on first use at the current capacity).
+void ensure_planes(ppq_ctx *c)
+{
+    if (c->pl_cap == c->cap) return;
+    const int64_t nc = c->cap;
+    for (int i = 0; i < c->npl; ++i) {
+        dfree(c->plP[i]);
+        dfree(c->pltask[i]);
+        dfree(c->pldig[i]);
+        if (c->pl_a[i] + 2 < c->g.D) c->plP[i] = dalloc<uint32_t>(nc);
+        c->pldig[i] = dalloc<uint16_t>(nc);
+        c->pltask[i] = dalloc<uint32_t>(nc / PLANE_WINDOW + 2);
+    }
+    dfree(c->pl_poff);
+    c->pl_poff = dalloc<uint32_t>(nc + 1);
+    c->pl_cap = nc;
+}
+
+PlanePass plane_pass_of(const ppq_ctx *c, int i)
+{
+    PlanePass pp;
+    const int a = c->pl_a[i];
+    pp.P = c->plP[i];
+    pp.dig = c->pldig[i];
+    pp.tstart = c->pltask[i];
+    pp.ntask = (uint32_t)((c->nact + PLANE_WINDOW - 1) / PLANE_WINDOW);
+    pp.na = c->nb[a];
+    pp.nb = c->nb[a + 1];
+    return pp;
+}
+
 void build_derived(ppq_ctx *c)
 {
     if (c->derived_valid) return;
     build_operator(c);
+    c->plane_mode = false;
+    {
+        const int D = c->g.D;
+        bool ok = c->hpsi_variant == 6 && !c->any_lattice && !any_long(c) && D >= 2 && c->pairs.empty() &&
+                  c->chains.empty();
+        for (int k = 0; k < D; ++k) ok = ok && c->nb[k] <= PLANE_NMAX;
+        // a task holds whole planes: a plane must fit a task's span
+        for (int a = D - 2; ok && a >= 0; a -= 2) ok = c->g.n[a] * c->g.n[a + 1] < PLANE_SPAN;
+        c->plane_ok = ok;
+        c->npl = ok ? D / 2 : 0;
+        for (int i = 0; i < c->npl; ++i) c->pl_a[i] = D - 2 - 2 * i;
+    }
     const int D = c->g.D;
     const int64_t n = c->nact;
     hipStream_t s = c->stream;
@@ -1072,6 +1135,14 @@ void build_derived(ppq_ctx *c)
         }
     }
     if (try_block) build_inner_first(c);
+    if (c->plane_ok && n > 0) {
+        ensure_planes(c);
+        for (int i = 0; i < c->npl; ++i)
+            plane_tables(keys, n, c->g, c->pl_a[i], c->bm, c->prefix, c->nwords, c->plP[i], c->pldig[i],
+                         c->pltask[i], c->pl_poff, reinterpret_cast<uint32_t *>(c->tmpmask), c->flags, c->fidx,
+                         c->scan_tmp, c->small + 3 * MAXD, s);
+        c->plane_mode = true;
+    }
     if (!c->any_lattice) {
         PotDesc pd{c->pot_nterm, D, c->pot_nmax, c->pot_coef, c->pot_tab, c->pot_tabs, c->pot_ntab};
         // flags is free once the fiber tables are built
@@ -1133,6 +1204,7 @@ BlockPass block_pass(const ppq_ctx *c, int which)
     bp.big = c->big[which];
     bp.nbig = c->nbig[which];
     bp.cap_small = c->hpsi_variant == 5 ? block2_cap_small(c->precision) : block_cap_small(c->precision);
+    bp.unroll = c->blk_unroll;
     bp.cap_big = bp.nbig ? (c->maxch[which] + 63u) / 64u * 64u : 0u;
     return bp;
 }
@@ -1192,6 +1264,26 @@ void apply_single(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int 
         return;
     }
     if (!c->any_lattice) {
+        if (c->plane_mode) {
+            // pairs of dimensions; the last pair's pass writes y with V fused
+            for (int i = 0; i < c->npl; ++i) {
+                const PlanePass pp = plane_pass_of(c, i);
+                const int a = c->pl_a[i];
+                if (c->precision == PPQ_FP64)
+                    hpsi_plane_f64(pp, c->T64[a], c->T64[a + 1], (const double2 *)xv, i == 0 ? c->V64 : nullptr,
+                                   (double2 *)yv, i == 0, skip_if, skip_j, s);
+                else
+                    hpsi_plane_f32(pp, c->T32[a], c->T32[a + 1], (const float2 *)xv, i == 0 ? c->V32 : nullptr,
+                                   (float2 *)yv, i == 0, skip_if, skip_j, s);
+            }
+            if (D % 2 == 1) {
+                if (c->precision == PPQ_FP64)
+                    hpsi_acc_f64(pass_of(c, 0), c->T64[0], (const double2 *)xv, (double2 *)yv, skip_if, skip_j, s);
+                else
+                    hpsi_acc_f32(pass_of(c, 0), c->T32[0], (const float2 *)xv, (float2 *)yv, skip_if, skip_j, s);
+            }
+            return;
+        }
         if (c->block_mode) {
             // inner-first pass over the outer dimensions writes y, the row-major
             // pass over the inner dimensions adds to it with the potential fused
@@ -2093,8 +2185,9 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
     c->precision = precision;
     if (const char *v = std::getenv("PPQ_HPSI")) {
         const int h = std::atoi(v);
-        if (h >= 0 && h <= 5) c->hpsi_variant = h;  // other values keep the default layout
+        if (h >= 0 && h <= 6) c->hpsi_variant = h;  // other values keep the default layout
     }
+    if (const char *v = std::getenv("PPQ_BLOCK_UNROLL")) c->blk_unroll = std::atoi(v) != 0;
     if (const char *v = std::getenv("PPQ_BLOCK_WINDOW")) {
         const long w = std::atol(v);
         if (w >= (long)BLOCK_WINDOW && w <= (1l << 20)) c->blk_window = (uint32_t)w;

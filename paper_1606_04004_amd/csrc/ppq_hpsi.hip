@@ -709,6 +709,7 @@ struct BlockArgs {
     uint32_t cap;
     int accumulate;
     const R *V;
+    int unroll;  // k_hpsi_blk2: unrolled row loop (1) or rolled with wave-uniform skips (0)
 };
 
 // One fiber, one group of 8 output rows: rows ws + 8g .. ws + 8g + 7 of the
@@ -1107,6 +1108,52 @@ __device__ __forceinline__ void body_blk2(uint32_t o, uint64_t m, uint64_t wm, i
     }
 }
 
+// The same contraction with the row loop unrolled: the factor's window comes
+// through the scalar cache for every row at once, so the loads of later rows
+// overlap the arithmetic of earlier ones; absent rows are predicated off.
+template <class R, int W>
+__device__ __forceinline__ void body_blk2u(uint32_t o, uint64_t m, int ws, const uint16_t *lq,
+                                           const R *__restrict__ T, int nb, const typename Cx<R>::T *xs,
+                                           typename Cx<R>::T *ys)
+{
+    using C = typename Cx<R>::T;
+    using CR = __attribute__((address_space(4))) const R;
+    C xw[W];
+    uint32_t q[W];
+    bool on[W];
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+        const int j = ws + jj;
+        on[jj] = (m >> j) & 1ull;
+        q[jj] = on[jj] ? o + (uint32_t)__popcll(m & ((1ull << j) - 1ull)) : o;
+    }
+    if (lq) {
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) q[jj] = lq[q[jj]];
+    }
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+        const C v = xs[q[jj]];
+        xw[jj] = on[jj] ? v : Cx<R>::make(0, 0);
+    }
+    CR *Tw = (CR *)(T + ws * nb + ws);
+#pragma unroll
+    for (int ll = 0; ll < W; ++ll) {
+        CR *Tr = Tw + ll * nb;
+        R ar = 0, ai = 0;
+#pragma unroll
+        for (int jj = 0; jj < W; ++jj) {
+            const R t = Tr[jj];
+            ar = fma(t, xw[jj].x, ar);
+            ai = fma(t, xw[jj].y, ai);
+        }
+        if (on[ll]) {
+            const C v = ys[q[ll]];
+            ys[q[ll]] = Cx<R>::make(v.x + ar, v.y + ai);
+        }
+    }
+}
+
 template <class R, int NBMAX, int NT, int SU>
 __global__ __launch_bounds__(NT) void k_hpsi_blk2(BlockArgs<R> a, const typename Cx<R>::T *__restrict__ x,
                                                   typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
@@ -1205,7 +1252,8 @@ __global__ __launch_bounds__(NT) void k_hpsi_blk2(BlockArgs<R> a, const typename
 #define PPQ_B2(WW)                                                          \
     {                                                                       \
         const int ws = wlo < nb - (WW) ? wlo : nb - (WW);                   \
-        body_blk2<R, WW>(o, m, wm, ws, lq, T, nb, xs, ys);                  \
+        if (a.unroll) body_blk2u<R, WW>(o, m, ws, lq, T, nb, xs, ys);      \
+        else body_blk2<R, WW>(o, m, wm, ws, lq, T, nb, xs, ys);             \
         continue;                                                           \
     }
             if (width <= 8) PPQ_B2(8)
@@ -1227,6 +1275,243 @@ __global__ __launch_bounds__(NT) void k_hpsi_blk2(BlockArgs<R> a, const typename
         const uint32_t i = u * NT + tid;
         if (i < len) y[p[u]] = ys[i];
     }
+}
+
+// ---- plane pass: two adjacent dimensions per pass ----------------------------
+// In the pair's frame a plane (every digit but d_a, d_b fixed) is a run of
+// frame ranks sorted by (d_a, d_b).  A wavefront takes a task, the planes
+// that start in one window of PLANE_WINDOW frame ranks, in rounds of at most
+// PLANE_SPAN ranks:
+//   1. every member of the round is loaded at once, 12 per lane (digits and
+//      position, then x and the base value: y, or V x on the first pass);
+//   2. plane by plane over the planes the round holds whole (bit 15 of the
+//      digits marks a plane's last member), the members scatter x into a dense
+//      n_a x n_b tile in the wavefront's own LDS region (absent cells are
+//      zero), the bounding box comes from two wavefront reductions, and
+//        Y[i][l] = sum_k h_a[i][k] X[k][l] + sum_j X[i][j] h_b[l][j]
+//      is formed over the box with 16x16x4 matrix-core steps: both products
+//      accumulate into the same 16 x 16 blocks (rows d_a, columns d_b), real
+//      and imaginary parts apart.  The blocks go back over the box, every
+//      member adds its cell to its base value, and the box is cleared;
+//   3. the members of those planes store y; a plane cut by the round's end
+//      starts the next round.
+// The two factors sit in LDS once per workgroup.  A point's x and base value
+// are read once and its y written once per pair of dimensions, where the
+// per-dimension passes read and write y once per dimension.
+__device__ inline uint32_t min2_u16(uint32_t u, uint32_t v)
+{
+    return (min(u >> 16, v >> 16) << 16) | min(u & 0xffffu, v & 0xffffu);
+}
+__device__ inline uint32_t max2_u16(uint32_t u, uint32_t v)
+{
+    return (max(u >> 16, v >> 16) << 16) | max(u & 0xffffu, v & 0xffffu);
+}
+__device__ inline uint32_t wave_min2_u16(uint32_t v)
+{
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = min2_u16(v, (uint32_t)__shfl_xor((int)v, s, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ inline uint32_t wave_max2_u16(uint32_t v)
+{
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = max2_u16(v, (uint32_t)__shfl_xor((int)v, s, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+constexpr int PLB = 256;               // 4 wavefronts per workgroup, one task each
+constexpr int PLU = PLANE_SPAN / 64;   // round members per lane
+constexpr uint32_t PL_END = 0x8000u;   // last member of its plane
+
+// Y over the box, one 16 x 16 block (rows d_a, columns d_b) at a time: the
+// block goes to the wavefront's block buffer Yr/Yi ([row][column]) and every
+// member of the plane (round slots [r0, r1)) whose cell lies in it adds it to
+// its base value.  X stays intact until the whole box is done.
+template <class R>
+__device__ __forceinline__ void plane_blocks(int a0, int a1, int b0, int b1, int na, int nb, int lane, int r0,
+                                             int r1, const uint32_t (&dg)[PLU], typename Cx<R>::T (&base)[PLU],
+                                             const R *__restrict__ sTa, const R *__restrict__ sTb, const R *Xr,
+                                             const R *Xi, R *Yr, R *Yi)
+{
+    using M = Mma<R>;
+    const int col = lane & 15, kr = lane >> 4;
+    const int Ra = a1 - a0 + 1, Rb = b1 - b0 + 1;
+    for (int i0 = a0; i0 <= a1; i0 += 16) {
+        for (int l0 = b0; l0 <= b1; l0 += 16) {
+            typename M::V4 accr{0, 0, 0, 0}, acci{0, 0, 0, 0};
+            const int i = i0 + col, l = l0 + col;
+            // dimension b: A = X[i][j] (rows of the tile), B = h_b[l][j]
+            for (int s = 0; s < (Rb + 3) >> 2; ++s) {
+                const int j = b0 + 4 * s + kr;
+                const bool ok = i < na && j < nb;
+                const R xr = ok ? Xr[i * nb + j] : R(0), xi = ok ? Xi[i * nb + j] : R(0);
+                const R tb = (l < nb && j < nb) ? sTb[l * nb + j] : R(0);
+                accr = M::op(xr, tb, accr);
+                acci = M::op(xi, tb, acci);
+            }
+            // dimension a: A = h_a[i][k], B = X[k][l] (columns of the tile)
+            for (int s = 0; s < (Ra + 3) >> 2; ++s) {
+                const int k = a0 + 4 * s + kr;
+                const R ta = (i < na && k < na) ? sTa[i * na + k] : R(0);
+                const bool ok = l < nb && k < na;
+                const R xr = ok ? Xr[k * nb + l] : R(0), xi = ok ? Xi[k * nb + l] : R(0);
+                accr = M::op(ta, xr, accr);
+                acci = M::op(ta, xi, acci);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Yr[M::row(kr, r) * 16 + col] = accr[r];
+                Yi[M::row(kr, r) * 16 + col] = acci[r];
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int u = 0; u < PLU; ++u) {
+                if (u * 64 >= r1 || u * 64 + 64 <= r0) continue;
+                const int m = u * 64 + lane;
+                const int di = (int)((dg[u] >> 8) & 0x7fu) - i0, dl = (int)(dg[u] & 0xffu) - l0;
+                if (m >= r0 && m < r1 && di >= 0 && di < 16 && dl >= 0 && dl < 16)
+                    base[u] = Cx<R>::make(base[u].x + Yr[di * 16 + dl], base[u].y + Yi[di * 16 + dl]);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(PLB, 2) void k_hpsi_plane(PlanePass pp, const R *__restrict__ Ta,
+                                                       const R *__restrict__ Tb,
+                                                       const typename Cx<R>::T *__restrict__ x,
+                                                       const R *__restrict__ V, typename Cx<R>::T *__restrict__ y,
+                                                       int first, const int *skip_if, int skip_j)
+{
+    using C = typename Cx<R>::T;
+    if (skip_if && skip_j >= *skip_if) return;
+    // consecutive tasks on one XCD (workgroups are dealt round-robin over 8)
+    const uint32_t nwg = (pp.ntask + PLB / 64 - 1) / (PLB / 64);
+    const uint32_t per = (nwg + 7) / 8, bi = blockIdx.x >> 3;
+    const uint32_t wg = (blockIdx.x & 7) * per + bi;
+    if (bi >= per || wg >= nwg) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int na = pp.na, nb = pp.nb, cells = na * nb;
+    R *sTa = reinterpret_cast<R *>(smem);
+    R *sTb = sTa + na * na;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    R *Xr = sTb + nb * nb + (size_t)wave * (2 * cells + 512);
+    R *Xi = Xr + cells;
+    R *Yr = Xi + cells;
+    R *Yi = Yr + 256;
+    const uint32_t t = wg * (PLB / 64) + (uint32_t)wave;
+    const bool has = t < pp.ntask;
+    const uint32_t T0 = has ? pp.tstart[t] : 0u, T1 = has ? pp.tstart[t + 1] : 0u;
+    for (int i = threadIdx.x; i < na * na; i += PLB) sTa[i] = Ta[i];
+    for (int i = threadIdx.x; i < nb * nb; i += PLB) sTb[i] = Tb[i];
+    for (int i = lane; i < 2 * cells; i += 64) Xr[i] = 0;
+    __syncthreads();
+    for (uint32_t c = T0; c < T1;) {
+        const int len = (int)min(T1 - c, (uint32_t)PLANE_SPAN);
+        // 1. the round's members
+        uint32_t pos[PLU], dg[PLU];
+#pragma unroll
+        for (int u = 0; u < PLU; ++u) {
+            const int i = u * 64 + lane;
+            pos[u] = 0xffffffffu;
+            dg[u] = 0;
+            if (u * 64 < len && i < len) {
+                const uint32_t q = c + (uint32_t)i;
+                dg[u] = pp.dig[q];
+                pos[u] = pp.P ? pp.P[q] : q;
+            }
+        }
+        C xv[PLU], base[PLU];
+#pragma unroll
+        for (int u = 0; u < PLU; ++u) {
+            xv[u] = Cx<R>::make(0, 0);
+            base[u] = Cx<R>::make(0, 0);
+            if (pos[u] != 0xffffffffu) {
+                xv[u] = x[pos[u]];
+                if (first) base[u].x = V[pos[u]];
+                else base[u] = y[pos[u]];
+            }
+        }
+        if (first) {
+#pragma unroll
+            for (int u = 0; u < PLU; ++u) base[u] = Cx<R>::make(base[u].x * xv[u].x, base[u].x * xv[u].y);
+        }
+        // `done` = members of the planes the round holds whole
+        int done = 0;
+#pragma unroll
+        for (int u = 0; u < PLU; ++u) {
+            const uint64_t e = __ballot(pos[u] != 0xffffffffu && (dg[u] & PL_END));
+            if (e) done = u * 64 + 64 - __clzll((long long)e);
+        }
+        if (done == 0) break;  // no whole plane (planes are shorter than a round: not reached)
+        // 2. plane by plane
+        for (int r0 = 0; r0 < done;) {
+            int r1 = done;
+#pragma unroll
+            for (int u = PLU - 1; u >= 0; --u) {
+                if (u * 64 + 63 < r0 || u * 64 >= r1) continue;
+                uint64_t e = __ballot(pos[u] != 0xffffffffu && (dg[u] & PL_END));
+                if (u * 64 < r0) e &= ~0ull << (r0 - u * 64);
+                if (e) r1 = u * 64 + __ffsll((unsigned long long)e);
+            }
+            uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+            for (int u = 0; u < PLU; ++u) {
+                if (u * 64 >= r1 || u * 64 + 64 <= r0) continue;
+                const int i = u * 64 + lane;
+                if (i >= r0 && i < r1) {
+                    const uint32_t da = (dg[u] >> 8) & 0x7fu, db = dg[u] & 0xffu;
+                    lo = min2_u16(lo, (da << 16) | db);
+                    hi = max2_u16(hi, (da << 16) | db);
+                    Xr[da * nb + db] = xv[u].x;
+                    Xi[da * nb + db] = xv[u].y;
+                }
+            }
+            lo = wave_min2_u16(lo);
+            hi = wave_max2_u16(hi);
+            const int a0 = (int)(lo >> 16), b0 = (int)(lo & 0xffffu), a1 = (int)(hi >> 16), b1 = (int)(hi & 0xffffu);
+            __builtin_amdgcn_wave_barrier();
+            plane_blocks<R>(a0, a1, b0, b1, na, nb, lane, r0, r1, dg, base, sTa, sTb, Xr, Xi, Yr, Yi);
+            // clear the plane's cells
+#pragma unroll
+            for (int u = 0; u < PLU; ++u) {
+                if (u * 64 >= r1 || u * 64 + 64 <= r0) continue;
+                const int i = u * 64 + lane;
+                if (i >= r0 && i < r1) {
+                    const uint32_t cell = ((dg[u] >> 8) & 0x7fu) * nb + (dg[u] & 0xffu);
+                    Xr[cell] = 0;
+                    Xi[cell] = 0;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            r0 = r1;
+        }
+        // 3. store the planes done
+#pragma unroll
+        for (int u = 0; u < PLU; ++u)
+            if (pos[u] != 0xffffffffu && u * 64 + lane < done) y[pos[u]] = base[u];
+        c += (uint32_t)done;
+    }
+}
+
+template <class R>
+void launch_plane(const PlanePass &pp, const R *Ta, const R *Tb, const typename Cx<R>::T *x, const R *V,
+                  typename Cx<R>::T *y, bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (pp.ntask == 0) return;
+    const int cells = pp.na * pp.nb;
+    const size_t lds = (size_t)(pp.na * pp.na + pp.nb * pp.nb + (PLB / 64) * (2 * cells + 512)) * sizeof(R);
+    const uint32_t nwg = (pp.ntask + PLB / 64 - 1) / (PLB / 64);
+    const dim3 grid(8 * ((nwg + 7) / 8));
+    static std::once_flag attr_once;
+    std::call_once(attr_once, [] {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_hpsi_plane<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES) != hipSuccess)
+            (void)hipGetLastError();
+    });
+    hipLaunchKernelGGL((k_hpsi_plane<R>), grid, dim3(PLB), lds, s, pp, Ta, Tb, x, V, y, first ? 1 : 0, skip_if,
+                       skip_j);
 }
 
 }  // namespace
@@ -1478,6 +1763,7 @@ void launch_block2(const BlockPass &bp, const R *const *T, const typename Cx<R>:
     a.P = bp.P;
     a.accumulate = accumulate ? 1 : 0;
     a.V = V;
+    a.unroll = bp.unroll;
     int npi = 0;
     for (int d = 0; d < bp.ndim; ++d) npi += bp.pi[d] ? 1 : 0;
     const size_t bpp = 2 * sizeof(C) + sizeof(uint16_t) * (size_t)npi;
@@ -1580,6 +1866,18 @@ void hpsi_long_cplx_f32(const LongPass &lp, const float2 *H, const CInput32 &in,
         a.c[i] = in.c[i];
     }
     launch_long<float, true>(lp, H, a, nullptr, y, accumulate ? 1 : 0, skip_if, skip_j, s);
+}
+
+void hpsi_plane_f64(const PlanePass &pp, const double *Ta, const double *Tb, const double2 *x, const double *V,
+                    double2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_plane<double>(pp, Ta, Tb, x, V, y, first, skip_if, skip_j, s);
+}
+
+void hpsi_plane_f32(const PlanePass &pp, const float *Ta, const float *Tb, const float2 *x, const float *V,
+                    float2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_plane<float>(pp, Ta, Tb, x, V, y, first, skip_if, skip_j, s);
 }
 
 void hpsi_block_f64(const BlockPass &bp, const double *const *T, const double2 *x, const double *V, double2 *y,

@@ -236,6 +236,7 @@ struct BlockPass {
     const uint32_t *big;                 // chunks longer than cap_small
     uint32_t nbig;
     uint32_t cap_small, cap_big;         // LDS capacity (points) of the two launches
+    int unroll = 1;                      // one-lane-per-fiber pass: unrolled row loop
 };
 void hpsi_block_f64(const BlockPass &bp, const double *const *T, const double2 *x, const double *V, double2 *y,
                     bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
@@ -246,6 +247,35 @@ void hpsi_block2_f64(const BlockPass &bp, const double *const *T, const double2 
                      bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
 void hpsi_block2_f32(const BlockPass &bp, const float *const *T, const float2 *x, const float *V, float2 *y,
                      bool accumulate, const int *skip_if, int skip_j, hipStream_t s);
+
+// ---- plane pass: two adjacent dimensions (a, a+1) per pass ------------------
+// Frame: every other digit in row-major order, then the pair's merged digit
+// d_a n_{a+1} + d_{a+1}; the points sharing every other digit (a plane) are a
+// contiguous run of it.  For the last two dimensions the frame is the key
+// order itself (P == nullptr).
+constexpr int PLANE_SPAN = 768;        // members one wavefront holds at once (a round)
+constexpr uint32_t PLANE_WINDOW = 512;  // task t: the planes starting in [t W, (t + 1) W)
+constexpr int PLANE_NMAX = 32;         // largest size of either dimension of a pair
+struct PlanePass {
+    const uint32_t *P;       // frame rank -> storage position; nullptr = identity
+    const uint16_t *dig;     // (d_a << 8) | d_{a+1} per frame rank; bit 15 marks a plane's last member
+    const uint32_t *tstart;  // first frame rank of each task (a plane start) [ntask + 1], tstart[ntask] = n
+    uint32_t ntask;          // ceil(n / PLANE_WINDOW)
+    int na, nb;              // tile shape: the two factors' padded sizes (leading dimensions)
+};
+// Builds a pair's frame tables.  bm/prefix: a bitmap of the grid (nwords + 2
+// words) and its prefix (rotated frames only); poff (n + 1), pkey, flags,
+// pidx (n each): work space; counter: one device word of work space.  A plane
+// must hold fewer than PLANE_SPAN points (n_a n_{a+1} < PLANE_SPAN).
+void plane_tables(const uint32_t *keys, int64_t n, const GridDesc &g, int a, uint64_t *bm, uint32_t *prefix,
+                  int64_t nwords, uint32_t *P, uint16_t *dig, uint32_t *tstart, uint32_t *poff, uint32_t *pkey,
+                  uint32_t *flags, uint32_t *pidx, uint32_t *scan_tmp, uint32_t *counter, hipStream_t s);
+// y (+)= (h_a (x) 1 + 1 (x) h_{a+1}) x over every plane; first == true writes
+// y = ... + V x.  Ta, Tb: the factors (na x na, nb x nb, row-major).
+void hpsi_plane_f64(const PlanePass &pp, const double *Ta, const double *Tb, const double2 *x, const double *V,
+                    double2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_plane_f32(const PlanePass &pp, const float *Ta, const float *Tb, const float2 *x, const float *V,
+                    float2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
 // FP32 forms
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);

@@ -722,6 +722,59 @@ __global__ void k_chunks(const uint32_t *keys, const uint32_t *P, uint32_t n, ui
     if (len > cap) big[atomicAdd(&counters[0], 1u)] = (uint32_t)t;
 }
 
+// ---- plane tables (two adjacent dimensions merged into one digit) ------------
+// q = the point's rank in the pair's frame (its own position in the identity
+// frame, bm == nullptr); P[q] = p, the pair's two digits and the plane key
+// (the frame key without the merged digit).
+__global__ void k_plane_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_t na, uint32_t nb,
+                             const uint64_t *bm, const uint32_t *prefix, uint32_t *P, uint16_t *dig, uint32_t *pkey)
+{
+    int64_t p = gid();
+    if (p >= n) return;
+    const uint32_t nk = na * nb;
+    uint32_t d;
+    const uint32_t rk = rotate_key(keys[p], sk, nk, &d);
+    uint32_t q = (uint32_t)p;
+    if (bm) {
+        q = prefix[rk >> 6] + (uint32_t)__popcll(bm[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
+        P[q] = (uint32_t)p;
+    }
+    dig[q] = (uint16_t)(((d / nb) << 8) | (d % nb));
+    pkey[q] = rk / nk;
+}
+
+// Marks the last member of every plane (bit 15 of its digits).
+__global__ void k_plane_flags(const uint32_t *pkey, int64_t n, uint32_t *flags, uint16_t *dig)
+{
+    int64_t q = gid();
+    if (q >= n) return;
+    const uint32_t k = pkey[q];
+    flags[q] = (q == 0 || k != pkey[q - 1]) ? 1u : 0u;
+    if (q == n - 1 || k != pkey[q + 1]) dig[q] = (uint16_t)(dig[q] | 0x8000u);
+}
+
+__global__ void k_plane_fill(const uint32_t *flags, const uint32_t *pidx, int64_t n, const uint32_t *np,
+                             uint32_t *poff)
+{
+    int64_t q = gid();
+    if (q == 0) poff[*np] = (uint32_t)n;
+    if (q < n && flags[q]) poff[pidx[q]] = (uint32_t)q;
+}
+
+// Task t starts at the first plane start at or after t S (n for none):
+// plane pl starts the tasks t with poff[pl - 1] < t S <= poff[pl].
+__global__ void k_plane_tasks(const uint32_t *poff, const uint32_t *np, int64_t n, uint32_t S, uint32_t ntask,
+                              uint32_t *tstart)
+{
+    int64_t pl = gid();
+    const uint32_t npl = *np;
+    if (pl > (int64_t)npl) return;
+    const uint32_t lo = pl == 0 ? 0u : poff[pl - 1] / S + 1u;
+    const uint32_t hi = pl == (int64_t)npl ? ntask : poff[pl] / S;
+    const uint32_t st = pl == (int64_t)npl ? (uint32_t)n : poff[pl];
+    for (uint32_t t = lo; t <= hi && t <= ntask; ++t) tstart[t] = st;
+}
+
 __global__ void k_fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
                            const uint32_t *nf, uint32_t *off, uint64_t *mask)
 {
@@ -1842,6 +1895,29 @@ void fiber_tables_all(const uint32_t *keys, int64_t n, const RotAll &r, uint64_t
     hipLaunchKernelGGL(k_fib_fill_all, dim3(nblocks(m)), dim3(TB), 0, s, flags, fidx, tmpmask, n, r.nd, &counters[2],
                        t);
 }
+void plane_tables(const uint32_t *keys, int64_t n, const GridDesc &g, int a, uint64_t *bm, uint32_t *prefix,
+                  int64_t nwords, uint32_t *P, uint16_t *dig, uint32_t *tstart, uint32_t *poff, uint32_t *pkey,
+                  uint32_t *flags, uint32_t *pidx, uint32_t *scan_tmp, uint32_t *counter, hipStream_t s)
+{
+    if (n <= 0) return;
+    const uint32_t na = (uint32_t)g.n[a], nb = (uint32_t)g.n[a + 1];
+    const bool ident = (a + 2 == g.D);
+    const uint32_t sk = g.stride[a + 1];
+    if (!ident) {
+        fill_u64(bm, nwords + 2, 0ull, s);
+        hipLaunchKernelGGL(k_rot_set, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, sk, na * nb, 0u, 0u, bm);
+        scan_popcount(bm, nwords, prefix, counter, scan_tmp, s);
+    }
+    hipLaunchKernelGGL(k_plane_rank, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, ident ? 1u : sk, na, nb,
+                       ident ? nullptr : bm, ident ? nullptr : prefix, ident ? nullptr : P, dig, pkey);
+    hipLaunchKernelGGL(k_plane_flags, dim3(nblocks(n)), dim3(TB), 0, s, pkey, n, flags, dig);
+    scan_u32(flags, n, pidx, counter, scan_tmp, s);
+    hipLaunchKernelGGL(k_plane_fill, dim3(nblocks(n)), dim3(TB), 0, s, flags, pidx, n, counter, poff);
+    const uint32_t ntask = (uint32_t)((n + PLANE_WINDOW - 1) / PLANE_WINDOW);
+    hipLaunchKernelGGL(k_plane_tasks, dim3(nblocks(n + 1)), dim3(TB), 0, s, poff, counter, n, PLANE_WINDOW, ntask,
+                       tstart);
+}
+
 void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n, const uint32_t *nf,
               uint32_t *off, uint64_t *mask, hipStream_t s)
 {

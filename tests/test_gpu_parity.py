@@ -634,10 +634,13 @@ def test_fp32_shadow_steps(name, nsteps, torch):
 
 
 # ---------------------------------------------------------------------------
-# block-fused layout (selected per context with PPQ_HPSI=4): the same
-# products and trajectories as the per-dimension layout
+# fused layouts (selected per context with PPQ_HPSI): the same products and
+# trajectories as the per-dimension layout
 # ---------------------------------------------------------------------------
-BLOCK_VARIANTS = ["4", "5"]  # block-fused layouts: row groups per wave task; one lane per fiber
+# 4, 5: block-fused (row groups per wave task; one lane per fiber);
+# 6: plane passes (two dimensions per pass through matrix-core tiles; a card
+# with a dimension above 32 points keeps the per-dimension layout)
+BLOCK_VARIANTS = ["4", "5", "6"]
 
 
 def make_block(cd, torch, precision=0, variant="4"):
@@ -716,6 +719,31 @@ def test_block_layout_oversized_blocks_fall_back(variant, torch):
     torch.cuda.synchronize()
     err = np.max(np.abs(yt.cpu().numpy() - ref)) / np.max(np.abs(ref))
     assert err < 1e-13
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("fill", [1.0, 0.3])
+def test_plane_pass_largest_planes(fill, prec, torch):
+    """Plane passes at the largest planes a task holds: a 6 x 27 x 28 grid,
+    full (756-point planes of the pair (1, 2), one per task, in 32 x 32
+    tiles; dimension 0 keeps its own pass) and a random subset."""
+    cd = card("small_3d", n=[6, 27, 28])
+    n = cd["n"]
+    keys = np.arange(int(np.prod(n)), dtype=np.uint64) if fill == 1.0 else random_active_set(n, fill, 31)
+    x = random_complex(keys.size, 32)
+    xin = x if prec == 0 else x.astype(np.complex64).astype(np.complex128)
+    ref = Oracle(cd).apply_def(keys, xin)
+    g = make_block(cd, torch, prec, "6")
+    g.set_state(keys, x)
+    xt = torch.from_numpy(x).cuda()
+    if prec == 1:
+        xt = xt.to(torch.complex64)
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(yt.cpu().numpy().astype(np.complex128) - ref)) / np.max(np.abs(ref))
+    say(f"  plane passes 6x27x28 fill {fill} prec {prec}: rel err {err:.2e}")
+    assert err < (1e-13 if prec == 0 else 1e-6)
 
 
 @pytest.mark.parametrize("variant", BLOCK_VARIANTS)
