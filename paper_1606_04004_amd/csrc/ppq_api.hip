@@ -193,6 +193,10 @@ struct ppq_ctx {
     uint32_t *pl_poff = nullptr;  // plane starts while the tables are built
     int64_t pl_cap = 0;
 
+    // <x|y> of a product fused into its last pass (Hermitian Krylov steps)
+    bool dot_want = false;  // the caller asks for it
+    int dot_nb = 0;         // blocks whose partials the last product stored (0: not fused)
+
     // work
     uint32_t *flags = nullptr, *fidx = nullptr;
     uint64_t *tmpmask = nullptr;
@@ -1231,6 +1235,16 @@ FiberPass pass_of(const ppq_ctx *c, int k)
     return fp;
 }
 
+// The partial buffer for a dot fused into the last pass of a product, or
+// nullptr when the caller did not ask for one or the pass has more blocks
+// than the buffer holds (dimension 0's fiber pass launches nf_0 / 256 blocks).
+double2 *fused_dot_partial(const ppq_ctx *c)
+{
+    if (!c->dot_want || c->g.D < 2) return nullptr;
+    const int64_t nb = (c->nf[0] + 255) / 256;
+    return nb <= DOT_BLOCKS_MAX ? c->partial : nullptr;
+}
+
 // y = P H_1 P x: the one-dimensional factors and the diagonal potential
 void apply_single(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
 {
@@ -1338,7 +1352,9 @@ void apply_single(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int 
                                 skip_if, skip_j, s);
                 for (int k = D - 2; k >= 0; --k) {
                     if (longf(k)) hpsi_mfma_f64(pass_of(c, k), c->T64p[k], x, nullptr, y, false, skip_if, skip_j, s);
-                    else if (c->nb[k] <= 32) hpsi_acc_f64(pass_of(c, k), c->T64[k], x, y, skip_if, skip_j, s);
+                    else if (c->nb[k] <= 32)
+                        c->dot_nb = hpsi_acc_f64(pass_of(c, k), c->T64[k], x, y, skip_if, skip_j, s,
+                                                 k == 0 ? fused_dot_partial(c) : nullptr);
                     else hpsi_real_f64(pass_of(c, k), c->T64[k], x, nullptr, y, false, skip_if, skip_j, s);
                 }
             } else {
@@ -1351,7 +1367,9 @@ void apply_single(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int 
                 hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
                 for (int k = D - 2; k >= 0; --k) {
                     if (longf(k)) hpsi_mfma_f32(pass_of(c, k), c->T32p[k], x, nullptr, y, false, skip_if, skip_j, s);
-                    else if (c->nb[k] <= 32) hpsi_acc_f32(pass_of(c, k), c->T32[k], x, y, skip_if, skip_j, s);
+                    else if (c->nb[k] <= 32)
+                        c->dot_nb = hpsi_acc_f32(pass_of(c, k), c->T32[k], x, y, skip_if, skip_j, s,
+                                                 k == 0 ? fused_dot_partial(c) : nullptr);
                     else hpsi_real_f32(pass_of(c, k), c->T32[k], x, nullptr, y, false, skip_if, skip_j, s);
                 }
             }
@@ -1522,7 +1540,12 @@ void apply_products(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, in
 // y = P H P x on the current set (device vectors of the context precision)
 void apply_launches(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int skip_j)
 {
+    // a fused <x|y> needs the single-factor passes to write y last
+    const bool want = c->dot_want;
+    c->dot_want = want && c->pairs.empty() && c->chains.empty();
+    c->dot_nb = 0;
     apply_single(c, xv, yv, skip_if, skip_j);
+    c->dot_want = want;
     if (c->nact > 0) apply_products(c, xv, yv, skip_if, skip_j);
 }
 
@@ -1602,18 +1625,26 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, doub
     for (int j = 0; j < m; ++j) {
         const C *vj = Vb + (int64_t)j * ld;
         mark(c, PPQ_PHASE_HPSI);
+        // Hermitian: alpha_j = <v_j|H v_j> is reduced by the product's last
+        // pass where it can be (every pass but the last only adds to w)
+        c->dot_want = herm;
         apply_internal(c, vj, w, meff, j);
+        c->dot_want = false;
+        const int fused = c->dot_nb;
         mark(c, PPQ_PHASE_KRYLOV);
         const bool last = (j == m - 1);
         if (last && herm) {
             // only alpha_{m-1} = <v_j|H v_j> enters the tridiagonal matrix
-            cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s);
+            if (fused) finalize_dot(c->partial, fused, ks, j, m, RED_H1, s);
+            else cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s);
             break;
         }
         // Hermitian: the first pass needs only alpha_j (two vectors read,
         // not j + 2); the recurrence supplies the rest, and the second pass
         // still orthogonalises against every v_i.
-        if (herm)
+        if (herm && fused)
+            finalize_dot(c->partial, fused, ks, j, m, RED_H1L, s);
+        else if (herm)
             cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s, RED_H1L);
         else
             cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, 0, s);

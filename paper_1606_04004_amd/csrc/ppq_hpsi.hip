@@ -148,10 +148,12 @@ __global__ __launch_bounds__(HB) void k_hpsi_real(const uint32_t *__restrict__ p
 // Accumulating pass with every memory access of the wavefront issued up
 // front: positions, x and the old y of all window digits are loaded before the
 // contraction, so the output loop has no dependent loads.
-template <class R, int W, int NMAX, bool IDENT>
-__device__ __forceinline__ void body_real_acc(uint32_t o, uint64_t m, int ws, const uint32_t *__restrict__ pi,
-                                              const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
-                                              typename Cx<R>::T *__restrict__ y)
+// DOT: also returns sum_p conj(x_p) y_p over the fiber (the stored y), the
+// lane's share of <x|y> when this pass writes y last.
+template <class R, int W, int NMAX, bool IDENT, bool DOT>
+__device__ __forceinline__ double2 body_real_acc(uint32_t o, uint64_t m, int ws, const uint32_t *__restrict__ pi,
+                                                 const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
+                                                 typename Cx<R>::T *__restrict__ y)
 {
     using C = typename Cx<R>::T;
     C xw[W], yw[W];
@@ -175,6 +177,7 @@ __device__ __forceinline__ void body_real_acc(uint32_t o, uint64_t m, int ws, co
         }
     }
     const R *Tw = T + ws * NMAX + ws;
+    double2 dot = make_double2(0.0, 0.0);
 #pragma unroll
     for (int ll = 0; ll < W; ++ll) {
         R ar = yw[ll].x, ai = yw[ll].y;
@@ -185,15 +188,26 @@ __device__ __forceinline__ void body_real_acc(uint32_t o, uint64_t m, int ws, co
             ar = fma(t, xw[jj].x, ar);
             ai = fma(t, xw[jj].y, ai);
         }
-        if ((m >> (ws + ll)) & 1ull) y[pw[ll]] = Cx<R>::make(ar, ai);
+        if ((m >> (ws + ll)) & 1ull) {
+            y[pw[ll]] = Cx<R>::make(ar, ai);
+            if (DOT) {
+                const double xr = (double)xw[ll].x, xi = (double)xw[ll].y;
+                dot.x = fma(xr, (double)ar, fma(xi, (double)ai, dot.x));
+                dot.y = fma(xr, (double)ai, fma(-xi, (double)ar, dot.y));
+            }
+        }
     }
+    return dot;
 }
 
-template <class R, int NMAX, bool IDENT>
+// DOT: every block also stores its share of <x|y> (the y this pass leaves)
+// in dotp[blockIdx.x], summed over the block in a fixed order.
+template <class R, int NMAX, bool IDENT, bool DOT>
 __global__ __launch_bounds__(HB) void k_hpsi_acc(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
                                                  const uint64_t *__restrict__ mask, int64_t nf,
                                                  const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
-                                                 typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j)
+                                                 typename Cx<R>::T *__restrict__ y, const int *skip_if, int skip_j,
+                                                 double2 *__restrict__ dotp)
 {
     if (skip_if && skip_j >= *skip_if) return;
     int64_t f = (int64_t)blockIdx.x * HB + threadIdx.x;
@@ -204,33 +218,55 @@ __global__ __launch_bounds__(HB) void k_hpsi_acc(const uint32_t *__restrict__ pi
         o = off[f];
     }
     uint64_t wm = wave_or64(m);
-    if (wm == 0) return;
-    int wlo = __ffsll((unsigned long long)wm) - 1;
-    int whi = 63 - __clzll((long long)wm);
-    int width = whi - wlo + 1;
-#define PPQ_BODY(W)                                                        \
-    {                                                                      \
-        int ws = wlo < NMAX - (W) ? wlo : NMAX - (W);                      \
-        body_real_acc<R, W, NMAX, IDENT>(o, m, ws, pi, T, x, y);          \
-        return;                                                            \
+    double2 dot = make_double2(0.0, 0.0);
+    if (wm != 0) {
+        int wlo = __ffsll((unsigned long long)wm) - 1;
+        int whi = 63 - __clzll((long long)wm);
+        int width = whi - wlo + 1;
+#define PPQ_BODY(W)                                                                 \
+    {                                                                               \
+        int ws = wlo < NMAX - (W) ? wlo : NMAX - (W);                               \
+        dot = body_real_acc<R, W, NMAX, IDENT, DOT>(o, m, ws, pi, T, x, y);        \
+        goto done;                                                                  \
     }
-    if constexpr (NMAX >= 8) {
-        if (width <= 8) PPQ_BODY(8)
-    }
-    if constexpr (NMAX >= 12) {
-        if (width <= 12) PPQ_BODY(12)
-    }
-    if constexpr (NMAX >= 16) {
-        if (width <= 16) PPQ_BODY(16)
-    }
-    if constexpr (NMAX >= 24) {
-        if (width <= 24) PPQ_BODY(24)
-    }
-    if constexpr (NMAX >= 32) {
-        if (width <= 32) PPQ_BODY(32)
-    }
-    PPQ_BODY(NMAX)
+        if constexpr (NMAX >= 8) {
+            if (width <= 8) PPQ_BODY(8)
+        }
+        if constexpr (NMAX >= 12) {
+            if (width <= 12) PPQ_BODY(12)
+        }
+        if constexpr (NMAX >= 16) {
+            if (width <= 16) PPQ_BODY(16)
+        }
+        if constexpr (NMAX >= 24) {
+            if (width <= 24) PPQ_BODY(24)
+        }
+        if constexpr (NMAX >= 32) {
+            if (width <= 32) PPQ_BODY(32)
+        }
+        PPQ_BODY(NMAX)
 #undef PPQ_BODY
+    }
+done:
+    if constexpr (DOT) {
+        __shared__ double2 wsum[HB / 64];
+#pragma unroll
+        for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+            dot.x += __shfl_xor(dot.x, s2, 64);
+            dot.y += __shfl_xor(dot.y, s2, 64);
+        }
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = dot;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double2 t = wsum[0];
+#pragma unroll
+            for (int w2 = 1; w2 < HB / 64; ++w2) {
+                t.x += wsum[w2].x;
+                t.y += wsum[w2].y;
+            }
+            dotp[blockIdx.x] = t;
+        }
+    }
 }
 
 // ---- complex factor (lattice bases), input a linear combination -----------------
@@ -1535,13 +1571,20 @@ void hpsi_pt_f32(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, c
 }
 
 template <class R>
-void launch_acc(const FiberPass &fp, const R *T, const typename Cx<R>::T *x, typename Cx<R>::T *y, const int *skip_if,
-                int skip_j, hipStream_t s)
+int launch_acc(const FiberPass &fp, const R *T, const typename Cx<R>::T *x, typename Cx<R>::T *y, const int *skip_if,
+               int skip_j, double2 *dotp, hipStream_t s)
 {
-    if (fp.nf <= 0) return;
-#define L(NM)                                                                                                  \
-    hipLaunchKernelGGL((k_hpsi_acc<R, NM, false>), dim3((unsigned)((fp.nf + HB - 1) / HB)), dim3(HB), 0, s, fp.pi, \
-                       fp.off, fp.mask, fp.nf, T, x, y, skip_if, skip_j)
+    if (fp.nf <= 0) return 0;
+    const unsigned nb = (unsigned)((fp.nf + HB - 1) / HB);
+#define L(NM)                                                                                                      \
+    do {                                                                                                           \
+        if (dotp)                                                                                                  \
+            hipLaunchKernelGGL((k_hpsi_acc<R, NM, false, true>), dim3(nb), dim3(HB), 0, s, fp.pi, fp.off, fp.mask, \
+                               fp.nf, T, x, y, skip_if, skip_j, dotp);                                             \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_hpsi_acc<R, NM, false, false>), dim3(nb), dim3(HB), 0, s, fp.pi, fp.off,         \
+                               fp.mask, fp.nf, T, x, y, skip_if, skip_j, dotp);                                    \
+    } while (0)
     switch (fp.nmax) {
     case 8: L(8); break;
     case 16: L(16); break;
@@ -1551,18 +1594,19 @@ void launch_acc(const FiberPass &fp, const R *T, const typename Cx<R>::T *x, typ
     default: L(64); break;
     }
 #undef L
+    return dotp ? (int)nb : 0;
 }
 
-void hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double2 *y, const int *skip_if, int skip_j,
-                  hipStream_t s)
+int hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double2 *y, const int *skip_if, int skip_j,
+                 hipStream_t s, double2 *dotp)
 {
-    launch_acc<double>(fp, T, x, y, skip_if, skip_j, s);
+    return launch_acc<double>(fp, T, x, y, skip_if, skip_j, dotp, s);
 }
 
-void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
-                  hipStream_t s)
+int hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
+                 hipStream_t s, double2 *dotp)
 {
-    launch_acc<float>(fp, T, x, y, skip_if, skip_j, s);
+    return launch_acc<float>(fp, T, x, y, skip_if, skip_j, dotp, s);
 }
 
 template <class R, bool CPLX>

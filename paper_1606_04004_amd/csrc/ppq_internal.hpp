@@ -185,11 +185,17 @@ void hpsi_pt_f64(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, c
                  const double *V, double2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
 void hpsi_pt_f32(const uint32_t *pi, const uint8_t *info, int64_t n, int nmax, const float *T, const float2 *x,
                  const float *V, float2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
-// accumulating pass (y += P h P x) with all loads issued before the contraction
-void hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double2 *y, const int *skip_if, int skip_j,
-                  hipStream_t s);
-void hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
-                  hipStream_t s);
+// accumulating pass (y += P h P x) with all loads issued before the contraction;
+// with dotp, every block also stores its share of <x|y> (the y it leaves) in
+// dotp[block] and the number of blocks is returned (0 without dotp)
+int hpsi_acc_f64(const FiberPass &fp, const double *T, const double2 *x, double2 *y, const int *skip_if, int skip_j,
+                 hipStream_t s, double2 *dotp = nullptr);
+int hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y, const int *skip_if, int skip_j,
+                 hipStream_t s, double2 *dotp = nullptr);
+// blocks of a fused <x|y> the shared partial buffer holds (RED_BLOCKS * PSTRIDE_H)
+constexpr int64_t DOT_BLOCKS_MAX = (int64_t)RED_BLOCKS * PSTRIDE_H;
+// Krylov reduction of nb per-block partials of <v_j|w> (mode RED_H1 or RED_H1L)
+void finalize_dot(const double2 *partial, int nb, KState *ks, int j, int m, int mode, hipStream_t s);
 // matrix-core forms (v_mfma_*_16x16x4); T64 / H64 are h zero-padded to 64 x 64
 void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);

@@ -2013,6 +2013,10 @@ void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *p
     PPQ_NV_SWITCH(nv, CALL)
 #undef CALL
 }
+void finalize_dot(const double2 *partial, int nb, KState *ks, int j, int m, int mode, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(TB), 0, s, partial, nb, ks, j, mode, m, j, 1, 0.0, 0.0);
+}
 template <class C>
 void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, double2 *partial, unsigned *counter,
                      KState *ks, int j, int m, bool with_norm, hipStream_t s)
