@@ -194,14 +194,21 @@ class Model:
         return any(is_dense(f) for f in t["factors"]) or t.get("coef_im", 0.0) != 0.0
 
     def single_dim_ops(self):
-        """Per dim: kinetic plus every one-factor term (dense in the lattice)."""
+        """Per dim: kinetic plus, in a lattice basis, every term on that one
+        dimension (the product of its factors' matrices, dense there) and, on
+        dimension 0, every constant term times the identity."""
         ops = [self.transform(k, self.T[k]) for k in range(self.D)]
         if self.pvb:
             for t in self.card["terms"]:
-                if len(t["factors"]) == 1:
-                    f = t["factors"][0]
-                    k = f["dim"]
-                    ops[k] = ops[k] + term_coef(t) * self.transform(k, self.factor_matrix(f))
+                dims = set(f["dim"] for f in t["factors"])
+                if not dims:
+                    ops[0] = ops[0] + term_coef(t) * np.eye(self.n[0])
+                elif len(dims) == 1:
+                    k = dims.pop()
+                    m = np.eye(self.n[k])
+                    for f in t["factors"]:
+                        m = m @ self.factor_matrix(f)
+                    ops[k] = ops[k] + term_coef(t) * self.transform(k, m)
         return ops
 
     def diag_terms(self):

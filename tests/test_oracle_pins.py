@@ -1240,3 +1240,70 @@ def test_fd_gradient_is_converged():
     scale = max(abs(v) for v in g1.values())
     for nm in names:
         assert abs(g1[nm] - g2[nm]) < 1e-6 * scale, nm
+
+
+@pytest.mark.parametrize("name", ["dwell2d", "dwell2d_literal"])
+def test_double_well_potential_closed_form(name):
+    """The double well's sum-of-products terms (Eq. ex_dwell written out in
+    powers) equal 6.4 (x-1)^2 (x-2)^2 + 37.5 (y-2)^2 + c(x, y) on its Fourier
+    grids, with the coupling c = 10 x^2 (y-2) of the card's reading or the
+    printed 10 x^2 y.  The reading keeps the double well the paper names:
+    along y = 2 the minima sit at x = 1 and 2 (V = 0) with a 0.4 barrier at
+    x = 1.5; the printed form has one minimum near x = 0.49 and puts the
+    packet's centre (2.1, 2.05) about 80 units above it."""
+    from oracle.model import factor_values, fgh_grid, term_coef
+    cd = card(name)
+    x, _ = fgh_grid(cd["n"][0], cd["lo"][0], cd["hi"][0])
+    y, _ = fgh_grid(cd["n"][1], cd["lo"][1], cd["hi"][1])
+
+    def sop(xv, yv):
+        q = (np.asarray(xv, float), np.asarray(yv, float))
+        tot = np.zeros(np.broadcast(*q).shape, complex)
+        for t in cd["terms"]:
+            v = term_coef(t) * np.ones_like(tot)
+            for f in t["factors"]:
+                v = v * factor_values(f, q[f["dim"]])
+            tot = tot + v
+        return tot.real
+
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    coupling = 10.0 * X ** 2 * (Y if name == "dwell2d_literal" else Y - 2.0)
+    ref = 6.4 * (X - 1) ** 2 * (X - 2) ** 2 + 37.5 * (Y - 2) ** 2 + coupling
+    assert np.max(np.abs(sop(X, Y) - ref)) < 1e-10 * np.max(np.abs(ref))
+    xs = np.linspace(-0.5, 3.7, 42001)
+    vline = sop(xs, 2.0 * np.ones_like(xs))
+    if name == "dwell2d":
+        assert abs(sop(1.0, 2.0)) < 1e-12 and abs(sop(2.0, 2.0)) < 1e-12
+        assert abs(sop(1.5, 2.0) - 0.4) < 1e-12
+        left, right = xs < 1.5, xs > 1.5
+        assert abs(xs[left][np.argmin(vline[left])] - 1.0) < 1e-3
+        assert abs(xs[right][np.argmin(vline[right])] - 2.0) < 1e-3
+    else:
+        assert abs(xs[np.argmin(vline)] - 0.493) < 2e-3
+        assert sop(2.1, 2.05) - vline.min() > 75.0
+
+
+@pytest.mark.parametrize("basis", ["pvb", "pw"])
+def test_lattice_constant_and_same_dimension_terms(basis):
+    """A reduced double well (15 x 9 Fourier grid, lattices 5 x 3 and 3 x 3)
+    with its constant term (175.6) and an added two-factor term on one
+    dimension (0.3 x * x): the unpruned lattice dynamics is the similarity
+    of the FGH dynamics, C(t) included, so a dropped constant (a phase
+    e^{-i 175.6 t}) or a dropped term fails it."""
+    base = card("dwell2d", n=[15, 9], lattice=[[5, 3], [3, 3]])
+    base["terms"] = base["terms"] + [{"coef": 0.3, "factors": [{"dim": 0, "kind": "power", "p": 1},
+                                                               {"dim": 0, "kind": "power", "p": 1}]}]
+    lat = dict(base, basis=basis)
+    od = orc.Oracle(base)
+    ol = orc.Oracle(lat)
+    kd, cd0 = _full_state(od)
+    kl, cl0 = _full_state(ol)
+    od.set_state(kd, cd0)
+    ol.set_state(kl, cl0)
+    td, _ = od.propagate(nsteps=6, dt=0.02, m=16, prune=False)
+    tl, _ = ol.propagate(nsteps=6, dt=0.02, m=16, prune=False)
+    cdt = td[:, 3] + 1j * td[:, 4]
+    clt = tl[:, 3] + 1j * tl[:, 4]
+    assert np.max(np.abs(cdt - clt)) < 1e-9
+    # the constant enters as a phase: without it C(t) turns by 175.6 t
+    assert abs(np.angle(cdt[-1] / clt[-1])) < 1e-8
