@@ -913,10 +913,14 @@ void build_operator(ppq_ctx *c)
             for (int k = 0; k < D; ++k)
                 if (!per[k].empty()) dims.push_back(k);
             const cd coef(t.coef, t.coef_im);
-            if (dims.size() == 1) {
+            if (dims.empty()) {
+                // a constant term: coef times the identity, carried by dimension 0
+                const int n0 = c->g.n[0];
+                for (int i = 0; i < n0; ++i) Hk[0][(size_t)i * n0 + i] += coef;
+            } else if (dims.size() == 1) {
                 const int k = dims[0];
                 for (size_t i = 0; i < Hk[k].size(); ++i) Hk[k][i] += coef * per[k][i];
-            } else if (dims.size() >= 2) {
+            } else {
                 std::vector<std::vector<cd>> dms;
                 for (int k : dims) dms.push_back(similarity(L[k], per[k], c->g.n[k]));
                 add_product(t.coef, t.coef_im, dims, dms, std::vector<std::vector<double>>(D));

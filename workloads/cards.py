@@ -185,18 +185,23 @@ def _sop3d():
     return c
 
 
-def _dwell2d():
+def _dwell2d(literal=False):
     """The paper's two-dimensional double well (Sec. III.A, Eqs. ex_dwell and
     ex_dwell_psiInitial): mass 200, V = 6.4 (x-1)^2 (x-2)^2 + 37.5 (y-2)^2 +
-    10 x^2 y written out in powers of x and y (sum-of-products terms, plus its
-    constant 175.6), the real Gaussian exp(-(x-2.1)^2/0.04 - (y-2.05)^2/0.02)
+    10 x^2 (y-2), written out in powers of x and y (sum-of-products terms plus
+    a constant), the real Gaussian exp(-(x-2.1)^2/0.04 - (y-2.05)^2/0.02)
     (widths sqrt(0.02) and 0.1 in exp(-(q-c)^2/(2 w^2))), Fourier grids of
     165 x 81 points on x in [-0.5, 3.7], y in [1.0, 2.9] (the phase-space
-    lattices take 15 x 11 and 9 x 9 on them), propagated to t_e = 24.6."""
+    lattices take 15 x 11 and 9 x 9 on them), propagated to t_e = 24.6.
+
+    The coupling is read as 10 x^2 (y-2): the printed 10 x^2 y adds 20 x^2 at
+    the y minimum, which leaves a single well near x = 0.5 with the packet
+    about 80 energy units up its wall, where it gains momenta beyond the
+    grid's |p| <= pi/dx.  ``literal=True`` gives the printed form."""
     terms = [
         {"coef": 6.4, "factors": [_power(0, 4)]},
         {"coef": -38.4, "factors": [_power(0, 3)]},
-        {"coef": 83.2, "factors": [_power(0, 2)]},
+        {"coef": 83.2 if literal else 63.2, "factors": [_power(0, 2)]},
         {"coef": -76.8, "factors": [_power(0, 1)]},
         {"coef": 37.5, "factors": [_power(1, 2)]},
         {"coef": -150.0, "factors": [_power(1, 1)]},
@@ -204,7 +209,8 @@ def _dwell2d():
         {"coef": 175.6, "factors": []},
     ]
     return {
-        "name": "dwell2d", "D": 2, "n": [165, 81], "lo": [-0.5, 1.0], "hi": [3.7, 2.9], "fgh": [0, 1],
+        "name": "dwell2d_literal" if literal else "dwell2d", "D": 2, "n": [165, 81], "lo": [-0.5, 1.0],
+        "hi": [3.7, 2.9], "fgh": [0, 1],
         "mass": 200.0, "terms": terms, "basis": "dvr", "lattice": [[15, 11], [9, 9]],
         "psi0": {"centre": [2.1, 2.05], "momentum": [0.0, 0.0], "width": [0.02 ** 0.5, 0.1]},
         "eps": 1e-5, "dt": 0.1, "nsteps": 246, "krylov": 16, "krylov_tol": 1e-10, "max_substeps": 64,
@@ -214,6 +220,7 @@ def _dwell2d():
 _BUILDERS = {
     "hh2d": _hh2d, "morse4d": _morse4d, "quartic6d": _quartic6d,
     "pvb4d": _pvb4d, "adjoint4d": _adjoint4d, "dwell2d": _dwell2d,
+    "dwell2d_literal": lambda: _dwell2d(literal=True),
 }
 
 
@@ -229,6 +236,7 @@ def card(name, **overrides):
       small_adjoint4d -> the adjoint card on 10 points per dimension, 20 steps
       sop3d     -> small_3d with general sum-of-products terms (dense factors,
                    complex coefficients, a three-factor product)
+      dwell2d_literal -> the double well with the coupling as printed (10 x^2 y)
     """
     if name in _BUILDERS:
         c = _BUILDERS[name]()
