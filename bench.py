@@ -37,7 +37,7 @@ SNAPSHOT_STEP = 250
 # workload's snapshot (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a 1 GiB
 # copy; profiles/hpsi_quartic6d_24pow6_traffic.md).  Valid for the
 # per-dimension layout's kernels as measured there.
-TRAFFIC_BYTES_PER_POINT_FP64 = 323.0
+TRAFFIC_BYTES_PER_POINT_FP64 = 322.5
 TRAFFIC_SOURCE = "profiles/hpsi_quartic6d_24pow6_traffic.md"
 
 
