@@ -324,7 +324,7 @@ template <class C>
 void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
               int j, int m, int ioff, hipStream_t s, int mode = RED_H1);
 template <class C>
-void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, double2 *partial, unsigned *counter,
+void cgs_update_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter,
                      KState *ks, int j, int m, bool with_norm, hipStream_t s);
 template <class C>
 void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,

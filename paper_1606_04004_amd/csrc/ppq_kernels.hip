@@ -1081,10 +1081,12 @@ __global__ __launch_bounds__(TB) void k_cgs_dots(const C *Vb, int64_t ld, const 
     block_reduce_store<NV>(acc, partial);
 }
 
-// w <- w - sum_i h1_i v_i; h2_i = <v_i|w>; with_norm: also |w|^2 and beta
+// w' = w - sum_i h1_i v_i formed on the fly (not stored); h2_i = <v_i|w'>;
+// with_norm: also |w'|^2 and beta
 template <class C, int NV>
-__global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld, C *w, int64_t n, double2 *partial,
-                                                        unsigned *counter, KState *ks, int j, int m, int with_norm)
+__global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld, const C *w, int64_t n,
+                                                        double2 *partial, unsigned *counter, KState *ks, int j, int m,
+                                                        int with_norm)
 {
     if (j >= ks->meff) return;
     double2 hc[NV];
@@ -1102,32 +1104,40 @@ __global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld,
             wv.x -= hc[i].x * vv[i].x - hc[i].y * vv[i].y;
             wv.y -= hc[i].x * vv[i].y + hc[i].y * vv[i].x;
         }
-        st2(w, p, wv);
-        const double2 wr = stored(w, wv);  // dots against the stored (possibly rounded) vector
 #pragma unroll
-        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], wr);
-        acc[NV].x = fma(wr.x, wr.x, fma(wr.y, wr.y, acc[NV].x));
+        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], wv);
+        acc[NV].x = fma(wv.x, wv.x, fma(wv.y, wv.y, acc[NV].x));
     }
     block_reduce_store<NV + 1>(acc, partial);
 }
 
-// out = (w - sum_i h2_i v_i) / beta
+// out = (w - sum_i (h1_i + h2_i) v_i) / beta: the first pass's update, which
+// k_cgs_update_dots formed without storing, and the second's
 template <class C, int NV>
 __global__ __launch_bounds__(TB) void k_cgs_update_scale(const C *Vb, int64_t ld, const C *w, C *out, int64_t n,
                                                          const KState *ks, int j)
 {
     if (j + 1 >= ks->meff) return;
-    double2 hc[NV];
+    double2 h1[NV], h2[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hc[i] = ks->h2[i * MAXM + j];
+    for (int i = 0; i < NV; ++i) {
+        h1[i] = ks->h1[i * MAXM + j];
+        h2[i] = ks->h2[i * MAXM + j];
+    }
     const double s = ks->inv_beta;
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
         double2 wv = ld2(w, p);
+        double2 vv[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            double2 vv = ld2(Vb, (int64_t)i * ld + p);
-            wv.x -= hc[i].x * vv.x - hc[i].y * vv.y;
-            wv.y -= hc[i].x * vv.y + hc[i].y * vv.x;
+            vv[i] = ld2(Vb, (int64_t)i * ld + p);
+            wv.x -= h1[i].x * vv[i].x - h1[i].y * vv[i].y;
+            wv.y -= h1[i].x * vv[i].y + h1[i].y * vv[i].x;
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            wv.x -= h2[i].x * vv[i].x - h2[i].y * vv[i].y;
+            wv.y -= h2[i].x * vv[i].y + h2[i].y * vv[i].x;
         }
         st2(out, p, make_double2(wv.x * s, wv.y * s));
     }
@@ -2018,7 +2028,7 @@ void finalize_dot(const double2 *partial, int nb, KState *ks, int j, int m, int 
     hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(TB), 0, s, partial, nb, ks, j, mode, m, j, 1, 0.0, 0.0);
 }
 template <class C>
-void cgs_update_dots(const C *Vb, int64_t ld, int nv, C *w, int64_t n, double2 *partial, unsigned *counter,
+void cgs_update_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter,
                      KState *ks, int j, int m, bool with_norm, hipStream_t s)
 {
 #define CALL(NV)                                                                                                    \
@@ -2057,7 +2067,7 @@ void lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, cons
                            hipStream_t);                                                                         \
     template void cgs_dots<C>(const C *, int64_t, int, const C *, int64_t, double2 *, unsigned *, KState *, int,  \
                               int, int, hipStream_t, int);                                                      \
-    template void cgs_update_dots<C>(const C *, int64_t, int, C *, int64_t, double2 *, unsigned *, KState *, int, \
+    template void cgs_update_dots<C>(const C *, int64_t, int, const C *, int64_t, double2 *, unsigned *, KState *, int, \
                                      int, bool, hipStream_t);                                                   \
     template void cgs_update_scale<C>(const C *, int64_t, int, const C *, C *, int64_t, const KState *, int,      \
                                       hipStream_t);                                                             \
