@@ -238,9 +238,10 @@ struct ppq_ctx {
     std::vector<double> factor[MAXD];  // caller's 1D factor per dimension (empty: sine-DVR kinetic)
     // fiber tables of all non-last dimensions at once (see fiber_tables_all)
     uint64_t *bmB = nullptr;
-    uint32_t *pfxB = nullptr, *flagsB = nullptr, *fidxB = nullptr, *scanB = nullptr, *cntB = nullptr;
-    uint64_t *tmaskB = nullptr;
-    int64_t bat_cap = 0;     // entries per dimension of flagsB/fidxB/tmaskB (0: not allocated)
+    uint32_t *pfxB = nullptr, *scanB = nullptr, *cntB = nullptr;
+    uint64_t *occB = nullptr;  // fiber-slot bitmaps of the non-last dimensions
+    uint32_t *opfxB = nullptr;
+    int64_t bat_cap = 0;     // capacity the batched work space was sized for (0: not allocated)
 
     // records
     double *rec = nullptr;
@@ -334,11 +335,10 @@ void free_state_buffers(ppq_ctx *c)
     for (int k = 0; k < MAXD; ++k) dfree(c->fch[k]);
     dfree(c->bmB);
     dfree(c->pfxB);
-    dfree(c->flagsB);
-    dfree(c->fidxB);
     dfree(c->scanB);
     dfree(c->cntB);
-    dfree(c->tmaskB);
+    dfree(c->occB);
+    dfree(c->opfxB);
     c->bat_cap = 0;
     for (int i = 0; i < MAXD; ++i) {
         dfree(c->plP[i]);
@@ -1020,12 +1020,27 @@ void build_inner_first(ppq_ctx *c)
 // Device memory the one-pass tables of all non-last dimensions need, or 0 if
 // they do not apply (one dimension; concatenated ranks beyond 32 bits).
 constexpr int64_t BATCH_BYTES_MAX = 8ll << 30;
+// Words of the fiber-slot bitmaps of the non-last dimensions, concatenated
+// (offsets in owoff[0..nd]): one bit per key with digit k removed.
+int64_t occ_words(const ppq_ctx *c, int64_t *owoff)
+{
+    const int nd = c->g.D - 1;
+    int64_t w = 0;
+    for (int k = 0; k < nd; ++k) {
+        if (owoff) owoff[k] = w;
+        w += ((int64_t)c->g.total / c->g.n[k] + 63) / 64;
+    }
+    if (owoff) owoff[nd] = w;
+    return w;
+}
+
 int64_t batched_bytes(const ppq_ctx *c)
 {
     const int64_t nd = c->g.D - 1;
+    // ranks of the concatenated bitmaps are offset by k |A| in 32 bits
     if (nd < 1 || (nd + 1) * c->cap >= (1ll << 32)) return 0;
-    const int64_t words = (nd + 1) * c->nwords + 2;
-    return words * 12 + nd * c->cap * 16 + scan_tmp_words(std::max(nd * c->cap, words)) * 4;
+    const int64_t words = (nd + 1) * c->nwords + 2, owords = occ_words(c, nullptr) + 2;
+    return (words + owords) * 12 + scan_tmp_words(std::max(words, owords)) * 4;
 }
 
 bool ensure_batched(ppq_ctx *c)
@@ -1035,21 +1050,19 @@ bool ensure_batched(ppq_ctx *c)
     const int64_t bytes = batched_bytes(c);
     if (bytes == 0 || bytes > BATCH_BYTES_MAX) return false;
     if (c->bat_cap == c->cap) return true;
-    const int64_t nd = c->g.D - 1, words = (nd + 1) * c->nwords + 2;
+    const int64_t nd = c->g.D - 1, words = (nd + 1) * c->nwords + 2, owords = occ_words(c, nullptr) + 2;
     dfree(c->bmB);
     dfree(c->pfxB);
-    dfree(c->flagsB);
-    dfree(c->fidxB);
     dfree(c->scanB);
     dfree(c->cntB);
-    dfree(c->tmaskB);
+    dfree(c->occB);
+    dfree(c->opfxB);
     c->bat_cap = 0;
     c->bmB = dalloc<uint64_t>(words);
     c->pfxB = dalloc<uint32_t>(words);
-    c->flagsB = dalloc<uint32_t>(nd * c->cap);
-    c->fidxB = dalloc<uint32_t>(nd * c->cap);
-    c->tmaskB = dalloc<uint64_t>(nd * c->cap);
-    c->scanB = dalloc<uint32_t>(scan_tmp_words(std::max(nd * c->cap, words)));
+    c->occB = dalloc<uint64_t>(owords);
+    c->opfxB = dalloc<uint32_t>(owords);
+    c->scanB = dalloc<uint32_t>(scan_tmp_words(std::max(words, owords)));
     c->cntB = dalloc<uint32_t>(2 + MAXD);
     c->bat_cap = c->cap;
     return true;
@@ -1127,6 +1140,7 @@ void build_derived(ppq_ctx *c)
         TabPtrs t{};
         r.nd = D - 1;
         r.nwords = c->nwords;
+        occ_words(c, r.owoff);
         for (int k = 0; k < D - 1; ++k) {
             r.sk[k] = c->g.stride[k];
             r.nk[k] = (uint32_t)c->g.n[k];
@@ -1134,8 +1148,7 @@ void build_derived(ppq_ctx *c)
             t.off[k] = c->off[k];
             t.mask[k] = c->mask[k];
         }
-        fiber_tables_all(keys, n, r, c->bmB, c->pfxB, t, c->flagsB, c->fidxB, c->tmaskB, c->scanB, c->cntB, c->small,
-                         s);
+        fiber_tables_all(keys, n, r, c->bmB, c->pfxB, c->occB, c->opfxB, t, c->scanB, c->cntB, c->small, s);
     } else {
         for (int k = try_block ? c->split : 0; k < D - 1; ++k) {
             build_row_major(c, k);

@@ -106,6 +106,7 @@ struct RotAll {
     uint32_t sk[MAXD];      // stride of the digit moved last
     uint32_t nk[MAXD];      // its size
     int64_t nwords;         // words per rotated bitmap
+    int64_t owoff[MAXD + 1];  // word offsets of the fiber-slot bitmaps (one bit per key without digit k)
 };
 struct TabPtrs {
     uint32_t *pi[MAXD];
@@ -113,11 +114,12 @@ struct TabPtrs {
     uint64_t *mask[MAXD];
 };
 // bm, prefix: (nd+1)*nwords + 2 words (nd rotated segments, then the row-major
-// one); flags, fidx, tmpmask: nd*n entries;
-// counters: 2 + nd entries of scratch; nf[k] receives dimension k's fiber count.
+// one); occ, oprefix: owoff[nd] + 2 words (per dimension a bit for every
+// fiber slot that holds a point; their ranks number the fibers); counters: 2
+// entries of scratch; nf[k] receives dimension k's fiber count.
 void fiber_tables_all(const uint32_t *keys, int64_t n, const RotAll &r, uint64_t *bm, uint32_t *prefix,
-                      const TabPtrs &t, uint32_t *flags, uint32_t *fidx, uint64_t *tmpmask, uint32_t *scan_tmp,
-                      uint32_t *counters, uint32_t *nf, hipStream_t s);
+                      uint64_t *occ, uint32_t *oprefix, const TabPtrs &t, uint32_t *scan_tmp, uint32_t *counters,
+                      uint32_t *nf, hipStream_t s);
 void rot_set(const uint32_t *keys, int64_t n, const RotFrame &f, uint64_t *bm, hipStream_t s);
 void rot_rank(const uint32_t *keys, int64_t n, const RotFrame &f, const uint64_t *bm, const uint32_t *prefix,
               const uint32_t *map, uint32_t *pi, uint32_t *inv, uint32_t *flags, uint64_t *tmpmask, uint8_t *info,

@@ -547,7 +547,7 @@ __global__ void k_rot_rank(const uint32_t *keys, int64_t n, uint32_t sk, uint32_
 // concatenation gives bitmap k's ranks offset by k n, and one scan over the
 // concatenated fiber-start flags gives dimension k's fiber numbers offset by
 // the count of the earlier dimensions.
-__global__ void k_rot_set_all(const uint32_t *keys, int64_t n, RotAll r, uint64_t *bm)
+__global__ void k_rot_set_all(const uint32_t *keys, int64_t n, RotAll r, uint64_t *bm, uint64_t *occ)
 {
     int64_t p = gid();
     const bool valid = p < n;
@@ -556,6 +556,8 @@ __global__ void k_rot_set_all(const uint32_t *keys, int64_t n, RotAll r, uint64_
         uint32_t d, rk = 0;
         if (valid) rk = rotate_key(key, r.sk[k], r.nk[k], &d);
         set_bit_wave(bm + (int64_t)k * r.nwords, rk, valid);
+        // the point's fiber slot (the rotated key without its last digit)
+        set_bit_wave(occ + r.owoff[k], rk / r.nk[k], valid);
     }
     // segment nd: the row-major bitmap of the set itself (point positions)
     set_bit_wave(bm + (int64_t)r.nd * r.nwords, key, valid);
@@ -584,9 +586,10 @@ __device__ inline int select_bit(uint64_t v, int r)
 // (a dense word's bits spread over the wavefront instead of one lane).  For
 // the bit of rotated key rk: q from the segment's prefix, the point's
 // position p from the row-major segment (rank of the un-rotated key), the
-// fiber start and mask from the n_k-bit window holding rk.
+// fiber start and mask from the n_k-bit window holding rk, and the fiber's
+// number from the rank of its slot among the occupied ones.
 __global__ __launch_bounds__(TB) void k_rank_gather(int64_t n, RotAll r, const uint64_t *bm, const uint32_t *prefix,
-                                                    TabPtrs t, uint32_t *flags, uint64_t *tmpmask)
+                                                    const uint64_t *occ, const uint32_t *oprefix, TabPtrs t)
 {
     __shared__ uint64_t s_word[TB];
     __shared__ uint32_t s_off[TB];
@@ -647,37 +650,27 @@ __global__ __launch_bounds__(TB) void k_rank_gather(int64_t n, RotAll r, const u
         t.pi[k][q] = p;
         const uint64_t *seg = bm + (int64_t)k * r.nwords;
         const uint64_t m = extract_bits(seg, rk - d, (int)nk);
-        const bool start = (m & ((1ull << d) - 1ull)) == 0;
-        const int64_t i = (int64_t)k * n + q;
-        flags[i] = start ? 1u : 0u;
-        if (start) tmpmask[i] = m;
+        if ((m & ((1ull << d) - 1ull)) == 0) {
+            // the fiber's first point: its slot tq's rank among the occupied slots
+            const int64_t o0 = r.owoff[k], ow = o0 + (tq >> 6);
+            const uint32_t f = oprefix[ow] - oprefix[o0] + (uint32_t)__popcll(occ[ow] & ((1ull << (tq & 63)) - 1ull));
+            t.off[k][f] = q;
+            t.mask[k][f] = m;
+        }
     }
 }
 
-// Per dimension: first fiber number (base), fiber count (nf) and the end
-// sentinel off_k[nf_k] = n.  `total` is the scan's total over all dimensions.
-__global__ void k_seg_counts(const uint32_t *fidx, int64_t n, int nd, const uint32_t *total, TabPtrs t,
-                             uint32_t *base, uint32_t *nf)
+// Per dimension: the fiber count (occupied slots) and the end sentinel
+// off_k[nf_k] = n.  `total` is the occupancy scan's total over all dimensions.
+__global__ void k_occ_counts(const uint32_t *oprefix, int64_t n, RotAll r, const uint32_t *total, TabPtrs t,
+                             uint32_t *nf)
 {
     const int k = threadIdx.x;
-    if (k >= nd) return;
-    const uint32_t b0 = fidx[(int64_t)k * n];
-    const uint32_t b1 = (k + 1 < nd) ? fidx[(int64_t)(k + 1) * n] : *total;
-    base[k] = b0;
+    if (k >= r.nd) return;
+    const uint32_t b0 = oprefix[r.owoff[k]];
+    const uint32_t b1 = (k + 1 < r.nd) ? oprefix[r.owoff[k + 1]] : *total;
     nf[k] = b1 - b0;
     t.off[k][b1 - b0] = (uint32_t)n;
-}
-
-__global__ void k_fib_fill_all(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
-                               int nd, const uint32_t *base, TabPtrs t)
-{
-    int64_t i = gid();
-    if (i >= (int64_t)nd * n || !flags[i]) return;
-    const int k = (int)(i / n);
-    const uint32_t q = (uint32_t)(i - (int64_t)k * n);
-    const uint32_t f = fidx[i] - base[k];
-    t.off[k][f] = q;
-    t.mask[k][f] = tmpmask[i];
 }
 
 // Chunks of whole blocks for the block-fused H*psi.  A block is a maximal run
@@ -1889,21 +1882,20 @@ void last_info(const uint32_t *keys, int64_t n, int nlast, uint8_t *info, hipStr
     hipLaunchKernelGGL(k_last_info, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, nlast, info);
 }
 void fiber_tables_all(const uint32_t *keys, int64_t n, const RotAll &r, uint64_t *bm, uint32_t *prefix,
-                      const TabPtrs &t, uint32_t *flags, uint32_t *fidx, uint64_t *tmpmask, uint32_t *scan_tmp,
-                      uint32_t *counters, uint32_t *nf, hipStream_t s)
+                      uint64_t *occ, uint32_t *oprefix, const TabPtrs &t, uint32_t *scan_tmp, uint32_t *counters,
+                      uint32_t *nf, hipStream_t s)
 {
     if (n <= 0 || r.nd <= 0) return;
     const int64_t words = (int64_t)(r.nd + 1) * r.nwords;  // nd rotated segments + the row-major one
-    const int64_t m = (int64_t)r.nd * n;
+    const int64_t owords = r.owoff[r.nd];
     fill_u64(bm, words + 2, 0ull, s);
-    hipLaunchKernelGGL(k_rot_set_all, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, r, bm);
+    fill_u64(occ, owords + 2, 0ull, s);
+    hipLaunchKernelGGL(k_rot_set_all, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, r, bm, occ);
     scan_popcount(bm, words, prefix, &counters[0], scan_tmp, s);
-    hipLaunchKernelGGL(k_rank_gather, dim3(nblocks((int64_t)r.nd * r.nwords)), dim3(TB), 0, s, n, r, bm, prefix, t,
-                       flags, tmpmask);
-    scan_u32(flags, m, fidx, &counters[1], scan_tmp, s);
-    hipLaunchKernelGGL(k_seg_counts, dim3(1), dim3(64), 0, s, fidx, n, r.nd, &counters[1], t, &counters[2], nf);
-    hipLaunchKernelGGL(k_fib_fill_all, dim3(nblocks(m)), dim3(TB), 0, s, flags, fidx, tmpmask, n, r.nd, &counters[2],
-                       t);
+    scan_popcount(occ, owords, oprefix, &counters[1], scan_tmp, s);
+    hipLaunchKernelGGL(k_occ_counts, dim3(1), dim3(64), 0, s, oprefix, n, r, &counters[1], t, nf);
+    hipLaunchKernelGGL(k_rank_gather, dim3(nblocks((int64_t)r.nd * r.nwords)), dim3(TB), 0, s, n, r, bm, prefix, occ,
+                       oprefix, t);
 }
 void plane_tables(const uint32_t *keys, int64_t n, const GridDesc &g, int a, uint64_t *bm, uint32_t *prefix,
                   int64_t nwords, uint32_t *P, uint16_t *dig, uint32_t *tstart, uint32_t *poff, uint32_t *pkey,
