@@ -1639,32 +1639,36 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, doub
     const bool herm = c->hermitian;
     norm0<C>(src, n, c->partial, c->counter, ks, m, dt, tol, s);
     normalise_from_master<C>(src, n, ks, Vb, s);
+    if (herm) {
+        // Lanczos with the second Gram-Schmidt pass of each vector applied in
+        // the next step's sweep: H is applied to the provisional q_j in slot
+        // j, <q_j|H q_j> comes from the product's last pass where it can,
+        // and one sweep per step corrects v_j and forms q_{j+1}
+        for (int j = 0; j < m; ++j) {
+            C *qj = Vb + (int64_t)j * ld;
+            mark(c, PPQ_PHASE_HPSI);
+            c->dot_want = true;
+            apply_internal(c, qj, w, meff, j);
+            c->dot_want = false;
+            const int fused = c->dot_nb;
+            mark(c, PPQ_PHASE_KRYLOV);
+            if (fused) finalize_dot(c->partial, fused, ks, j, m, RED_DELAY, s);
+            else cgs_dots<C>(qj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s, RED_DELAY);
+            if (j == m - 1) {
+                if (j > 0) lanczos_fix<C>(Vb, ld, n, ks, j, s);
+                break;
+            }
+            lanczos_sweep<C>(Vb, ld, w, n, c->partial, c->counter, ks, j, m, s);
+        }
+        return;
+    }
     for (int j = 0; j < m; ++j) {
         const C *vj = Vb + (int64_t)j * ld;
         mark(c, PPQ_PHASE_HPSI);
-        // Hermitian: alpha_j = <v_j|H v_j> is reduced by the product's last
-        // pass where it can be (every pass but the last only adds to w)
-        c->dot_want = herm;
         apply_internal(c, vj, w, meff, j);
-        c->dot_want = false;
-        const int fused = c->dot_nb;
         mark(c, PPQ_PHASE_KRYLOV);
         const bool last = (j == m - 1);
-        if (last && herm) {
-            // only alpha_{m-1} = <v_j|H v_j> enters the tridiagonal matrix
-            if (fused) finalize_dot(c->partial, fused, ks, j, m, RED_H1, s);
-            else cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s);
-            break;
-        }
-        // Hermitian: the first pass needs only alpha_j (two vectors read,
-        // not j + 2); the recurrence supplies the rest, and the second pass
-        // still orthogonalises against every v_i.
-        if (herm && fused)
-            finalize_dot(c->partial, fused, ks, j, m, RED_H1L, s);
-        else if (herm)
-            cgs_dots<C>(vj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s, RED_H1L);
-        else
-            cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, 0, s);
+        cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, 0, s);
         cgs_update_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, !last, s);
         if (last) break;
         cgs_update_scale<C>(Vb, ld, j + 1, w, Vb + (int64_t)(j + 1) * ld, n, ks, j, s);

@@ -53,6 +53,8 @@ struct KState {
     double2 h1[MAXM * MAXM];   // Hessenberg, first Gram-Schmidt pass  [i*MAXM + j]
     double2 h2[MAXM * MAXM];   // second pass
     double2 y[MAXM];           // coefficients of the propagated vector
+    double2 cc[MAXM];          // delayed correction (Hermitian): H v_j = (H q_j - sum_k cc_k v_k) / beta_{j-1}
+    double inv_b;              // 1 / beta_{j-1} for the provisional q_j
     double inv_beta;           // 1/beta of the last completed iteration
     double norm2_scratch;
     double est;                // error estimate of the current order: n0 dt^k/k! prod beta_i
@@ -318,7 +320,9 @@ void diag_scale(const uint32_t *keys, const C *x, int64_t n, const GridDesc &g, 
 // RED_H1L: Hermitian first pass, where only <v_j|w> is reduced; the other
 // first-pass coefficients are those of the three-term recurrence (beta_{j-1}
 // for v_{j-1}, zero below), and the second pass removes what they leave.
-enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3, RED_H1L = 4 };
+// RED_DELAY: Hermitian step with delayed correction, r[0] = <q_j|H q_j> of the
+// provisional vector; sets alpha_j, cc and inv_b (see k_lanczos_sweep).
+enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3, RED_H1L = 4, RED_DELAY = 5 };
 template <class C>
 void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, double dt,
            double tol, hipStream_t s);
@@ -328,6 +332,15 @@ void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *p
 template <class C>
 void cgs_update_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter,
                      KState *ks, int j, int m, bool with_norm, hipStream_t s);
+// Hermitian Lanczos step j with the second Gram-Schmidt pass delayed by one
+// step (see k_lanczos_sweep): corrects v_j in its slot, writes the provisional
+// q_{j+1} to slot j+1 and reduces <v_i|q_{j+1}> (i <= j) and |q_{j+1}|^2
+// into h2[.][j] and beta_j.  lanczos_fix corrects the last vector alone.
+template <class C>
+void lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, unsigned *counter, KState *ks, int j,
+                   int m, hipStream_t s);
+template <class C>
+void lanczos_fix(C *Vb, int64_t ld, int64_t n, const KState *ks, int j, hipStream_t s);
 template <class C>
 void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,
                       hipStream_t s);

@@ -1012,6 +1012,46 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         if (mode == RED_H1L)
             for (int i = 0; i < j; ++i)
                 ks->h1[i * MAXM + j] = make_double2(i == j - 1 ? ks->beta[j - 1] : 0.0, 0.0);
+    } else if (mode == RED_DELAY) {
+        // The provisional q_j = beta_{j-1} v_j + sum_{i<j} h_i v_i with
+        // h_i = h2[i][j-1] (the second pass's coefficients, not yet applied).
+        // From mu = <q_j|H q_j>, using H v_i = beta_i v_{i+1} + alpha_i v_i +
+        // beta_{i-1} v_{i-1} for i < j (all terms beyond O(h^2) kept):
+        //   g_i = <v_i|H q_j> = beta_i <v_{i+1}|q_j> + alpha_i h_i + beta_{i-1} h_{i-1}
+        //   alpha_j = (mu - 2 Re sum conj(h_i) g_i + sum conj(h_i) T_ik h_k) / beta_{j-1}^2
+        //   cc_k = sum_{i<j} T_ki h_i  (k <= j), so H v_j = (H q_j - sum cc_k v_k) / beta_{j-1}
+        const double2 mu = r[0];
+        for (int k = 0; k < MAXM; ++k) ks->cc[k] = make_double2(0.0, 0.0);
+        if (j == 0) {
+            ks->alpha[0] = mu.x;
+            ks->inv_b = 1.0;
+        } else {
+            const double b = ks->beta[j - 1];
+            const double2 *hh = ks->h2 + (j - 1);  // hh[i * MAXM] = h_i
+            double s1 = 0.0, s2 = 0.0;
+            for (int i = 0; i < j; ++i) {
+                const double2 hi = hh[i * MAXM];
+                const double2 hn = (i + 1 < j) ? hh[(i + 1) * MAXM] : make_double2(b, 0.0);
+                const double2 hp = (i >= 1) ? hh[(i - 1) * MAXM] : make_double2(0.0, 0.0);
+                const double bp = (i >= 1) ? ks->beta[i - 1] : 0.0;
+                const double2 g = make_double2(ks->beta[i] * hn.x + ks->alpha[i] * hi.x + bp * hp.x,
+                                               ks->beta[i] * hn.y + ks->alpha[i] * hi.y + bp * hp.y);
+                s1 += hi.x * g.x + hi.y * g.y;  // Re(conj(h_i) g_i)
+                s2 += ks->alpha[i] * (hi.x * hi.x + hi.y * hi.y);
+                if (i + 1 < j) s2 += 2.0 * ks->beta[i] * (hi.x * hn.x + hi.y * hn.y);
+                // cc_k = alpha_k h_k + beta_k h_{k+1} + beta_{k-1} h_{k-1}, gathered per h_i
+                ks->cc[i].x += ks->alpha[i] * hi.x;
+                ks->cc[i].y += ks->alpha[i] * hi.y;
+                ks->cc[i + 1].x += ks->beta[i] * hi.x;
+                ks->cc[i + 1].y += ks->beta[i] * hi.y;
+                if (i >= 1) {
+                    ks->cc[i - 1].x += ks->beta[i - 1] * hi.x;
+                    ks->cc[i - 1].y += ks->beta[i - 1] * hi.y;
+                }
+            }
+            ks->alpha[j] = (mu.x - 2.0 * s1 + s2) / (b * b);
+            ks->inv_b = 1.0 / b;
+        }
     } else {  // RED_H2 (+ beta from |w'|^2 - sum |h2_i|^2 when RED_BETA)
         const int nh = (mode == RED_BETA) ? nvals - 1 : nvals;
         double hh = 0.0, last = 0.0;
@@ -1133,6 +1173,87 @@ __global__ __launch_bounds__(TB) void k_cgs_update_scale(const C *Vb, int64_t ld
             wv.y -= h2[i].x * vv[i].y + h2[i].y * vv[i].x;
         }
         st2(out, p, make_double2(wv.x * s, wv.y * s));
+    }
+}
+
+// Hermitian Lanczos step j with the second Gram-Schmidt pass of each vector
+// delayed to the next step's sweep.  Slot j holds the provisional
+// q_j = beta_{j-1} v_j + sum_{i<j} h_i v_i (first pass only, unnormalised) and
+// z = H q_j; with h_i = h2[i][j-1] and alpha_j, cc from RED_DELAY, one pass
+//   v_j     = (q_j - sum_{i<j} h_i v_i) / beta_{j-1}           -> slot j
+//   H v_j   = (z - sum_{k<j} cc_k v_k - cc_j v_j) / beta_{j-1}
+//   q_{j+1} = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}          -> slot j+1
+// with the partial sums of <v_i|q_{j+1}> (i <= j) and |q_{j+1}|^2: the next
+// second pass's coefficients and, after RED_BETA, beta_j.  In exact arithmetic
+// h = 0 and this is the three-term recurrence; with rounding it applies the
+// same second projection as two separate sweeps would, one step later.
+template <class C, int NV>
+__global__ __launch_bounds__(TB) void k_lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial,
+                                                      unsigned *counter, KState *ks, int j)
+{
+    if (j >= ks->meff) return;
+    constexpr int NH = NV > 0 ? NV : 1;
+    double2 hq[NH], cc[NV + 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hq[i] = ks->h2[i * MAXM + (j - 1)];
+#pragma unroll
+    for (int k = 0; k <= NV; ++k) cc[k] = ks->cc[k];
+    const double ib = ks->inv_b, al = ks->alpha[j], bm = NV > 0 ? ks->beta[j - 1] : 0.0;
+    C *qs = Vb + (int64_t)j * ld;
+    C *qn = Vb + (int64_t)(j + 1) * ld;
+    double2 acc[NV + 2];
+#pragma unroll
+    for (int i = 0; i < NV + 2; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 qv = ld2(qs, p), hv = ld2(z, p);
+        double2 vv[NH];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            vv[i] = ld2(Vb, (int64_t)i * ld + p);
+            qv.x -= hq[i].x * vv[i].x - hq[i].y * vv[i].y;
+            qv.y -= hq[i].x * vv[i].y + hq[i].y * vv[i].x;
+            hv.x -= cc[i].x * vv[i].x - cc[i].y * vv[i].y;
+            hv.y -= cc[i].x * vv[i].y + cc[i].y * vv[i].x;
+        }
+        st2(qs, p, make_double2(qv.x * ib, qv.y * ib));
+        const double2 vj = stored(qs, make_double2(qv.x * ib, qv.y * ib));
+        hv.x -= cc[NV].x * vj.x - cc[NV].y * vj.y;
+        hv.y -= cc[NV].x * vj.y + cc[NV].y * vj.x;
+        double2 wp = make_double2(hv.x * ib - al * vj.x, hv.y * ib - al * vj.y);
+        if (NV > 0) {
+            wp.x -= bm * vv[NV - 1].x;
+            wp.y -= bm * vv[NV - 1].y;
+        }
+        st2(qn, p, wp);
+        const double2 ws = stored(qn, wp);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], ws);
+        cdot_acc(acc[NV], vj, ws);
+        acc[NV + 1].x = fma(ws.x, ws.x, fma(ws.y, ws.y, acc[NV + 1].x));
+    }
+    block_reduce_store<NV + 2>(acc, partial);
+}
+
+// v_j = (q_j - sum_{i<j} h_i v_i) / beta_{j-1} in slot j: the last vector of a
+// step that ran to its full order (no later sweep corrects it).
+template <class C, int NV>
+__global__ __launch_bounds__(TB) void k_lanczos_fix(C *Vb, int64_t ld, int64_t n, const KState *ks, int j)
+{
+    if (j >= ks->meff) return;
+    double2 hq[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hq[i] = ks->h2[i * MAXM + (j - 1)];
+    const double ib = ks->inv_b;
+    C *qs = Vb + (int64_t)j * ld;
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 qv = ld2(qs, p);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double2 v = ld2(Vb, (int64_t)i * ld + p);
+            qv.x -= hq[i].x * v.x - hq[i].y * v.y;
+            qv.y -= hq[i].x * v.y + hq[i].y * v.x;
+        }
+        st2(qs, p, make_double2(qv.x * ib, qv.y * ib));
     }
 }
 
@@ -2032,6 +2153,43 @@ void cgs_update_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, dou
 #undef CALL
 }
 template <class C>
+void lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, unsigned *counter, KState *ks, int j,
+                   int m, hipStream_t s)
+{
+#define CALL(NV)                                                                                                    \
+    hipLaunchKernelGGL((k_lanczos_sweep<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, z, n, partial, counter, \
+                       ks, j);                                                                                   \
+    hipLaunchKernelGGL(k_finalize<NV + 2>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, (int)RED_BETA, m, 0, \
+                       NV + 2, 0.0, 0.0)
+    switch (j) {
+    case 0: CALL(0); break;
+    case 1: CALL(1); break;
+    case 2: CALL(2); break;
+    case 3: CALL(3); break;
+    case 4: CALL(4); break;
+    case 5: CALL(5); break;
+    case 6: CALL(6); break;
+    case 7: CALL(7); break;
+    case 8: CALL(8); break;
+    case 9: CALL(9); break;
+    case 10: CALL(10); break;
+    case 11: CALL(11); break;
+    case 12: CALL(12); break;
+    case 13: CALL(13); break;
+    case 14: CALL(14); break;
+    default: break;
+    }
+#undef CALL
+}
+template <class C>
+void lanczos_fix(C *Vb, int64_t ld, int64_t n, const KState *ks, int j, hipStream_t s)
+{
+    unsigned b = red_blocks(n) * 4;
+#define CALL(NV) hipLaunchKernelGGL((k_lanczos_fix<C, NV>), dim3(b), dim3(TB), 0, s, Vb, ld, n, ks, j)
+    PPQ_NV_SWITCH(j, CALL)
+#undef CALL
+}
+template <class C>
 void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,
                       hipStream_t s)
 {
@@ -2063,6 +2221,9 @@ void lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, cons
                                      int, bool, hipStream_t);                                                   \
     template void cgs_update_scale<C>(const C *, int64_t, int, const C *, C *, int64_t, const KState *, int,      \
                                       hipStream_t);                                                             \
+    template void lanczos_sweep<C>(C *, int64_t, const C *, int64_t, double2 *, unsigned *, KState *, int, int,   \
+                                   hipStream_t);                                                                \
+    template void lanczos_fix<C>(C *, int64_t, int64_t, const KState *, int, hipStream_t);                        \
     template void normalise_from_master<C>(const double2 *, int64_t, KState *, C *, hipStream_t);                 \
     template void lincomb<C>(const C *, int64_t, const double2 *, int64_t, const KState *, double2 *, hipStream_t);
 PPQ_INST(double2)
