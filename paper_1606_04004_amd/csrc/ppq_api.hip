@@ -1629,7 +1629,11 @@ void mark(ppq_ctx *c, int phase)
 // tol > 0: the order is chosen per step by the error estimate (the adjoint's
 // recorded steps use the full order)
 template <class C>
-void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, double dt = 0.0, double tol = 0.0)
+// fix_last: leave every basis vector corrected in memory (the adjoint reads the
+// basis); otherwise a full-order step's last vector stays provisional and
+// lanczos_coef folds its correction into the coefficients.
+void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, double dt = 0.0, double tol = 0.0,
+                  bool fix_last = true)
 {
     hipStream_t s = c->stream;
     const int64_t n = c->nact;
@@ -1655,7 +1659,7 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, doub
             if (fused) finalize_dot(c->partial, fused, ks, j, m, RED_DELAY, s);
             else cgs_dots<C>(qj, ld, 1, w, n, c->partial, c->counter, ks, j, m, j, s, RED_DELAY);
             if (j == m - 1) {
-                if (j > 0) lanczos_fix<C>(Vb, ld, n, ks, j, s);
+                if (j > 0 && fix_last) lanczos_fix<C>(Vb, ld, n, ks, j, s);
                 break;
             }
             lanczos_sweep<C>(Vb, ld, w, n, c->partial, c->counter, ks, j, m, s);
@@ -1680,8 +1684,9 @@ void step_impl(ppq_ctx *c, double dt, int m, double tol)
 {
     mark(c, PPQ_PHASE_KRYLOV);
     C *Vb = (C *)c->Vk;
-    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m, dt, tol);
+    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m, dt, tol, !c->hermitian);
     krylov_expv(c->ks, m, dt, c->hermitian ? 1 : 0, c->stream);
+    if (c->hermitian) lanczos_coef(c->ks, m, c->stream);
     lincomb<C>(Vb, c->cap, c->psi[c->cur], c->nact, c->ks, c->psi_tmp, c->stream);
     std::swap(c->psi[c->cur], c->psi_tmp);
 }

@@ -341,6 +341,10 @@ void lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, u
                    int m, hipStream_t s);
 template <class C>
 void lanczos_fix(C *Vb, int64_t ld, int64_t n, const KState *ks, int j, hipStream_t s);
+// after the exponential: fold the last vector's pending correction into the
+// coefficients y of a step that ran to its full order m (for a recombination
+// that reads the provisional last vector)
+void lanczos_coef(KState *ks, int m, hipStream_t s);
 template <class C>
 void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,
                       hipStream_t s);

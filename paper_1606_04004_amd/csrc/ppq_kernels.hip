@@ -1257,6 +1257,24 @@ __global__ __launch_bounds__(TB) void k_lanczos_fix(C *Vb, int64_t ld, int64_t n
     }
 }
 
+// A step that ran to its full order m leaves its last vector provisional:
+// v_L = (q_L - sum_{i<L} h_i v_i) / beta_{L-1}, L = m - 1.  The propagated
+// vector sum_k y_k v_k is then sum_{k<L} (y_k - y_L h_k / beta_{L-1}) v_k +
+// (y_L / beta_{L-1}) q_L: the coefficients absorb the correction.
+__global__ void k_lanczos_coef(KState *ks, int m)
+{
+    if (threadIdx.x != 0 || ks->meff != m || m < 2) return;
+    const int L = m - 1;
+    const double2 yl = ks->y[L];
+    const double ib = ks->inv_b;
+    for (int k = 0; k < L; ++k) {
+        const double2 h = ks->h2[k * MAXM + (L - 1)];
+        ks->y[k].x -= ib * (yl.x * h.x - yl.y * h.y);
+        ks->y[k].y -= ib * (yl.x * h.y + yl.y * h.x);
+    }
+    ks->y[L] = make_double2(yl.x * ib, yl.y * ib);
+}
+
 template <class C>
 __global__ void k_normalise(const double2 *psi, int64_t n, const KState *ks, C *v0)
 {
@@ -2180,6 +2198,10 @@ void lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, u
     default: break;
     }
 #undef CALL
+}
+void lanczos_coef(KState *ks, int m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lanczos_coef, dim3(1), dim3(64), 0, s, ks, m);
 }
 template <class C>
 void lanczos_fix(C *Vb, int64_t ld, int64_t n, const KState *ks, int j, hipStream_t s)
