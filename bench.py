@@ -156,9 +156,6 @@ def secondary(stream, steps, warmup, adjoint_steps):
         g = ppq.Propagator(cd, precision=prec, device=0, stream=stream)
         g.reserve(min(16_000_000, int(np.prod(cd["n"]))))  # as for the headline
         g.init_state()
-        ms_h = g.time_apply(100)
-        na = g.active_count()
-        nf = g.fiber_counts()
         # algorithmic flops of one product: a complex factor application costs
         # 8 L flops per point for fibers of mean length L = |A| / nf_k; one per
         # dimension for the single-dimension factors and two per pair term
@@ -167,14 +164,26 @@ def secondary(stream, steps, warmup, adjoint_steps):
             dims = sorted(set(f["dim"] for f in t["factors"]))
             if len(dims) > 1:
                 apps += dims
-        alg = float(sum(8.0 * na * (na / nf[k]) for k in apps))
+
+        def product_flops():
+            n_act, nf = g.active_count(), g.fiber_counts()
+            return n_act, float(sum(8.0 * n_act * (n_act / nf[k]) for k in apps))
+
+        ms_h = g.time_apply(100)
+        na, alg = product_flops()
         rate, ms, _ = timed_steps(g, steps, warmup)
+        # the same product on the set the timed steps grew to (near the full grid)
+        ms_g = g.time_apply(20)
+        na_g, alg_g = product_flops()
         out[f"pvb4d_{tag}"] = {"active_points": int(na), "hpsi_ms": ms_h, "updates_per_s": rate, "ms_per_step": ms,
                                "factor_applications": len(apps),
                                "algorithmic_gflop_per_product": alg / 1e9,
                                "algorithmic_tflops": alg / (ms_h * 1e-3) / 1e12,
+                               "grown_active_points": int(na_g), "grown_hpsi_ms": ms_g,
+                               "grown_algorithmic_tflops": alg_g / (ms_g * 1e-3) / 1e12,
                                "from": "initial set of the 4D phase-space lattice card (48^4, 6x8 lattice per "
-                                       "dimension), complex factors on the matrix cores"}
+                                       "dimension), complex factors on the matrix cores; grown_*: the set after "
+                                       "the timed steps"}
         del g
     cd = dict(card("pvb4d"), basis="pw")
     for prec, tag in ((ppq.PPQ_FP64, "fp64"), (ppq.PPQ_FP32, "fp32")):
