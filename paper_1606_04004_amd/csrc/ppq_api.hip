@@ -1666,16 +1666,17 @@ void krylov_build(ppq_ctx *c, const double2 *src, C *Vb, KState *ks, int m, doub
         }
         return;
     }
+    // Arnoldi with the same delayed second pass: H is applied to the
+    // provisional q_j, the first-pass column of H v_j follows from the Arnoldi
+    // relation, and one sweep corrects v_j and forms q_{j+1}
     for (int j = 0; j < m; ++j) {
-        const C *vj = Vb + (int64_t)j * ld;
+        const C *qj = Vb + (int64_t)j * ld;
         mark(c, PPQ_PHASE_HPSI);
-        apply_internal(c, vj, w, meff, j);
+        apply_internal(c, qj, w, meff, j);
         mark(c, PPQ_PHASE_KRYLOV);
         const bool last = (j == m - 1);
-        cgs_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, 0, s);
-        cgs_update_dots<C>(Vb, ld, j + 1, w, n, c->partial, c->counter, ks, j, m, !last, s);
-        if (last) break;
-        cgs_update_scale<C>(Vb, ld, j + 1, w, Vb + (int64_t)(j + 1) * ld, n, ks, j, s);
+        arnoldi_step<C>(Vb, ld, w, n, c->partial, c->counter, ks, j, m, last, s);
+        if (last && j > 0 && fix_last) lanczos_fix<C>(Vb, ld, n, ks, j, s);
     }
 }
 
@@ -1684,9 +1685,9 @@ void step_impl(ppq_ctx *c, double dt, int m, double tol)
 {
     mark(c, PPQ_PHASE_KRYLOV);
     C *Vb = (C *)c->Vk;
-    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m, dt, tol, !c->hermitian);
+    krylov_build<C>(c, c->psi[c->cur], Vb, c->ks, m, dt, tol, false);
     krylov_expv(c->ks, m, dt, c->hermitian ? 1 : 0, c->stream);
-    if (c->hermitian) lanczos_coef(c->ks, m, c->stream);
+    lanczos_coef(c->ks, m, c->stream);
     lincomb<C>(Vb, c->cap, c->psi[c->cur], c->nact, c->ks, c->psi_tmp, c->stream);
     std::swap(c->psi[c->cur], c->psi_tmp);
 }

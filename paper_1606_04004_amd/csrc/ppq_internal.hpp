@@ -53,10 +53,8 @@ struct KState {
     double2 h1[MAXM * MAXM];   // Hessenberg, first Gram-Schmidt pass  [i*MAXM + j]
     double2 h2[MAXM * MAXM];   // second pass
     double2 y[MAXM];           // coefficients of the propagated vector
-    double2 cc[MAXM];          // delayed correction (Hermitian): H v_j = (H q_j - sum_k cc_k v_k) / beta_{j-1}
+    double2 cc[MAXM];          // delayed correction: H v_j = (H q_j - sum_k cc_k v_k) / beta_{j-1}
     double inv_b;              // 1 / beta_{j-1} for the provisional q_j
-    double inv_beta;           // 1/beta of the last completed iteration
-    double norm2_scratch;
     double est;                // error estimate of the current order: n0 dt^k/k! prod beta_i
     double kdt, ktol;          // step and order tolerance of this step (ktol 0: full order)
     int meff;                  // Krylov dimension actually built
@@ -198,7 +196,7 @@ int hpsi_acc_f32(const FiberPass &fp, const float *T, const float2 *x, float2 *y
                  hipStream_t s, double2 *dotp = nullptr);
 // blocks of a fused <x|y> the shared partial buffer holds (RED_BLOCKS * PSTRIDE_H)
 constexpr int64_t DOT_BLOCKS_MAX = (int64_t)RED_BLOCKS * PSTRIDE_H;
-// Krylov reduction of nb per-block partials of <v_j|w> (mode RED_H1 or RED_H1L)
+// Krylov reduction of nb per-block partials of one value (mode RED_H1 or RED_DELAY)
 void finalize_dot(const double2 *partial, int nb, KState *ks, int j, int m, int mode, hipStream_t s);
 // matrix-core forms (v_mfma_*_16x16x4); T64 / H64 are h zero-padded to 64 x 64
 void hpsi_mfma_f32(const FiberPass &fp, const float *T64, const float2 *x, const float *V, float2 *y, bool first,
@@ -315,23 +313,22 @@ void diag_scale(const uint32_t *keys, const C *x, int64_t n, const GridDesc &g, 
                 unsigned use, double2 w, C *y, bool acc, const int *skip_if, int skip_j, hipStream_t s);
 
 // Krylov vector kernels. V_i = Vb + i*ld (elements); C is double2 or float2.
-// Reductions end in the last block to finish, which sums the per-block
-// partials in a fixed order (run-to-run deterministic) and updates KState.
-// RED_H1L: Hermitian first pass, where only <v_j|w> is reduced; the other
-// first-pass coefficients are those of the three-term recurrence (beta_{j-1}
-// for v_{j-1}, zero below), and the second pass removes what they leave.
+// Reductions write per-block partials; one finalising block sums them in a
+// fixed order (run-to-run deterministic) and updates KState.
+// RED_H1: first-pass dots into h1[.][j] (alpha_j from the diagonal one).
+// RED_BETA: second-pass dots into h2[.][j], then beta_j from the last value,
+// |q_{j+1}|^2, less their squares, and the order's error estimate.
 // RED_DELAY: Hermitian step with delayed correction, r[0] = <q_j|H q_j> of the
 // provisional vector; sets alpha_j, cc and inv_b (see k_lanczos_sweep).
-enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_H2 = 2, RED_BETA = 3, RED_H1L = 4, RED_DELAY = 5 };
+// RED_ADELAY: the same for an Arnoldi step, r[i] = <v_i|H q_j> (i < j) and
+// r[j] = <q_j|H q_j>; sets the first-pass column h1[.][j], cc and inv_b.
+enum ReduceMode { RED_NORM0 = 0, RED_H1 = 1, RED_BETA = 2, RED_DELAY = 3, RED_ADELAY = 4 };
 template <class C>
 void norm0(const double2 *psi, int64_t n, double2 *partial, unsigned *counter, KState *ks, int m, double dt,
            double tol, hipStream_t s);
 template <class C>
 void cgs_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter, KState *ks,
               int j, int m, int ioff, hipStream_t s, int mode = RED_H1);
-template <class C>
-void cgs_update_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter,
-                     KState *ks, int j, int m, bool with_norm, hipStream_t s);
 // Hermitian Lanczos step j with the second Gram-Schmidt pass delayed by one
 // step (see k_lanczos_sweep): corrects v_j in its slot, writes the provisional
 // q_{j+1} to slot j+1 and reduces <v_i|q_{j+1}> (i <= j) and |q_{j+1}|^2
@@ -341,13 +338,17 @@ void lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, u
                    int m, hipStream_t s);
 template <class C>
 void lanczos_fix(C *Vb, int64_t ld, int64_t n, const KState *ks, int j, hipStream_t s);
+// Arnoldi step j with the second pass delayed: the dots <v_i|z> (i < j) and
+// <q_j|z> of z = H q_j (RED_ADELAY), then one sweep that corrects v_j, forms
+// q_{j+1} = H v_j - sum_{i<=j} h1_ij v_i and reduces its second-pass dots and
+// norm (RED_BETA); `last`: the first reduction only (the step's last column)
+template <class C>
+void arnoldi_step(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, unsigned *counter, KState *ks, int j,
+                  int m, bool last, hipStream_t s);
 // after the exponential: fold the last vector's pending correction into the
 // coefficients y of a step that ran to its full order m (for a recombination
 // that reads the provisional last vector)
 void lanczos_coef(KState *ks, int m, hipStream_t s);
-template <class C>
-void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,
-                      hipStream_t s);
 template <class C>
 void normalise_from_master(const double2 *psi, int64_t n, KState *ks, C *v0, hipStream_t s);
 template <class C>

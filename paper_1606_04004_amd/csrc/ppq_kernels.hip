@@ -1001,7 +1001,7 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         ks->est = ks->n0;
         ks->kdt = fabs(dt);  // the estimate is a magnitude: |dt|^k
         ks->ktol = tol;
-    } else if (mode == RED_H1 || mode == RED_H1L) {
+    } else if (mode == RED_H1) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             if (i < nvals) {
@@ -1009,9 +1009,6 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
                 if (i + ioff == j) ks->alpha[j] = r[i].x;
             }
         }
-        if (mode == RED_H1L)
-            for (int i = 0; i < j; ++i)
-                ks->h1[i * MAXM + j] = make_double2(i == j - 1 ? ks->beta[j - 1] : 0.0, 0.0);
     } else if (mode == RED_DELAY) {
         // The provisional q_j = beta_{j-1} v_j + sum_{i<j} h_i v_i with
         // h_i = h2[i][j-1] (the second pass's coefficients, not yet applied).
@@ -1052,8 +1049,62 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
             ks->alpha[j] = (mu.x - 2.0 * s1 + s2) / (b * b);
             ks->inv_b = 1.0 / b;
         }
-    } else {  // RED_H2 (+ beta from |w'|^2 - sum |h2_i|^2 when RED_BETA)
-        const int nh = (mode == RED_BETA) ? nvals - 1 : nvals;
+    } else if (mode == RED_ADELAY) {
+        // Arnoldi: q_j = beta_{j-1} v_j + sum_{i<j} h_i v_i (h_i = h2[i][j-1]);
+        // H v_i = sum_{k<=i+1} H_ki v_k with H_ki = h1 + h2 (k <= i), beta_i (k = i+1):
+        //   cc_k = sum_{i<j} H_ki h_i, so H v_j = (z - sum_{k<=j} cc_k v_k) / beta_{j-1}
+        //   <v_j|z> = (<q_j|z> - sum_{i<j} conj(h_i) <v_i|z>) / beta_{j-1}
+        //   h1_ij = <v_i|H v_j> = (<v_i|z> - cc_i) / beta_{j-1}   (i <= j)
+        // column j's second-pass terms come from this step's sweep (RED_BETA);
+        // a step's last column keeps only its first pass
+        for (int k = 0; k < MAXM; ++k) {
+            ks->cc[k] = make_double2(0.0, 0.0);
+            ks->h2[k * MAXM + j] = make_double2(0.0, 0.0);
+        }
+        if (j == 0) {
+            ks->h1[0] = r[0];
+            ks->alpha[0] = r[0].x;
+            ks->inv_b = 1.0;
+        } else {
+            const double b = ks->beta[j - 1], ib = 1.0 / b;
+            const double2 *hh = ks->h2 + (j - 1);
+            for (int i = 0; i < j; ++i) {
+                const double2 hi = hh[i * MAXM];
+                for (int k = 0; k <= i; ++k) {
+                    const double2 a1 = ks->h1[k * MAXM + i], a2 = ks->h2[k * MAXM + i];
+                    const double2 hk = make_double2(a1.x + a2.x, a1.y + a2.y);
+                    ks->cc[k].x += hk.x * hi.x - hk.y * hi.y;
+                    ks->cc[k].y += hk.x * hi.y + hk.y * hi.x;
+                }
+                ks->cc[i + 1].x += ks->beta[i] * hi.x;
+                ks->cc[i + 1].y += ks->beta[i] * hi.y;
+            }
+            // <v_j|z>, r[i] = <v_i|z> for i < j, r[j] = <q_j|z> (loops to NV with a predicate)
+            double2 vz = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                if (i < j) {
+                    const double2 hi = hh[i * MAXM];
+                    vz.x += hi.x * r[i].x + hi.y * r[i].y;  // conj(h_i) r_i
+                    vz.y += hi.x * r[i].y - hi.y * r[i].x;
+                } else if (i == j) {
+                    vz = make_double2((r[i].x - vz.x) * ib, (r[i].y - vz.y) * ib);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                if (i < j) {
+                    ks->h1[i * MAXM + j] = make_double2((r[i].x - ks->cc[i].x) * ib, (r[i].y - ks->cc[i].y) * ib);
+                } else if (i == j) {
+                    const double2 g = make_double2((vz.x - ks->cc[j].x) * ib, (vz.y - ks->cc[j].y) * ib);
+                    ks->h1[j * MAXM + j] = g;
+                    ks->alpha[j] = g.x;
+                }
+            }
+            ks->inv_b = ib;
+        }
+    } else {  // RED_BETA: h2[.][j] and beta_j from |q_{j+1}|^2 - sum |h2_i|^2
+        const int nh = nvals - 1;
         double hh = 0.0, last = 0.0;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
@@ -1064,23 +1115,19 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
                 last = r[i].x;
             }
         }
-        if (mode == RED_BETA) {
-            double b2 = last - hh;
-            double b = sqrt(b2 > 0.0 ? b2 : 0.0);
-            ks->beta[j] = b;
-            if (j < m - 1) {
-                if (b < 1e-13) {
-                    ks->meff = j + 1;
-                    ks->inv_beta = 0.0;
-                } else {
-                    ks->inv_beta = 1.0 / b;
-                    // Park and Light's estimate of the order-(j+1) step: the
-                    // first Taylor term the Krylov space leaves out; with a
-                    // tolerance, the step stops at the first order within it
-                    const double est = ks->est * ks->kdt * b / (double)(j + 1);
-                    ks->est = est;
-                    if (ks->ktol > 0.0 && est <= ks->ktol) ks->meff = j + 1;
-                }
+        double b2 = last - hh;
+        double b = sqrt(b2 > 0.0 ? b2 : 0.0);
+        ks->beta[j] = b;
+        if (j < m - 1) {
+            if (b < 1e-13) {
+                ks->meff = j + 1;
+            } else {
+                // Park and Light's estimate of the order-(j+1) step: the
+                // first Taylor term the Krylov space leaves out; with a
+                // tolerance, the step stops at the first order within it
+                const double est = ks->est * ks->kdt * b / (double)(j + 1);
+                ks->est = est;
+                if (ks->ktol > 0.0 && est <= ks->ktol) ks->meff = j + 1;
             }
         }
     }
@@ -1112,68 +1159,6 @@ __global__ __launch_bounds__(TB) void k_cgs_dots(const C *Vb, int64_t ld, const 
         for (int i = 0; i < NV; ++i) cdot_acc(acc[i], ld2(Vb, (int64_t)i * ld + p), wv);
     }
     block_reduce_store<NV>(acc, partial);
-}
-
-// w' = w - sum_i h1_i v_i formed on the fly (not stored); h2_i = <v_i|w'>;
-// with_norm: also |w'|^2 and beta
-template <class C, int NV>
-__global__ __launch_bounds__(TB) void k_cgs_update_dots(const C *Vb, int64_t ld, const C *w, int64_t n,
-                                                        double2 *partial, unsigned *counter, KState *ks, int j, int m,
-                                                        int with_norm)
-{
-    if (j >= ks->meff) return;
-    double2 hc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) hc[i] = ks->h1[i * MAXM + j];
-    double2 acc[NV + 1];
-#pragma unroll
-    for (int i = 0; i <= NV; ++i) acc[i] = make_double2(0.0, 0.0);
-    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
-        double2 wv = ld2(w, p);
-        double2 vv[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            vv[i] = ld2(Vb, (int64_t)i * ld + p);
-            wv.x -= hc[i].x * vv[i].x - hc[i].y * vv[i].y;
-            wv.y -= hc[i].x * vv[i].y + hc[i].y * vv[i].x;
-        }
-#pragma unroll
-        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], wv);
-        acc[NV].x = fma(wv.x, wv.x, fma(wv.y, wv.y, acc[NV].x));
-    }
-    block_reduce_store<NV + 1>(acc, partial);
-}
-
-// out = (w - sum_i (h1_i + h2_i) v_i) / beta: the first pass's update, which
-// k_cgs_update_dots formed without storing, and the second's
-template <class C, int NV>
-__global__ __launch_bounds__(TB) void k_cgs_update_scale(const C *Vb, int64_t ld, const C *w, C *out, int64_t n,
-                                                         const KState *ks, int j)
-{
-    if (j + 1 >= ks->meff) return;
-    double2 h1[NV], h2[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        h1[i] = ks->h1[i * MAXM + j];
-        h2[i] = ks->h2[i * MAXM + j];
-    }
-    const double s = ks->inv_beta;
-    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
-        double2 wv = ld2(w, p);
-        double2 vv[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            vv[i] = ld2(Vb, (int64_t)i * ld + p);
-            wv.x -= h1[i].x * vv[i].x - h1[i].y * vv[i].y;
-            wv.y -= h1[i].x * vv[i].y + h1[i].y * vv[i].x;
-        }
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            wv.x -= h2[i].x * vv[i].x - h2[i].y * vv[i].y;
-            wv.y -= h2[i].x * vv[i].y + h2[i].y * vv[i].x;
-        }
-        st2(out, p, make_double2(wv.x * s, wv.y * s));
-    }
 }
 
 // Hermitian Lanczos step j with the second Gram-Schmidt pass of each vector
@@ -1224,6 +1209,85 @@ __global__ __launch_bounds__(TB) void k_lanczos_sweep(C *Vb, int64_t ld, const C
             wp.x -= bm * vv[NV - 1].x;
             wp.y -= bm * vv[NV - 1].y;
         }
+        st2(qn, p, wp);
+        const double2 ws = stored(qn, wp);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], vv[i], ws);
+        cdot_acc(acc[NV], vj, ws);
+        acc[NV + 1].x = fma(ws.x, ws.x, fma(ws.y, ws.y, acc[NV + 1].x));
+    }
+    block_reduce_store<NV + 2>(acc, partial);
+}
+
+// Arnoldi step j, first reduction: <v_i|z> for i < j and <q_j|z> (slot j
+// holds the provisional q_j, z = H q_j).
+template <class C, int NV>
+__global__ __launch_bounds__(TB) void k_arnoldi_dots(const C *Vb, int64_t ld, const C *z, int64_t n,
+                                                     double2 *partial, unsigned *counter, KState *ks, int j)
+{
+    if (j >= ks->meff) return;
+    const C *qs = Vb + (int64_t)j * ld;
+    double2 acc[NV + 1];
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        const double2 zv = ld2(z, p);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], ld2(Vb, (int64_t)i * ld + p), zv);
+        cdot_acc(acc[NV], ld2(qs, p), zv);
+    }
+    block_reduce_store<NV + 1>(acc, partial);
+}
+
+// Arnoldi step j, the sweep: with h_i = h2[i][j-1], cc, inv_b and the
+// first-pass column h1[.][j] from RED_ADELAY,
+//   v_j     = (q_j - sum_{i<j} h_i v_i) / beta_{j-1}           -> slot j
+//   H v_j   = (z - sum_{k<=j} cc_k v_k) / beta_{j-1}
+//   q_{j+1} = H v_j - sum_{i<=j} h1_ij v_i                       -> slot j+1
+// and the partial sums of <v_i|q_{j+1}> (i <= j) and |q_{j+1}|^2.
+template <class C, int NV>
+__global__ __launch_bounds__(TB) void k_arnoldi_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial,
+                                                      unsigned *counter, KState *ks, int j)
+{
+    if (j >= ks->meff) return;
+    constexpr int NH = NV > 0 ? NV : 1;
+    double2 hq[NH], cc[NV + 1], g1[NV + 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hq[i] = ks->h2[i * MAXM + (j - 1)];
+#pragma unroll
+    for (int k = 0; k <= NV; ++k) {
+        cc[k] = ks->cc[k];
+        g1[k] = ks->h1[k * MAXM + j];
+    }
+    const double ib = ks->inv_b;
+    C *qs = Vb + (int64_t)j * ld;
+    C *qn = Vb + (int64_t)(j + 1) * ld;
+    double2 acc[NV + 2];
+#pragma unroll
+    for (int i = 0; i < NV + 2; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
+        double2 qv = ld2(qs, p), hv = ld2(z, p);
+        double2 vv[NH];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            vv[i] = ld2(Vb, (int64_t)i * ld + p);
+            qv.x -= hq[i].x * vv[i].x - hq[i].y * vv[i].y;
+            qv.y -= hq[i].x * vv[i].y + hq[i].y * vv[i].x;
+            hv.x -= cc[i].x * vv[i].x - cc[i].y * vv[i].y;
+            hv.y -= cc[i].x * vv[i].y + cc[i].y * vv[i].x;
+        }
+        st2(qs, p, make_double2(qv.x * ib, qv.y * ib));
+        const double2 vj = stored(qs, make_double2(qv.x * ib, qv.y * ib));
+        hv.x -= cc[NV].x * vj.x - cc[NV].y * vj.y;
+        hv.y -= cc[NV].x * vj.y + cc[NV].y * vj.x;
+        double2 wp = make_double2(hv.x * ib, hv.y * ib);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            wp.x -= g1[i].x * vv[i].x - g1[i].y * vv[i].y;
+            wp.y -= g1[i].x * vv[i].y + g1[i].y * vv[i].x;
+        }
+        wp.x -= g1[NV].x * vj.x - g1[NV].y * vj.y;
+        wp.y -= g1[NV].x * vj.y + g1[NV].y * vj.x;
         st2(qn, p, wp);
         const double2 ws = stored(qn, wp);
 #pragma unroll
@@ -2159,18 +2223,6 @@ void finalize_dot(const double2 *partial, int nb, KState *ks, int j, int m, int 
     hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(TB), 0, s, partial, nb, ks, j, mode, m, j, 1, 0.0, 0.0);
 }
 template <class C>
-void cgs_update_dots(const C *Vb, int64_t ld, int nv, const C *w, int64_t n, double2 *partial, unsigned *counter,
-                     KState *ks, int j, int m, bool with_norm, hipStream_t s)
-{
-#define CALL(NV)                                                                                                    \
-    hipLaunchKernelGGL((k_cgs_update_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, w, n, partial, counter, \
-                       ks, j, m, with_norm ? 1 : 0);                                                            \
-    hipLaunchKernelGGL(k_finalize<NV + 1>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j,                  \
-                       with_norm ? (int)RED_BETA : (int)RED_H2, m, 0, with_norm ? NV + 1 : NV, 0.0, 0.0)
-    PPQ_NV_SWITCH(nv, CALL)
-#undef CALL
-}
-template <class C>
 void lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, unsigned *counter, KState *ks, int j,
                    int m, hipStream_t s)
 {
@@ -2199,6 +2251,42 @@ void lanczos_sweep(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, u
     }
 #undef CALL
 }
+template <class C>
+void arnoldi_step(C *Vb, int64_t ld, const C *z, int64_t n, double2 *partial, unsigned *counter, KState *ks, int j,
+                  int m, bool last, hipStream_t s)
+{
+#define CALL(NV)                                                                                                   \
+    hipLaunchKernelGGL((k_arnoldi_dots<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, z, n, partial, counter, \
+                       ks, j);                                                                                  \
+    hipLaunchKernelGGL(k_finalize<NV + 1>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, (int)RED_ADELAY, m, \
+                       0, NV + 1, 0.0, 0.0);                                                                    \
+    if (!last) {                                                                                               \
+        hipLaunchKernelGGL((k_arnoldi_sweep<C, NV>), dim3(RED_BLOCKS), dim3(TB), 0, s, Vb, ld, z, n, partial,   \
+                           counter, ks, j);                                                                     \
+        hipLaunchKernelGGL(k_finalize<NV + 2>, dim3(1), dim3(TB), 0, s, partial, RED_BLOCKS, ks, j, (int)RED_BETA, \
+                           m, 0, NV + 2, 0.0, 0.0);                                                            \
+    }
+    switch (j) {
+    case 0: CALL(0); break;
+    case 1: CALL(1); break;
+    case 2: CALL(2); break;
+    case 3: CALL(3); break;
+    case 4: CALL(4); break;
+    case 5: CALL(5); break;
+    case 6: CALL(6); break;
+    case 7: CALL(7); break;
+    case 8: CALL(8); break;
+    case 9: CALL(9); break;
+    case 10: CALL(10); break;
+    case 11: CALL(11); break;
+    case 12: CALL(12); break;
+    case 13: CALL(13); break;
+    case 14: CALL(14); break;
+    case 15: CALL(15); break;
+    default: break;
+    }
+#undef CALL
+}
 void lanczos_coef(KState *ks, int m, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lanczos_coef, dim3(1), dim3(64), 0, s, ks, m);
@@ -2209,15 +2297,6 @@ void lanczos_fix(C *Vb, int64_t ld, int64_t n, const KState *ks, int j, hipStrea
     unsigned b = red_blocks(n) * 4;
 #define CALL(NV) hipLaunchKernelGGL((k_lanczos_fix<C, NV>), dim3(b), dim3(TB), 0, s, Vb, ld, n, ks, j)
     PPQ_NV_SWITCH(j, CALL)
-#undef CALL
-}
-template <class C>
-void cgs_update_scale(const C *Vb, int64_t ld, int nv, const C *w, C *out, int64_t n, const KState *ks, int j,
-                      hipStream_t s)
-{
-    unsigned b = red_blocks(n) * 4;
-#define CALL(NV) hipLaunchKernelGGL((k_cgs_update_scale<C, NV>), dim3(b), dim3(TB), 0, s, Vb, ld, w, out, n, ks, j)
-    PPQ_NV_SWITCH(nv, CALL)
 #undef CALL
 }
 template <class C>
@@ -2239,13 +2318,11 @@ void lincomb(const C *Vb, int64_t ld, const double2 *psi_master, int64_t n, cons
                            hipStream_t);                                                                         \
     template void cgs_dots<C>(const C *, int64_t, int, const C *, int64_t, double2 *, unsigned *, KState *, int,  \
                               int, int, hipStream_t, int);                                                      \
-    template void cgs_update_dots<C>(const C *, int64_t, int, const C *, int64_t, double2 *, unsigned *, KState *, int, \
-                                     int, bool, hipStream_t);                                                   \
-    template void cgs_update_scale<C>(const C *, int64_t, int, const C *, C *, int64_t, const KState *, int,      \
-                                      hipStream_t);                                                             \
     template void lanczos_sweep<C>(C *, int64_t, const C *, int64_t, double2 *, unsigned *, KState *, int, int,   \
                                    hipStream_t);                                                                \
     template void lanczos_fix<C>(C *, int64_t, int64_t, const KState *, int, hipStream_t);                        \
+    template void arnoldi_step<C>(C *, int64_t, const C *, int64_t, double2 *, unsigned *, KState *, int, int,    \
+                                  bool, hipStream_t);                                                           \
     template void normalise_from_master<C>(const double2 *, int64_t, KState *, C *, hipStream_t);                 \
     template void lincomb<C>(const C *, int64_t, const double2 *, int64_t, const KState *, double2 *, hipStream_t);
 PPQ_INST(double2)
