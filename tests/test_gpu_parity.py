@@ -310,6 +310,54 @@ def test_krylov_space_exhausted(prec, torch):
     assert abs(np.vdot(co, co).real - np.vdot(c5, c5).real) < 1e-12  # unitary on the set
     assert np.max(np.abs(cg - co)) < (1e-12 if prec == 0 else 1e-6)
 
+@pytest.mark.parametrize("m", [1, 2, 3, 16])
+def test_arnoldi_single_step_krylov_orders(m, torch):
+    """One SIL step on a phase-space lattice (non-Hermitian P S^-1 H P, so
+    Arnoldi) at the extreme Krylov orders: m = 1 and 2 reach the first
+    Hessenberg column without and with a correction of the provisional
+    vector, m = 16 the largest order, whose last column keeps its first
+    Gram-Schmidt pass only. Coefficients within 1e-12 of the largest."""
+    cd = lattice_card(eps=1e-4)
+    o = Oracle(cd)
+    o.init_state()
+    keys, c = o.state()
+    g = make(cd, torch)
+    g.set_state(keys, c)
+    say(f"single Arnoldi step small_lattice4d, m = {m}")
+    g.step(dt=0.05, m=m)
+    o.sil_step(dt=0.05, m=m)
+    _, cg = g.state()
+    _, co = o.state()
+    assert np.max(np.abs(cg - co)) < 1e-12 * np.max(np.abs(co))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_arnoldi_space_exhausted(prec, torch):
+    """Five lattice functions hold at most a 5-dimensional Krylov space: at
+    m = 16 the Arnoldi process breaks down (beta below 1e-13) and the space
+    is truncated; the steps agree to 1e-12 (FP64), 1e-6 in the FP32 form,
+    relative to the largest coefficient."""
+    cd = lattice_card(eps=1e-4)
+    o = Oracle(cd)
+    o.init_state()
+    keys, c = o.state()
+    sel = np.argsort(-np.abs(c))[:5]
+    sel.sort()
+    k5, c5 = keys[sel].copy(), c[sel].copy()
+    o.set_state(k5, c5)
+    g = make(cd, torch, precision=prec)
+    g.set_state(k5, c5)
+    say(f"exhausted Arnoldi space: 5 lattice functions, m = 16, precision {prec}")
+    for _ in range(3):
+        g.step(dt=0.05, m=16)
+        o.sil_step(dt=0.05, m=16)
+    kg, cg = g.state()
+    ko, co = o.state()
+    assert np.array_equal(kg, ko)
+    assert np.all(np.isfinite(cg))
+    assert np.max(np.abs(cg - co)) < (1e-12 if prec == 0 else 1e-6) * np.max(np.abs(co))
+
+
 def test_hh2d_trajectory_sets_every_step(torch):
     """Config 1 (2D, 48x48, eps=1e-5): identical active set after every step, 200 steps."""
     cd = card("hh2d")
