@@ -168,7 +168,8 @@ struct ppq_ctx {
     uint64_t *mask[MAXD]{};
     uint8_t *info[MAXD]{};
     int64_t nf[MAXD]{};
-    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides; 4, 5 = block-fused, 6 = plane passes)
+    int hpsi_variant = 2;  // H*psi layout (PPQ_HPSI overrides; 4, 5 = block-fused, 6 = plane passes,
+                           // 7 = the last two dimensions in one pass)
     uint32_t blk_window = BLOCK_WINDOW;  // chunk window of the block layouts (PPQ_BLOCK_WINDOW)
     int blk_unroll = 1;                  // one-lane-per-fiber block pass: row loop unrolled (PPQ_BLOCK_UNROLL)
 
@@ -192,6 +193,11 @@ struct ppq_ctx {
     uint16_t *pldig[MAXD]{};
     uint32_t *pl_poff = nullptr;  // plane starts while the tables are built
     int64_t pl_cap = 0;
+
+    // pair pass: the last two dimensions in one pass (whole planes per task)
+    bool pair_ok = false;          // the operator and grid admit it
+    uint32_t *pair_task = nullptr;  // task starts of the current set
+    int64_t pair_cap = 0;
 
     // <x|y> of a product fused into its last pass (Hermitian Krylov steps)
     bool dot_want = false;  // the caller asks for it
@@ -348,6 +354,8 @@ void free_state_buffers(ppq_ctx *c)
     dfree(c->pl_poff);
     c->pl_cap = 0;
     c->plane_mode = false;
+    dfree(c->pair_task);
+    c->pair_cap = 0;
     c->cap = 0;
 }
 
@@ -1086,6 +1094,21 @@ void ensure_planes(ppq_ctx *c)
     c->pl_cap = nc;
 }
 
+PairPass pair_pass_of(const ppq_ctx *c)
+{
+    const int D = c->g.D;
+    PairPass pp;
+    pp.keys = c->keys[c->cur];
+    pp.pi_a = c->pi[D - 2];
+    pp.tstart = c->pair_task;
+    pp.ntask = (uint32_t)((c->nact + PAIR_WINDOW - 1) / PAIR_WINDOW);
+    pp.n_a = c->g.n[D - 2];
+    pp.n_b = c->g.n[D - 1];
+    pp.lda = c->nb[D - 2];
+    pp.ldb = c->nb[D - 1];
+    return pp;
+}
+
 PlanePass plane_pass_of(const ppq_ctx *c, int i)
 {
     PlanePass pp;
@@ -1114,6 +1137,12 @@ void build_derived(ppq_ctx *c)
         c->plane_ok = ok;
         c->npl = ok ? D / 2 : 0;
         for (int i = 0; i < c->npl; ++i) c->pl_a[i] = D - 2 - 2 * i;
+        // pair pass: the last two dimensions' factors in LDS, their digits in
+        // 6 bits, a plane within a task's span; dimension 0 keeps its own
+        // pass (it carries the fused <x|y>)
+        c->pair_ok = c->hpsi_variant == 7 && !c->any_lattice && !any_long(c) && D >= 3 && c->pairs.empty() &&
+                     c->chains.empty() && c->nb[D - 2] <= 32 && c->nb[D - 1] <= 32 &&
+                     (uint32_t)(c->g.n[D - 2] * c->g.n[D - 1]) <= PAIR_NAB_MAX;
     }
     const int D = c->g.D;
     const int64_t n = c->nact;
@@ -1156,6 +1185,14 @@ void build_derived(ppq_ctx *c)
         }
     }
     if (try_block) build_inner_first(c);
+    if (c->pair_ok && n > 0) {
+        if (c->pair_cap != c->cap) {
+            dfree(c->pair_task);
+            c->pair_task = dalloc<uint32_t>(c->cap / PAIR_WINDOW + 2);
+            c->pair_cap = c->cap;
+        }
+        pair_tasks(keys, n, (uint32_t)(c->g.n[D - 2] * c->g.n[D - 1]), c->pair_task, s);
+    }
     if (c->plane_ok && n > 0) {
         ensure_planes(c);
         for (int i = 0; i < c->npl; ++i)
@@ -1353,21 +1390,26 @@ void apply_single(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int 
             }
             return;
         }
-        if (c->hpsi_variant == 2 || c->hpsi_variant == 4) {
+        if (c->hpsi_variant == 2 || c->hpsi_variant == 4 || c->hpsi_variant == 7) {
             // point-parallel last dimension and lane-per-fiber passes while
             // fibers are short (gather-bound, no dense tile forms); fibers
-            // averaging more than 16 points form dense tiles: matrix cores
+            // averaging more than 16 points form dense tiles: matrix cores.
+            // Layout 7 takes the last two dimensions in one pass while both
+            // have short fibers.
             const int64_t n = c->nact;
             auto longf = [&](int k) { return c->nf[k] > 0 && n > 16 * c->nf[k]; };
+            const bool pair = c->pair_ok && !longf(D - 1) && !longf(D - 2);
             if (c->precision == PPQ_FP64) {
                 const double2 *x = (const double2 *)xv;
                 double2 *y = (double2 *)yv;
-                if (longf(D - 1))
+                if (pair)
+                    hpsi_pair_f64(pair_pass_of(c), c->T64[D - 2], c->T64[D - 1], x, c->V64, y, skip_if, skip_j, s);
+                else if (longf(D - 1))
                     hpsi_mfma_f64(pass_of(c, D - 1), c->T64p[D - 1], x, c->V64, y, true, skip_if, skip_j, s);
                 else
                     hpsi_pt_f64(nullptr, c->info[D - 1], n, c->nb[D - 1], c->T64[D - 1], x, c->V64, y, true,
                                 skip_if, skip_j, s);
-                for (int k = D - 2; k >= 0; --k) {
+                for (int k = pair ? D - 3 : D - 2; k >= 0; --k) {
                     if (longf(k)) hpsi_mfma_f64(pass_of(c, k), c->T64p[k], x, nullptr, y, false, skip_if, skip_j, s);
                     else if (c->nb[k] <= 32)
                         c->dot_nb = hpsi_acc_f64(pass_of(c, k), c->T64[k], x, y, skip_if, skip_j, s,
@@ -1381,8 +1423,11 @@ void apply_single(ppq_ctx *c, const void *xv, void *yv, const int *skip_if, int 
                 // matrix-core pass gathers with coalesced loads: in FP32 it beats
                 // the point-parallel pass even on short fibers (25.6 against
                 // 41.2 us on the 6D snapshot; in FP64 the two are level)
-                hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
-                for (int k = D - 2; k >= 0; --k) {
+                if (pair)
+                    hpsi_pair_f32(pair_pass_of(c), c->T32[D - 2], c->T32[D - 1], x, c->V32, y, skip_if, skip_j, s);
+                else
+                    hpsi_mfma_f32(pass_of(c, D - 1), c->T32p[D - 1], x, c->V32, y, true, skip_if, skip_j, s);
+                for (int k = pair ? D - 3 : D - 2; k >= 0; --k) {
                     if (longf(k)) hpsi_mfma_f32(pass_of(c, k), c->T32p[k], x, nullptr, y, false, skip_if, skip_j, s);
                     else if (c->nb[k] <= 32)
                         c->dot_nb = hpsi_acc_f32(pass_of(c, k), c->T32[k], x, y, skip_if, skip_j, s,
@@ -2243,7 +2288,7 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
     c->precision = precision;
     if (const char *v = std::getenv("PPQ_HPSI")) {
         const int h = std::atoi(v);
-        if (h >= 0 && h <= 6) c->hpsi_variant = h;  // other values keep the default layout
+        if (h >= 0 && h <= 7) c->hpsi_variant = h;  // other values keep the default layout
     }
     if (const char *v = std::getenv("PPQ_BLOCK_UNROLL")) c->blk_unroll = std::atoi(v) != 0;
     if (const char *v = std::getenv("PPQ_BLOCK_WINDOW")) {

@@ -1550,7 +1550,153 @@ void launch_plane(const PlanePass &pp, const R *Ta, const R *Tb, const typename 
                        skip_j);
 }
 
+// ---- pair pass: the last two dimensions in one pass ---------------------------
+// A workgroup takes one task (whole planes, contiguous in the sorted state),
+// stages x in LDS and gives every point one thread, which sums its row run
+// (dimension b = D-1: the points of its plane with its digit a, contiguous) and
+// its column run (dimension a: the points of its plane with its digit b,
+// contiguous in dimension a's rotated order, whose ranks the permutation maps
+// onto the task's own positions) and writes y = V x + both sums once.  The
+// per-dimension layout writes y in both passes and reads it in the second.
+// LDS: x [span], the two factors, then per entry its digits and run flags
+// (dg: d_a << 8 | d_b, bit 15 starts a row run, bit 14 a plane), rank ->
+// position (pil), position -> rank (rpos) and per rank its digit a with bit
+// 15 starting a column run (rinfo).
+constexpr int PRB = 256;
+constexpr int PRU = (int)((PAIR_WINDOW + PAIR_NAB_MAX + PRB - 1) / PRB);  // positions per thread
+constexpr uint16_t PR_ROW = 0x8000u, PR_PLANE = 0x4000u;
+
+template <class R>
+__global__ __launch_bounds__(PRB) void k_hpsi_pair(PairPass pp, const R *__restrict__ Ta, const R *__restrict__ Tb,
+                                                   const typename Cx<R>::T *__restrict__ x, const R *__restrict__ V,
+                                                   typename Cx<R>::T *__restrict__ y, int span, const int *skip_if,
+                                                   int skip_j)
+{
+    using C = typename Cx<R>::T;
+    if (skip_if && skip_j >= *skip_if) return;
+    const uint32_t T0 = pp.tstart[blockIdx.x], T1 = pp.tstart[blockIdx.x + 1];
+    if (T0 >= T1) return;  // the whole workgroup: no barrier is left waiting
+    const int len = (int)(T1 - T0);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lda = pp.lda, ldb = pp.ldb;
+    C *xs = reinterpret_cast<C *>(smem);
+    R *sTa = reinterpret_cast<R *>(xs + span);
+    R *sTb = sTa + lda * lda;
+    uint16_t *dg = reinterpret_cast<uint16_t *>(sTb + ldb * ldb);
+    uint16_t *pil = dg + span;
+    uint16_t *rpos = pil + span;
+    uint16_t *rinfo = rpos + span;
+    const int tid = threadIdx.x;
+    const uint32_t nb = (uint32_t)pp.n_b, na = (uint32_t)pp.n_a;
+    // 1. the task's keys, x, V and rank -> position, all loads at once
+    R vr[PRU];
+#pragma unroll
+    for (int u = 0; u < PRU; ++u) {
+        const int i = tid + u * PRB;
+        vr[u] = 0;
+        if (i < len) {
+            const uint32_t q = T0 + (uint32_t)i;
+            const uint32_t k = pp.keys[q];
+            const uint32_t kp = i > 0 ? pp.keys[q - 1] : 0u;
+            const uint32_t kb = k / nb, db = k - kb * nb, ka = kb / na, da = kb - ka * na;
+            const uint32_t kpb = kp / nb;
+            const bool plane = i == 0 || kpb / na != ka;
+            const bool row = plane || kpb != kb;
+            dg[i] = (uint16_t)((da << 8) | db | (row ? PR_ROW : 0u) | (plane ? PR_PLANE : 0u));
+            xs[i] = x[q];
+            pil[i] = (uint16_t)(pp.pi_a[q] - T0);
+            vr[u] = V[q];
+        }
+    }
+    for (int i = tid; i < lda * lda; i += PRB) sTa[i] = Ta[i];
+    for (int i = tid; i < ldb * ldb; i += PRB) sTb[i] = Tb[i];
+    __syncthreads();
+    // 2. per rank: its position's rank, digit a and column-run start (a plane
+    // starts at the same index in both orders)
+#pragma unroll
+    for (int u = 0; u < PRU; ++u) {
+        const int r = tid + u * PRB;
+        if (r < len) {
+            const int p = pil[r];
+            rpos[p] = (uint16_t)r;
+            const uint16_t dp = dg[p];
+            const bool col = (dg[r] & PR_PLANE) || ((dg[pil[r - 1]] ^ dp) & 0x3fu);
+            rinfo[r] = (uint16_t)(((dp >> 8) & 0x3fu) | (col ? PR_ROW : 0u));
+        }
+    }
+    __syncthreads();
+    // 3. one thread per point: row run, column run, V x; y written once
+#pragma unroll
+    for (int u = 0; u < PRU; ++u) {
+        const int i = tid + u * PRB;
+        if (i >= len) continue;
+        const uint16_t d = dg[i];
+        const R *rb = sTb + (d & 0x3fu) * ldb;
+        R ar = 0, ai = 0;
+        for (int j = i;; --j) {
+            const uint16_t e = dg[j];
+            const R t = rb[e & 0x3fu];
+            const C v = xs[j];
+            ar = fma(t, v.x, ar);
+            ai = fma(t, v.y, ai);
+            if (e & PR_ROW) break;
+        }
+        for (int j = i + 1; j < len; ++j) {
+            const uint16_t e = dg[j];
+            if (e & PR_ROW) break;
+            const R t = rb[e & 0x3fu];
+            const C v = xs[j];
+            ar = fma(t, v.x, ar);
+            ai = fma(t, v.y, ai);
+        }
+        const R *ra = sTa + ((d >> 8) & 0x3fu) * lda;
+        const int r = rpos[i];
+        for (int q = r;; --q) {
+            const uint16_t e = rinfo[q];
+            const R t = ra[e & 0x3fu];
+            const C v = xs[pil[q]];
+            ar = fma(t, v.x, ar);
+            ai = fma(t, v.y, ai);
+            if (e & PR_ROW) break;
+        }
+        for (int q = r + 1; q < len; ++q) {
+            const uint16_t e = rinfo[q];
+            if (e & PR_ROW) break;
+            const R t = ra[e & 0x3fu];
+            const C v = xs[pil[q]];
+            ar = fma(t, v.x, ar);
+            ai = fma(t, v.y, ai);
+        }
+        const C xv = xs[i];
+        y[T0 + i] = Cx<R>::make(fma(vr[u], xv.x, ar), fma(vr[u], xv.y, ai));
+    }
+}
+
+template <class R>
+void launch_pair(const PairPass &pp, const R *Ta, const R *Tb, const typename Cx<R>::T *x, const R *V,
+                 typename Cx<R>::T *y, const int *skip_if, int skip_j, hipStream_t s)
+{
+    if (pp.ntask == 0) return;
+    const int span = (int)PAIR_WINDOW + pp.n_a * pp.n_b;
+    const size_t lds = (size_t)span * sizeof(typename Cx<R>::T) +
+                       (size_t)(pp.lda * pp.lda + pp.ldb * pp.ldb) * sizeof(R) + (size_t)span * 4 * sizeof(uint16_t);
+    hipLaunchKernelGGL((k_hpsi_pair<R>), dim3(pp.ntask), dim3(PRB), lds, s, pp, Ta, Tb, x, V, y, span, skip_if,
+                       skip_j);
+}
+
 }  // namespace
+
+void hpsi_pair_f64(const PairPass &pp, const double *Ta, const double *Tb, const double2 *x, const double *V,
+                   double2 *y, const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_pair<double>(pp, Ta, Tb, x, V, y, skip_if, skip_j, s);
+}
+
+void hpsi_pair_f32(const PairPass &pp, const float *Ta, const float *Tb, const float2 *x, const float *V, float2 *y,
+                   const int *skip_if, int skip_j, hipStream_t s)
+{
+    launch_pair<float>(pp, Ta, Tb, x, V, y, skip_if, skip_j, s);
+}
 
 void hpsi_real_f64(const FiberPass &fp, const double *T, const double2 *x, const double *V, double2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s)

@@ -284,6 +284,28 @@ void hpsi_plane_f64(const PlanePass &pp, const double *Ta, const double *Tb, con
                     double2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
 void hpsi_plane_f32(const PlanePass &pp, const float *Ta, const float *Tb, const float2 *x, const float *V,
                     float2 *y, bool first, const int *skip_if, int skip_j, hipStream_t s);
+// ---- pair pass: the last two dimensions (a = D-2, b = D-1) in one pass -------
+// A plane (every digit but the last two fixed) is a contiguous run of the
+// sorted state and, in the rotated order of dimension a (digit a moved last),
+// occupies the same range of ranks.  Task t holds the planes that start in
+// [t PAIR_WINDOW, (t + 1) PAIR_WINDOW); a plane holds at most n_a n_b points.
+constexpr uint32_t PAIR_WINDOW = 256;
+constexpr uint32_t PAIR_NAB_MAX = 1024;  // largest n_a n_b the pass takes
+struct PairPass {
+    const uint32_t *keys;    // sorted keys of the set
+    const uint32_t *pi_a;    // dimension a's permutation: rank -> position
+    const uint32_t *tstart;  // first position of each task [ntask + 1], tstart[ntask] = n
+    uint32_t ntask;          // ceil(n / PAIR_WINDOW)
+    int n_a, n_b;            // grid sizes of the two dimensions (digit extraction)
+    int lda, ldb;            // padded sizes: row strides of the two factors
+};
+// tstart of the pair pass (ntask + 1 words)
+void pair_tasks(const uint32_t *keys, int64_t n, uint32_t nab, uint32_t *tstart, hipStream_t s);
+// y = (V + h_a (x) 1 + 1 (x) h_b) x over the last two dimensions (writes y)
+void hpsi_pair_f64(const PairPass &pp, const double *Ta, const double *Tb, const double2 *x, const double *V,
+                   double2 *y, const int *skip_if, int skip_j, hipStream_t s);
+void hpsi_pair_f32(const PairPass &pp, const float *Ta, const float *Tb, const float2 *x, const float *V, float2 *y,
+                   const int *skip_if, int skip_j, hipStream_t s);
 // FP32 forms
 void hpsi_real_f32(const FiberPass &fp, const float *T, const float2 *x, const float *V, float2 *y, bool first,
                    const int *skip_if, int skip_j, hipStream_t s);

@@ -768,6 +768,31 @@ __global__ void k_plane_tasks(const uint32_t *poff, const uint32_t *np, int64_t 
     for (uint32_t t = lo; t <= hi && t <= ntask; ++t) tstart[t] = st;
 }
 
+// Pair-pass tasks: task t starts at the first plane start at or after t W (n
+// if none).  The plane holding position t W ends within nab positions, so one
+// wavefront per task looks at positions [t W, t W + nab] only.
+__global__ void k_pair_tasks(const uint32_t *keys, int64_t n, uint32_t nab, uint32_t W, uint32_t ntask,
+                             uint32_t *tstart)
+{
+    const int64_t t = gid() >> 6;
+    const int lane = threadIdx.x & 63;
+    if (t > (int64_t)ntask) return;
+    uint32_t st = (uint32_t)n;
+    if (t < (int64_t)ntask) {
+        const int64_t q0 = t * W, qe = q0 + (int64_t)nab < n - 1 ? q0 + (int64_t)nab : n - 1;
+        for (int64_t b = q0; b <= qe; b += 64) {
+            const int64_t q = b + lane;
+            const bool start = q <= qe && (q == 0 || keys[q] / nab != keys[q - 1] / nab);
+            const uint64_t m = __ballot(start);
+            if (m) {
+                st = (uint32_t)(b + __ffsll((unsigned long long)m) - 1);
+                break;
+            }
+        }
+    }
+    if (lane == 0) tstart[t] = st;
+}
+
 __global__ void k_fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n,
                            const uint32_t *nf, uint32_t *off, uint64_t *mask)
 {
@@ -2121,6 +2146,15 @@ void plane_tables(const uint32_t *keys, int64_t n, const GridDesc &g, int a, uin
     const uint32_t ntask = (uint32_t)((n + PLANE_WINDOW - 1) / PLANE_WINDOW);
     hipLaunchKernelGGL(k_plane_tasks, dim3(nblocks(n + 1)), dim3(TB), 0, s, poff, counter, n, PLANE_WINDOW, ntask,
                        tstart);
+}
+
+void pair_tasks(const uint32_t *keys, int64_t n, uint32_t nab, uint32_t *tstart, hipStream_t s)
+{
+    if (n <= 0) return;
+    const uint32_t ntask = (uint32_t)((n + PAIR_WINDOW - 1) / PAIR_WINDOW);
+    const int64_t threads = ((int64_t)ntask + 1) * 64;
+    hipLaunchKernelGGL(k_pair_tasks, dim3((unsigned)((threads + TB - 1) / TB)), dim3(TB), 0, s, keys, n, nab,
+                       PAIR_WINDOW, ntask, tstart);
 }
 
 void fib_fill(const uint32_t *flags, const uint32_t *fidx, const uint64_t *tmpmask, int64_t n, const uint32_t *nf,

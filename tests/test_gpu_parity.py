@@ -687,8 +687,10 @@ def test_fp32_shadow_steps(name, nsteps, torch):
 # ---------------------------------------------------------------------------
 # 4, 5: block-fused (row groups per wave task; one lane per fiber);
 # 6: plane passes (two dimensions per pass through matrix-core tiles; a card
-# with a dimension above 32 points keeps the per-dimension layout)
-BLOCK_VARIANTS = ["4", "5", "6"]
+# with a dimension above 32 points keeps the per-dimension layout);
+# 7: the last two dimensions in one pass (one thread per point, whole planes
+# per workgroup), the others one lane per fiber
+BLOCK_VARIANTS = ["4", "5", "6", "7"]
 
 
 def make_block(cd, torch, precision=0, variant="4"):
@@ -791,6 +793,34 @@ def test_plane_pass_largest_planes(fill, prec, torch):
     torch.cuda.synchronize()
     err = np.max(np.abs(yt.cpu().numpy().astype(np.complex128) - ref)) / np.max(np.abs(ref))
     say(f"  plane passes 6x27x28 fill {fill} prec {prec}: rel err {err:.2e}")
+    assert err < (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pair_pass_largest_plane(prec, torch):
+    """Layout 7 with a task at its largest span: on a 5 x 32 x 32 grid one
+    plane is full (1024 points, the most a plane may hold) and the others
+    hold 5% of their points, so the mean fibers stay short and the pass is
+    taken; the full plane shares its task with the planes around it."""
+    cd = card("small_3d", n=[5, 32, 32])
+    n = cd["n"]
+    sparse = random_active_set(n, 0.05, 41, blob=False)
+    keys = np.union1d(sparse, np.arange(2 * 1024, 3 * 1024, dtype=np.uint64)).astype(np.uint64)
+    x = random_complex(keys.size, 42)
+    xin = x if prec == 0 else x.astype(np.complex64).astype(np.complex128)
+    ref = Oracle(cd).apply_def(keys, xin)
+    g = make_block(cd, torch, prec, "7")
+    g.set_state(keys, x)
+    nf = g.fiber_counts()
+    assert keys.size <= 16 * min(nf[1], nf[2]), "fibers too long for the pair pass"
+    xt = torch.from_numpy(x).cuda()
+    if prec == 1:
+        xt = xt.to(torch.complex64)
+    yt = torch.zeros_like(xt)
+    g.apply_h(xt, yt)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(yt.cpu().numpy().astype(np.complex128) - ref)) / np.max(np.abs(ref))
+    say(f"  pair pass 5x32x32, |A| {keys.size}, prec {prec}: rel err {err:.2e}")
     assert err < (1e-13 if prec == 0 else 1e-6)
 
 
