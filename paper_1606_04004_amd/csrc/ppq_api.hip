@@ -210,6 +210,9 @@ struct ppq_ctx {
     int64_t scan_tmp_n = 0;
     uint64_t *bm = nullptr;
     uint32_t *prefix = nullptr;
+    uint64_t *kbm = nullptr;  // adaption: the functions above the threshold (word-parallel dilation)
+    int64_t kbm_words = 0;
+    int dilate_mode = 0;      // 0: by the sizes, 1: per function (atomics), 2: word by word (PPQ_DILATE)
     uint32_t *small = nullptr;            // device counters
     unsigned long long *count = nullptr;  // device counter
     uint32_t *h_small = nullptr;          // pinned mirrors
@@ -1830,9 +1833,23 @@ void do_prune(ppq_ctx *c, double eps, int64_t *nabove_out)
     hipStream_t s = c->stream;
     const int64_t n_old = c->nact;
     double eps2 = eps * eps;
-    fill_u64(c->bm, c->nwords + 2, 0ull, s);
     fill_u64((uint64_t *)c->count, 1, 0ull, s);
-    dilate(c->keys[c->cur], c->psi[c->cur], n_old, c->g, eps2, c->bm, c->count, c->flags, s);
+    // the +-1 stencil on DVR axes word by word while the grid's bitmap is not
+    // much larger than the set (every word is visited); else per function
+    const bool words = c->g.pairs == 0 && !c->any_lattice && c->dilate_mode != 1 &&
+                       (c->dilate_mode == 2 || c->nwords <= 4 * n_old + 4096);
+    if (words) {
+        if (c->kbm_words != c->nwords) {
+            dfree(c->kbm);
+            c->kbm = dalloc<uint64_t>(c->nwords);
+            c->kbm_words = c->nwords;
+        }
+        dilate_words(c->keys[c->cur], c->psi[c->cur], n_old, c->g, eps2, c->kbm, c->bm, c->nwords, c->count,
+                     c->flags, s);
+    } else {
+        fill_u64(c->bm, c->nwords + 2, 0ull, s);
+        dilate(c->keys[c->cur], c->psi[c->cur], n_old, c->g, eps2, c->bm, c->count, c->flags, s);
+    }
     if (c->rel_excl > 0.0)
         keep_all_if_few_dropped(c->keys[c->cur], n_old, c->bm, c->rel_excl, c->flags, c->count + 1, s);
     scan_popcount(c->bm, c->nwords, c->prefix, &c->small[MAXD], c->scan_tmp, s);
@@ -2291,6 +2308,10 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
         if (h >= 0 && h <= 7) c->hpsi_variant = h;  // other values keep the default layout
     }
     if (const char *v = std::getenv("PPQ_BLOCK_UNROLL")) c->blk_unroll = std::atoi(v) != 0;
+    if (const char *v = std::getenv("PPQ_DILATE")) {
+        const int d = std::atoi(v);
+        if (d >= 0 && d <= 2) c->dilate_mode = d;
+    }
     if (const char *v = std::getenv("PPQ_BLOCK_WINDOW")) {
         const long w = std::atol(v);
         if (w >= (long)BLOCK_WINDOW && w <= (1l << 20)) c->blk_window = (uint32_t)w;
@@ -2338,6 +2359,7 @@ void ppq_destroy(ppq_ctx *c)
     free_operator(c);
     dfree(c->bm);
     dfree(c->prefix);
+    dfree(c->kbm);
     dfree(c->ks);
     dfree(c->partial);
     dfree(c->counter);
@@ -2413,6 +2435,8 @@ int ppq_set_grid(ppq_ctx *c, int D, const int32_t *n, const double *lo, const do
         free_operator(c);
         dfree(c->bm);
         dfree(c->prefix);
+        dfree(c->kbm);
+        c->kbm_words = 0;
         c->terms.clear();
         c->has_state = false;
         c->nact = 0;

@@ -79,6 +79,12 @@ void product_values(const uint32_t *keys, int64_t n, const GridDesc &g, const do
 // block_counts: work space of at least n / 256 + 1 entries
 void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, double eps2, uint64_t *bm,
             unsigned long long *nabove, unsigned *block_counts, hipStream_t s);
+// The same dilation for the +-1 stencil on a grid without lattice axes, word
+// by word: K (nwords words of work space) gets one bit per function above the
+// threshold, then every word of bm (nwords + 2 words) is written from K and
+// its shifts by the strides.  Costs O(nwords) instead of O(n) atomics.
+void dilate_words(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, double eps2, uint64_t *K,
+                  uint64_t *bm, int64_t nwords, unsigned long long *nabove, unsigned *block_counts, hipStream_t s);
 void compact(const uint64_t *bm, const uint32_t *prefix, int64_t nwords, uint32_t *keys_out, hipStream_t s);
 void remap(const uint32_t *okeys, const double2 *opsi, int64_t n_old, const uint64_t *bm, const uint32_t *prefix,
            double2 *npsi, hipStream_t s);

@@ -365,6 +365,71 @@ __global__ void k_dilate(const uint32_t *keys, const double2 *psi, int64_t n, Gr
     count_block(keep, block_counts);
 }
 
+// ---- word-parallel dilation (the +-1 stencil on DVR axes) ---------------------
+__device__ inline int64_t i64min(int64_t a, int64_t b) { return a < b ? a : b; }
+__device__ inline int64_t i64max(int64_t a, int64_t b) { return a > b ? a : b; }
+
+// bits [lo, hi) of a word (0 <= lo, hi <= 64)
+__device__ inline uint64_t bit_range(int lo, int hi)
+{
+    if (hi <= lo) return 0ull;
+    const uint64_t up = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return up & ~((1ull << lo) - 1ull);
+}
+
+// the 64 bits of K from bit b on (bits outside the nwords words read 0)
+__device__ inline uint64_t bit_window(const uint64_t *K, int64_t nwords, int64_t b)
+{
+    const int64_t q = b >> 6;  // rounds down for negative b
+    const int r = (int)(b & 63);
+    const uint64_t lo = (q >= 0 && q < nwords) ? K[q] : 0ull;
+    if (r == 0) return lo;
+    const uint64_t hi = (q + 1 >= 0 && q + 1 < nwords) ? K[q + 1] : 0ull;
+    return (lo >> r) | (hi << (64 - r));
+}
+
+// K: one bit per function above the threshold (and the block counts of them)
+__global__ void k_mark_kept(const uint32_t *keys, const double2 *psi, int64_t n, double eps2, uint64_t *K,
+                            unsigned *block_counts)
+{
+    int64_t p = gid();
+    bool keep = false;
+    uint32_t key = 0;
+    if (p < n) {
+        key = keys[p];
+        keep = above_eps(psi[p], eps2);
+    }
+    set_bit_wave(K, key, keep);
+    count_block(keep, block_counts);
+}
+
+// bm = K with every +-1 neighbour on one axis, one word per thread: the
+// neighbours one stride s_k below are K read s_k bits earlier, kept where the
+// key's digit k is not 0 (one stride above: not n_k - 1).  With P = s_k n_k,
+// digit k is 0 on the runs [m P, m P + s_k) and n_k - 1 on [(m + 1) P - s_k,
+// (m + 1) P).  Every word is written, the grid's tail bits cleared.
+__global__ void k_dilate_words(const uint64_t *K, int64_t nwords, GridDesc g, uint64_t *bm)
+{
+    for (int64_t w = gid(); w < nwords; w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = w * 64;
+        uint64_t acc = K[w];
+        for (int k = 0; k < g.D; ++k) {
+            const int64_t st = g.stride[k], P = st * g.n[k];
+            uint64_t zm = 0ull, tm = 0ull;
+            for (int64_t rs = (a / P) * P; rs < a + 64; rs += P) {
+                if (rs + st > a) zm |= bit_range((int)(i64max(rs, a) - a), (int)(i64min(rs + st, a + 64) - a));
+                const int64_t ts = rs + P - st;
+                if (rs + P > a && ts < a + 64)
+                    tm |= bit_range((int)(i64max(ts, a) - a), (int)(i64min(rs + P, a + 64) - a));
+            }
+            acc |= (bit_window(K, nwords, a - st) & ~zm) | (bit_window(K, nwords, a + st) & ~tm);
+        }
+        const int64_t tail = (int64_t)g.total - a;
+        if (tail < 64) acc &= tail > 0 ? ((1ull << tail) - 1ull) : 0ull;
+        bm[w] = acc;
+    }
+}
+
 // Relative exclusion (Sec. II.E): counts the current functions whose bit the
 // dilated set leaves clear, i.e. those adaption would drop (block counts).
 __global__ void k_count_dropped(const uint32_t *keys, int64_t n, const uint64_t *bm, unsigned *block_counts)
@@ -2031,6 +2096,19 @@ void dilate(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc 
     const unsigned nb = nblocks(n);
     hipLaunchKernelGGL(k_dilate, dim3(nb), dim3(TB), 0, s, keys, psi, n, g, eps2, bm, block_counts);
     hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts, (int64_t)nb, nabove);
+}
+void dilate_words(const uint32_t *keys, const double2 *psi, int64_t n, const GridDesc &g, double eps2, uint64_t *K,
+                  uint64_t *bm, int64_t nwords, unsigned long long *nabove, unsigned *block_counts, hipStream_t s)
+{
+    fill_u64(K, nwords, 0ull, s);
+    if (n > 0) {
+        const unsigned nb = nblocks(n);
+        hipLaunchKernelGGL(k_mark_kept, dim3(nb), dim3(TB), 0, s, keys, psi, n, eps2, K, block_counts);
+        hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts, (int64_t)nb, nabove);
+    }
+    const unsigned nbw = (unsigned)std::min<int64_t>((nwords + TB - 1) / TB, 8192);
+    hipLaunchKernelGGL(k_dilate_words, dim3(nbw), dim3(TB), 0, s, K, nwords, g, bm);
+    fill_u64(bm + nwords, 2, 0ull, s);
 }
 void keep_all_if_few_dropped(const uint32_t *keys, int64_t n, uint64_t *bm, double rel, unsigned *block_counts,
                              unsigned long long *dropped, hipStream_t s)

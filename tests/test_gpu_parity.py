@@ -150,6 +150,40 @@ def test_prune_bit_exact(name, seed, torch):
     assert nab_g == nab_o and na == ko.size
 
 
+@pytest.mark.parametrize("name,n", [("small_3d", [24, 24, 24]), ("small_3d", [5, 2, 7]), ("small_3d", [2, 9, 70]),
+                                    ("small_2d", [130, 3]), ("small_6d", [4, 4, 4, 4, 4, 4])])
+@pytest.mark.parametrize("fill", [0.01, 0.3])
+def test_dilation_word_and_point_forms_agree(name, n, fill, torch):
+    """Adaption's two dilation forms (per function with atomics, and word by
+    word from the bitmap of the functions above the threshold, chosen by the
+    grid-to-set size ratio) give the oracle's set: grids whose size is not a
+    multiple of 64, axes of 2 points, strides below and above a word."""
+    import os
+    cd = card(name, n=n)
+    eps = 2.0 ** -10
+    keys = random_active_set(n, fill, 51, blob=False)
+    c = random_complex(keys.size, 52) * 2.0 ** -9
+    o = Oracle(cd)
+    o.set_state(keys, c)
+    nab_o = o.prune(eps=eps)
+    ko, _ = o.state()
+    old = os.environ.get("PPQ_DILATE")
+    try:
+        for mode in ("1", "2"):
+            os.environ["PPQ_DILATE"] = mode
+            g = make(cd, torch)
+            g.set_state(keys, c)
+            na, nab_g = g.prune(eps=eps)
+            kg, _ = g.state()
+            say(f"  dilation form {mode}, n={n}, fill {fill}: |A| {keys.size} -> {kg.size}")
+            assert np.array_equal(kg, ko) and nab_g == nab_o and na == ko.size
+    finally:
+        if old is None:
+            del os.environ["PPQ_DILATE"]
+        else:
+            os.environ["PPQ_DILATE"] = old
+
+
 def test_prune_edge_cases(torch):
     cd = card("small_3d")
     total = int(np.prod(cd["n"]))
