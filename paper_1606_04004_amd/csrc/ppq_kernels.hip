@@ -279,23 +279,38 @@ __global__ __launch_bounds__(1024) void k_scan_top(uint32_t *tile, int64_t ntile
     if (threadIdx.x == 0) *total = tot;
 }
 
+// The tile's SI rows of SB consecutive elements, each row read and written by
+// the whole block (coalesced): a wavefront scan per row and wave, then every
+// thread adds the totals of the (row, wave) pieces before its own.
 template <class L>
 __global__ __launch_bounds__(SB) void k_scan_apply(L ld, int64_t n, const uint32_t *tile_off, uint32_t *out)
 {
-    int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SI;
-    uint32_t v[SI];
-    uint32_t s = 0;
+    constexpr int NW = SB / 64;
+    __shared__ uint32_t wsum[SI * NW];
+    const int64_t base = (int64_t)blockIdx.x * STILE + threadIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t v[SI], inc[SI];
+#pragma unroll
+    for (int i = 0; i < SI; ++i) v[i] = (base + (int64_t)i * SB < n) ? ld(base + (int64_t)i * SB) : 0u;
 #pragma unroll
     for (int i = 0; i < SI; ++i) {
-        v[i] = (base + i < n) ? ld(base + i) : 0u;
-        s += v[i];
+        inc[i] = wave_incl_scan(v[i]);
+        if (lane == 63) wsum[i * NW + w] = inc[i];
     }
-    uint32_t tot;
-    uint32_t off = block_excl_scan<SB>(s, &tot) + tile_off[blockIdx.x];
+    __syncthreads();
+    uint32_t off = tile_off[blockIdx.x];
 #pragma unroll
     for (int i = 0; i < SI; ++i) {
-        if (base + i < n) out[base + i] = off;
-        off += v[i];
+        uint32_t before = 0, row = 0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t t = wsum[i * NW + ww];
+            before += ww < w ? t : 0u;
+            row += t;
+        }
+        const int64_t idx = base + (int64_t)i * SB;
+        if (idx < n) out[idx] = off + before + inc[i] - v[i];
+        off += row;
     }
 }
 
