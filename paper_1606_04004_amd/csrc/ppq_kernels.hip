@@ -418,26 +418,51 @@ __global__ void k_mark_kept(const uint32_t *keys, const double2 *psi, int64_t n,
     count_block(keep, block_counts);
 }
 
-// bm = K with every +-1 neighbour on one axis, one word per thread: the
-// neighbours one stride s_k below are K read s_k bits earlier, kept where the
-// key's digit k is not 0 (one stride above: not n_k - 1).  With P = s_k n_k,
-// digit k is 0 on the runs [m P, m P + s_k) and n_k - 1 on [(m + 1) P - s_k,
-// (m + 1) P).  Every word is written, the grid's tail bits cleared.
+// bm = K with every +-1 neighbour on one axis: the neighbours one stride s_k
+// below are K read s_k bits earlier, kept where the key's digit k is not 0
+// (one stride above: not n_k - 1).  With P = s_k n_k, digit k is 0 on the
+// runs [m P, m P + s_k) and n_k - 1 on [(m + 1) P - s_k, (m + 1) P).  A
+// wavefront takes DW_ITER rows of 64 consecutive words; each lane keeps, per
+// dimension, the position of its word's first bit within the period and
+// advances it by 64 words' worth per row (no division per word).  Every word
+// is written, the grid's tail bits cleared.
+constexpr int DW_ITER = 8;
 __global__ void k_dilate_words(const uint64_t *K, int64_t nwords, GridDesc g, uint64_t *bm)
 {
-    for (int64_t w = gid(); w < nwords; w += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = (gid() >> 6) * 64 * DW_ITER;
+    if (wbase >= nwords) return;
+    const int64_t w0 = wbase + lane;
+    int64_t pos[MAXD], inc[MAXD];
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) {
+        pos[k] = 0;
+        inc[k] = 0;
+        if (k < g.D) {
+            const int64_t P = (int64_t)g.stride[k] * g.n[k];
+            pos[k] = (w0 * 64) % P;
+            inc[k] = (int64_t)(64 * 64) % P;
+        }
+    }
+    for (int it = 0; it < DW_ITER; ++it) {
+        const int64_t w = w0 + (int64_t)it * 64;
+        if (w >= nwords) break;
         const int64_t a = w * 64;
         uint64_t acc = K[w];
-        for (int k = 0; k < g.D; ++k) {
-            const int64_t st = g.stride[k], P = st * g.n[k];
-            uint64_t zm = 0ull, tm = 0ull;
-            for (int64_t rs = (a / P) * P; rs < a + 64; rs += P) {
-                if (rs + st > a) zm |= bit_range((int)(i64max(rs, a) - a), (int)(i64min(rs + st, a + 64) - a));
-                const int64_t ts = rs + P - st;
-                if (rs + P > a && ts < a + 64)
-                    tm |= bit_range((int)(i64max(ts, a) - a), (int)(i64min(rs + P, a + 64) - a));
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            if (k < g.D) {
+                const int64_t st = g.stride[k], P = st * g.n[k];
+                uint64_t zm = 0ull, tm = 0ull;
+                for (int64_t r0 = -pos[k]; r0 < 64; r0 += P) {
+                    if (r0 + st > 0) zm |= bit_range((int)i64max(r0, 0), (int)i64min(r0 + st, 64));
+                    const int64_t ts = r0 + P - st;
+                    if (r0 + P > 0 && ts < 64) tm |= bit_range((int)i64max(ts, 0), (int)i64min(r0 + P, 64));
+                }
+                acc |= (bit_window(K, nwords, a - st) & ~zm) | (bit_window(K, nwords, a + st) & ~tm);
+                pos[k] += inc[k];
+                if (pos[k] >= P) pos[k] -= P;
             }
-            acc |= (bit_window(K, nwords, a - st) & ~zm) | (bit_window(K, nwords, a + st) & ~tm);
         }
         const int64_t tail = (int64_t)g.total - a;
         if (tail < 64) acc &= tail > 0 ? ((1ull << tail) - 1ull) : 0ull;
@@ -1122,38 +1147,57 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         //   g_i = <v_i|H q_j> = beta_i <v_{i+1}|q_j> + alpha_i h_i + beta_{i-1} h_{i-1}
         //   alpha_j = (mu - 2 Re sum conj(h_i) g_i + sum conj(h_i) T_ik h_k) / beta_{j-1}^2
         //   cc_k = sum_{i<j} T_ki h_i  (k <= j), so H v_j = (H q_j - sum cc_k v_k) / beta_{j-1}
+        // (the step's scalars are loaded at once and cc is summed in registers:
+        // loops run to MAXM with a predicate, so nothing goes to scratch)
         const double2 mu = r[0];
-        for (int k = 0; k < MAXM; ++k) ks->cc[k] = make_double2(0.0, 0.0);
+        double2 cc[MAXM];
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) cc[k] = make_double2(0.0, 0.0);
         if (j == 0) {
             ks->alpha[0] = mu.x;
             ks->inv_b = 1.0;
         } else {
             const double b = ks->beta[j - 1];
             const double2 *hh = ks->h2 + (j - 1);  // hh[i * MAXM] = h_i
+            double2 h[MAXM];
+            double al[MAXM], be[MAXM];
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                h[i] = i < j ? hh[i * MAXM] : make_double2(0.0, 0.0);
+                al[i] = i < j ? ks->alpha[i] : 0.0;
+                be[i] = i < j ? ks->beta[i] : 0.0;
+            }
             double s1 = 0.0, s2 = 0.0;
-            for (int i = 0; i < j; ++i) {
-                const double2 hi = hh[i * MAXM];
-                const double2 hn = (i + 1 < j) ? hh[(i + 1) * MAXM] : make_double2(b, 0.0);
-                const double2 hp = (i >= 1) ? hh[(i - 1) * MAXM] : make_double2(0.0, 0.0);
-                const double bp = (i >= 1) ? ks->beta[i - 1] : 0.0;
-                const double2 g = make_double2(ks->beta[i] * hn.x + ks->alpha[i] * hi.x + bp * hp.x,
-                                               ks->beta[i] * hn.y + ks->alpha[i] * hi.y + bp * hp.y);
-                s1 += hi.x * g.x + hi.y * g.y;  // Re(conj(h_i) g_i)
-                s2 += ks->alpha[i] * (hi.x * hi.x + hi.y * hi.y);
-                if (i + 1 < j) s2 += 2.0 * ks->beta[i] * (hi.x * hn.x + hi.y * hn.y);
-                // cc_k = alpha_k h_k + beta_k h_{k+1} + beta_{k-1} h_{k-1}, gathered per h_i
-                ks->cc[i].x += ks->alpha[i] * hi.x;
-                ks->cc[i].y += ks->alpha[i] * hi.y;
-                ks->cc[i + 1].x += ks->beta[i] * hi.x;
-                ks->cc[i + 1].y += ks->beta[i] * hi.y;
-                if (i >= 1) {
-                    ks->cc[i - 1].x += ks->beta[i - 1] * hi.x;
-                    ks->cc[i - 1].y += ks->beta[i - 1] * hi.y;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                if (i < j) {
+                    const double2 hi = h[i];
+                    const double2 hn = (i + 1 < j) ? h[(i + 1) % MAXM] : make_double2(b, 0.0);
+                    const double2 hp = (i >= 1) ? h[(i + MAXM - 1) % MAXM] : make_double2(0.0, 0.0);
+                    const double bp = (i >= 1) ? be[(i + MAXM - 1) % MAXM] : 0.0;
+                    const double2 g = make_double2(be[i] * hn.x + al[i] * hi.x + bp * hp.x,
+                                                   be[i] * hn.y + al[i] * hi.y + bp * hp.y);
+                    s1 += hi.x * g.x + hi.y * g.y;  // Re(conj(h_i) g_i)
+                    s2 += al[i] * (hi.x * hi.x + hi.y * hi.y);
+                    if (i + 1 < j) s2 += 2.0 * be[i] * (hi.x * hn.x + hi.y * hn.y);
+                    // cc_k = alpha_k h_k + beta_k h_{k+1} + beta_{k-1} h_{k-1}, gathered per h_i
+                    cc[i].x += al[i] * hi.x;
+                    cc[i].y += al[i] * hi.y;
+                    if (i + 1 < MAXM) {
+                        cc[(i + 1) % MAXM].x += be[i] * hi.x;
+                        cc[(i + 1) % MAXM].y += be[i] * hi.y;
+                    }
+                    if (i >= 1) {
+                        cc[(i + MAXM - 1) % MAXM].x += bp * hi.x;
+                        cc[(i + MAXM - 1) % MAXM].y += bp * hi.y;
+                    }
                 }
             }
             ks->alpha[j] = (mu.x - 2.0 * s1 + s2) / (b * b);
             ks->inv_b = 1.0 / b;
         }
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) ks->cc[k] = cc[k];
     } else if (mode == RED_ADELAY) {
         // Arnoldi: q_j = beta_{j-1} v_j + sum_{i<j} h_i v_i (h_i = h2[i][j-1]);
         // H v_i = sum_{k<=i+1} H_ki v_k with H_ki = h1 + h2 (k <= i), beta_i (k = i+1):
@@ -1162,8 +1206,11 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         //   h1_ij = <v_i|H v_j> = (<v_i|z> - cc_i) / beta_{j-1}   (i <= j)
         // column j's second-pass terms come from this step's sweep (RED_BETA);
         // a step's last column keeps only its first pass
+        // (cc is summed in registers; loops run to MAXM with a predicate)
+        double2 cc[MAXM];
+#pragma unroll
         for (int k = 0; k < MAXM; ++k) {
-            ks->cc[k] = make_double2(0.0, 0.0);
+            cc[k] = make_double2(0.0, 0.0);
             ks->h2[k * MAXM + j] = make_double2(0.0, 0.0);
         }
         if (j == 0) {
@@ -1173,16 +1220,23 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
         } else {
             const double b = ks->beta[j - 1], ib = 1.0 / b;
             const double2 *hh = ks->h2 + (j - 1);
-            for (int i = 0; i < j; ++i) {
-                const double2 hi = hh[i * MAXM];
-                for (int k = 0; k <= i; ++k) {
-                    const double2 a1 = ks->h1[k * MAXM + i], a2 = ks->h2[k * MAXM + i];
-                    const double2 hk = make_double2(a1.x + a2.x, a1.y + a2.y);
-                    ks->cc[k].x += hk.x * hi.x - hk.y * hi.y;
-                    ks->cc[k].y += hk.x * hi.y + hk.y * hi.x;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                if (i < j) {
+                    const double2 hi = hh[i * MAXM];
+#pragma unroll
+                    for (int k = 0; k <= i; ++k) {
+                        const double2 a1 = ks->h1[k * MAXM + i], a2 = ks->h2[k * MAXM + i];
+                        const double2 hk = make_double2(a1.x + a2.x, a1.y + a2.y);
+                        cc[k].x += hk.x * hi.x - hk.y * hi.y;
+                        cc[k].y += hk.x * hi.y + hk.y * hi.x;
+                    }
+                    if (i + 1 < MAXM) {
+                        const double bi = ks->beta[i];
+                        cc[(i + 1) % MAXM].x += bi * hi.x;
+                        cc[(i + 1) % MAXM].y += bi * hi.y;
+                    }
                 }
-                ks->cc[i + 1].x += ks->beta[i] * hi.x;
-                ks->cc[i + 1].y += ks->beta[i] * hi.y;
             }
             // <v_j|z>, r[i] = <v_i|z> for i < j, r[j] = <q_j|z> (loops to NV with a predicate)
             double2 vz = make_double2(0.0, 0.0);
@@ -1199,15 +1253,17 @@ __global__ __launch_bounds__(TB) void k_finalize(const double2 *partial, int nb,
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 if (i < j) {
-                    ks->h1[i * MAXM + j] = make_double2((r[i].x - ks->cc[i].x) * ib, (r[i].y - ks->cc[i].y) * ib);
+                    ks->h1[i * MAXM + j] = make_double2((r[i].x - cc[i % MAXM].x) * ib, (r[i].y - cc[i % MAXM].y) * ib);
                 } else if (i == j) {
-                    const double2 g = make_double2((vz.x - ks->cc[j].x) * ib, (vz.y - ks->cc[j].y) * ib);
+                    const double2 g = make_double2((vz.x - cc[i % MAXM].x) * ib, (vz.y - cc[i % MAXM].y) * ib);
                     ks->h1[j * MAXM + j] = g;
                     ks->alpha[j] = g.x;
                 }
             }
             ks->inv_b = ib;
         }
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) ks->cc[k] = cc[k];
     } else {  // RED_BETA: h2[.][j] and beta_j from |q_{j+1}|^2 - sum |h2_i|^2
         const int nh = nvals - 1;
         double hh = 0.0, last = 0.0;
@@ -2121,8 +2177,8 @@ void dilate_words(const uint32_t *keys, const double2 *psi, int64_t n, const Gri
         hipLaunchKernelGGL(k_mark_kept, dim3(nb), dim3(TB), 0, s, keys, psi, n, eps2, K, block_counts);
         hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, block_counts, (int64_t)nb, nabove);
     }
-    const unsigned nbw = (unsigned)std::min<int64_t>((nwords + TB - 1) / TB, 8192);
-    hipLaunchKernelGGL(k_dilate_words, dim3(nbw), dim3(TB), 0, s, K, nwords, g, bm);
+    const int64_t waves = (nwords + 64 * DW_ITER - 1) / (64 * DW_ITER);
+    hipLaunchKernelGGL(k_dilate_words, dim3((unsigned)((waves * 64 + TB - 1) / TB)), dim3(TB), 0, s, K, nwords, g, bm);
     fill_u64(bm + nwords, 2, 0ull, s);
 }
 void keep_all_if_few_dropped(const uint32_t *keys, int64_t n, uint64_t *bm, double rel, unsigned *block_counts,
