@@ -41,8 +41,17 @@
  *   PPQ_HPSI=1  point-parallel in every pass; PPQ_HPSI=0 lane per fiber in
  *               every pass (earlier layouts, for comparison).
  *   PPQ_HPSI=4  block-fused layout: two LDS-staged passes over chunks of
- *               blocks (falls back to 2 when a chunk exceeds LDS).
+ *               blocks (falls back to 2 when a chunk exceeds LDS); 5 the
+ *               same chunks with one lane per fiber in each.
+ *   PPQ_HPSI=6  plane passes: two adjacent dimensions per pass through
+ *               matrix-core tiles (dimensions of at most 32 points).
+ *   PPQ_HPSI=7  the last two dimensions in one pass (whole planes per
+ *               workgroup), the others as in 2.
  *   PPQ_BLOCK_STATS=1  report the block layout's chunk statistics on stderr.
+ *   PPQ_DILATE=1 / 2  adaption's dilation per function (atomics) / word by
+ *               word from the bitmap of the functions kept (the +-1 stencil
+ *               on DVR axes only); 0 (default) chooses by the grid-to-set
+ *               size ratio.  Both give the same set.
  *   Every layout computes the same product; only the summation order of
  *   the dimensions' contributions differs.
  */
