@@ -48,6 +48,9 @@
  *   PPQ_HPSI=7  the last two dimensions in one pass (whole planes per
  *               workgroup), the others as in 2.
  *   PPQ_BLOCK_STATS=1  report the block layout's chunk statistics on stderr.
+ *   PPQ_ACC_STAGE=1  lane-per-fiber passes (but the one with the fused
+ *               <x|y>) read the permutation from each wavefront's copy of its
+ *               rank range in LDS instead of scattered global loads.
  *   PPQ_DILATE=1 / 2  adaption's dilation per function (atomics) / word by
  *               word from the bitmap of the functions kept (the +-1 stencil
  *               on DVR axes only); 0 (default) chooses by the grid-to-set

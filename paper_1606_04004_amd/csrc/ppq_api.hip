@@ -172,6 +172,8 @@ struct ppq_ctx {
                            // 7 = the last two dimensions in one pass)
     uint32_t blk_window = BLOCK_WINDOW;  // chunk window of the block layouts (PPQ_BLOCK_WINDOW)
     int blk_unroll = 1;                  // one-lane-per-fiber block pass: row loop unrolled (PPQ_BLOCK_UNROLL)
+    bool acc_stage = false;              // lane-per-fiber passes stage pi in LDS (PPQ_ACC_STAGE;
+                                         // faster back to back in FP32, slower within steps)
 
     // block-fused H*psi: outer dimensions [0, split) through the inner-first
     // frame, inner dimensions [split, D) in the row-major frame
@@ -1289,6 +1291,7 @@ FiberPass pass_of(const ppq_ctx *c, int k)
     fp.mask = c->mask[k];
     fp.nf = c->nf[k];
     fp.nmax = c->nb[k];
+    fp.stage = c->acc_stage;
     return fp;
 }
 
@@ -2308,6 +2311,7 @@ int ppq_create(ppq_ctx **out, int device, void *hip_stream, int precision)
         if (h >= 0 && h <= 7) c->hpsi_variant = h;  // other values keep the default layout
     }
     if (const char *v = std::getenv("PPQ_BLOCK_UNROLL")) c->blk_unroll = std::atoi(v) != 0;
+    if (const char *v = std::getenv("PPQ_ACC_STAGE")) c->acc_stage = std::atoi(v) != 0;
     if (const char *v = std::getenv("PPQ_DILATE")) {
         const int d = std::atoi(v);
         if (d >= 0 && d <= 2) c->dilate_mode = d;

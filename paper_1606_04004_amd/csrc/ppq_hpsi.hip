@@ -150,10 +150,13 @@ __global__ __launch_bounds__(HB) void k_hpsi_real(const uint32_t *__restrict__ p
 // contraction, so the output loop has no dependent loads.
 // DOT: also returns sum_p conj(x_p) y_p over the fiber (the stored y), the
 // lane's share of <x|y> when this pass writes y last.
-template <class R, int W, int NMAX, bool IDENT, bool DOT>
+// STAGE: the positions come from the wavefront's copy of its rank range of
+// pi in LDS (sp[rank - r0]) instead of scattered global loads.
+template <class R, int W, int NMAX, bool IDENT, bool DOT, bool STAGE = false>
 __device__ __forceinline__ double2 body_real_acc(uint32_t o, uint64_t m, int ws, const uint32_t *__restrict__ pi,
                                                  const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
-                                                 typename Cx<R>::T *__restrict__ y)
+                                                 typename Cx<R>::T *__restrict__ y, const uint32_t *sp = nullptr,
+                                                 uint32_t r0 = 0)
 {
     using C = typename Cx<R>::T;
     C xw[W], yw[W];
@@ -164,7 +167,7 @@ __device__ __forceinline__ double2 body_real_acc(uint32_t o, uint64_t m, int ws,
         pw[jj] = 0;
         if ((m >> j) & 1ull) {
             uint32_t pos = o + (uint32_t)__popcll(m & ((1ull << j) - 1ull));
-            pw[jj] = IDENT ? pos : pi[pos];
+            pw[jj] = IDENT ? pos : (STAGE ? sp[pos - r0] : pi[pos]);
         }
     }
 #pragma unroll
@@ -202,7 +205,11 @@ __device__ __forceinline__ double2 body_real_acc(uint32_t o, uint64_t m, int ws,
 
 // DOT: every block also stores its share of <x|y> (the y this pass leaves)
 // in dotp[blockIdx.x], summed over the block in a fixed order.
-template <class R, int NMAX, bool IDENT, bool DOT>
+// STAGE: a wavefront's 64 consecutive fibers cover one contiguous range of
+// ranks; it copies that range of pi into LDS with coalesced loads first, so
+// the per-digit position lookups read LDS (a lane's lookups otherwise touch
+// a cache line of their own for every window digit).
+template <class R, int NMAX, bool IDENT, bool DOT, bool STAGE = false>
 __global__ __launch_bounds__(HB) void k_hpsi_acc(const uint32_t *__restrict__ pi, const uint32_t *__restrict__ off,
                                                  const uint64_t *__restrict__ mask, int64_t nf,
                                                  const R *__restrict__ T, const typename Cx<R>::T *__restrict__ x,
@@ -218,16 +225,34 @@ __global__ __launch_bounds__(HB) void k_hpsi_acc(const uint32_t *__restrict__ pi
         o = off[f];
     }
     uint64_t wm = wave_or64(m);
+    constexpr int SPW = STAGE ? 64 * NMAX : 1;  // a wavefront's ranks: 64 fibers of at most NMAX points
+    __shared__ uint32_t s_pi[STAGE ? HB / 64 : 1][SPW];
+    uint32_t r0 = 0;
+    if constexpr (STAGE) {
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        // the valid fibers are the wavefront's first lanes; their ranks are
+        // [o of lane 0, end of the last valid lane)
+        const uint64_t valid = __ballot(f < nf);
+        uint32_t span = 0;
+        if (valid) {
+            const int last = 63 - __clzll((long long)valid);
+            r0 = (uint32_t)__shfl((int)o, 0, 64);
+            span = (uint32_t)__shfl((int)(o + (uint32_t)__popcll(m)), last, 64) - r0;
+        }
+        for (uint32_t i = (uint32_t)lane; i < span; i += 64) s_pi[wv][i] = pi[r0 + i];
+        __syncthreads();
+    }
     double2 dot = make_double2(0.0, 0.0);
     if (wm != 0) {
         int wlo = __ffsll((unsigned long long)wm) - 1;
         int whi = 63 - __clzll((long long)wm);
         int width = whi - wlo + 1;
-#define PPQ_BODY(W)                                                                 \
-    {                                                                               \
-        int ws = wlo < NMAX - (W) ? wlo : NMAX - (W);                               \
-        dot = body_real_acc<R, W, NMAX, IDENT, DOT>(o, m, ws, pi, T, x, y);        \
-        goto done;                                                                  \
+#define PPQ_BODY(W)                                                                                   \
+    {                                                                                                 \
+        int ws = wlo < NMAX - (W) ? wlo : NMAX - (W);                                                 \
+        dot = body_real_acc<R, W, NMAX, IDENT, DOT, STAGE>(o, m, ws, pi, T, x, y,                     \
+                                                           STAGE ? s_pi[threadIdx.x >> 6] : nullptr, r0); \
+        goto done;                                                                                    \
     }
         if constexpr (NMAX >= 8) {
             if (width <= 8) PPQ_BODY(8)
@@ -1722,22 +1747,23 @@ int launch_acc(const FiberPass &fp, const R *T, const typename Cx<R>::T *x, type
 {
     if (fp.nf <= 0) return 0;
     const unsigned nb = (unsigned)((fp.nf + HB - 1) / HB);
-#define L(NM)                                                                                                      \
+#define L(NM, ST)                                                                                                  \
     do {                                                                                                           \
         if (dotp)                                                                                                  \
-            hipLaunchKernelGGL((k_hpsi_acc<R, NM, false, true>), dim3(nb), dim3(HB), 0, s, fp.pi, fp.off, fp.mask, \
-                               fp.nf, T, x, y, skip_if, skip_j, dotp);                                             \
+            hipLaunchKernelGGL((k_hpsi_acc<R, NM, false, true, ST>), dim3(nb), dim3(HB), 0, s, fp.pi, fp.off,      \
+                               fp.mask, fp.nf, T, x, y, skip_if, skip_j, dotp);                                    \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_hpsi_acc<R, NM, false, false>), dim3(nb), dim3(HB), 0, s, fp.pi, fp.off,         \
+            hipLaunchKernelGGL((k_hpsi_acc<R, NM, false, false, ST>), dim3(nb), dim3(HB), 0, s, fp.pi, fp.off,     \
                                fp.mask, fp.nf, T, x, y, skip_if, skip_j, dotp);                                    \
     } while (0)
+    const bool st = fp.stage && fp.pi != nullptr && !dotp;  // the pass with the fused <x|y> keeps global loads
     switch (fp.nmax) {
-    case 8: L(8); break;
-    case 16: L(16); break;
-    case 24: L(24); break;
-    case 32: L(32); break;
-    case 48: L(48); break;
-    default: L(64); break;
+    case 8: if (st) L(8, true); else L(8, false); break;
+    case 16: if (st) L(16, true); else L(16, false); break;
+    case 24: if (st) L(24, true); else L(24, false); break;
+    case 32: if (st) L(32, true); else L(32, false); break;
+    case 48: L(48, false); break;
+    default: L(64, false); break;
     }
 #undef L
     return dotp ? (int)nb : 0;

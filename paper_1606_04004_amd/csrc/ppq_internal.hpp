@@ -157,6 +157,7 @@ struct FiberPass {
     const uint64_t *mask;
     int64_t nf;
     int nmax;               // padded 1D size (matrix leading dimension)
+    bool stage = false;     // lane-per-fiber pass: stage each wavefront's ranks of pi in LDS
 };
 // a pass over a dimension longer than NMAX_MASK: fibers as (off) runs of the
 // dimension's order with the digit of every entry (no masks)

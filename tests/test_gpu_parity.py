@@ -831,6 +831,47 @@ def test_plane_pass_largest_planes(fill, prec, torch):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_staged_permutation_same_results(prec, torch):
+    """The lane-per-fiber passes read the permutation either from scattered
+    global loads or from a wavefront's copy of its rank range in LDS
+    (PPQ_ACC_STAGE=1): the same arithmetic, so the products, and 5 steps
+    (whose Krylov iterations also take the fused <x|y> pass), are bitwise
+    identical; the product also matches the oracle."""
+    import os
+    cd = card("small_6d")
+    keys = random_active_set(cd["n"], 0.5, 61)
+    x = random_complex(keys.size, 62)
+    xin = x if prec == 0 else x.astype(np.complex64).astype(np.complex128)
+    ref = Oracle(cd).apply_def(keys, xin)
+    old = os.environ.get("PPQ_ACC_STAGE")
+    out, traj = {}, {}
+    try:
+        for st in ("0", "1"):
+            os.environ["PPQ_ACC_STAGE"] = st
+            g = make(cd, torch, precision=prec)
+            g.set_state(keys, x)
+            xt = torch.from_numpy(x).cuda()
+            if prec == 1:
+                xt = xt.to(torch.complex64)
+            yt = torch.zeros_like(xt)
+            g.apply_h(xt, yt)
+            torch.cuda.synchronize()
+            out[st] = yt.cpu().numpy().astype(np.complex128)
+            g.init_state()
+            traj[st] = g.propagate(nsteps=5)
+    finally:
+        if old is None:
+            del os.environ["PPQ_ACC_STAGE"]
+        else:
+            os.environ["PPQ_ACC_STAGE"] = old
+    assert np.array_equal(out["0"], out["1"])
+    assert np.array_equal(traj["0"], traj["1"])
+    err = np.max(np.abs(out["1"] - ref)) / np.max(np.abs(ref))
+    say(f"  staged permutation, prec {prec}: identical; rel err vs oracle {err:.2e}")
+    assert err < (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_pair_pass_largest_plane(prec, torch):
     """Layout 7 with a task at its largest span: on a 5 x 32 x 32 grid one
     plane is full (1024 points, the most a plane may hold) and the others
