@@ -1022,6 +1022,32 @@ __device__ inline double2 ld2(const float2 *p, int64_t i)
 }
 __device__ inline void st2(double2 *p, int64_t i, double2 v) { p[i] = v; }
 __device__ inline void st2(float2 *p, int64_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+// Streaming forms for the Krylov basis: the sweeps and the recombination
+// stream every earlier basis vector (more than the last-level cache holds),
+// so their loads and the corrected vectors' stores carry the non-temporal
+// hint and leave the cache to the product's tables and vectors.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+__device__ inline double2 ld2nt(const double2 *p, int64_t i)
+{
+    const nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p) + i);
+    return make_double2(v.x, v.y);
+}
+__device__ inline double2 ld2nt(const float2 *p, int64_t i)
+{
+    const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2 *>(p) + i);
+    return make_double2((double)v.x, (double)v.y);
+}
+__device__ inline void st2nt(double2 *p, int64_t i, double2 v)
+{
+    const nt_d2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_d2 *>(p) + i);
+}
+__device__ inline void st2nt(float2 *p, int64_t i, double2 v)
+{
+    const nt_f2 w = {(float)v.x, (float)v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<nt_f2 *>(p) + i);
+}
 // the value a store of v into a C vector holds, without reading it back
 __device__ inline double2 stored(const double2 *, double2 v) { return v; }
 __device__ inline double2 stored(const float2 *, double2 v) { return make_double2((float)v.x, (float)v.y); }
@@ -1351,17 +1377,17 @@ __global__ __launch_bounds__(TB) void k_lanczos_sweep(C *Vb, int64_t ld, const C
 #pragma unroll
     for (int i = 0; i < NV + 2; ++i) acc[i] = make_double2(0.0, 0.0);
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
-        double2 qv = ld2(qs, p), hv = ld2(z, p);
+        double2 qv = ld2nt(qs, p), hv = ld2nt(z, p);
         double2 vv[NH];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            vv[i] = ld2(Vb, (int64_t)i * ld + p);
+            vv[i] = ld2nt(Vb, (int64_t)i * ld + p);
             qv.x -= hq[i].x * vv[i].x - hq[i].y * vv[i].y;
             qv.y -= hq[i].x * vv[i].y + hq[i].y * vv[i].x;
             hv.x -= cc[i].x * vv[i].x - cc[i].y * vv[i].y;
             hv.y -= cc[i].x * vv[i].y + cc[i].y * vv[i].x;
         }
-        st2(qs, p, make_double2(qv.x * ib, qv.y * ib));
+        st2nt(qs, p, make_double2(qv.x * ib, qv.y * ib));
         const double2 vj = stored(qs, make_double2(qv.x * ib, qv.y * ib));
         hv.x -= cc[NV].x * vj.x - cc[NV].y * vj.y;
         hv.y -= cc[NV].x * vj.y + cc[NV].y * vj.x;
@@ -1394,7 +1420,7 @@ __global__ __launch_bounds__(TB) void k_arnoldi_dots(const C *Vb, int64_t ld, co
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
         const double2 zv = ld2(z, p);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], ld2(Vb, (int64_t)i * ld + p), zv);
+        for (int i = 0; i < NV; ++i) cdot_acc(acc[i], ld2nt(Vb, (int64_t)i * ld + p), zv);
         cdot_acc(acc[NV], ld2(qs, p), zv);
     }
     block_reduce_store<NV + 1>(acc, partial);
@@ -1427,17 +1453,17 @@ __global__ __launch_bounds__(TB) void k_arnoldi_sweep(C *Vb, int64_t ld, const C
 #pragma unroll
     for (int i = 0; i < NV + 2; ++i) acc[i] = make_double2(0.0, 0.0);
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * TB) {
-        double2 qv = ld2(qs, p), hv = ld2(z, p);
+        double2 qv = ld2nt(qs, p), hv = ld2nt(z, p);
         double2 vv[NH];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            vv[i] = ld2(Vb, (int64_t)i * ld + p);
+            vv[i] = ld2nt(Vb, (int64_t)i * ld + p);
             qv.x -= hq[i].x * vv[i].x - hq[i].y * vv[i].y;
             qv.y -= hq[i].x * vv[i].y + hq[i].y * vv[i].x;
             hv.x -= cc[i].x * vv[i].x - cc[i].y * vv[i].y;
             hv.y -= cc[i].x * vv[i].y + cc[i].y * vv[i].x;
         }
-        st2(qs, p, make_double2(qv.x * ib, qv.y * ib));
+        st2nt(qs, p, make_double2(qv.x * ib, qv.y * ib));
         const double2 vj = stored(qs, make_double2(qv.x * ib, qv.y * ib));
         hv.x -= cc[NV].x * vj.x - cc[NV].y * vj.y;
         hv.y -= cc[NV].x * vj.y + cc[NV].y * vj.x;
@@ -1474,7 +1500,7 @@ __global__ __launch_bounds__(TB) void k_lanczos_fix(C *Vb, int64_t ld, int64_t n
         double2 qv = ld2(qs, p);
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const double2 v = ld2(Vb, (int64_t)i * ld + p);
+            const double2 v = ld2nt(Vb, (int64_t)i * ld + p);
             qv.x -= hq[i].x * v.x - hq[i].y * v.y;
             qv.y -= hq[i].x * v.y + hq[i].y * v.x;
         }
@@ -1505,7 +1531,7 @@ __global__ void k_normalise(const double2 *psi, int64_t n, const KState *ks, C *
 {
     double s = 1.0 / ks->n0;
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        double2 a = psi[p];
+        double2 a = ld2nt(psi, p);
         st2(v0, p, make_double2(a.x * s, a.y * s));
     }
 }
@@ -1520,15 +1546,15 @@ __global__ void k_lincomb(const C *Vb, int64_t ld, const double2 *psi_master, in
     for (int i = 0; i < MAXM; ++i) y[i] = ks->y[i];
     double inv_n0 = 1.0 / ks->n0;
     for (int64_t p = gid(); p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        // j = 0 from the FP64 master copy (exact v_0 direction), j >= 1 from the basis
-        double2 v = psi_master[p];
+        // j = 0 from the FP64 master copy (exact v_0 direction, its last use), j >= 1 from the basis
+        double2 v = ld2nt(psi_master, p);
         v.x *= inv_n0;
         v.y *= inv_n0;
         double2 acc = make_double2(y[0].x * v.x - y[0].y * v.y, y[0].x * v.y + y[0].y * v.x);
 #pragma unroll
         for (int i = 1; i < MAXM; ++i) {
             if (i < meff) {
-                double2 b = ld2(Vb, (int64_t)i * ld + p);
+                double2 b = ld2nt(Vb, (int64_t)i * ld + p);
                 acc.x += y[i].x * b.x - y[i].y * b.y;
                 acc.y += y[i].x * b.y + y[i].y * b.x;
             }
