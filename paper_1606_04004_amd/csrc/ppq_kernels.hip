@@ -547,30 +547,42 @@ __global__ void k_last_info(const uint32_t *keys, int64_t n, int nl, uint8_t *in
     info[p] = (uint8_t)((keys[p] % (uint32_t)nl) | flag);
 }
 
+// mask[0, *nf) = 0 (the fiber count is on the device)
+__global__ void k_zero_masks(uint64_t *mask, const uint32_t *nf)
+{
+    const int64_t m = *nf;
+    for (int64_t i = gid(); i < m; i += (int64_t)gridDim.x * blockDim.x) mask[i] = 0ull;
+}
+
+// One thread per point: the fiber start writes off; every point's digit bit
+// is ORed over the wavefront's consecutive lanes of its fiber and the
+// segment's last lane adds it to the (zeroed) mask, so a fiber costs one or
+// two atomics however its points fall over the wavefronts.  A dimension
+// longer than a mask word keeps no mask.
 __global__ void k_last_fill(const uint32_t *keys, int64_t n, int nl, const uint32_t *flags, const uint32_t *fidx,
                             const uint32_t *nf, uint32_t *off, uint64_t *mask)
 {
-    int64_t p = gid();
+    const int64_t p = gid();
+    const int lane = threadIdx.x & 63;
     if (p == 0) off[*nf] = (uint32_t)n;
-    if (p >= n || !flags[p]) return;
-    uint32_t f = fidx[p];
-    uint32_t fk = keys[p] / (uint32_t)nl;
-    uint64_t m = 0;
-    // the fiber's keys are consecutive: read them 8 at a time (independent
-    // loads); a dimension longer than a mask word keeps no mask
-    bool more = nl <= NMAX_MASK;
-    for (int64_t q0 = p; more && q0 < n; q0 += 8) {
-        uint32_t kv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) kv[u] = q0 + u < n ? keys[q0 + u] : 0xffffffffu;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (more && kv[u] != 0xffffffffu && kv[u] / (uint32_t)nl == fk) m |= 1ull << (kv[u] % (uint32_t)nl);
-            else more = false;
-        }
+    const bool valid = p < n;
+    uint32_t f = 0xffffffffu;
+    uint64_t bits = 0ull;
+    if (valid) {
+        const uint32_t st = flags[p];
+        f = fidx[p] - (st ? 0u : 1u);  // fidx counts the starts before p
+        if (st) off[f] = (uint32_t)p;
+        if (nl <= NMAX_MASK) bits = 1ull << (keys[p] % (uint32_t)nl);
     }
-    off[f] = (uint32_t)p;
-    if (nl <= NMAX_MASK) mask[f] = m;
+    if (nl > NMAX_MASK) return;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t of = __shfl_up(f, d, 64);
+        const uint32_t lo = __shfl_up((uint32_t)bits, d, 64), hi = __shfl_up((uint32_t)(bits >> 32), d, 64);
+        if (lane >= d && of == f) bits |= ((uint64_t)hi << 32) | lo;
+    }
+    const uint32_t nxt = __shfl_down(f, 1, 64);
+    if (valid && (lane == 63 || nxt != f)) atomicOr((unsigned long long *)&mask[f], (unsigned long long)bits);
 }
 
 __device__ inline uint32_t rotate_key(uint32_t key, uint32_t sk, uint32_t nk, uint32_t *dig)
@@ -2240,6 +2252,8 @@ void last_flags(const uint32_t *keys, int64_t n, int nlast, uint32_t *flags, hip
 void last_fill(const uint32_t *keys, int64_t n, int nlast, const uint32_t *flags, const uint32_t *fidx,
                const uint32_t *nf, uint32_t *off, uint64_t *mask, hipStream_t s)
 {
+    if (nlast <= NMAX_MASK)
+        hipLaunchKernelGGL(k_zero_masks, dim3(std::min<unsigned>(nblocks(n), 2048u)), dim3(TB), 0, s, mask, nf);
     hipLaunchKernelGGL(k_last_fill, dim3(nblocks(n)), dim3(TB), 0, s, keys, n, nlast, flags, fidx, nf, off, mask);
 }
 void rot_set(const uint32_t *keys, int64_t n, const RotFrame &f, uint64_t *bm, hipStream_t s)
